@@ -1,0 +1,239 @@
+"""CPU oracle for the Ozaki-scheme INT8 emulation of DGEMM / ZGEMM.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the benchmark's
+CPU-baseline leg import this package; the product library never does, and the
+oracle never imports the product.  It shares no code with the GPU path: the
+arithmetic lives in ``oz_oracle.c`` (plain C, built by ``oracle/build.py``)
+and ``exact.py`` (rational arithmetic); this module only marshals numpy arrays.
+
+Functions (every array is a numpy array in column-major / Fortran order,
+float64 or complex128; ``trans`` is 'N', 'T' or 'C'):
+
+* ``gemm_plain``  O1: FP64 GEMM, plain dot products in index order.
+* ``gemm_dd``     O2: double-double (Dot2) GEMM, rounded once; the accuracy
+                  reference every error report uses.
+* ``split``       the per-vector scale exponent and the s INT8 digits
+                  (Sec. 2.2: matrices are split into low-precision slices).
+* ``diag_sums``   the exact integer anti-diagonal sums S_{d,chunk}.
+* ``emu_gemm``    the full emulated product: digits, pair products with
+                  p + q <= s + 1, FP64 accumulation, alpha/beta.
+* ``kchunk``      the INT32 chunk length (products per chunk).
+
+Parity of each function is pinned in tests/test_oracle_*.py; none is unpinned.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+from .exact import exact_gemm, exact_gemm_rounded  # noqa: F401
+
+_lib = None
+
+INT32_MAX = 2 ** 31 - 1
+DIGIT_MAX = 127
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_build.LIB) or os.path.getmtime(_build.LIB) < os.path.getmtime(_build.SRC):
+        _build.build()
+    lib = ctypes.CDLL(_build.LIB)
+    I64, D, P, C = ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_char
+    I32 = ctypes.c_int
+    lib.oro_dgemm_plain.argtypes = [C, C, I64, I64, I64, D, P, I64, P, I64, D, P, I64]
+    lib.oro_zgemm_plain.argtypes = [C, C, I64, I64, I64, P, P, I64, P, I64, P, P, I64]
+    lib.oro_dgemm_dd.argtypes = [C, C, I64, I64, I64, D, P, I64, P, I64, D, P, I64, P, I64, P, I64, P, I64]
+    lib.oro_zgemm_dd.argtypes = [C, C, I64, I64, I64, P, P, I64, P, I64, P, P, I64, P, I64, P, I64, P, I64]
+    lib.oro_split.argtypes = [C, C, I32, I64, I64, P, I64, I32, P, P]
+    lib.oro_diag_sums.argtypes = [I32, I32, I64, I64, P, I64, P, I64, P, I64, P, I64, P]
+    lib.oro_emu_dgemm.argtypes = [C, C, I64, I64, I64, D, P, I64, P, I64, D, P, I64, I32, I64,
+                                  P, I64, P, I64, P, I64]
+    lib.oro_emu_zgemm.argtypes = [C, C, I64, I64, I64, P, P, I64, P, I64, P, P, I64, I32, I64,
+                                  P, I64, P, I64, P, I64]
+    lib.oro_num_threads.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def num_threads():
+    """OpenMP threads the oracle runs on."""
+    return _load().oro_num_threads()
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def _f(a, dtype):
+    a = np.asarray(a, dtype=dtype)
+    return np.asfortranarray(a)
+
+
+def _dims(trans, X, side):
+    """(rows, cols) of op(X): side 'A' gives (m, k), side 'B' gives (k, n)."""
+    r, c = X.shape
+    return (c, r) if trans.upper() in "TC" else (r, c)
+
+
+def _sel(sel, n):
+    if sel is None:
+        return None, n
+    s = np.ascontiguousarray(np.asarray(sel, dtype=np.int64))
+    assert s.ndim == 1 and (s.size == 0 or (s.min() >= 0 and s.max() < n))
+    return s, s.size
+
+
+def _ld(X):
+    return max(1, X.shape[0])
+
+
+def kchunk(s, cplx=False):
+    """INT32 chunk length in products per output entry.
+
+    An anti-diagonal sum of one chunk holds at most s pair products per term
+    (diagonal d = s + 1 has s pairs) and every pair product is at most 127^2 in
+    magnitude, so kc terms are safe while s * kc * 127^2 <= 2^31 - 1.  kc is
+    rounded down to a multiple of 64; a complex entry consumes two products per
+    value of l, so complex chunks cover kc / 2 values of l.
+    """
+    kc = INT32_MAX // (s * DIGIT_MAX * DIGIT_MAX)
+    kc -= kc % 64
+    return int(kc)
+
+
+def gemm_plain(transa, transb, A, B, alpha=1.0, beta=0.0, C=None):
+    """O1: C = alpha*op(A)*op(B) + beta*C in plain FP64."""
+    cplx = np.iscomplexobj(A) or np.iscomplexobj(B) or np.iscomplexobj(alpha) or np.iscomplexobj(beta)
+    dt = np.complex128 if cplx else np.float64
+    A, B = _f(A, dt), _f(B, dt)
+    m, k = _dims(transa, A, "A")
+    k2, n = _dims(transb, B, "B")
+    assert k == k2
+    Cout = np.zeros((m, n), dtype=dt, order="F") if C is None else _f(C, dt).copy(order="F")
+    lib = _load()
+    if cplx:
+        al = np.array([complex(alpha).real, complex(alpha).imag])
+        be = np.array([complex(beta).real, complex(beta).imag])
+        lib.oro_zgemm_plain(transa.encode(), transb.encode(), m, n, k, _ptr(al), _ptr(A), _ld(A),
+                            _ptr(B), _ld(B), _ptr(be), _ptr(Cout), max(1, m))
+    else:
+        lib.oro_dgemm_plain(transa.encode(), transb.encode(), m, n, k, float(alpha), _ptr(A), _ld(A),
+                            _ptr(B), _ld(B), float(beta), _ptr(Cout), max(1, m))
+    return Cout
+
+
+def gemm_dd(transa, transb, A, B, alpha=1.0, beta=0.0, C=None, rows=None, cols=None):
+    """O2: double-double GEMM on the selected rows x cols of C (all by default)."""
+    cplx = np.iscomplexobj(A) or np.iscomplexobj(B) or np.iscomplexobj(alpha) or np.iscomplexobj(beta)
+    dt = np.complex128 if cplx else np.float64
+    A, B = _f(A, dt), _f(B, dt)
+    m, k = _dims(transa, A, "A")
+    k2, n = _dims(transb, B, "B")
+    assert k == k2
+    Cin = np.zeros((max(m, 1), max(n, 1)), dtype=dt, order="F") if C is None else _f(C, dt)
+    rs, nr = _sel(rows, m)
+    cs, nc = _sel(cols, n)
+    out = np.zeros((nr, nc), dtype=dt, order="F")
+    lib = _load()
+    if cplx:
+        al = np.array([complex(alpha).real, complex(alpha).imag])
+        be = np.array([complex(beta).real, complex(beta).imag])
+        lib.oro_zgemm_dd(transa.encode(), transb.encode(), m, n, k, _ptr(al), _ptr(A), _ld(A), _ptr(B),
+                         _ld(B), _ptr(be), _ptr(Cin), _ld(Cin), _ptr(rs), nr, _ptr(cs), nc, _ptr(out),
+                         max(1, nr))
+    else:
+        lib.oro_dgemm_dd(transa.encode(), transb.encode(), m, n, k, float(alpha), _ptr(A), _ld(A),
+                         _ptr(B), _ld(B), float(beta), _ptr(Cin), _ld(Cin), _ptr(rs), nr, _ptr(cs), nc,
+                         _ptr(out), max(1, nr))
+    return out
+
+
+def split(side, trans, X, s):
+    """Scale exponents and digits of the vectors of one operand.
+
+    side 'A': the vectors are the rows of op(X); side 'B': the columns of op(X).
+    Returns (E, dig): E int32 [nv]; dig int8 [s, nv, k] for real data or
+    [s, nv, k, 2] (real part, imaginary part) for complex data.
+    """
+    cplx = np.iscomplexobj(X)
+    X = _f(X, np.complex128 if cplx else np.float64)
+    if side == "A":
+        nv, k = _dims(trans, X, "A")
+    else:
+        k, nv = _dims(trans, X, "B")
+    E = np.zeros(nv, dtype=np.int32)
+    shape = (s, nv, k, 2) if cplx else (s, nv, k)
+    dig = np.zeros(shape, dtype=np.int8)
+    _load().oro_split(side.encode(), trans.encode(), int(cplx), nv, k, _ptr(X), _ld(X), s, _ptr(E),
+                      _ptr(dig))
+    return E, dig
+
+
+def diag_sums(digA, digB, s, kc=None, rows=None, cols=None):
+    """Exact anti-diagonal sums S[c, d-2, i, j] (d = 2..s+1) from split digits.
+
+    digA, digB as returned by ``split``; complex digits give a pair (Sr, Si).
+    kc is the chunk length in products (``kchunk`` by default).
+    """
+    cplx = digA.ndim == 4
+    k = digA.shape[2]
+    kc = kchunk(s, cplx) if kc is None else kc
+    assert kc > 0 and (not cplx or kc % 2 == 0)
+    nvA, nvB = digA.shape[1], digB.shape[1]
+    lch = kc // 2 if cplx else kc
+    nch = (k + lch - 1) // lch if k > 0 else 0
+    rs, nr = _sel(rows, nvA)
+    cs, nc = _sel(cols, nvB)
+    planes = 2 if cplx else 1
+    out = np.zeros(planes * nch * s * nc * nr, dtype=np.int64)
+    dA = np.ascontiguousarray(digA)
+    dB = np.ascontiguousarray(digB)
+    _load().oro_diag_sums(int(cplx), s, k, kc, _ptr(dA), nvA, _ptr(dB), nvB, _ptr(rs), nr, _ptr(cs), nc,
+                          _ptr(out))
+    out = out.reshape(planes, nch, s, nc, nr).transpose(0, 1, 2, 4, 3)
+    return (out[0], out[1]) if cplx else out[0]
+
+
+def emu_gemm(transa, transb, A, B, s, alpha=1.0, beta=0.0, C=None, kc=None, rows=None, cols=None):
+    """O4: the emulated GEMM on the selected rows x cols (all by default)."""
+    cplx = np.iscomplexobj(A) or np.iscomplexobj(B) or np.iscomplexobj(alpha) or np.iscomplexobj(beta)
+    dt = np.complex128 if cplx else np.float64
+    A, B = _f(A, dt), _f(B, dt)
+    m, k = _dims(transa, A, "A")
+    k2, n = _dims(transb, B, "B")
+    assert k == k2
+    kc = kchunk(s, cplx) if kc is None else kc
+    assert kc > 0 and (not cplx or kc % 2 == 0)
+    Cin = np.zeros((max(m, 1), max(n, 1)), dtype=dt, order="F") if C is None else _f(C, dt)
+    rs, nr = _sel(rows, m)
+    cs, nc = _sel(cols, n)
+    out = np.zeros((nr, nc), dtype=dt, order="F")
+    lib = _load()
+    if cplx:
+        al = np.array([complex(alpha).real, complex(alpha).imag])
+        be = np.array([complex(beta).real, complex(beta).imag])
+        lib.oro_emu_zgemm(transa.encode(), transb.encode(), m, n, k, _ptr(al), _ptr(A), _ld(A), _ptr(B),
+                          _ld(B), _ptr(be), _ptr(Cin), _ld(Cin), s, kc, _ptr(rs), nr, _ptr(cs), nc,
+                          _ptr(out), max(1, nr))
+    else:
+        lib.oro_emu_dgemm(transa.encode(), transb.encode(), m, n, k, float(alpha), _ptr(A), _ld(A),
+                          _ptr(B), _ld(B), float(beta), _ptr(Cin), _ld(Cin), s, kc, _ptr(rs), nr,
+                          _ptr(cs), nc, _ptr(out), max(1, nr))
+    return out
+
+
+def weighted_error(Cx, Cref, A_rowmax, B_colmax):
+    """Scale-weighted normwise relative error of Cx against Cref.
+
+    Each entry is weighted by 1 / (max_l |op(A)_il| * max_l |op(B)_lj|), which
+    removes wide row/column scalings; without them it is the plain
+    Frobenius-norm relative error up to a few percent.
+    """
+    W = 1.0 / np.outer(A_rowmax, B_colmax)
+    num = np.linalg.norm((W * (Cx - Cref)).ravel())
+    den = np.linalg.norm((W * Cref).ravel())
+    return float(num / den) if den > 0 else float(num)
