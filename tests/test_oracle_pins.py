@@ -281,6 +281,15 @@ def test_exact_when_no_pair_is_dropped(cplx):
     assert np.array_equal(got, want)
     # one slice fewer drops nonzero pairs: not exact any more
     assert not np.array_equal(oracle.emu_gemm("N", "N", A, B, 2), want)
+    # alpha and beta with few bits keep every product and sum exact as well
+    C0 = few_digit_matrix(rng, (m, n), 2)
+    if cplx:
+        C0 = C0 + 1j * few_digit_matrix(rng, (m, n), 2)
+        alpha, beta = complex(3, -2), complex(0.5, 1.5)
+    else:
+        alpha, beta = -3.0, 0.75
+    got = oracle.emu_gemm("N", "N", A, B, 3, alpha=alpha, beta=beta, C=C0)
+    assert np.array_equal(got, exact_gemm_rounded("N", "N", A, B, alpha, beta, C0))
 
 
 # ---------------------------------------------------------------- a-priori bound
