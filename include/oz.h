@@ -1,0 +1,185 @@
+/*
+ * oz.h -- C ABI of the Ozaki-scheme FP64 / complex-FP64 GEMM emulation on
+ * INT8 matrix cores (AMD Instinct MI355X, gfx950).
+ *
+ * The method (paper Sec. 2.2): each FP64 operand is split into s INT8 slices
+ * under a power-of-two scale per row of op(A) and per column of op(B); the
+ * slice products run on INT8 matrix units with INT32 accumulation and are
+ * rescaled and summed in FP64.  The number of splits s sets the precision
+ * (Sec. 3.1, modes with 3 to 18 splits; Sec. 4: about two decimal digits per
+ * split, cost quadratic in s).  The paper reaches the emulation through
+ * intercepted BLAS dgemm/zgemm calls (Sec. 3.1), so the entry points below
+ * keep the BLAS argument list.
+ *
+ * Conventions shared by every entry point
+ *  - Storage is BLAS column-major.  op(A) is m x k, op(B) is k x n, C is
+ *    m x n; element (i, j) of C lives at C[i + j*ldc].  trans is 'N', 'T' or
+ *    'C' (either case); for real data 'C' means 'T'.
+ *  - A, B, C and every other array argument named "device" are device
+ *    pointers owned by the caller; alpha and beta are host pointers.
+ *  - Work is enqueued on the handle's stream and the call returns without
+ *    waiting, unless a report is requested (rep != NULL), in which case the
+ *    call waits for its own work so that it can fill the report.
+ *  - C must not overlap A or B.  Calls on one handle must not overlap in time
+ *    from several host threads (the handle owns one workspace).
+ *  - Return value: 0 on success; a positive value is the position of the
+ *    first invalid argument, counted as in reference BLAS (1 transa,
+ *    2 transb, 3 m, 4 n, 5 k, 8 lda, 10 ldb, 13 ldc, 14 prec); a negative
+ *    value is one of the OZ_ERR_* codes below.  Nothing is enqueued when a
+ *    call returns nonzero.
+ *  - Quick returns as in reference BLAS: m = 0 or n = 0 does nothing; when
+ *    alpha = 0 or k = 0, C = beta*C (exact zeros when beta = 0, C not read).
+ *  - Non-finite inputs: the scale of a row of op(A) or column of op(B) that
+ *    holds an Inf or NaN is undefined; every entry of C that depends on such
+ *    a row or column is set to NaN, the other entries are computed normally,
+ *    and the report (if requested) carries status OZ_ERR_NONFINITE.
+ */
+#ifndef OZ_H
+#define OZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    OZ_OK = 0,
+    OZ_ERR_HIP = -1,         /* a HIP runtime call failed                         */
+    OZ_ERR_ALLOC = -2,       /* device workspace allocation failed or too small   */
+    OZ_ERR_NONFINITE = -3,   /* an input row / column held Inf or NaN (report only) */
+    OZ_ERR_HANDLE = -4,      /* NULL or destroyed handle                          */
+    OZ_ERR_UNSUPPORTED = -5, /* no gfx950 device, or a size beyond the int32 grid  */
+    OZ_ERR_ARG = -6          /* invalid argument of a non-BLAS entry point        */
+};
+
+/* Largest slice count accepted (the paper's modes run up to 18 splits). */
+#define OZ_MAX_SLICES 18
+
+typedef struct oz_handle_s* oz_handle_t;
+
+/* Precision request.
+ *  slices : s in 1..OZ_MAX_SLICES, the number of INT8 slices per operand
+ *           (Sec. 3.1 "fp64_int8_<s>" modes); 0 selects s from tol.
+ *  tol    : target relative error when slices == 0 (must then be > 0).
+ *  smax   : largest s the tol-driven selection may use (0: 12).
+ *  kchunk : products per INT32 chunk along k; 0 picks the largest multiple of
+ *           64 with s*kchunk*127^2 <= 2^31-1; a nonzero value must be a
+ *           positive multiple of 64 not above that bound (used to exercise
+ *           the chunked accumulation on small k).
+ *  zmode  : complex only; 0 or 4: the 4-real-product form (the only one
+ *           built so far).
+ */
+typedef struct {
+    int32_t slices;
+    int32_t smax;
+    int32_t kchunk;
+    int32_t zmode;
+    double tol;
+} oz_prec_t;
+
+/* Per-call report, filled when rep != NULL (the call then synchronises). */
+typedef struct {
+    int32_t status;        /* OZ_OK or OZ_ERR_NONFINITE                      */
+    int32_t slices_used;   /* s of the final result                          */
+    int32_t fallbacks;     /* extra slices added by the residual check       */
+    int32_t kchunks;       /* INT32 chunks along k                           */
+    int32_t zmode_used;    /* 4 for complex, 0 for real                      */
+    int32_t reserved;
+    double resid_est;      /* a-posteriori error estimate (tol mode), else 0 */
+} oz_report_t;
+
+/* Create a handle bound to HIP device `device` (made current for the call)
+ * with the null stream and a library-owned, grow-only workspace.
+ * Returns OZ_ERR_UNSUPPORTED when the device is not gfx950. */
+int oz_create(oz_handle_t* handle, int device);
+
+/* Free the handle and its library-owned workspace (waits for its stream). */
+int oz_destroy(oz_handle_t handle);
+
+/* Set the stream (a hipStream_t) every later call enqueues on; NULL is the
+ * null stream.  The stream stays owned by the caller. */
+int oz_set_stream(oz_handle_t handle, void* stream);
+
+/* Text of a status code (static storage). */
+const char* oz_status_string(int status);
+
+/* Device workspace bytes oz_dgemm (is_complex = 0) or oz_zgemm (1) needs for
+ * these sizes and precision (prec->slices must be nonzero). */
+int oz_workspace_size(oz_handle_t handle, char transa, char transb, int64_t m, int64_t n, int64_t k,
+                      int is_complex, const oz_prec_t* prec, size_t* bytes);
+
+/* Hand the handle a caller-owned device workspace (NULL releases it and
+ * returns to library-owned allocation).  A call whose need exceeds the bytes
+ * given returns OZ_ERR_ALLOC. */
+int oz_set_workspace(oz_handle_t handle, void* dptr, size_t bytes);
+
+/* C = alpha*op(A)*op(B) + beta*C, FP64, emulated with prec->slices INT8
+ * slices (Sec. 2.2 / 3.1).  prec NULL means s = 7.  With beta == 0, C is not
+ * read.  Per entry the result is ldexp(acc, E_i + F_j) scaled by alpha,
+ * where acc sums, chunk by chunk and then from the highest anti-diagonal
+ * d = s+1 down to d = 2, the INT32 sums S_d of the slice-pair products with
+ * p + q = d, each times 2^(-7d); the products alpha*v and beta*C are rounded
+ * separately and added (no fused multiply-add). */
+int oz_dgemm(oz_handle_t handle, char transa, char transb, int64_t m, int64_t n, int64_t k,
+             const double* alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
+             const double* beta, double* C, int64_t ldc, const oz_prec_t* prec, oz_report_t* rep);
+
+/* Complex version (interleaved real/imaginary FP64 pairs, i.e. the memory
+ * layout of double _Complex / hipDoubleComplex).  alpha and beta point at
+ * two doubles each (real, imaginary).  One power-of-two scale serves both
+ * parts of a row of op(A) / column of op(B): the exponent of its largest real
+ * or imaginary part.  Re C and Im C are each a real emulated product over 2k
+ * terms (ar*br - ai*bi and ar*bi + ai*br), so the INT8 work is that of four
+ * real products.  out = (xr*vr - xi*vi) + (yr*cr - yi*ci) for the real part
+ * and (xr*vi + xi*vr) + (yr*ci + yi*cr) for the imaginary part, with
+ * alpha = (xr, xi), beta = (yr, yi), each product and sum rounded. */
+int oz_zgemm(oz_handle_t handle, char transa, char transb, int64_t m, int64_t n, int64_t k,
+             const double* alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
+             const double* beta, double* C, int64_t ldc, const oz_prec_t* prec, oz_report_t* rep);
+
+/* ---- The steps of the method, exposed for verification ------------------
+ *
+ * Slice layout (the library's own, shared by its kernels):
+ *   An operand is a set of vectors: the rows of op(A) (side 'A') or the
+ *   columns of op(B) (side 'B').  A real operand has nv vectors of K' = k
+ *   terms.  A complex side-'B' operand has nv vectors of K' = 2k terms, term
+ *   2l holding the real and 2l+1 the imaginary part of element l.  A complex
+ *   side-'A' operand has 2*ceil(nv/16)*16 vectors of K' = 2k terms: complex
+ *   row c maps to vector r = 32*(c/16) + 16*((c/8)%2) + (c%8) for the
+ *   real-part row (terms: ar, -ai) and r + 8 for the imaginary-part row
+ *   (terms: ai, ar).  Vectors are padded with zeros to rows_pad (a multiple
+ *   of 64) and terms to kpad (a multiple of 32).
+ *   Digit p (1..s) of term t of vector v is the int8 at byte offset
+ *     (((t/16)*s + (p-1)) * rows_pad + v) * 16 + t%16.
+ *   The scale exponent of vector v (per complex row c for a complex side 'A')
+ *   is the int32 E[v]; INT32_MIN marks a vector that holds Inf or NaN.
+ */
+
+/* Sizes of the slice layout above. */
+int oz_split_layout(char side, int is_complex, int64_t nv, int64_t k, int32_t slices,
+                    int64_t* rows_pad, int64_t* kpad, size_t* slice_bytes);
+
+/* Step 1-2 of the method for one operand: scale exponents and INT8 digits.
+ * X is the device operand (real or interleaved complex doubles) with leading
+ * dimension ldx; vectors are taken from op(X) as described above (side 'A':
+ * op(X) is nv x k; side 'B': op(X) is k x nv).  E (device int32, nv entries)
+ * and slices (device, slice_bytes of oz_split_layout) receive the result. */
+int oz_split(oz_handle_t handle, char side, char trans, int is_complex, int64_t nv, int64_t k,
+             const double* X, int64_t ldx, int32_t slices, int32_t* E, int8_t* slices_out);
+
+/* Step 3: the exact anti-diagonal sums S_{d,c} = sum over p + q = d of the
+ * INT32 slice-pair products over chunk c of kchunk terms, from two slice
+ * buffers laid out by oz_split (A: rows_pad_a vectors, B: rows_pad_b vectors,
+ * same kpad).  out (device int32) receives
+ *   out[((c*s + (d-2)) * rows_pad_b + j) * rows_pad_a + i]
+ * for every chunk c < ceil(kpad/kchunk), d = 2..s+1, and all padded i, j. */
+int oz_diag_sums(oz_handle_t handle, int32_t slices, int64_t kchunk, int64_t rows_pad_a,
+                 int64_t rows_pad_b, int64_t kpad, const int8_t* slices_a, const int8_t* slices_b,
+                 int32_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OZ_H */

@@ -1,0 +1,168 @@
+"""Python binding of liboz.so, the Ozaki-scheme FP64 / complex-FP64 GEMM
+emulation on MI355X INT8 matrix cores (C ABI: include/oz.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of liboz.so.  Functions keep the C names; pointer arguments accept a
+torch tensor (its data_ptr), a plain integer address, or None.  There is no
+CPU fallback: importing this module without the built library raises.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboz.so")
+
+OZ_OK = 0
+OZ_ERR_HIP = -1
+OZ_ERR_ALLOC = -2
+OZ_ERR_NONFINITE = -3
+OZ_ERR_HANDLE = -4
+OZ_ERR_UNSUPPORTED = -5
+OZ_ERR_ARG = -6
+OZ_MAX_SLICES = 18
+
+# Every symbol include/oz.h declares (checked by the CPU test-suite).
+EXPORTS = ["oz_create", "oz_destroy", "oz_set_stream", "oz_status_string", "oz_workspace_size",
+           "oz_set_workspace", "oz_dgemm", "oz_zgemm", "oz_split_layout", "oz_split", "oz_diag_sums"]
+
+
+class OzError(RuntimeError):
+    def __init__(self, fn, status):
+        super().__init__("%s failed: status %d (%s)" % (fn, status, oz_status_string(status)))
+        self.status = status
+
+
+class oz_prec_t(ctypes.Structure):
+    _fields_ = [("slices", ctypes.c_int32), ("smax", ctypes.c_int32), ("kchunk", ctypes.c_int32),
+                ("zmode", ctypes.c_int32), ("tol", ctypes.c_double)]
+
+
+class oz_report_t(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("slices_used", ctypes.c_int32), ("fallbacks", ctypes.c_int32),
+                ("kchunks", ctypes.c_int32), ("zmode_used", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("resid_est", ctypes.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("liboz.so is not built (%s); run __graft_entry__.build() first" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I64, I32, C, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_char, ctypes.c_double
+    PP = ctypes.POINTER
+    sig = {
+        "oz_create": [PP(P), ctypes.c_int],
+        "oz_destroy": [P],
+        "oz_set_stream": [P, P],
+        "oz_status_string": [ctypes.c_int],
+        "oz_workspace_size": [P, C, C, I64, I64, I64, ctypes.c_int, PP(oz_prec_t), PP(ctypes.c_size_t)],
+        "oz_set_workspace": [P, P, ctypes.c_size_t],
+        "oz_dgemm": [P, C, C, I64, I64, I64, PP(D), P, I64, P, I64, PP(D), P, I64, PP(oz_prec_t),
+                     PP(oz_report_t)],
+        "oz_zgemm": [P, C, C, I64, I64, I64, PP(D), P, I64, P, I64, PP(D), P, I64, PP(oz_prec_t),
+                     PP(oz_report_t)],
+        "oz_split_layout": [C, ctypes.c_int, I64, I64, I32, PP(I64), PP(I64), PP(ctypes.c_size_t)],
+        "oz_split": [P, C, C, ctypes.c_int, I64, I64, P, I64, I32, P, P],
+        "oz_diag_sums": [P, I32, I64, I64, I64, I64, P, P, P],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_char_p if name == "oz_status_string" else ctypes.c_int
+    return lib
+
+
+_lib = _load()
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _ch(c):
+    return c.encode() if isinstance(c, str) else c
+
+
+def _check(fn, status, allow=()):
+    if status != OZ_OK and status not in allow:
+        raise OzError(fn, status)
+    return status
+
+
+def oz_status_string(status):
+    return _lib.oz_status_string(status).decode()
+
+
+def oz_create(device=0):
+    h = ctypes.c_void_p()
+    _check("oz_create", _lib.oz_create(ctypes.byref(h), device))
+    return h
+
+
+def oz_destroy(handle):
+    return _check("oz_destroy", _lib.oz_destroy(handle))
+
+
+def oz_set_stream(handle, stream):
+    """stream: a hipStream_t address (e.g. torch.cuda.current_stream().cuda_stream) or None."""
+    return _check("oz_set_stream", _lib.oz_set_stream(handle, stream))
+
+
+def prec(slices=7, tol=0.0, smax=0, kchunk=0, zmode=0):
+    return oz_prec_t(slices, smax, kchunk, zmode, tol)
+
+
+def oz_workspace_size(handle, transa, transb, m, n, k, is_complex, p=None):
+    out = ctypes.c_size_t()
+    _check("oz_workspace_size", _lib.oz_workspace_size(handle, _ch(transa), _ch(transb), m, n, k, int(is_complex),
+                                                        ctypes.byref(p) if p is not None else None,
+                                                        ctypes.byref(out)))
+    return out.value
+
+
+def oz_set_workspace(handle, dptr, nbytes):
+    return _check("oz_set_workspace", _lib.oz_set_workspace(handle, _ptr(dptr), nbytes))
+
+
+def _gemm(fn, cplx, handle, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, p, report, check):
+    al = (ctypes.c_double * 2)(complex(alpha).real, complex(alpha).imag)
+    be = (ctypes.c_double * 2)(complex(beta).real, complex(beta).imag)
+    rep = oz_report_t() if report else None
+    st = getattr(_lib, fn)(handle, _ch(transa), _ch(transb), m, n, k, al, _ptr(A), lda, _ptr(B), ldb, be, _ptr(C),
+                           ldc, ctypes.byref(p) if p is not None else None,
+                           ctypes.byref(rep) if rep is not None else None)
+    if check:
+        _check(fn, st)
+    return (st, rep) if report else st
+
+
+def oz_dgemm(handle, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, p=None, report=False, check=True):
+    """C = alpha*op(A)*op(B) + beta*C (column-major device buffers)."""
+    return _gemm("oz_dgemm", False, handle, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, p,
+                 report, check)
+
+
+def oz_zgemm(handle, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, p=None, report=False, check=True):
+    """Complex version; A, B, C hold interleaved (re, im) doubles."""
+    return _gemm("oz_zgemm", True, handle, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, p,
+                 report, check)
+
+
+def oz_split_layout(side, is_complex, nv, k, slices):
+    rp, kp, nb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_size_t()
+    _check("oz_split_layout", _lib.oz_split_layout(_ch(side), int(is_complex), nv, k, slices, ctypes.byref(rp),
+                                                    ctypes.byref(kp), ctypes.byref(nb)))
+    return rp.value, kp.value, nb.value
+
+
+def oz_split(handle, side, trans, is_complex, nv, k, X, ldx, slices, E, slices_out):
+    return _check("oz_split", _lib.oz_split(handle, _ch(side), _ch(trans), int(is_complex), nv, k, _ptr(X), ldx,
+                                            slices, _ptr(E), _ptr(slices_out)))
+
+
+def oz_diag_sums(handle, slices, kchunk, rows_pad_a, rows_pad_b, kpad, slices_a, slices_b, out):
+    return _check("oz_diag_sums", _lib.oz_diag_sums(handle, slices, kchunk, rows_pad_a, rows_pad_b, kpad,
+                                                    _ptr(slices_a), _ptr(slices_b), _ptr(out)))

@@ -1,0 +1,244 @@
+// oz_gemm.hip -- INT8 slice-pair products on CDNA4 matrix cores with the
+// FP64 rescale-accumulate epilogue fused (paper Sec. 2.2: INT8 matrix units
+// with INT32 accumulation, result accumulated at higher precision).
+//
+// One block computes a 64 x 64 tile of C' = A' * B' (A', B' the slice
+// buffers of oz_split) with 4 waves, each owning a 32 x 32 sub-tile and one
+// v_mfma_i32_32x32x32_i8 per slice pair and 32-term step.
+//
+// All-diagonal form: every step stages the s slices of both operands in LDS
+// once and runs all s(s+1)/2 pairs (p, q) with p + q <= s + 1, accumulating
+// pair (p, q) into the INT32 register tile of its anti-diagonal d = p + q.
+// Loading s slices for s(s+1)/2 products gives (s+1)/2 times the arithmetic
+// intensity of streaming one pair at a time, and no INT32 partial ever
+// leaves the registers.  Per INT32 chunk (kchunk terms, sized so that
+// s * kchunk * 127^2 <= 2^31 - 1) the s diagonal tiles are folded into an
+// FP64 tile, from d = s+1 down to 2, each times 2^(-7d) (exact).  The final
+// epilogue applies 2^(E_i + F_j) with ldexp and alpha/beta.
+//
+// LDS stage (double buffered): for each operand, 16-term half h, slice p:
+// 64 rows x 16 bytes, a contiguous 1 KiB run that is also contiguous in the
+// global slice layout, so the global->LDS copy is a straight coalesced copy
+// and each MFMA operand read (32 lanes x 16 consecutive bytes) is free of
+// bank conflicts.
+#include "oz_internal.h"
+
+namespace oz {
+
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+// 2^(-7d) for d = dd + 2, exact.
+template <int DD>
+struct DiagScale {
+    static constexpr double value = DiagScale<DD - 1>::value * (1.0 / 128.0);
+};
+template <>
+struct DiagScale<0> {
+    static constexpr double value = 1.0 / 16384.0;
+};
+
+template <int S, int DD>
+__device__ __forceinline__ void fold_diags(double (&acc64)[16], v16i (&acc)[S]) {
+    // d = DD + 2 from the top: DD = S-1, S-2, ..., 0
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc64[r] = acc64[r] + static_cast<double>(acc[DD][r]) * DiagScale<DD>::value;
+    if constexpr (DD > 0) fold_diags<S, DD - 1>(acc64, acc);
+}
+
+template <int S, bool CPLX, bool DIAG>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
+    constexpr int A_CHUNKS = 2 * S * 64;  // 16-byte chunks of one operand per stage
+    constexpr int STAGE = 2 * A_CHUNKS;   // A then B
+    constexpr int LOADS = STAGE / 256;    // chunks per thread per stage (== S)
+    __shared__ v4i lds[2][STAGE];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int half = lane >> 5, row = lane & 31;
+    const int64_t tn = blockIdx.x, tm = blockIdx.y;
+    const v4i* SA = reinterpret_cast<const v4i*>(g.SA);
+    const v4i* SB = reinterpret_cast<const v4i*>(g.SB);
+    const int64_t nsteps = g.kpad / kStep;
+
+    v4i pre[LOADS];
+    auto gload = [&](int64_t ks) {
+#pragma unroll
+        for (int i = 0; i < LOADS; ++i) {
+            const int c = tid + 256 * i;
+            if (c < A_CHUNKS)
+                pre[i] = SA[(2 * ks * S + c / 64) * g.Mp + tm * 64 + (c % 64)];
+            else
+                pre[i] = SB[(2 * ks * S + (c - A_CHUNKS) / 64) * g.Np + tn * 64 + ((c - A_CHUNKS) % 64)];
+        }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < LOADS; ++i) lds[buf][tid + 256 * i] = pre[i];
+    };
+
+    v16i acc[S];
+#pragma unroll
+    for (int d = 0; d < S; ++d)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[d][r] = 0;
+    double acc64[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc64[r] = 0.0;
+
+    // rows / column of this lane's 16 accumulator entries inside the tile
+    const int64_t col = tn * 64 + wn * 32 + row;
+    auto row_of = [&](int r) -> int64_t { return tm * 64 + wm * 32 + 8 * (r >> 2) + 4 * half + (r & 3); };
+
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    int64_t chunk_pos = 0, chunk = 0;
+    for (int64_t ks = 0; ks < nsteps; ++ks) {
+        const int buf = static_cast<int>(ks & 1);
+        if (ks + 1 < nsteps) gload(ks + 1);
+        const v4i* L = lds[buf];
+        v4i bq[S];
+#pragma unroll
+        for (int q = 0; q < S; ++q) bq[q] = L[A_CHUNKS + (half * S + q) * 64 + wn * 32 + row];
+#pragma unroll
+        for (int p = 0; p < S; ++p) {
+            const v4i a = L[(half * S + p) * 64 + wm * 32 + row];
+#pragma unroll
+            for (int q = 0; q < S - p; ++q)
+                acc[p + q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, bq[q], acc[p + q], 0, 0, 0);
+        }
+        if (++chunk_pos == g.chunk_steps || ks + 1 == nsteps) {
+            if constexpr (DIAG) {
+#pragma unroll
+                for (int d = 0; d < S; ++d)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r)
+                        g.diag_out[((chunk * S + d) * g.Np + col) * g.Mp + row_of(r)] = acc[d][r];
+            } else {
+                fold_diags<S, S - 1>(acc64, acc);
+            }
+#pragma unroll
+            for (int d = 0; d < S; ++d)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[d][r] = 0;
+            chunk_pos = 0;
+            ++chunk;
+        }
+        if (ks + 1 < nsteps) lstore(buf ^ 1);
+        __syncthreads();
+    }
+    if constexpr (DIAG) return;
+
+    const double nan = __longlong_as_double(0x7ff8000000000000ll);
+    if (col >= g.n) return;
+    const int32_t f = g.FB[col];
+    if constexpr (!CPLX) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int64_t i = row_of(r);
+            if (i >= g.m) continue;
+            const int32_t e = g.EA[i];
+            double* c = g.C + i + col * g.ldc;
+            double out;
+            if (e == kNonFiniteExp || f == kNonFiniteExp) {
+                out = nan;
+            } else {
+                const double v = ldexp(acc64[r], e + f);
+                out = g.alpha_r * v;
+                if (!g.beta_zero) out = out + g.beta_r * (*c);
+            }
+            *c = out;
+        }
+    } else {
+        // tile rows: 32 per wave = 16 complex rows; register r (r%8 < 4) holds the
+        // real part and r + 4 the imaginary part of complex row
+        // (tm*64 + wm*32)/2 + 8*(r/8) + 4*half + r%4
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            if ((r & 4) != 0) continue;
+            const int64_t ci = (tm * 64 + wm * 32) / 2 + 8 * (r >> 3) + 4 * half + (r & 3);
+            if (ci >= g.m) continue;
+            const int32_t e = g.EA[ci];
+            double* c = g.C + 2 * (ci + col * g.ldc);
+            double outr, outi;
+            if (e == kNonFiniteExp || f == kNonFiniteExp) {
+                outr = outi = nan;
+            } else {
+                const double vr = ldexp(acc64[r], e + f);
+                const double vi = ldexp(acc64[r + 4], e + f);
+                outr = g.alpha_r * vr - g.alpha_i * vi;
+                outi = g.alpha_r * vi + g.alpha_i * vr;
+                if (!g.beta_zero) {
+                    const double cr = c[0], cim = c[1];
+                    outr = outr + (g.beta_r * cr - g.beta_i * cim);
+                    outi = outi + (g.beta_r * cim + g.beta_i * cr);
+                }
+            }
+            c[0] = outr;
+            c[1] = outi;
+        }
+    }
+}
+
+__global__ void scale_c_kernel(double* C, int64_t ldc, int64_t m, int64_t n, int cplx, double br, double bi,
+                               int beta_zero) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    for (int64_t j = blockIdx.y; j < n; j += gridDim.y) {
+        if (!cplx) {
+            double* c = C + i + j * ldc;
+            *c = beta_zero ? 0.0 : br * (*c);
+        } else {
+            double* c = C + 2 * (i + j * ldc);
+            if (beta_zero) {
+                c[0] = 0.0;
+                c[1] = 0.0;
+            } else {
+                const double cr = c[0], cim = c[1];
+                c[0] = br * cr - bi * cim;
+                c[1] = br * cim + bi * cr;
+            }
+        }
+    }
+}
+
+template <int S>
+hipError_t launch_s(const GemmArgs& g, hipStream_t st) {
+    dim3 grid(static_cast<unsigned>(g.Np / kTile), static_cast<unsigned>(g.Mp / kTile));
+    if (g.diag_out)
+        hipLaunchKernelGGL((gemm_kernel<S, false, true>), grid, dim3(256), 0, st, g);
+    else if (g.cplx)
+        hipLaunchKernelGGL((gemm_kernel<S, true, false>), grid, dim3(256), 0, st, g);
+    else
+        hipLaunchKernelGGL((gemm_kernel<S, false, false>), grid, dim3(256), 0, st, g);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_gemm(const GemmArgs& g, hipStream_t st) {
+    switch (g.s) {
+        case 1: return launch_s<1>(g, st);
+        case 2: return launch_s<2>(g, st);
+        case 3: return launch_s<3>(g, st);
+        case 4: return launch_s<4>(g, st);
+        case 5: return launch_s<5>(g, st);
+        case 6: return launch_s<6>(g, st);
+        case 7: return launch_s<7>(g, st);
+        case 8: return launch_s<8>(g, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_scale_c(double* C, int64_t ldc, int64_t m, int64_t n, int cplx, double br, double bi,
+                          int beta_zero, hipStream_t st) {
+    if (m <= 0 || n <= 0) return hipSuccess;
+    dim3 grid(static_cast<unsigned>((m + 255) / 256), static_cast<unsigned>(n < 65535 ? n : 65535));
+    hipLaunchKernelGGL(scale_c_kernel, grid, dim3(256), 0, st, C, ldc, m, n, cplx, br, bi, beta_zero);
+    return hipGetLastError();
+}
+
+}  // namespace oz

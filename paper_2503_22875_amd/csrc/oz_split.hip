@@ -1,0 +1,267 @@
+// oz_split.hip -- scale exponents and INT8 digits of one operand (the
+// splitting step of the Ozaki scheme, paper Sec. 2.2).
+//
+// Pure integer work on the IEEE-754 bit pattern: no FP64 arithmetic runs
+// here.  Two passes, both bound by HBM bandwidth:
+//   scan   : per vector (row of op(A) / column of op(B)) the largest magnitude
+//            as raw bits; the unsigned order of |x| bit patterns is the order
+//            of |x|, so a max over uint64 is the max over values (atomicMax
+//            merges the partial maxima of a 2-D grid).
+//   digits : E = frexp exponent of that maximum; digit p of x is
+//            floor(|x| * 2^(7p - E)) mod 128 with the sign of x, read off the
+//            53-bit significand by one shift; written in the K-blocked slice
+//            layout the GEMM kernel streams (see oz.h).
+#include "oz_internal.h"
+
+namespace oz {
+
+namespace {
+
+constexpr uint64_t kMagMask = 0x7fffffffffffffffull;
+constexpr uint64_t kMantMask = (1ull << 52) - 1;
+constexpr uint64_t kInfBits = 0x7ff0000000000000ull;
+
+__device__ __forceinline__ uint64_t mag_bits(double x) {
+    return static_cast<uint64_t>(__double_as_longlong(x)) & kMagMask;
+}
+
+__device__ __forceinline__ uint64_t umax64(uint64_t a, uint64_t b) { return a > b ? a : b; }
+
+// frexp exponent of the value whose magnitude bits are b (b finite, nonzero).
+__device__ __forceinline__ int frexp_exp_bits(uint64_t b) {
+    int eb = static_cast<int>(b >> 52);
+    if (eb > 0) return eb - 1022;
+    // subnormal: value = mant * 2^-1074, frexp exponent = bitlength(mant) - 1074
+    return (64 - __clzll(static_cast<long long>(b & kMantMask))) - 1074;
+}
+
+__device__ __forceinline__ int32_t exponent_of_max(uint64_t b) {
+    if (b == 0) return 0;
+    if (b >= kInfBits) return kNonFiniteExp;
+    return frexp_exp_bits(b);
+}
+
+// Digit decomposition of one double under scale exponent E.
+struct Sig {
+    uint64_t M;  // significand as an integer (with the hidden bit when normal)
+    int sh0;     // right shift giving floor(|x| * 2^-E) scaled by 2^0 ... see digit()
+    bool neg;
+};
+
+__device__ __forceinline__ Sig sig_of(double x, int E) {
+    uint64_t b = static_cast<uint64_t>(__double_as_longlong(x));
+    Sig g;
+    g.neg = (b >> 63) != 0;
+    uint64_t mag = b & kMagMask;
+    int eb = static_cast<int>(mag >> 52);
+    g.M = (mag & kMantMask) | (eb ? (1ull << 52) : 0ull);
+    int e_eff = eb ? eb : 1;  // |x| = M * 2^(e_eff - 1075)
+    // digit p = floor(M * 2^(e_eff - 1075 + 7p - E)) mod 128: right shift by sh0 - 7p
+    g.sh0 = 1075 + E - e_eff;
+    return g;
+}
+
+__device__ __forceinline__ int digit(const Sig& g, int p /* 1-based */) {
+    int sh = g.sh0 - 7 * p;
+    uint32_t t;
+    if (sh >= 64)
+        t = 0;
+    else if (sh >= 0)
+        t = static_cast<uint32_t>(g.M >> sh) & 127u;
+    else if (sh > -7)
+        t = static_cast<uint32_t>(g.M << (-sh)) & 127u;
+    else
+        t = 0;
+    return g.neg ? -static_cast<int>(t) : static_cast<int>(t);
+}
+
+__global__ void zero_u64_kernel(uint64_t* p, int64_t n) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+// One block: 64 vectors x lspan terms.
+// LCONTIG: terms of a vector are contiguous (sl == 1): each wave walks 16
+//          vectors, its 64 lanes reading 64 consecutive terms.
+// else   : vectors are contiguous (sv == 1): lane = vector, the 4 waves
+//          split the terms, partial maxima merged through LDS.
+template <bool LCONTIG, bool CPLX>
+__global__ __launch_bounds__(256) void scan_kernel(OperandView op, uint64_t* maxbits, int64_t lspan) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t v0 = static_cast<int64_t>(blockIdx.y) * 64;
+    const int64_t l0 = static_cast<int64_t>(blockIdx.x) * lspan;
+    const int64_t l1 = (l0 + lspan < op.k) ? l0 + lspan : op.k;
+    const int w = CPLX ? 2 : 1;
+    if (LCONTIG) {
+        for (int vi = 0; vi < 16; ++vi) {
+            const int64_t v = v0 + wave * 16 + vi;
+            if (v >= op.nv) break;  // wave-uniform
+            uint64_t mx = 0;
+            const double* base = op.X + v * op.sv * w;
+            for (int64_t l = l0 + lane; l < l1; l += 64) {
+                mx = umax64(mx, mag_bits(base[l * op.sl * w]));
+                if (CPLX) mx = umax64(mx, mag_bits(base[l * op.sl * w + 1]));
+            }
+            for (int off = 32; off > 0; off >>= 1) mx = umax64(mx, __shfl_xor(mx, off));
+            if (lane == 0 && mx != 0) atomicMax(reinterpret_cast<unsigned long long*>(maxbits + v), mx);
+        }
+    } else {
+        __shared__ uint64_t red[4][64];
+        const int64_t v = v0 + lane;
+        uint64_t mx = 0;
+        if (v < op.nv) {
+            for (int64_t l = l0 + wave; l < l1; l += 4) {
+                const double* e = op.X + (v + l * op.sl) * w;
+                mx = umax64(mx, mag_bits(e[0]));
+                if (CPLX) mx = umax64(mx, mag_bits(e[1]));
+            }
+        }
+        red[wave][lane] = mx;
+        __syncthreads();
+        if (wave == 0 && v < op.nv) {
+            mx = umax64(umax64(red[0][lane], red[1][lane]), umax64(red[2][lane], red[3][lane]));
+            if (mx != 0) atomicMax(reinterpret_cast<unsigned long long*>(maxbits + v), mx);
+        }
+    }
+}
+
+// Slice byte offset of (term t, digit p 0-based, vector r) in the layout of oz.h.
+__device__ __forceinline__ int64_t slice_off(int64_t t, int p, int64_t r, int s, int64_t rows_pad) {
+    return (((t >> 4) * s + p) * rows_pad + r) * 16 + (t & 15);
+}
+
+__device__ __forceinline__ uint64_t pack8(const int* d) {
+    uint64_t r = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) r |= static_cast<uint64_t>(static_cast<uint8_t>(static_cast<int8_t>(d[i]))) << (8 * i);
+    return r;
+}
+
+// One block: 64 vectors (64 complex rows for a complex side-'A' operand) x one
+// MFMA step of 32 terms.  Each thread owns 8 consecutive terms of one vector:
+// 8 real elements, or 4 complex elements (terms 2l, 2l+1).
+template <bool LCONTIG, bool CPLX, bool SIDE_A>
+__global__ __launch_bounds__(256) void digits_kernel(OperandView op, const uint64_t* maxbits, SliceLayout lay,
+                                                     int32_t* E, int8_t* slices) {
+    const int tid = threadIdx.x;
+    const int vi = LCONTIG ? (tid >> 2) : (tid & 63);
+    const int sub = LCONTIG ? (tid & 3) : (tid >> 6);
+    const int64_t v = static_cast<int64_t>(blockIdx.y) * 64 + vi;
+    const int64_t step = blockIdx.x;
+    const int64_t t0 = step * kStep + sub * 8;  // first term of this thread
+    const bool live = v < op.nv;
+
+    int32_t ex = 0;
+    if (live) ex = exponent_of_max(maxbits[v]);
+    const bool bad = ex == kNonFiniteExp;
+    if (live && step == 0 && sub == 0) E[v] = ex;
+
+    // 8 doubles: real -> elements l = t0 .. t0+7; complex -> l = t0/2 .. t0/2+3 (re, im)
+    double x[8];
+    constexpr int NEL = CPLX ? 4 : 8;
+    const int64_t lbase = CPLX ? t0 / 2 : t0;
+#pragma unroll
+    for (int e = 0; e < NEL; ++e) {
+        const int64_t l = lbase + e;
+        double re = 0.0, im = 0.0;
+        if (live && !bad && l < op.k) {
+            const double* src = op.X + (v * op.sv + l * op.sl) * (CPLX ? 2 : 1);
+            re = src[0];
+            if (CPLX) im = op.conj ? -src[1] : src[1];
+        }
+        if (CPLX) {
+            x[2 * e] = re;
+            x[2 * e + 1] = im;
+        } else {
+            x[e] = re;
+        }
+    }
+    Sig g[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) g[e] = sig_of(x[e], ex);
+
+    if (CPLX && SIDE_A) {
+        // real-part row holds (ar, -ai), imaginary-part row holds (ai, ar)
+        const int64_t r_re = 32 * (v >> 4) + 16 * ((v >> 3) & 1) + (v & 7);
+        const int64_t r_im = r_re + 8;
+        if (r_re >= lay.rows_pad) return;
+        for (int p = 0; p < lay.s; ++p) {
+            int dre[8], dim[8];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int ar = digit(g[2 * e], p + 1), ai = digit(g[2 * e + 1], p + 1);
+                dre[2 * e] = ar;
+                dre[2 * e + 1] = -ai;
+                dim[2 * e] = ai;
+                dim[2 * e + 1] = ar;
+            }
+            *reinterpret_cast<uint64_t*>(slices + slice_off(t0, p, r_re, lay.s, lay.rows_pad)) = pack8(dre);
+            *reinterpret_cast<uint64_t*>(slices + slice_off(t0, p, r_im, lay.s, lay.rows_pad)) = pack8(dim);
+        }
+    } else {
+        if (v >= lay.rows_pad) return;
+        for (int p = 0; p < lay.s; ++p) {
+            int d[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) d[e] = digit(g[e], p + 1);
+            *reinterpret_cast<uint64_t*>(slices + slice_off(t0, p, v, lay.s, lay.rows_pad)) = pack8(d);
+        }
+    }
+}
+
+}  // namespace
+
+SliceLayout slice_layout(int side_a, int cplx, int64_t nv, int64_t k, int s) {
+    SliceLayout L;
+    int64_t rows = (cplx && side_a) ? 2 * round_up(nv, 16) : nv;
+    L.rows_pad = round_up(rows > 0 ? rows : 1, kTile);
+    int64_t terms = cplx ? 2 * k : k;
+    L.kpad = round_up(terms > 0 ? terms : 1, kStep);
+    L.s = s;
+    return L;
+}
+
+hipError_t launch_zero_u64(uint64_t* p, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan(const OperandView& op, uint64_t* maxbits, hipStream_t st) {
+    if (op.nv <= 0 || op.k <= 0) return hipSuccess;
+    const bool lcontig = op.sl == 1;
+    const int64_t lspan = 512;
+    dim3 grid(static_cast<unsigned>((op.k + lspan - 1) / lspan), static_cast<unsigned>((op.nv + 63) / 64));
+    if (lcontig) {
+        if (op.cplx) hipLaunchKernelGGL((scan_kernel<true, true>), grid, dim3(256), 0, st, op, maxbits, lspan);
+        else hipLaunchKernelGGL((scan_kernel<true, false>), grid, dim3(256), 0, st, op, maxbits, lspan);
+    } else {
+        if (op.cplx) hipLaunchKernelGGL((scan_kernel<false, true>), grid, dim3(256), 0, st, op, maxbits, lspan);
+        else hipLaunchKernelGGL((scan_kernel<false, false>), grid, dim3(256), 0, st, op, maxbits, lspan);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_digits(const OperandView& op, const uint64_t* maxbits, const SliceLayout& lay, int32_t* E,
+                         int8_t* slices, hipStream_t st) {
+    const bool lcontig = op.sl == 1;
+    const bool two_row = op.cplx && op.side_a;
+    // blocks along vectors: 64 vectors each (64 complex rows = 128 slice rows for two_row)
+    const int64_t vec_cover = two_row ? lay.rows_pad / 2 : lay.rows_pad;
+    dim3 grid(static_cast<unsigned>(lay.kpad / kStep), static_cast<unsigned>((vec_cover + 63) / 64));
+#define OZ_DIG(LC, CP, SA) \
+    hipLaunchKernelGGL((digits_kernel<LC, CP, SA>), grid, dim3(256), 0, st, op, maxbits, lay, E, slices)
+    if (lcontig) {
+        if (two_row) OZ_DIG(true, true, true);
+        else if (op.cplx) OZ_DIG(true, true, false);
+        else OZ_DIG(true, false, false);
+    } else {
+        if (two_row) OZ_DIG(false, true, true);
+        else if (op.cplx) OZ_DIG(false, true, false);
+        else OZ_DIG(false, false, false);
+    }
+#undef OZ_DIG
+    return hipGetLastError();
+}
+
+}  // namespace oz
