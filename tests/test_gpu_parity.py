@@ -296,7 +296,7 @@ def test_deterministic(oz, handle):
     A, B = wide(rng, (200, 300), 10, True), wide(rng, (300, 150), 10, True)
     g1 = run_gemm(oz, handle, 1, "N", "N", A, B, 7)
     g2 = run_gemm(oz, handle, 1, "N", "N", A, B, 7)
-    assert np.array_equal(g1.view(np.float64), g2.view(np.float64))
+    assert np.array_equal(np.ascontiguousarray(g1).view(np.float64), np.ascontiguousarray(g2).view(np.float64))
 
 
 # ----------------------------------------------------------------- full sizes, sampled
