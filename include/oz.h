@@ -139,6 +139,15 @@ int oz_zgemm(oz_handle_t handle, char transa, char transb, int64_t m, int64_t n,
              const double* alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
              const double* beta, double* C, int64_t ldc, const oz_prec_t* prec, oz_report_t* rep);
 
+/* Profiling aid.  While enabled, every oz_dgemm / oz_zgemm call records HIP
+ * events on the handle's stream before its split kernels, between the split
+ * kernels and the GEMM kernel, and after the GEMM kernel.  oz_timing_read
+ * waits for the stream, returns the summed milliseconds of the split phase
+ * and of the GEMM kernel and the number of timed calls since the previous
+ * read, and starts a new count.  Any output pointer may be NULL. */
+int oz_timing_enable(oz_handle_t handle, int enable);
+int oz_timing_read(oz_handle_t handle, double* split_ms, double* gemm_ms, int64_t* calls);
+
 /* ---- The steps of the method, exposed for verification ------------------
  *
  * Slice layout (the library's own, shared by its kernels):

@@ -23,7 +23,8 @@ OZ_MAX_SLICES = 18
 
 # Every symbol include/oz.h declares (checked by the CPU test-suite).
 EXPORTS = ["oz_create", "oz_destroy", "oz_set_stream", "oz_status_string", "oz_workspace_size",
-           "oz_set_workspace", "oz_dgemm", "oz_zgemm", "oz_split_layout", "oz_split", "oz_diag_sums"]
+           "oz_set_workspace", "oz_dgemm", "oz_zgemm", "oz_split_layout", "oz_split", "oz_diag_sums",
+           "oz_timing_enable", "oz_timing_read"]
 
 
 class OzError(RuntimeError):
@@ -63,6 +64,8 @@ def _load():
         "oz_split_layout": [C, ctypes.c_int, I64, I64, I32, PP(I64), PP(I64), PP(ctypes.c_size_t)],
         "oz_split": [P, C, C, ctypes.c_int, I64, I64, P, I64, I32, P, P],
         "oz_diag_sums": [P, I32, I64, I64, I64, I64, P, P, P],
+        "oz_timing_enable": [P, ctypes.c_int],
+        "oz_timing_read": [P, PP(D), PP(D), PP(I64)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -166,3 +169,14 @@ def oz_split(handle, side, trans, is_complex, nv, k, X, ldx, slices, E, slices_o
 def oz_diag_sums(handle, slices, kchunk, rows_pad_a, rows_pad_b, kpad, slices_a, slices_b, out):
     return _check("oz_diag_sums", _lib.oz_diag_sums(handle, slices, kchunk, rows_pad_a, rows_pad_b, kpad,
                                                     _ptr(slices_a), _ptr(slices_b), _ptr(out)))
+
+
+def oz_timing_enable(handle, enable=True):
+    return _check("oz_timing_enable", _lib.oz_timing_enable(handle, int(enable)))
+
+
+def oz_timing_read(handle):
+    """-> (split_ms, gemm_ms, calls) summed since the previous read."""
+    a, b, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+    _check("oz_timing_read", _lib.oz_timing_read(handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(n)))
+    return a.value, b.value, n.value

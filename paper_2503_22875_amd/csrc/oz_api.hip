@@ -17,6 +17,10 @@ struct oz_handle_s {
     void* ws;
     size_t ws_bytes;
     bool ws_owned;
+    // profiling: event triples (before split, before GEMM, after GEMM) per call
+    bool timing;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<hipEvent_t> ev_pending;
 };
 
 namespace {
@@ -121,6 +125,21 @@ oz::OperandView view_b(char tb, const double* B, int64_t ldb, int64_t n, int64_t
 
 int hip_status(hipError_t e) { return e == hipSuccess ? OZ_OK : OZ_ERR_HIP; }
 
+// Record a timing event on the handle's stream (no-op unless timing is on).
+hipError_t mark(oz_handle_t h) {
+    if (!h->timing) return hipSuccess;
+    hipEvent_t ev;
+    if (!h->ev_pool.empty()) {
+        ev = h->ev_pool.back();
+        h->ev_pool.pop_back();
+    } else {
+        hipError_t e = hipEventCreate(&ev);
+        if (e != hipSuccess) return e;
+    }
+    h->ev_pending.push_back(ev);
+    return hipEventRecord(ev, h->stream);
+}
+
 bool grid_fits(const Plan& p) {
     // gemm grid: y = Mp/64; scan grid y = nv/64; keep within 65535
     return p.la.rows_pad / oz::kTile <= 65535 && p.lb.rows_pad / oz::kTile <= 65535 &&
@@ -190,7 +209,8 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
 
     oz::OperandView va = view_a(transa, A, lda, m, k, cplx);
     oz::OperandView vb = view_b(transb, B, ldb, n, k, cplx);
-    hipError_t e = oz::launch_zero_u64(maxa, static_cast<int64_t>((p.off_ea - p.off_maxa) / 8), h->stream);
+    hipError_t e = mark(h);
+    if (e == hipSuccess) e = oz::launch_zero_u64(maxa, static_cast<int64_t>((p.off_ea - p.off_maxa) / 8), h->stream);
     if (e == hipSuccess) e = oz::launch_scan(va, maxa, h->stream);
     if (e == hipSuccess) e = oz::launch_scan(vb, maxb, h->stream);
     if (e == hipSuccess) e = oz::launch_digits(va, maxa, p.la, EA, SA, h->stream);
@@ -219,7 +239,9 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
     g.beta_i = bi;
     g.beta_zero = beta_zero ? 1 : 0;
     g.diag_out = nullptr;
-    e = oz::launch_gemm(g, h->stream);
+    e = mark(h);
+    if (e == hipSuccess) e = oz::launch_gemm(g, h->stream);
+    if (e == hipSuccess) e = mark(h);
     if (e != hipSuccess) return OZ_ERR_HIP;
 
     if (rep) {
@@ -258,6 +280,7 @@ int oz_create(oz_handle_t* handle, int device) {
     h->ws = nullptr;
     h->ws_bytes = 0;
     h->ws_owned = true;
+    h->timing = false;
     *handle = h;
     return OZ_OK;
 }
@@ -267,9 +290,40 @@ int oz_destroy(oz_handle_t h) {
     use_device(h);
     hipStreamSynchronize(h->stream);
     if (h->ws_owned && h->ws) hipFree(h->ws);
+    for (hipEvent_t ev : h->ev_pool) hipEventDestroy(ev);
+    for (hipEvent_t ev : h->ev_pending) hipEventDestroy(ev);
     h->magic = 0;
     delete h;
     return OZ_OK;
+}
+
+int oz_timing_enable(oz_handle_t h, int enable) {
+    if (!valid(h)) return OZ_ERR_HANDLE;
+    h->timing = enable != 0;
+    return OZ_OK;
+}
+
+int oz_timing_read(oz_handle_t h, double* split_ms, double* gemm_ms, int64_t* calls) {
+    if (!valid(h)) return OZ_ERR_HANDLE;
+    if (use_device(h)) return OZ_ERR_HIP;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return OZ_ERR_HIP;
+    double ts = 0.0, tg = 0.0;
+    const size_t n = h->ev_pending.size() / 3;
+    int st = OZ_OK;
+    for (size_t c = 0; c < n; ++c) {
+        float a = 0.f, b = 0.f;
+        hipEvent_t* e = &h->ev_pending[3 * c];
+        if (hipEventElapsedTime(&a, e[0], e[1]) != hipSuccess || hipEventElapsedTime(&b, e[1], e[2]) != hipSuccess)
+            st = OZ_ERR_HIP;
+        ts += a;
+        tg += b;
+    }
+    for (hipEvent_t ev : h->ev_pending) h->ev_pool.push_back(ev);
+    h->ev_pending.clear();
+    if (split_ms) *split_ms = ts;
+    if (gemm_ms) *gemm_ms = tg;
+    if (calls) *calls = static_cast<int64_t>(n);
+    return st;
 }
 
 int oz_set_stream(oz_handle_t h, void* stream) {

@@ -18,9 +18,11 @@
 //
 // LDS stage (double buffered): for each operand, 16-term half h, slice p:
 // 64 rows x 16 bytes, a contiguous 1 KiB run that is also contiguous in the
-// global slice layout, so the global->LDS copy is a straight coalesced copy
-// and each MFMA operand read (32 lanes x 16 consecutive bytes) is free of
-// bank conflicts.
+// global slice layout.  The copy is done by global_load_lds_dwordx4 (global
+// memory straight into LDS, 16 bytes per lane, no staging registers), one
+// wave per 1 KiB run, and each MFMA operand read (32 lanes x 16 consecutive
+// bytes) is free of bank conflicts.  The next stage's copy is in flight while
+// the MFMAs of the current stage run.
 #include "oz_internal.h"
 
 namespace oz {
@@ -48,8 +50,34 @@ __device__ __forceinline__ void fold_diags(double (&acc64)[16], v16i (&acc)[S]) 
     if constexpr (DD > 0) fold_diags<S, DD - 1>(acc64, acc);
 }
 
-template <int S, bool CPLX, bool DIAG>
-__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
+// Tile order: the hardware hands consecutive blocks to the 8 XCDs in turn,
+// and each XCD has its own L2.  Block b is given the tile t = start(x) + b/8 of
+// a contiguous range per XCD x = b % 8, and inside that range tiles run in
+// groups of kGroupM tile rows, column by column, so the blocks resident on one
+// XCD at a time share a few 64-row slices of A' and 64-column slices of B'.
+constexpr int kXcds = 8;
+constexpr int kGroupM = 8;
+
+__device__ __forceinline__ void tile_of_block(int64_t b, int64_t tiles_m, int64_t tiles_n, int64_t& tm,
+                                              int64_t& tn) {
+    const int64_t T = tiles_m * tiles_n;
+    const int64_t x = b % kXcds, r = b / kXcds;
+    const int64_t q = T / kXcds, rr = T % kXcds;
+    const int64_t t = x * q + (x < rr ? x : rr) + r;
+    const int64_t per_group = static_cast<int64_t>(kGroupM) * tiles_n;
+    const int64_t grp = t / per_group, in = t % per_group;
+    const int64_t gm0 = grp * kGroupM;
+    const int64_t gh = (tiles_m - gm0) < kGroupM ? (tiles_m - gm0) : kGroupM;
+    tm = gm0 + in % gh;
+    tn = in / gh;
+}
+
+typedef __attribute__((address_space(3))) void lds_void;
+typedef __attribute__((address_space(1))) const void global_cvoid;
+
+template <int S, bool CPLX, bool DIAG, bool MULTI>
+__global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(2, 2)))
+void gemm_kernel(GemmArgs g) {
     constexpr int A_CHUNKS = 2 * S * 64;  // 16-byte chunks of one operand per stage
     constexpr int STAGE = 2 * A_CHUNKS;   // A then B
     constexpr int LOADS = STAGE / 256;    // chunks per thread per stage (== S)
@@ -58,25 +86,27 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int half = lane >> 5, row = lane & 31;
-    const int64_t tn = blockIdx.x, tm = blockIdx.y;
+    int64_t tm, tn;
+    tile_of_block(blockIdx.x, g.Mp / kTile, g.Np / kTile, tm, tn);
     const v4i* SA = reinterpret_cast<const v4i*>(g.SA);
     const v4i* SB = reinterpret_cast<const v4i*>(g.SB);
     const int64_t nsteps = g.kpad / kStep;
 
-    v4i pre[LOADS];
-    auto gload = [&](int64_t ks) {
+    // Stage ks -> LDS buffer: wave w moves chunks w*64 + 256*i + lane (i < S),
+    // each lane 16 bytes, straight into LDS (no staging registers).  A chunk c
+    // (c < A_CHUNKS) is 16-term half h, slice p = (c/64) split as h*S + p, row
+    // c % 64; the 64 chunks of one wave are 1 KiB contiguous in global memory.
+    auto issue = [&](int64_t ks, int buf) {
 #pragma unroll
         for (int i = 0; i < LOADS; ++i) {
-            const int c = tid + 256 * i;
-            if (c < A_CHUNKS)
-                pre[i] = SA[(2 * ks * S + c / 64) * g.Mp + tm * 64 + (c % 64)];
+            const int cw = wave * 64 + 256 * i;  // first chunk of this wave (uniform)
+            const v4i* src;
+            if (cw < A_CHUNKS)
+                src = SA + (2 * ks * S + cw / 64) * g.Mp + tm * 64 + lane;
             else
-                pre[i] = SB[(2 * ks * S + (c - A_CHUNKS) / 64) * g.Np + tn * 64 + ((c - A_CHUNKS) % 64)];
+                src = SB + (2 * ks * S + (cw - A_CHUNKS) / 64) * g.Np + tn * 64 + lane;
+            __builtin_amdgcn_global_load_lds((global_cvoid*)(src), (lds_void*)(&lds[buf][cw]), 16, 0, 0);
         }
-    };
-    auto lstore = [&](int buf) {
-#pragma unroll
-        for (int i = 0; i < LOADS; ++i) lds[buf][tid + 256 * i] = pre[i];
     };
 
     v16i acc[S];
@@ -85,20 +115,22 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[d][r] = 0;
     double acc64[16];
+    if constexpr (MULTI) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc64[r] = 0.0;
+        for (int r = 0; r < 16; ++r) acc64[r] = 0.0;
+    }
 
     // rows / column of this lane's 16 accumulator entries inside the tile
     const int64_t col = tn * 64 + wn * 32 + row;
     auto row_of = [&](int r) -> int64_t { return tm * 64 + wm * 32 + 8 * (r >> 2) + 4 * half + (r & 3); };
 
-    gload(0);
-    lstore(0);
+    issue(0, 0);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     int64_t chunk_pos = 0, chunk = 0;
     for (int64_t ks = 0; ks < nsteps; ++ks) {
         const int buf = static_cast<int>(ks & 1);
-        if (ks + 1 < nsteps) gload(ks + 1);
+        if (ks + 1 < nsteps) issue(ks + 1, buf ^ 1);
         const v4i* L = lds[buf];
         v4i bq[S];
 #pragma unroll
@@ -110,27 +142,34 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
             for (int q = 0; q < S - p; ++q)
                 acc[p + q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, bq[q], acc[p + q], 0, 0, 0);
         }
-        if (++chunk_pos == g.chunk_steps || ks + 1 == nsteps) {
-            if constexpr (DIAG) {
+        if constexpr (MULTI || DIAG) {
+            if (++chunk_pos == g.chunk_steps || ks + 1 == nsteps) {
+                if constexpr (DIAG) {
+#pragma unroll
+                    for (int d = 0; d < S; ++d)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r)
+                            g.diag_out[((chunk * S + d) * g.Np + col) * g.Mp + row_of(r)] = acc[d][r];
+                } else {
+                    fold_diags<S, S - 1>(acc64, acc);
+                }
 #pragma unroll
                 for (int d = 0; d < S; ++d)
 #pragma unroll
-                    for (int r = 0; r < 16; ++r)
-                        g.diag_out[((chunk * S + d) * g.Np + col) * g.Mp + row_of(r)] = acc[d][r];
-            } else {
-                fold_diags<S, S - 1>(acc64, acc);
+                    for (int r = 0; r < 16; ++r) acc[d][r] = 0;
+                chunk_pos = 0;
+                ++chunk;
             }
-#pragma unroll
-            for (int d = 0; d < S; ++d)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) acc[d][r] = 0;
-            chunk_pos = 0;
-            ++chunk;
         }
-        if (ks + 1 < nsteps) lstore(buf ^ 1);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
     }
     if constexpr (DIAG) return;
+    if constexpr (!MULTI) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc64[r] = 0.0;
+        fold_diags<S, S - 1>(acc64, acc);
+    }
 
     const double nan = __longlong_as_double(0x7ff8000000000000ll);
     if (col >= g.n) return;
@@ -207,13 +246,20 @@ __global__ void scale_c_kernel(double* C, int64_t ldc, int64_t m, int64_t n, int
 
 template <int S>
 hipError_t launch_s(const GemmArgs& g, hipStream_t st) {
-    dim3 grid(static_cast<unsigned>(g.Np / kTile), static_cast<unsigned>(g.Mp / kTile));
+    const int64_t blocks = (g.Np / kTile) * (g.Mp / kTile);
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    dim3 grid(static_cast<unsigned>(blocks));
+    const bool multi = g.chunk_steps < g.kpad / kStep;
     if (g.diag_out)
-        hipLaunchKernelGGL((gemm_kernel<S, false, true>), grid, dim3(256), 0, st, g);
+        hipLaunchKernelGGL((gemm_kernel<S, false, true, true>), grid, dim3(256), 0, st, g);
+    else if (g.cplx && multi)
+        hipLaunchKernelGGL((gemm_kernel<S, true, false, true>), grid, dim3(256), 0, st, g);
     else if (g.cplx)
-        hipLaunchKernelGGL((gemm_kernel<S, true, false>), grid, dim3(256), 0, st, g);
+        hipLaunchKernelGGL((gemm_kernel<S, true, false, false>), grid, dim3(256), 0, st, g);
+    else if (multi)
+        hipLaunchKernelGGL((gemm_kernel<S, false, false, true>), grid, dim3(256), 0, st, g);
     else
-        hipLaunchKernelGGL((gemm_kernel<S, false, false>), grid, dim3(256), 0, st, g);
+        hipLaunchKernelGGL((gemm_kernel<S, false, false, false>), grid, dim3(256), 0, st, g);
     return hipGetLastError();
 }
 
