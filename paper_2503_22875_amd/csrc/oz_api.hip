@@ -171,7 +171,6 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
     }
     if (kc < 0 || kc % 64 != 0 || (kc > 0 && kc > kchunk_bound(s))) return 14;
     if (kc == 0) kc = kchunk_bound(s);
-    if (s > oz::kMaxLiveSlices) return OZ_ERR_UNSUPPORTED;
     if (!alpha || !beta) return OZ_ERR_ARG;
 
     if (rep) {
@@ -428,7 +427,6 @@ int oz_diag_sums(oz_handle_t h, int32_t slices, int64_t kchunk, int64_t rows_pad
                  const int8_t* slices_a, const int8_t* slices_b, int32_t* out) {
     if (!valid(h)) return OZ_ERR_HANDLE;
     if (slices < 1 || slices > OZ_MAX_SLICES) return OZ_ERR_ARG;
-    if (slices > oz::kMaxLiveSlices) return OZ_ERR_UNSUPPORTED;
     if (kchunk <= 0 || kchunk % 64 != 0 || kchunk > kchunk_bound(slices)) return OZ_ERR_ARG;
     if (rows_pad_a <= 0 || rows_pad_b <= 0 || rows_pad_a % oz::kTile || rows_pad_b % oz::kTile) return OZ_ERR_ARG;
     if (kpad <= 0 || kpad % oz::kStep) return OZ_ERR_ARG;

@@ -75,6 +75,63 @@ __device__ __forceinline__ void tile_of_block(int64_t b, int64_t tiles_m, int64_
 typedef __attribute__((address_space(3))) void lds_void;
 typedef __attribute__((address_space(1))) const void global_cvoid;
 
+// Final epilogue of a 64 x 64 tile: v = ldexp(acc64, E_i + F_j), then alpha/beta
+// (two rounded products and one rounded add per part, no fused multiply-add),
+// or NaN where the row or column scale marks Inf/NaN input.
+template <bool CPLX, typename RowOf>
+__device__ __forceinline__ void store_tile(const GemmArgs& g, const double (&acc64)[16], int64_t tm, int wm, int half,
+                                           int64_t col, RowOf row_of) {
+    const double nan = __longlong_as_double(0x7ff8000000000000ll);
+    if (col >= g.n) return;
+    const int32_t f = g.FB[col];
+    if constexpr (!CPLX) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int64_t i = row_of(r);
+            if (i >= g.m) continue;
+            const int32_t e = g.EA[i];
+            double* c = g.C + i + col * g.ldc;
+            double out;
+            if (e == kNonFiniteExp || f == kNonFiniteExp) {
+                out = nan;
+            } else {
+                const double v = ldexp(acc64[r], e + f);
+                out = g.alpha_r * v;
+                if (!g.beta_zero) out = out + g.beta_r * (*c);
+            }
+            *c = out;
+        }
+    } else {
+        // tile rows: 32 per wave = 16 complex rows; register r (r%8 < 4) holds the
+        // real part and r + 4 the imaginary part of complex row
+        // (tm*64 + wm*32)/2 + 8*(r/8) + 4*half + r%4
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            if ((r & 4) != 0) continue;
+            const int64_t ci = (tm * 64 + wm * 32) / 2 + 8 * (r >> 3) + 4 * half + (r & 3);
+            if (ci >= g.m) continue;
+            const int32_t e = g.EA[ci];
+            double* c = g.C + 2 * (ci + col * g.ldc);
+            double outr, outi;
+            if (e == kNonFiniteExp || f == kNonFiniteExp) {
+                outr = outi = nan;
+            } else {
+                const double vr = ldexp(acc64[r], e + f);
+                const double vi = ldexp(acc64[r + 4], e + f);
+                outr = g.alpha_r * vr - g.alpha_i * vi;
+                outi = g.alpha_r * vi + g.alpha_i * vr;
+                if (!g.beta_zero) {
+                    const double cr = c[0], cim = c[1];
+                    outr = outr + (g.beta_r * cr - g.beta_i * cim);
+                    outi = outi + (g.beta_r * cim + g.beta_i * cr);
+                }
+            }
+            c[0] = outr;
+            c[1] = outi;
+        }
+    }
+}
+
 template <int S, bool CPLX, bool DIAG, bool MULTI>
 __global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(2, 2)))
 void gemm_kernel(GemmArgs g) {
@@ -171,55 +228,80 @@ void gemm_kernel(GemmArgs g) {
         fold_diags<S, S - 1>(acc64, acc);
     }
 
-    const double nan = __longlong_as_double(0x7ff8000000000000ll);
-    if (col >= g.n) return;
-    const int32_t f = g.FB[col];
-    if constexpr (!CPLX) {
+    store_tile<CPLX>(g, acc64, tm, wm, half, col, row_of);
+}
+
+// Streaming form for any s (used above the all-diagonal kernel's register
+// budget, s > kMaxLiveSlices): one INT32 tile, one anti-diagonal at a time.
+// For each INT32 chunk and each d = s+1 down to 2, the pairs (p, d-p) of that
+// diagonal are streamed step by step (one A slice and one B slice, 4 KiB per
+// stage, double buffered) into the INT32 tile, which is then folded into the
+// FP64 tile -- the same order as the all-diagonal kernel, hence the same bits.
+template <bool CPLX, bool DIAG>
+__global__ __attribute__((amdgpu_flat_work_group_size(256, 256))) void gemm_stream_kernel(GemmArgs g) {
+    __shared__ v4i lds[2][256];  // [A: h*64 + row | B: 128 + h*64 + col]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int half = lane >> 5, row = lane & 31;
+    const int s = g.s;
+    int64_t tm, tn;
+    tile_of_block(blockIdx.x, g.Mp / kTile, g.Np / kTile, tm, tn);
+    const v4i* SA = reinterpret_cast<const v4i*>(g.SA);
+    const v4i* SB = reinterpret_cast<const v4i*>(g.SB);
+    const int64_t nsteps = g.kpad / kStep;
+    const int64_t col = tn * 64 + wn * 32 + row;
+    auto row_of = [&](int r) -> int64_t { return tm * 64 + wm * 32 + 8 * (r >> 2) + 4 * half + (r & 3); };
+
+    // wave 0/1: A half 0/1 of slice p; wave 2/3: B half 0/1 of slice q
+    auto issue = [&](int64_t ks, int p, int q, int buf) {
+        const int h = wave & 1;
+        const v4i* src = (wave < 2) ? SA + ((2 * ks + h) * s + (p - 1)) * g.Mp + tm * 64 + lane
+                                    : SB + ((2 * ks + h) * s + (q - 1)) * g.Np + tn * 64 + lane;
+        __builtin_amdgcn_global_load_lds((global_cvoid*)(src), (lds_void*)(&lds[buf][wave * 64]), 16, 0, 0);
+    };
+
+    double acc64[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int64_t i = row_of(r);
-            if (i >= g.m) continue;
-            const int32_t e = g.EA[i];
-            double* c = g.C + i + col * g.ldc;
-            double out;
-            if (e == kNonFiniteExp || f == kNonFiniteExp) {
-                out = nan;
-            } else {
-                const double v = ldexp(acc64[r], e + f);
-                out = g.alpha_r * v;
-                if (!g.beta_zero) out = out + g.beta_r * (*c);
-            }
-            *c = out;
-        }
-    } else {
-        // tile rows: 32 per wave = 16 complex rows; register r (r%8 < 4) holds the
-        // real part and r + 4 the imaginary part of complex row
-        // (tm*64 + wm*32)/2 + 8*(r/8) + 4*half + r%4
+    for (int r = 0; r < 16; ++r) acc64[r] = 0.0;
+    const int64_t nchunks = (nsteps + g.chunk_steps - 1) / g.chunk_steps;
+    for (int64_t c = 0; c < nchunks; ++c) {
+        const int64_t k0 = c * g.chunk_steps;
+        const int64_t k1 = (k0 + g.chunk_steps < nsteps) ? k0 + g.chunk_steps : nsteps;
+        for (int d = s + 1; d >= 2; --d) {
+            const int plo = (d - s > 1) ? d - s : 1;
+            const int phi = (d - 1 < s) ? d - 1 : s;
+            const int np = phi - plo + 1;
+            const int64_t items = static_cast<int64_t>(np) * (k1 - k0);
+            v16i acc;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            if ((r & 4) != 0) continue;
-            const int64_t ci = (tm * 64 + wm * 32) / 2 + 8 * (r >> 3) + 4 * half + (r & 3);
-            if (ci >= g.m) continue;
-            const int32_t e = g.EA[ci];
-            double* c = g.C + 2 * (ci + col * g.ldc);
-            double outr, outi;
-            if (e == kNonFiniteExp || f == kNonFiniteExp) {
-                outr = outi = nan;
-            } else {
-                const double vr = ldexp(acc64[r], e + f);
-                const double vi = ldexp(acc64[r + 4], e + f);
-                outr = g.alpha_r * vr - g.alpha_i * vi;
-                outi = g.alpha_r * vi + g.alpha_i * vr;
-                if (!g.beta_zero) {
-                    const double cr = c[0], cim = c[1];
-                    outr = outr + (g.beta_r * cr - g.beta_i * cim);
-                    outi = outi + (g.beta_r * cim + g.beta_i * cr);
+            for (int r = 0; r < 16; ++r) acc[r] = 0;
+            issue(k0, plo, d - plo, 0);
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();
+            for (int64_t it = 0; it < items; ++it) {
+                const int buf = static_cast<int>(it & 1);
+                if (it + 1 < items) {
+                    const int p1 = plo + static_cast<int>((it + 1) % np);
+                    issue(k0 + (it + 1) / np, p1, d - p1, buf ^ 1);
                 }
+                const v4i a = lds[buf][half * 64 + wm * 32 + row];
+                const v4i b = lds[buf][128 + half * 64 + wn * 32 + row];
+                acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, acc, 0, 0, 0);
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                __syncthreads();
             }
-            c[0] = outr;
-            c[1] = outi;
+            if constexpr (DIAG) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) g.diag_out[((c * s + (d - 2)) * g.Np + col) * g.Mp + row_of(r)] = acc[r];
+            } else {
+                const double sc = ldexp(1.0, -7 * d);  // exact power of two
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc64[r] = acc64[r] + static_cast<double>(acc[r]) * sc;
+            }
         }
     }
+    if constexpr (DIAG) return;
+    store_tile<CPLX>(g, acc64, tm, wm, half, col, row_of);
 }
 
 __global__ void scale_c_kernel(double* C, int64_t ldc, int64_t m, int64_t n, int cplx, double br, double bi,
@@ -275,8 +357,19 @@ hipError_t launch_gemm(const GemmArgs& g, hipStream_t st) {
         case 6: return launch_s<6>(g, st);
         case 7: return launch_s<7>(g, st);
         case 8: return launch_s<8>(g, st);
-        default: return hipErrorInvalidValue;
+        default: break;
     }
+    if (g.s < 1 || g.s > 18) return hipErrorInvalidValue;
+    const int64_t blocks = (g.Np / kTile) * (g.Mp / kTile);
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    dim3 grid(static_cast<unsigned>(blocks));
+    if (g.diag_out)
+        hipLaunchKernelGGL((gemm_stream_kernel<false, true>), grid, dim3(256), 0, st, g);
+    else if (g.cplx)
+        hipLaunchKernelGGL((gemm_stream_kernel<true, false>), grid, dim3(256), 0, st, g);
+    else
+        hipLaunchKernelGGL((gemm_stream_kernel<false, false>), grid, dim3(256), 0, st, g);
+    return hipGetLastError();
 }
 
 hipError_t launch_scale_c(double* C, int64_t ldc, int64_t m, int64_t n, int cplx, double br, double bi,

@@ -332,3 +332,41 @@ def test_dgemm_wide_range_full_size_sampled(oz, handle):
     got = run_gemm(oz, handle, 0, "N", "N", A, B, 8)
     rows = sampled_rows(4096, 1, 4)
     assert np.array_equal(got[rows], oracle.emu_gemm("N", "N", A, B, 8, rows=rows))
+
+
+# ----------------------------------------------------------------- s above the register-resident range
+
+
+@pytest.mark.parametrize("cplx", [0, 1])
+@pytest.mark.parametrize("s,kc", [(9, 0), (12, 128), (18, 0)])
+def test_large_slice_counts_bit_exact(oz, handle, cplx, s, kc):
+    rng = np.random.default_rng(100 + s)
+    m, n, k = 70, 65, 300
+    A, B = wide(rng, (m, k), 40, bool(cplx)), wide(rng, (k, n), 40, bool(cplx))
+    print("large s", cplx, s, kc, flush=True)
+    got = run_gemm(oz, handle, cplx, "N", "T" if cplx else "N", A, B.T.copy() if cplx else B, s, kc=kc)
+    want = oracle.emu_gemm("N", "T" if cplx else "N", A, B.T.copy() if cplx else B, s, kc=kc if kc else None)
+    assert np.array_equal(got, want)
+
+
+def test_large_slice_diagonal_sums_bit_exact(oz, handle):
+    rng = np.random.default_rng(9)
+    m, n, k, s, kc = 66, 64, 200, 11, 128
+    A, B = wide(rng, (m, k), 20), wide(rng, (k, n), 20)
+    ra, kpad, nba = oz.oz_split_layout("A", 0, m, k, s)
+    rb, _, nbb = oz.oz_split_layout("B", 0, n, k, s)
+    dA, lda = to_dev(A)
+    dB, ldb = to_dev(B)
+    sa = torch.zeros(nba, dtype=torch.int8, device="cuda")
+    sb = torch.zeros(nbb, dtype=torch.int8, device="cuda")
+    ea = torch.zeros(m, dtype=torch.int32, device="cuda")
+    fb = torch.zeros(n, dtype=torch.int32, device="cuda")
+    oz.oz_split(handle, "A", "N", 0, m, k, dA, lda, s, ea, sa)
+    oz.oz_split(handle, "B", "N", 0, n, k, dB, ldb, s, fb, sb)
+    nch = -(-kpad // kc)
+    out = torch.zeros(nch * s * rb * ra, dtype=torch.int32, device="cuda")
+    oz.oz_diag_sums(handle, s, kc, ra, rb, kpad, sa, sb, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().reshape(nch, s, rb, ra).transpose(0, 1, 3, 2)
+    ref = oracle.diag_sums(oracle.split("A", "N", A, s)[1], oracle.split("B", "N", B, s)[1], s, kc=kc)
+    assert np.array_equal(got[:, :, :m, :n], ref)
