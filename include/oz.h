@@ -70,12 +70,18 @@ typedef struct oz_handle_s* oz_handle_t;
  *           the chunked accumulation on small k).
  *  zmode  : complex only; 0 or 4: the 4-real-product form (the only one
  *           built so far).
+ *  kernel : GEMM kernel shape; 0 chooses by size, 1 = 128 x 64 block with a
+ *           3-stage LDS ring, 2 = 64 x 64 block with 2 stages (both for
+ *           s <= 8), 3 = per-diagonal streaming (any s; the only choice for
+ *           s > 8).  Every shape gives the same bits.
  */
 typedef struct {
     int32_t slices;
     int32_t smax;
     int32_t kchunk;
     int32_t zmode;
+    int32_t kernel;
+    int32_t reserved;
     double tol;
 } oz_prec_t;
 
@@ -159,7 +165,7 @@ int oz_timing_read(oz_handle_t handle, double* split_ms, double* gemm_ms, int64_
  *   row c maps to vector r = 32*(c/16) + 16*((c/8)%2) + (c%8) for the
  *   real-part row (terms: ar, -ai) and r + 8 for the imaginary-part row
  *   (terms: ai, ar).  Vectors are padded with zeros to rows_pad (a multiple
- *   of 64) and terms to kpad (a multiple of 32).
+ *   of 128) and terms to kpad (a multiple of 32).
  *   Digit p (1..s) of term t of vector v is the int8 at byte offset
  *     (((t/16)*s + (p-1)) * rows_pad + v) * 16 + t%16.
  *   The scale exponent of vector v (per complex row c for a complex side 'A')
@@ -181,10 +187,11 @@ int oz_split(oz_handle_t handle, char side, char trans, int is_complex, int64_t 
 /* Step 3: the exact anti-diagonal sums S_{d,c} = sum over p + q = d of the
  * INT32 slice-pair products over chunk c of kchunk terms, from two slice
  * buffers laid out by oz_split (A: rows_pad_a vectors, B: rows_pad_b vectors,
- * same kpad).  out (device int32) receives
+ * same kpad), computed by the GEMM kernel `kernel` (as in oz_prec_t).
+ * out (device int32) receives
  *   out[((c*s + (d-2)) * rows_pad_b + j) * rows_pad_a + i]
  * for every chunk c < ceil(kpad/kchunk), d = 2..s+1, and all padded i, j. */
-int oz_diag_sums(oz_handle_t handle, int32_t slices, int64_t kchunk, int64_t rows_pad_a,
+int oz_diag_sums(oz_handle_t handle, int32_t slices, int64_t kchunk, int32_t kernel, int64_t rows_pad_a,
                  int64_t rows_pad_b, int64_t kpad, const int8_t* slices_a, const int8_t* slices_b,
                  int32_t* out);
 

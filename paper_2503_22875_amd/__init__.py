@@ -35,7 +35,8 @@ class OzError(RuntimeError):
 
 class oz_prec_t(ctypes.Structure):
     _fields_ = [("slices", ctypes.c_int32), ("smax", ctypes.c_int32), ("kchunk", ctypes.c_int32),
-                ("zmode", ctypes.c_int32), ("tol", ctypes.c_double)]
+                ("zmode", ctypes.c_int32), ("kernel", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("tol", ctypes.c_double)]
 
 
 class oz_report_t(ctypes.Structure):
@@ -63,7 +64,7 @@ def _load():
                      PP(oz_report_t)],
         "oz_split_layout": [C, ctypes.c_int, I64, I64, I32, PP(I64), PP(I64), PP(ctypes.c_size_t)],
         "oz_split": [P, C, C, ctypes.c_int, I64, I64, P, I64, I32, P, P],
-        "oz_diag_sums": [P, I32, I64, I64, I64, I64, P, P, P],
+        "oz_diag_sums": [P, I32, I64, I32, I64, I64, I64, P, P, P],
         "oz_timing_enable": [P, ctypes.c_int],
         "oz_timing_read": [P, PP(D), PP(D), PP(I64)],
     }
@@ -114,8 +115,8 @@ def oz_set_stream(handle, stream):
     return _check("oz_set_stream", _lib.oz_set_stream(handle, stream))
 
 
-def prec(slices=7, tol=0.0, smax=0, kchunk=0, zmode=0):
-    return oz_prec_t(slices, smax, kchunk, zmode, tol)
+def prec(slices=7, tol=0.0, smax=0, kchunk=0, zmode=0, kernel=0):
+    return oz_prec_t(slices, smax, kchunk, zmode, kernel, 0, tol)
 
 
 def oz_workspace_size(handle, transa, transb, m, n, k, is_complex, p=None):
@@ -166,8 +167,8 @@ def oz_split(handle, side, trans, is_complex, nv, k, X, ldx, slices, E, slices_o
                                             slices, _ptr(E), _ptr(slices_out)))
 
 
-def oz_diag_sums(handle, slices, kchunk, rows_pad_a, rows_pad_b, kpad, slices_a, slices_b, out):
-    return _check("oz_diag_sums", _lib.oz_diag_sums(handle, slices, kchunk, rows_pad_a, rows_pad_b, kpad,
+def oz_diag_sums(handle, slices, kchunk, rows_pad_a, rows_pad_b, kpad, slices_a, slices_b, out, kernel=0):
+    return _check("oz_diag_sums", _lib.oz_diag_sums(handle, slices, kchunk, kernel, rows_pad_a, rows_pad_b, kpad,
                                                     _ptr(slices_a), _ptr(slices_b), _ptr(out)))
 
 

@@ -141,9 +141,8 @@ hipError_t mark(oz_handle_t h) {
 }
 
 bool grid_fits(const Plan& p) {
-    // gemm grid: y = Mp/64; scan grid y = nv/64; keep within 65535
-    return p.la.rows_pad / oz::kTile <= 65535 && p.lb.rows_pad / oz::kTile <= 65535 &&
-           (p.nva + 63) / 64 <= 65535 && (p.nvb + 63) / 64 <= 65535;
+    // split grids run 64 vectors per block along grid.y (at most 65535)
+    return p.la.rows_pad / 64 <= 65535 && p.lb.rows_pad / 64 <= 65535;
 }
 
 int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, int64_t n, int64_t k,
@@ -162,13 +161,17 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
     if (ldc < (m > 1 ? m : 1)) return 13;
     int s = kDefaultSlices;
     int64_t kc = 0;
+    int kernel = 0;
     if (prec) {
         if (prec->slices < 0 || prec->slices > OZ_MAX_SLICES) return 14;
         if (prec->slices == 0) return OZ_ERR_UNSUPPORTED;  // tolerance-driven selection: not in this build
         if (prec->zmode != 0 && prec->zmode != 4) return 14;
+        if (prec->kernel < 0 || prec->kernel > 3) return 14;
         s = prec->slices;
         kc = prec->kchunk;
+        kernel = prec->kernel;
     }
+    if (s > oz::kMaxLiveSlices && (kernel == 1 || kernel == 2)) return 14;
     if (kc < 0 || kc % 64 != 0 || (kc > 0 && kc > kchunk_bound(s))) return 14;
     if (kc == 0) kc = kchunk_bound(s);
     if (!alpha || !beta) return OZ_ERR_ARG;
@@ -228,6 +231,7 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
     g.chunk_steps = kc / oz::kStep;
     g.s = s;
     g.cplx = cplx;
+    g.tile = kernel;
     g.C = C;
     g.ldc = ldc;
     g.m = m;
@@ -413,7 +417,7 @@ int oz_split(oz_handle_t h, char side, char trans, int is_complex, int64_t nv, i
     const int cplx = is_complex ? 1 : 0;
     oz::OperandView v = sa ? view_a(trans, X, ldx, nv, k, cplx) : view_b(trans, X, ldx, nv, k, cplx);
     oz::SliceLayout L = oz::slice_layout(sa, cplx, nv, k, slices);
-    if ((nv + 63) / 64 > 65535 || L.rows_pad / oz::kTile > 65535) return OZ_ERR_UNSUPPORTED;
+    if (L.rows_pad / 64 > 65535) return OZ_ERR_UNSUPPORTED;
     int st = ensure_ws(h, align256(sizeof(uint64_t) * static_cast<size_t>(nv > 0 ? nv : 1)));
     if (st) return st;
     uint64_t* mx = static_cast<uint64_t*>(h->ws);
@@ -423,14 +427,14 @@ int oz_split(oz_handle_t h, char side, char trans, int is_complex, int64_t nv, i
     return hip_status(e);
 }
 
-int oz_diag_sums(oz_handle_t h, int32_t slices, int64_t kchunk, int64_t rows_pad_a, int64_t rows_pad_b, int64_t kpad,
-                 const int8_t* slices_a, const int8_t* slices_b, int32_t* out) {
+int oz_diag_sums(oz_handle_t h, int32_t slices, int64_t kchunk, int32_t kernel, int64_t rows_pad_a,
+                 int64_t rows_pad_b, int64_t kpad, const int8_t* slices_a, const int8_t* slices_b, int32_t* out) {
     if (!valid(h)) return OZ_ERR_HANDLE;
     if (slices < 1 || slices > OZ_MAX_SLICES) return OZ_ERR_ARG;
+    if (kernel < 0 || kernel > 3 || (slices > oz::kMaxLiveSlices && (kernel == 1 || kernel == 2))) return OZ_ERR_ARG;
     if (kchunk <= 0 || kchunk % 64 != 0 || kchunk > kchunk_bound(slices)) return OZ_ERR_ARG;
-    if (rows_pad_a <= 0 || rows_pad_b <= 0 || rows_pad_a % oz::kTile || rows_pad_b % oz::kTile) return OZ_ERR_ARG;
+    if (rows_pad_a <= 0 || rows_pad_b <= 0 || rows_pad_a % oz::kRowPad || rows_pad_b % oz::kRowPad) return OZ_ERR_ARG;
     if (kpad <= 0 || kpad % oz::kStep) return OZ_ERR_ARG;
-    if (rows_pad_a / oz::kTile > 65535) return OZ_ERR_UNSUPPORTED;
     if (use_device(h)) return OZ_ERR_HIP;
     oz::GemmArgs g;
     std::memset(&g, 0, sizeof(g));
@@ -441,6 +445,7 @@ int oz_diag_sums(oz_handle_t h, int32_t slices, int64_t kchunk, int64_t rows_pad
     g.kpad = kpad;
     g.chunk_steps = kchunk / oz::kStep;
     g.s = slices;
+    g.tile = kernel;
     g.diag_out = out;
     return hip_status(oz::launch_gemm(g, h->stream));
 }

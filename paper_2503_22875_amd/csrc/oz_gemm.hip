@@ -2,8 +2,8 @@
 // FP64 rescale-accumulate epilogue fused (paper Sec. 2.2: INT8 matrix units
 // with INT32 accumulation, result accumulated at higher precision).
 //
-// One block computes a 64 x 64 tile of C' = A' * B' (A', B' the slice
-// buffers of oz_split) with 4 waves, each owning a 32 x 32 sub-tile and one
+// A block computes a BM x BN tile of C' = A' * B' (A', B' the slice buffers
+// of oz_split) with WMW x WNW waves, each owning a 32 x 32 sub-tile and one
 // v_mfma_i32_32x32x32_i8 per slice pair and 32-term step.
 //
 // All-diagonal form: every step stages the s slices of both operands in LDS
@@ -16,13 +16,13 @@
 // FP64 tile, from d = s+1 down to 2, each times 2^(-7d) (exact).  The final
 // epilogue applies 2^(E_i + F_j) with ldexp and alpha/beta.
 //
-// LDS stage (double buffered): for each operand, 16-term half h, slice p:
-// 64 rows x 16 bytes, a contiguous 1 KiB run that is also contiguous in the
-// global slice layout.  The copy is done by global_load_lds_dwordx4 (global
-// memory straight into LDS, 16 bytes per lane, no staging registers), one
-// wave per 1 KiB run, and each MFMA operand read (32 lanes x 16 consecutive
-// bytes) is free of bank conflicts.  The next stage's copy is in flight while
-// the MFMAs of the current stage run.
+// LDS stages (a ring of NST): for each operand, 16-term half h, slice p:
+// 64 rows x 16 bytes, a contiguous 1 KiB run in the global slice layout,
+// moved by global_load_lds_dwordx4 (global memory straight into LDS, one wave
+// per run, 16 bytes per lane, no staging registers).  Each MFMA operand read
+// (32 lanes x 16 consecutive bytes) is free of bank conflicts.  The copy of
+// step ks + NST - 1 is in flight while the MFMAs of step ks run, so NST - 1
+// steps of MFMA work cover the memory latency.
 #include "oz_internal.h"
 
 namespace oz {
@@ -31,6 +31,8 @@ namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
+typedef __attribute__((address_space(3))) void lds_void;
+typedef __attribute__((address_space(1))) const void global_cvoid;
 
 // 2^(-7d) for d = dd + 2, exact.
 template <int DD>
@@ -54,7 +56,7 @@ __device__ __forceinline__ void fold_diags(double (&acc64)[16], v16i (&acc)[S]) 
 // and each XCD has its own L2.  Block b is given the tile t = start(x) + b/8 of
 // a contiguous range per XCD x = b % 8, and inside that range tiles run in
 // groups of kGroupM tile rows, column by column, so the blocks resident on one
-// XCD at a time share a few 64-row slices of A' and 64-column slices of B'.
+// XCD at a time share a few row slices of A' and column slices of B'.
 constexpr int kXcds = 8;
 constexpr int kGroupM = 8;
 
@@ -72,22 +74,28 @@ __device__ __forceinline__ void tile_of_block(int64_t b, int64_t tiles_m, int64_
     tn = in / gh;
 }
 
-typedef __attribute__((address_space(3))) void lds_void;
-typedef __attribute__((address_space(1))) const void global_cvoid;
+// Wait until at most N vector-memory operations of this wave are in flight
+// (loads and stores retire in issue order on this architecture).
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
 
-// Final epilogue of a 64 x 64 tile: v = ldexp(acc64, E_i + F_j), then alpha/beta
-// (two rounded products and one rounded add per part, no fused multiply-add),
-// or NaN where the row or column scale marks Inf/NaN input.
-template <bool CPLX, typename RowOf>
-__device__ __forceinline__ void store_tile(const GemmArgs& g, const double (&acc64)[16], int64_t tm, int wm, int half,
-                                           int64_t col, RowOf row_of) {
+// Final epilogue of one wave's 32 x 32 sub-tile whose first row of C' is
+// row0: v = ldexp(acc64, E_i + F_j), then alpha/beta (two rounded products
+// and one rounded add per part, no fused multiply-add), or NaN where the row
+// or column scale marks Inf/NaN input.  Register r holds C' row
+// row0 + 8*(r/4) + 4*half + r%4 of column col.
+template <bool CPLX>
+__device__ __forceinline__ void store_tile(const GemmArgs& g, const double (&acc64)[16], int64_t row0, int half,
+                                           int64_t col) {
     const double nan = __longlong_as_double(0x7ff8000000000000ll);
     if (col >= g.n) return;
     const int32_t f = g.FB[col];
     if constexpr (!CPLX) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            const int64_t i = row_of(r);
+            const int64_t i = row0 + 8 * (r >> 2) + 4 * half + (r & 3);
             if (i >= g.m) continue;
             const int32_t e = g.EA[i];
             double* c = g.C + i + col * g.ldc;
@@ -102,13 +110,12 @@ __device__ __forceinline__ void store_tile(const GemmArgs& g, const double (&acc
             *c = out;
         }
     } else {
-        // tile rows: 32 per wave = 16 complex rows; register r (r%8 < 4) holds the
-        // real part and r + 4 the imaginary part of complex row
-        // (tm*64 + wm*32)/2 + 8*(r/8) + 4*half + r%4
+        // 32 C' rows = 16 complex rows; register r (r%8 < 4) holds the real part
+        // and r + 4 the imaginary part of complex row row0/2 + 8*(r/8) + 4*half + r%4
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             if ((r & 4) != 0) continue;
-            const int64_t ci = (tm * 64 + wm * 32) / 2 + 8 * (r >> 3) + 4 * half + (r & 3);
+            const int64_t ci = row0 / 2 + 8 * (r >> 3) + 4 * half + (r & 3);
             if (ci >= g.m) continue;
             const int32_t e = g.EA[ci];
             double* c = g.C + 2 * (ci + col * g.ldc);
@@ -132,38 +139,62 @@ __device__ __forceinline__ void store_tile(const GemmArgs& g, const double (&acc
     }
 }
 
-template <int S, bool CPLX, bool DIAG, bool MULTI>
-__global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(2, 2)))
-void gemm_kernel(GemmArgs g) {
-    constexpr int A_CHUNKS = 2 * S * 64;  // 16-byte chunks of one operand per stage
-    constexpr int STAGE = 2 * A_CHUNKS;   // A then B
-    constexpr int LOADS = STAGE / 256;    // chunks per thread per stage (== S)
-    __shared__ v4i lds[2][STAGE];
+template <int S, int WMW, int WNW, int NST>
+struct TileCfg {
+    static constexpr int BM = 32 * WMW, BN = 32 * WNW;
+    static constexpr int NW = WMW * WNW;                     // waves per block
+    static constexpr int RA = 2 * S * (BM / 64);             // 1 KiB runs of A per stage
+    static constexpr int RB = 2 * S * (BN / 64);             // 1 KiB runs of B per stage
+    static constexpr int R = RA + RB;
+    static constexpr int A_CHUNKS = RA * 64;                 // 16-byte chunks
+    static constexpr int STAGE = R * 64;
+    static constexpr int RHI = (R + NW - 1) / NW;            // runs of waves w < R % NW (all if 0)
+    static constexpr int RLO = R / NW;                       // runs of the other waves (may be 0)
+    static_assert(BM % 64 == 0 && BN % 64 == 0, "block sides are multiples of 64");
+};
+
+template <int S, int WMW, int WNW, int NST, bool CPLX, bool DIAG, bool MULTI>
+__global__ __attribute__((amdgpu_flat_work_group_size(64 * WMW * WNW, 64 * WMW * WNW),
+                          amdgpu_waves_per_eu(2, 2))) void gemm_kernel(GemmArgs g) {
+    using T = TileCfg<S, WMW, WNW, NST>;
+    __shared__ v4i lds[NST][T::STAGE];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wm = wave / WNW, wn = wave % WNW;
     const int half = lane >> 5, row = lane & 31;
     int64_t tm, tn;
-    tile_of_block(blockIdx.x, g.Mp / kTile, g.Np / kTile, tm, tn);
+    tile_of_block(blockIdx.x, g.Mp / T::BM, g.Np / T::BN, tm, tn);
     const v4i* SA = reinterpret_cast<const v4i*>(g.SA);
     const v4i* SB = reinterpret_cast<const v4i*>(g.SB);
     const int64_t nsteps = g.kpad / kStep;
 
-    // Stage ks -> LDS buffer: wave w moves chunks w*64 + 256*i + lane (i < S),
-    // each lane 16 bytes, straight into LDS (no staging registers).  A chunk c
-    // (c < A_CHUNKS) is 16-term half h, slice p = (c/64) split as h*S + p, row
-    // c % 64; the 64 chunks of one wave are 1 KiB contiguous in global memory.
+    // Stage of step ks -> LDS buffer: run j (< R) of the stage is moved by wave
+    // j % NW.  A run j < RA is (h*S + p) = j / (BM/64), 64-row block j % (BM/64);
+    // a B run likewise.  LDS holds A as [h*S + p][BM rows] and B as
+    // [h*S + p][BN cols], 16 bytes each.
     auto issue = [&](int64_t ks, int buf) {
 #pragma unroll
-        for (int i = 0; i < LOADS; ++i) {
-            const int cw = wave * 64 + 256 * i;  // first chunk of this wave (uniform)
+        for (int i = 0; i < T::RHI; ++i) {
+            const int j = wave + T::NW * i;  // wave-uniform
+            if (j >= T::R) break;
             const v4i* src;
-            if (cw < A_CHUNKS)
-                src = SA + (2 * ks * S + cw / 64) * g.Mp + tm * 64 + lane;
-            else
-                src = SB + (2 * ks * S + (cw - A_CHUNKS) / 64) * g.Np + tn * 64 + lane;
-            __builtin_amdgcn_global_load_lds((global_cvoid*)(src), (lds_void*)(&lds[buf][cw]), 16, 0, 0);
+            if (j < T::RA) {
+                const int hp = j / (T::BM / 64), rb = j % (T::BM / 64);
+                src = SA + (2 * ks * S + hp) * g.Mp + tm * T::BM + rb * 64 + lane;
+            } else {
+                const int jb = j - T::RA;
+                const int hp = jb / (T::BN / 64), cb = jb % (T::BN / 64);
+                src = SB + (2 * ks * S + hp) * g.Np + tn * T::BN + cb * 64 + lane;
+            }
+            __builtin_amdgcn_global_load_lds((global_cvoid*)(src), (lds_void*)(&lds[buf][j * 64]), 16, 0, 0);
         }
+    };
+    // all but the newest stage's copies of this wave have landed
+    auto wait_older = [&]() {
+        if (T::R % T::NW == 0 || wave < T::R % T::NW)
+            wait_vm<T::RHI>();
+        else
+            wait_vm<T::RLO>();
     };
 
     v16i acc[S];
@@ -177,24 +208,31 @@ void gemm_kernel(GemmArgs g) {
         for (int r = 0; r < 16; ++r) acc64[r] = 0.0;
     }
 
-    // rows / column of this lane's 16 accumulator entries inside the tile
-    const int64_t col = tn * 64 + wn * 32 + row;
-    auto row_of = [&](int r) -> int64_t { return tm * 64 + wm * 32 + 8 * (r >> 2) + 4 * half + (r & 3); };
+    const int64_t row0 = tm * T::BM + wm * 32;
+    const int64_t col = tn * T::BN + wn * 32 + row;
 
-    issue(0, 0);
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    // prologue: stages 0 .. NST-2 in flight
+#pragma unroll
+    for (int st = 0; st < NST - 1; ++st)
+        if (st < nsteps) issue(st, st);
+    if (NST > 2 && nsteps > 1)
+        wait_older();  // stage 0 landed, stage 1 may still fly
+    else
+        wait_vm<0>();
     __syncthreads();
+
     int64_t chunk_pos = 0, chunk = 0;
+    int buf = 0;
     for (int64_t ks = 0; ks < nsteps; ++ks) {
-        const int buf = static_cast<int>(ks & 1);
-        if (ks + 1 < nsteps) issue(ks + 1, buf ^ 1);
+        const bool more = ks + NST - 1 < nsteps;
+        if (more) issue(ks + NST - 1, (buf + NST - 1) % NST);
         const v4i* L = lds[buf];
         v4i bq[S];
 #pragma unroll
-        for (int q = 0; q < S; ++q) bq[q] = L[A_CHUNKS + (half * S + q) * 64 + wn * 32 + row];
+        for (int q = 0; q < S; ++q) bq[q] = L[T::A_CHUNKS + (half * S + q) * T::BN + wn * 32 + row];
 #pragma unroll
         for (int p = 0; p < S; ++p) {
-            const v4i a = L[(half * S + p) * 64 + wm * 32 + row];
+            const v4i a = L[(half * S + p) * T::BM + wm * 32 + row];
 #pragma unroll
             for (int q = 0; q < S - p; ++q)
                 acc[p + q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, bq[q], acc[p + q], 0, 0, 0);
@@ -206,7 +244,8 @@ void gemm_kernel(GemmArgs g) {
                     for (int d = 0; d < S; ++d)
 #pragma unroll
                         for (int r = 0; r < 16; ++r)
-                            g.diag_out[((chunk * S + d) * g.Np + col) * g.Mp + row_of(r)] = acc[d][r];
+                            g.diag_out[((chunk * S + d) * g.Np + col) * g.Mp + row0 + 8 * (r >> 2) + 4 * half +
+                                       (r & 3)] = acc[d][r];
                 } else {
                     fold_diags<S, S - 1>(acc64, acc);
                 }
@@ -218,8 +257,13 @@ void gemm_kernel(GemmArgs g) {
                 ++chunk;
             }
         }
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        // the stage of step ks + 1 must have landed before the barrier
+        if (NST > 2 && more)
+            wait_older();
+        else
+            wait_vm<0>();
         __syncthreads();
+        buf = (buf + 1 == NST) ? 0 : buf + 1;
     }
     if constexpr (DIAG) return;
     if constexpr (!MULTI) {
@@ -227,8 +271,7 @@ void gemm_kernel(GemmArgs g) {
         for (int r = 0; r < 16; ++r) acc64[r] = 0.0;
         fold_diags<S, S - 1>(acc64, acc);
     }
-
-    store_tile<CPLX>(g, acc64, tm, wm, half, col, row_of);
+    store_tile<CPLX>(g, acc64, row0, half, col);
 }
 
 // Streaming form for any s (used above the all-diagonal kernel's register
@@ -237,6 +280,7 @@ void gemm_kernel(GemmArgs g) {
 // diagonal are streamed step by step (one A slice and one B slice, 4 KiB per
 // stage, double buffered) into the INT32 tile, which is then folded into the
 // FP64 tile -- the same order as the all-diagonal kernel, hence the same bits.
+// 64 x 64 block tile, 4 waves.
 template <bool CPLX, bool DIAG>
 __global__ __attribute__((amdgpu_flat_work_group_size(256, 256))) void gemm_stream_kernel(GemmArgs g) {
     __shared__ v4i lds[2][256];  // [A: h*64 + row | B: 128 + h*64 + col]
@@ -245,12 +289,12 @@ __global__ __attribute__((amdgpu_flat_work_group_size(256, 256))) void gemm_stre
     const int half = lane >> 5, row = lane & 31;
     const int s = g.s;
     int64_t tm, tn;
-    tile_of_block(blockIdx.x, g.Mp / kTile, g.Np / kTile, tm, tn);
+    tile_of_block(blockIdx.x, g.Mp / 64, g.Np / 64, tm, tn);
     const v4i* SA = reinterpret_cast<const v4i*>(g.SA);
     const v4i* SB = reinterpret_cast<const v4i*>(g.SB);
     const int64_t nsteps = g.kpad / kStep;
+    const int64_t row0 = tm * 64 + wm * 32;
     const int64_t col = tn * 64 + wn * 32 + row;
-    auto row_of = [&](int r) -> int64_t { return tm * 64 + wm * 32 + 8 * (r >> 2) + 4 * half + (r & 3); };
 
     // wave 0/1: A half 0/1 of slice p; wave 2/3: B half 0/1 of slice q
     auto issue = [&](int64_t ks, int p, int q, int buf) {
@@ -276,7 +320,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(256, 256))) void gemm_stre
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[r] = 0;
             issue(k0, plo, d - plo, 0);
-            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            wait_vm<0>();
             __syncthreads();
             for (int64_t it = 0; it < items; ++it) {
                 const int buf = static_cast<int>(it & 1);
@@ -287,12 +331,14 @@ __global__ __attribute__((amdgpu_flat_work_group_size(256, 256))) void gemm_stre
                 const v4i a = lds[buf][half * 64 + wm * 32 + row];
                 const v4i b = lds[buf][128 + half * 64 + wn * 32 + row];
                 acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, acc, 0, 0, 0);
-                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                wait_vm<0>();
                 __syncthreads();
             }
             if constexpr (DIAG) {
 #pragma unroll
-                for (int r = 0; r < 16; ++r) g.diag_out[((c * s + (d - 2)) * g.Np + col) * g.Mp + row_of(r)] = acc[r];
+                for (int r = 0; r < 16; ++r)
+                    g.diag_out[((c * s + (d - 2)) * g.Np + col) * g.Mp + row0 + 8 * (r >> 2) + 4 * half + (r & 3)] =
+                        acc[r];
             } else {
                 const double sc = ldexp(1.0, -7 * d);  // exact power of two
 #pragma unroll
@@ -301,7 +347,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(256, 256))) void gemm_stre
         }
     }
     if constexpr (DIAG) return;
-    store_tile<CPLX>(g, acc64, tm, wm, half, col, row_of);
+    store_tile<CPLX>(g, acc64, row0, half, col);
 }
 
 __global__ void scale_c_kernel(double* C, int64_t ldc, int64_t m, int64_t n, int cplx, double br, double bi,
@@ -326,41 +372,37 @@ __global__ void scale_c_kernel(double* C, int64_t ldc, int64_t m, int64_t n, int
     }
 }
 
-template <int S>
-hipError_t launch_s(const GemmArgs& g, hipStream_t st) {
-    const int64_t blocks = (g.Np / kTile) * (g.Mp / kTile);
+template <int S, int WMW, int WNW, int NST>
+hipError_t launch_cfg(const GemmArgs& g, hipStream_t st) {
+    using T = TileCfg<S, WMW, WNW, NST>;
+    const int64_t blocks = (g.Np / T::BN) * (g.Mp / T::BM);
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    dim3 grid(static_cast<unsigned>(blocks));
+    dim3 grid(static_cast<unsigned>(blocks)), block(64 * T::NW);
     const bool multi = g.chunk_steps < g.kpad / kStep;
     if (g.diag_out)
-        hipLaunchKernelGGL((gemm_kernel<S, false, true, true>), grid, dim3(256), 0, st, g);
+        hipLaunchKernelGGL((gemm_kernel<S, WMW, WNW, NST, false, true, true>), grid, block, 0, st, g);
     else if (g.cplx && multi)
-        hipLaunchKernelGGL((gemm_kernel<S, true, false, true>), grid, dim3(256), 0, st, g);
+        hipLaunchKernelGGL((gemm_kernel<S, WMW, WNW, NST, true, false, true>), grid, block, 0, st, g);
     else if (g.cplx)
-        hipLaunchKernelGGL((gemm_kernel<S, true, false, false>), grid, dim3(256), 0, st, g);
+        hipLaunchKernelGGL((gemm_kernel<S, WMW, WNW, NST, true, false, false>), grid, block, 0, st, g);
     else if (multi)
-        hipLaunchKernelGGL((gemm_kernel<S, false, false, true>), grid, dim3(256), 0, st, g);
+        hipLaunchKernelGGL((gemm_kernel<S, WMW, WNW, NST, false, false, true>), grid, block, 0, st, g);
     else
-        hipLaunchKernelGGL((gemm_kernel<S, false, false, false>), grid, dim3(256), 0, st, g);
+        hipLaunchKernelGGL((gemm_kernel<S, WMW, WNW, NST, false, false, false>), grid, block, 0, st, g);
     return hipGetLastError();
 }
 
-}  // namespace
+// Block shape: 128 x 64 (8 waves, 3-stage ring) when the grid still fills
+// the 256 compute units twice over, else 64 x 64 (4 waves, 2 stages).
+template <int S>
+hipError_t launch_s(const GemmArgs& g, hipStream_t st) {
+    const int64_t big_tiles = (g.Mp / 128) * (g.Np / 64);
+    if (g.tile == 1 || (g.tile == 0 && big_tiles >= 512)) return launch_cfg<S, 4, 2, 3>(g, st);
+    return launch_cfg<S, 2, 2, 2>(g, st);
+}
 
-hipError_t launch_gemm(const GemmArgs& g, hipStream_t st) {
-    switch (g.s) {
-        case 1: return launch_s<1>(g, st);
-        case 2: return launch_s<2>(g, st);
-        case 3: return launch_s<3>(g, st);
-        case 4: return launch_s<4>(g, st);
-        case 5: return launch_s<5>(g, st);
-        case 6: return launch_s<6>(g, st);
-        case 7: return launch_s<7>(g, st);
-        case 8: return launch_s<8>(g, st);
-        default: break;
-    }
-    if (g.s < 1 || g.s > 18) return hipErrorInvalidValue;
-    const int64_t blocks = (g.Np / kTile) * (g.Mp / kTile);
+hipError_t launch_stream(const GemmArgs& g, hipStream_t st) {
+    const int64_t blocks = (g.Np / 64) * (g.Mp / 64);
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     dim3 grid(static_cast<unsigned>(blocks));
     if (g.diag_out)
@@ -370,6 +412,24 @@ hipError_t launch_gemm(const GemmArgs& g, hipStream_t st) {
     else
         hipLaunchKernelGGL((gemm_stream_kernel<false, false>), grid, dim3(256), 0, st, g);
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_gemm(const GemmArgs& g, hipStream_t st) {
+    if (g.s < 1 || g.s > 18) return hipErrorInvalidValue;
+    if (g.tile == 3) return launch_stream(g, st);
+    switch (g.s) {
+        case 1: return launch_s<1>(g, st);
+        case 2: return launch_s<2>(g, st);
+        case 3: return launch_s<3>(g, st);
+        case 4: return launch_s<4>(g, st);
+        case 5: return launch_s<5>(g, st);
+        case 6: return launch_s<6>(g, st);
+        case 7: return launch_s<7>(g, st);
+        case 8: return launch_s<8>(g, st);
+        default: return launch_stream(g, st);
+    }
 }
 
 hipError_t launch_scale_c(double* C, int64_t ldc, int64_t m, int64_t n, int cplx, double br, double bi,

@@ -7,8 +7,9 @@
 
 namespace oz {
 
-// Rows and columns of a slice buffer are padded to the GEMM block tile.
-constexpr int kTile = 64;
+// Rows of a slice buffer are padded to a multiple of the largest GEMM block
+// tile side, so any tile shape reads whole tiles without bounds checks.
+constexpr int kRowPad = 128;
 // Terms per MFMA step (v_mfma_i32_32x32x32_i8 consumes 32 int8 per row).
 constexpr int kStep = 32;
 // Terms per 16-byte chunk of the slice layout.
@@ -33,7 +34,7 @@ struct OperandView {
 
 // Layout of the slices of one operand (see oz.h).
 struct SliceLayout {
-    int64_t rows_pad;   // padded vector count (multiple of kTile)
+    int64_t rows_pad;   // padded vector count (multiple of kRowPad)
     int64_t kpad;       // padded term count (multiple of kStep)
     int s;              // slices
 };
@@ -56,6 +57,7 @@ struct GemmArgs {
     int64_t chunk_steps;   // MFMA steps (of kStep terms) per INT32 chunk
     int s;
     int cplx;
+    int tile;              // 0 auto, 1: 128 x 64 block, 2: 64 x 64 block, 3: per-diagonal streaming
     // epilogue
     double* C;
     int64_t ldc;

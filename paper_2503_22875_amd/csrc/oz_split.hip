@@ -214,7 +214,7 @@ __global__ __launch_bounds__(256) void digits_kernel(OperandView op, const uint6
 SliceLayout slice_layout(int side_a, int cplx, int64_t nv, int64_t k, int s) {
     SliceLayout L;
     int64_t rows = (cplx && side_a) ? 2 * round_up(nv, 16) : nv;
-    L.rows_pad = round_up(rows > 0 ? rows : 1, kTile);
+    L.rows_pad = round_up(rows > 0 ? rows : 1, kRowPad);
     int64_t terms = cplx ? 2 * k : k;
     L.kpad = round_up(terms > 0 ? terms : 1, kStep);
     L.s = s;

@@ -95,10 +95,11 @@ def test_split_bit_exact(oz, handle, side, trans, cplx, nv, k, s):
 # ----------------------------------------------------------------- INT32 diagonals (a3)
 
 
+@pytest.mark.parametrize("kernel", [1, 2, 3])
 @pytest.mark.parametrize("cplx", [0, 1])
 @pytest.mark.parametrize("m,n,k,s,kc", [(70, 65, 300, 7, 64), (64, 64, 128, 8, None), (130, 20, 33, 3, 128),
                                         (5, 7, 2000, 5, 512)])
-def test_diagonal_sums_bit_exact(oz, handle, cplx, m, n, k, s, kc):
+def test_diagonal_sums_bit_exact(oz, handle, cplx, m, n, k, s, kc, kernel):
     rng = np.random.default_rng(m + n + k + s)
     A = wide(rng, (m, k), 20, bool(cplx))
     B = wide(rng, (k, n), 20, bool(cplx))
@@ -115,8 +116,8 @@ def test_diagonal_sums_bit_exact(oz, handle, cplx, m, n, k, s, kc):
     oz.oz_split(handle, "B", "N", cplx, n, k, dB, ldb, s, fb, sb)
     nch = -(-kpad // kc)
     out = torch.full((nch * s * rb * ra,), -7, dtype=torch.int32, device="cuda")
-    print("diag", cplx, m, n, k, s, kc, flush=True)
-    oz.oz_diag_sums(handle, s, kc, ra, rb, kpad, sa, sb, out)
+    print("diag", cplx, m, n, k, s, kc, kernel, flush=True)
+    oz.oz_diag_sums(handle, s, kc, ra, rb, kpad, sa, sb, out, kernel=kernel)
     torch.cuda.synchronize()
     got = out.cpu().numpy().reshape(nch, s, rb, ra).transpose(0, 1, 3, 2)  # [c, d-2, i, j]
     _, digA = oracle.split("A", "N", A, s)
@@ -138,7 +139,7 @@ def test_diagonal_sums_bit_exact(oz, handle, cplx, m, n, k, s, kc):
 # ----------------------------------------------------------------- FP64 result (a4, a5)
 
 
-def run_gemm(oz, handle, cplx, ta, tb, A, B, s, alpha=1.0, beta=0.0, C0=None, kc=0, pad=0):
+def run_gemm(oz, handle, cplx, ta, tb, A, B, s, alpha=1.0, beta=0.0, C0=None, kc=0, pad=0, kernel=0):
     m = A.shape[0] if ta == "N" else A.shape[1]
     k = A.shape[1] if ta == "N" else A.shape[0]
     n = B.shape[1] if tb == "N" else B.shape[0]
@@ -148,7 +149,7 @@ def run_gemm(oz, handle, cplx, ta, tb, A, B, s, alpha=1.0, beta=0.0, C0=None, kc
     C0 = np.zeros((m, n), dt, order="F") if C0 is None else C0
     dC, ldc = to_dev(C0, m + pad)
     fn = oz.oz_zgemm if cplx else oz.oz_dgemm
-    fn(handle, ta, tb, m, n, k, alpha, dA, lda, dB, ldb, beta, dC, ldc, oz.prec(s, kchunk=kc))
+    fn(handle, ta, tb, m, n, k, alpha, dA, lda, dB, ldb, beta, dC, ldc, oz.prec(s, kchunk=kc, kernel=kernel))
     torch.cuda.synchronize()
     return from_dev(dC, m, n, ldc)
 
@@ -156,27 +157,29 @@ def run_gemm(oz, handle, cplx, ta, tb, A, B, s, alpha=1.0, beta=0.0, C0=None, kc
 GEMM_SHAPES = [(1, 1, 1), (63, 65, 33), (130, 70, 257), (64, 192, 64)]
 
 
+@pytest.mark.parametrize("kernel", [0, 1, 3])
 @pytest.mark.parametrize("ta,tb", [("N", "N"), ("T", "N"), ("N", "T"), ("T", "T")])
 @pytest.mark.parametrize("m,n,k", GEMM_SHAPES)
 @pytest.mark.parametrize("s", [1, 3, 7, 8])
-def test_dgemm_bit_exact(oz, handle, ta, tb, m, n, k, s):
+def test_dgemm_bit_exact(oz, handle, ta, tb, m, n, k, s, kernel):
     rng = np.random.default_rng(7 * m + 11 * n + 13 * k + s)
     A = wide(rng, (m, k) if ta == "N" else (k, m), 25)
     B = wide(rng, (k, n) if tb == "N" else (n, k), 25)
-    print("dgemm", ta, tb, m, n, k, s, flush=True)
-    got = run_gemm(oz, handle, 0, ta, tb, A, B, s, pad=2)
+    print("dgemm", ta, tb, m, n, k, s, kernel, flush=True)
+    got = run_gemm(oz, handle, 0, ta, tb, A, B, s, pad=2, kernel=kernel)
     assert np.array_equal(got, oracle.emu_gemm(ta, tb, A, B, s))
 
 
+@pytest.mark.parametrize("kernel", [0, 1, 3])
 @pytest.mark.parametrize("ta,tb", [("N", "N"), ("C", "N"), ("T", "C"), ("C", "T")])
 @pytest.mark.parametrize("m,n,k", GEMM_SHAPES)
 @pytest.mark.parametrize("s", [2, 6, 7, 8])
-def test_zgemm_bit_exact(oz, handle, ta, tb, m, n, k, s):
+def test_zgemm_bit_exact(oz, handle, ta, tb, m, n, k, s, kernel):
     rng = np.random.default_rng(17 * m + 19 * n + 23 * k + s)
     A = wide(rng, (m, k) if ta == "N" else (k, m), 25, True)
     B = wide(rng, (k, n) if tb == "N" else (n, k), 25, True)
-    print("zgemm", ta, tb, m, n, k, s, flush=True)
-    got = run_gemm(oz, handle, 1, ta, tb, A, B, s, pad=1)
+    print("zgemm", ta, tb, m, n, k, s, kernel, flush=True)
+    got = run_gemm(oz, handle, 1, ta, tb, A, B, s, pad=1, kernel=kernel)
     assert np.array_equal(got, oracle.emu_gemm(ta, tb, A, B, s))
 
 
@@ -193,13 +196,14 @@ def test_alpha_beta_bit_exact(oz, handle, cplx, alpha, beta):
     assert np.array_equal(got, oracle.emu_gemm("N", "N", A, B, 7, alpha=alpha, beta=beta, C=C0))
 
 
+@pytest.mark.parametrize("kernel", [1, 2, 3])
 @pytest.mark.parametrize("cplx", [0, 1])
 @pytest.mark.parametrize("kc", [64, 128, 1024])
-def test_forced_split_k_bit_exact(oz, handle, cplx, kc):
+def test_forced_split_k_bit_exact(oz, handle, cplx, kc, kernel):
     rng = np.random.default_rng(kc)
     m, n, k = 70, 66, 1100
     A, B = wide(rng, (m, k), 10, bool(cplx)), wide(rng, (k, n), 10, bool(cplx))
-    got = run_gemm(oz, handle, cplx, "N", "N", A, B, 7, kc=kc)
+    got = run_gemm(oz, handle, cplx, "N", "N", A, B, 7, kc=kc, kernel=kernel)
     assert np.array_equal(got, oracle.emu_gemm("N", "N", A, B, 7, kc=kc))
 
 
@@ -365,7 +369,7 @@ def test_large_slice_diagonal_sums_bit_exact(oz, handle):
     oz.oz_split(handle, "B", "N", 0, n, k, dB, ldb, s, fb, sb)
     nch = -(-kpad // kc)
     out = torch.zeros(nch * s * rb * ra, dtype=torch.int32, device="cuda")
-    oz.oz_diag_sums(handle, s, kc, ra, rb, kpad, sa, sb, out)
+    oz.oz_diag_sums(handle, s, kc, ra, rb, kpad, sa, sb, out, kernel=0)
     torch.cuda.synchronize()
     got = out.cpu().numpy().reshape(nch, s, rb, ra).transpose(0, 1, 3, 2)
     ref = oracle.diag_sums(oracle.split("A", "N", A, s)[1], oracle.split("B", "N", B, s)[1], s, kc=kc)

@@ -40,7 +40,7 @@ def test_status_strings():
 
 @pytest.mark.parametrize("side,cplx,nv,k,s,rows,kpad", [
     ("A", 0, 256, 256, 7, 256, 256),
-    ("A", 0, 1, 1, 1, 64, 32),
+    ("A", 0, 1, 1, 1, 128, 32),
     ("B", 0, 65, 33, 3, 128, 64),
     ("A", 1, 100, 37, 7, 256, 96),   # 2*ceil(100/16)*16 = 224 rows -> 256; 74 terms -> 96
     ("B", 1, 100, 37, 7, 128, 96),
