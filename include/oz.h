@@ -62,7 +62,16 @@ typedef struct oz_handle_s* oz_handle_t;
 /* Precision request.
  *  slices : s in 1..OZ_MAX_SLICES, the number of INT8 slices per operand
  *           (Sec. 3.1 "fp64_int8_<s>" modes); 0 selects s from tol.
- *  tol    : target relative error when slices == 0 (must then be > 0).
+ *  tol    : target when slices == 0 (must then be > 0): the scale-weighted
+ *           relative error || D1 (C - AB) D2 ||_F / || D1 AB D2 ||_F with
+ *           D1 = diag(1 / max|op(A)_i:|), D2 = diag(1 / max|op(B)_:j|), on
+ *           the product before alpha/beta.  The call picks a starting s by a
+ *           rule on operand statistics (oz_select_slices), emulates, checks
+ *           the result a posteriori with a randomised double-double residual,
+ *           and while the estimate exceeds tol adds one slice (the next digit
+ *           and the next anti-diagonal, added last) up to smax.  Sec. 4 of
+ *           the paper motivates adjusting the split number to the operator.
+ *           Tolerance-driven calls synchronise their stream.
  *  smax   : largest s the tol-driven selection may use (0: 12).
  *  kchunk : products per INT32 chunk along k; 0 picks the largest multiple of
  *           64 with s*kchunk*127^2 <= 2^31-1; a nonzero value must be a
@@ -74,6 +83,8 @@ typedef struct oz_handle_s* oz_handle_t;
  *           3-stage LDS ring, 2 = 64 x 64 block with 2 stages (both for
  *           s <= 8), 3 = per-diagonal streaming (any s; the only choice for
  *           s > 8).  Every shape gives the same bits.
+ *  sstart : tolerance-driven calls only: the starting slice count (e.g. from
+ *           a learned predictor); 0 uses the rule of oz_select_slices.
  */
 typedef struct {
     int32_t slices;
@@ -81,7 +92,7 @@ typedef struct {
     int32_t kchunk;
     int32_t zmode;
     int32_t kernel;
-    int32_t reserved;
+    int32_t sstart;
     double tol;
 } oz_prec_t;
 
@@ -89,7 +100,7 @@ typedef struct {
 typedef struct {
     int32_t status;        /* OZ_OK or OZ_ERR_NONFINITE                      */
     int32_t slices_used;   /* s of the final result                          */
-    int32_t fallbacks;     /* extra slices added by the residual check       */
+    int32_t fallbacks;     /* slices added after the residual check failed   */
     int32_t kchunks;       /* INT32 chunks along k                           */
     int32_t zmode_used;    /* 4 for complex, 0 for real                      */
     int32_t reserved;
@@ -144,6 +155,15 @@ int oz_dgemm(oz_handle_t handle, char transa, char transb, int64_t m, int64_t n,
 int oz_zgemm(oz_handle_t handle, char transa, char transb, int64_t m, int64_t n, int64_t k,
              const double* alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
              const double* beta, double* C, int64_t ldc, const oz_prec_t* prec, oz_report_t* rep);
+
+/* The starting slice count of a tolerance-driven call: the smallest s in
+ * [1, smax] (smax 0: 12) with 2.5 (s+1) 2^(-7s) sqrt((1/M_A + 1/M_B)/3) <= tol,
+ * M_A / M_B the mean over rows of op(A) / columns of op(B) of the mean square
+ * of x * 2^-E.  Synchronises the handle's stream.  Arguments as oz_dgemm /
+ * oz_zgemm (is_complex selects interleaved complex storage). */
+int oz_select_slices(oz_handle_t handle, char transa, char transb, int64_t m, int64_t n, int64_t k,
+                     int is_complex, const double* A, int64_t lda, const double* B, int64_t ldb,
+                     double tol, int32_t smax, int32_t* s_out);
 
 /* Profiling aid.  While enabled, every oz_dgemm / oz_zgemm call records HIP
  * events on the handle's stream before its split kernels, between the split

@@ -50,9 +50,9 @@ def _load():
     lib.oro_zgemm_dd.argtypes = [C, C, I64, I64, I64, P, P, I64, P, I64, P, P, I64, P, I64, P, I64, P, I64]
     lib.oro_split.argtypes = [C, C, I32, I64, I64, P, I64, I32, P, P]
     lib.oro_diag_sums.argtypes = [I32, I32, I64, I64, P, I64, P, I64, P, I64, P, I64, P]
-    lib.oro_emu_dgemm.argtypes = [C, C, I64, I64, I64, D, P, I64, P, I64, D, P, I64, I32, I64,
+    lib.oro_emu_dgemm.argtypes = [C, C, I64, I64, I64, D, P, I64, P, I64, D, P, I64, I32, I32, I64,
                                   P, I64, P, I64, P, I64]
-    lib.oro_emu_zgemm.argtypes = [C, C, I64, I64, I64, P, P, I64, P, I64, P, P, I64, I32, I64,
+    lib.oro_emu_zgemm.argtypes = [C, C, I64, I64, I64, P, P, I64, P, I64, P, P, I64, I32, I32, I64,
                                   P, I64, P, I64, P, I64]
     lib.oro_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -198,15 +198,22 @@ def diag_sums(digA, digB, s, kc=None, rows=None, cols=None):
     return (out[0], out[1]) if cplx else out[0]
 
 
-def emu_gemm(transa, transb, A, B, s, alpha=1.0, beta=0.0, C=None, kc=None, rows=None, cols=None):
-    """O4: the emulated GEMM on the selected rows x cols (all by default)."""
+def emu_gemm(transa, transb, A, B, s, alpha=1.0, beta=0.0, C=None, kc=None, rows=None, cols=None, s_to=None):
+    """O4: the emulated GEMM on the selected rows x cols (all by default).
+
+    s_to > s: start at s slices and grow one slice at a time to s_to, adding
+    each new anti-diagonal last (the order of the incremental fallback); kc is
+    then the chunk length of the s_to plan (``kchunk(s_to)`` by default).
+    """
+    s1 = s if s_to is None else s_to
+    assert s1 >= s
     cplx = np.iscomplexobj(A) or np.iscomplexobj(B) or np.iscomplexobj(alpha) or np.iscomplexobj(beta)
     dt = np.complex128 if cplx else np.float64
     A, B = _f(A, dt), _f(B, dt)
     m, k = _dims(transa, A, "A")
     k2, n = _dims(transb, B, "B")
     assert k == k2
-    kc = kchunk(s, cplx) if kc is None else kc
+    kc = kchunk(s1, cplx) if kc is None else kc
     assert kc > 0 and (not cplx or kc % 2 == 0)
     Cin = np.zeros((max(m, 1), max(n, 1)), dtype=dt, order="F") if C is None else _f(C, dt)
     rs, nr = _sel(rows, m)
@@ -217,11 +224,11 @@ def emu_gemm(transa, transb, A, B, s, alpha=1.0, beta=0.0, C=None, kc=None, rows
         al = np.array([complex(alpha).real, complex(alpha).imag])
         be = np.array([complex(beta).real, complex(beta).imag])
         lib.oro_emu_zgemm(transa.encode(), transb.encode(), m, n, k, _ptr(al), _ptr(A), _ld(A), _ptr(B),
-                          _ld(B), _ptr(be), _ptr(Cin), _ld(Cin), s, kc, _ptr(rs), nr, _ptr(cs), nc,
+                          _ld(B), _ptr(be), _ptr(Cin), _ld(Cin), s, s1, kc, _ptr(rs), nr, _ptr(cs), nc,
                           _ptr(out), max(1, nr))
     else:
         lib.oro_emu_dgemm(transa.encode(), transb.encode(), m, n, k, float(alpha), _ptr(A), _ld(A),
-                          _ptr(B), _ld(B), float(beta), _ptr(Cin), _ld(Cin), s, kc, _ptr(rs), nr,
+                          _ptr(B), _ld(B), float(beta), _ptr(Cin), _ld(Cin), s, s1, kc, _ptr(rs), nr,
                           _ptr(cs), nc, _ptr(out), max(1, nr))
     return out
 

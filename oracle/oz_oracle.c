@@ -40,6 +40,11 @@
  *       v   = ldexp(acc, E_i + F_j)
  *   - real:    C = alpha*v + beta*C (two rounded products, one rounded add);
  *              with beta == 0 the old C is not read;
+ *   - incremental growth s0 -> s1 (the fallback of a tolerance-driven call):
+ *     starting from acc at s0, for s = s0 .. s1-1 the new anti-diagonal
+ *     d = s + 2 (pairs p + q = d, 1 <= p, q <= s + 1) is added chunk by chunk:
+ *     acc = acc + S_{d,c} * 2^(-7d); digits do not depend on s, so digit s+1
+ *     comes from the same scale exponents;
  *   - complex: Cr = sum_l (ar*br - ai*bi), Ci = sum_l (ar*bi + ai*br), every
  *     product of two slices is an exact integer, both parts use the shared
  *     scales, each chunk holds kc/2 values of l (kc even);
@@ -323,6 +328,38 @@ static void diag_sums_cplx(const int8_t* da, const int8_t* db, int64_t ps_a, int
 
 static double pow2i(int e) { return ldexp(1.0, e); }
 
+/* S_d of one diagonal d only, slices 1..s available (real / complex) */
+static void one_diag_real(const int8_t* da, const int8_t* db, int64_t ps_a, int64_t ps_b, int s, int d,
+                          int64_t l0, int64_t l1, int64_t* out) {
+    int64_t acc = 0;
+    for (int p = 1; p <= s; ++p) {
+        int q = d - p;
+        if (q < 1 || q > s) continue;
+        const int8_t* a = da + (p - 1) * ps_a;
+        const int8_t* b = db + (q - 1) * ps_b;
+        for (int64_t l = l0; l < l1; ++l) acc += (int64_t)a[l] * (int64_t)b[l];
+    }
+    *out = acc;
+}
+
+static void one_diag_cplx(const int8_t* da, const int8_t* db, int64_t ps_a, int64_t ps_b, int s, int d,
+                          int64_t l0, int64_t l1, int64_t* outr, int64_t* outi) {
+    int64_t accr = 0, acci = 0;
+    for (int p = 1; p <= s; ++p) {
+        int q = d - p;
+        if (q < 1 || q > s) continue;
+        const int8_t* a = da + (p - 1) * ps_a;
+        const int8_t* b = db + (q - 1) * ps_b;
+        for (int64_t l = l0; l < l1; ++l) {
+            int64_t ar = a[2 * l], ai = a[2 * l + 1], br = b[2 * l], bi = b[2 * l + 1];
+            accr += ar * br - ai * bi;
+            acci += ar * bi + ai * br;
+        }
+    }
+    *outr = accr;
+    *outi = acci;
+}
+
 /* Exported anti-diagonal sums for parity of the integer stage.
    out[((c*(s) + (d-2)) * nc + jj) * nr + ii] = S_{d,c}(rows[ii], cols[jj]) for
    d = 2..s+1, chunk c = 0..nchunks-1 (real: one plane set; complex: the real
@@ -361,14 +398,16 @@ void oro_diag_sums(int cplx, int s, int64_t k, int64_t kc, const int8_t* digA, i
    selected entries; out (nr x nc, ldo) receives the result. */
 void oro_emu_dgemm(char ta, char tb, int64_t m, int64_t n, int64_t k, double alpha,
                    const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
-                   const double* C, int64_t ldc, int s, int64_t kc, const int64_t* rows, int64_t nr,
+                   const double* C, int64_t ldc, int s, int s1, int64_t kc, const int64_t* rows, int64_t nr,
                    const int64_t* cols, int64_t nc, double* out, int64_t ldo) {
+    /* s1 >= s: grow incrementally from s to s1 (s1 == s: plain emulation) */
+    int sd = s1 > s ? s1 : s; /* digits needed */
     int32_t* EA = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m + 1));
     int32_t* FB = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
-    int8_t* dA = (int8_t*)malloc((size_t)(s * m * k + 1));
-    int8_t* dB = (int8_t*)malloc((size_t)(s * n * k + 1));
-    oro_split('A', ta, 0, m, k, A, lda, s, EA, dA);
-    oro_split('B', tb, 0, n, k, B, ldb, s, FB, dB);
+    int8_t* dA = (int8_t*)malloc((size_t)(sd * m * k + 1));
+    int8_t* dB = (int8_t*)malloc((size_t)(sd * n * k + 1));
+    oro_split('A', ta, 0, m, k, A, lda, sd, EA, dA);
+    oro_split('B', tb, 0, n, k, B, ldb, sd, FB, dB);
     int64_t nch = k > 0 ? (k + kc - 1) / kc : 0;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t jj = 0; jj < nc; ++jj) {
@@ -381,6 +420,14 @@ void oro_emu_dgemm(char ta, char tb, int64_t m, int64_t n, int64_t k, double alp
                 diag_sums_real(dA + i * k, dB + j * k, m * k, n * k, s, l0, l1, S);
                 for (int d = s + 1; d >= 2; --d) acc = acc + (double)S[d] * pow2i(-7 * d);
             }
+            for (int st = s; st < sd; ++st) {
+                int d = st + 2;
+                for (int64_t c = 0; c < nch; ++c) {
+                    int64_t l0 = c * kc, l1 = l0 + kc < k ? l0 + kc : k, Sd;
+                    one_diag_real(dA + i * k, dB + j * k, m * k, n * k, st + 1, d, l0, l1, &Sd);
+                    acc = acc + (double)Sd * pow2i(-7 * d);
+                }
+            }
             double v = ldexp(acc, EA[i] + FB[j]);
             double r = alpha * v;
             if (beta != 0.0) r = r + beta * C[i + j * ldc];
@@ -392,14 +439,15 @@ void oro_emu_dgemm(char ta, char tb, int64_t m, int64_t n, int64_t k, double alp
 
 void oro_emu_zgemm(char ta, char tb, int64_t m, int64_t n, int64_t k, const double* alpha,
                    const double* A, int64_t lda, const double* B, int64_t ldb, const double* beta,
-                   const double* C, int64_t ldc, int s, int64_t kc, const int64_t* rows, int64_t nr,
+                   const double* C, int64_t ldc, int s, int s1, int64_t kc, const int64_t* rows, int64_t nr,
                    const int64_t* cols, int64_t nc, double* out, int64_t ldo) {
+    int sd = s1 > s ? s1 : s;
     int32_t* EA = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m + 1));
     int32_t* FB = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
-    int8_t* dA = (int8_t*)malloc((size_t)(2 * s * m * k + 1));
-    int8_t* dB = (int8_t*)malloc((size_t)(2 * s * n * k + 1));
-    oro_split('A', ta, 1, m, k, A, lda, s, EA, dA);
-    oro_split('B', tb, 1, n, k, B, ldb, s, FB, dB);
+    int8_t* dA = (int8_t*)malloc((size_t)(2 * sd * m * k + 1));
+    int8_t* dB = (int8_t*)malloc((size_t)(2 * sd * n * k + 1));
+    oro_split('A', ta, 1, m, k, A, lda, sd, EA, dA);
+    oro_split('B', tb, 1, n, k, B, ldb, sd, FB, dB);
     int64_t lchunk = kc / 2;
     int64_t nch = k > 0 ? (k + lchunk - 1) / lchunk : 0;
     int bnz = beta[0] != 0.0 || beta[1] != 0.0;
@@ -415,6 +463,15 @@ void oro_emu_zgemm(char ta, char tb, int64_t m, int64_t n, int64_t k, const doub
                 for (int d = s + 1; d >= 2; --d) {
                     accr = accr + (double)Sr[d] * pow2i(-7 * d);
                     acci = acci + (double)Si[d] * pow2i(-7 * d);
+                }
+            }
+            for (int st = s; st < sd; ++st) {
+                int d = st + 2;
+                for (int64_t c = 0; c < nch; ++c) {
+                    int64_t l0 = c * lchunk, l1 = l0 + lchunk < k ? l0 + lchunk : k, Sdr, Sdi;
+                    one_diag_cplx(dA + i * k * 2, dB + j * k * 2, m * k * 2, n * k * 2, st + 1, d, l0, l1, &Sdr, &Sdi);
+                    accr = accr + (double)Sdr * pow2i(-7 * d);
+                    acci = acci + (double)Sdi * pow2i(-7 * d);
                 }
             }
             double vr = ldexp(accr, EA[i] + FB[j]);

@@ -24,7 +24,7 @@ OZ_MAX_SLICES = 18
 # Every symbol include/oz.h declares (checked by the CPU test-suite).
 EXPORTS = ["oz_create", "oz_destroy", "oz_set_stream", "oz_status_string", "oz_workspace_size",
            "oz_set_workspace", "oz_dgemm", "oz_zgemm", "oz_split_layout", "oz_split", "oz_diag_sums",
-           "oz_timing_enable", "oz_timing_read"]
+           "oz_timing_enable", "oz_timing_read", "oz_select_slices"]
 
 
 class OzError(RuntimeError):
@@ -35,7 +35,7 @@ class OzError(RuntimeError):
 
 class oz_prec_t(ctypes.Structure):
     _fields_ = [("slices", ctypes.c_int32), ("smax", ctypes.c_int32), ("kchunk", ctypes.c_int32),
-                ("zmode", ctypes.c_int32), ("kernel", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("zmode", ctypes.c_int32), ("kernel", ctypes.c_int32), ("sstart", ctypes.c_int32),
                 ("tol", ctypes.c_double)]
 
 
@@ -67,6 +67,7 @@ def _load():
         "oz_diag_sums": [P, I32, I64, I32, I64, I64, I64, P, P, P],
         "oz_timing_enable": [P, ctypes.c_int],
         "oz_timing_read": [P, PP(D), PP(D), PP(I64)],
+        "oz_select_slices": [P, C, C, I64, I64, I64, ctypes.c_int, P, I64, P, I64, D, I32, PP(I32)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -115,8 +116,9 @@ def oz_set_stream(handle, stream):
     return _check("oz_set_stream", _lib.oz_set_stream(handle, stream))
 
 
-def prec(slices=7, tol=0.0, smax=0, kchunk=0, zmode=0, kernel=0):
-    return oz_prec_t(slices, smax, kchunk, zmode, kernel, 0, tol)
+def prec(slices=7, tol=0.0, smax=0, kchunk=0, zmode=0, kernel=0, sstart=0):
+    """Precision record; prec(0, tol=...) asks for a tolerance-driven call."""
+    return oz_prec_t(slices, smax, kchunk, zmode, kernel, sstart, tol)
 
 
 def oz_workspace_size(handle, transa, transb, m, n, k, is_complex, p=None):
@@ -181,3 +183,12 @@ def oz_timing_read(handle):
     a, b, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
     _check("oz_timing_read", _lib.oz_timing_read(handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(n)))
     return a.value, b.value, n.value
+
+
+def oz_select_slices(handle, transa, transb, m, n, k, is_complex, A, lda, B, ldb, tol, smax=0):
+    """Starting slice count of a tolerance-driven call (the rule)."""
+    out = ctypes.c_int32()
+    _check("oz_select_slices", _lib.oz_select_slices(handle, _ch(transa), _ch(transb), m, n, k, int(is_complex),
+                                                      _ptr(A), lda, _ptr(B), ldb, float(tol), smax,
+                                                      ctypes.byref(out)))
+    return out.value

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <climits>
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -27,6 +28,15 @@ namespace {
 
 constexpr uint32_t kMagic = 0x6f7a3335u;  // "oz35"
 constexpr int kDefaultSlices = 7;
+constexpr int kDefaultSmax = 12;
+// Rule for the starting slice count of a tolerance-driven call: the
+// scale-weighted error of the emulation behaves like
+//   eps(s) ~ c (s + 1) 2^(-7s) sqrt((1/M_A + 1/M_B) / 3),
+// M = mean over vectors of the mean square of x * 2^-E (truncation leaves
+// about 2^-7s per scaled operand entry; the dropped pairs add a term growing
+// with s).  c = 2.5 covers the data families measured (0.7 .. 2.0).
+constexpr double kRuleC = 2.5;
+constexpr uint64_t kProbeSeed = 0x6f7a5eedull;
 
 bool valid(oz_handle_t h) { return h != nullptr && h->magic == kMagic; }
 
@@ -51,28 +61,46 @@ int64_t kchunk_bound(int s) {
     return kc - kc % 64;
 }
 
-// Workspace carve-up for one GEMM call.
+// Workspace carve-up for one GEMM call (s_lay digit planes; the tol buffers
+// only when a tolerance-driven call needs them).
 struct Plan {
     oz::SliceLayout la, lb;
     int64_t nva, nvb;
-    size_t off_maxa, off_maxb, off_ea, off_fb, off_sa, off_sb, total;
+    size_t off_maxa, off_maxb, off_ea, off_fb, off_sa, off_sb;
+    size_t off_acc, off_msa, off_msb, off_t, off_u, off_diff, off_ref, off_norms, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
-Plan make_plan(int cplx, int64_t m, int64_t n, int64_t k, int s) {
+Plan make_plan(int cplx, int64_t m, int64_t n, int64_t k, int s_lay, bool tol_bufs) {
     Plan p;
     p.nva = m;
     p.nvb = n;
-    p.la = oz::slice_layout(1, cplx, m, k, s);
-    p.lb = oz::slice_layout(0, cplx, n, k, s);
+    p.la = oz::slice_layout(1, cplx, m, k, s_lay);
+    p.lb = oz::slice_layout(0, cplx, n, k, s_lay);
     size_t o = 0;
-    p.off_maxa = o; o = align256(o + sizeof(uint64_t) * static_cast<size_t>(m));
-    p.off_maxb = o; o = align256(o + sizeof(uint64_t) * static_cast<size_t>(n));
-    p.off_ea = o;   o = align256(o + sizeof(int32_t) * static_cast<size_t>(m));
-    p.off_fb = o;   o = align256(o + sizeof(int32_t) * static_cast<size_t>(p.lb.rows_pad));
-    p.off_sa = o;   o = align256(o + static_cast<size_t>(s) * p.la.rows_pad * p.la.kpad);
-    p.off_sb = o;   o = align256(o + static_cast<size_t>(s) * p.lb.rows_pad * p.lb.kpad);
+    auto take = [&o](size_t bytes) {
+        const size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    p.off_maxa = take(sizeof(uint64_t) * static_cast<size_t>(m));
+    p.off_maxb = take(sizeof(uint64_t) * static_cast<size_t>(n));
+    p.off_ea = take(sizeof(int32_t) * static_cast<size_t>(m));
+    p.off_fb = take(sizeof(int32_t) * static_cast<size_t>(p.lb.rows_pad));
+    p.off_sa = take(static_cast<size_t>(s_lay) * p.la.rows_pad * p.la.kpad);
+    p.off_sb = take(static_cast<size_t>(s_lay) * p.lb.rows_pad * p.lb.kpad);
+    p.off_acc = p.off_msa = p.off_msb = p.off_t = p.off_u = p.off_diff = p.off_ref = p.off_norms = 0;
+    if (tol_bufs) {
+        p.off_acc = take(sizeof(double) * static_cast<size_t>(p.la.rows_pad) * p.lb.rows_pad);
+        p.off_msa = take(sizeof(double) * static_cast<size_t>(m));
+        p.off_msb = take(sizeof(double) * static_cast<size_t>(n));
+        p.off_t = take(sizeof(double) * static_cast<size_t>(n));
+        p.off_u = take(sizeof(double) * 4 * static_cast<size_t>(k));
+        p.off_diff = take(sizeof(double) * 2 * static_cast<size_t>(m));
+        p.off_ref = take(sizeof(double) * 2 * static_cast<size_t>(m));
+        p.off_norms = take(sizeof(double) * 2);
+    }
     p.total = o;
     return p;
 }
@@ -145,6 +173,38 @@ bool grid_fits(const Plan& p) {
     return p.la.rows_pad / 64 <= 65535 && p.lb.rows_pad / 64 <= 65535;
 }
 
+// Mean over vectors of the per-vector mean square of x * 2^-E (stats kernel).
+int vector_msq(oz_handle_t h, const oz::OperandView& v, const uint64_t* mx, double* ms, double* mean) {
+    if (oz::launch_vec_stats(v, mx, ms, h->stream) != hipSuccess) return OZ_ERR_HIP;
+    std::vector<double> host(static_cast<size_t>(v.nv));
+    if (v.nv > 0 && (hipMemcpyAsync(host.data(), ms, sizeof(double) * v.nv, hipMemcpyDeviceToHost, h->stream) !=
+                         hipSuccess ||
+                     hipStreamSynchronize(h->stream) != hipSuccess))
+        return OZ_ERR_HIP;
+    double sum = 0.0;
+    for (double x : host) sum += x;
+    *mean = v.nv > 0 ? sum / static_cast<double>(v.nv) : 0.0;
+    return OZ_OK;
+}
+
+// Smallest s in [1, smax] whose rule estimate meets tol (smax if none does).
+int rule_slices(oz_handle_t h, const oz::OperandView& va, const oz::OperandView& vb, const uint64_t* maxa,
+                const uint64_t* maxb, double* msa, double* msb, double tol, int smax, int* s_out) {
+    double ma = 0.0, mb = 0.0;
+    int st = vector_msq(h, va, maxa, msa, &ma);
+    if (!st) st = vector_msq(h, vb, maxb, msb, &mb);
+    if (st) return st;
+    if (!(ma > 0.0) || !(mb > 0.0)) {  // a zero operand: every s is exact
+        *s_out = 1;
+        return OZ_OK;
+    }
+    const double spread = std::sqrt((1.0 / ma + 1.0 / mb) / 3.0);
+    int s = 1;
+    while (s < smax && kRuleC * (s + 1) * std::ldexp(1.0, -7 * s) * spread > tol) ++s;
+    *s_out = s;
+    return OZ_OK;
+}
+
 int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, int64_t n, int64_t k,
                 const double* alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
                 const double* beta, double* C, int64_t ldc, const oz_prec_t* prec, oz_report_t* rep) {
@@ -162,18 +222,30 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
     int s = kDefaultSlices;
     int64_t kc = 0;
     int kernel = 0;
+    bool tol_mode = false;
+    double tol = 0.0;
+    int smax = kDefaultSmax;
     if (prec) {
         if (prec->slices < 0 || prec->slices > OZ_MAX_SLICES) return 14;
-        if (prec->slices == 0) return OZ_ERR_UNSUPPORTED;  // tolerance-driven selection: not in this build
         if (prec->zmode != 0 && prec->zmode != 4) return 14;
         if (prec->kernel < 0 || prec->kernel > 3) return 14;
-        s = prec->slices;
+        if (prec->slices == 0) {
+            tol_mode = true;
+            tol = prec->tol;
+            if (!(tol > 0.0)) return 14;
+            if (prec->smax) smax = prec->smax;
+            if (smax < 1 || smax > OZ_MAX_SLICES) return 14;
+            if (prec->sstart < 0 || prec->sstart > smax) return 14;
+        } else {
+            s = prec->slices;
+        }
         kc = prec->kchunk;
         kernel = prec->kernel;
     }
-    if (s > oz::kMaxLiveSlices && (kernel == 1 || kernel == 2)) return 14;
-    if (kc < 0 || kc % 64 != 0 || (kc > 0 && kc > kchunk_bound(s))) return 14;
-    if (kc == 0) kc = kchunk_bound(s);
+    const int s_plan = tol_mode ? smax : s;  // largest slice count this call may use
+    if (kc < 0 || kc % 64 != 0 || (kc > 0 && kc > kchunk_bound(s_plan))) return 14;
+    if (kc == 0) kc = kchunk_bound(s_plan);
+    if (!tol_mode && s > oz::kMaxLiveSlices && (kernel == 1 || kernel == 2)) return 14;
     if (!alpha || !beta) return OZ_ERR_ARG;
 
     if (rep) {
@@ -197,7 +269,7 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
         return st;
     }
 
-    Plan p = make_plan(cplx, m, n, k, s);
+    Plan p = make_plan(cplx, m, n, k, s_plan, tol_mode);
     if (!grid_fits(p)) return OZ_ERR_UNSUPPORTED;
     st = ensure_ws(h, p.total);
     if (st) return st;
@@ -211,7 +283,7 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
 
     oz::OperandView va = view_a(transa, A, lda, m, k, cplx);
     oz::OperandView vb = view_b(transb, B, ldb, n, k, cplx);
-    hipError_t e = mark(h);
+    hipError_t e = tol_mode ? hipSuccess : mark(h);
     if (e == hipSuccess) e = oz::launch_zero_u64(maxa, static_cast<int64_t>((p.off_ea - p.off_maxa) / 8), h->stream);
     if (e == hipSuccess) e = oz::launch_scan(va, maxa, h->stream);
     if (e == hipSuccess) e = oz::launch_scan(vb, maxb, h->stream);
@@ -230,6 +302,7 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
     g.kpad = p.la.kpad;
     g.chunk_steps = kc / oz::kStep;
     g.s = s;
+    g.s_lay = s_plan;
     g.cplx = cplx;
     g.tile = kernel;
     g.C = C;
@@ -242,13 +315,75 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
     g.beta_i = bi;
     g.beta_zero = beta_zero ? 1 : 0;
     g.diag_out = nullptr;
-    e = mark(h);
-    if (e == hipSuccess) e = oz::launch_gemm(g, h->stream);
-    if (e == hipSuccess) e = mark(h);
-    if (e != hipSuccess) return OZ_ERR_HIP;
+    if (rep) rep->kchunks = static_cast<int32_t>((p.la.kpad + kc - 1) / kc);
+
+    if (!tol_mode) {
+        g.mode = oz::kFinal;
+        e = mark(h);
+        if (e == hipSuccess) e = oz::launch_gemm(g, h->stream);
+        if (e == hipSuccess) e = mark(h);
+        if (e != hipSuccess) return OZ_ERR_HIP;
+    } else {
+        // (1) starting s from the operand statistics
+        double* msa = reinterpret_cast<double*>(ws + p.off_msa);
+        double* msb = reinterpret_cast<double*>(ws + p.off_msb);
+        if (prec->sstart > 0) {
+            s = prec->sstart;
+        } else {
+            st = rule_slices(h, va, vb, maxa, maxb, msa, msb, tol, smax, &s);
+            if (st) return st;
+        }
+        // (2) emulate at s into the raw FP64 sums
+        g.acc = reinterpret_cast<double*>(ws + p.off_acc);
+        g.s = s;
+        g.mode = oz::kRawWrite;
+        if (oz::launch_gemm(g, h->stream) != hipSuccess) return OZ_ERR_HIP;
+        // (3) check; grow by one slice (new digit, new anti-diagonal) until it passes
+        oz::CheckArgs c;
+        c.opa = va;
+        c.opb = vb;
+        c.maxa = maxa;
+        c.maxb = maxb;
+        c.acc = g.acc;
+        c.Mp = p.la.rows_pad;
+        c.EA = EA;
+        c.FB = FB;
+        c.seed = kProbeSeed;
+        c.t = reinterpret_cast<double*>(ws + p.off_t);
+        c.u = reinterpret_cast<double*>(ws + p.off_u);
+        c.diff = reinterpret_cast<double*>(ws + p.off_diff);
+        c.ref = reinterpret_cast<double*>(ws + p.off_ref);
+        c.norms = reinterpret_cast<double*>(ws + p.off_norms);
+        int fallbacks = 0;
+        double eps = 0.0;
+        for (;;) {
+            if (oz::launch_residual(c, h->stream) != hipSuccess) return OZ_ERR_HIP;
+            double nrm[2];
+            if (hipMemcpyAsync(nrm, c.norms, sizeof(nrm), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+                hipStreamSynchronize(h->stream) != hipSuccess)
+                return OZ_ERR_HIP;
+            eps = nrm[1] > 0.0 ? std::sqrt(nrm[0] / nrm[1]) : std::sqrt(nrm[0]);
+            if (!(eps > tol) || s >= smax) break;  // NaN (non-finite input) also stops
+            g.s = s + 1;
+            g.top = 1;
+            g.mode = oz::kRawAdd;
+            if (oz::launch_gemm(g, h->stream) != hipSuccess) return OZ_ERR_HIP;
+            g.top = 0;
+            ++s;
+            ++fallbacks;
+        }
+        // (4) C = alpha * ldexp(acc, E + F) + beta * C
+        if (oz::launch_finalize(g.acc, p.la.rows_pad, EA, FB, C, ldc, m, n, cplx, ar, ai, br, bi, beta_zero ? 1 : 0,
+                                h->stream) != hipSuccess)
+            return OZ_ERR_HIP;
+        if (rep) {
+            rep->slices_used = s;
+            rep->fallbacks = fallbacks;
+            rep->resid_est = eps;
+        }
+    }
 
     if (rep) {
-        rep->kchunks = static_cast<int32_t>((p.la.kpad + kc - 1) / kc);
         if (hipStreamSynchronize(h->stream) != hipSuccess) return OZ_ERR_HIP;
         std::vector<int32_t> ea(static_cast<size_t>(m)), fb(static_cast<size_t>(n));
         if (hipMemcpy(ea.data(), EA, sizeof(int32_t) * m, hipMemcpyDeviceToHost) != hipSuccess ||
@@ -358,8 +493,11 @@ int oz_workspace_size(oz_handle_t h, char transa, char transb, int64_t m, int64_
     if (k < 0) return 5;
     if (!bytes) return OZ_ERR_ARG;
     int s = prec ? prec->slices : kDefaultSlices;
-    if (s < 1 || s > OZ_MAX_SLICES) return 14;
-    *bytes = make_plan(is_complex ? 1 : 0, m, n, k, s).total;
+    if (s < 0 || s > OZ_MAX_SLICES) return 14;
+    const bool tol = prec && prec->slices == 0;
+    const int smax = (prec && prec->smax) ? prec->smax : kDefaultSmax;
+    if (tol && (smax < 1 || smax > OZ_MAX_SLICES)) return 14;
+    *bytes = make_plan(is_complex ? 1 : 0, m, n, k, tol ? smax : s, tol).total;
     return OZ_OK;
 }
 
@@ -445,9 +583,59 @@ int oz_diag_sums(oz_handle_t h, int32_t slices, int64_t kchunk, int32_t kernel, 
     g.kpad = kpad;
     g.chunk_steps = kchunk / oz::kStep;
     g.s = slices;
+    g.s_lay = slices;
     g.tile = kernel;
     g.diag_out = out;
     return hip_status(oz::launch_gemm(g, h->stream));
+}
+
+int oz_select_slices(oz_handle_t h, char transa, char transb, int64_t m, int64_t n, int64_t k, int is_complex,
+                     const double* A, int64_t lda, const double* B, int64_t ldb, double tol, int32_t smax,
+                     int32_t* s_out) {
+    if (!valid(h)) return OZ_ERR_HANDLE;
+    if (!trans_ok(transa)) return 1;
+    if (!trans_ok(transb)) return 2;
+    if (m < 0) return 3;
+    if (n < 0) return 4;
+    if (k < 0) return 5;
+    const int64_t rows_a = up(transa) == 'N' ? m : k;
+    const int64_t rows_b = up(transb) == 'N' ? k : n;
+    if (lda < (rows_a > 1 ? rows_a : 1)) return 8;
+    if (ldb < (rows_b > 1 ? rows_b : 1)) return 10;
+    if (!(tol > 0.0) || smax < 0 || smax > OZ_MAX_SLICES || !s_out) return OZ_ERR_ARG;
+    if (smax == 0) smax = kDefaultSmax;
+    if (use_device(h)) return OZ_ERR_HIP;
+    if (m == 0 || n == 0 || k == 0) {
+        *s_out = 1;
+        return OZ_OK;
+    }
+    const int cplx = is_complex ? 1 : 0;
+    size_t o = 0;
+    const size_t off_ma = o;
+    o = align256(o + sizeof(uint64_t) * m);
+    const size_t off_mb = o;
+    o = align256(o + sizeof(uint64_t) * n);
+    const size_t off_sa = o;
+    o = align256(o + sizeof(double) * m);
+    const size_t off_sb = o;
+    o = align256(o + sizeof(double) * n);
+    int st = ensure_ws(h, o);
+    if (st) return st;
+    char* ws = static_cast<char*>(h->ws);
+    uint64_t* maxa = reinterpret_cast<uint64_t*>(ws + off_ma);
+    uint64_t* maxb = reinterpret_cast<uint64_t*>(ws + off_mb);
+    oz::OperandView va = view_a(transa, A, lda, m, k, cplx);
+    oz::OperandView vb = view_b(transb, B, ldb, n, k, cplx);
+    hipError_t e = oz::launch_zero_u64(maxa, static_cast<int64_t>((off_sa - off_ma) / 8), h->stream);
+    if (e == hipSuccess) e = oz::launch_scan(va, maxa, h->stream);
+    if (e == hipSuccess) e = oz::launch_scan(vb, maxb, h->stream);
+    if (e != hipSuccess) return OZ_ERR_HIP;
+    int s = 0;
+    st = rule_slices(h, va, vb, maxa, maxb, reinterpret_cast<double*>(ws + off_sa),
+                     reinterpret_cast<double*>(ws + off_sb), tol, smax, &s);
+    if (st) return st;
+    *s_out = s;
+    return OZ_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,268 @@
+// oz_check.hip -- tolerance-driven slice count: operand statistics for the
+// a-priori rule, the a-posteriori residual check, and the final scaling pass.
+//
+// Residual check (randomised, one probe vector): with D1 = diag(1/max|op(A)_i:|),
+// D2 = diag(1/max|op(B)_:j|) and sigma a +-1 vector drawn from a counter-based
+// hash,
+//   y1 = D1 * C_emu * D2 * sigma        (C_emu = ldexp(acc, E_i + F_j))
+//   y2 = D1 * op(A) * (op(B) * (D2 * sigma))
+// are formed in double-double arithmetic, and
+//   eps_est = || y1 - y2 || / || y2 ||
+// estimates the scale-weighted Frobenius error || D1 (C_emu - AB) D2 ||_F /
+// || D1 AB D2 ||_F (for +-1 entries E||X sigma||^2 = ||X||_F^2).  Both sides use
+// the same rounded weights t_j = D2_jj * sigma_j and w_i = D1_ii, so y1 - y2
+// carries the emulation error only.  The work is O(mk + kn + mn), against
+// O(mnk) for the product itself.
+#include "oz_internal.h"
+
+namespace oz {
+
+namespace {
+
+// ---- double-double helpers (FMA TwoProduct, Knuth TwoSum) ----------------
+struct dd {
+    double hi, lo;
+};
+__device__ __forceinline__ dd two_sum(double a, double b) {
+    const double s = a + b, z = s - a;
+    return {s, (a - (s - z)) + (b - z)};
+}
+__device__ __forceinline__ dd dd_add_prod(dd acc, double a, double b) {
+    // acc + a*b, Dot2 style: error terms gathered in lo
+    const double p = a * b, e = fma(a, b, -p);
+    const dd s = two_sum(acc.hi, p);
+    return {s.hi, acc.lo + (s.lo + e)};
+}
+__device__ __forceinline__ dd dd_norm(dd x) { return two_sum(x.hi, x.lo); }
+__device__ __forceinline__ dd dd_mul_d(dd x, double w) {
+    const double p = x.hi * w, e = fma(x.hi, w, -p);
+    return dd_norm({p, e + x.lo * w});
+}
+__device__ __forceinline__ double dd_sub_to_d(dd a, dd b) {
+    const dd s = two_sum(a.hi, -b.hi);
+    return s.hi + (s.lo + (a.lo - b.lo));
+}
+
+__device__ __forceinline__ double max_of_bits(uint64_t b) { return __longlong_as_double(static_cast<long long>(b)); }
+
+// +-1 from the splitmix64 mixer of (seed, j)
+__device__ __forceinline__ double rademacher(uint64_t seed, int64_t j) {
+    uint64_t z = seed + static_cast<uint64_t>(j + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (z >> 63) ? -1.0 : 1.0;
+}
+
+__device__ __forceinline__ void load_elem(const OperandView& op, int64_t v, int64_t l, double& re, double& im) {
+    const double* e = op.X + (v * op.sv + l * op.sl) * (op.cplx ? 2 : 1);
+    re = e[0];
+    im = op.cplx ? (op.conj ? -e[1] : e[1]) : 0.0;
+}
+
+// ---- per-vector mean square of x * 2^-E ------------------------------------
+// One block per 64 vectors; 4 waves split the terms; fixed-order reduction.
+__global__ __launch_bounds__(256) void vec_stats_kernel(OperandView op, const uint64_t* maxbits, double* ms) {
+    __shared__ double red[4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t v = static_cast<int64_t>(blockIdx.x) * 64 + lane;
+    double acc = 0.0;
+    if (v < op.nv) {
+        const uint64_t mb = maxbits[v];
+        int E = 0;
+        if (mb != 0 && mb < 0x7ff0000000000000ull) frexp(max_of_bits(mb), &E);
+        for (int64_t l = wave; l < op.k; l += 4) {
+            double re, im;
+            load_elem(op, v, l, re, im);
+            const double a = ldexp(re, -E), b = ldexp(im, -E);
+            acc += a * a + b * b;
+        }
+    }
+    red[wave][lane] = acc;
+    __syncthreads();
+    if (wave == 0 && v < op.nv) {
+        const double t = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+        ms[v] = op.k > 0 ? t / (static_cast<double>(op.k) * (op.cplx ? 2.0 : 1.0)) : 0.0;
+    }
+}
+
+// ---- t_j = sigma_j / max|op(B)_:j| ------------------------------------------
+__global__ void weights_kernel(const uint64_t* maxbits_b, int64_t n, uint64_t seed, double* t) {
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const double mx = max_of_bits(maxbits_b[j]);
+    t[j] = mx > 0.0 ? rademacher(seed, j) / mx : 0.0;
+}
+
+// ---- u = op(B) t in double-double; u[l] = (re.hi, re.lo, im.hi, im.lo) ------
+__global__ void gemv_b_kernel(OperandView opb, const double* t, double* u) {
+    const int64_t l = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (l >= opb.k) return;
+    dd sr = {0.0, 0.0}, si = {0.0, 0.0};
+    for (int64_t j = 0; j < opb.nv; ++j) {
+        double re, im;
+        load_elem(opb, j, l, re, im);
+        sr = dd_add_prod(sr, re, t[j]);
+        si = dd_add_prod(si, im, t[j]);
+    }
+    sr = dd_norm(sr);
+    si = dd_norm(si);
+    u[4 * l] = sr.hi;
+    u[4 * l + 1] = sr.lo;
+    u[4 * l + 2] = si.hi;
+    u[4 * l + 3] = si.lo;
+}
+
+// ---- per row i of op(A): y2 = w_i op(A)_i: u, y1 = w_i sum_j C_emu_ij t_j ----
+// Writes diff[i] = y1 - y2 and ref[i] = y2 (real, or real and imaginary parts
+// at 2i, 2i+1 for complex).
+__global__ void rows_kernel(OperandView opa, const uint64_t* maxbits_a, const double* u, const double* acc,
+                            int64_t Mp, const int32_t* EA, const int32_t* FB, const double* t, int64_t n,
+                            double* diff, double* ref) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= opa.nv) return;
+    const double mx = max_of_bits(maxbits_a[i]);
+    const double w = mx > 0.0 ? 1.0 / mx : 0.0;
+    // y2 = a_i . u  (complex: (ar + i ai)(ur + i ui))
+    dd y2r = {0.0, 0.0}, y2i = {0.0, 0.0};
+    for (int64_t l = 0; l < opa.k; ++l) {
+        double ar, ai;
+        load_elem(opa, i, l, ar, ai);
+        const double urh = u[4 * l], url = u[4 * l + 1], uih = u[4 * l + 2], uil = u[4 * l + 3];
+        y2r = dd_add_prod(y2r, ar, urh);
+        y2r = dd_add_prod(y2r, ar, url);
+        if (opa.cplx) {
+            y2r = dd_add_prod(y2r, -ai, uih);
+            y2r = dd_add_prod(y2r, -ai, uil);
+            y2i = dd_add_prod(y2i, ar, uih);
+            y2i = dd_add_prod(y2i, ar, uil);
+            y2i = dd_add_prod(y2i, ai, urh);
+            y2i = dd_add_prod(y2i, ai, url);
+        }
+    }
+    // y1 = sum_j ldexp(acc_ij, E_i + F_j) t_j over the slice-row(s) of row i
+    const int64_t r_re = opa.cplx ? 32 * (i >> 4) + 16 * ((i >> 3) & 1) + (i & 7) : i;
+    const int64_t r_im = r_re + 8;
+    dd y1r = {0.0, 0.0}, y1i = {0.0, 0.0};
+    const int32_t e = EA[i];
+    for (int64_t j = 0; j < n; ++j) {
+        const int ef = e + FB[j];
+        y1r = dd_add_prod(y1r, ldexp(acc[j * Mp + r_re], ef), t[j]);
+        if (opa.cplx) y1i = dd_add_prod(y1i, ldexp(acc[j * Mp + r_im], ef), t[j]);
+    }
+    y1r = dd_mul_d(dd_norm(y1r), w);
+    y2r = dd_mul_d(dd_norm(y2r), w);
+    if (!opa.cplx) {
+        diff[i] = dd_sub_to_d(y1r, y2r);
+        ref[i] = y2r.hi + y2r.lo;
+    } else {
+        y1i = dd_mul_d(dd_norm(y1i), w);
+        y2i = dd_mul_d(dd_norm(y2i), w);
+        diff[2 * i] = dd_sub_to_d(y1r, y2r);
+        diff[2 * i + 1] = dd_sub_to_d(y1i, y2i);
+        ref[2 * i] = y2r.hi + y2r.lo;
+        ref[2 * i + 1] = y2i.hi + y2i.lo;
+    }
+}
+
+// ---- out[0] = sum diff^2, out[1] = sum ref^2 (one block, fixed order) ------
+__global__ __launch_bounds__(256) void norms_kernel(const double* diff, const double* ref, int64_t len, double* out) {
+    __shared__ double sd[256], sr[256];
+    double a = 0.0, b = 0.0;
+    for (int64_t i = threadIdx.x; i < len; i += 256) {
+        a += diff[i] * diff[i];
+        b += ref[i] * ref[i];
+    }
+    sd[threadIdx.x] = a;
+    sr[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            sd[threadIdx.x] += sd[threadIdx.x + w];
+            sr[threadIdx.x] += sr[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = sd[0];
+        out[1] = sr[0];
+    }
+}
+
+// ---- C = alpha * ldexp(acc, E+F) + beta * C (same arithmetic as the fused
+// GEMM epilogue); NaN where a scale marks Inf/NaN input ---------------------
+__global__ void finalize_kernel(const double* acc, int64_t Mp, const int32_t* EA, const int32_t* FB, double* C,
+                                int64_t ldc, int64_t m, int64_t n, int cplx, double ar, double ai, double br,
+                                double bi, int beta_zero) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const double nan = __longlong_as_double(0x7ff8000000000000ll);
+    const int32_t e = EA[i];
+    const int64_t r_re = cplx ? 32 * (i >> 4) + 16 * ((i >> 3) & 1) + (i & 7) : i;
+    for (int64_t j = blockIdx.y; j < n; j += gridDim.y) {
+        const int32_t f = FB[j];
+        const bool bad = e == kNonFiniteExp || f == kNonFiniteExp;
+        if (!cplx) {
+            double* c = C + i + j * ldc;
+            double out = nan;
+            if (!bad) {
+                const double v = ldexp(acc[j * Mp + r_re], e + f);
+                out = ar * v;
+                if (!beta_zero) out = out + br * (*c);
+            }
+            *c = out;
+        } else {
+            double* c = C + 2 * (i + j * ldc);
+            double outr = nan, outi = nan;
+            if (!bad) {
+                const double vr = ldexp(acc[j * Mp + r_re], e + f);
+                const double vi = ldexp(acc[j * Mp + r_re + 8], e + f);
+                outr = ar * vr - ai * vi;
+                outi = ar * vi + ai * vr;
+                if (!beta_zero) {
+                    const double cr = c[0], cim = c[1];
+                    outr = outr + (br * cr - bi * cim);
+                    outi = outi + (br * cim + bi * cr);
+                }
+            }
+            c[0] = outr;
+            c[1] = outi;
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_vec_stats(const OperandView& op, const uint64_t* maxbits, double* ms, hipStream_t st) {
+    if (op.nv <= 0) return hipSuccess;
+    hipLaunchKernelGGL(vec_stats_kernel, dim3(static_cast<unsigned>((op.nv + 63) / 64)), dim3(256), 0, st, op, maxbits,
+                       ms);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(const CheckArgs& c, hipStream_t st) {
+    const int64_t n = c.opb.nv, k = c.opa.k, m = c.opa.nv;
+    if (m <= 0 || n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(weights_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, c.maxb, n,
+                       c.seed, c.t);
+    if (k > 0)
+        hipLaunchKernelGGL(gemv_b_kernel, dim3(static_cast<unsigned>((k + 255) / 256)), dim3(256), 0, st, c.opb, c.t,
+                           c.u);
+    hipLaunchKernelGGL(rows_kernel, dim3(static_cast<unsigned>((m + 255) / 256)), dim3(256), 0, st, c.opa, c.maxa, c.u,
+                       c.acc, c.Mp, c.EA, c.FB, c.t, n, c.diff, c.ref);
+    const int64_t len = c.opa.cplx ? 2 * m : m;
+    hipLaunchKernelGGL(norms_kernel, dim3(1), dim3(256), 0, st, c.diff, c.ref, len, c.norms);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double* acc, int64_t Mp, const int32_t* EA, const int32_t* FB, double* C,
+                           int64_t ldc, int64_t m, int64_t n, int cplx, double ar, double ai, double br, double bi,
+                           int beta_zero, hipStream_t st) {
+    if (m <= 0 || n <= 0) return hipSuccess;
+    dim3 grid(static_cast<unsigned>((m + 255) / 256), static_cast<unsigned>(n < 65535 ? n : 65535));
+    hipLaunchKernelGGL(finalize_kernel, grid, dim3(256), 0, st, acc, Mp, EA, FB, C, ldc, m, n, cplx, ar, ai, br, bi,
+                       beta_zero);
+    return hipGetLastError();
+}
+
+}  // namespace oz

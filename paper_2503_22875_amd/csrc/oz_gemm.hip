@@ -44,12 +44,14 @@ struct DiagScale<0> {
     static constexpr double value = 1.0 / 16384.0;
 };
 
-template <int S, int DD>
-__device__ __forceinline__ void fold_diags(double (&acc64)[16], v16i (&acc)[S]) {
-    // d = DD + 2 from the top: DD = S-1, S-2, ..., 0
+// Fold the live INT32 diagonal tiles into the FP64 tile, from the top
+// (d = DD + 2 = S + 1) down to d = DLO + 2; acc[i] holds diagonal DLO + i.
+template <int ND, int DLO, int DD>
+__device__ __forceinline__ void fold_diags(double (&acc64)[16], v16i (&acc)[ND]) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc64[r] = acc64[r] + static_cast<double>(acc[DD][r]) * DiagScale<DD>::value;
-    if constexpr (DD > 0) fold_diags<S, DD - 1>(acc64, acc);
+    for (int r = 0; r < 16; ++r)
+        acc64[r] = acc64[r] + static_cast<double>(acc[DD - DLO][r]) * DiagScale<DD>::value;
+    if constexpr (DD > DLO) fold_diags<ND, DLO, DD - 1>(acc64, acc);
 }
 
 // Tile order: the hardware hands consecutive blocks to the 8 XCDs in turn,
@@ -86,13 +88,18 @@ __device__ __forceinline__ void wait_vm() {
 // and one rounded add per part, no fused multiply-add), or NaN where the row
 // or column scale marks Inf/NaN input.  Register r holds C' row
 // row0 + 8*(r/4) + 4*half + r%4 of column col.
-template <bool CPLX>
 __device__ __forceinline__ void store_tile(const GemmArgs& g, const double (&acc64)[16], int64_t row0, int half,
                                            int64_t col) {
     const double nan = __longlong_as_double(0x7ff8000000000000ll);
+    if (g.mode != kFinal) {
+        // raw tile sums in C' space (every padded row and column is stored)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) g.acc[col * g.Mp + row0 + 8 * (r >> 2) + 4 * half + (r & 3)] = acc64[r];
+        return;
+    }
     if (col >= g.n) return;
     const int32_t f = g.FB[col];
-    if constexpr (!CPLX) {
+    if (!g.cplx) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int64_t i = row0 + 8 * (r >> 2) + 4 * half + (r & 3);
@@ -153,10 +160,14 @@ struct TileCfg {
     static_assert(BM % 64 == 0 && BN % 64 == 0, "block sides are multiples of 64");
 };
 
-template <int S, int WMW, int WNW, int NST, bool CPLX, bool DIAG, bool MULTI>
+// TOP: only the anti-diagonal d = S + 1 (pairs p + q = S + 1), the growth
+// step S-1 -> S of a tolerance-driven call; otherwise all d = 2 .. S+1.
+template <int S, int WMW, int WNW, int NST, bool TOP, bool DIAG, bool MULTI>
 __global__ __attribute__((amdgpu_flat_work_group_size(64 * WMW * WNW, 64 * WMW * WNW),
                           amdgpu_waves_per_eu(2, 2))) void gemm_kernel(GemmArgs g) {
     using T = TileCfg<S, WMW, WNW, NST>;
+    constexpr int DLO = TOP ? S - 1 : 0;  // lowest live diagonal index (d - 2)
+    constexpr int ND = S - DLO;           // live INT32 diagonal tiles
     __shared__ v4i lds[NST][T::STAGE];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -178,13 +189,16 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64 * WMW * WNW, 64 * WMW *
             const int j = wave + T::NW * i;  // wave-uniform
             if (j >= T::R) break;
             const v4i* src;
+            // LDS plane hp = h*S + p  <-  global plane (2*ks + h)*s_lay + p
             if (j < T::RA) {
                 const int hp = j / (T::BM / 64), rb = j % (T::BM / 64);
-                src = SA + (2 * ks * S + hp) * g.Mp + tm * T::BM + rb * 64 + lane;
+                const int64_t plane = (2 * ks + hp / S) * g.s_lay + hp % S;
+                src = SA + plane * g.Mp + tm * T::BM + rb * 64 + lane;
             } else {
                 const int jb = j - T::RA;
                 const int hp = jb / (T::BN / 64), cb = jb % (T::BN / 64);
-                src = SB + (2 * ks * S + hp) * g.Np + tn * T::BN + cb * 64 + lane;
+                const int64_t plane = (2 * ks + hp / S) * g.s_lay + hp % S;
+                src = SB + plane * g.Np + tn * T::BN + cb * 64 + lane;
             }
             __builtin_amdgcn_global_load_lds((global_cvoid*)(src), (lds_void*)(&lds[buf][j * 64]), 16, 0, 0);
         }
@@ -197,19 +211,22 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64 * WMW * WNW, 64 * WMW *
             wait_vm<T::RLO>();
     };
 
-    v16i acc[S];
+    v16i acc[ND];
 #pragma unroll
-    for (int d = 0; d < S; ++d)
+    for (int d = 0; d < ND; ++d)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[d][r] = 0;
-    double acc64[16];
-    if constexpr (MULTI) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc64[r] = 0.0;
-    }
 
     const int64_t row0 = tm * T::BM + wm * 32;
     const int64_t col = tn * T::BN + wn * 32 + row;
+    // FP64 tile: 0, or the raw sums of the previous slice count (kRawAdd)
+    auto init64 = [&](double (&a64)[16]) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            a64[r] = (g.mode == kRawAdd) ? g.acc[col * g.Mp + row0 + 8 * (r >> 2) + 4 * half + (r & 3)] : 0.0;
+    };
+    double acc64[16];
+    if constexpr (MULTI) init64(acc64);
 
     // prologue: stages 0 .. NST-2 in flight
 #pragma unroll
@@ -234,23 +251,23 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64 * WMW * WNW, 64 * WMW *
         for (int p = 0; p < S; ++p) {
             const v4i a = L[(half * S + p) * T::BM + wm * 32 + row];
 #pragma unroll
-            for (int q = 0; q < S - p; ++q)
-                acc[p + q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, bq[q], acc[p + q], 0, 0, 0);
+            for (int q = (DLO > p ? DLO - p : 0); q < S - p; ++q)
+                acc[p + q - DLO] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, bq[q], acc[p + q - DLO], 0, 0, 0);
         }
         if constexpr (MULTI || DIAG) {
             if (++chunk_pos == g.chunk_steps || ks + 1 == nsteps) {
                 if constexpr (DIAG) {
 #pragma unroll
-                    for (int d = 0; d < S; ++d)
+                    for (int d = 0; d < ND; ++d)
 #pragma unroll
                         for (int r = 0; r < 16; ++r)
-                            g.diag_out[((chunk * S + d) * g.Np + col) * g.Mp + row0 + 8 * (r >> 2) + 4 * half +
-                                       (r & 3)] = acc[d][r];
+                            g.diag_out[((chunk * S + d + DLO) * g.Np + col) * g.Mp + row0 + 8 * (r >> 2) +
+                                       4 * half + (r & 3)] = acc[d][r];
                 } else {
-                    fold_diags<S, S - 1>(acc64, acc);
+                    fold_diags<ND, DLO, S - 1>(acc64, acc);
                 }
 #pragma unroll
-                for (int d = 0; d < S; ++d)
+                for (int d = 0; d < ND; ++d)
 #pragma unroll
                     for (int r = 0; r < 16; ++r) acc[d][r] = 0;
                 chunk_pos = 0;
@@ -267,11 +284,10 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64 * WMW * WNW, 64 * WMW *
     }
     if constexpr (DIAG) return;
     if constexpr (!MULTI) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc64[r] = 0.0;
-        fold_diags<S, S - 1>(acc64, acc);
+        init64(acc64);
+        fold_diags<ND, DLO, S - 1>(acc64, acc);
     }
-    store_tile<CPLX>(g, acc64, row0, half, col);
+    store_tile(g, acc64, row0, half, col);
 }
 
 // Streaming form for any s (used above the all-diagonal kernel's register
@@ -281,7 +297,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64 * WMW * WNW, 64 * WMW *
 // stage, double buffered) into the INT32 tile, which is then folded into the
 // FP64 tile -- the same order as the all-diagonal kernel, hence the same bits.
 // 64 x 64 block tile, 4 waves.
-template <bool CPLX, bool DIAG>
+template <bool DIAG>
 __global__ __attribute__((amdgpu_flat_work_group_size(256, 256))) void gemm_stream_kernel(GemmArgs g) {
     __shared__ v4i lds[2][256];  // [A: h*64 + row | B: 128 + h*64 + col]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -299,19 +315,21 @@ __global__ __attribute__((amdgpu_flat_work_group_size(256, 256))) void gemm_stre
     // wave 0/1: A half 0/1 of slice p; wave 2/3: B half 0/1 of slice q
     auto issue = [&](int64_t ks, int p, int q, int buf) {
         const int h = wave & 1;
-        const v4i* src = (wave < 2) ? SA + ((2 * ks + h) * s + (p - 1)) * g.Mp + tm * 64 + lane
-                                    : SB + ((2 * ks + h) * s + (q - 1)) * g.Np + tn * 64 + lane;
+        const v4i* src = (wave < 2) ? SA + ((2 * ks + h) * g.s_lay + (p - 1)) * g.Mp + tm * 64 + lane
+                                    : SB + ((2 * ks + h) * g.s_lay + (q - 1)) * g.Np + tn * 64 + lane;
         __builtin_amdgcn_global_load_lds((global_cvoid*)(src), (lds_void*)(&lds[buf][wave * 64]), 16, 0, 0);
     };
 
     double acc64[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc64[r] = 0.0;
+    for (int r = 0; r < 16; ++r)
+        acc64[r] = (g.mode == kRawAdd) ? g.acc[col * g.Mp + row0 + 8 * (r >> 2) + 4 * half + (r & 3)] : 0.0;
     const int64_t nchunks = (nsteps + g.chunk_steps - 1) / g.chunk_steps;
+    const int dmin = g.top ? s + 1 : 2;
     for (int64_t c = 0; c < nchunks; ++c) {
         const int64_t k0 = c * g.chunk_steps;
         const int64_t k1 = (k0 + g.chunk_steps < nsteps) ? k0 + g.chunk_steps : nsteps;
-        for (int d = s + 1; d >= 2; --d) {
+        for (int d = s + 1; d >= dmin; --d) {
             const int plo = (d - s > 1) ? d - s : 1;
             const int phi = (d - 1 < s) ? d - 1 : s;
             const int np = phi - plo + 1;
@@ -347,7 +365,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(256, 256))) void gemm_stre
         }
     }
     if constexpr (DIAG) return;
-    store_tile<CPLX>(g, acc64, row0, half, col);
+    store_tile(g, acc64, row0, half, col);
 }
 
 __global__ void scale_c_kernel(double* C, int64_t ldc, int64_t m, int64_t n, int cplx, double br, double bi,
@@ -379,11 +397,13 @@ hipError_t launch_cfg(const GemmArgs& g, hipStream_t st) {
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     dim3 grid(static_cast<unsigned>(blocks)), block(64 * T::NW);
     const bool multi = g.chunk_steps < g.kpad / kStep;
-    if (g.diag_out)
+    if (g.diag_out && !g.top)
         hipLaunchKernelGGL((gemm_kernel<S, WMW, WNW, NST, false, true, true>), grid, block, 0, st, g);
-    else if (g.cplx && multi)
+    else if (g.diag_out)
+        hipLaunchKernelGGL((gemm_kernel<S, WMW, WNW, NST, true, true, true>), grid, block, 0, st, g);
+    else if (g.top && multi)
         hipLaunchKernelGGL((gemm_kernel<S, WMW, WNW, NST, true, false, true>), grid, block, 0, st, g);
-    else if (g.cplx)
+    else if (g.top)
         hipLaunchKernelGGL((gemm_kernel<S, WMW, WNW, NST, true, false, false>), grid, block, 0, st, g);
     else if (multi)
         hipLaunchKernelGGL((gemm_kernel<S, WMW, WNW, NST, false, false, true>), grid, block, 0, st, g);
@@ -406,18 +426,17 @@ hipError_t launch_stream(const GemmArgs& g, hipStream_t st) {
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     dim3 grid(static_cast<unsigned>(blocks));
     if (g.diag_out)
-        hipLaunchKernelGGL((gemm_stream_kernel<false, true>), grid, dim3(256), 0, st, g);
-    else if (g.cplx)
-        hipLaunchKernelGGL((gemm_stream_kernel<true, false>), grid, dim3(256), 0, st, g);
+        hipLaunchKernelGGL((gemm_stream_kernel<true>), grid, dim3(256), 0, st, g);
     else
-        hipLaunchKernelGGL((gemm_stream_kernel<false, false>), grid, dim3(256), 0, st, g);
+        hipLaunchKernelGGL((gemm_stream_kernel<false>), grid, dim3(256), 0, st, g);
     return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t st) {
-    if (g.s < 1 || g.s > 18) return hipErrorInvalidValue;
+    if (g.s < 1 || g.s > 18 || g.s_lay < g.s) return hipErrorInvalidValue;
+    if (g.mode != kFinal && g.acc == nullptr) return hipErrorInvalidValue;
     if (g.tile == 3) return launch_stream(g, st);
     switch (g.s) {
         case 1: return launch_s<1>(g, st);

@@ -55,9 +55,13 @@ struct GemmArgs {
     const int32_t* FB;  // scale exponents of B (per column)
     int64_t Mp, Np, kpad;
     int64_t chunk_steps;   // MFMA steps (of kStep terms) per INT32 chunk
-    int s;
+    int s;                 // slices used: pairs p + q <= s + 1
+    int s_lay;             // digit planes in the slice layout (>= s)
+    int top;               // 1: only the anti-diagonal d = s + 1 (growth s-1 -> s)
     int cplx;
     int tile;              // 0 auto, 1: 128 x 64 block, 2: 64 x 64 block, 3: per-diagonal streaming
+    int mode;              // kFinal, kRawWrite, kRawAdd (see below)
+    double* acc;           // raw FP64 tile sums acc[col * Mp + row] for the raw modes
     // epilogue
     double* C;
     int64_t ldc;
@@ -67,7 +71,33 @@ struct GemmArgs {
     // verification mode: write INT32 anti-diagonal sums instead of C
     int32_t* diag_out;
 };
+// Epilogue modes: kFinal writes alpha*ldexp(acc, E+F) + beta*C into C; kRawWrite
+// stores the FP64 tile sum acc (before ldexp) into g.acc; kRawAdd adds the new
+// anti-diagonal terms onto the acc already in g.acc (chunk by chunk).
+constexpr int kFinal = 0, kRawWrite = 1, kRawAdd = 2;
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t st);
+
+// Tolerance-driven calls: operand statistics, residual check, final scaling.
+hipError_t launch_vec_stats(const OperandView& op, const uint64_t* maxbits, double* ms, hipStream_t st);
+struct CheckArgs {
+    OperandView opa, opb;      // op(A) rows and op(B) columns as vectors
+    const uint64_t* maxa;      // max |.| bits per row of op(A) / column of op(B)
+    const uint64_t* maxb;
+    const double* acc;         // raw FP64 tile sums, acc[col * Mp + slice row]
+    int64_t Mp;
+    const int32_t* EA;
+    const int32_t* FB;
+    uint64_t seed;             // probe vector seed
+    double* t;                 // n      : sigma_j / max|B_:j|
+    double* u;                 // 4k     : op(B) t in double-double (re, im)
+    double* diff;              // 2m     : y1 - y2
+    double* ref;               // 2m     : y2
+    double* norms;             // 2      : sum diff^2, sum ref^2
+};
+hipError_t launch_residual(const CheckArgs& c, hipStream_t st);
+hipError_t launch_finalize(const double* acc, int64_t Mp, const int32_t* EA, const int32_t* FB, double* C,
+                           int64_t ldc, int64_t m, int64_t n, int cplx, double ar, double ai, double br, double bi,
+                           int beta_zero, hipStream_t st);
 
 // C = beta*C for the alpha == 0 / k == 0 quick return.
 hipError_t launch_scale_c(double* C, int64_t ldc, int64_t m, int64_t n, int cplx, double br, double bi,

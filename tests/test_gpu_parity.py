@@ -374,3 +374,112 @@ def test_large_slice_diagonal_sums_bit_exact(oz, handle):
     got = out.cpu().numpy().reshape(nch, s, rb, ra).transpose(0, 1, 3, 2)
     ref = oracle.diag_sums(oracle.split("A", "N", A, s)[1], oracle.split("B", "N", B, s)[1], s, kc=kc)
     assert np.array_equal(got[:, :, :m, :n], ref)
+
+
+# ----------------------------------------------------------------- tolerance-driven slice count (a6)
+
+TOL_CASES = [
+    ("uniform", 0, 1e-6), ("uniform", 0, 1e-12), ("rowexp", 1, 1e-10), ("rowexp", 1, 1e-14),
+    ("wide", 0, 1e-6), ("wide", 0, 1e-10), ("wide", 0, 1e-14), ("spread30", 0, 1e-12),
+]
+
+
+def tol_inputs(kind, cplx, seed=0):
+    if kind == "uniform":
+        return workloads.dgemm_uniform(150, 130, 170, seed=seed)
+    if kind == "rowexp":
+        return workloads.zgemm_rowexp(96, seed=seed, m=130, k=110)
+    if kind == "wide":
+        return workloads.dgemm_wide(140, 120, 260, seed=seed)
+    return workloads.dgemm_spread(150, 130, 170, 30, seed=seed)
+
+
+def scale_weights(A, B):
+    if np.iscomplexobj(A):
+        return (np.maximum(np.abs(A.real), np.abs(A.imag)).max(1), np.maximum(np.abs(B.real), np.abs(B.imag)).max(0))
+    return np.abs(A).max(1), np.abs(B).max(0)
+
+
+def run_tol(oz, handle, A, B, tol, smax=12, sstart=0, alpha=1.0, beta=0.0, C0=None):
+    cplx = np.iscomplexobj(A)
+    m, k = A.shape
+    n = B.shape[1]
+    dA, lda = to_dev(A)
+    dB, ldb = to_dev(B)
+    C0 = np.zeros((m, n), A.dtype, order="F") if C0 is None else C0
+    dC, ldc = to_dev(C0)
+    fn = oz.oz_zgemm if cplx else oz.oz_dgemm
+    st, rep = fn(handle, "N", "N", m, n, k, alpha, dA, lda, dB, ldb, beta, dC, ldc,
+                 oz.prec(0, tol=tol, smax=smax, sstart=sstart), report=True)
+    assert st == 0 and rep.status == 0
+    return from_dev(dC, m, n, ldc), rep
+
+
+@pytest.mark.parametrize("kind,cplx,tol", TOL_CASES)
+def test_tolerance_mode_meets_tol_and_matches_oracle(oz, handle, kind, cplx, tol):
+    A, B = tol_inputs(kind, cplx)
+    got, rep = run_tol(oz, handle, A, B, tol)
+    s1, s0 = rep.slices_used, rep.slices_used - rep.fallbacks
+    print("tol %s %g: start %d, used %d, resid %.3g" % (kind, tol, s0, s1, rep.resid_est))
+    want = oracle.emu_gemm("N", "N", A, B, s0, s_to=s1, kc=oracle.kchunk(12, bool(cplx)))
+    assert np.array_equal(got, want)
+    ref = oracle.gemm_dd("N", "N", A, B)
+    wa, wb = scale_weights(A, B)
+    err = oracle.weighted_error(got, ref, wa, wb)
+    assert err <= 2 * tol, (err, tol)
+    # the a-posteriori estimate tracks the true weighted error
+    assert err / 3 <= rep.resid_est <= 3 * err + 1e-17
+    # one slice fewer would not have met the tolerance estimate (s is minimal for the check)
+    if rep.fallbacks:
+        assert rep.resid_est <= tol
+
+
+@pytest.mark.parametrize("cplx", [0, 1])
+def test_growth_from_a_low_start_is_incremental(oz, handle, cplx):
+    A, B = tol_inputs("rowexp" if cplx else "uniform", cplx, seed=3)
+    got, rep = run_tol(oz, handle, A, B, 1e-12, sstart=2, alpha=0.5 - 0.25j if cplx else 0.5, beta=0.0)
+    assert rep.fallbacks >= 3 and rep.slices_used == 2 + rep.fallbacks
+    want = oracle.emu_gemm("N", "N", A, B, 2, s_to=rep.slices_used, kc=oracle.kchunk(12, bool(cplx)),
+                           alpha=0.5 - 0.25j if cplx else 0.5)
+    assert np.array_equal(got, want)
+
+
+def test_growth_past_eight_slices_uses_streaming_kernel(oz, handle):
+    # tolerance below what 8 slices reach on wide data: the growth goes on with the streaming kernel
+    A, B = tol_inputs("wide", 0, seed=4)
+    got, rep = run_tol(oz, handle, A, B, 1e-300, smax=11, sstart=7)
+    assert rep.slices_used == 11 and rep.fallbacks == 4
+    want = oracle.emu_gemm("N", "N", A, B, 7, s_to=11, kc=oracle.kchunk(11))
+    assert np.array_equal(got, want)
+
+
+def test_tolerance_mode_beta_and_nonfinite(oz, handle):
+    rng = np.random.default_rng(8)
+    A, B = tol_inputs("uniform", 0, seed=5)
+    C0 = rng.standard_normal((A.shape[0], B.shape[1]))
+    got, rep = run_tol(oz, handle, A, B, 1e-10, alpha=-1.5, beta=0.75, C0=np.asfortranarray(C0))
+    s0 = rep.slices_used - rep.fallbacks
+    want = oracle.emu_gemm("N", "N", A, B, s0, s_to=rep.slices_used, kc=oracle.kchunk(12), alpha=-1.5, beta=0.75,
+                           C=C0)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("kind,cplx", [("uniform", 0), ("rowexp", 1), ("wide", 0), ("spread30", 0)])
+def test_select_slices_statistic(oz, handle, kind, cplx):
+    A, B = tol_inputs(kind, cplx)
+    m, k = A.shape
+    n = B.shape[1]
+    dA, lda = to_dev(A)
+    dB, ldb = to_dev(B)
+
+    def msq(X, axis):
+        mx = np.maximum(np.abs(X.real), np.abs(X.imag)).max(axis=axis, keepdims=True)
+        E = np.frexp(mx)[1]
+        xs = X * np.exp2(-E.astype(float))
+        sq = (xs.real ** 2 + xs.imag ** 2) / (2.0 if cplx else 1.0)
+        return sq.mean(axis=axis).mean()
+    spread = np.sqrt((1 / msq(A, 1) + 1 / msq(B, 0)) / 3)
+    for tol in (1e-6, 1e-10, 1e-13):
+        s = oz.oz_select_slices(handle, "N", "N", m, n, k, cplx, dA, lda, dB, ldb, tol)
+        want = next((t for t in range(1, 13) if 2.5 * (t + 1) * 2.0 ** (-7 * t) * spread <= tol), 12)
+        assert s == want, (kind, tol, s, want)

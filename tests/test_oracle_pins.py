@@ -422,3 +422,44 @@ def test_error_decay_per_slice_matches_table1():
     assert eps[7] <= 1e-12               # the FP64-equivalent target
     native = oracle.weighted_error(oracle.gemm_plain("N", "N", A, B), ref, amax, bmax)
     assert eps[8] < 10 * native          # s = 8 at the FP64 floor
+
+
+# ---------------------------------------------------------------- incremental growth
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_incremental_growth_reduces_and_is_exact(cplx):
+    rng = np.random.default_rng(31)
+    A = rand_cwide(rng, (7, 20), 10) if cplx else rand_wide(rng, (7, 20), 10)
+    B = rand_cwide(rng, (20, 6), 10) if cplx else rand_wide(rng, (20, 6), 10)
+    # no growth: the plain emulation
+    assert np.array_equal(oracle.emu_gemm("N", "N", A, B, 5, s_to=5), oracle.emu_gemm("N", "N", A, B, 5))
+    # digits p <= 2 only: growing 2 -> 3 adds exactly the missing pairs (2,2),(1,3),(3,1)
+    # (the latter two are zero), so the grown result is the exact product
+    A2 = few_digit_matrix(rng, (7, 9), 2)
+    B2 = few_digit_matrix(rng, (9, 6), 2)
+    A2[:, 0], B2[0, :] = 100 / 128, 90 / 128
+    if cplx:
+        A2 = A2 + 1j * few_digit_matrix(rng, (7, 9), 2)
+        B2 = B2 + 1j * few_digit_matrix(rng, (9, 6), 2)
+    assert np.array_equal(oracle.emu_gemm("N", "N", A2, B2, 2, s_to=3), exact_gemm_rounded("N", "N", A2, B2))
+
+
+@pytest.mark.parametrize("s0,s1", [(3, 4), (4, 7), (5, 9)])
+def test_incremental_growth_equals_fresh_run_up_to_rounding(s0, s1):
+    # the grown and the fresh s1 results add the same exact terms in different
+    # orders: they differ by at most ~ (s1 + 1) u sum|terms| <= (s1 + 1) u K 2^(E+F)
+    rng = np.random.default_rng(s0 * 10 + s1)
+    A, B = rand_wide(rng, (9, 40), 8), rand_wide(rng, (40, 8), 8)
+    E, _ = oracle.split("A", "N", A, 1)
+    F, _ = oracle.split("B", "N", B, 1)
+    grown = oracle.emu_gemm("N", "N", A, B, s0, s_to=s1)
+    fresh = oracle.emu_gemm("N", "N", A, B, s1)
+    bound = (s1 + 1) * U * 40 * np.exp2(E[:, None] + F[None, :].astype(float))
+    assert np.all(np.abs(grown - fresh) <= bound)
+    # and each growth step brings the error down like a fresh run would
+    ref = oracle.gemm_dd("N", "N", A, B)
+    amax, bmax = np.abs(A).max(1), np.abs(B).max(0)
+    e0 = oracle.weighted_error(oracle.emu_gemm("N", "N", A, B, s0), ref, amax, bmax)
+    e1 = oracle.weighted_error(grown, ref, amax, bmax)
+    assert e1 < e0 * 2.0 ** (-5 * (s1 - s0)) or e1 < 1e-15
