@@ -165,6 +165,53 @@ int oz_select_slices(oz_handle_t handle, char transa, char transb, int64_t m, in
                      int is_complex, const double* A, int64_t lda, const double* B, int64_t ldb,
                      double tol, int32_t smax, int32_t* s_out);
 
+/* ---- Batched products ----------------------------------------------------
+ *
+ * Many independent products of uneven sizes (real: is_complex = 0, complex:
+ * 1).  All array arguments are host arrays of `batch` entries (alpha and beta:
+ * one double per problem, or two -- real, imaginary -- for complex); A[b],
+ * B[b], C[b] are device pointers.  Each problem follows the oz_dgemm /
+ * oz_zgemm semantics with its own slice count: slices[b] if the array is given,
+ * else prec->slices (1..8; prec NULL: 7).  Errors are reported for the first
+ * problem that has one, at the reference-BLAS argument position.
+ *
+ * A plan computes the layouts, carves one device allocation (owned by the
+ * plan) for every problem's scales, slices and the work lists, and uploads the
+ * descriptors.  Executing it enqueues a fixed sequence on the handle's stream:
+ * one launch clearing the scale scratch, one batched exponent scan, one
+ * batched digit split, and one persistent GEMM launch per distinct slice count
+ * (a single one when every problem uses the same s) whose blocks walk a tile
+ * list ordered by work.  No host synchronisation and no allocation happen in
+ * an execution, so it can be captured: oz_batch_graph_launch captures it into
+ * a HIP graph on its first call (the handle's stream must not be the null
+ * stream) and replays the graph afterwards.  The operand and output buffers
+ * must stay valid while the plan is used. */
+typedef struct oz_batch_s* oz_batch_t;
+
+int oz_gemm_batched_plan(oz_handle_t handle, int is_complex, int32_t batch, const char* transa,
+                         const char* transb, const int64_t* m, const int64_t* n, const int64_t* k,
+                         const double* alpha, const double* const* A, const int64_t* lda,
+                         const double* const* B, const int64_t* ldb, const double* beta, double* const* C,
+                         const int64_t* ldc, const oz_prec_t* prec, const int32_t* slices, oz_batch_t* plan);
+int oz_batch_execute(oz_batch_t plan);
+int oz_batch_graph_launch(oz_batch_t plan);
+int oz_batch_destroy(oz_batch_t plan);
+/* Plan facts: GEMM launches, tiles, device bytes held, slices per problem
+ * (array of batch entries; any pointer may be NULL). */
+int oz_batch_info(oz_batch_t plan, int32_t* launches, int64_t* tiles, size_t* device_bytes, int32_t* slices);
+
+/* One-shot batched calls: plan, execute, destroy. */
+int oz_zgemm_batched(oz_handle_t handle, int32_t batch, const char* transa, const char* transb,
+                     const int64_t* m, const int64_t* n, const int64_t* k, const double* alpha,
+                     const double* const* A, const int64_t* lda, const double* const* B, const int64_t* ldb,
+                     const double* beta, double* const* C, const int64_t* ldc, const oz_prec_t* prec,
+                     const int32_t* slices);
+int oz_dgemm_batched(oz_handle_t handle, int32_t batch, const char* transa, const char* transb,
+                     const int64_t* m, const int64_t* n, const int64_t* k, const double* alpha,
+                     const double* const* A, const int64_t* lda, const double* const* B, const int64_t* ldb,
+                     const double* beta, double* const* C, const int64_t* ldc, const oz_prec_t* prec,
+                     const int32_t* slices);
+
 /* Profiling aid.  While enabled, every oz_dgemm / oz_zgemm call records HIP
  * events on the handle's stream before its split kernels, between the split
  * kernels and the GEMM kernel, and after the GEMM kernel.  oz_timing_read

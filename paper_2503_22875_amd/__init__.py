@@ -24,7 +24,8 @@ OZ_MAX_SLICES = 18
 # Every symbol include/oz.h declares (checked by the CPU test-suite).
 EXPORTS = ["oz_create", "oz_destroy", "oz_set_stream", "oz_status_string", "oz_workspace_size",
            "oz_set_workspace", "oz_dgemm", "oz_zgemm", "oz_split_layout", "oz_split", "oz_diag_sums",
-           "oz_timing_enable", "oz_timing_read", "oz_select_slices"]
+           "oz_timing_enable", "oz_timing_read", "oz_select_slices", "oz_gemm_batched_plan", "oz_batch_execute",
+           "oz_batch_graph_launch", "oz_batch_destroy", "oz_batch_info", "oz_zgemm_batched", "oz_dgemm_batched"]
 
 
 class OzError(RuntimeError):
@@ -68,6 +69,14 @@ def _load():
         "oz_timing_enable": [P, ctypes.c_int],
         "oz_timing_read": [P, PP(D), PP(D), PP(I64)],
         "oz_select_slices": [P, C, C, I64, I64, I64, ctypes.c_int, P, I64, P, I64, D, I32, PP(I32)],
+        "oz_gemm_batched_plan": [P, ctypes.c_int, I32, P, P, P, P, P, P, P, P, P, P, P, P, P, PP(oz_prec_t), P,
+                                 PP(P)],
+        "oz_batch_execute": [P],
+        "oz_batch_graph_launch": [P],
+        "oz_batch_destroy": [P],
+        "oz_batch_info": [P, PP(I32), PP(I64), PP(ctypes.c_size_t), P],
+        "oz_zgemm_batched": [P, I32, P, P, P, P, P, P, P, P, P, P, P, P, P, PP(oz_prec_t), P],
+        "oz_dgemm_batched": [P, I32, P, P, P, P, P, P, P, P, P, P, P, P, P, PP(oz_prec_t), P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -192,3 +201,88 @@ def oz_select_slices(handle, transa, transb, m, n, k, is_complex, A, lda, B, ldb
                                                       _ptr(A), lda, _ptr(B), ldb, float(tol), smax,
                                                       ctypes.byref(out)))
     return out.value
+
+
+def _batch_args(is_complex, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, slices):
+    nb = len(m)
+    I64A = ctypes.c_int64 * nb
+    PA = ctypes.c_void_p * nb
+    w = 2 if is_complex else 1
+    DA = ctypes.c_double * (w * nb)
+
+    def scal(vals):
+        out = []
+        for v in vals:
+            z = complex(v)
+            out += [z.real, z.imag] if is_complex else [z.real]
+        return DA(*out)
+    ta = ctypes.create_string_buffer(("".join(transa) if not isinstance(transa, str) else transa).encode(), nb + 1)
+    tb = ctypes.create_string_buffer(("".join(transb) if not isinstance(transb, str) else transb).encode(), nb + 1)
+    keep = dict(ta=ta, tb=tb, m=I64A(*m), n=I64A(*n), k=I64A(*k), alpha=scal(alpha), beta=scal(beta),
+                A=PA(*[_ptr(x) for x in A]), lda=I64A(*lda), B=PA(*[_ptr(x) for x in B]), ldb=I64A(*ldb),
+                C=PA(*[_ptr(x) for x in C]), ldc=I64A(*ldc),
+                slices=(ctypes.c_int32 * nb)(*slices) if slices is not None else None)
+    return nb, keep
+
+
+def oz_gemm_batched_plan(handle, is_complex, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, p=None,
+                         slices=None):
+    """Plan a batch (host lists of per-problem arguments); returns the plan handle.
+    transa / transb: strings or lists of one character per problem."""
+    nb, a = _batch_args(is_complex, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, slices)
+    plan = ctypes.c_void_p()
+    _check("oz_gemm_batched_plan", _lib.oz_gemm_batched_plan(
+        handle, int(is_complex), nb, ctypes.cast(a["ta"], ctypes.c_void_p), ctypes.cast(a["tb"], ctypes.c_void_p),
+        ctypes.cast(a["m"], ctypes.c_void_p), ctypes.cast(a["n"], ctypes.c_void_p),
+        ctypes.cast(a["k"], ctypes.c_void_p), ctypes.cast(a["alpha"], ctypes.c_void_p),
+        ctypes.cast(a["A"], ctypes.c_void_p), ctypes.cast(a["lda"], ctypes.c_void_p),
+        ctypes.cast(a["B"], ctypes.c_void_p), ctypes.cast(a["ldb"], ctypes.c_void_p),
+        ctypes.cast(a["beta"], ctypes.c_void_p), ctypes.cast(a["C"], ctypes.c_void_p),
+        ctypes.cast(a["ldc"], ctypes.c_void_p), ctypes.byref(p) if p is not None else None,
+        ctypes.cast(a["slices"], ctypes.c_void_p) if a["slices"] is not None else None, ctypes.byref(plan)))
+    return plan
+
+
+def oz_batch_execute(plan):
+    return _check("oz_batch_execute", _lib.oz_batch_execute(plan))
+
+
+def oz_batch_graph_launch(plan):
+    return _check("oz_batch_graph_launch", _lib.oz_batch_graph_launch(plan))
+
+
+def oz_batch_destroy(plan):
+    return _check("oz_batch_destroy", _lib.oz_batch_destroy(plan))
+
+
+def oz_batch_info(plan, batch):
+    """-> (gemm launches, tiles, device bytes, slices per problem)."""
+    la, ti, by = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_size_t()
+    sl = (ctypes.c_int32 * max(1, batch))()
+    _check("oz_batch_info", _lib.oz_batch_info(plan, ctypes.byref(la), ctypes.byref(ti), ctypes.byref(by),
+                                                ctypes.cast(sl, ctypes.c_void_p)))
+    return la.value, ti.value, by.value, list(sl)[:batch]
+
+
+def _gemm_batched(fn, is_complex, handle, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, p, slices,
+                  check):
+    nb, a = _batch_args(is_complex, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, slices)
+    cv = lambda x: ctypes.cast(x, ctypes.c_void_p) if x is not None else None  # noqa: E731
+    st = getattr(_lib, fn)(handle, nb, cv(a["ta"]), cv(a["tb"]), cv(a["m"]), cv(a["n"]), cv(a["k"]), cv(a["alpha"]),
+                           cv(a["A"]), cv(a["lda"]), cv(a["B"]), cv(a["ldb"]), cv(a["beta"]), cv(a["C"]),
+                           cv(a["ldc"]), ctypes.byref(p) if p is not None else None, cv(a["slices"]))
+    if check:
+        _check(fn, st)
+    return st
+
+
+def oz_zgemm_batched(handle, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, p=None, slices=None,
+                     check=True):
+    return _gemm_batched("oz_zgemm_batched", True, handle, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C,
+                         ldc, p, slices, check)
+
+
+def oz_dgemm_batched(handle, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, p=None, slices=None,
+                     check=True):
+    return _gemm_batched("oz_dgemm_batched", False, handle, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C,
+                         ldc, p, slices, check)

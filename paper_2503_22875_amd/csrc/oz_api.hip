@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/oz.h"
+#include "oz_handle.h"
 #include "oz_internal.h"
 
 struct oz_handle_s {
@@ -398,6 +399,11 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
 }
 
 }  // namespace
+
+bool oz_handle_valid(oz_handle_t h) { return valid(h); }
+int oz_handle_use_device(oz_handle_t h) { return use_device(h); }
+hipStream_t oz_handle_stream(oz_handle_t h) { return h->stream; }
+int oz_handle_device(oz_handle_t h) { return h->device; }
 
 extern "C" {
 

@@ -162,19 +162,18 @@ struct TileCfg {
 
 // TOP: only the anti-diagonal d = S + 1 (pairs p + q = S + 1), the growth
 // step S-1 -> S of a tolerance-driven call; otherwise all d = 2 .. S+1.
+// One BM x BN tile (tile row tm, tile column tn) of the product described by g,
+// staged through the caller's LDS ring lds[NST][STAGE].
 template <int S, int WMW, int WNW, int NST, bool TOP, bool DIAG, bool MULTI>
-__global__ __attribute__((amdgpu_flat_work_group_size(64 * WMW * WNW, 64 * WMW * WNW),
-                          amdgpu_waves_per_eu(2, 2))) void gemm_kernel(GemmArgs g) {
+__device__ __forceinline__ void tile_body(const GemmArgs& g, int64_t tm, int64_t tn,
+                                          v4i (*lds)[TileCfg<S, WMW, WNW, NST>::STAGE]) {
     using T = TileCfg<S, WMW, WNW, NST>;
     constexpr int DLO = TOP ? S - 1 : 0;  // lowest live diagonal index (d - 2)
     constexpr int ND = S - DLO;           // live INT32 diagonal tiles
-    __shared__ v4i lds[NST][T::STAGE];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / WNW, wn = wave % WNW;
     const int half = lane >> 5, row = lane & 31;
-    int64_t tm, tn;
-    tile_of_block(blockIdx.x, g.Mp / T::BM, g.Np / T::BN, tm, tn);
     const v4i* SA = reinterpret_cast<const v4i*>(g.SA);
     const v4i* SB = reinterpret_cast<const v4i*>(g.SB);
     const int64_t nsteps = g.kpad / kStep;
@@ -288,6 +287,34 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64 * WMW * WNW, 64 * WMW *
         fold_diags<ND, DLO, S - 1>(acc64, acc);
     }
     store_tile(g, acc64, row0, half, col);
+}
+
+template <int S, int WMW, int WNW, int NST, bool TOP, bool DIAG, bool MULTI>
+__global__ __attribute__((amdgpu_flat_work_group_size(64 * WMW * WNW, 64 * WMW * WNW),
+                          amdgpu_waves_per_eu(2, 2))) void gemm_kernel(GemmArgs g) {
+    using T = TileCfg<S, WMW, WNW, NST>;
+    __shared__ v4i lds[NST][T::STAGE];
+    int64_t tm, tn;
+    tile_of_block(blockIdx.x, g.Mp / T::BM, g.Np / T::BN, tm, tn);
+    tile_body<S, WMW, WNW, NST, TOP, DIAG, MULTI>(g, tm, tn, lds);
+}
+
+// Persistent form for a batch: block b takes tiles b, b + gridDim.x, ... of the
+// tile list; a tile names its problem (a GemmArgs in device memory) and its
+// tile row and column.  Every problem of one launch has the same s; MULTI is
+// set when any problem of the launch spans more than one INT32 chunk.
+template <int S, int WMW, int WNW, int NST, bool TOP, bool MULTI>
+__global__ __attribute__((amdgpu_flat_work_group_size(64 * WMW * WNW, 64 * WMW * WNW),
+                          amdgpu_waves_per_eu(2, 2))) void gemm_persistent_kernel(const GemmArgs* __restrict__ probs,
+                                                                                  const TileItem* __restrict__ items,
+                                                                                  int64_t nitems) {
+    using T = TileCfg<S, WMW, WNW, NST>;
+    __shared__ v4i lds[NST][T::STAGE];
+    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const TileItem ti = items[it];
+        tile_body<S, WMW, WNW, NST, TOP, false, MULTI>(probs[ti.prob], ti.tm, ti.tn, lds);
+        __syncthreads();  // the next tile refills the LDS ring
+    }
 }
 
 // Streaming form for any s (used above the all-diagonal kernel's register
@@ -412,6 +439,29 @@ hipError_t launch_cfg(const GemmArgs& g, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <int S, int WMW, int WNW, int NST>
+hipError_t launch_persistent_cfg(const GemmArgs* probs, const TileItem* items, int64_t nitems, int blocks, bool top,
+                                 bool multi, hipStream_t st) {
+    using T = TileCfg<S, WMW, WNW, NST>;
+    dim3 grid(static_cast<unsigned>(blocks)), block(64 * T::NW);
+#define OZ_PERSIST(TOPV, MULTIV)                                                                              \
+    hipLaunchKernelGGL((gemm_persistent_kernel<S, WMW, WNW, NST, TOPV, MULTIV>), grid, block, 0, st, probs, \
+                       items, nitems)
+    if (top && multi) OZ_PERSIST(true, true);
+    else if (top) OZ_PERSIST(true, false);
+    else if (multi) OZ_PERSIST(false, true);
+    else OZ_PERSIST(false, false);
+#undef OZ_PERSIST
+    return hipGetLastError();
+}
+
+template <int S>
+hipError_t launch_persistent_s(const GemmArgs* probs, const TileItem* items, int64_t nitems, int blocks, int tile,
+                               bool top, bool multi, hipStream_t st) {
+    if (tile == 1) return launch_persistent_cfg<S, 4, 2, 3>(probs, items, nitems, blocks, top, multi, st);
+    return launch_persistent_cfg<S, 2, 2, 2>(probs, items, nitems, blocks, top, multi, st);
+}
+
 // Block shape: 128 x 64 (8 waves, 3-stage ring) when the grid still fills
 // the 256 compute units twice over, else 64 x 64 (4 waves, 2 stages).
 template <int S>
@@ -448,6 +498,23 @@ hipError_t launch_gemm(const GemmArgs& g, hipStream_t st) {
         case 7: return launch_s<7>(g, st);
         case 8: return launch_s<8>(g, st);
         default: return launch_stream(g, st);
+    }
+}
+
+hipError_t launch_gemm_persistent(const GemmArgs* probs, const TileItem* items, int64_t nitems, int s, int tile,
+                                  int blocks, bool top, bool multi, hipStream_t st) {
+    if (nitems <= 0) return hipSuccess;
+    if (blocks <= 0 || (tile != 1 && tile != 2)) return hipErrorInvalidValue;
+    switch (s) {
+        case 1: return launch_persistent_s<1>(probs, items, nitems, blocks, tile, top, multi, st);
+        case 2: return launch_persistent_s<2>(probs, items, nitems, blocks, tile, top, multi, st);
+        case 3: return launch_persistent_s<3>(probs, items, nitems, blocks, tile, top, multi, st);
+        case 4: return launch_persistent_s<4>(probs, items, nitems, blocks, tile, top, multi, st);
+        case 5: return launch_persistent_s<5>(probs, items, nitems, blocks, tile, top, multi, st);
+        case 6: return launch_persistent_s<6>(probs, items, nitems, blocks, tile, top, multi, st);
+        case 7: return launch_persistent_s<7>(probs, items, nitems, blocks, tile, top, multi, st);
+        case 8: return launch_persistent_s<8>(probs, items, nitems, blocks, tile, top, multi, st);
+        default: return hipErrorInvalidValue;
     }
 }
 

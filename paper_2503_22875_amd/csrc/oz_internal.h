@@ -47,6 +47,26 @@ hipError_t launch_scan(const OperandView& op, uint64_t* maxbits, hipStream_t st)
 hipError_t launch_digits(const OperandView& op, const uint64_t* maxbits, const SliceLayout& lay,
                          int32_t* E, int8_t* slices, hipStream_t st);
 
+// Batched split: one block per item; an item names its operand and the block
+// coordinates the one-operand launch would have used.
+struct SplitOp {
+    OperandView op;
+    uint64_t* maxbits;
+    int32_t* E;
+    int8_t* slices;
+    SliceLayout lay;
+};
+struct BlockItem {
+    int32_t op;
+    int32_t bx;
+    int32_t by;
+    int32_t pad;
+};
+void scan_blocks(const OperandView& op, int64_t* bx, int64_t* by);
+void digits_blocks(const OperandView& op, const SliceLayout& lay, int64_t* bx, int64_t* by);
+hipError_t launch_scan_batched(const SplitOp* ops, const BlockItem* items, int64_t nitems, hipStream_t st);
+hipError_t launch_digits_batched(const SplitOp* ops, const BlockItem* items, int64_t nitems, hipStream_t st);
+
 // GEMM over slice buffers with fused FP64 epilogue.
 struct GemmArgs {
     const int8_t* SA;   // slices of A' (rows_pad = Mp)
@@ -76,6 +96,17 @@ struct GemmArgs {
 // anti-diagonal terms onto the acc already in g.acc (chunk by chunk).
 constexpr int kFinal = 0, kRawWrite = 1, kRawAdd = 2;
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t st);
+
+// Batched products: one persistent launch over a list of tiles of many
+// problems (all with the same s); tile 1 = 128 x 64 blocks, 2 = 64 x 64.
+struct TileItem {
+    int32_t prob;
+    int32_t tm;
+    int32_t tn;
+    int32_t pad;
+};
+hipError_t launch_gemm_persistent(const GemmArgs* probs, const TileItem* items, int64_t nitems, int s, int tile,
+                                  int blocks, bool top, bool multi, hipStream_t st);
 
 // Tolerance-driven calls: operand statistics, residual check, final scaling.
 hipError_t launch_vec_stats(const OperandView& op, const uint64_t* maxbits, double* ms, hipStream_t st);

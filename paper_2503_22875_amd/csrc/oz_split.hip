@@ -86,10 +86,11 @@ __global__ void zero_u64_kernel(uint64_t* p, int64_t n) {
 // else   : vectors are contiguous (sv == 1): lane = vector, the 4 waves
 //          split the terms, partial maxima merged through LDS.
 template <bool LCONTIG, bool CPLX>
-__global__ __launch_bounds__(256) void scan_kernel(OperandView op, uint64_t* maxbits, int64_t lspan) {
+__device__ __forceinline__ void scan_body(const OperandView& op, uint64_t* maxbits, int64_t lspan, int64_t bx,
+                                          int64_t by) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t v0 = static_cast<int64_t>(blockIdx.y) * 64;
-    const int64_t l0 = static_cast<int64_t>(blockIdx.x) * lspan;
+    const int64_t v0 = by * 64;
+    const int64_t l0 = bx * lspan;
     const int64_t l1 = (l0 + lspan < op.k) ? l0 + lspan : op.k;
     const int w = CPLX ? 2 : 1;
     if (LCONTIG) {
@@ -125,6 +126,11 @@ __global__ __launch_bounds__(256) void scan_kernel(OperandView op, uint64_t* max
     }
 }
 
+template <bool LCONTIG, bool CPLX>
+__global__ __launch_bounds__(256) void scan_kernel(OperandView op, uint64_t* maxbits, int64_t lspan) {
+    scan_body<LCONTIG, CPLX>(op, maxbits, lspan, blockIdx.x, blockIdx.y);
+}
+
 // Slice byte offset of (term t, digit p 0-based, vector r) in the layout of oz.h.
 __device__ __forceinline__ int64_t slice_off(int64_t t, int p, int64_t r, int s, int64_t rows_pad) {
     return (((t >> 4) * s + p) * rows_pad + r) * 16 + (t & 15);
@@ -141,13 +147,13 @@ __device__ __forceinline__ uint64_t pack8(const int* d) {
 // MFMA step of 32 terms.  Each thread owns 8 consecutive terms of one vector:
 // 8 real elements, or 4 complex elements (terms 2l, 2l+1).
 template <bool LCONTIG, bool CPLX, bool SIDE_A>
-__global__ __launch_bounds__(256) void digits_kernel(OperandView op, const uint64_t* maxbits, SliceLayout lay,
-                                                     int32_t* E, int8_t* slices) {
+__device__ __forceinline__ void digits_body(const OperandView& op, const uint64_t* maxbits, const SliceLayout& lay,
+                                            int32_t* E, int8_t* slices, int64_t bx, int64_t by) {
     const int tid = threadIdx.x;
     const int vi = LCONTIG ? (tid >> 2) : (tid & 63);
     const int sub = LCONTIG ? (tid & 3) : (tid >> 6);
-    const int64_t v = static_cast<int64_t>(blockIdx.y) * 64 + vi;
-    const int64_t step = blockIdx.x;
+    const int64_t v = by * 64 + vi;
+    const int64_t step = bx;
     const int64_t t0 = step * kStep + sub * 8;  // first term of this thread
     const bool live = v < op.nv;
 
@@ -209,6 +215,43 @@ __global__ __launch_bounds__(256) void digits_kernel(OperandView op, const uint6
     }
 }
 
+template <bool LCONTIG, bool CPLX, bool SIDE_A>
+__global__ __launch_bounds__(256) void digits_kernel(OperandView op, const uint64_t* maxbits, SliceLayout lay,
+                                                     int32_t* E, int8_t* slices) {
+    digits_body<LCONTIG, CPLX, SIDE_A>(op, maxbits, lay, E, slices, blockIdx.x, blockIdx.y);
+}
+
+// Batched forms: block b runs item b of a list naming the operand and the
+// block coordinates its one-operand launch would have had.
+__global__ __launch_bounds__(256) void scan_batched_kernel(const SplitOp* __restrict__ ops,
+                                                           const BlockItem* __restrict__ items, int64_t lspan) {
+    const BlockItem it = items[blockIdx.x];
+    const SplitOp& o = ops[it.op];
+    const bool lc = o.op.sl == 1;
+    if (lc && o.op.cplx) scan_body<true, true>(o.op, o.maxbits, lspan, it.bx, it.by);
+    else if (lc) scan_body<true, false>(o.op, o.maxbits, lspan, it.bx, it.by);
+    else if (o.op.cplx) scan_body<false, true>(o.op, o.maxbits, lspan, it.bx, it.by);
+    else scan_body<false, false>(o.op, o.maxbits, lspan, it.bx, it.by);
+}
+
+__global__ __launch_bounds__(256) void digits_batched_kernel(const SplitOp* __restrict__ ops,
+                                                             const BlockItem* __restrict__ items) {
+    const BlockItem it = items[blockIdx.x];
+    const SplitOp& o = ops[it.op];
+    const bool lc = o.op.sl == 1, two_row = o.op.cplx && o.op.side_a;
+#define OZ_DB(LC, CP, SA) digits_body<LC, CP, SA>(o.op, o.maxbits, o.lay, o.E, o.slices, it.bx, it.by)
+    if (lc) {
+        if (two_row) OZ_DB(true, true, true);
+        else if (o.op.cplx) OZ_DB(true, true, false);
+        else OZ_DB(true, false, false);
+    } else {
+        if (two_row) OZ_DB(false, true, true);
+        else if (o.op.cplx) OZ_DB(false, true, false);
+        else OZ_DB(false, false, false);
+    }
+#undef OZ_DB
+}
+
 }  // namespace
 
 SliceLayout slice_layout(int side_a, int cplx, int64_t nv, int64_t k, int s) {
@@ -221,6 +264,33 @@ SliceLayout slice_layout(int side_a, int cplx, int64_t nv, int64_t k, int s) {
     return L;
 }
 
+int64_t scan_lspan() { return 512; }
+
+void scan_blocks(const OperandView& op, int64_t* bx, int64_t* by) {
+    *bx = op.k > 0 ? (op.k + scan_lspan() - 1) / scan_lspan() : 0;
+    *by = op.nv > 0 ? (op.nv + 63) / 64 : 0;
+}
+
+void digits_blocks(const OperandView& op, const SliceLayout& lay, int64_t* bx, int64_t* by) {
+    const bool two_row = op.cplx && op.side_a;
+    const int64_t vec_cover = two_row ? lay.rows_pad / 2 : lay.rows_pad;
+    *bx = lay.kpad / kStep;
+    *by = (vec_cover + 63) / 64;
+}
+
+hipError_t launch_scan_batched(const SplitOp* ops, const BlockItem* items, int64_t nitems, hipStream_t st) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(scan_batched_kernel, dim3(static_cast<unsigned>(nitems)), dim3(256), 0, st, ops, items,
+                       scan_lspan());
+    return hipGetLastError();
+}
+
+hipError_t launch_digits_batched(const SplitOp* ops, const BlockItem* items, int64_t nitems, hipStream_t st) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(digits_batched_kernel, dim3(static_cast<unsigned>(nitems)), dim3(256), 0, st, ops, items);
+    return hipGetLastError();
+}
+
 hipError_t launch_zero_u64(uint64_t* p, int64_t n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(zero_u64_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, p, n);
@@ -230,7 +300,7 @@ hipError_t launch_zero_u64(uint64_t* p, int64_t n, hipStream_t st) {
 hipError_t launch_scan(const OperandView& op, uint64_t* maxbits, hipStream_t st) {
     if (op.nv <= 0 || op.k <= 0) return hipSuccess;
     const bool lcontig = op.sl == 1;
-    const int64_t lspan = 512;
+    const int64_t lspan = scan_lspan();
     dim3 grid(static_cast<unsigned>((op.k + lspan - 1) / lspan), static_cast<unsigned>((op.nv + 63) / 64));
     if (lcontig) {
         if (op.cplx) hipLaunchKernelGGL((scan_kernel<true, true>), grid, dim3(256), 0, st, op, maxbits, lspan);

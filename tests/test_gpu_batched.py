@@ -1,0 +1,174 @@
+"""Batched products (one persistent GEMM launch per slice count, hipGraph
+replay) against the CPU oracle, problem by problem, bit for bit."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from gpu_util import from_dev, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def oz():
+    import paper_2503_22875_amd as mod
+    return mod
+
+
+@pytest.fixture(scope="module")
+def stream():
+    torch.cuda.set_device(0)
+    return torch.cuda.Stream()
+
+
+@pytest.fixture(scope="module")
+def handle(oz, stream):
+    h = oz.oz_create(0)
+    oz.oz_set_stream(h, stream.cuda_stream)
+    yield h
+    oz.oz_destroy(h)
+
+
+def make_problem(rng, cplx, m, n, k, ta, tb):
+    def mat(r, c):
+        x = rng.standard_normal((r, c)) * np.exp2(rng.integers(-8, 9, size=(r, c)))
+        if cplx:
+            x = x + 1j * rng.standard_normal((r, c)) * np.exp2(rng.integers(-8, 9, size=(r, c)))
+        return np.asfortranarray(x)
+    A = mat(m, k) if ta == "N" else mat(k, m)
+    B = mat(k, n) if tb == "N" else mat(n, k)
+    C0 = mat(m, n)
+    return A, B, C0
+
+
+def batch_call(oz, handle, stream, cplx, probs, slices, use_plan=False, replays=0):
+    dev = []
+    for (ta, tb, A, B, C0, al, be) in probs:
+        dA, lda = to_dev(A, A.shape[0] + 1)
+        dB, ldb = to_dev(B)
+        dC, ldc = to_dev(C0)
+        dev.append((dA, lda, dB, ldb, dC, ldc))
+    torch.cuda.synchronize()
+    args = dict(transa=[p[0] for p in probs], transb=[p[1] for p in probs],
+                m=[(p[2].shape[0] if p[0] == "N" else p[2].shape[1]) for p in probs],
+                n=[(p[3].shape[1] if p[1] == "N" else p[3].shape[0]) for p in probs],
+                k=[(p[2].shape[1] if p[0] == "N" else p[2].shape[0]) for p in probs],
+                alpha=[p[5] for p in probs], A=[d[0] for d in dev], lda=[d[1] for d in dev],
+                B=[d[2] for d in dev], ldb=[d[3] for d in dev], beta=[p[6] for p in probs],
+                C=[d[4] for d in dev], ldc=[d[5] for d in dev])
+    if not use_plan:
+        fn = oz.oz_zgemm_batched if cplx else oz.oz_dgemm_batched
+        fn(handle, p=oz.prec(slices if isinstance(slices, int) else 7),
+           slices=None if isinstance(slices, int) else slices, **args)
+    else:
+        plan = oz.oz_gemm_batched_plan(handle, cplx, p=oz.prec(slices if isinstance(slices, int) else 7),
+                                       slices=None if isinstance(slices, int) else slices, **args)
+        oz.oz_batch_graph_launch(plan)
+        return plan, dev, args
+    stream.synchronize()
+    return [from_dev(d[4], args["m"][i], args["n"][i], d[5]) for i, d in enumerate(dev)]
+
+
+@pytest.mark.parametrize("cplx", [0, 1])
+def test_batched_bit_exact_mixed(oz, handle, stream, cplx):
+    rng = np.random.default_rng(10 + cplx)
+    probs, slices = [], []
+    shapes = [(1, 1, 1), (70, 65, 33), (130, 70, 257), (64, 192, 64), (5, 300, 17), (200, 3, 90), (96, 96, 96),
+              (33, 47, 2), (0, 5, 5), (6, 0, 4), (7, 8, 0), (40, 30, 20)]
+    for i, (m, n, k) in enumerate(shapes):
+        ta = "NTC"[i % 3] if cplx else "NT"[i % 2]
+        tb = "NCT"[(i // 3) % 3] if cplx else "TN"[i % 2]
+        A, B, C0 = make_problem(rng, cplx, m, n, k, ta, tb)
+        al = complex(1.0 + 0.1 * i, -0.2 * i) if cplx else 1.0 - 0.1 * i
+        be = (complex(0.5, 0.25) if i % 2 else 0.0) if cplx else (0.5 if i % 2 else 0.0)
+        if i == len(shapes) - 1:
+            al = 0.0  # alpha = 0: C = beta * C
+        probs.append((ta, tb, A, B, C0, al, be))
+        slices.append(3 + i % 6)
+    got = batch_call(oz, handle, stream, cplx, probs, slices)
+    for i, (ta, tb, A, B, C0, al, be) in enumerate(probs):
+        want = oracle.emu_gemm(ta, tb, A, B, slices[i], alpha=al, beta=be, C=C0) if A.size and B.size else None
+        if want is None or al == 0.0:
+            m = got[i].shape[0]
+            want = (be * C0) if be != 0.0 else np.zeros_like(C0)
+            if got[i].size and m:
+                assert np.array_equal(got[i], want), i
+            continue
+        assert np.array_equal(got[i], want), (i, ta, tb, A.shape, B.shape)
+
+
+def test_batched_graph_replays_track_new_inputs(oz, handle, stream):
+    rng = np.random.default_rng(20)
+    probs = []
+    for i, nb in enumerate([32, 96, 64, 160, 128, 32]):
+        A, B, C0 = make_problem(rng, 1, nb, nb, nb, "N", "N")
+        probs.append(("N", "N", A, B, C0, 1.0, 0.0))
+    plan, dev, args = batch_call(oz, handle, stream, 1, probs, 6, use_plan=True)
+    try:
+        launches, tiles, nbytes, sl = oz.oz_batch_info(plan, len(probs))
+        assert launches == 1 and sl == [6] * len(probs)
+        for rep in range(3):
+            stream.synchronize()
+            # eager work between replays: new operands written in place
+            for i, (_, _, A, B, _, _, _) in enumerate(probs):
+                A2 = np.asfortranarray(A * (rep + 1) + 1j * rep)
+                probs[i] = ("N", "N", A2, B, None, 1.0, 0.0)
+                dA, lda = dev[i][0], dev[i][1]
+                buf = np.zeros((lda, A2.shape[1]), np.complex128, order="F")
+                buf[:A2.shape[0]] = A2
+                with torch.cuda.stream(stream):
+                    dA.copy_(torch.from_numpy(buf.ravel(order="F")))
+            if rep:
+                oz.oz_batch_graph_launch(plan)
+            else:
+                oz.oz_batch_execute(plan)
+            stream.synchronize()
+            for i, (_, _, A2, B, _, _, _) in enumerate(probs):
+                got = from_dev(dev[i][4], A2.shape[0], B.shape[1], dev[i][5])
+                assert np.array_equal(got, oracle.emu_gemm("N", "N", A2, B, 6)), (rep, i)
+    finally:
+        oz.oz_batch_destroy(plan)
+
+
+def test_config3_batch_512_problems(oz, handle, stream):
+    """The batched workload: 512 square complex products, n_b = 32 * randint(1, 16),
+    s = 6, one persistent launch replayed from a graph; sampled problems bit-exact,
+    every problem within the s = 6 error level of the native product."""
+    problems = workloads.zgemm_batch(512, seed=0)
+    probs = [("N", "N", A, B, np.zeros((A.shape[0], B.shape[1]), np.complex128, order="F"), 1.0, 0.0)
+             for A, B in problems]
+    plan, dev, args = batch_call(oz, handle, stream, 1, probs, 6, use_plan=True)
+    try:
+        launches, tiles, nbytes, sl = oz.oz_batch_info(plan, 512)
+        print("config3: launches %d tiles %d device %.1f MB" % (launches, tiles, nbytes / 1e6))
+        assert launches == 1
+        oz.oz_batch_graph_launch(plan)
+        stream.synchronize()
+        rng = np.random.default_rng(1)
+        sample = sorted(set(rng.integers(0, 512, size=8).tolist()) | {0, 511})
+        worst = 0.0
+        for i, (A, B) in enumerate(problems):
+            got = from_dev(dev[i][4], A.shape[0], B.shape[1], dev[i][5])
+            if i in sample:
+                assert np.array_equal(got, oracle.emu_gemm("N", "N", A, B, 6)), i
+            tA = torch.from_numpy(A).cuda()
+            tB = torch.from_numpy(B).cuda()
+            nat = (tA @ tB).cpu().numpy()
+            worst = max(worst, float(np.linalg.norm(got - nat) / np.linalg.norm(nat)))
+        print("config3 worst relative error vs native: %.3g" % worst)
+        assert worst < 1e-10
+    finally:
+        oz.oz_batch_destroy(plan)
+
+
+def test_batched_argument_errors(oz, handle):
+    d = torch.zeros(16, dtype=torch.complex128, device="cuda")
+    base = dict(transa=["N", "N"], transb=["N", "N"], m=[4, 4], n=[4, 4], k=[4, 4], alpha=[1, 1], A=[d, d],
+                lda=[4, 4], B=[d, d], ldb=[4, 4], beta=[0, 0], C=[d, d], ldc=[4, 4])
+    for key, val, pos in [("transa", ["N", "X"], 1), ("m", [4, -1], 3), ("lda", [4, 3], 8), ("ldc", [2, 4], 13)]:
+        args = dict(base)
+        args[key] = val
+        assert oz.oz_zgemm_batched(handle, check=False, p=oz.prec(6), **args) == pos
+    assert oz.oz_zgemm_batched(handle, check=False, p=oz.prec(9), **base) == 14
