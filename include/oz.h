@@ -200,6 +200,13 @@ int oz_batch_destroy(oz_batch_t plan);
  * (array of batch entries; any pointer may be NULL). */
 int oz_batch_info(oz_batch_t plan, int32_t* launches, int64_t* tiles, size_t* device_bytes, int32_t* slices);
 
+/* Load the batched-plan tuning table written by the package's autotuner
+ * (JSON: an "entries" array of {"complex", "n", "s", "tile", "order", ...}).
+ * Later plans take, per slice-count group, the block shape and tile order of
+ * the entry nearest (in log n) to each problem, weighted by its work; without
+ * a table, or with prec->kernel set, a size rule decides.  NULL clears it. */
+int oz_load_tuning(oz_handle_t handle, const char* path);
+
 /* One-shot batched calls: plan, execute, destroy. */
 int oz_zgemm_batched(oz_handle_t handle, int32_t batch, const char* transa, const char* transb,
                      const int64_t* m, const int64_t* n, const int64_t* k, const double* alpha,

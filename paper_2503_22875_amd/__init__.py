@@ -9,6 +9,15 @@ CPU fallback: importing this module without the built library raises.
 import ctypes
 import os
 
+try:
+    # torch ships its own HIP runtime under the same soname (libamdhip64.so.7)
+    # as the one liboz.so links; whichever is loaded first serves the whole
+    # process.  Loading torch first makes the library share torch's runtime, so
+    # torch device pointers and streams passed in are valid for it.
+    import torch  # noqa: F401
+except ImportError:  # the library itself does not need torch
+    pass
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboz.so")
 
@@ -25,7 +34,8 @@ OZ_MAX_SLICES = 18
 EXPORTS = ["oz_create", "oz_destroy", "oz_set_stream", "oz_status_string", "oz_workspace_size",
            "oz_set_workspace", "oz_dgemm", "oz_zgemm", "oz_split_layout", "oz_split", "oz_diag_sums",
            "oz_timing_enable", "oz_timing_read", "oz_select_slices", "oz_gemm_batched_plan", "oz_batch_execute",
-           "oz_batch_graph_launch", "oz_batch_destroy", "oz_batch_info", "oz_zgemm_batched", "oz_dgemm_batched"]
+           "oz_batch_graph_launch", "oz_batch_destroy", "oz_batch_info", "oz_zgemm_batched", "oz_dgemm_batched",
+           "oz_load_tuning"]
 
 
 class OzError(RuntimeError):
@@ -77,6 +87,7 @@ def _load():
         "oz_batch_info": [P, PP(I32), PP(I64), PP(ctypes.c_size_t), P],
         "oz_zgemm_batched": [P, I32, P, P, P, P, P, P, P, P, P, P, P, P, P, PP(oz_prec_t), P],
         "oz_dgemm_batched": [P, I32, P, P, P, P, P, P, P, P, P, P, P, P, P, PP(oz_prec_t), P],
+        "oz_load_tuning": [P, ctypes.c_char_p],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -86,6 +97,9 @@ def _load():
 
 
 _lib = _load()
+
+# Tuning table written by the autotuner for this device (see autotune.py)
+TUNE_PATH = os.path.join(_HERE, "tune", "gfx950.json")
 
 
 def _ptr(x):
@@ -286,3 +300,11 @@ def oz_dgemm_batched(handle, transa, transb, m, n, k, alpha, A, lda, B, ldb, bet
                      check=True):
     return _gemm_batched("oz_dgemm_batched", False, handle, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C,
                          ldc, p, slices, check)
+
+
+def oz_load_tuning(handle, path=None):
+    """Load an autotuner table (default: the package's table for gfx950, if present)."""
+    path = TUNE_PATH if path is None else path
+    if path == "" or not os.path.exists(path):
+        return _check("oz_load_tuning", _lib.oz_load_tuning(handle, None))
+    return _check("oz_load_tuning", _lib.oz_load_tuning(handle, path.encode()))

@@ -4,7 +4,10 @@
 
 #include <climits>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <string>
 #include <new>
 #include <vector>
 
@@ -23,6 +26,8 @@ struct oz_handle_s {
     bool timing;
     std::vector<hipEvent_t> ev_pool;
     std::vector<hipEvent_t> ev_pending;
+    // batched plans: autotuner results (oz_load_tuning)
+    std::vector<oz::TuneEntry> tune;
 };
 
 namespace {
@@ -401,9 +406,11 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
 }  // namespace
 
 bool oz_handle_valid(oz_handle_t h) { return valid(h); }
+const std::vector<oz::TuneEntry>& oz_handle_tuning(oz_handle_t h) { return h->tune; }
 int oz_handle_use_device(oz_handle_t h) { return use_device(h); }
 hipStream_t oz_handle_stream(oz_handle_t h) { return h->stream; }
 int oz_handle_device(oz_handle_t h) { return h->device; }
+hipError_t oz_handle_mark(oz_handle_t h) { return mark(h); }
 
 extern "C" {
 
@@ -641,6 +648,56 @@ int oz_select_slices(oz_handle_t h, char transa, char transb, int64_t m, int64_t
                      reinterpret_cast<double*>(ws + off_sb), tol, smax, &s);
     if (st) return st;
     *s_out = s;
+    return OZ_OK;
+}
+
+// Reads the "entries" array of the autotuner's JSON file: objects with the
+// integer fields complex, n, s, tile, order (other fields are skipped).
+int oz_load_tuning(oz_handle_t h, const char* path) {
+    if (!valid(h)) return OZ_ERR_HANDLE;
+    if (!path) {
+        h->tune.clear();
+        return OZ_OK;
+    }
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return OZ_ERR_ARG;
+    std::string text;
+    char buf[4096];
+    size_t got;
+    while ((got = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got);
+    std::fclose(f);
+    const size_t arr = text.find("\"entries\"");
+    if (arr == std::string::npos) return OZ_ERR_ARG;
+    std::vector<oz::TuneEntry> out;
+    size_t pos = text.find('[', arr);
+    if (pos == std::string::npos) return OZ_ERR_ARG;
+    auto field = [](const std::string& obj, const char* key, double* v) {
+        const std::string k = std::string("\"") + key + "\"";
+        const size_t at = obj.find(k);
+        if (at == std::string::npos) return false;
+        const size_t colon = obj.find(':', at + k.size());
+        if (colon == std::string::npos) return false;
+        char* end = nullptr;
+        *v = std::strtod(obj.c_str() + colon + 1, &end);
+        return end != obj.c_str() + colon + 1;
+    };
+    for (;;) {
+        const size_t open = text.find('{', pos);
+        const size_t close_arr = text.find(']', pos);
+        if (open == std::string::npos || (close_arr != std::string::npos && close_arr < open)) break;
+        const size_t close = text.find('}', open);
+        if (close == std::string::npos) return OZ_ERR_ARG;
+        const std::string obj = text.substr(open, close - open + 1);
+        double c, n, s, t, o;
+        if (!field(obj, "complex", &c) || !field(obj, "n", &n) || !field(obj, "s", &s) || !field(obj, "tile", &t) ||
+            !field(obj, "order", &o))
+            return OZ_ERR_ARG;
+        if ((t != 1 && t != 2) || (o != 0 && o != 1) || s < 1 || s > oz::kMaxLiveSlices || n < 1) return OZ_ERR_ARG;
+        out.push_back({static_cast<int>(c), static_cast<int64_t>(n), static_cast<int>(s), static_cast<int>(t),
+                       static_cast<int>(o)});
+        pos = close + 1;
+    }
+    h->tune = out;
     return OZ_OK;
 }
 

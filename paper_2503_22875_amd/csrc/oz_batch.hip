@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -262,35 +264,92 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
         if (std::find(svals.begin(), svals.end(), q.s) == svals.end()) svals.push_back(q.s);
     std::sort(svals.begin(), svals.end());
     std::vector<std::vector<oz::TileItem>> group_items;
+    const std::vector<oz::TuneEntry>& tune = oz_handle_tuning(h);
+    // tuned choice for one problem: the entry with the same complexity and s
+    // (else the nearest s) nearest in log n; -1 when there is no table
+    auto tuned = [&](const oz::GemmArgs& g, int sv, int* tile, int* order) {
+        int best = -1;
+        double bd = 1e300;
+        const double size = static_cast<double>(g.m > g.n ? g.m : g.n);
+        for (size_t i = 0; i < tune.size(); ++i) {
+            const oz::TuneEntry& t = tune[i];
+            if (t.cplx != cplx) continue;
+            const double d = std::fabs(std::log2(size / static_cast<double>(t.n))) + 4.0 * std::abs(t.s - sv);
+            if (d < bd) {
+                bd = d;
+                best = static_cast<int>(i);
+            }
+        }
+        if (best < 0) return false;
+        *tile = tune[best].tile;
+        *order = tune[best].order;
+        return true;
+    };
     for (int sv : svals) {
-        // block shape for the group: as chosen, else 128 x 64 when the group has
-        // at least two such tiles per compute unit
         int64_t big = 0;
         bool multi = false;
         std::vector<size_t> members;
+        double vote_tile[3] = {0, 0, 0}, vote_order[2] = {0, 0};
+        bool have_tune = false;
         for (size_t i = 0; i < probs.size(); ++i)
             if (probs[i].s == sv) {
                 members.push_back(i);
                 big += (args[i].Mp / 128) * (args[i].Np / 64);
                 multi = multi || args[i].chunk_steps < args[i].kpad / oz::kStep;
+                int t, od;
+                if (tuned(args[i], sv, &t, &od)) {
+                    const double work = static_cast<double>(args[i].Mp) * args[i].Np * args[i].kpad;
+                    vote_tile[t] += work;
+                    vote_order[od] += work;
+                    have_tune = true;
+                }
             }
-        const int tile = kernel ? kernel : (big >= 2 * cus ? 1 : 2);
+        // block shape: as requested, else the tuned vote, else 128 x 64 when the
+        // group has at least two such tiles per compute unit
+        int tile = kernel;
+        if (!tile) tile = have_tune ? (vote_tile[1] > vote_tile[2] ? 1 : 2) : (big >= 2 * cus ? 1 : 2);
+        const int order = have_tune && vote_order[1] > vote_order[0] ? 1 : 0;
         const int64_t bm = tile == 1 ? 128 : 64, bn = 64;
-        // problems with the most work per tile first, tiles row by row
+        // problems with the most work per tile first
         std::stable_sort(members.begin(), members.end(),
                          [&](size_t a, size_t b) { return args[a].kpad > args[b].kpad; });
-        std::vector<oz::TileItem> items;
-        for (size_t i : members)
+        auto tiles_of = [&](size_t i, std::vector<oz::TileItem>& dst) {
             for (int64_t tm = 0; tm < args[i].Mp / bm; ++tm)
                 for (int64_t tn = 0; tn < args[i].Np / bn; ++tn)
-                    items.push_back({static_cast<int32_t>(i), static_cast<int32_t>(tm), static_cast<int32_t>(tn), 0});
+                    dst.push_back({static_cast<int32_t>(i), static_cast<int32_t>(tm), static_cast<int32_t>(tn), 0});
+        };
+        std::vector<oz::TileItem> items;
+        const int64_t per_cu = tile == 1 ? 1 : 2;  // blocks resident per compute unit
+        if (order == 0) {
+            for (size_t i : members) tiles_of(i, items);
+        } else {
+            // deal whole problems to 8 queues (least work first), then interleave
+            // the queues so that item i lands on a block of XCD i % 8 (blocks of
+            // a persistent grid with a multiple of 8 blocks go round-robin to
+            // the XCDs); exhausted queues leave null items
+            constexpr int kX = 8;
+            std::vector<oz::TileItem> q[kX];
+            double load[kX] = {0};
+            for (size_t i : members) {
+                int x = 0;
+                for (int y = 1; y < kX; ++y)
+                    if (load[y] < load[x]) x = y;
+                tiles_of(i, q[x]);
+                load[x] += static_cast<double>(args[i].Mp / bm) * (args[i].Np / bn) * args[i].kpad;
+            }
+            size_t longest = 0;
+            for (int x = 0; x < kX; ++x) longest = std::max(longest, q[x].size());
+            for (size_t j = 0; j < longest; ++j)
+                for (int x = 0; x < kX; ++x) items.push_back(j < q[x].size() ? q[x][j] : oz::TileItem{-1, 0, 0, 0});
+        }
         Group gr;
         gr.s = sv;
         gr.tile = tile;
         gr.multi = multi;
         gr.nitems = static_cast<int64_t>(items.size());
-        const int64_t per_cu = tile == 1 ? 1 : 2;  // blocks resident per compute unit
-        gr.blocks = static_cast<int>(std::min<int64_t>(gr.nitems, per_cu * cus));
+        int64_t blocks = std::min<int64_t>(gr.nitems, per_cu * cus);
+        if (order == 1) blocks -= blocks % 8;  // keep the XCD stride
+        gr.blocks = static_cast<int>(blocks > 0 ? blocks : 1);
         gr.off_items = 0;
         P->groups.push_back(gr);
         group_items.push_back(std::move(items));
@@ -349,7 +408,7 @@ int oz_batch_execute(oz_batch_t P) {
     if (oz_handle_use_device(h)) return OZ_ERR_HIP;
     hipStream_t st = oz_handle_stream(h);
     char* dev = static_cast<char*>(P->dev);
-    hipError_t e = hipSuccess;
+    hipError_t e = oz_handle_mark(h);  // timing: before the split launches
     for (const ScaleOnly& so : P->scale_only)
         if (e == hipSuccess) e = oz::launch_scale_c(so.C, so.ldc, so.m, so.n, so.cplx, so.br, so.bi, so.beta_zero, st);
     if (e == hipSuccess && P->n_maxbits)
@@ -361,10 +420,12 @@ int oz_batch_execute(oz_batch_t P) {
         e = oz::launch_digits_batched(ops, reinterpret_cast<const oz::BlockItem*>(dev + P->off_digits), P->n_digits,
                                       st);
     const oz::GemmArgs* args = reinterpret_cast<const oz::GemmArgs*>(dev + P->off_args);
+    if (e == hipSuccess) e = oz_handle_mark(h);  // between split and GEMM
     for (const Group& gr : P->groups)
         if (e == hipSuccess)
             e = oz::launch_gemm_persistent(args, reinterpret_cast<const oz::TileItem*>(dev + gr.off_items), gr.nitems,
                                            gr.s, gr.tile, gr.blocks, false, gr.multi, st);
+    if (e == hipSuccess) e = oz_handle_mark(h);  // after the GEMM launches
     return e == hipSuccess ? OZ_OK : OZ_ERR_HIP;
 }
 

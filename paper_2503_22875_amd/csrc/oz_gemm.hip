@@ -301,7 +301,8 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64 * WMW * WNW, 64 * WMW *
 
 // Persistent form for a batch: block b takes tiles b, b + gridDim.x, ... of the
 // tile list; a tile names its problem (a GemmArgs in device memory) and its
-// tile row and column.  Every problem of one launch has the same s; MULTI is
+// tile row and column (problem -1: a padding item, skipped).  Every problem of
+// one launch has the same s; MULTI is
 // set when any problem of the launch spans more than one INT32 chunk.
 template <int S, int WMW, int WNW, int NST, bool TOP, bool MULTI>
 __global__ __attribute__((amdgpu_flat_work_group_size(64 * WMW * WNW, 64 * WMW * WNW),
@@ -312,6 +313,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64 * WMW * WNW, 64 * WMW *
     __shared__ v4i lds[NST][T::STAGE];
     for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
         const TileItem ti = items[it];
+        if (ti.prob < 0) continue;  // padding item (uniform over the block)
         tile_body<S, WMW, WNW, NST, TOP, false, MULTI>(probs[ti.prob], ti.tm, ti.tn, lds);
         __syncthreads();  // the next tile refills the LDS ring
     }
