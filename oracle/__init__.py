@@ -19,6 +19,10 @@ float64 or complex128; ``trans`` is 'N', 'T' or 'C'):
                   p + q <= s + 1, FP64 accumulation, alpha/beta.
 * ``kchunk``      the INT32 chunk length (products per chunk).
 
+Submodules ``select`` (features, error table and labels of the learned
+slice-count selector) and ``mlp`` (the selector network: forward, pinball
+loss, backward, Adam) are plain numpy.
+
 Parity of each function is pinned in tests/test_oracle_*.py; none is unpinned.
 """
 import ctypes

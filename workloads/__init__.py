@@ -94,3 +94,136 @@ def dgemm_spread(m, n, k, sigma, seed=0, per_row_frac=0.5):
         return np.asfortranarray(np.ldexp(x, e))
 
     return one(m, k, 0), one(k, n, 1)
+
+
+# ---------------------------------------------------------------------------
+# Counter-based instances for the slice-count selector.  The GPU library has
+# its own implementation of the same generator (splitmix64, Steele, Lea and
+# Flood, OOPSLA 2014): output number c (0-based) of the stream seeded with key
+# is mix64(key + (c + 1) * GAMMA).  Both sides draw bit-identical operands
+# from the parameter table below, so neither ships the other its inputs.
+# ---------------------------------------------------------------------------
+GAMMA = 0x9E3779B97F4A7C15
+_M1 = 0xBF58476D1CE4E5B9
+_M2 = 0x94D049BB133111EB
+_U64 = (1 << 64) - 1
+
+# fields of one instance (the C struct oz_gen_t has the same order)
+GEN_FIELDS = ("m", "n", "k", "sig_el", "sig_vec", "bits", "family", "zero_q", "key")
+
+
+def mix64(z):
+    """splitmix64 output function on a numpy uint64 array (wrapping)."""
+    z = np.asarray(z, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(_M1)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(_M2)
+    return z ^ (z >> np.uint64(31))
+
+
+def draw(key, ctr):
+    """Output number ctr of the splitmix64 stream seeded with key."""
+    ctr = np.asarray(ctr, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        return mix64(np.uint64(key) + (ctr + np.uint64(1)) * np.uint64(GAMMA))
+
+
+def _draw_scalar(key, ctr):
+    z = (key + (ctr + 1) * GAMMA) & _U64
+    z = ((z ^ (z >> 30)) * _M1) & _U64
+    z = ((z ^ (z >> 27)) * _M2) & _U64
+    return z ^ (z >> 31)
+
+
+def gen_keys(key):
+    """Sub-stream keys: A entries, B entries, A row exponents, B column exponents."""
+    return tuple(_draw_scalar(int(key), c) for c in range(4))
+
+
+def _gen_side(p, rows, cols, ekey, vkey, vec_axis):
+    """One operand (rows x cols, column-major).  Five draws per entry, at
+    counters 5*idx .. 5*idx + 4 with idx = i + j*rows:
+      family 0: sign and 53-bit significand from draw 0, value in [1/2, 1);
+      family 1: Irwin-Hall bell, ((u0 + u1) + u2) + u3 - 2 with u = (d >> 11) 2^-53;
+      draw 4:   zero if (d4 >> 40) < zero_q, element exponent (d4 & 0xffffffff) mod (sig_el + 1) - sig_el // 2.
+    Then the low 53 - bits significand bits are cleared, and the value is
+    scaled by 2^(element exponent + vector exponent), the vector exponent of row
+    i (A) / column j (B) being draw(vkey, i or j) mod (sig_vec + 1) - sig_vec // 2."""
+    idx = np.arange(rows * cols, dtype=np.uint64)
+    base = idx * np.uint64(5)
+    d = [draw(ekey, base + np.uint64(c)) for c in range(5)]
+    if p["family"] == 0:
+        mant = (d[0] >> np.uint64(11)) | np.uint64(1 << 52)
+        x = np.ldexp(mant.astype(np.float64), -53)
+        x = np.where((d[0] & np.uint64(1)) == 1, -x, x)
+    else:
+        u = [(dd >> np.uint64(11)).astype(np.float64) * 2.0 ** -53 for dd in d[:4]]
+        x = (((u[0] + u[1]) + u[2]) + u[3]) - 2.0
+    bits = int(p["bits"])
+    if bits < 53:
+        xb = x.view(np.uint64) & np.uint64(_U64 ^ ((1 << (53 - bits)) - 1))
+        x = xb.view(np.float64)
+    zero = (d[4] >> np.uint64(40)) < np.uint64(int(p["zero_q"]))
+    sig_el, sig_vec = int(p["sig_el"]), int(p["sig_vec"])
+    e_el = ((d[4] & np.uint64(0xFFFFFFFF)) % np.uint64(sig_el + 1)).astype(np.int64) - sig_el // 2
+    nvec = rows if vec_axis == 0 else cols
+    e_vec = (draw(vkey, np.arange(nvec, dtype=np.uint64)) % np.uint64(sig_vec + 1)).astype(np.int64) - sig_vec // 2
+    i = (idx % np.uint64(rows)).astype(np.int64)
+    j = (idx // np.uint64(rows)).astype(np.int64)
+    e = e_el + (e_vec[i] if vec_axis == 0 else e_vec[j])
+    x = np.where(zero, 0.0, np.ldexp(x, e))
+    return np.asfortranarray(x.reshape(cols, rows).T)
+
+
+def gen_operands(p):
+    """A (m x k) and B (k x n) of one selector instance, column-major float64."""
+    ka, kb, kva, kvb = gen_keys(p["key"])
+    A = _gen_side(p, int(p["m"]), int(p["k"]), ka, kva, 0)
+    B = _gen_side(p, int(p["k"]), int(p["n"]), kb, kvb, 1)
+    return A, B
+
+
+def selector_instances(count, seed=0, lo=64, hi=2048, tols_per=4, tol_lo=1e-15, tol_hi=1e-4):
+    """Parameter table of the selector's training / test instances.
+
+    m, n, k log-uniform in [lo, hi] rounded to a multiple of 16; spread
+    sigma ~ randint(0, 40) dealt per entry, per vector, or half and half (one
+    third each); 70% full 53-bit significands, else randint(4, 52) bits; 70%
+    without zeros, else a zero fraction U(0, 0.8); family 0 or 1 with equal
+    odds; tols_per tolerances log-uniform in [tol_lo, tol_hi] per instance.
+    Returns (list of dicts, tols array [count, tols_per])."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        dims = [int(max(16, round(np.exp(rng.uniform(np.log(lo), np.log(hi))) / 16) * 16)) for _ in range(3)]
+        sigma = int(rng.integers(0, 41))
+        mode = int(rng.integers(0, 3))
+        sig_el = sigma if mode == 0 else (0 if mode == 1 else sigma // 2)
+        sig_vec = sigma - sig_el
+        bits = 53 if rng.random() < 0.7 else int(rng.integers(4, 53))
+        zero_q = 0 if rng.random() < 0.7 else int(rng.uniform(0.0, 0.8) * (1 << 24))
+        out.append(dict(m=dims[0], n=dims[1], k=dims[2], sig_el=sig_el, sig_vec=sig_vec, bits=bits,
+                        family=int(rng.integers(0, 2)), zero_q=zero_q,
+                        key=int(rng.integers(0, 1 << 63, dtype=np.int64))))
+    tols = np.exp(rng.uniform(np.log(tol_lo), np.log(tol_hi), size=(count, tols_per)))
+    return out, tols
+
+
+def zgemm_batch_spread(count=512, seed=0, sig_max=40):
+    """The batched workload with a per-problem exponent spread: n_b =
+    32 * randint(1, 16), Re, Im ~ N(0,1) scaled by 2^e, e per entry
+    ~ randint(-sigma//2, sigma - sigma//2), sigma ~ randint(0, sig_max)."""
+    sizes = zgemm_batch_sizes(count, seed)
+    rng = np.random.default_rng(seed + 2)
+    out = []
+    for nb in sizes:
+        sigma = int(rng.integers(0, sig_max + 1))
+        lo, hi = -(sigma // 2), sigma - sigma // 2
+
+        def one():
+            re = np.ldexp(rng.standard_normal((nb, nb)), rng.integers(lo, hi + 1, size=(nb, nb)))
+            im = np.ldexp(rng.standard_normal((nb, nb)), rng.integers(lo, hi + 1, size=(nb, nb)))
+            return np.asfortranarray(re + 1j * im)
+
+        out.append((one(), one()))
+    return out
