@@ -83,8 +83,12 @@ typedef struct oz_handle_s* oz_handle_t;
  *           3-stage LDS ring, 2 = 64 x 64 block with 2 stages (both for
  *           s <= 8), 3 = per-diagonal streaming (any s; the only choice for
  *           s > 8).  Every shape gives the same bits.
- *  sstart : tolerance-driven calls only: the starting slice count (e.g. from
- *           a learned predictor); 0 uses the rule of oz_select_slices.
+ *  sstart : tolerance-driven calls only: the starting slice count; 0 lets
+ *           `selector` choose it.
+ *  selector: tolerance-driven calls with sstart == 0: 0 = the rule of
+ *           oz_select_slices, 1 = the learned selector attached to the handle
+ *           (oz_set_selector; OZ_ERR_ARG without one), see oz_predict_slices.
+ *  reserved: must be 0.
  */
 typedef struct {
     int32_t slices;
@@ -93,6 +97,8 @@ typedef struct {
     int32_t zmode;
     int32_t kernel;
     int32_t sstart;
+    int32_t selector;
+    int32_t reserved;
     double tol;
 } oz_prec_t;
 
@@ -165,6 +171,144 @@ int oz_select_slices(oz_handle_t handle, char transa, char transb, int64_t m, in
                      int is_complex, const double* A, int64_t lda, const double* B, int64_t ldb,
                      double tol, int32_t smax, int32_t* s_out);
 
+/* ---- Learned slice-count selection ------------------------------------------
+ *
+ * The paper proposes adjusting the split number to the operator (Sec. 4).
+ * The learned selector predicts the starting s of a tolerance-driven call
+ * from 16 statistics of the operands and the tolerance, with a small network
+ * (16 -> 64 -> 64 -> 1, ReLU, FP32) trained on the GPU against labels that
+ * the emulation itself produces.  The residual check and the incremental
+ * growth of the tolerance-driven call still guarantee the tolerance; a good
+ * start only saves work (a start below the final s costs check rounds, a start
+ * above it costs slice pairs).
+ *
+ * Features of a product op(A) op(B) at tolerance tol (FP32, in this order).
+ * For each operand -- rows of op(A), then columns of op(B); a complex operand
+ * contributes real and imaginary parts as separate entries under the shared
+ * scale -- with E_v the scale exponent of vector v, over its non-zero entries
+ * x the gap g = E_v - exponent(x) (frexp convention) and the width
+ * w = g + bit length of the odd significand of x (the entry is exact with
+ * ceil(w/7) digits), both capped at 127:
+ *   zero fraction, mean g, std g, 90th percentile g, mean w, 90th percentile w
+ * (percentile: smallest v with at least 90% of the entries at or below v);
+ * then log2 of the term count (k, or 2k for complex), log2(m n) / 2,
+ * -log10(tol), and log2 sqrt((1/M_A + 1/M_B)/3) with M as in
+ * oz_select_slices (0 when an operand is zero). */
+#define OZ_NUM_FEATURES 16
+#define OZ_MLP_NIN 16
+#define OZ_MLP_NHIDDEN 64
+#define OZ_MLP_NPARAM 5313
+
+typedef struct oz_mlp_s* oz_mlp_t;
+
+/* One synthetic instance of the selector's training distribution, drawn by a
+ * counter-based generator (splitmix64: draw c of the stream with key K is
+ * mix64(K + (c+1) * 0x9E3779B97F4A7C15)).  Sub-stream keys are draws 0..3 of
+ * `key`: entries of A, entries of B, row exponents of A, column exponents of
+ * B.  Entry (i, j) of a rows x cols operand uses draws 5 idx .. 5 idx + 4 of
+ * its entry stream, idx = i + j*rows:
+ *   family 0: sign = bit 0 and significand = (draw 0 >> 11) | 2^52 of draw 0,
+ *             value (-1)^sign * significand * 2^-53, in [1/2, 1);
+ *   family 1: u_c = (draw c >> 11) * 2^-53, value ((u0 + u1) + u2) + u3 - 2;
+ *   the significand then keeps its top `bits` bits; draw 4 makes the entry
+ *   zero when (draw 4 >> 40) < zero_q, else scales it by 2^(e_el + e_vec),
+ *   e_el = ((draw 4) mod 2^32) mod (sig_el + 1) - sig_el/2 and e_vec = (draw r
+ *   of the row / column exponent stream) mod (sig_vec + 1) - sig_vec/2, r the
+ *   row of A or column of B.  Every step is exact or one IEEE addition, so any
+ *   implementation reproduces the same operands. */
+typedef struct {
+    int64_t m, n, k;
+    int32_t sig_el;   /* exponent spread per entry, >= 0       */
+    int32_t sig_vec;  /* exponent spread per row / column, >= 0 */
+    int32_t bits;     /* significand bits kept, 1..53          */
+    int32_t family;   /* 0 or 1                                */
+    int64_t zero_q;   /* zero threshold, 0..2^24               */
+    uint64_t key;
+} oz_gen_t;
+
+/* A (m x k, lda >= m) and B (k x n, ldb >= k), column-major device arrays,
+ * of instance p.  Asynchronous on the handle's stream. */
+int oz_gen_operands(oz_handle_t handle, const oz_gen_t* p, double* A, int64_t lda, double* B, int64_t ldb);
+
+/* Feature rows of op(A) op(B) for ntol tolerances (host array tols): feat is
+ * a device array of ntol x OZ_NUM_FEATURES floats (row-major); s_rule (host,
+ * ntol entries, may be NULL) receives oz_select_slices' choice per tolerance
+ * with smax (0: 12).  Operand arguments as oz_dgemm / oz_zgemm.
+ * Synchronises the handle's stream. */
+int oz_features(oz_handle_t handle, char transa, char transb, int64_t m, int64_t n, int64_t k, int is_complex,
+                const double* A, int64_t lda, const double* B, int64_t ldb, int32_t ntol, const double* tols,
+                int32_t smax, float* feat, int32_t* s_rule);
+
+/* Training / test data of the selector, generated and labelled on the GPU.
+ * For each instance b (params[b], real operands, k <= 11072 so that the
+ * reference emulation needs one INT32 chunk) the library draws the operands,
+ * runs the s_ref emulation (2 <= s_ref <= 18) keeping its INT32 anti-diagonal
+ * sums, and from them forms every C_s, s < s_ref, exactly as the fixed-s
+ * emulation would (one chunk: sum from d = s+1 down to 2 of S_d 2^-7d), and
+ *   eps_s = || W o (C_s - C_ref) ||_F / || W o C_ref ||_F,
+ *   W_ij = 1 / (max|A_i:| max|B_:j|).
+ * Row r = b*ntol + t of the output is the feature row of instance b at
+ * tolerance tols[r] (host array), with label y[r] = the smallest s in
+ * [2, s_ref] with eps_s <= tol.  X (device, rows x OZ_NUM_FEATURES floats)
+ * and y (device, rows floats) receive the data; s_rule (host, rows entries)
+ * the rule's choice with smax_rule; eps (host, count x s_ref doubles) the
+ * table eps_1 .. eps_s_ref (eps_s_ref = 0).  s_rule and eps may be NULL.
+ * Synchronises the handle's stream. */
+int oz_selector_dataset(oz_handle_t handle, int32_t count, const oz_gen_t* params, int32_t ntol,
+                        const double* tols, int32_t s_ref, int32_t smax_rule, float* X, float* y,
+                        int32_t* s_rule, double* eps);
+
+/* The network.  Parameters (OZ_MLP_NPARAM floats, host order): W1[64][16]
+ * (row = hidden unit), b1[64], W2[64][64], b2[64], W3[64], b3; inputs are
+ * normalised as (x - mu) / sd per feature before the first layer.
+ *   y = W3 . relu(W2 relu(W1 xn + b1) + b2) + b3.
+ * Loss of a batch of B rows with targets t: (1/B) sum rho(t - y) with
+ * rho(r) = tau r for r > 0, (tau - 1) r otherwise (pinball loss; tau near 1
+ * penalises predictions below the target, which cost extra check rounds, more
+ * than those above).  Optimiser: Adam, beta1 0.9, beta2 0.999, eps 1e-8. */
+/* New network: He-uniform weights drawn from the splitmix64 stream of seed,
+ * zero biases, mu = 0, sd = 1.  Bound to the handle's device and stream. */
+int oz_mlp_create(oz_handle_t handle, uint64_t seed, oz_mlp_t* mlp);
+int oz_mlp_destroy(oz_mlp_t mlp);
+/* Host copies in and out (any pointer may be NULL).  Setting the parameters
+ * restarts Adam.  Both synchronise the handle's stream. */
+int oz_mlp_set_params(oz_mlp_t mlp, const float* params, const float* mu, const float* sd);
+int oz_mlp_get_params(oz_mlp_t mlp, float* params, float* mu, float* sd);
+/* mu, sd = per-feature mean and standard deviation of the rows of X (device,
+ * rows x 16; a deviation below 1e-6 is taken as 1). */
+int oz_mlp_fit_norm(oz_mlp_t mlp, int64_t rows, const float* X);
+/* y (device, rows) = network(X (device, rows x 16)).  Asynchronous. */
+int oz_mlp_forward(oz_mlp_t mlp, int64_t rows, const float* X, float* y);
+/* Gradient of the batch loss with respect to the parameters (host,
+ * OZ_MLP_NPARAM floats, may be NULL) and the loss (host, may be NULL), for
+ * device rows X and targets t.  Synchronous. */
+int oz_mlp_grad(oz_mlp_t mlp, int64_t rows, const float* X, const float* t, float tau, float* grad, float* loss);
+/* One Adam step on one batch; loss (host, may be NULL) is the batch loss
+ * before the step (then the call synchronises). */
+int oz_mlp_train_step(oz_mlp_t mlp, int64_t rows, const float* X, const float* t, float tau, float lr,
+                      float* loss);
+/* epochs passes over the rows in batches of `batch`, each pass in an order
+ * shuffled by the splitmix64 stream of seed; an untrained network first sets
+ * b3 to the mean target.  epoch_loss (host, epochs entries, may be NULL)
+ * receives the mean loss of each pass.  Synchronous. */
+int oz_mlp_train(oz_mlp_t mlp, int64_t rows, const float* X, const float* t, int32_t epochs, int32_t batch,
+                 float tau, float lr, uint64_t seed, float* epoch_loss);
+/* Binary file: 8-byte magic "OZMLP001", int32 16, 64, 5313, then mu[16],
+ * sd[16] and the parameters as little-endian floats. */
+int oz_mlp_save(oz_mlp_t mlp, const char* path);
+int oz_mlp_load(oz_handle_t handle, const char* path, oz_mlp_t* mlp);
+
+/* Attach a network as the handle's learned selector (NULL detaches).  The
+ * network is not copied and must outlive its use. */
+int oz_set_selector(oz_handle_t handle, oz_mlp_t mlp);
+
+/* The learned starting slice count: s = clamp(ceil(y), 2, smax) (smax 0: 12)
+ * for the network output y on the features of the product at tol.  Operand
+ * arguments as oz_select_slices.  Synchronises the handle's stream. */
+int oz_predict_slices(oz_handle_t handle, char transa, char transb, int64_t m, int64_t n, int64_t k,
+                      int is_complex, const double* A, int64_t lda, const double* B, int64_t ldb, double tol,
+                      int32_t smax, int32_t* s_out);
+
 /* ---- Batched products ----------------------------------------------------
  *
  * Many independent products of uneven sizes (real: is_complex = 0, complex:
@@ -194,10 +338,31 @@ int oz_gemm_batched_plan(oz_handle_t handle, int is_complex, int32_t batch, cons
                          const double* const* B, const int64_t* ldb, const double* beta, double* const* C,
                          const int64_t* ldc, const oz_prec_t* prec, const int32_t* slices, oz_batch_t* plan);
 int oz_batch_execute(oz_batch_t plan);
+/* Replay the captured execution (fixed slice counts only; a tolerance-driven
+ * plan returns OZ_ERR_ARG). */
 int oz_batch_graph_launch(oz_batch_t plan);
 int oz_batch_destroy(oz_batch_t plan);
+/* Tolerance-driven batches: prec->slices == 0 with prec->tol > 0 (slices
+ * array NULL) plans every problem as a tolerance-driven oz_dgemm / oz_zgemm
+ * call with the same tol, smax (0: 12, up to OZ_MAX_SLICES), sstart and
+ * selector.  An execution then runs: the batched split with smax digit planes;
+ * the starting s of every problem (sstart, or one batched statistics pass and
+ * the rule or the handle's learned selector); raw sums at those s (problems
+ * grouped by s, one persistent launch per group with s <= 8, the streaming
+ * kernel per problem above); then rounds of a batched residual check over the
+ * problems still open and one more slice (digit already split, next
+ * anti-diagonal added last) for those whose estimate exceeds tol, until all
+ * pass or reach smax; finally one batched scaling pass into C.  Each problem's
+ * result is bit-identical to the single tolerance-driven call that starts at
+ * the same s.  The execution synchronises the stream at every round. */
+/* Per-problem reports of the last execution (batch entries): slices used,
+ * slices added by the check, INT32 chunks, the final error estimate (tol
+ * plans), status OZ_ERR_NONFINITE for non-finite input.  Synchronises. */
+int oz_batch_report(oz_batch_t plan, oz_report_t* reps);
 /* Plan facts: GEMM launches, tiles, device bytes held, slices per problem
- * (array of batch entries; any pointer may be NULL). */
+ * (array of batch entries; any pointer may be NULL).  For a tolerance-driven
+ * plan the launch and tile counts are those of a fixed plan (0) and the slices
+ * are the final ones of the last execution. */
 int oz_batch_info(oz_batch_t plan, int32_t* launches, int64_t* tiles, size_t* device_bytes, int32_t* slices);
 
 /* Load the batched-plan tuning table written by the package's autotuner

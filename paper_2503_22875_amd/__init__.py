@@ -35,7 +35,13 @@ EXPORTS = ["oz_create", "oz_destroy", "oz_set_stream", "oz_status_string", "oz_w
            "oz_set_workspace", "oz_dgemm", "oz_zgemm", "oz_split_layout", "oz_split", "oz_diag_sums",
            "oz_timing_enable", "oz_timing_read", "oz_select_slices", "oz_gemm_batched_plan", "oz_batch_execute",
            "oz_batch_graph_launch", "oz_batch_destroy", "oz_batch_info", "oz_zgemm_batched", "oz_dgemm_batched",
-           "oz_load_tuning"]
+           "oz_load_tuning", "oz_gen_operands", "oz_features", "oz_selector_dataset", "oz_mlp_create",
+           "oz_mlp_destroy", "oz_mlp_set_params", "oz_mlp_get_params", "oz_mlp_fit_norm", "oz_mlp_forward",
+           "oz_mlp_grad", "oz_mlp_train_step", "oz_mlp_train", "oz_mlp_save", "oz_mlp_load", "oz_set_selector",
+           "oz_predict_slices", "oz_batch_report"]
+
+OZ_NUM_FEATURES = 16
+OZ_MLP_NPARAM = 5313
 
 
 class OzError(RuntimeError):
@@ -47,13 +53,24 @@ class OzError(RuntimeError):
 class oz_prec_t(ctypes.Structure):
     _fields_ = [("slices", ctypes.c_int32), ("smax", ctypes.c_int32), ("kchunk", ctypes.c_int32),
                 ("zmode", ctypes.c_int32), ("kernel", ctypes.c_int32), ("sstart", ctypes.c_int32),
-                ("tol", ctypes.c_double)]
+                ("selector", ctypes.c_int32), ("reserved", ctypes.c_int32), ("tol", ctypes.c_double)]
 
 
 class oz_report_t(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("slices_used", ctypes.c_int32), ("fallbacks", ctypes.c_int32),
                 ("kchunks", ctypes.c_int32), ("zmode_used", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("resid_est", ctypes.c_double)]
+
+
+class oz_gen_t(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("k", ctypes.c_int64), ("sig_el", ctypes.c_int32),
+                ("sig_vec", ctypes.c_int32), ("bits", ctypes.c_int32), ("family", ctypes.c_int32),
+                ("zero_q", ctypes.c_int64), ("key", ctypes.c_uint64)]
+
+
+def gen_params(d):
+    """oz_gen_t from a dict with the fields of oz_gen_t."""
+    return oz_gen_t(*[int(d[name]) for name, _ in oz_gen_t._fields_])
 
 
 def _load():
@@ -85,9 +102,26 @@ def _load():
         "oz_batch_graph_launch": [P],
         "oz_batch_destroy": [P],
         "oz_batch_info": [P, PP(I32), PP(I64), PP(ctypes.c_size_t), P],
+        "oz_batch_report": [P, P],
         "oz_zgemm_batched": [P, I32, P, P, P, P, P, P, P, P, P, P, P, P, P, PP(oz_prec_t), P],
         "oz_dgemm_batched": [P, I32, P, P, P, P, P, P, P, P, P, P, P, P, P, PP(oz_prec_t), P],
         "oz_load_tuning": [P, ctypes.c_char_p],
+        "oz_gen_operands": [P, PP(oz_gen_t), P, I64, P, I64],
+        "oz_features": [P, C, C, I64, I64, I64, ctypes.c_int, P, I64, P, I64, I32, P, I32, P, P],
+        "oz_selector_dataset": [P, I32, P, I32, P, I32, I32, P, P, P, P],
+        "oz_mlp_create": [P, ctypes.c_uint64, PP(P)],
+        "oz_mlp_destroy": [P],
+        "oz_mlp_set_params": [P, P, P, P],
+        "oz_mlp_get_params": [P, P, P, P],
+        "oz_mlp_fit_norm": [P, I64, P],
+        "oz_mlp_forward": [P, I64, P, P],
+        "oz_mlp_grad": [P, I64, P, P, ctypes.c_float, P, P],
+        "oz_mlp_train_step": [P, I64, P, P, ctypes.c_float, ctypes.c_float, P],
+        "oz_mlp_train": [P, I64, P, P, I32, I32, ctypes.c_float, ctypes.c_float, ctypes.c_uint64, P],
+        "oz_mlp_save": [P, ctypes.c_char_p],
+        "oz_mlp_load": [P, ctypes.c_char_p, PP(P)],
+        "oz_set_selector": [P, P],
+        "oz_predict_slices": [P, C, C, I64, I64, I64, ctypes.c_int, P, I64, P, I64, D, I32, PP(I32)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -139,9 +173,9 @@ def oz_set_stream(handle, stream):
     return _check("oz_set_stream", _lib.oz_set_stream(handle, stream))
 
 
-def prec(slices=7, tol=0.0, smax=0, kchunk=0, zmode=0, kernel=0, sstart=0):
+def prec(slices=7, tol=0.0, smax=0, kchunk=0, zmode=0, kernel=0, sstart=0, selector=0):
     """Precision record; prec(0, tol=...) asks for a tolerance-driven call."""
-    return oz_prec_t(slices, smax, kchunk, zmode, kernel, sstart, tol)
+    return oz_prec_t(slices, smax, kchunk, zmode, kernel, sstart, selector, 0, tol)
 
 
 def oz_workspace_size(handle, transa, transb, m, n, k, is_complex, p=None):
@@ -278,6 +312,13 @@ def oz_batch_info(plan, batch):
     return la.value, ti.value, by.value, list(sl)[:batch]
 
 
+def oz_batch_report(plan, batch):
+    """Per-problem reports (oz_report_t) of the plan's last execution."""
+    reps = (oz_report_t * max(1, batch))()
+    _check("oz_batch_report", _lib.oz_batch_report(plan, ctypes.cast(reps, ctypes.c_void_p)))
+    return list(reps)[:batch]
+
+
 def _gemm_batched(fn, is_complex, handle, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, p, slices,
                   check):
     nb, a = _batch_args(is_complex, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, slices)
@@ -308,3 +349,136 @@ def oz_load_tuning(handle, path=None):
     if path == "" or not os.path.exists(path):
         return _check("oz_load_tuning", _lib.oz_load_tuning(handle, None))
     return _check("oz_load_tuning", _lib.oz_load_tuning(handle, path.encode()))
+
+
+# ---- learned slice-count selection -------------------------------------------
+
+# Trained selector network for this device (see train_selector.py)
+SELECTOR_PATH = os.path.join(_HERE, "tune", "selector_gfx950.bin")
+
+
+def _host_array(ctype, n, values=None):
+    arr = (ctype * max(1, n))()
+    if values is not None:
+        for i, v in enumerate(values):
+            arr[i] = v
+    return arr
+
+
+def oz_gen_operands(handle, params, A, lda, B, ldb):
+    """Draw the operands of one selector instance (dict or oz_gen_t) into device buffers."""
+    g = params if isinstance(params, oz_gen_t) else gen_params(params)
+    return _check("oz_gen_operands", _lib.oz_gen_operands(handle, ctypes.byref(g), _ptr(A), lda, _ptr(B), ldb))
+
+
+def oz_features(handle, transa, transb, m, n, k, is_complex, A, lda, B, ldb, tols, feat, smax=0):
+    """Feature rows (device float32 [len(tols), 16]) of op(A) op(B); returns the rule's s per tolerance."""
+    nt = len(tols)
+    th = _host_array(ctypes.c_double, nt, [float(t) for t in tols])
+    sr = _host_array(ctypes.c_int32, nt)
+    _check("oz_features", _lib.oz_features(handle, _ch(transa), _ch(transb), m, n, k, int(is_complex), _ptr(A), lda,
+                                            _ptr(B), ldb, nt, ctypes.cast(th, ctypes.c_void_p), smax, _ptr(feat),
+                                            ctypes.cast(sr, ctypes.c_void_p)))
+    return list(sr)[:nt]
+
+
+def oz_selector_dataset(handle, params, tols, X, y, s_ref=12, smax_rule=0):
+    """Generate and label instances on the GPU.  params: list of dicts / oz_gen_t;
+    tols: [count][ntol] tolerances; X, y: device float32 buffers of count*ntol rows.
+    Returns (rule s per row, eps table [count][s_ref]) as lists."""
+    count = len(params)
+    ntol = len(tols[0]) if count else 1
+    ga = (oz_gen_t * max(1, count))(*[p if isinstance(p, oz_gen_t) else gen_params(p) for p in params])
+    flat = [float(t) for row in tols for t in row]
+    th = _host_array(ctypes.c_double, len(flat), flat)
+    sr = _host_array(ctypes.c_int32, count * ntol)
+    ep = _host_array(ctypes.c_double, count * s_ref)
+    _check("oz_selector_dataset", _lib.oz_selector_dataset(
+        handle, count, ctypes.cast(ga, ctypes.c_void_p), ntol, ctypes.cast(th, ctypes.c_void_p), s_ref, smax_rule,
+        _ptr(X), _ptr(y), ctypes.cast(sr, ctypes.c_void_p), ctypes.cast(ep, ctypes.c_void_p)))
+    eps = list(ep)[:count * s_ref]
+    return list(sr)[:count * ntol], [eps[b * s_ref:(b + 1) * s_ref] for b in range(count)]
+
+
+def oz_mlp_create(handle, seed=0):
+    out = ctypes.c_void_p()
+    _check("oz_mlp_create", _lib.oz_mlp_create(handle, seed, ctypes.byref(out)))
+    return out
+
+
+def oz_mlp_destroy(mlp):
+    return _check("oz_mlp_destroy", _lib.oz_mlp_destroy(mlp))
+
+
+def oz_mlp_set_params(mlp, params=None, mu=None, sd=None):
+    """Host sequences of floats (any may be None)."""
+    def arr(v, n):
+        return ctypes.cast(_host_array(ctypes.c_float, n, [float(x) for x in v]), ctypes.c_void_p) \
+            if v is not None else None
+    keep = [arr(params, OZ_MLP_NPARAM), arr(mu, 16), arr(sd, 16)]
+    return _check("oz_mlp_set_params", _lib.oz_mlp_set_params(mlp, *keep))
+
+
+def oz_mlp_get_params(mlp):
+    """-> (params, mu, sd) as lists of floats."""
+    p = _host_array(ctypes.c_float, OZ_MLP_NPARAM)
+    mu = _host_array(ctypes.c_float, 16)
+    sd = _host_array(ctypes.c_float, 16)
+    _check("oz_mlp_get_params", _lib.oz_mlp_get_params(mlp, ctypes.cast(p, ctypes.c_void_p),
+                                                        ctypes.cast(mu, ctypes.c_void_p),
+                                                        ctypes.cast(sd, ctypes.c_void_p)))
+    return list(p), list(mu), list(sd)
+
+
+def oz_mlp_fit_norm(mlp, rows, X):
+    return _check("oz_mlp_fit_norm", _lib.oz_mlp_fit_norm(mlp, rows, _ptr(X)))
+
+
+def oz_mlp_forward(mlp, rows, X, y):
+    return _check("oz_mlp_forward", _lib.oz_mlp_forward(mlp, rows, _ptr(X), _ptr(y)))
+
+
+def oz_mlp_grad(mlp, rows, X, t, tau):
+    """-> (gradient list, loss)."""
+    g = _host_array(ctypes.c_float, OZ_MLP_NPARAM)
+    loss = ctypes.c_float()
+    _check("oz_mlp_grad", _lib.oz_mlp_grad(mlp, rows, _ptr(X), _ptr(t), tau, ctypes.cast(g, ctypes.c_void_p),
+                                            ctypes.byref(loss)))
+    return list(g), loss.value
+
+
+def oz_mlp_train_step(mlp, rows, X, t, tau, lr):
+    loss = ctypes.c_float()
+    _check("oz_mlp_train_step", _lib.oz_mlp_train_step(mlp, rows, _ptr(X), _ptr(t), tau, lr, ctypes.byref(loss)))
+    return loss.value
+
+
+def oz_mlp_train(mlp, rows, X, t, epochs, batch=256, tau=0.9, lr=1e-3, seed=0):
+    """-> mean loss of every epoch."""
+    el = _host_array(ctypes.c_float, epochs)
+    _check("oz_mlp_train", _lib.oz_mlp_train(mlp, rows, _ptr(X), _ptr(t), epochs, batch, tau, lr, seed,
+                                              ctypes.cast(el, ctypes.c_void_p)))
+    return list(el)[:epochs]
+
+
+def oz_mlp_save(mlp, path):
+    return _check("oz_mlp_save", _lib.oz_mlp_save(mlp, path.encode()))
+
+
+def oz_mlp_load(handle, path=None):
+    out = ctypes.c_void_p()
+    _check("oz_mlp_load", _lib.oz_mlp_load(handle, (SELECTOR_PATH if path is None else path).encode(),
+                                            ctypes.byref(out)))
+    return out
+
+
+def oz_set_selector(handle, mlp):
+    return _check("oz_set_selector", _lib.oz_set_selector(handle, mlp))
+
+
+def oz_predict_slices(handle, transa, transb, m, n, k, is_complex, A, lda, B, ldb, tol, smax=0):
+    out = ctypes.c_int32()
+    _check("oz_predict_slices", _lib.oz_predict_slices(handle, _ch(transa), _ch(transb), m, n, k, int(is_complex),
+                                                        _ptr(A), lda, _ptr(B), ldb, float(tol), smax,
+                                                        ctypes.byref(out)))
+    return out.value

@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liboz.so")
-SOURCES = ["oz_split.hip", "oz_gemm.hip", "oz_check.hip", "oz_api.hip", "oz_batch.hip"]
+SOURCES = ["oz_split.hip", "oz_gemm.hip", "oz_check.hip", "oz_api.hip", "oz_batch.hip", "oz_select.hip",
+           "oz_mlp.hip", "oz_learn.hip"]
 HEADERS = ["oz_internal.h", os.path.join("..", "..", "include", "oz.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -28,6 +28,8 @@ struct oz_handle_s {
     std::vector<hipEvent_t> ev_pending;
     // batched plans: autotuner results (oz_load_tuning)
     std::vector<oz::TuneEntry> tune;
+    // learned slice-count selector (oz_set_selector), not owned
+    oz_mlp_t selector;
 };
 
 namespace {
@@ -35,13 +37,6 @@ namespace {
 constexpr uint32_t kMagic = 0x6f7a3335u;  // "oz35"
 constexpr int kDefaultSlices = 7;
 constexpr int kDefaultSmax = 12;
-// Rule for the starting slice count of a tolerance-driven call: the
-// scale-weighted error of the emulation behaves like
-//   eps(s) ~ c (s + 1) 2^(-7s) sqrt((1/M_A + 1/M_B) / 3),
-// M = mean over vectors of the mean square of x * 2^-E (truncation leaves
-// about 2^-7s per scaled operand entry; the dropped pairs add a term growing
-// with s).  c = 2.5 covers the data families measured (0.7 .. 2.0).
-constexpr double kRuleC = 2.5;
 constexpr uint64_t kProbeSeed = 0x6f7a5eedull;
 
 bool valid(oz_handle_t h) { return h != nullptr && h->magic == kMagic; }
@@ -73,7 +68,7 @@ struct Plan {
     oz::SliceLayout la, lb;
     int64_t nva, nvb;
     size_t off_maxa, off_maxb, off_ea, off_fb, off_sa, off_sb;
-    size_t off_acc, off_msa, off_msb, off_t, off_u, off_diff, off_ref, off_norms, total;
+    size_t off_acc, off_msa, off_msb, off_t, off_u, off_diff, off_ref, off_norms, off_sel, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
@@ -96,7 +91,7 @@ Plan make_plan(int cplx, int64_t m, int64_t n, int64_t k, int s_lay, bool tol_bu
     p.off_fb = take(sizeof(int32_t) * static_cast<size_t>(p.lb.rows_pad));
     p.off_sa = take(static_cast<size_t>(s_lay) * p.la.rows_pad * p.la.kpad);
     p.off_sb = take(static_cast<size_t>(s_lay) * p.lb.rows_pad * p.lb.kpad);
-    p.off_acc = p.off_msa = p.off_msb = p.off_t = p.off_u = p.off_diff = p.off_ref = p.off_norms = 0;
+    p.off_acc = p.off_msa = p.off_msb = p.off_t = p.off_u = p.off_diff = p.off_ref = p.off_norms = p.off_sel = 0;
     if (tol_bufs) {
         p.off_acc = take(sizeof(double) * static_cast<size_t>(p.la.rows_pad) * p.lb.rows_pad);
         p.off_msa = take(sizeof(double) * static_cast<size_t>(m));
@@ -106,6 +101,7 @@ Plan make_plan(int cplx, int64_t m, int64_t n, int64_t k, int s_lay, bool tol_bu
         p.off_diff = take(sizeof(double) * 2 * static_cast<size_t>(m));
         p.off_ref = take(sizeof(double) * 2 * static_cast<size_t>(m));
         p.off_norms = take(sizeof(double) * 2);
+        p.off_sel = take(oz_learned_scratch_bytes());
     }
     p.total = o;
     return p;
@@ -204,10 +200,7 @@ int rule_slices(oz_handle_t h, const oz::OperandView& va, const oz::OperandView&
         *s_out = 1;
         return OZ_OK;
     }
-    const double spread = std::sqrt((1.0 / ma + 1.0 / mb) / 3.0);
-    int s = 1;
-    while (s < smax && kRuleC * (s + 1) * std::ldexp(1.0, -7 * s) * spread > tol) ++s;
-    *s_out = s;
+    *s_out = oz::rule_slices_of(ma, mb, tol, smax);
     return OZ_OK;
 }
 
@@ -235,6 +228,7 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
         if (prec->slices < 0 || prec->slices > OZ_MAX_SLICES) return 14;
         if (prec->zmode != 0 && prec->zmode != 4) return 14;
         if (prec->kernel < 0 || prec->kernel > 3) return 14;
+        if (prec->reserved != 0) return 14;
         if (prec->slices == 0) {
             tol_mode = true;
             tol = prec->tol;
@@ -242,6 +236,8 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
             if (prec->smax) smax = prec->smax;
             if (smax < 1 || smax > OZ_MAX_SLICES) return 14;
             if (prec->sstart < 0 || prec->sstart > smax) return 14;
+            if (prec->selector != 0 && prec->selector != 1) return 14;
+            if (prec->selector == 1 && prec->sstart == 0 && !oz_mlp_valid(h->selector)) return OZ_ERR_ARG;
         } else {
             s = prec->slices;
         }
@@ -335,6 +331,10 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
         double* msb = reinterpret_cast<double*>(ws + p.off_msb);
         if (prec->sstart > 0) {
             s = prec->sstart;
+        } else if (prec->selector == 1) {
+            st = oz_learned_start(h, h->selector, va, vb, maxa, maxb, msa, msb, m, n, k, cplx, tol, smax,
+                                  ws + p.off_sel, &s);
+            if (st) return st;
         } else {
             st = rule_slices(h, va, vb, maxa, maxb, msa, msb, tol, smax, &s);
             if (st) return st;
@@ -411,6 +411,13 @@ int oz_handle_use_device(oz_handle_t h) { return use_device(h); }
 hipStream_t oz_handle_stream(oz_handle_t h) { return h->stream; }
 int oz_handle_device(oz_handle_t h) { return h->device; }
 hipError_t oz_handle_mark(oz_handle_t h) { return mark(h); }
+char* oz_handle_ws(oz_handle_t h, size_t bytes, int* status) {
+    const int st = ensure_ws(h, bytes);
+    if (status) *status = st;
+    return st ? nullptr : static_cast<char*>(h->ws);
+}
+oz_mlp_t oz_handle_selector(oz_handle_t h) { return h->selector; }
+void oz_handle_set_selector(oz_handle_t h, oz_mlp_t mlp) { h->selector = mlp; }
 
 extern "C" {
 
@@ -432,6 +439,7 @@ int oz_create(oz_handle_t* handle, int device) {
     h->ws_bytes = 0;
     h->ws_owned = true;
     h->timing = false;
+    h->selector = nullptr;
     *handle = h;
     return OZ_OK;
 }

@@ -3,6 +3,10 @@
 // a fixed sequence of launches on the handle's stream -- zero, batched scan,
 // batched digits, one persistent GEMM launch per slice count (one for a batch
 // with a single s) -- which can be captured into a HIP graph and replayed.
+// A tolerance-driven plan instead picks each problem's starting s (rule or
+// learned selector, one batched statistics pass), accumulates raw sums, and
+// alternates a batched residual check with incremental growth of the failing
+// problems (grouped by s) before one batched scaling pass.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -17,6 +21,9 @@
 #include "oz_handle.h"
 
 namespace {
+
+constexpr uint64_t kProbeSeed = 0x6f7a5eedull;  // probe vector of the residual check
+constexpr int kDefaultSmax = 12;
 
 constexpr uint32_t kBatchMagic = 0x6f7a6274u;  // "ozbt"
 
@@ -53,6 +60,19 @@ struct oz_batch_s {
     std::vector<int32_t> slices;  // per problem (0 for quick returns)
     hipGraph_t graph;
     hipGraphExec_t graph_exec;
+    // ---- tolerance-driven plans ----
+    bool tol_mode;
+    double tol;
+    int smax, sstart, selector, kernel, cplx, cus;
+    std::vector<int32_t> prob_b;          // plan problem -> batch index
+    std::vector<oz::GemmArgs> host_args;  // raw-write descriptors (host copies)
+    size_t off_args_add;                  // raw-add descriptors
+    size_t off_stat_sides, off_stat_items, off_hist, off_fp, off_feat, off_y, off_s, off_tols;
+    int64_t n_stat_items, n_hist;
+    size_t off_check, off_active, off_norms, off_wt, off_gv, off_row, off_final, off_final_items, off_dyn;
+    int64_t n_wt, n_gv, n_row, n_final, dyn_cap;
+    std::vector<int32_t> s_cur, fallbacks;
+    std::vector<double> resid;
 };
 
 namespace {
@@ -89,6 +109,94 @@ oz::OperandView view(char t, const double* X, int64_t ld, int64_t nv, int64_t k,
     return v;
 }
 
+// One persistent launch over the tiles of `members` (indices into args), all
+// with slice count sv: block shape as requested (kernel 1 / 2), else the tuned
+// vote, else 128 x 64 when the group has at least two such tiles per compute
+// unit; tile order 0 (problems with the most work per tile first) or 1
+// (whole problems dealt to per-XCD queues) as tuned.
+void build_group(const std::vector<oz::GemmArgs>& args, std::vector<size_t> members, int sv, int kernel, int cplx,
+                 int cus, const std::vector<oz::TuneEntry>& tune, Group* out, std::vector<oz::TileItem>* out_items) {
+    // tuned choice for one problem: the entry with the same complexity and s
+    // (else the nearest s) nearest in log n; false when there is no table
+    auto tuned = [&](const oz::GemmArgs& g, int* tile, int* order) {
+        int best = -1;
+        double bd = 1e300;
+        const double size = static_cast<double>(g.m > g.n ? g.m : g.n);
+        for (size_t i = 0; i < tune.size(); ++i) {
+            const oz::TuneEntry& t = tune[i];
+            if (t.cplx != cplx) continue;
+            const double d = std::fabs(std::log2(size / static_cast<double>(t.n))) + 4.0 * std::abs(t.s - sv);
+            if (d < bd) {
+                bd = d;
+                best = static_cast<int>(i);
+            }
+        }
+        if (best < 0) return false;
+        *tile = tune[best].tile;
+        *order = tune[best].order;
+        return true;
+    };
+    int64_t big = 0;
+    bool multi = false;
+    double vote_tile[3] = {0, 0, 0}, vote_order[2] = {0, 0};
+    bool have_tune = false;
+    for (size_t i : members) {
+        big += (args[i].Mp / 128) * (args[i].Np / 64);
+        multi = multi || args[i].chunk_steps < args[i].kpad / oz::kStep;
+        int t, od;
+        if (tuned(args[i], &t, &od)) {
+            const double work = static_cast<double>(args[i].Mp) * args[i].Np * args[i].kpad;
+            vote_tile[t] += work;
+            vote_order[od] += work;
+            have_tune = true;
+        }
+    }
+    int tile = kernel;
+    if (!tile) tile = have_tune ? (vote_tile[1] > vote_tile[2] ? 1 : 2) : (big >= 2 * cus ? 1 : 2);
+    const int order = have_tune && vote_order[1] > vote_order[0] ? 1 : 0;
+    const int64_t bm = tile == 1 ? 128 : 64, bn = 64;
+    std::stable_sort(members.begin(), members.end(), [&](size_t a, size_t b) { return args[a].kpad > args[b].kpad; });
+    auto tiles_of = [&](size_t i, std::vector<oz::TileItem>& dst) {
+        for (int64_t tm = 0; tm < args[i].Mp / bm; ++tm)
+            for (int64_t tn = 0; tn < args[i].Np / bn; ++tn)
+                dst.push_back({static_cast<int32_t>(i), static_cast<int32_t>(tm), static_cast<int32_t>(tn), 0});
+    };
+    std::vector<oz::TileItem>& items = *out_items;
+    items.clear();
+    const int64_t per_cu = tile == 1 ? 1 : 2;  // blocks resident per compute unit
+    if (order == 0) {
+        for (size_t i : members) tiles_of(i, items);
+    } else {
+        // deal whole problems to 8 queues (least work first), then interleave
+        // the queues so that item i lands on a block of XCD i % 8 (blocks of a
+        // persistent grid with a multiple of 8 blocks go round-robin to the
+        // XCDs); exhausted queues leave null items
+        constexpr int kX = 8;
+        std::vector<oz::TileItem> q[kX];
+        double load[kX] = {0};
+        for (size_t i : members) {
+            int x = 0;
+            for (int y = 1; y < kX; ++y)
+                if (load[y] < load[x]) x = y;
+            tiles_of(i, q[x]);
+            load[x] += static_cast<double>(args[i].Mp / bm) * (args[i].Np / bn) * args[i].kpad;
+        }
+        size_t longest = 0;
+        for (int x = 0; x < kX; ++x) longest = std::max(longest, q[x].size());
+        for (size_t j = 0; j < longest; ++j)
+            for (int x = 0; x < kX; ++x) items.push_back(j < q[x].size() ? q[x][j] : oz::TileItem{-1, 0, 0, 0});
+    }
+    Group& gr = *out;
+    gr.s = sv;
+    gr.tile = tile;
+    gr.multi = multi;
+    gr.nitems = static_cast<int64_t>(items.size());
+    int64_t blocks = std::min<int64_t>(gr.nitems, per_cu * cus);
+    if (order == 1) blocks -= blocks % 8;  // keep the XCD stride
+    gr.blocks = static_cast<int>(blocks > 0 ? blocks : 1);
+    gr.off_items = 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -107,10 +215,27 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
     const int w = cplx ? 2 : 1;
     int s_default = 7, kernel = 0;
     int64_t kc_forced = 0;
+    bool tol_mode = false;
+    double tol = 0.0;
+    int smax = kDefaultSmax, sstart = 0, selector = 0;
     if (prec) {
-        if (prec->slices < 1 || prec->slices > oz::kMaxLiveSlices) return 14;  // fixed s per problem, s <= 8
-        if (prec->kernel < 0 || prec->kernel > 2) return 14;
-        s_default = prec->slices;
+        if (prec->kernel < 0 || prec->kernel > 2 || prec->reserved != 0) return 14;
+        if (prec->slices == 0) {
+            // tolerance-driven: s per problem chosen at execution
+            tol_mode = true;
+            tol = prec->tol;
+            if (prec->smax) smax = prec->smax;
+            sstart = prec->sstart;
+            selector = prec->selector;
+            if (!(tol > 0.0) || smax < 1 || smax > OZ_MAX_SLICES || sstart < 0 || sstart > smax ||
+                (selector != 0 && selector != 1) || slices)
+                return 14;
+            if (selector == 1 && sstart == 0 && !oz_mlp_valid(oz_handle_selector(h))) return OZ_ERR_ARG;
+            s_default = smax;  // digit planes held for growth
+        } else {
+            if (prec->slices < 1 || prec->slices > oz::kMaxLiveSlices) return 14;  // fixed s per problem, s <= 8
+            s_default = prec->slices;
+        }
         kernel = prec->kernel;
         kc_forced = prec->kchunk;
     }
@@ -127,7 +252,7 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
         if (ldb[b] < (rb > 1 ? rb : 1)) return 10;
         if (ldc[b] < (m[b] > 1 ? m[b] : 1)) return 13;
         const int sb = slices ? slices[b] : s_default;
-        if (sb < 1 || sb > oz::kMaxLiveSlices) return 14;
+        if (sb < 1 || sb > (tol_mode ? OZ_MAX_SLICES : oz::kMaxLiveSlices)) return 14;
         if (kc_forced < 0 || kc_forced % 64 != 0 || (kc_forced > 0 && kc_forced > kchunk_bound(sb))) return 14;
     }
     if (oz_handle_use_device(h)) return OZ_ERR_HIP;
@@ -140,6 +265,14 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
     P->graph = nullptr;
     P->graph_exec = nullptr;
     P->slices.assign(static_cast<size_t>(batch), 0);
+    P->tol_mode = tol_mode;
+    P->tol = tol;
+    P->smax = smax;
+    P->sstart = sstart;
+    P->selector = selector;
+    P->kernel = kernel;
+    P->cplx = cplx;
+    P->n_stat_items = P->n_hist = P->n_wt = P->n_gv = P->n_row = P->n_final = P->dyn_cap = 0;
 
     // ---- per-problem layouts and workspace offsets --------------------------
     struct Prob {
@@ -186,7 +319,8 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
         q.off_maxb = static_cast<size_t>(n_max) * 8;
         n_max += n[b];
         probs.push_back(q);
-        P->slices[b] = q.s;
+        P->prob_b.push_back(b);
+        P->slices[b] = tol_mode ? 0 : q.s;
     }
     P->off_maxbits = take(static_cast<size_t>(n_max) * 8);
     P->n_maxbits = n_max;
@@ -197,6 +331,34 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
         q.off_fb = take(sizeof(int32_t) * static_cast<size_t>(q.lb.rows_pad));
         q.off_sa = take(static_cast<size_t>(q.s) * q.la.rows_pad * q.la.kpad);
         q.off_sb = take(static_cast<size_t>(q.s) * q.lb.rows_pad * q.lb.kpad);
+    }
+    // tolerance-driven buffers per problem: raw sums, statistics, check vectors
+    struct TolOff {
+        size_t acc, msa, msb, t, u, diff, ref;
+    };
+    std::vector<TolOff> toff(tol_mode ? probs.size() : 0);
+    const size_t nprob = probs.size();
+    if (tol_mode) {
+        for (size_t i = 0; i < nprob; ++i) {
+            const Prob& q = probs[i];
+            const int64_t mm = q.va.nv, nn = q.vb.nv, kk = q.va.k;
+            TolOff& t = toff[i];
+            t.acc = take(sizeof(double) * static_cast<size_t>(q.la.rows_pad) * q.lb.rows_pad);
+            t.msa = take(sizeof(double) * mm);
+            t.msb = take(sizeof(double) * nn);
+            t.t = take(sizeof(double) * nn);
+            t.u = take(sizeof(double) * 4 * kk);
+            t.diff = take(sizeof(double) * 2 * mm);
+            t.ref = take(sizeof(double) * 2 * mm);
+        }
+        P->off_norms = take(sizeof(double) * 2 * nprob);
+        P->n_hist = static_cast<int64_t>(2 * oz::kHistLen * nprob);
+        P->off_hist = take(sizeof(unsigned long long) * P->n_hist);
+        P->off_feat = take(sizeof(float) * oz::kNumFeat * nprob);
+        P->off_y = take(sizeof(float) * nprob);
+        P->off_s = take(sizeof(int32_t) * nprob);
+        P->off_tols = take(sizeof(double) * nprob);
+        P->off_active = take(sizeof(int32_t) * nprob);
     }
 
     // ---- split work lists -----------------------------------------------------
@@ -232,6 +394,7 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, oz_handle_device(h)) == hipSuccess) cus = prop.multiProcessorCount;
     }
+    P->cus = cus;
     std::vector<oz::GemmArgs> args(probs.size());
     for (size_t i = 0; i < probs.size(); ++i) {
         const Prob& q = probs[i];
@@ -248,7 +411,8 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
         g.s = q.s;
         g.s_lay = q.s;
         g.cplx = cplx;
-        g.mode = oz::kFinal;
+        g.mode = tol_mode ? oz::kRawWrite : oz::kFinal;
+        g.acc = tol_mode ? reinterpret_cast<double*>(at(toff[i].acc)) : nullptr;
         g.C = C[q.b];
         g.ldc = ldc[q.b];
         g.m = m[q.b];
@@ -259,102 +423,23 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
         g.beta_i = cplx ? beta[w * q.b + 1] : 0.0;
         g.beta_zero = (g.beta_r == 0.0 && g.beta_i == 0.0) ? 1 : 0;
     }
-    std::vector<int> svals;
-    for (const Prob& q : probs)
-        if (std::find(svals.begin(), svals.end(), q.s) == svals.end()) svals.push_back(q.s);
-    std::sort(svals.begin(), svals.end());
     std::vector<std::vector<oz::TileItem>> group_items;
-    const std::vector<oz::TuneEntry>& tune = oz_handle_tuning(h);
-    // tuned choice for one problem: the entry with the same complexity and s
-    // (else the nearest s) nearest in log n; -1 when there is no table
-    auto tuned = [&](const oz::GemmArgs& g, int sv, int* tile, int* order) {
-        int best = -1;
-        double bd = 1e300;
-        const double size = static_cast<double>(g.m > g.n ? g.m : g.n);
-        for (size_t i = 0; i < tune.size(); ++i) {
-            const oz::TuneEntry& t = tune[i];
-            if (t.cplx != cplx) continue;
-            const double d = std::fabs(std::log2(size / static_cast<double>(t.n))) + 4.0 * std::abs(t.s - sv);
-            if (d < bd) {
-                bd = d;
-                best = static_cast<int>(i);
-            }
+    if (!tol_mode) {
+        std::vector<int> svals;
+        for (const Prob& q : probs)
+            if (std::find(svals.begin(), svals.end(), q.s) == svals.end()) svals.push_back(q.s);
+        std::sort(svals.begin(), svals.end());
+        for (int sv : svals) {
+            std::vector<size_t> members;
+            for (size_t i = 0; i < probs.size(); ++i)
+                if (probs[i].s == sv) members.push_back(i);
+            Group gr;
+            std::vector<oz::TileItem> items;
+            build_group(args, members, sv, kernel, cplx, cus, oz_handle_tuning(h), &gr, &items);
+            P->groups.push_back(gr);
+            group_items.push_back(std::move(items));
         }
-        if (best < 0) return false;
-        *tile = tune[best].tile;
-        *order = tune[best].order;
-        return true;
-    };
-    for (int sv : svals) {
-        int64_t big = 0;
-        bool multi = false;
-        std::vector<size_t> members;
-        double vote_tile[3] = {0, 0, 0}, vote_order[2] = {0, 0};
-        bool have_tune = false;
-        for (size_t i = 0; i < probs.size(); ++i)
-            if (probs[i].s == sv) {
-                members.push_back(i);
-                big += (args[i].Mp / 128) * (args[i].Np / 64);
-                multi = multi || args[i].chunk_steps < args[i].kpad / oz::kStep;
-                int t, od;
-                if (tuned(args[i], sv, &t, &od)) {
-                    const double work = static_cast<double>(args[i].Mp) * args[i].Np * args[i].kpad;
-                    vote_tile[t] += work;
-                    vote_order[od] += work;
-                    have_tune = true;
-                }
-            }
-        // block shape: as requested, else the tuned vote, else 128 x 64 when the
-        // group has at least two such tiles per compute unit
-        int tile = kernel;
-        if (!tile) tile = have_tune ? (vote_tile[1] > vote_tile[2] ? 1 : 2) : (big >= 2 * cus ? 1 : 2);
-        const int order = have_tune && vote_order[1] > vote_order[0] ? 1 : 0;
-        const int64_t bm = tile == 1 ? 128 : 64, bn = 64;
-        // problems with the most work per tile first
-        std::stable_sort(members.begin(), members.end(),
-                         [&](size_t a, size_t b) { return args[a].kpad > args[b].kpad; });
-        auto tiles_of = [&](size_t i, std::vector<oz::TileItem>& dst) {
-            for (int64_t tm = 0; tm < args[i].Mp / bm; ++tm)
-                for (int64_t tn = 0; tn < args[i].Np / bn; ++tn)
-                    dst.push_back({static_cast<int32_t>(i), static_cast<int32_t>(tm), static_cast<int32_t>(tn), 0});
-        };
-        std::vector<oz::TileItem> items;
-        const int64_t per_cu = tile == 1 ? 1 : 2;  // blocks resident per compute unit
-        if (order == 0) {
-            for (size_t i : members) tiles_of(i, items);
-        } else {
-            // deal whole problems to 8 queues (least work first), then interleave
-            // the queues so that item i lands on a block of XCD i % 8 (blocks of
-            // a persistent grid with a multiple of 8 blocks go round-robin to
-            // the XCDs); exhausted queues leave null items
-            constexpr int kX = 8;
-            std::vector<oz::TileItem> q[kX];
-            double load[kX] = {0};
-            for (size_t i : members) {
-                int x = 0;
-                for (int y = 1; y < kX; ++y)
-                    if (load[y] < load[x]) x = y;
-                tiles_of(i, q[x]);
-                load[x] += static_cast<double>(args[i].Mp / bm) * (args[i].Np / bn) * args[i].kpad;
-            }
-            size_t longest = 0;
-            for (int x = 0; x < kX; ++x) longest = std::max(longest, q[x].size());
-            for (size_t j = 0; j < longest; ++j)
-                for (int x = 0; x < kX; ++x) items.push_back(j < q[x].size() ? q[x][j] : oz::TileItem{-1, 0, 0, 0});
-        }
-        Group gr;
-        gr.s = sv;
-        gr.tile = tile;
-        gr.multi = multi;
-        gr.nitems = static_cast<int64_t>(items.size());
-        int64_t blocks = std::min<int64_t>(gr.nitems, per_cu * cus);
-        if (order == 1) blocks -= blocks % 8;  // keep the XCD stride
-        gr.blocks = static_cast<int>(blocks > 0 ? blocks : 1);
-        gr.off_items = 0;
-        P->groups.push_back(gr);
-        group_items.push_back(std::move(items));
     }
-
     // descriptors after the workspace
     P->off_ops = take(sizeof(oz::SplitOp) * ops.size());
     P->off_scan = take(sizeof(oz::BlockItem) * scan_items.size());
@@ -364,6 +449,103 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
         P->groups[gi].off_items = take(sizeof(oz::TileItem) * group_items[gi].size());
     P->n_scan = static_cast<int64_t>(scan_items.size());
     P->n_digits = static_cast<int64_t>(dig_items.size());
+    std::vector<oz::StatSide> stat_sides;
+    std::vector<oz::BlockItem> stat_items, wt_items, gv_items, row_items, fin_items;
+    std::vector<oz::FeatProb> fps;
+    std::vector<oz::CheckArgs> checks;
+    std::vector<oz::FinalArgs> finals;
+    std::vector<oz::GemmArgs> args_add;
+    if (tol_mode) {
+        int64_t tiles = 0;
+        for (size_t i = 0; i < nprob; ++i) {
+            const Prob& q = probs[i];
+            const TolOff& t = toff[i];
+            const int64_t mm = q.va.nv, nn = q.vb.nv, kk = q.va.k;
+            unsigned long long* hist =
+                reinterpret_cast<unsigned long long*>(at(P->off_hist)) + 2 * oz::kHistLen * i;
+            double* msa = reinterpret_cast<double*>(at(t.msa));
+            double* msb = reinterpret_cast<double*>(at(t.msb));
+            for (int side = 0; side < 2; ++side) {
+                const int32_t si = static_cast<int32_t>(stat_sides.size());
+                oz::StatSide ss{side == 0 ? q.va : q.vb,
+                                reinterpret_cast<const uint64_t*>(at(side == 0 ? q.off_maxa : q.off_maxb)),
+                                side == 0 ? msa : msb, hist + side * oz::kHistLen};
+                stat_sides.push_back(ss);
+                int64_t nb;
+                oz::stat_blocks(ss.op, &nb);
+                for (int64_t y = 0; y < nb; ++y) stat_items.push_back({si, 0, static_cast<int32_t>(y), 0});
+            }
+            oz::FeatProb fp;
+            std::memset(&fp, 0, sizeof(fp));
+            fp.msq[0] = msa;
+            fp.msq[1] = msb;
+            fp.hist[0] = hist;
+            fp.hist[1] = hist + oz::kHistLen;
+            fp.nv[0] = mm;
+            fp.nv[1] = nn;
+            fp.m = mm;
+            fp.n = nn;
+            fp.k = kk;
+            fp.cplx = cplx;
+            fp.ntol = 1;
+            fp.tols = reinterpret_cast<const double*>(at(P->off_tols)) + i;
+            fp.feat = reinterpret_cast<float*>(at(P->off_feat)) + oz::kNumFeat * i;
+            fp.s_rule = reinterpret_cast<int32_t*>(at(P->off_s)) + i;
+            fp.smax = smax;
+            fps.push_back(fp);
+            oz::CheckArgs c;
+            std::memset(&c, 0, sizeof(c));
+            c.opa = q.va;
+            c.opb = q.vb;
+            c.maxa = reinterpret_cast<const uint64_t*>(at(q.off_maxa));
+            c.maxb = reinterpret_cast<const uint64_t*>(at(q.off_maxb));
+            c.acc = args[i].acc;
+            c.Mp = q.la.rows_pad;
+            c.EA = args[i].EA;
+            c.FB = args[i].FB;
+            c.seed = kProbeSeed;
+            c.t = reinterpret_cast<double*>(at(t.t));
+            c.u = reinterpret_cast<double*>(at(t.u));
+            c.diff = reinterpret_cast<double*>(at(t.diff));
+            c.ref = reinterpret_cast<double*>(at(t.ref));
+            c.norms = reinterpret_cast<double*>(at(P->off_norms)) + 2 * i;
+            checks.push_back(c);
+            const int32_t pi = static_cast<int32_t>(i);
+            for (int64_t x = 0; x < (nn + 255) / 256; ++x) wt_items.push_back({pi, static_cast<int32_t>(x), 0, 0});
+            for (int64_t x = 0; x < (kk + 255) / 256; ++x) gv_items.push_back({pi, static_cast<int32_t>(x), 0, 0});
+            for (int64_t x = 0; x < (mm + 255) / 256; ++x) row_items.push_back({pi, static_cast<int32_t>(x), 0, 0});
+            for (int64_t x = 0; x < (mm + 255) / 256; ++x) fin_items.push_back({pi, static_cast<int32_t>(x), 0, 0});
+            const oz::GemmArgs& g = args[i];
+            finals.push_back({g.acc, g.Mp, g.EA, g.FB, g.C, g.ldc, g.m, g.n, cplx, g.alpha_r, g.alpha_i, g.beta_r,
+                              g.beta_i, g.beta_zero});
+            oz::GemmArgs ga = g;
+            ga.mode = oz::kRawAdd;
+            args_add.push_back(ga);
+            tiles += (g.Mp / 64) * (g.Np / 64);
+        }
+        // dynamic tile lists of one growth round: every problem at most once,
+        // plus the null items of the per-XCD queues (at most 8 per problem)
+        P->dyn_cap = tiles + 8 * static_cast<int64_t>(nprob) + 8;
+        P->off_args_add = take(sizeof(oz::GemmArgs) * nprob);
+        P->off_stat_sides = take(sizeof(oz::StatSide) * stat_sides.size());
+        P->off_stat_items = take(sizeof(oz::BlockItem) * stat_items.size());
+        P->off_fp = take(sizeof(oz::FeatProb) * nprob);
+        P->off_check = take(sizeof(oz::CheckArgs) * nprob);
+        P->off_wt = take(sizeof(oz::BlockItem) * wt_items.size());
+        P->off_gv = take(sizeof(oz::BlockItem) * gv_items.size());
+        P->off_row = take(sizeof(oz::BlockItem) * row_items.size());
+        P->off_final = take(sizeof(oz::FinalArgs) * nprob);
+        P->off_final_items = take(sizeof(oz::BlockItem) * fin_items.size());
+        P->off_dyn = take(sizeof(oz::TileItem) * P->dyn_cap);
+        P->n_stat_items = static_cast<int64_t>(stat_items.size());
+        P->n_wt = static_cast<int64_t>(wt_items.size());
+        P->n_gv = static_cast<int64_t>(gv_items.size());
+        P->n_row = static_cast<int64_t>(row_items.size());
+        P->n_final = static_cast<int64_t>(fin_items.size());
+    }
+    P->s_cur.assign(nprob, 0);
+    P->fallbacks.assign(nprob, 0);
+    P->resid.assign(nprob, 0.0);
     P->dev_bytes = o;
     if (o > 0 && hipMalloc(&P->dev, o) != hipSuccess) {
         delete P;
@@ -382,7 +564,47 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
         g.SB = fix(g.SB);
         g.EA = fix(g.EA);
         g.FB = fix(g.FB);
+        if (g.acc) g.acc = fix(g.acc);
     }
+    for (oz::GemmArgs& g : args_add) {
+        g.SA = fix(g.SA);
+        g.SB = fix(g.SB);
+        g.EA = fix(g.EA);
+        g.FB = fix(g.FB);
+        g.acc = fix(g.acc);
+    }
+    for (oz::StatSide& ss : stat_sides) {
+        ss.maxbits = fix(ss.maxbits);
+        ss.msq = fix(ss.msq);
+        ss.hist = fix(ss.hist);
+    }
+    for (oz::FeatProb& fp : fps) {
+        fp.msq[0] = fix(fp.msq[0]);
+        fp.msq[1] = fix(fp.msq[1]);
+        fp.hist[0] = fix(fp.hist[0]);
+        fp.hist[1] = fix(fp.hist[1]);
+        fp.tols = fix(fp.tols);
+        fp.feat = fix(fp.feat);
+        fp.s_rule = fix(fp.s_rule);
+    }
+    for (oz::CheckArgs& c : checks) {
+        c.maxa = fix(c.maxa);
+        c.maxb = fix(c.maxb);
+        c.acc = fix(c.acc);
+        c.EA = fix(c.EA);
+        c.FB = fix(c.FB);
+        c.t = fix(c.t);
+        c.u = fix(c.u);
+        c.diff = fix(c.diff);
+        c.ref = fix(c.ref);
+        c.norms = fix(c.norms);
+    }
+    for (oz::FinalArgs& f : finals) {
+        f.acc = fix(f.acc);
+        f.EA = fix(f.EA);
+        f.FB = fix(f.FB);
+    }
+    P->host_args = args;
     hipError_t e = hipSuccess;
     auto up_load = [&](size_t off, const void* src, size_t bytes) {
         if (e == hipSuccess && bytes) e = hipMemcpy(dev + off, src, bytes, hipMemcpyHostToDevice);
@@ -393,6 +615,20 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
     up_load(P->off_args, args.data(), sizeof(oz::GemmArgs) * args.size());
     for (size_t gi = 0; gi < P->groups.size(); ++gi)
         up_load(P->groups[gi].off_items, group_items[gi].data(), sizeof(oz::TileItem) * group_items[gi].size());
+    if (tol_mode) {
+        const std::vector<double> tolv(nprob, tol);
+        up_load(P->off_args_add, args_add.data(), sizeof(oz::GemmArgs) * nprob);
+        up_load(P->off_stat_sides, stat_sides.data(), sizeof(oz::StatSide) * stat_sides.size());
+        up_load(P->off_stat_items, stat_items.data(), sizeof(oz::BlockItem) * stat_items.size());
+        up_load(P->off_fp, fps.data(), sizeof(oz::FeatProb) * nprob);
+        up_load(P->off_check, checks.data(), sizeof(oz::CheckArgs) * nprob);
+        up_load(P->off_wt, wt_items.data(), sizeof(oz::BlockItem) * wt_items.size());
+        up_load(P->off_gv, gv_items.data(), sizeof(oz::BlockItem) * gv_items.size());
+        up_load(P->off_row, row_items.data(), sizeof(oz::BlockItem) * row_items.size());
+        up_load(P->off_final, finals.data(), sizeof(oz::FinalArgs) * nprob);
+        up_load(P->off_final_items, fin_items.data(), sizeof(oz::BlockItem) * fin_items.size());
+        up_load(P->off_tols, tolv.data(), sizeof(double) * nprob);
+    }
     if (e != hipSuccess) {
         hipFree(P->dev);
         delete P;
@@ -402,10 +638,164 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
     return OZ_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// One round of GEMM work of a tolerance-driven plan: every listed problem at
+// its current slice count, raw-write (first round) or only the new
+// anti-diagonal added to the raw sums (growth).  Problems are grouped by s;
+// s <= 8 runs as one persistent launch per group, larger s problem by problem
+// on the streaming kernel.
+int tol_round(oz_batch_t P, const std::vector<size_t>& members, bool growth, hipStream_t st) {
+    char* dev = static_cast<char*>(P->dev);
+    const oz::GemmArgs* dargs =
+        reinterpret_cast<const oz::GemmArgs*>(dev + (growth ? P->off_args_add : P->off_args));
+    std::vector<int> svals;
+    for (size_t i : members)
+        if (std::find(svals.begin(), svals.end(), P->s_cur[i]) == svals.end()) svals.push_back(P->s_cur[i]);
+    std::sort(svals.begin(), svals.end());
+    std::vector<oz::TileItem> all;
+    std::vector<Group> groups;
+    for (int sv : svals) {
+        std::vector<size_t> mem;
+        for (size_t i : members)
+            if (P->s_cur[i] == sv) mem.push_back(i);
+        if (sv > oz::kMaxLiveSlices) {
+            for (size_t i : mem) {
+                oz::GemmArgs g = P->host_args[i];
+                g.s = sv;
+                g.top = growth ? 1 : 0;
+                g.mode = growth ? oz::kRawAdd : oz::kRawWrite;
+                g.tile = 3;
+                if (oz::launch_gemm(g, st) != hipSuccess) return OZ_ERR_HIP;
+            }
+            continue;
+        }
+        Group gr;
+        std::vector<oz::TileItem> items;
+        build_group(P->host_args, mem, sv, P->kernel, P->cplx, P->cus, oz_handle_tuning(P->h), &gr, &items);
+        gr.off_items = all.size();
+        all.insert(all.end(), items.begin(), items.end());
+        groups.push_back(gr);
+    }
+    if (groups.empty()) return OZ_OK;
+    if (static_cast<int64_t>(all.size()) > P->dyn_cap) return OZ_ERR_ALLOC;
+    oz::TileItem* ditems = reinterpret_cast<oz::TileItem*>(dev + P->off_dyn);
+    // the host list must outlive the copy: wait for it
+    if (hipMemcpyAsync(ditems, all.data(), sizeof(oz::TileItem) * all.size(), hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return OZ_ERR_HIP;
+    for (const Group& gr : groups)
+        if (oz::launch_gemm_persistent(dargs, ditems + gr.off_items, gr.nitems, gr.s, gr.tile, gr.blocks, growth,
+                                       gr.multi, st) != hipSuccess)
+            return OZ_ERR_HIP;
+    return OZ_OK;
+}
+
+int execute_tol(oz_batch_t P) {
+    oz_handle_t h = P->h;
+    hipStream_t st = oz_handle_stream(h);
+    char* dev = static_cast<char*>(P->dev);
+    const size_t nprob = P->prob_b.size();
+    hipError_t e = hipSuccess;
+    for (const ScaleOnly& so : P->scale_only)
+        if (e == hipSuccess) e = oz::launch_scale_c(so.C, so.ldc, so.m, so.n, so.cplx, so.br, so.bi, so.beta_zero, st);
+    if (e == hipSuccess && P->n_maxbits)
+        e = oz::launch_zero_u64(reinterpret_cast<uint64_t*>(dev + P->off_maxbits), P->n_maxbits, st);
+    const oz::SplitOp* ops = reinterpret_cast<const oz::SplitOp*>(dev + P->off_ops);
+    if (e == hipSuccess)
+        e = oz::launch_scan_batched(ops, reinterpret_cast<const oz::BlockItem*>(dev + P->off_scan), P->n_scan, st);
+    if (e == hipSuccess)
+        e = oz::launch_digits_batched(ops, reinterpret_cast<const oz::BlockItem*>(dev + P->off_digits), P->n_digits,
+                                      st);
+    if (e != hipSuccess) return OZ_ERR_HIP;
+    if (nprob == 0) return OZ_OK;
+    // (1) starting slice counts
+    std::vector<int32_t> s0(nprob, P->sstart);
+    if (P->sstart == 0) {
+        int32_t* sdev = reinterpret_cast<int32_t*>(dev + P->off_s);
+        e = oz::launch_zero_u64(reinterpret_cast<uint64_t*>(dev + P->off_hist), P->n_hist, st);
+        if (e == hipSuccess)
+            e = oz::launch_stats_batched(reinterpret_cast<const oz::StatSide*>(dev + P->off_stat_sides),
+                                         reinterpret_cast<const oz::BlockItem*>(dev + P->off_stat_items),
+                                         P->n_stat_items, st);
+        if (e == hipSuccess)
+            e = oz::launch_features(reinterpret_cast<const oz::FeatProb*>(dev + P->off_fp),
+                                    static_cast<int64_t>(nprob), st);
+        if (e == hipSuccess && P->selector == 1) {
+            oz_mlp_t mlp = oz_handle_selector(h);
+            if (!oz_mlp_valid(mlp)) return OZ_ERR_ARG;
+            e = oz_mlp_predict_device(mlp, static_cast<int64_t>(nprob), reinterpret_cast<float*>(dev + P->off_feat),
+                                      reinterpret_cast<float*>(dev + P->off_y), P->smax < 2 ? P->smax : 2, P->smax,
+                                      sdev, st);
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(s0.data(), sdev, sizeof(int32_t) * nprob, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return OZ_ERR_HIP;
+    }
+    std::vector<size_t> members(nprob);
+    for (size_t i = 0; i < nprob; ++i) {
+        P->s_cur[i] = s0[i];
+        P->fallbacks[i] = 0;
+        P->resid[i] = 0.0;
+        members[i] = i;
+    }
+    // (2) raw sums at the starting s
+    int rc = tol_round(P, members, false, st);
+    if (rc) return rc;
+    // (3) check the active problems; grow the failing ones by one slice
+    std::vector<int32_t> active(nprob, 1);
+    std::vector<double> norms(2 * nprob);
+    const oz::CheckArgs* checks = reinterpret_cast<const oz::CheckArgs*>(dev + P->off_check);
+    int32_t* dactive = reinterpret_cast<int32_t*>(dev + P->off_active);
+    for (;;) {
+        e = hipMemcpyAsync(dactive, active.data(), sizeof(int32_t) * nprob, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = oz::launch_residual_batched(checks, static_cast<int64_t>(nprob), dactive,
+                                            reinterpret_cast<const oz::BlockItem*>(dev + P->off_wt), P->n_wt,
+                                            reinterpret_cast<const oz::BlockItem*>(dev + P->off_gv), P->n_gv,
+                                            reinterpret_cast<const oz::BlockItem*>(dev + P->off_row), P->n_row, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(norms.data(), dev + P->off_norms, sizeof(double) * 2 * nprob, hipMemcpyDeviceToHost,
+                               st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return OZ_ERR_HIP;
+        std::vector<size_t> grow;
+        for (size_t i = 0; i < nprob; ++i) {
+            if (!active[i]) continue;
+            const double n0 = norms[2 * i], n1 = norms[2 * i + 1];
+            const double eps = n1 > 0.0 ? std::sqrt(n0 / n1) : std::sqrt(n0);
+            P->resid[i] = eps;
+            if (!(eps > P->tol) || P->s_cur[i] >= P->smax) {  // NaN (non-finite input) also stops
+                active[i] = 0;
+                continue;
+            }
+            ++P->s_cur[i];
+            ++P->fallbacks[i];
+            grow.push_back(i);
+        }
+        if (grow.empty()) break;
+        rc = tol_round(P, grow, true, st);
+        if (rc) return rc;
+    }
+    // (4) C = alpha * ldexp(acc, E + F) + beta * C
+    e = oz::launch_finalize_batched(reinterpret_cast<const oz::FinalArgs*>(dev + P->off_final),
+                                    reinterpret_cast<const oz::BlockItem*>(dev + P->off_final_items), P->n_final, st);
+    for (size_t i = 0; i < nprob; ++i) P->slices[P->prob_b[i]] = P->s_cur[i];
+    return e == hipSuccess ? OZ_OK : OZ_ERR_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
 int oz_batch_execute(oz_batch_t P) {
     if (!P || P->magic != kBatchMagic) return OZ_ERR_HANDLE;
     oz_handle_t h = P->h;
     if (oz_handle_use_device(h)) return OZ_ERR_HIP;
+    if (P->tol_mode) return execute_tol(P);
     hipStream_t st = oz_handle_stream(h);
     char* dev = static_cast<char*>(P->dev);
     hipError_t e = oz_handle_mark(h);  // timing: before the split launches
@@ -431,6 +821,7 @@ int oz_batch_execute(oz_batch_t P) {
 
 int oz_batch_graph_launch(oz_batch_t P) {
     if (!P || P->magic != kBatchMagic) return OZ_ERR_HANDLE;
+    if (P->tol_mode) return OZ_ERR_ARG;  // host decisions between launches: not capturable
     hipStream_t st = oz_handle_stream(P->h);
     if (st == nullptr) return OZ_ERR_ARG;  // the null stream cannot be captured
     if (oz_handle_use_device(P->h)) return OZ_ERR_HIP;
@@ -462,6 +853,39 @@ int oz_batch_destroy(oz_batch_t P) {
     if (P->dev) hipFree(P->dev);
     P->magic = 0;
     delete P;
+    return OZ_OK;
+}
+
+int oz_batch_report(oz_batch_t P, oz_report_t* reps) {
+    if (!P || P->magic != kBatchMagic) return OZ_ERR_HANDLE;
+    if (!reps) return OZ_ERR_ARG;
+    for (size_t b = 0; b < P->slices.size(); ++b) {
+        std::memset(&reps[b], 0, sizeof(oz_report_t));
+        reps[b].slices_used = P->slices[b];
+        reps[b].zmode_used = P->cplx ? 4 : 0;
+    }
+    for (size_t i = 0; i < P->prob_b.size(); ++i) {
+        oz_report_t& r = reps[P->prob_b[i]];
+        r.fallbacks = P->fallbacks[i];
+        r.resid_est = P->resid[i];
+        const oz::GemmArgs& g = P->host_args[i];
+        r.kchunks = static_cast<int32_t>((g.kpad / oz::kStep + g.chunk_steps - 1) / g.chunk_steps);
+    }
+    // scale exponents marking non-finite input
+    std::vector<int32_t> ea, fb;
+    for (size_t i = 0; i < P->host_args.size(); ++i) {
+        const oz::GemmArgs& g = P->host_args[i];
+        ea.resize(static_cast<size_t>(g.m));
+        fb.resize(static_cast<size_t>(g.n));
+        if (hipStreamSynchronize(oz_handle_stream(P->h)) != hipSuccess ||
+            hipMemcpy(ea.data(), g.EA, sizeof(int32_t) * g.m, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(fb.data(), g.FB, sizeof(int32_t) * g.n, hipMemcpyDeviceToHost) != hipSuccess)
+            return OZ_ERR_HIP;
+        bool bad = false;
+        for (int32_t x : ea) bad = bad || x == oz::kNonFiniteExp;
+        for (int32_t x : fb) bad = bad || x == oz::kNonFiniteExp;
+        if (bad) reps[P->prob_b[i]].status = OZ_ERR_NONFINITE;
+    }
     return OZ_OK;
 }
 

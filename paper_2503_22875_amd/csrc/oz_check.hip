@@ -87,16 +87,17 @@ __global__ __launch_bounds__(256) void vec_stats_kernel(OperandView op, const ui
 }
 
 // ---- t_j = sigma_j / max|op(B)_:j| ------------------------------------------
-__global__ void weights_kernel(const uint64_t* maxbits_b, int64_t n, uint64_t seed, double* t) {
-    const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    const double mx = max_of_bits(maxbits_b[j]);
-    t[j] = mx > 0.0 ? rademacher(seed, j) / mx : 0.0;
+__device__ __forceinline__ void weights_body(const CheckArgs& c, int64_t j) {
+    if (j >= c.opb.nv) return;
+    const double mx = max_of_bits(c.maxb[j]);
+    c.t[j] = mx > 0.0 ? rademacher(c.seed, j) / mx : 0.0;
 }
 
 // ---- u = op(B) t in double-double; u[l] = (re.hi, re.lo, im.hi, im.lo) ------
-__global__ void gemv_b_kernel(OperandView opb, const double* t, double* u) {
-    const int64_t l = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void gemv_b_body(const CheckArgs& c, int64_t l) {
+    const OperandView& opb = c.opb;
+    const double* t = c.t;
+    double* u = c.u;
     if (l >= opb.k) return;
     dd sr = {0.0, 0.0}, si = {0.0, 0.0};
     for (int64_t j = 0; j < opb.nv; ++j) {
@@ -116,10 +117,17 @@ __global__ void gemv_b_kernel(OperandView opb, const double* t, double* u) {
 // ---- per row i of op(A): y2 = w_i op(A)_i: u, y1 = w_i sum_j C_emu_ij t_j ----
 // Writes diff[i] = y1 - y2 and ref[i] = y2 (real, or real and imaginary parts
 // at 2i, 2i+1 for complex).
-__global__ void rows_kernel(OperandView opa, const uint64_t* maxbits_a, const double* u, const double* acc,
-                            int64_t Mp, const int32_t* EA, const int32_t* FB, const double* t, int64_t n,
-                            double* diff, double* ref) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void rows_body(const CheckArgs& c, int64_t i) {
+    const OperandView& opa = c.opa;
+    const uint64_t* maxbits_a = c.maxa;
+    const double* u = c.u;
+    const double* acc = c.acc;
+    const int64_t Mp = c.Mp, n = c.opb.nv;
+    const int32_t* EA = c.EA;
+    const int32_t* FB = c.FB;
+    const double* t = c.t;
+    double* diff = c.diff;
+    double* ref = c.ref;
     if (i >= opa.nv) return;
     const double mx = max_of_bits(maxbits_a[i]);
     const double w = mx > 0.0 ? 1.0 / mx : 0.0;
@@ -166,7 +174,7 @@ __global__ void rows_kernel(OperandView opa, const uint64_t* maxbits_a, const do
 }
 
 // ---- out[0] = sum diff^2, out[1] = sum ref^2 (one block, fixed order) ------
-__global__ __launch_bounds__(256) void norms_kernel(const double* diff, const double* ref, int64_t len, double* out) {
+__device__ __forceinline__ void norms_body(const double* diff, const double* ref, int64_t len, double* out) {
     __shared__ double sd[256], sr[256];
     double a = 0.0, b = 0.0;
     for (int64_t i = threadIdx.x; i < len; i += 256) {
@@ -191,15 +199,15 @@ __global__ __launch_bounds__(256) void norms_kernel(const double* diff, const do
 
 // ---- C = alpha * ldexp(acc, E+F) + beta * C (same arithmetic as the fused
 // GEMM epilogue); NaN where a scale marks Inf/NaN input ---------------------
-__global__ void finalize_kernel(const double* acc, int64_t Mp, const int32_t* EA, const int32_t* FB, double* C,
-                                int64_t ldc, int64_t m, int64_t n, int cplx, double ar, double ai, double br,
-                                double bi, int beta_zero) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void finalize_body(const double* acc, int64_t Mp, const int32_t* EA, const int32_t* FB,
+                                              double* C, int64_t ldc, int64_t m, int64_t n, int cplx, double ar,
+                                              double ai, double br, double bi, int beta_zero, int64_t i, int64_t j0,
+                                              int64_t jstep) {
     if (i >= m) return;
     const double nan = __longlong_as_double(0x7ff8000000000000ll);
     const int32_t e = EA[i];
     const int64_t r_re = cplx ? 32 * (i >> 4) + 16 * ((i >> 3) & 1) + (i & 7) : i;
-    for (int64_t j = blockIdx.y; j < n; j += gridDim.y) {
+    for (int64_t j = j0; j < n; j += jstep) {
         const int32_t f = FB[j];
         const bool bad = e == kNonFiniteExp || f == kNonFiniteExp;
         if (!cplx) {
@@ -231,6 +239,50 @@ __global__ void finalize_kernel(const double* acc, int64_t Mp, const int32_t* EA
     }
 }
 
+// ---- kernels: one product -------------------------------------------------------
+__global__ void weights_kernel(CheckArgs c) { weights_body(c, static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x); }
+__global__ void gemv_b_kernel(CheckArgs c) { gemv_b_body(c, static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x); }
+__global__ void rows_kernel(CheckArgs c) { rows_body(c, static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x); }
+__global__ __launch_bounds__(256) void norms_kernel(const double* diff, const double* ref, int64_t len,
+                                                    double* out) {
+    norms_body(diff, ref, len, out);
+}
+__global__ void finalize_kernel(const double* acc, int64_t Mp, const int32_t* EA, const int32_t* FB, double* C,
+                                int64_t ldc, int64_t m, int64_t n, int cplx, double ar, double ai, double br,
+                                double bi, int beta_zero) {
+    finalize_body(acc, Mp, EA, FB, C, ldc, m, n, cplx, ar, ai, br, bi, beta_zero,
+                  static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x, blockIdx.y, gridDim.y);
+}
+
+// ---- kernels: many products; an item names the product (op) and the block
+// index along its phase (bx); products whose flag is 0 are skipped -------------
+__global__ void weights_batched_kernel(const CheckArgs* c, const int32_t* active, const BlockItem* items) {
+    const BlockItem it = items[blockIdx.x];
+    if (!active[it.op]) return;
+    weights_body(c[it.op], static_cast<int64_t>(it.bx) * 256 + threadIdx.x);
+}
+__global__ void gemv_b_batched_kernel(const CheckArgs* c, const int32_t* active, const BlockItem* items) {
+    const BlockItem it = items[blockIdx.x];
+    if (!active[it.op]) return;
+    gemv_b_body(c[it.op], static_cast<int64_t>(it.bx) * 256 + threadIdx.x);
+}
+__global__ void rows_batched_kernel(const CheckArgs* c, const int32_t* active, const BlockItem* items) {
+    const BlockItem it = items[blockIdx.x];
+    if (!active[it.op]) return;
+    rows_body(c[it.op], static_cast<int64_t>(it.bx) * 256 + threadIdx.x);
+}
+__global__ __launch_bounds__(256) void norms_batched_kernel(const CheckArgs* c, const int32_t* active) {
+    const int p = blockIdx.x;
+    if (!active[p]) return;
+    norms_body(c[p].diff, c[p].ref, c[p].opa.cplx ? 2 * c[p].opa.nv : c[p].opa.nv, c[p].norms);
+}
+__global__ void finalize_batched_kernel(const FinalArgs* f, const BlockItem* items) {
+    const BlockItem it = items[blockIdx.x];
+    const FinalArgs& a = f[it.op];
+    finalize_body(a.acc, a.Mp, a.EA, a.FB, a.C, a.ldc, a.m, a.n, a.cplx, a.ar, a.ai, a.br, a.bi, a.beta_zero,
+                  static_cast<int64_t>(it.bx) * 256 + threadIdx.x, 0, 1);
+}
+
 }  // namespace
 
 hipError_t launch_vec_stats(const OperandView& op, const uint64_t* maxbits, double* ms, hipStream_t st) {
@@ -243,13 +295,9 @@ hipError_t launch_vec_stats(const OperandView& op, const uint64_t* maxbits, doub
 hipError_t launch_residual(const CheckArgs& c, hipStream_t st) {
     const int64_t n = c.opb.nv, k = c.opa.k, m = c.opa.nv;
     if (m <= 0 || n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(weights_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, c.maxb, n,
-                       c.seed, c.t);
-    if (k > 0)
-        hipLaunchKernelGGL(gemv_b_kernel, dim3(static_cast<unsigned>((k + 255) / 256)), dim3(256), 0, st, c.opb, c.t,
-                           c.u);
-    hipLaunchKernelGGL(rows_kernel, dim3(static_cast<unsigned>((m + 255) / 256)), dim3(256), 0, st, c.opa, c.maxa, c.u,
-                       c.acc, c.Mp, c.EA, c.FB, c.t, n, c.diff, c.ref);
+    hipLaunchKernelGGL(weights_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, c);
+    if (k > 0) hipLaunchKernelGGL(gemv_b_kernel, dim3(static_cast<unsigned>((k + 255) / 256)), dim3(256), 0, st, c);
+    hipLaunchKernelGGL(rows_kernel, dim3(static_cast<unsigned>((m + 255) / 256)), dim3(256), 0, st, c);
     const int64_t len = c.opa.cplx ? 2 * m : m;
     hipLaunchKernelGGL(norms_kernel, dim3(1), dim3(256), 0, st, c.diff, c.ref, len, c.norms);
     return hipGetLastError();
@@ -262,6 +310,29 @@ hipError_t launch_finalize(const double* acc, int64_t Mp, const int32_t* EA, con
     dim3 grid(static_cast<unsigned>((m + 255) / 256), static_cast<unsigned>(n < 65535 ? n : 65535));
     hipLaunchKernelGGL(finalize_kernel, grid, dim3(256), 0, st, acc, Mp, EA, FB, C, ldc, m, n, cplx, ar, ai, br, bi,
                        beta_zero);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_batched(const CheckArgs* c, int64_t nprob, const int32_t* active, const BlockItem* wt_items,
+                                   int64_t n_wt, const BlockItem* gv_items, int64_t n_gv, const BlockItem* row_items,
+                                   int64_t n_row, hipStream_t st) {
+    if (nprob <= 0) return hipSuccess;
+    if (n_wt > 0)
+        hipLaunchKernelGGL(weights_batched_kernel, dim3(static_cast<unsigned>(n_wt)), dim3(256), 0, st, c, active,
+                           wt_items);
+    if (n_gv > 0)
+        hipLaunchKernelGGL(gemv_b_batched_kernel, dim3(static_cast<unsigned>(n_gv)), dim3(256), 0, st, c, active,
+                           gv_items);
+    if (n_row > 0)
+        hipLaunchKernelGGL(rows_batched_kernel, dim3(static_cast<unsigned>(n_row)), dim3(256), 0, st, c, active,
+                           row_items);
+    hipLaunchKernelGGL(norms_batched_kernel, dim3(static_cast<unsigned>(nprob)), dim3(256), 0, st, c, active);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_batched(const FinalArgs* f, const BlockItem* items, int64_t nitems, hipStream_t st) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(finalize_batched_kernel, dim3(static_cast<unsigned>(nitems)), dim3(256), 0, st, f, items);
     return hipGetLastError();
 }
 

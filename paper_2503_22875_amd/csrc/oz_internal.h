@@ -32,6 +32,23 @@ struct OperandView {
     int side_a;         // complex side 'A' writes the two-row (re, im) form
 };
 
+// Vectors of op(X): side 'A' rows of op(A) (nv = m), side 'B' columns of
+// op(B) (nv = n); trans 'N', 'T' or 'C' (upper case).
+inline OperandView operand_view(char trans, const double* X, int64_t ld, int64_t nv, int64_t k, int cplx,
+                                int side_a) {
+    OperandView v;
+    const bool t = trans != 'N';
+    v.X = X;
+    v.sv = side_a ? (t ? ld : 1) : (t ? 1 : ld);
+    v.sl = side_a ? (t ? 1 : ld) : (t ? ld : 1);
+    v.nv = nv;
+    v.k = k;
+    v.cplx = cplx;
+    v.conj = cplx && trans == 'C';
+    v.side_a = side_a;
+    return v;
+}
+
 // Layout of the slices of one operand (see oz.h).
 struct SliceLayout {
     int64_t rows_pad;   // padded vector count (multiple of kRowPad)
@@ -129,6 +146,110 @@ hipError_t launch_residual(const CheckArgs& c, hipStream_t st);
 hipError_t launch_finalize(const double* acc, int64_t Mp, const int32_t* EA, const int32_t* FB, double* C,
                            int64_t ldc, int64_t m, int64_t n, int cplx, double ar, double ai, double br, double bi,
                            int beta_zero, hipStream_t st);
+// Many products: items of the weights (256 columns of op(B) per block), gemv
+// (256 terms) and rows (256 rows of op(A)) phases name the product (op) and
+// the block (bx); the norms phase runs one block per product.  Products whose
+// active flag is 0 are skipped.
+hipError_t launch_residual_batched(const CheckArgs* c, int64_t nprob, const int32_t* active, const BlockItem* wt_items,
+                                   int64_t n_wt, const BlockItem* gv_items, int64_t n_gv, const BlockItem* row_items,
+                                   int64_t n_row, hipStream_t st);
+struct FinalArgs {
+    const double* acc;
+    int64_t Mp;
+    const int32_t* EA;
+    const int32_t* FB;
+    double* C;
+    int64_t ldc, m, n;
+    int cplx;
+    double ar, ai, br, bi;
+    int beta_zero;
+};
+// items: (product, block of 256 rows); every block walks all columns
+hipError_t launch_finalize_batched(const FinalArgs* f, const BlockItem* items, int64_t nitems, hipStream_t st);
+
+// ---- slice-count selection ------------------------------------------------
+// Rule for the starting slice count of a tolerance-driven call: the
+// scale-weighted error of the emulation behaves like
+//   eps(s) ~ c (s + 1) 2^(-7s) sqrt((1/M_A + 1/M_B) / 3),
+// M = mean over vectors of the mean square of x * 2^-E (truncation leaves
+// about 2^-7s per scaled operand entry; the dropped pairs add a term growing
+// with s).  c = 2.5 covers the data families measured (0.7 .. 2.0).  The
+// smallest s in [1, smax] meeting tol (smax if none; 1 for a zero operand).
+constexpr double kRuleC = 2.5;
+__host__ __device__ inline int rule_slices_of(double ma, double mb, double tol, int smax) {
+    if (!(ma > 0.0) || !(mb > 0.0)) return 1;
+    const double spread = sqrt((1.0 / ma + 1.0 / mb) / 3.0);
+    int s = 1;
+    while (s < smax && kRuleC * (s + 1) * ldexp(1.0, -7 * s) * spread > tol) ++s;
+    return s;
+}
+
+// splitmix64 (Steele, Lea, Flood 2014): output number c (0-based) of the
+// stream seeded with key.
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+__host__ __device__ inline uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__host__ __device__ inline uint64_t sm64_draw(uint64_t key, uint64_t c) { return mix64(key + (c + 1) * kGamma); }
+
+// One operand of a synthetic selector instance (see oz.h, oz_gen_t).
+struct GenSide {
+    double* X;
+    int64_t rows, cols, ld;
+    uint64_t ekey, vkey;   // entry stream, vector-exponent stream
+    int vec_axis;          // 0: vectors are rows (A), 1: columns (B)
+    int sig_el, sig_vec, bits, family;
+    int64_t zero_q;
+};
+hipError_t launch_gen(const GenSide& g, hipStream_t st);
+
+// Exponent statistics of one operand: per-vector mean square of x 2^-E and
+// histograms of the gap g = E - exponent(x) and the width w = g + bit length
+// of the odd significand of x (both capped at kHistCap) over its non-zero
+// entries, plus the zero count.
+constexpr int kHistCap = 127;
+constexpr int kHistBins = kHistCap + 1;
+constexpr int kHistLen = 2 * kHistBins + 1;  // [g bins | w bins | zeros]
+struct StatSide {
+    OperandView op;
+    const uint64_t* maxbits;
+    double* msq;                 // nv
+    unsigned long long* hist;    // kHistLen, cleared by the caller
+};
+void stat_blocks(const OperandView& op, int64_t* blocks);
+hipError_t launch_stats(const StatSide& s, hipStream_t st);
+hipError_t launch_stats_batched(const StatSide* sides, const BlockItem* items, int64_t nitems, hipStream_t st);
+
+// The 16 selector features of one product (rows for ntol tolerances), the
+// rule's slice count per row, and (with an error table) the label per row.
+constexpr int kNumFeat = 16;
+struct FeatProb {
+    const double* msq[2];
+    const unsigned long long* hist[2];
+    int64_t nv[2];
+    int64_t m, n, k;
+    int cplx;
+    int ntol;
+    const double* tols;     // ntol
+    float* feat;            // ntol x kNumFeat
+    int32_t* s_rule;        // ntol (may be null)
+    int smax;
+    const double* eps;      // s_ref entries, eps of s = 1..s_ref (may be null)
+    int s_ref;
+    float* label;           // ntol (with eps)
+    double* mstat;          // 2: M_A, M_B (may be null)
+};
+hipError_t launch_features(const FeatProb* probs, int64_t nprob, hipStream_t st);
+
+// Error table of a labelled instance from the INT32 anti-diagonal sums of the
+// s_ref emulation (one chunk): eps_s = ||W o (C_s - C_ref)||_F / ||W o C_ref||_F.
+constexpr int kMaxRef = 18;
+hipError_t launch_eps_table(const int32_t* diag, int64_t Mp, int64_t Np, int s_ref, const int32_t* EA,
+                            const int32_t* FB, const uint64_t* maxa, const uint64_t* maxb, int64_t m, int64_t n,
+                            double* partial, double* eps, hipStream_t st);
+int64_t eps_partial_len(int64_t m, int64_t n);
 
 // C = beta*C for the alpha == 0 / k == 0 quick return.
 hipError_t launch_scale_c(double* C, int64_t ldc, int64_t m, int64_t n, int cplx, double br, double bi,

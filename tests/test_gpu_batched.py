@@ -172,3 +172,101 @@ def test_batched_argument_errors(oz, handle):
         args[key] = val
         assert oz.oz_zgemm_batched(handle, check=False, p=oz.prec(6), **args) == pos
     assert oz.oz_zgemm_batched(handle, check=False, p=oz.prec(9), **base) == 14
+
+
+def _tol_batch(oz, handle, stream, cplx, probs, p):
+    dev = []
+    for (ta, tb, A, B, C0, al, be) in probs:
+        dA, lda = to_dev(A, A.shape[0] + 1)
+        dB, ldb = to_dev(B)
+        dC, ldc = to_dev(C0)
+        dev.append((dA, lda, dB, ldb, dC, ldc))
+    torch.cuda.synchronize()
+    m = [(q[2].shape[0] if q[0] == "N" else q[2].shape[1]) for q in probs]
+    n = [(q[3].shape[1] if q[1] == "N" else q[3].shape[0]) for q in probs]
+    k = [(q[2].shape[1] if q[0] == "N" else q[2].shape[0]) for q in probs]
+    plan = oz.oz_gemm_batched_plan(handle, cplx, [q[0] for q in probs], [q[1] for q in probs], m, n, k,
+                                   [q[5] for q in probs], [d[0] for d in dev], [d[1] for d in dev],
+                                   [d[2] for d in dev], [d[3] for d in dev], [q[6] for q in probs],
+                                   [d[4] for d in dev], [d[5] for d in dev], p=p)
+    try:
+        oz.oz_batch_execute(plan)
+        stream.synchronize()
+        reps = oz.oz_batch_report(plan, len(probs))
+        with pytest.raises(oz.OzError):
+            oz.oz_batch_graph_launch(plan)
+    finally:
+        oz.oz_batch_destroy(plan)
+    got = [from_dev(d[4], m[i], n[i], d[5]) for i, d in enumerate(dev)]
+    return got, reps
+
+
+def _tol_probs(rng, cplx, shapes, beta_every=2):
+    probs = []
+    for i, (mm, nn, kk) in enumerate(shapes):
+        ta = "NTC"[i % 3] if cplx else "NT"[i % 2]
+        tb = "NCT"[(i // 2) % 3] if cplx else "TN"[i % 2]
+        A, B, C0 = make_problem(rng, cplx, mm, nn, kk, ta, tb)
+        al = complex(1.0, -0.5) if cplx else 1.5
+        be = (complex(0.25, 0.5) if cplx else -0.5) if i % beta_every == 1 else 0.0
+        probs.append((ta, tb, A, B, C0, al, be))
+    return probs
+
+
+def _check_tol_results(probs, got, reps, smax, tol, kc_s):
+    for i, (ta, tb, A, B, C0, al, be) in enumerate(probs):
+        r = reps[i]
+        s1, s0 = r.slices_used, r.slices_used - r.fallbacks
+        assert 1 <= s0 <= s1 <= smax, (i, s0, s1)
+        assert r.resid_est <= tol or s1 == smax, (i, r.resid_est)
+        want = oracle.emu_gemm(ta, tb, A, B, s0, alpha=al, beta=be, C=C0, s_to=s1,
+                               kc=oracle.kchunk(kc_s, np.iscomplexobj(A)))
+        assert np.array_equal(got[i], want), (i, ta, tb, A.shape, B.shape, s0, s1)
+
+
+@pytest.mark.parametrize("cplx", [0, 1])
+def test_batched_tolerance_rule_matches_oracle(oz, handle, stream, cplx):
+    rng = np.random.default_rng(30 + cplx)
+    shapes = [(70, 65, 33), (130, 70, 257), (64, 192, 64), (5, 300, 17), (96, 96, 96), (40, 30, 20), (1, 1, 1)]
+    probs = _tol_probs(rng, cplx, shapes)
+    tol = 1e-11
+    got, reps = _tol_batch(oz, handle, stream, cplx, probs, oz.prec(0, tol=tol, smax=12))
+    print("rule starts / finals:", [(r.slices_used - r.fallbacks, r.slices_used) for r in reps])
+    _check_tol_results(probs, got, reps, 12, tol, 12)
+
+
+@pytest.mark.parametrize("cplx", [0, 1])
+def test_batched_tolerance_growth_from_two(oz, handle, stream, cplx):
+    rng = np.random.default_rng(40 + cplx)
+    probs = _tol_probs(rng, cplx, [(48, 40, 56), (33, 90, 70), (128, 64, 40)])
+    got, reps = _tol_batch(oz, handle, stream, cplx, probs, oz.prec(0, tol=1e-9, smax=8, sstart=2))
+    assert all(r.slices_used - r.fallbacks == 2 and r.fallbacks >= 3 for r in reps)
+    _check_tol_results(probs, got, reps, 8, 1e-9, 8)
+
+
+def test_batched_tolerance_growth_past_eight(oz, handle, stream):
+    rng = np.random.default_rng(50)
+    probs = _tol_probs(rng, 0, [(40, 50, 60), (70, 20, 30)])
+    got, reps = _tol_batch(oz, handle, stream, 0, probs, oz.prec(0, tol=1e-300, smax=11, sstart=7))
+    assert all(r.slices_used == 11 and r.fallbacks == 4 for r in reps)
+    _check_tol_results(probs, got, reps, 11, 1e-300, 11)
+
+
+def test_batched_tolerance_learned_start(oz, handle, stream):
+    from oracle import mlp as omlp
+    P = {name: np.zeros(shape) for name, shape in omlp.SIZES}
+    P["b3"][0] = 4.5
+    net = oz.oz_mlp_create(handle, 0)
+    oz.oz_mlp_set_params(net, omlp.pack(P).astype(np.float32), np.zeros(16), np.ones(16))
+    rng = np.random.default_rng(60)
+    probs = _tol_probs(rng, 1, [(48, 40, 56), (96, 96, 96), (17, 130, 45)])
+    try:
+        with pytest.raises(oz.OzError):  # no selector attached yet
+            _tol_batch(oz, handle, stream, 1, probs, oz.prec(0, tol=1e-10, selector=1))
+        oz.oz_set_selector(handle, net)
+        got, reps = _tol_batch(oz, handle, stream, 1, probs, oz.prec(0, tol=1e-10, selector=1))
+        assert all(r.slices_used - r.fallbacks == 5 for r in reps)
+        _check_tol_results(probs, got, reps, 12, 1e-10, 12)
+    finally:
+        oz.oz_set_selector(handle, None)
+        oz.oz_mlp_destroy(net)
