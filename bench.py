@@ -162,9 +162,119 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_select(args):
+    """Gain of the learned slice-count selector.  Tolerance-driven batches of
+    512 square complex problems (n_b = 32 * randint(1, 16)) -- the batched
+    workload (N(0,1) entries) and a variant with a per-problem exponent spread
+    sigma ~ randint(0, 40) -- at tol 1e-10, 1e-12, 1e-14, each run four ways:
+    fixed: one slice count for all, the smallest at which every problem
+           passes (from the escalation run); a fixed plan, no check;
+    rule:  starting s from the operand statistics rule, check and growth;
+    escalate: every problem starts at s = 2, check and growth;
+    learned: starting s from the trained network, check and growth.
+    Time = whole execution on the stream (split, selection, GEMM rounds, checks,
+    scaling), median of --steps runs; error = scale-weighted error of every
+    problem against the native complex128 product."""
+    import torch
+
+    import paper_2503_22875_amd as oz
+    import workloads
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    h = oz.oz_create(0)
+    oz.oz_set_stream(h, stream.cuda_stream)
+    oz.oz_load_tuning(h)
+    if not os.path.exists(oz.SELECTOR_PATH):
+        raise SystemExit("no trained selector at %s (python -m paper_2503_22875_amd.train_selector)" %
+                         oz.SELECTOR_PATH)
+    net = oz.oz_mlp_load(h)
+    oz.oz_set_selector(h, net)
+    results = []
+    for dname in args.select_data.split(","):
+        problems = (workloads.zgemm_batch(512, seed=0) if dname == "normal"
+                    else workloads.zgemm_batch_spread(512, seed=0, sig_max=40))
+        cnt = len(problems)
+        ns = [A.shape[0] for A, _ in problems]
+        dev = [(torch.from_numpy(A.ravel(order="F")).cuda(), torch.from_numpy(B.ravel(order="F")).cuda(),
+                torch.zeros(A.shape[0] * B.shape[1], dtype=torch.complex128, device="cuda")) for A, B in problems]
+        del problems
+        flops = sum(8.0 * n ** 3 for n in ns)
+        # native products and scale weights for the error check
+        nat, wts = [], []
+        for (dA, dB, _), n in zip(dev, ns):
+            Ad = dA.view(n, n).t()  # column-major storage seen as a row-major transpose
+            Bd = dB.view(n, n).t()
+            nat.append(Ad @ Bd)
+            wa = torch.maximum(Ad.real.abs(), Ad.imag.abs()).amax(1)
+            wb = torch.maximum(Bd.real.abs(), Bd.imag.abs()).amax(0)
+            wts.append((1.0 / wa)[:, None] * (1.0 / wb)[None, :])
+        torch.cuda.synchronize()
+
+        def true_errors():
+            errs = []
+            for (_, _, dC), n, C0, W in zip(dev, ns, nat, wts):
+                C = dC.view(n, n).t()
+                errs.append(float(torch.linalg.norm(W * (C - C0)) / torch.linalg.norm(W * C0)))
+            return np.array(errs)
+
+        def run(p, fixed=False):
+            plan = oz.oz_gemm_batched_plan(h, 1, "N" * cnt, "N" * cnt, ns, ns, ns, [1.0] * cnt,
+                                           [d[0] for d in dev], ns, [d[1] for d in dev], ns, [0.0] * cnt,
+                                           [d[2] for d in dev], ns, p=p)
+            try:
+                for _ in range(args.warmup):
+                    oz.oz_batch_execute(plan)
+                stream.synchronize()
+                times = []
+                for _ in range(args.steps):
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    oz.oz_batch_execute(plan)
+                    e1.record(stream)
+                    stream.synchronize()
+                    times.append(e0.elapsed_time(e1))
+                reps = oz.oz_batch_report(plan, cnt)
+            finally:
+                oz.oz_batch_destroy(plan)
+            err = true_errors()
+            start = np.array([r.slices_used - r.fallbacks for r in reps])
+            final = np.array([r.slices_used for r in reps])
+            return float(np.median(times)), start, final, err, np.array([r.resid_est for r in reps])
+
+        for tol in [float(t) for t in args.select_tols.split(",")]:
+            row = {"data": dname, "tol": tol}
+            ms, st0, fin, err, est = run(oz.prec(0, tol=tol, smax=12, sstart=2))
+            s_fix = int(fin.max())
+            for name, p in (("escalate", None), ("rule", oz.prec(0, tol=tol, smax=12, selector=0)),
+                            ("learned", oz.prec(0, tol=tol, smax=12, selector=1)),
+                            ("fixed", oz.prec(s_fix) if s_fix <= 8 else oz.prec(0, tol=tol, smax=s_fix,
+                                                                                 sstart=s_fix))):
+                if p is not None:
+                    ms, st0, fin, err, est = run(p)
+                row[name] = {"ms": round(ms, 3), "tflops": round(flops / (ms * 1e-3) / 1e12, 2),
+                             "mean_start": round(float(st0.mean()), 3), "mean_final": round(float(fin.mean()), 3),
+                             "check_rounds": int((fin - st0).sum() + (cnt if name != "fixed" or s_fix > 8 else 0)),
+                             "pass_true": float(np.mean(err <= tol)), "worst_err": float(err.max())}
+                if name == "fixed":
+                    row[name]["s"] = s_fix
+            row["learned_speedup"] = {k: round(row[k]["ms"] / row["learned"]["ms"], 3)
+                                      for k in ("fixed", "rule", "escalate")}
+            print(json.dumps(row), flush=True)
+            results.append(row)
+        del dev, nat, wts
+        torch.cuda.empty_cache()
+    oz.oz_set_selector(h, None)
+    oz.oz_mlp_destroy(net)
+    oz.oz_destroy(h)
+    print(json.dumps({"workload": "selector gain", "rows": results}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="zgemm4096", choices=["zgemm4096", "batch512"])
+    ap.add_argument("--workload", default="zgemm4096", choices=["zgemm4096", "batch512", "select"])
+    ap.add_argument("--select-data", default="normal,spread")
+    ap.add_argument("--select-tols", default="1e-10,1e-12,1e-14")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
@@ -181,6 +291,8 @@ def main():
         sys.exit(2)
     if args.workload == "batch512":
         return bench_batch(args)
+    if args.workload == "select":
+        return bench_select(args)
 
     import torch
 

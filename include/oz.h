@@ -302,8 +302,9 @@ int oz_mlp_load(oz_handle_t handle, const char* path, oz_mlp_t* mlp);
  * network is not copied and must outlive its use. */
 int oz_set_selector(oz_handle_t handle, oz_mlp_t mlp);
 
-/* The learned starting slice count: s = clamp(ceil(y), 2, smax) (smax 0: 12)
- * for the network output y on the features of the product at tol.  Operand
+/* The learned starting slice count: s = clamp(floor(y + 1/2), 2, smax)
+ * (smax 0: 12) for the network output y on the features of the product at
+ * tol (y estimates an upper quantile of the smallest passing s).  Operand
  * arguments as oz_select_slices.  Synchronises the handle's stream. */
 int oz_predict_slices(oz_handle_t handle, char transa, char transb, int64_t m, int64_t n, int64_t k,
                       int is_complex, const double* A, int64_t lda, const double* B, int64_t ldb, double tol,
@@ -348,8 +349,8 @@ int oz_batch_destroy(oz_batch_t plan);
  * selector.  An execution then runs: the batched split with smax digit planes;
  * the starting s of every problem (sstart, or one batched statistics pass and
  * the rule or the handle's learned selector); raw sums at those s (problems
- * grouped by s, one persistent launch per group with s <= 8, the streaming
- * kernel per problem above); then rounds of a batched residual check over the
+ * grouped by s, one persistent launch per group: the all-diagonal kernel for
+ * s <= 8, the streaming kernel above); then rounds of a batched residual check over the
  * problems still open and one more slice (digit already split, next
  * anti-diagonal added last) for those whose estimate exceeds tol, until all
  * pass or reach smax; finally one batched scaling pass into C.  Each problem's

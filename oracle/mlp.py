@@ -86,5 +86,9 @@ def adam_step(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
 
 
 def predict_slices(y, smin=2, smax=12):
-    """Slice count from the network output: clamp(ceil(y), smin, smax)."""
-    return np.clip(np.ceil(y), smin, smax).astype(np.int64)
+    """Slice count from the network output, rounded half up and clamped:
+    clamp(floor(y + 1/2), smin, smax).  The pinball loss with tau near 1 puts
+    y at an upper quantile of the integer labels, so the nearest integer is
+    the prediction (a ceiling would add one slice whenever y lands just above
+    the label)."""
+    return np.clip(np.floor(np.asarray(y) + 0.5), smin, smax).astype(np.int64)

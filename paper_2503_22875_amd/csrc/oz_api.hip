@@ -289,8 +289,9 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
     if (e == hipSuccess) e = oz::launch_zero_u64(maxa, static_cast<int64_t>((p.off_ea - p.off_maxa) / 8), h->stream);
     if (e == hipSuccess) e = oz::launch_scan(va, maxa, h->stream);
     if (e == hipSuccess) e = oz::launch_scan(vb, maxb, h->stream);
-    if (e == hipSuccess) e = oz::launch_digits(va, maxa, p.la, EA, SA, h->stream);
-    if (e == hipSuccess) e = oz::launch_digits(vb, maxb, p.lb, FB, SB, h->stream);
+    // a tolerance-driven call splits its digit planes as the slice count is chosen and grown
+    if (e == hipSuccess && !tol_mode) e = oz::launch_digits(va, maxa, p.la, EA, SA, h->stream);
+    if (e == hipSuccess && !tol_mode) e = oz::launch_digits(vb, maxb, p.lb, FB, SB, h->stream);
     if (e != hipSuccess) return OZ_ERR_HIP;
 
     oz::GemmArgs g;
@@ -339,10 +340,14 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
             st = rule_slices(h, va, vb, maxa, maxb, msa, msb, tol, smax, &s);
             if (st) return st;
         }
-        // (2) emulate at s into the raw FP64 sums
+        // (2) digit planes 1..s, then emulate at s into the raw FP64 sums
+        if (oz::launch_digits(va, maxa, p.la, EA, SA, h->stream, 0, s) != hipSuccess ||
+            oz::launch_digits(vb, maxb, p.lb, FB, SB, h->stream, 0, s) != hipSuccess)
+            return OZ_ERR_HIP;
         g.acc = reinterpret_cast<double*>(ws + p.off_acc);
         g.s = s;
-        g.mode = oz::kRawWrite;
+        // with beta = 0 the first pass also writes C, rewritten only if s grows
+        g.mode = beta_zero ? oz::kRawWriteFinal : oz::kRawWrite;
         if (oz::launch_gemm(g, h->stream) != hipSuccess) return OZ_ERR_HIP;
         // (3) check; grow by one slice (new digit, new anti-diagonal) until it passes
         oz::CheckArgs c;
@@ -370,6 +375,10 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
                 return OZ_ERR_HIP;
             eps = nrm[1] > 0.0 ? std::sqrt(nrm[0] / nrm[1]) : std::sqrt(nrm[0]);
             if (!(eps > tol) || s >= smax) break;  // NaN (non-finite input) also stops
+            // digit plane s + 1, then the anti-diagonal s + 2
+            if (oz::launch_digits(va, maxa, p.la, EA, SA, h->stream, s, s + 1) != hipSuccess ||
+                oz::launch_digits(vb, maxb, p.lb, FB, SB, h->stream, s, s + 1) != hipSuccess)
+                return OZ_ERR_HIP;
             g.s = s + 1;
             g.top = 1;
             g.mode = oz::kRawAdd;
@@ -378,8 +387,9 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
             ++s;
             ++fallbacks;
         }
-        // (4) C = alpha * ldexp(acc, E + F) + beta * C
-        if (oz::launch_finalize(g.acc, p.la.rows_pad, EA, FB, C, ldc, m, n, cplx, ar, ai, br, bi, beta_zero ? 1 : 0,
+        // (4) C = alpha * ldexp(acc, E + F) + beta * C (unless the first pass wrote it)
+        if ((fallbacks > 0 || !beta_zero) &&
+            oz::launch_finalize(g.acc, p.la.rows_pad, EA, FB, C, ldc, m, n, cplx, ar, ai, br, bi, beta_zero ? 1 : 0,
                                 h->stream) != hipSuccess)
             return OZ_ERR_HIP;
         if (rep) {

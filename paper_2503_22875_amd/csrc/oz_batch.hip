@@ -70,6 +70,7 @@ struct oz_batch_s {
     size_t off_stat_sides, off_stat_items, off_hist, off_fp, off_feat, off_y, off_s, off_tols;
     int64_t n_stat_items, n_hist;
     size_t off_check, off_active, off_norms, off_wt, off_gv, off_row, off_final, off_final_items, off_dyn;
+    size_t off_prange;  // digit-plane range per operand of a split round
     int64_t n_wt, n_gv, n_row, n_final, dyn_cap;
     std::vector<int32_t> s_cur, fallbacks;
     std::vector<double> resid;
@@ -359,6 +360,7 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
         P->off_s = take(sizeof(int32_t) * nprob);
         P->off_tols = take(sizeof(double) * nprob);
         P->off_active = take(sizeof(int32_t) * nprob);
+        P->off_prange = take(sizeof(int32_t) * 4 * nprob);
     }
 
     // ---- split work lists -----------------------------------------------------
@@ -411,6 +413,8 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
         g.s = q.s;
         g.s_lay = q.s;
         g.cplx = cplx;
+        // tolerance-driven: raw sums for the check; with beta = 0 also C, which
+        // is then rewritten only for problems whose slice count grows
         g.mode = tol_mode ? oz::kRawWrite : oz::kFinal;
         g.acc = tol_mode ? reinterpret_cast<double*>(at(toff[i].acc)) : nullptr;
         g.C = C[q.b];
@@ -422,6 +426,7 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
         g.beta_r = beta[w * q.b];
         g.beta_i = cplx ? beta[w * q.b + 1] : 0.0;
         g.beta_zero = (g.beta_r == 0.0 && g.beta_i == 0.0) ? 1 : 0;
+        if (tol_mode && g.beta_zero) g.mode = oz::kRawWriteFinal;
     }
     std::vector<std::vector<oz::TileItem>> group_items;
     if (!tol_mode) {
@@ -512,8 +517,8 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
             checks.push_back(c);
             const int32_t pi = static_cast<int32_t>(i);
             for (int64_t x = 0; x < (nn + 255) / 256; ++x) wt_items.push_back({pi, static_cast<int32_t>(x), 0, 0});
-            for (int64_t x = 0; x < (kk + 255) / 256; ++x) gv_items.push_back({pi, static_cast<int32_t>(x), 0, 0});
-            for (int64_t x = 0; x < (mm + 255) / 256; ++x) row_items.push_back({pi, static_cast<int32_t>(x), 0, 0});
+            for (int64_t x = 0; x < (kk + 63) / 64; ++x) gv_items.push_back({pi, static_cast<int32_t>(x), 0, 0});
+            for (int64_t x = 0; x < (mm + 63) / 64; ++x) row_items.push_back({pi, static_cast<int32_t>(x), 0, 0});
             for (int64_t x = 0; x < (mm + 255) / 256; ++x) fin_items.push_back({pi, static_cast<int32_t>(x), 0, 0});
             const oz::GemmArgs& g = args[i];
             finals.push_back({g.acc, g.Mp, g.EA, g.FB, g.C, g.ldc, g.m, g.n, cplx, g.alpha_r, g.alpha_i, g.beta_r,
@@ -644,9 +649,9 @@ namespace {
 
 // One round of GEMM work of a tolerance-driven plan: every listed problem at
 // its current slice count, raw-write (first round) or only the new
-// anti-diagonal added to the raw sums (growth).  Problems are grouped by s;
-// s <= 8 runs as one persistent launch per group, larger s problem by problem
-// on the streaming kernel.
+// anti-diagonal added to the raw sums (growth).  Problems are grouped by s,
+// one persistent launch per group: the all-diagonal kernel for s <= 8, the
+// streaming kernel above.
 int tol_round(oz_batch_t P, const std::vector<size_t>& members, bool growth, hipStream_t st) {
     char* dev = static_cast<char*>(P->dev);
     const oz::GemmArgs* dargs =
@@ -661,20 +666,13 @@ int tol_round(oz_batch_t P, const std::vector<size_t>& members, bool growth, hip
         std::vector<size_t> mem;
         for (size_t i : members)
             if (P->s_cur[i] == sv) mem.push_back(i);
-        if (sv > oz::kMaxLiveSlices) {
-            for (size_t i : mem) {
-                oz::GemmArgs g = P->host_args[i];
-                g.s = sv;
-                g.top = growth ? 1 : 0;
-                g.mode = growth ? oz::kRawAdd : oz::kRawWrite;
-                g.tile = 3;
-                if (oz::launch_gemm(g, st) != hipSuccess) return OZ_ERR_HIP;
-            }
-            continue;
-        }
+        // above the all-diagonal kernel's register budget: the streaming body on 64 x 64 tiles
+        const bool stream = sv > oz::kMaxLiveSlices;
         Group gr;
         std::vector<oz::TileItem> items;
-        build_group(P->host_args, mem, sv, P->kernel, P->cplx, P->cus, oz_handle_tuning(P->h), &gr, &items);
+        build_group(P->host_args, mem, sv, stream ? 2 : P->kernel, P->cplx, P->cus, oz_handle_tuning(P->h), &gr,
+                    &items);
+        gr.tile = stream ? 3 : gr.tile;
         gr.off_items = all.size();
         all.insert(all.end(), items.begin(), items.end());
         groups.push_back(gr);
@@ -687,10 +685,14 @@ int tol_round(oz_batch_t P, const std::vector<size_t>& members, bool growth, hip
             hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
         return OZ_ERR_HIP;
-    for (const Group& gr : groups)
-        if (oz::launch_gemm_persistent(dargs, ditems + gr.off_items, gr.nitems, gr.s, gr.tile, gr.blocks, growth,
-                                       gr.multi, st) != hipSuccess)
-            return OZ_ERR_HIP;
+    for (const Group& gr : groups) {
+        const hipError_t e =
+            gr.tile == 3 ? oz::launch_gemm_stream_persistent(dargs, ditems + gr.off_items, gr.nitems, gr.s, growth,
+                                                             gr.blocks, st)
+                         : oz::launch_gemm_persistent(dargs, ditems + gr.off_items, gr.nitems, gr.s, gr.tile,
+                                                      gr.blocks, growth, gr.multi, st);
+        if (e != hipSuccess) return OZ_ERR_HIP;
+    }
     return OZ_OK;
 }
 
@@ -707,11 +709,19 @@ int execute_tol(oz_batch_t P) {
     const oz::SplitOp* ops = reinterpret_cast<const oz::SplitOp*>(dev + P->off_ops);
     if (e == hipSuccess)
         e = oz::launch_scan_batched(ops, reinterpret_cast<const oz::BlockItem*>(dev + P->off_scan), P->n_scan, st);
-    if (e == hipSuccess)
-        e = oz::launch_digits_batched(ops, reinterpret_cast<const oz::BlockItem*>(dev + P->off_digits), P->n_digits,
-                                      st);
     if (e != hipSuccess) return OZ_ERR_HIP;
     if (nprob == 0) return OZ_OK;
+    // digit planes [lo, hi) of both operands of every problem (2 ops per problem)
+    std::vector<int32_t> prange(4 * nprob, 0);
+    int32_t* dprange = reinterpret_cast<int32_t*>(dev + P->off_prange);
+    auto split_round = [&]() {
+        hipError_t r = hipMemcpyAsync(dprange, prange.data(), sizeof(int32_t) * prange.size(), hipMemcpyHostToDevice,
+                                      st);
+        if (r == hipSuccess)
+            r = oz::launch_digits_batched(ops, reinterpret_cast<const oz::BlockItem*>(dev + P->off_digits),
+                                          P->n_digits, st, dprange);
+        return r;
+    };
     // (1) starting slice counts
     std::vector<int32_t> s0(nprob, P->sstart);
     if (P->sstart == 0) {
@@ -741,8 +751,14 @@ int execute_tol(oz_batch_t P) {
         P->fallbacks[i] = 0;
         P->resid[i] = 0.0;
         members[i] = i;
+        for (int side = 0; side < 2; ++side) {
+            prange[4 * i + 2 * side] = 0;
+            prange[4 * i + 2 * side + 1] = s0[i];
+        }
     }
-    // (2) raw sums at the starting s
+    // (2) digit planes 1..s and raw sums at the starting s (the round waits
+    // for its uploads, so prange may change afterwards)
+    if (split_round() != hipSuccess) return OZ_ERR_HIP;
     int rc = tol_round(P, members, false, st);
     if (rc) return rc;
     // (3) check the active problems; grow the failing ones by one slice
@@ -777,12 +793,35 @@ int execute_tol(oz_batch_t P) {
             grow.push_back(i);
         }
         if (grow.empty()) break;
+        // the new digit plane of the growing problems only
+        std::fill(prange.begin(), prange.end(), 0);
+        for (size_t i : grow)
+            for (int side = 0; side < 2; ++side) {
+                prange[4 * i + 2 * side] = P->s_cur[i] - 1;
+                prange[4 * i + 2 * side + 1] = P->s_cur[i];
+            }
+        if (split_round() != hipSuccess) return OZ_ERR_HIP;
         rc = tol_round(P, grow, true, st);
         if (rc) return rc;
     }
-    // (4) C = alpha * ldexp(acc, E + F) + beta * C
-    e = oz::launch_finalize_batched(reinterpret_cast<const oz::FinalArgs*>(dev + P->off_final),
-                                    reinterpret_cast<const oz::BlockItem*>(dev + P->off_final_items), P->n_final, st);
+    // (4) C = alpha * ldexp(acc, E + F) + beta * C where the first pass did not
+    // write the final C (beta != 0) or the slice count grew since
+    bool any = false;
+    for (size_t i = 0; i < nprob; ++i) {
+        active[i] = (P->fallbacks[i] > 0 || P->host_args[i].mode != oz::kRawWriteFinal) ? 1 : 0;
+        any = any || active[i];
+    }
+    e = hipSuccess;
+    if (any) {
+        // the flags of the last check round may still be in use: the stream orders the copy after it
+        e = hipMemcpyAsync(dactive, active.data(), sizeof(int32_t) * nprob, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = oz::launch_finalize_batched(reinterpret_cast<const oz::FinalArgs*>(dev + P->off_final), dactive,
+                                            reinterpret_cast<const oz::BlockItem*>(dev + P->off_final_items),
+                                            P->n_final, st);
+        // the host flags must outlive the copy
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+    }
     for (size_t i = 0; i < nprob; ++i) P->slices[P->prob_b[i]] = P->s_cur[i];
     return e == hipSuccess ? OZ_OK : OZ_ERR_HIP;
 }

@@ -94,82 +94,113 @@ __device__ __forceinline__ void weights_body(const CheckArgs& c, int64_t j) {
 }
 
 // ---- u = op(B) t in double-double; u[l] = (re.hi, re.lo, im.hi, im.lo) ------
-__device__ __forceinline__ void gemv_b_body(const CheckArgs& c, int64_t l) {
+// Block: 64 terms (lanes) x 4 parts (waves); part w sums the columns
+// j = w, w + 4, ...; the four partial sums are added in part order.
+__device__ __forceinline__ dd dd_add(dd a, dd b) {
+    const dd s = two_sum(a.hi, b.hi);
+    return {s.hi, s.lo + (a.lo + b.lo)};
+}
+constexpr int kParts = 4;
+constexpr int kLanes = 64;
+
+__device__ __forceinline__ void gemv_b_body(const CheckArgs& c, int64_t lb) {
+    __shared__ dd red[kParts][2][kLanes];
     const OperandView& opb = c.opb;
-    const double* t = c.t;
-    double* u = c.u;
-    if (l >= opb.k) return;
+    const int lane = threadIdx.x & 63, part = threadIdx.x >> 6;
+    const int64_t l = lb * kLanes + lane;
     dd sr = {0.0, 0.0}, si = {0.0, 0.0};
-    for (int64_t j = 0; j < opb.nv; ++j) {
-        double re, im;
-        load_elem(opb, j, l, re, im);
-        sr = dd_add_prod(sr, re, t[j]);
-        si = dd_add_prod(si, im, t[j]);
+    if (l < opb.k) {
+        for (int64_t j = part; j < opb.nv; j += kParts) {
+            double re, im;
+            load_elem(opb, j, l, re, im);
+            const double tj = c.t[j];
+            sr = dd_add_prod(sr, re, tj);
+            si = dd_add_prod(si, im, tj);
+        }
+    }
+    red[part][0][lane] = sr;
+    red[part][1][lane] = si;
+    __syncthreads();
+    if (part != 0 || l >= opb.k) return;
+    for (int q = 1; q < kParts; ++q) {
+        sr = dd_add(sr, red[q][0][lane]);
+        si = dd_add(si, red[q][1][lane]);
     }
     sr = dd_norm(sr);
     si = dd_norm(si);
-    u[4 * l] = sr.hi;
-    u[4 * l + 1] = sr.lo;
-    u[4 * l + 2] = si.hi;
-    u[4 * l + 3] = si.lo;
+    c.u[4 * l] = sr.hi;
+    c.u[4 * l + 1] = sr.lo;
+    c.u[4 * l + 2] = si.hi;
+    c.u[4 * l + 3] = si.lo;
 }
 
 // ---- per row i of op(A): y2 = w_i op(A)_i: u, y1 = w_i sum_j C_emu_ij t_j ----
 // Writes diff[i] = y1 - y2 and ref[i] = y2 (real, or real and imaginary parts
-// at 2i, 2i+1 for complex).
-__device__ __forceinline__ void rows_body(const CheckArgs& c, int64_t i) {
+// at 2i, 2i+1 for complex).  Block: 64 rows (lanes) x 4 parts (waves); part w
+// takes the terms l = w, w + 4, ... and the columns j = w, w + 4, ...; the
+// partial sums are added in part order.
+__device__ __forceinline__ void rows_body(const CheckArgs& c, int64_t rb) {
+    __shared__ dd red[kParts][4][kLanes];
     const OperandView& opa = c.opa;
-    const uint64_t* maxbits_a = c.maxa;
-    const double* u = c.u;
-    const double* acc = c.acc;
+    const int lane = threadIdx.x & 63, part = threadIdx.x >> 6;
+    const int64_t i = rb * kLanes + lane;
     const int64_t Mp = c.Mp, n = c.opb.nv;
-    const int32_t* EA = c.EA;
-    const int32_t* FB = c.FB;
-    const double* t = c.t;
-    double* diff = c.diff;
-    double* ref = c.ref;
-    if (i >= opa.nv) return;
-    const double mx = max_of_bits(maxbits_a[i]);
-    const double w = mx > 0.0 ? 1.0 / mx : 0.0;
-    // y2 = a_i . u  (complex: (ar + i ai)(ur + i ui))
-    dd y2r = {0.0, 0.0}, y2i = {0.0, 0.0};
-    for (int64_t l = 0; l < opa.k; ++l) {
-        double ar, ai;
-        load_elem(opa, i, l, ar, ai);
-        const double urh = u[4 * l], url = u[4 * l + 1], uih = u[4 * l + 2], uil = u[4 * l + 3];
-        y2r = dd_add_prod(y2r, ar, urh);
-        y2r = dd_add_prod(y2r, ar, url);
-        if (opa.cplx) {
-            y2r = dd_add_prod(y2r, -ai, uih);
-            y2r = dd_add_prod(y2r, -ai, uil);
-            y2i = dd_add_prod(y2i, ar, uih);
-            y2i = dd_add_prod(y2i, ar, uil);
-            y2i = dd_add_prod(y2i, ai, urh);
-            y2i = dd_add_prod(y2i, ai, url);
+    const double* u = c.u;
+    dd y2r = {0.0, 0.0}, y2i = {0.0, 0.0}, y1r = {0.0, 0.0}, y1i = {0.0, 0.0};
+    if (i < opa.nv) {
+        // y2 = a_i . u  (complex: (ar + i ai)(ur + i ui))
+        for (int64_t l = part; l < opa.k; l += kParts) {
+            double ar, ai;
+            load_elem(opa, i, l, ar, ai);
+            const double urh = u[4 * l], url = u[4 * l + 1], uih = u[4 * l + 2], uil = u[4 * l + 3];
+            y2r = dd_add_prod(y2r, ar, urh);
+            y2r = dd_add_prod(y2r, ar, url);
+            if (opa.cplx) {
+                y2r = dd_add_prod(y2r, -ai, uih);
+                y2r = dd_add_prod(y2r, -ai, uil);
+                y2i = dd_add_prod(y2i, ar, uih);
+                y2i = dd_add_prod(y2i, ar, uil);
+                y2i = dd_add_prod(y2i, ai, urh);
+                y2i = dd_add_prod(y2i, ai, url);
+            }
+        }
+        // y1 = sum_j ldexp(acc_ij, E_i + F_j) t_j over the slice-row(s) of row i
+        const int64_t r_re = opa.cplx ? 32 * (i >> 4) + 16 * ((i >> 3) & 1) + (i & 7) : i;
+        const int64_t r_im = r_re + 8;
+        const int32_t e = c.EA[i];
+        for (int64_t j = part; j < n; j += kParts) {
+            const int ef = e + c.FB[j];
+            const double tj = c.t[j];
+            y1r = dd_add_prod(y1r, ldexp(c.acc[j * Mp + r_re], ef), tj);
+            if (opa.cplx) y1i = dd_add_prod(y1i, ldexp(c.acc[j * Mp + r_im], ef), tj);
         }
     }
-    // y1 = sum_j ldexp(acc_ij, E_i + F_j) t_j over the slice-row(s) of row i
-    const int64_t r_re = opa.cplx ? 32 * (i >> 4) + 16 * ((i >> 3) & 1) + (i & 7) : i;
-    const int64_t r_im = r_re + 8;
-    dd y1r = {0.0, 0.0}, y1i = {0.0, 0.0};
-    const int32_t e = EA[i];
-    for (int64_t j = 0; j < n; ++j) {
-        const int ef = e + FB[j];
-        y1r = dd_add_prod(y1r, ldexp(acc[j * Mp + r_re], ef), t[j]);
-        if (opa.cplx) y1i = dd_add_prod(y1i, ldexp(acc[j * Mp + r_im], ef), t[j]);
+    red[part][0][lane] = y1r;
+    red[part][1][lane] = y1i;
+    red[part][2][lane] = y2r;
+    red[part][3][lane] = y2i;
+    __syncthreads();
+    if (part != 0 || i >= opa.nv) return;
+    for (int q = 1; q < kParts; ++q) {
+        y1r = dd_add(y1r, red[q][0][lane]);
+        y1i = dd_add(y1i, red[q][1][lane]);
+        y2r = dd_add(y2r, red[q][2][lane]);
+        y2i = dd_add(y2i, red[q][3][lane]);
     }
+    const double mx = max_of_bits(c.maxa[i]);
+    const double w = mx > 0.0 ? 1.0 / mx : 0.0;
     y1r = dd_mul_d(dd_norm(y1r), w);
     y2r = dd_mul_d(dd_norm(y2r), w);
     if (!opa.cplx) {
-        diff[i] = dd_sub_to_d(y1r, y2r);
-        ref[i] = y2r.hi + y2r.lo;
+        c.diff[i] = dd_sub_to_d(y1r, y2r);
+        c.ref[i] = y2r.hi + y2r.lo;
     } else {
         y1i = dd_mul_d(dd_norm(y1i), w);
         y2i = dd_mul_d(dd_norm(y2i), w);
-        diff[2 * i] = dd_sub_to_d(y1r, y2r);
-        diff[2 * i + 1] = dd_sub_to_d(y1i, y2i);
-        ref[2 * i] = y2r.hi + y2r.lo;
-        ref[2 * i + 1] = y2i.hi + y2i.lo;
+        c.diff[2 * i] = dd_sub_to_d(y1r, y2r);
+        c.diff[2 * i + 1] = dd_sub_to_d(y1i, y2i);
+        c.ref[2 * i] = y2r.hi + y2r.lo;
+        c.ref[2 * i + 1] = y2i.hi + y2i.lo;
     }
 }
 
@@ -241,8 +272,8 @@ __device__ __forceinline__ void finalize_body(const double* acc, int64_t Mp, con
 
 // ---- kernels: one product -------------------------------------------------------
 __global__ void weights_kernel(CheckArgs c) { weights_body(c, static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x); }
-__global__ void gemv_b_kernel(CheckArgs c) { gemv_b_body(c, static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x); }
-__global__ void rows_kernel(CheckArgs c) { rows_body(c, static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x); }
+__global__ __launch_bounds__(256) void gemv_b_kernel(CheckArgs c) { gemv_b_body(c, blockIdx.x); }
+__global__ __launch_bounds__(256) void rows_kernel(CheckArgs c) { rows_body(c, blockIdx.x); }
 __global__ __launch_bounds__(256) void norms_kernel(const double* diff, const double* ref, int64_t len,
                                                     double* out) {
     norms_body(diff, ref, len, out);
@@ -261,23 +292,26 @@ __global__ void weights_batched_kernel(const CheckArgs* c, const int32_t* active
     if (!active[it.op]) return;
     weights_body(c[it.op], static_cast<int64_t>(it.bx) * 256 + threadIdx.x);
 }
-__global__ void gemv_b_batched_kernel(const CheckArgs* c, const int32_t* active, const BlockItem* items) {
+__global__ __launch_bounds__(256) void gemv_b_batched_kernel(const CheckArgs* c, const int32_t* active,
+                                                             const BlockItem* items) {
     const BlockItem it = items[blockIdx.x];
-    if (!active[it.op]) return;
-    gemv_b_body(c[it.op], static_cast<int64_t>(it.bx) * 256 + threadIdx.x);
+    if (!active[it.op]) return;  // uniform over the block
+    gemv_b_body(c[it.op], it.bx);
 }
-__global__ void rows_batched_kernel(const CheckArgs* c, const int32_t* active, const BlockItem* items) {
+__global__ __launch_bounds__(256) void rows_batched_kernel(const CheckArgs* c, const int32_t* active,
+                                                           const BlockItem* items) {
     const BlockItem it = items[blockIdx.x];
-    if (!active[it.op]) return;
-    rows_body(c[it.op], static_cast<int64_t>(it.bx) * 256 + threadIdx.x);
+    if (!active[it.op]) return;  // uniform over the block
+    rows_body(c[it.op], it.bx);
 }
 __global__ __launch_bounds__(256) void norms_batched_kernel(const CheckArgs* c, const int32_t* active) {
     const int p = blockIdx.x;
     if (!active[p]) return;
     norms_body(c[p].diff, c[p].ref, c[p].opa.cplx ? 2 * c[p].opa.nv : c[p].opa.nv, c[p].norms);
 }
-__global__ void finalize_batched_kernel(const FinalArgs* f, const BlockItem* items) {
+__global__ void finalize_batched_kernel(const FinalArgs* f, const int32_t* active, const BlockItem* items) {
     const BlockItem it = items[blockIdx.x];
+    if (!active[it.op]) return;
     const FinalArgs& a = f[it.op];
     finalize_body(a.acc, a.Mp, a.EA, a.FB, a.C, a.ldc, a.m, a.n, a.cplx, a.ar, a.ai, a.br, a.bi, a.beta_zero,
                   static_cast<int64_t>(it.bx) * 256 + threadIdx.x, 0, 1);
@@ -296,8 +330,8 @@ hipError_t launch_residual(const CheckArgs& c, hipStream_t st) {
     const int64_t n = c.opb.nv, k = c.opa.k, m = c.opa.nv;
     if (m <= 0 || n <= 0) return hipSuccess;
     hipLaunchKernelGGL(weights_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, c);
-    if (k > 0) hipLaunchKernelGGL(gemv_b_kernel, dim3(static_cast<unsigned>((k + 255) / 256)), dim3(256), 0, st, c);
-    hipLaunchKernelGGL(rows_kernel, dim3(static_cast<unsigned>((m + 255) / 256)), dim3(256), 0, st, c);
+    if (k > 0) hipLaunchKernelGGL(gemv_b_kernel, dim3(static_cast<unsigned>((k + 63) / 64)), dim3(256), 0, st, c);
+    hipLaunchKernelGGL(rows_kernel, dim3(static_cast<unsigned>((m + 63) / 64)), dim3(256), 0, st, c);
     const int64_t len = c.opa.cplx ? 2 * m : m;
     hipLaunchKernelGGL(norms_kernel, dim3(1), dim3(256), 0, st, c.diff, c.ref, len, c.norms);
     return hipGetLastError();
@@ -330,9 +364,11 @@ hipError_t launch_residual_batched(const CheckArgs* c, int64_t nprob, const int3
     return hipGetLastError();
 }
 
-hipError_t launch_finalize_batched(const FinalArgs* f, const BlockItem* items, int64_t nitems, hipStream_t st) {
+hipError_t launch_finalize_batched(const FinalArgs* f, const int32_t* active, const BlockItem* items, int64_t nitems,
+                                   hipStream_t st) {
     if (nitems <= 0) return hipSuccess;
-    hipLaunchKernelGGL(finalize_batched_kernel, dim3(static_cast<unsigned>(nitems)), dim3(256), 0, st, f, items);
+    hipLaunchKernelGGL(finalize_batched_kernel, dim3(static_cast<unsigned>(nitems)), dim3(256), 0, st, f, active,
+                       items);
     return hipGetLastError();
 }
 

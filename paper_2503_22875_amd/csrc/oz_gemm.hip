@@ -95,7 +95,7 @@ __device__ __forceinline__ void store_tile(const GemmArgs& g, const double (&acc
         // raw tile sums in C' space (every padded row and column is stored)
 #pragma unroll
         for (int r = 0; r < 16; ++r) g.acc[col * g.Mp + row0 + 8 * (r >> 2) + 4 * half + (r & 3)] = acc64[r];
-        return;
+        if (g.mode != kRawWriteFinal) return;
     }
     if (col >= g.n) return;
     const int32_t f = g.FB[col];
@@ -327,14 +327,12 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64 * WMW * WNW, 64 * WMW *
 // FP64 tile -- the same order as the all-diagonal kernel, hence the same bits.
 // 64 x 64 block tile, 4 waves.
 template <bool DIAG>
-__global__ __attribute__((amdgpu_flat_work_group_size(256, 256))) void gemm_stream_kernel(GemmArgs g) {
-    __shared__ v4i lds[2][256];  // [A: h*64 + row | B: 128 + h*64 + col]
+__device__ __forceinline__ void stream_body(const GemmArgs& g, int s, int top, int64_t tm, int64_t tn,
+                                            v4i (*lds)[256]) {
+    // lds: [A: h*64 + row | B: 128 + h*64 + col]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int half = lane >> 5, row = lane & 31;
-    const int s = g.s;
-    int64_t tm, tn;
-    tile_of_block(blockIdx.x, g.Mp / 64, g.Np / 64, tm, tn);
     const v4i* SA = reinterpret_cast<const v4i*>(g.SA);
     const v4i* SB = reinterpret_cast<const v4i*>(g.SB);
     const int64_t nsteps = g.kpad / kStep;
@@ -354,7 +352,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(256, 256))) void gemm_stre
     for (int r = 0; r < 16; ++r)
         acc64[r] = (g.mode == kRawAdd) ? g.acc[col * g.Mp + row0 + 8 * (r >> 2) + 4 * half + (r & 3)] : 0.0;
     const int64_t nchunks = (nsteps + g.chunk_steps - 1) / g.chunk_steps;
-    const int dmin = g.top ? s + 1 : 2;
+    const int dmin = top ? s + 1 : 2;
     for (int64_t c = 0; c < nchunks; ++c) {
         const int64_t k0 = c * g.chunk_steps;
         const int64_t k1 = (k0 + g.chunk_steps < nsteps) ? k0 + g.chunk_steps : nsteps;
@@ -395,6 +393,27 @@ __global__ __attribute__((amdgpu_flat_work_group_size(256, 256))) void gemm_stre
     }
     if constexpr (DIAG) return;
     store_tile(g, acc64, row0, half, col);
+}
+
+template <bool DIAG>
+__global__ __attribute__((amdgpu_flat_work_group_size(256, 256))) void gemm_stream_kernel(GemmArgs g) {
+    __shared__ v4i lds[2][256];
+    int64_t tm, tn;
+    tile_of_block(blockIdx.x, g.Mp / 64, g.Np / 64, tm, tn);
+    stream_body<DIAG>(g, g.s, g.top, tm, tn, lds);
+}
+
+// Batched streaming form: a persistent grid walking 64 x 64 tiles of many
+// problems, all at slice count s (top: only the anti-diagonal s + 1).
+__global__ __attribute__((amdgpu_flat_work_group_size(256, 256))) void gemm_stream_persistent_kernel(
+    const GemmArgs* __restrict__ probs, const TileItem* __restrict__ items, int64_t nitems, int s, int top) {
+    __shared__ v4i lds[2][256];
+    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const TileItem ti = items[it];
+        if (ti.prob < 0) continue;  // padding item (uniform over the block)
+        stream_body<false>(probs[ti.prob], s, top, ti.tm, ti.tn, lds);
+        __syncthreads();
+    }
 }
 
 __global__ void scale_c_kernel(double* C, int64_t ldc, int64_t m, int64_t n, int cplx, double br, double bi,
@@ -518,6 +537,15 @@ hipError_t launch_gemm_persistent(const GemmArgs* probs, const TileItem* items, 
         case 8: return launch_persistent_s<8>(probs, items, nitems, blocks, tile, top, multi, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_gemm_stream_persistent(const GemmArgs* probs, const TileItem* items, int64_t nitems, int s,
+                                         bool top, int blocks, hipStream_t st) {
+    if (nitems <= 0) return hipSuccess;
+    if (blocks <= 0 || s < 1 || s > 18) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(gemm_stream_persistent_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, probs,
+                       items, nitems, s, top ? 1 : 0);
+    return hipGetLastError();
 }
 
 hipError_t launch_scale_c(double* C, int64_t ldc, int64_t m, int64_t n, int cplx, double br, double bi,

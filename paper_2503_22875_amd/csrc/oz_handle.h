@@ -42,6 +42,6 @@ int oz_learned_start(oz_handle_t h, oz_mlp_t mlp, const oz::OperandView& va, con
 
 // selector network (oz_mlp.hip)
 bool oz_mlp_valid(oz_mlp_t p);
-// y = network(X) for rows feature rows, then s = clamp(ceil(y), smin, smax)
+// y = network(X) for rows feature rows, then s = clamp(floor(y + 1/2), smin, smax)
 hipError_t oz_mlp_predict_device(oz_mlp_t p, int64_t rows, const float* X, float* y, int smin, int smax,
                                  int32_t* s_out, hipStream_t st);

@@ -61,8 +61,10 @@ SliceLayout slice_layout(int side_a, int cplx, int64_t nv, int64_t k, int s);
 // Split: per-vector max magnitude bits (uint64) -> exponent + digits.
 hipError_t launch_zero_u64(uint64_t* p, int64_t n, hipStream_t st);
 hipError_t launch_scan(const OperandView& op, uint64_t* maxbits, hipStream_t st);
+// Digit planes p_lo .. p_hi - 1 (0-based; p_hi < 0: all planes of the layout).
+// The scale exponents E are written by every call.
 hipError_t launch_digits(const OperandView& op, const uint64_t* maxbits, const SliceLayout& lay,
-                         int32_t* E, int8_t* slices, hipStream_t st);
+                         int32_t* E, int8_t* slices, hipStream_t st, int p_lo = 0, int p_hi = -1);
 
 // Batched split: one block per item; an item names its operand and the block
 // coordinates the one-operand launch would have used.
@@ -82,7 +84,10 @@ struct BlockItem {
 void scan_blocks(const OperandView& op, int64_t* bx, int64_t* by);
 void digits_blocks(const OperandView& op, const SliceLayout& lay, int64_t* bx, int64_t* by);
 hipError_t launch_scan_batched(const SplitOp* ops, const BlockItem* items, int64_t nitems, hipStream_t st);
-hipError_t launch_digits_batched(const SplitOp* ops, const BlockItem* items, int64_t nitems, hipStream_t st);
+// prange (device, 2 ints per operand, may be null = all planes): digit planes
+// [prange[2 op], prange[2 op + 1]) of operand op; an empty range skips it.
+hipError_t launch_digits_batched(const SplitOp* ops, const BlockItem* items, int64_t nitems, hipStream_t st,
+                                 const int32_t* prange = nullptr);
 
 // GEMM over slice buffers with fused FP64 epilogue.
 struct GemmArgs {
@@ -110,8 +115,10 @@ struct GemmArgs {
 };
 // Epilogue modes: kFinal writes alpha*ldexp(acc, E+F) + beta*C into C; kRawWrite
 // stores the FP64 tile sum acc (before ldexp) into g.acc; kRawAdd adds the new
-// anti-diagonal terms onto the acc already in g.acc (chunk by chunk).
-constexpr int kFinal = 0, kRawWrite = 1, kRawAdd = 2;
+// anti-diagonal terms onto the acc already in g.acc (chunk by chunk);
+// kRawWriteFinal does both kRawWrite and kFinal (for beta = 0, where C can be
+// rewritten from acc if the slice count grows).
+constexpr int kFinal = 0, kRawWrite = 1, kRawAdd = 2, kRawWriteFinal = 3;
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t st);
 
 // Batched products: one persistent launch over a list of tiles of many
@@ -124,6 +131,9 @@ struct TileItem {
 };
 hipError_t launch_gemm_persistent(const GemmArgs* probs, const TileItem* items, int64_t nitems, int s, int tile,
                                   int blocks, bool top, bool multi, hipStream_t st);
+// Same for any s with the per-diagonal streaming body (64 x 64 tiles).
+hipError_t launch_gemm_stream_persistent(const GemmArgs* probs, const TileItem* items, int64_t nitems, int s,
+                                         bool top, int blocks, hipStream_t st);
 
 // Tolerance-driven calls: operand statistics, residual check, final scaling.
 hipError_t launch_vec_stats(const OperandView& op, const uint64_t* maxbits, double* ms, hipStream_t st);
@@ -147,8 +157,8 @@ hipError_t launch_finalize(const double* acc, int64_t Mp, const int32_t* EA, con
                            int64_t ldc, int64_t m, int64_t n, int cplx, double ar, double ai, double br, double bi,
                            int beta_zero, hipStream_t st);
 // Many products: items of the weights (256 columns of op(B) per block), gemv
-// (256 terms) and rows (256 rows of op(A)) phases name the product (op) and
-// the block (bx); the norms phase runs one block per product.  Products whose
+// (64 terms) and rows (64 rows of op(A)) phases name the product (op) and the
+// block (bx); the norms phase runs one block per product.  Products whose
 // active flag is 0 are skipped.
 hipError_t launch_residual_batched(const CheckArgs* c, int64_t nprob, const int32_t* active, const BlockItem* wt_items,
                                    int64_t n_wt, const BlockItem* gv_items, int64_t n_gv, const BlockItem* row_items,
@@ -164,8 +174,10 @@ struct FinalArgs {
     double ar, ai, br, bi;
     int beta_zero;
 };
-// items: (product, block of 256 rows); every block walks all columns
-hipError_t launch_finalize_batched(const FinalArgs* f, const BlockItem* items, int64_t nitems, hipStream_t st);
+// items: (product, block of 256 rows); every block walks all columns; products
+// whose flag is 0 are skipped
+hipError_t launch_finalize_batched(const FinalArgs* f, const int32_t* active, const BlockItem* items, int64_t nitems,
+                                   hipStream_t st);
 
 // ---- slice-count selection ------------------------------------------------
 // Rule for the starting slice count of a tolerance-driven call: the

@@ -194,7 +194,7 @@ __global__ void slices_from_output_kernel(const float* y, int64_t rows, int smin
     const float v = y[r];
     int q = smax;
     if (v == v) {  // NaN keeps smax
-        const float c = ceilf(v);
+        const float c = floorf(v + 0.5f);
         q = c < static_cast<float>(smin) ? smin : (c > static_cast<float>(smax) ? smax : static_cast<int>(c));
     }
     s[r] = q;

@@ -148,7 +148,7 @@ __device__ __forceinline__ uint64_t pack8(const int* d) {
 // 8 real elements, or 4 complex elements (terms 2l, 2l+1).
 template <bool LCONTIG, bool CPLX, bool SIDE_A>
 __device__ __forceinline__ void digits_body(const OperandView& op, const uint64_t* maxbits, const SliceLayout& lay,
-                                            int32_t* E, int8_t* slices, int64_t bx, int64_t by) {
+                                            int32_t* E, int8_t* slices, int64_t bx, int64_t by, int p_lo, int p_hi) {
     const int tid = threadIdx.x;
     const int vi = LCONTIG ? (tid >> 2) : (tid & 63);
     const int sub = LCONTIG ? (tid & 3) : (tid >> 6);
@@ -191,7 +191,7 @@ __device__ __forceinline__ void digits_body(const OperandView& op, const uint64_
         const int64_t r_re = 32 * (v >> 4) + 16 * ((v >> 3) & 1) + (v & 7);
         const int64_t r_im = r_re + 8;
         if (r_re >= lay.rows_pad) return;
-        for (int p = 0; p < lay.s; ++p) {
+        for (int p = p_lo; p < p_hi; ++p) {
             int dre[8], dim[8];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
@@ -206,7 +206,7 @@ __device__ __forceinline__ void digits_body(const OperandView& op, const uint64_
         }
     } else {
         if (v >= lay.rows_pad) return;
-        for (int p = 0; p < lay.s; ++p) {
+        for (int p = p_lo; p < p_hi; ++p) {
             int d[8];
 #pragma unroll
             for (int e = 0; e < 8; ++e) d[e] = digit(g[e], p + 1);
@@ -217,8 +217,8 @@ __device__ __forceinline__ void digits_body(const OperandView& op, const uint64_
 
 template <bool LCONTIG, bool CPLX, bool SIDE_A>
 __global__ __launch_bounds__(256) void digits_kernel(OperandView op, const uint64_t* maxbits, SliceLayout lay,
-                                                     int32_t* E, int8_t* slices) {
-    digits_body<LCONTIG, CPLX, SIDE_A>(op, maxbits, lay, E, slices, blockIdx.x, blockIdx.y);
+                                                     int32_t* E, int8_t* slices, int p_lo, int p_hi) {
+    digits_body<LCONTIG, CPLX, SIDE_A>(op, maxbits, lay, E, slices, blockIdx.x, blockIdx.y, p_lo, p_hi);
 }
 
 // Batched forms: block b runs item b of a list naming the operand and the
@@ -235,11 +235,14 @@ __global__ __launch_bounds__(256) void scan_batched_kernel(const SplitOp* __rest
 }
 
 __global__ __launch_bounds__(256) void digits_batched_kernel(const SplitOp* __restrict__ ops,
-                                                             const BlockItem* __restrict__ items) {
+                                                             const BlockItem* __restrict__ items,
+                                                             const int32_t* __restrict__ prange) {
     const BlockItem it = items[blockIdx.x];
     const SplitOp& o = ops[it.op];
+    const int p_lo = prange ? prange[2 * it.op] : 0, p_hi = prange ? prange[2 * it.op + 1] : o.lay.s;
+    if (p_lo >= p_hi) return;  // nothing to split for this operand (uniform over the block)
     const bool lc = o.op.sl == 1, two_row = o.op.cplx && o.op.side_a;
-#define OZ_DB(LC, CP, SA) digits_body<LC, CP, SA>(o.op, o.maxbits, o.lay, o.E, o.slices, it.bx, it.by)
+#define OZ_DB(LC, CP, SA) digits_body<LC, CP, SA>(o.op, o.maxbits, o.lay, o.E, o.slices, it.bx, it.by, p_lo, p_hi)
     if (lc) {
         if (two_row) OZ_DB(true, true, true);
         else if (o.op.cplx) OZ_DB(true, true, false);
@@ -285,9 +288,11 @@ hipError_t launch_scan_batched(const SplitOp* ops, const BlockItem* items, int64
     return hipGetLastError();
 }
 
-hipError_t launch_digits_batched(const SplitOp* ops, const BlockItem* items, int64_t nitems, hipStream_t st) {
+hipError_t launch_digits_batched(const SplitOp* ops, const BlockItem* items, int64_t nitems, hipStream_t st,
+                                 const int32_t* prange) {
     if (nitems <= 0) return hipSuccess;
-    hipLaunchKernelGGL(digits_batched_kernel, dim3(static_cast<unsigned>(nitems)), dim3(256), 0, st, ops, items);
+    hipLaunchKernelGGL(digits_batched_kernel, dim3(static_cast<unsigned>(nitems)), dim3(256), 0, st, ops, items,
+                       prange);
     return hipGetLastError();
 }
 
@@ -313,14 +318,16 @@ hipError_t launch_scan(const OperandView& op, uint64_t* maxbits, hipStream_t st)
 }
 
 hipError_t launch_digits(const OperandView& op, const uint64_t* maxbits, const SliceLayout& lay, int32_t* E,
-                         int8_t* slices, hipStream_t st) {
+                         int8_t* slices, hipStream_t st, int p_lo, int p_hi) {
+    if (p_hi < 0) p_hi = lay.s;
+    if (p_lo < 0 || p_hi > lay.s || p_lo >= p_hi) return p_lo == p_hi ? hipSuccess : hipErrorInvalidValue;
     const bool lcontig = op.sl == 1;
     const bool two_row = op.cplx && op.side_a;
     // blocks along vectors: 64 vectors each (64 complex rows = 128 slice rows for two_row)
     const int64_t vec_cover = two_row ? lay.rows_pad / 2 : lay.rows_pad;
     dim3 grid(static_cast<unsigned>(lay.kpad / kStep), static_cast<unsigned>((vec_cover + 63) / 64));
 #define OZ_DIG(LC, CP, SA) \
-    hipLaunchKernelGGL((digits_kernel<LC, CP, SA>), grid, dim3(256), 0, st, op, maxbits, lay, E, slices)
+    hipLaunchKernelGGL((digits_kernel<LC, CP, SA>), grid, dim3(256), 0, st, op, maxbits, lay, E, slices, p_lo, p_hi)
     if (lcontig) {
         if (two_row) OZ_DIG(true, true, true);
         else if (op.cplx) OZ_DIG(true, true, false);

@@ -255,7 +255,7 @@ def test_batched_tolerance_growth_past_eight(oz, handle, stream):
 def test_batched_tolerance_learned_start(oz, handle, stream):
     from oracle import mlp as omlp
     P = {name: np.zeros(shape) for name, shape in omlp.SIZES}
-    P["b3"][0] = 4.5
+    P["b3"][0] = 4.75
     net = oz.oz_mlp_create(handle, 0)
     oz.oz_mlp_set_params(net, omlp.pack(P).astype(np.float32), np.zeros(16), np.ones(16))
     rng = np.random.default_rng(60)

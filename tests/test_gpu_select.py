@@ -223,10 +223,10 @@ def test_mlp_training_fits_and_round_trips(oz, handle, tmp_path):
 
 
 def test_learned_start_in_tolerance_mode(oz, handle):
-    """A hand-set network that always answers 3.5 (so s = 4): the call starts at
+    """A hand-set network that always answers 3.75 (so s = 4): the call starts at
     4, grows incrementally, and gives the oracle's incremental result."""
     P = {name: np.zeros(shape) for name, shape in omlp.SIZES}
-    P["b3"][0] = 3.5
+    P["b3"][0] = 3.75
     net = _upload_net(oz, handle, omlp.pack(P).astype(np.float32), np.zeros(16, np.float32),
                       np.ones(16, np.float32))
     try:
@@ -276,8 +276,8 @@ def test_predicted_slices_match_oracle_network(oz, handle):
                 s = oz.oz_predict_slices(handle, "N", "N", A.shape[0], 50, 70, 0, dA, lda, dB, ldb, tol, smax=12)
                 f = osel.features("N", "N", A, B, tol).astype(np.float32).astype(np.float64)
                 yv, _ = omlp.forward(p.astype(np.float64), f[None, :], mu.astype(np.float64), sd.astype(np.float64))
-                if abs(yv[0] - round(yv[0])) < 1e-3:
-                    continue  # too close to an integer for float32 to decide the ceiling
+                if abs((yv[0] - 0.5) - round(yv[0] - 0.5)) < 1e-3:
+                    continue  # too close to a half-integer for float32 to decide the rounding
                 assert s == omlp.predict_slices(yv, 2, 12)[0]
                 checked += 1
         assert checked >= 12

@@ -86,5 +86,5 @@ def test_adam_first_step_closed_form():
 
 
 def test_predict_slices():
-    y = np.array([-3.0, 2.0, 2.01, 6.5, 11.999, 40.0])
-    assert list(mlp.predict_slices(y)) == [2, 2, 3, 7, 12, 12]
+    y = np.array([-3.0, 2.0, 2.01, 2.49, 6.5, 6.7, 11.2, 11.999, 40.0])
+    assert list(mlp.predict_slices(y)) == [2, 2, 2, 2, 7, 7, 11, 12, 12]
