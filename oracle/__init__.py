@@ -17,6 +17,7 @@ float64 or complex128; ``trans`` is 'N', 'T' or 'C'):
 * ``diag_sums``   the exact integer anti-diagonal sums S_{d,chunk}.
 * ``emu_gemm``    the full emulated product: digits, pair products with
                   p + q <= s + 1, FP64 accumulation, alpha/beta.
+* ``emu_zgemm3``  the complex product as three real emulated products (3M).
 * ``kchunk``      the INT32 chunk length (products per chunk).
 
 Submodules ``select`` (features, error table and labels of the learned
@@ -200,6 +201,48 @@ def diag_sums(digA, digB, s, kc=None, rows=None, cols=None):
                           _ptr(out))
     out = out.reshape(planes, nch, s, nc, nr).transpose(0, 1, 2, 4, 3)
     return (out[0], out[1]) if cplx else out[0]
+
+
+def _op(trans, X):
+    t = trans.upper()
+    return X if t == "N" else (X.T if t == "T" else X.conj().T)
+
+
+def emu_zgemm3(transa, transb, A, B, s, alpha=1.0, beta=0.0, C=None, kc=None, rows=None, cols=None):
+    """O4, complex product in the 3-real-product form (3M).
+
+    With op(A) = Ar + i Ai and op(B) = Br + i Bi, the pre-added operands
+    As = Ar + Ai and Bs = Br + Bi are rounded once in FP64; the three real
+    emulated products T1 = Ar Br, T2 = Ai Bi, T3 = As Bs (each with its own
+    row / column scales, kc = ``kchunk(s)`` real terms) are combined as
+    Cr = T1 - T2, Ci = (T3 - T1) - T2, and then alpha, beta are applied with
+    the complex formula of the 4-product form (each product and sum rounded)."""
+    A = _op(transa, _f(A, np.complex128))
+    B = _op(transb, _f(B, np.complex128))
+    Ar, Ai = np.asfortranarray(A.real), np.asfortranarray(A.imag)
+    Br, Bi = np.asfortranarray(B.real), np.asfortranarray(B.imag)
+    As = np.asfortranarray(Ar + Ai)
+    Bs = np.asfortranarray(Br + Bi)
+    kc = kchunk(s) if kc is None else kc
+    T1 = emu_gemm("N", "N", Ar, Br, s, kc=kc, rows=rows, cols=cols)
+    T2 = emu_gemm("N", "N", Ai, Bi, s, kc=kc, rows=rows, cols=cols)
+    T3 = emu_gemm("N", "N", As, Bs, s, kc=kc, rows=rows, cols=cols)
+    Cr = T1 - T2
+    Ci = (T3 - T1) - T2
+    xr, xi = complex(alpha).real, complex(alpha).imag
+    yr, yi = complex(beta).real, complex(beta).imag
+    outr = xr * Cr - xi * Ci
+    outi = xr * Ci + xi * Cr
+    if yr != 0.0 or yi != 0.0:
+        m, n = A.shape[0], B.shape[1]
+        C0 = _f(C, np.complex128) if C is not None else np.zeros((m, n), np.complex128, order="F")
+        rs = np.arange(m) if rows is None else np.asarray(rows)
+        cs = np.arange(n) if cols is None else np.asarray(cols)
+        C0 = C0[np.ix_(rs, cs)]
+        cr, ci = C0.real, C0.imag
+        outr = outr + (yr * cr - yi * ci)
+        outi = outi + (yr * ci + yi * cr)
+    return np.asfortranarray(outr + 1j * outi)
 
 
 def emu_gemm(transa, transb, A, B, s, alpha=1.0, beta=0.0, C=None, kc=None, rows=None, cols=None, s_to=None):

@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 
 import oracle
+import workloads
 from oracle.exact import exact_gemm, exact_gemm_rounded
 
 U = 2.0 ** -53
@@ -463,3 +464,61 @@ def test_incremental_growth_equals_fresh_run_up_to_rounding(s0, s1):
     e0 = oracle.weighted_error(oracle.emu_gemm("N", "N", A, B, s0), ref, amax, bmax)
     e1 = oracle.weighted_error(grown, ref, amax, bmax)
     assert e1 < e0 * 2.0 ** (-5 * (s1 - s0)) or e1 < 1e-15
+
+
+# ---------------------------------------------------------------- 3M complex form
+
+def _int_complex(rng, shape, lim):
+    return (rng.integers(-lim, lim + 1, shape) + 1j * rng.integers(-lim, lim + 1, shape)).astype(np.complex128)
+
+
+def test_3m_exact_on_small_integers():
+    """Parts in [-63, 63]: Ar, Ai, Ar + Ai, Br, Bi, Br + Bi are integers of at
+    most 7 bits, so one slice represents each exactly and the three real
+    products, their combination and the result are exact (k 127^2 << 2^53)."""
+    rng = np.random.default_rng(31)
+    A = _int_complex(rng, (23, 40), 63)
+    B = _int_complex(rng, (40, 17), 63)
+    want = (A.astype(np.complex128) @ B.astype(np.complex128))  # exact: integer sums below 2^53
+    Ai = A.real.astype(np.int64), A.imag.astype(np.int64)
+    Bi = B.real.astype(np.int64), B.imag.astype(np.int64)
+    exact_r = Ai[0] @ Bi[0] - Ai[1] @ Bi[1]
+    exact_i = Ai[0] @ Bi[1] + Ai[1] @ Bi[0]
+    assert np.array_equal(want.real, exact_r) and np.array_equal(want.imag, exact_i)
+    for s in (1, 3):
+        got = oracle.emu_zgemm3("N", "N", np.asfortranarray(A), np.asfortranarray(B), s)
+        assert np.array_equal(got.real, exact_r.astype(float)) and np.array_equal(got.imag, exact_i.astype(float))
+    # complex alpha / beta on exact data: the epilogue formula, exact here
+    C0 = _int_complex(rng, (23, 17), 9)
+    got = oracle.emu_zgemm3("N", "N", np.asfortranarray(A), np.asfortranarray(B), 2, alpha=2 - 1j, beta=0.5 + 0.25j,
+                            C=np.asfortranarray(C0))
+    want = (2 - 1j) * (exact_r + 1j * exact_i) + (0.5 + 0.25j) * C0
+    assert np.array_equal(got, want)
+
+
+def test_3m_trans_conj_and_rows():
+    rng = np.random.default_rng(32)
+    A = np.asfortranarray(rng.standard_normal((30, 44)) + 1j * rng.standard_normal((30, 44)))
+    B = np.asfortranarray(rng.standard_normal((44, 21)) + 1j * rng.standard_normal((44, 21)))
+    ref = oracle.emu_zgemm3("N", "N", A, B, 5)
+    # op() given by trans / conj-trans storage yields the same operands bit for bit
+    assert np.array_equal(oracle.emu_zgemm3("C", "T", np.asfortranarray(A.conj().T), np.asfortranarray(B.T), 5), ref)
+    # row / column subsets select entries
+    rows, cols = [3, 0, 29], [20, 1]
+    assert np.array_equal(oracle.emu_zgemm3("N", "N", A, B, 5, rows=rows, cols=cols), ref[np.ix_(rows, cols)])
+
+
+def test_3m_error_decays_and_stays_near_4m():
+    A, B = workloads.zgemm_rowexp(n=96, seed=5, m=80, k=120)
+    dd = oracle.gemm_dd("N", "N", A, B)
+    wa = np.maximum(np.abs(A.real), np.abs(A.imag)).max(1)
+    wb = np.maximum(np.abs(B.real), np.abs(B.imag)).max(0)
+    prev = None
+    for s in (3, 4, 5, 6, 7):
+        e3 = oracle.weighted_error(oracle.emu_zgemm3("N", "N", A, B, s), dd, wa, wb)
+        e4 = oracle.weighted_error(oracle.emu_gemm("N", "N", A, B, s), dd, wa, wb)
+        assert e4 / 2 <= e3 <= 4 * e4, (s, e3, e4)     # same order as the 4-product form
+        if prev is not None:
+            assert 2 ** 5 < prev / e3 < 2 ** 8.5, s        # about 2^6.6 per slice (Table 1)
+        prev = e3
+    assert prev < 1e-12
