@@ -4,8 +4,10 @@ Workload: one complex double GEMM C = A*B, square n = 4096, operands with a
 per-row power-of-two exponent in [-20, 20] shared by real and imaginary parts
 (normal(0,1) entries), emulated with s = 7 INT8 slices -- the smallest slice
 count whose error is below 1e-12 on this data.  One step is one oz_zgemm
-call: exponent scan, digit split of both operands, the INT8 slice-pair GEMM
-with the fused FP64 epilogue.  Inputs are resident in HBM before timing.
+call: exponent scan, digit split of both operands, the INT8 slice-pair GEMM(s)
+with the fused FP64 epilogue; by default in the 3-real-product form (three
+real products, the last one's epilogue combining them; --zmode 4: one real
+product over the two-row form).  Inputs are resident in HBM before timing.
 
 Printed: one JSON line with the effective rate (8 n^3 / time), the roofline of
 the dominant kernel (the INT8 GEMM, HIP events on its own stream), the native
@@ -47,11 +49,14 @@ def traffic_for(workload):
     return ent["bytes_per_launch"]
 
 
-def cpu_baseline(A, B, s, C_gpu, rows):
+def cpu_baseline(A, B, s, C_gpu, rows, zmode=4):
     """Oracle (step-by-step CPU emulation) on the first `rows` rows of C."""
     import oracle
     t0 = time.perf_counter()
-    ref = oracle.emu_gemm("N", "N", np.asfortranarray(A[:rows]), B, s)
+    if zmode == 3:
+        ref = oracle.emu_zgemm3("N", "N", np.asfortranarray(A[:rows]), B, s)
+    else:
+        ref = oracle.emu_gemm("N", "N", np.asfortranarray(A[:rows]), B, s)
     t = time.perf_counter() - t0
     n, k = B.shape[1], A.shape[1]
     dd = oracle.gemm_dd("N", "N", np.asfortranarray(A[:rows]), B)
@@ -280,6 +285,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--slices", type=int, default=7)
+    ap.add_argument("--zmode", type=int, default=3, choices=[3, 4],
+                    help="complex form: 3 = three real products (default), 4 = one real product over the two-row form")
     ap.add_argument("--cpu-rows", type=int, default=512)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (reference for HBM byte counters)")
@@ -308,7 +315,7 @@ def main():
     dC = torch.zeros(n * n, dtype=torch.complex128, device="cuda")
     h = oz.oz_create(0)
     oz.oz_set_stream(h, stream.cuda_stream)
-    p = oz.prec(s)
+    p = oz.prec(s, zmode=args.zmode)
 
     def step():
         oz.oz_zgemm(h, "N", "N", n, n, n, 1.0, dA, n, dB, n, 0.0, dC, n, p)
@@ -333,11 +340,15 @@ def main():
 
     C_gpu = dC.cpu().numpy().reshape(n, n, order="F")
 
-    # dominant kernel: INT8 slice GEMM over C' = A' B' (2n x n x 2n), P(s) pairs
-    int8_ops = pairs(s) * 2.0 * (2 * n) * n * (2 * n)
-    gemm_avg_ms = gemm_ms / calls
+    # dominant kernel: the INT8 slice GEMM, P(s) pairs; 4-product form: one
+    # launch over C' = A' B' (2n x n x 2n); 3-product form: three n x n x n
+    # launches (the timed GEMM phase spans all three)
+    launches = 3 if args.zmode == 3 else 1
+    int8_ops = pairs(s) * 2.0 * ((2 * n) * n * (2 * n) if args.zmode != 3 else n * n * n)
+    gemm_avg_ms = gemm_ms / calls / launches
     achieved = int8_ops / (gemm_avg_ms * 1e-3) / 1e12
-    workload = "zgemm n=%d s=%d (row exponents +-20, normal entries)" % (n, s)
+    form = "3-product form" if args.zmode == 3 else "4-product form"
+    workload = "zgemm n=%d s=%d %s (row exponents +-20, normal entries)" % (n, s, form)
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -351,11 +362,11 @@ def main():
         "vs_baseline": None,
         "dtype": "int8",
         "data": "synthetic",
-        "config": {"workload": workload, "m": n, "n": n, "k": n, "slices": s, "complex": True,
+        "config": {"workload": workload, "m": n, "n": n, "k": n, "slices": s, "complex": True, "zmode": args.zmode,
                    "inputs": "seed 0, (N(0,1) + i N(0,1)) * 2^e_row, e_row ~ randint(-20, 20)"},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": INT8_PEAK_TOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / INT8_PEAK_TOPS, 4), "traffic": traffic_for(workload),
-                     "kernel": "gemm_kernel (INT8 ops of the s(s+1)/2 slice pairs)",
+                     "kernel": "gemm_kernel (INT8 ops of the s(s+1)/2 slice pairs)", "launches_per_step": launches,
                      "avg_ms": round(gemm_avg_ms, 4), "split_avg_ms": round(split_ms / calls, 4)},
     }
 
@@ -384,7 +395,7 @@ def main():
         torch.cuda.synchronize()
         del x, y
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(A, B, s, C_gpu, args.cpu_rows)
+        out["cpu_baseline"] = cpu_baseline(A, B, s, C_gpu, args.cpu_rows, args.zmode)
     oz.oz_destroy(h)
     print(json.dumps(out), flush=True)
 

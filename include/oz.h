@@ -77,8 +77,18 @@ typedef struct oz_handle_s* oz_handle_t;
  *           64 with s*kchunk*127^2 <= 2^31-1; a nonzero value must be a
  *           positive multiple of 64 not above that bound (used to exercise
  *           the chunked accumulation on small k).
- *  zmode  : complex only; 0 or 4: the 4-real-product form (the only one
- *           built so far).
+ *  zmode  : complex only.  0 or 4: the 4-real-product form -- one real
+ *           emulated product over the two-row form of op(A) (see oz_zgemm).
+ *           3: the 3-real-product form (fixed slice counts only; a
+ *           tolerance-driven or batched call with zmode 3 returns 14): with
+ *           op(A) = Ar + i Ai, op(B) = Br + i Bi and the FP64 sums As = Ar + Ai,
+ *           Bs = Br + Bi (each rounded once), T1 = Ar Br, T2 = Ai Bi and
+ *           T3 = As Bs are three real emulated products, each with its own
+ *           per-row / per-column scales and INT32 chunks of kchunk real terms;
+ *           then Cr = T1 - T2, Ci = (T3 - T1) - T2 and alpha, beta as for
+ *           zmode 4.  Three quarters of the INT8 work; the error is of the same
+ *           order (the sums can double the scale of T3).  A row or column
+ *           whose sum overflows counts as non-finite.
  *  kernel : GEMM kernel shape; 0 chooses by size, 1 = 128 x 64 block with a
  *           3-stage LDS ring, 2 = 64 x 64 block with 2 stages (both for
  *           s <= 8), 3 = per-diagonal streaming (any s; the only choice for

@@ -107,6 +107,39 @@ Plan make_plan(int cplx, int64_t m, int64_t n, int64_t k, int s_lay, bool tol_bu
     return p;
 }
 
+// Workspace of a complex product in the 3-real-product form: per real operand
+// (parts 1: real, 2: imaginary, 3: their sum) the scale scratch, exponents and
+// slices of A and B, then the real products T1, T2 (m x n).
+struct Plan3 {
+    oz::SliceLayout la, lb;
+    size_t off_max, off_ea[3], off_fb[3], off_sa[3], off_sb[3], off_t1, off_t2, total;
+    int64_t nmax;
+};
+
+Plan3 make_plan3(int64_t m, int64_t n, int64_t k, int s) {
+    Plan3 p;
+    p.la = oz::slice_layout(1, 0, m, k, s);
+    p.lb = oz::slice_layout(0, 0, n, k, s);
+    size_t o = 0;
+    auto take = [&o](size_t bytes) {
+        const size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    p.nmax = 3 * (m + n);
+    p.off_max = take(sizeof(uint64_t) * static_cast<size_t>(p.nmax));
+    for (int q = 0; q < 3; ++q) {
+        p.off_ea[q] = take(sizeof(int32_t) * static_cast<size_t>(m));
+        p.off_fb[q] = take(sizeof(int32_t) * static_cast<size_t>(p.lb.rows_pad));
+        p.off_sa[q] = take(static_cast<size_t>(s) * p.la.rows_pad * p.la.kpad);
+        p.off_sb[q] = take(static_cast<size_t>(s) * p.lb.rows_pad * p.lb.kpad);
+    }
+    p.off_t1 = take(sizeof(double) * static_cast<size_t>(m) * n);
+    p.off_t2 = take(sizeof(double) * static_cast<size_t>(m) * n);
+    p.total = o;
+    return p;
+}
+
 int ensure_ws(oz_handle_t h, size_t bytes) {
     if (bytes <= h->ws_bytes) return OZ_OK;
     if (!h->ws_owned) return OZ_ERR_ALLOC;
@@ -204,6 +237,103 @@ int rule_slices(oz_handle_t h, const oz::OperandView& va, const oz::OperandView&
     return OZ_OK;
 }
 
+// Complex product in the 3-real-product form (zmode 3): with op(A) = Ar + i Ai
+// and op(B) = Br + i Bi, T1 = Ar Br, T2 = Ai Bi and T3 = (Ar + Ai)(Br + Bi)
+// are three real emulated products (each with its own scales; the pre-added
+// operands rounded once in FP64 as the split reads them); the last one's
+// epilogue forms Cr = T1 - T2, Ci = (T3 - T1) - T2 and applies alpha, beta.
+// Three quarters of the INT8 work of the 4-product form.
+int zgemm_3m(oz_handle_t h, char transa, char transb, int64_t m, int64_t n, int64_t k, const double* alpha,
+             const double* A, int64_t lda, const double* B, int64_t ldb, const double* beta, double* C, int64_t ldc,
+             int s, int64_t kc, int kernel, oz_report_t* rep) {
+    Plan3 p = make_plan3(m, n, k, s);
+    if (p.la.rows_pad / 64 > 65535 || p.lb.rows_pad / 64 > 65535) return OZ_ERR_UNSUPPORTED;
+    int st = ensure_ws(h, p.total);
+    if (st) return st;
+    char* ws = static_cast<char*>(h->ws);
+    uint64_t* mx = reinterpret_cast<uint64_t*>(ws + p.off_max);
+    const double ar = alpha[0], ai = alpha[1], br = beta[0], bi = beta[1];
+    hipError_t e = mark(h);
+    if (e == hipSuccess) e = oz::launch_zero_u64(mx, p.nmax, h->stream);
+    // the three real operands of each side (real parts, imaginary parts,
+    // their sums) in one scan and one digit pass over the complex operand
+    const oz::OperandView va = view_a(transa, A, lda, m, k, 1);
+    const oz::OperandView vb = view_b(transb, B, ldb, n, k, 1);
+    oz::Split3Out oa, ob;
+    for (int q = 0; q < 3; ++q) {
+        oa.maxbits[q] = mx + q * (m + n);
+        ob.maxbits[q] = oa.maxbits[q] + m;
+        oa.E[q] = reinterpret_cast<int32_t*>(ws + p.off_ea[q]);
+        ob.E[q] = reinterpret_cast<int32_t*>(ws + p.off_fb[q]);
+        oa.slices[q] = reinterpret_cast<int8_t*>(ws + p.off_sa[q]);
+        ob.slices[q] = reinterpret_cast<int8_t*>(ws + p.off_sb[q]);
+    }
+    if (e == hipSuccess) e = oz::launch_scan3(va, oa, h->stream);
+    if (e == hipSuccess) e = oz::launch_scan3(vb, ob, h->stream);
+    if (e == hipSuccess) e = oz::launch_digits3(va, p.la, oa, h->stream);
+    if (e == hipSuccess) e = oz::launch_digits3(vb, p.lb, ob, h->stream);
+    if (e == hipSuccess) e = mark(h);
+    double* T[2] = {reinterpret_cast<double*>(ws + p.off_t1), reinterpret_cast<double*>(ws + p.off_t2)};
+    for (int q = 0; q < 3 && e == hipSuccess; ++q) {
+        oz::GemmArgs g;
+        std::memset(&g, 0, sizeof(g));
+        g.SA = reinterpret_cast<const int8_t*>(ws + p.off_sa[q]);
+        g.SB = reinterpret_cast<const int8_t*>(ws + p.off_sb[q]);
+        g.EA = reinterpret_cast<const int32_t*>(ws + p.off_ea[q]);
+        g.FB = reinterpret_cast<const int32_t*>(ws + p.off_fb[q]);
+        g.Mp = p.la.rows_pad;
+        g.Np = p.lb.rows_pad;
+        g.kpad = p.la.kpad;
+        g.chunk_steps = kc / oz::kStep;
+        g.s = s;
+        g.s_lay = s;
+        g.tile = kernel;
+        g.m = m;
+        g.n = n;
+        if (q < 2) {
+            // T1, T2: plain FP64 results (alpha = 1, beta = 0: 1 * v is exact)
+            g.mode = oz::kFinal;
+            g.C = T[q];
+            g.ldc = m;
+            g.alpha_r = 1.0;
+            g.beta_zero = 1;
+        } else {
+            g.mode = oz::kCombine3M;
+            g.C = C;
+            g.ldc = ldc;
+            g.alpha_r = ar;
+            g.alpha_i = ai;
+            g.beta_r = br;
+            g.beta_i = bi;
+            g.beta_zero = (br == 0.0 && bi == 0.0) ? 1 : 0;
+            g.t1 = T[0];
+            g.t2 = T[1];
+            g.ldt = m;
+        }
+        e = oz::launch_gemm(g, h->stream);
+    }
+    if (e == hipSuccess) e = mark(h);
+    if (e != hipSuccess) return OZ_ERR_HIP;
+    if (rep) {
+        rep->slices_used = s;
+        rep->zmode_used = 3;
+        rep->kchunks = static_cast<int32_t>((p.la.kpad + kc - 1) / kc);
+        if (hipStreamSynchronize(h->stream) != hipSuccess) return OZ_ERR_HIP;
+        std::vector<int32_t> ex(static_cast<size_t>(m > n ? m : n));
+        for (int q = 0; q < 3; ++q) {
+            if (hipMemcpy(ex.data(), ws + p.off_ea[q], sizeof(int32_t) * m, hipMemcpyDeviceToHost) != hipSuccess)
+                return OZ_ERR_HIP;
+            for (int64_t i = 0; i < m; ++i)
+                if (ex[i] == oz::kNonFiniteExp) rep->status = OZ_ERR_NONFINITE;
+            if (hipMemcpy(ex.data(), ws + p.off_fb[q], sizeof(int32_t) * n, hipMemcpyDeviceToHost) != hipSuccess)
+                return OZ_ERR_HIP;
+            for (int64_t j = 0; j < n; ++j)
+                if (ex[j] == oz::kNonFiniteExp) rep->status = OZ_ERR_NONFINITE;
+        }
+    }
+    return OZ_OK;
+}
+
 int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, int64_t n, int64_t k,
                 const double* alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
                 const double* beta, double* C, int64_t ldc, const oz_prec_t* prec, oz_report_t* rep) {
@@ -226,7 +356,8 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
     int smax = kDefaultSmax;
     if (prec) {
         if (prec->slices < 0 || prec->slices > OZ_MAX_SLICES) return 14;
-        if (prec->zmode != 0 && prec->zmode != 4) return 14;
+        if (prec->zmode != 0 && prec->zmode != 3 && prec->zmode != 4) return 14;
+        if (cplx && prec->zmode == 3 && prec->slices == 0) return 14;  // 3M: fixed slice counts only
         if (prec->kernel < 0 || prec->kernel > 3) return 14;
         if (prec->reserved != 0) return 14;
         if (prec->slices == 0) {
@@ -271,6 +402,11 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
         return st;
     }
 
+    if (cplx && prec && prec->zmode == 3) {
+        // 3-real-product form: real INT32 chunks of k terms
+        const int64_t kc3 = prec->kchunk ? prec->kchunk : kchunk_bound(s);
+        return zgemm_3m(h, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, s, kc3, kernel, rep);
+    }
     Plan p = make_plan(cplx, m, n, k, s_plan, tol_mode);
     if (!grid_fits(p)) return OZ_ERR_UNSUPPORTED;
     st = ensure_ws(h, p.total);
@@ -528,6 +664,10 @@ int oz_workspace_size(oz_handle_t h, char transa, char transb, int64_t m, int64_
     const bool tol = prec && prec->slices == 0;
     const int smax = (prec && prec->smax) ? prec->smax : kDefaultSmax;
     if (tol && (smax < 1 || smax > OZ_MAX_SLICES)) return 14;
+    if (is_complex && prec && prec->zmode == 3 && !tol) {
+        *bytes = make_plan3(m, n, k, s).total;
+        return OZ_OK;
+    }
     *bytes = make_plan(is_complex ? 1 : 0, m, n, k, tol ? smax : s, tol).total;
     return OZ_OK;
 }

@@ -91,6 +91,32 @@ __device__ __forceinline__ void wait_vm() {
 __device__ __forceinline__ void store_tile(const GemmArgs& g, const double (&acc64)[16], int64_t row0, int half,
                                            int64_t col) {
     const double nan = __longlong_as_double(0x7ff8000000000000ll);
+    if (g.mode == kCombine3M) {
+        // this product is T3 of the 3-real-product form; one entry per register
+        if (col >= g.n) return;
+        const int32_t f = g.FB[col];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int64_t i = row0 + 8 * (r >> 2) + 4 * half + (r & 3);
+            if (i >= g.m) continue;
+            const int32_t e = g.EA[i];
+            const double t3 = (e == kNonFiniteExp || f == kNonFiniteExp) ? nan : ldexp(acc64[r], e + f);
+            const double t1 = g.t1[i + col * g.ldt], t2 = g.t2[i + col * g.ldt];
+            const double cr = t1 - t2;
+            const double ci = (t3 - t1) - t2;
+            double* c = g.C + 2 * (i + col * g.ldc);
+            double outr = g.alpha_r * cr - g.alpha_i * ci;
+            double outi = g.alpha_r * ci + g.alpha_i * cr;
+            if (!g.beta_zero) {
+                const double c0 = c[0], c1 = c[1];
+                outr = outr + (g.beta_r * c0 - g.beta_i * c1);
+                outi = outi + (g.beta_r * c1 + g.beta_i * c0);
+            }
+            c[0] = outr;
+            c[1] = outi;
+        }
+        return;
+    }
     if (g.mode != kFinal) {
         // raw tile sums in C' space (every padded row and column is stored)
 #pragma unroll
@@ -507,7 +533,9 @@ hipError_t launch_stream(const GemmArgs& g, hipStream_t st) {
 
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t st) {
     if (g.s < 1 || g.s > 18 || g.s_lay < g.s) return hipErrorInvalidValue;
-    if (g.mode != kFinal && g.acc == nullptr) return hipErrorInvalidValue;
+    const bool raw = g.mode == kRawWrite || g.mode == kRawAdd || g.mode == kRawWriteFinal;
+    if (raw && g.acc == nullptr) return hipErrorInvalidValue;
+    if (g.mode == kCombine3M && (g.t1 == nullptr || g.t2 == nullptr || g.cplx)) return hipErrorInvalidValue;
     if (g.tile == 3) return launch_stream(g, st);
     switch (g.s) {
         case 1: return launch_s<1>(g, st);

@@ -66,6 +66,18 @@ hipError_t launch_scan(const OperandView& op, uint64_t* maxbits, hipStream_t st)
 hipError_t launch_digits(const OperandView& op, const uint64_t* maxbits, const SliceLayout& lay,
                          int32_t* E, int8_t* slices, hipStream_t st, int p_lo = 0, int p_hi = -1);
 
+// Split of a complex operand into the three real operands of the
+// 3-real-product form (parts: real, imaginary, their sum) in one pass each for
+// the scan and the digits; the view is the complex operand (cplx = 1), the
+// layout the real one.  maxbits[q] are cleared by the caller.
+struct Split3Out {
+    uint64_t* maxbits[3];
+    int32_t* E[3];
+    int8_t* slices[3];
+};
+hipError_t launch_scan3(const OperandView& op, const Split3Out& o, hipStream_t st);
+hipError_t launch_digits3(const OperandView& op, const SliceLayout& lay, const Split3Out& o, hipStream_t st);
+
 // Batched split: one block per item; an item names its operand and the block
 // coordinates the one-operand launch would have used.
 struct SplitOp {
@@ -112,13 +124,19 @@ struct GemmArgs {
     int beta_zero;
     // verification mode: write INT32 anti-diagonal sums instead of C
     int32_t* diag_out;
+    // kCombine3M: the other two real products (m x n, leading dimension ldt)
+    const double* t1;
+    const double* t2;
+    int64_t ldt;
 };
 // Epilogue modes: kFinal writes alpha*ldexp(acc, E+F) + beta*C into C; kRawWrite
 // stores the FP64 tile sum acc (before ldexp) into g.acc; kRawAdd adds the new
 // anti-diagonal terms onto the acc already in g.acc (chunk by chunk);
 // kRawWriteFinal does both kRawWrite and kFinal (for beta = 0, where C can be
-// rewritten from acc if the slice count grows).
-constexpr int kFinal = 0, kRawWrite = 1, kRawAdd = 2, kRawWriteFinal = 3;
+// rewritten from acc if the slice count grows); kCombine3M finishes a complex
+// product in the 3-real-product form: this product is T3, t1 / t2 hold T1 / T2,
+// and C (complex) receives alpha (T1 - T2 + i ((T3 - T1) - T2)) + beta C.
+constexpr int kFinal = 0, kRawWrite = 1, kRawAdd = 2, kRawWriteFinal = 3, kCombine3M = 4;
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t st);
 
 // Batched products: one persistent launch over a list of tiles of many

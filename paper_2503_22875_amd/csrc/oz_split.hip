@@ -255,7 +255,130 @@ __global__ __launch_bounds__(256) void digits_batched_kernel(const SplitOp* __re
 #undef OZ_DB
 }
 
+// ---- three real operands of one complex operand in one pass ---------------
+// Parts q = 0, 1, 2: the real parts, the imaginary parts (negated for 'C')
+// and their FP64 sums, each a real operand with its own scales and slices
+// (the complex product in its 3-real-product form).
+__device__ __forceinline__ void parts3(const OperandView& op, const double* e, double (&x)[3]) {
+    const double re = e[0], im = op.conj ? -e[1] : e[1];
+    x[0] = re;
+    x[1] = im;
+    x[2] = re + im;
+}
+
+template <bool LCONTIG>
+__device__ __forceinline__ void scan3_body(const OperandView& op, const Split3Out& o, int64_t lspan, int64_t bx,
+                                           int64_t by) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t v0 = by * 64;
+    const int64_t l0 = bx * lspan;
+    const int64_t l1 = (l0 + lspan < op.k) ? l0 + lspan : op.k;
+    if (LCONTIG) {
+        for (int vi = 0; vi < 16; ++vi) {
+            const int64_t v = v0 + wave * 16 + vi;
+            if (v >= op.nv) break;  // wave-uniform
+            uint64_t mx[3] = {0, 0, 0};
+            const double* base = op.X + v * op.sv * 2;
+            for (int64_t l = l0 + lane; l < l1; l += 64) {
+                double x[3];
+                parts3(op, base + l * op.sl * 2, x);
+#pragma unroll
+                for (int q = 0; q < 3; ++q) mx[q] = umax64(mx[q], mag_bits(x[q]));
+            }
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                for (int off = 32; off > 0; off >>= 1) mx[q] = umax64(mx[q], __shfl_xor(mx[q], off));
+                if (lane == 0 && mx[q] != 0) atomicMax(reinterpret_cast<unsigned long long*>(o.maxbits[q] + v), mx[q]);
+            }
+        }
+    } else {
+        __shared__ uint64_t red[3][4][64];
+        const int64_t v = v0 + lane;
+        uint64_t mx[3] = {0, 0, 0};
+        if (v < op.nv) {
+            for (int64_t l = l0 + wave; l < l1; l += 4) {
+                double x[3];
+                parts3(op, op.X + (v + l * op.sl) * 2, x);
+#pragma unroll
+                for (int q = 0; q < 3; ++q) mx[q] = umax64(mx[q], mag_bits(x[q]));
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) red[q][wave][lane] = mx[q];
+        __syncthreads();
+        if (wave == 0 && v < op.nv) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const uint64_t m = umax64(umax64(red[q][0][lane], red[q][1][lane]), umax64(red[q][2][lane], red[q][3][lane]));
+                if (m != 0) atomicMax(reinterpret_cast<unsigned long long*>(o.maxbits[q] + v), m);
+            }
+        }
+    }
+}
+
+template <bool LCONTIG>
+__global__ __launch_bounds__(256) void scan3_kernel(OperandView op, Split3Out o, int64_t lspan) {
+    scan3_body<LCONTIG>(op, o, lspan, blockIdx.x, blockIdx.y);
+}
+
+// One block: 64 vectors x one step of 32 terms; each thread owns 8 consecutive
+// terms (complex elements) of one vector and writes them into all three parts.
+template <bool LCONTIG>
+__global__ __launch_bounds__(256) void digits3_kernel(OperandView op, SliceLayout lay, Split3Out o) {
+    const int tid = threadIdx.x;
+    const int vi = LCONTIG ? (tid >> 2) : (tid & 63);
+    const int sub = LCONTIG ? (tid & 3) : (tid >> 6);
+    const int64_t v = static_cast<int64_t>(blockIdx.y) * 64 + vi;
+    const int64_t step = blockIdx.x;
+    const int64_t t0 = step * kStep + sub * 8;
+    const bool live = v < op.nv;
+    if (v >= lay.rows_pad) return;
+    int32_t ex[3] = {0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        if (live) ex[q] = exponent_of_max(o.maxbits[q][v]);
+        if (live && step == 0 && sub == 0) o.E[q][v] = ex[q];
+    }
+    double x[3][8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int64_t l = t0 + e;
+        double px[3] = {0.0, 0.0, 0.0};
+        if (live && l < op.k) parts3(op, op.X + (v * op.sv + l * op.sl) * 2, px);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) x[q][e] = (ex[q] == kNonFiniteExp) ? 0.0 : px[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        Sig g[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) g[e] = sig_of(x[q][e], ex[q]);
+        for (int p = 0; p < lay.s; ++p) {
+            int d[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) d[e] = digit(g[e], p + 1);
+            *reinterpret_cast<uint64_t*>(o.slices[q] + slice_off(t0, p, v, lay.s, lay.rows_pad)) = pack8(d);
+        }
+    }
+}
+
 }  // namespace
+
+hipError_t launch_scan3(const OperandView& op, const Split3Out& o, hipStream_t st) {
+    if (op.nv <= 0 || op.k <= 0) return hipSuccess;
+    const int64_t lspan = 512;
+    dim3 grid(static_cast<unsigned>((op.k + lspan - 1) / lspan), static_cast<unsigned>((op.nv + 63) / 64));
+    if (op.sl == 1) hipLaunchKernelGGL(scan3_kernel<true>, grid, dim3(256), 0, st, op, o, lspan);
+    else hipLaunchKernelGGL(scan3_kernel<false>, grid, dim3(256), 0, st, op, o, lspan);
+    return hipGetLastError();
+}
+
+hipError_t launch_digits3(const OperandView& op, const SliceLayout& lay, const Split3Out& o, hipStream_t st) {
+    dim3 grid(static_cast<unsigned>(lay.kpad / kStep), static_cast<unsigned>((lay.rows_pad + 63) / 64));
+    if (op.sl == 1) hipLaunchKernelGGL(digits3_kernel<true>, grid, dim3(256), 0, st, op, lay, o);
+    else hipLaunchKernelGGL(digits3_kernel<false>, grid, dim3(256), 0, st, op, lay, o);
+    return hipGetLastError();
+}
 
 SliceLayout slice_layout(int side_a, int cplx, int64_t nv, int64_t k, int s) {
     SliceLayout L;

@@ -172,6 +172,11 @@ def test_batched_argument_errors(oz, handle):
         args[key] = val
         assert oz.oz_zgemm_batched(handle, check=False, p=oz.prec(6), **args) == pos
     assert oz.oz_zgemm_batched(handle, check=False, p=oz.prec(9), **base) == 14
+    # the 3-real-product form is for single calls with a fixed slice count
+    assert oz.oz_zgemm_batched(handle, check=False, p=oz.prec(6, zmode=3), **base) == 14
+    st = oz.oz_zgemm(handle, "N", "N", 4, 4, 4, 1.0, d, 4, d, 4, 0.0, d, 4, oz.prec(0, tol=1e-10, zmode=3),
+                     check=False)
+    assert st == 14
 
 
 def _tol_batch(oz, handle, stream, cplx, probs, p):

@@ -483,3 +483,78 @@ def test_select_slices_statistic(oz, handle, kind, cplx):
         s = oz.oz_select_slices(handle, "N", "N", m, n, k, cplx, dA, lda, dB, ldb, tol)
         want = next((t for t in range(1, 13) if 2.5 * (t + 1) * 2.0 ** (-7 * t) * spread <= tol), 12)
         assert s == want, (kind, tol, s, want)
+
+
+# ----------------------------------------------------------------- 3-real-product complex form
+
+
+def run_z3(oz, handle, ta, tb, A, B, s, alpha=1.0, beta=0.0, C0=None, kernel=0, kchunk=0, lda_pad=0):
+    m = A.shape[0] if ta == "N" else A.shape[1]
+    k = A.shape[1] if ta == "N" else A.shape[0]
+    n = B.shape[1] if tb == "N" else B.shape[0]
+    dA, lda = to_dev(A, A.shape[0] + lda_pad)
+    dB, ldb = to_dev(B)
+    C0 = np.zeros((m, n), np.complex128, order="F") if C0 is None else C0
+    dC, ldc = to_dev(C0, m + 1)
+    st, rep = oz.oz_zgemm(handle, ta, tb, m, n, k, alpha, dA, lda, dB, ldb, beta, dC, ldc,
+                          oz.prec(s, zmode=3, kernel=kernel, kchunk=kchunk), report=True)
+    assert st == 0 and rep.zmode_used == 3
+    return from_dev(dC, m, n, ldc), rep
+
+
+Z3_CASES = [("N", "N", 70, 65, 33, 7, 0), ("T", "C", 130, 70, 257, 5, 1), ("C", "T", 64, 192, 64, 3, 2),
+            ("N", "C", 5, 300, 17, 8, 0), ("T", "N", 200, 3, 90, 10, 3), ("C", "N", 33, 47, 2, 1, 0)]
+
+
+@pytest.mark.parametrize("ta,tb,m,n,k,s,kernel", Z3_CASES)
+def test_zgemm_3m_bit_exact(oz, handle, ta, tb, m, n, k, s, kernel):
+    rng = np.random.default_rng(m * 7 + n + k)
+    A = wide(rng, (m, k) if ta == "N" else (k, m), 12, True)
+    B = wide(rng, (k, n) if tb == "N" else (n, k), 12, True)
+    C0 = wide(rng, (m, n), 3, True)
+    for al, be in ((1.0, 0.0), (0.75 - 0.5j, -1.25 + 0.5j)):
+        print("z3", ta, tb, m, n, k, s, kernel, al, be, flush=True)
+        got, rep = run_z3(oz, handle, ta, tb, A, B, s, al, be, C0, kernel=kernel, lda_pad=2)
+        want = oracle.emu_zgemm3(ta, tb, A, B, s, alpha=al, beta=be, C=C0)
+        assert np.array_equal(got, want)
+
+
+def test_zgemm_3m_chunks_and_nonfinite(oz, handle):
+    rng = np.random.default_rng(77)
+    A = wide(rng, (40, 700), 8, True)
+    B = wide(rng, (700, 30), 8, True)
+    got, rep = run_z3(oz, handle, "N", "N", A, B, 6, kchunk=128)
+    assert rep.kchunks == 6
+    assert np.array_equal(got, oracle.emu_zgemm3("N", "N", A, B, 6, kc=128))
+    A[5, 3] = np.inf + 0j
+    B[10, 7] = complex(1.0, np.nan)
+    got, rep = run_z3(oz, handle, "N", "N", A, B, 6)
+    assert rep.status == oz.OZ_ERR_NONFINITE
+    bad = np.zeros(got.shape, bool)
+    bad[5, :] = True
+    bad[:, 7] = True
+    assert np.all(np.isnan(got.real[bad])) and np.all(np.isnan(got.imag[bad]))
+    # every other entry as if the row / column held zeros
+    A2, B2 = A.copy(), B.copy()
+    A2[5, :] = 0
+    B2[:, 7] = 0
+    want = oracle.emu_zgemm3("N", "N", A2, B2, 6)
+    assert np.array_equal(got[~bad], want[~bad])
+
+
+def test_zgemm_3m_full_size_samples(oz, handle):
+    """The benchmark product (n = 4096, s = 7) in the 3-product form: sampled
+    entries bit-exact, error within the 1e-12 gate against double-double."""
+    A, B = workloads.zgemm_rowexp(4096, seed=0)
+    got, rep = run_z3(oz, handle, "N", "N", A, B, 7)
+    rng = np.random.default_rng(5)
+    rows = np.sort(rng.choice(4096, 24, replace=False))
+    cols = np.sort(rng.choice(4096, 24, replace=False))
+    want = oracle.emu_zgemm3("N", "N", A, B, 7, rows=rows, cols=cols)
+    assert np.array_equal(got[np.ix_(rows, cols)], want)
+    dd = oracle.gemm_dd("N", "N", A, B, rows=rows, cols=cols)
+    wa = np.maximum(np.abs(A.real), np.abs(A.imag)).max(1)[rows]
+    wb = np.maximum(np.abs(B.real), np.abs(B.imag)).max(0)[cols]
+    err = oracle.weighted_error(got[np.ix_(rows, cols)], dd, wa, wb)
+    print("3M n=4096 s=7 sampled weighted error %.3g" % err)
+    assert err < 1e-12
