@@ -275,11 +275,136 @@ def bench_select(args):
     print(json.dumps({"workload": "selector gain", "rows": results}), flush=True)
 
 
+def _time_ms(fn, stream, steps, warmup):
+    """Mean milliseconds per call of fn() on `stream` (HIP events)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    stream.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    stream.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def _weighted_err(C, Cn, wa, wb):
+    """Scale-weighted relative error of C against Cn (torch tensors on the GPU)."""
+    import torch
+    W = (1.0 / wa)[:, None] * (1.0 / wb)[None, :]
+    return float(torch.linalg.norm(W * (C - Cn)) / torch.linalg.norm(W * Cn))
+
+
+def bench_sweep(args):
+    """Slice-count sweep of the square ZGEMM (row exponents in [-20, 20]):
+    n = 2048 and 4096, s = 3 .. 8, both complex forms.  Per point: time per
+    call, effective FP64 rate, and the scale-weighted error against the
+    native complex128 product (rocBLAS zgemm on the same GPU, timed beside)."""
+    import torch
+
+    import paper_2503_22875_amd as oz
+    import workloads
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    h = oz.oz_create(0)
+    oz.oz_set_stream(h, stream.cuda_stream)
+    rows = []
+    for n in [int(v) for v in args.sweep_n.split(",")]:
+        A, B = workloads.zgemm_rowexp(n, seed=0)
+        dA = torch.from_numpy(A.ravel(order="F")).cuda()
+        dB = torch.from_numpy(B.ravel(order="F")).cuda()
+        dC = torch.zeros(n * n, dtype=torch.complex128, device="cuda")
+        tA, tB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+        del A, B
+        out = {}
+        nms = _time_ms(lambda: out.__setitem__("C", tA @ tB), stream, args.steps, 3)
+        Cn = out["C"]
+        wa = torch.maximum(tA.real.abs(), tA.imag.abs()).amax(1)
+        wb = torch.maximum(tB.real.abs(), tB.imag.abs()).amax(0)
+        flops = 8.0 * n ** 3
+        for zmode in (3, 4):
+            for s in range(3, 9):
+                p = oz.prec(s, zmode=zmode)
+                ms = _time_ms(lambda: oz.oz_zgemm(h, "N", "N", n, n, n, 1.0, dA, n, dB, n, 0.0, dC, n, p),
+                              stream, args.steps, args.warmup)
+                C = dC.view(n, n).t()
+                row = {"n": n, "zmode": zmode, "s": s, "ms": round(ms, 4),
+                       "tflops": round(flops / (ms * 1e-3) / 1e12, 2),
+                       "speedup_vs_native": round(nms / ms, 3),
+                       "err_vs_native": _weighted_err(C, Cn, wa, wb)}
+                print(json.dumps(row), flush=True)
+                rows.append(row)
+        rows.append({"n": n, "native_ms": round(nms, 4), "native_tflops": round(flops / (nms * 1e-3) / 1e12, 2)})
+        print(json.dumps(rows[-1]), flush=True)
+        del dA, dB, dC, tA, tB, Cn
+        torch.cuda.empty_cache()
+    oz.oz_destroy(h)
+    print(json.dumps({"workload": "zgemm slice sweep (row exponents +-20, normal entries)", "rows": rows}),
+          flush=True)
+
+
+def bench_wide_tol(args):
+    """Tolerance-driven wide-range DGEMM: m = n = 4096, k = 8192, rows of A and
+    columns of B scaled by 10^U(-8, 8), tol 1e-6, 1e-10, 1e-14 (smax 12).
+    Per tolerance: time of the whole call (selection, split, products, checks,
+    growth), the start and final slice counts, the check's estimate, the true
+    scale-weighted error against the native float64 product, and the time of
+    a fixed-s call at the final s (no check) and of the native DGEMM."""
+    import torch
+
+    import paper_2503_22875_amd as oz
+    import workloads
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    h = oz.oz_create(0)
+    oz.oz_set_stream(h, stream.cuda_stream)
+    m, n, k = 4096, 4096, 8192
+    A, B = workloads.dgemm_wide(m, n, k, seed=0)
+    dA = torch.from_numpy(A.ravel(order="F")).cuda()
+    dB = torch.from_numpy(B.ravel(order="F")).cuda()
+    dC = torch.zeros(m * n, dtype=torch.float64, device="cuda")
+    tA, tB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    del A, B
+    out = {}
+    nms = _time_ms(lambda: out.__setitem__("C", tA @ tB), stream, args.steps, 3)
+    Cn = out["C"]
+    wa, wb = tA.abs().amax(1), tB.abs().amax(0)
+    flops = 2.0 * m * n * k
+    rows = []
+    for tol in [float(v) for v in args.wide_tols.split(",")]:
+        p = oz.prec(0, tol=tol, smax=12)
+        ms = _time_ms(lambda: oz.oz_dgemm(h, "N", "N", m, n, k, 1.0, dA, m, dB, k, 0.0, dC, m, p),
+                      stream, args.steps, args.warmup)
+        st, rep = oz.oz_dgemm(h, "N", "N", m, n, k, 1.0, dA, m, dB, k, 0.0, dC, m, p, report=True)
+        C = dC.view(n, m).t()
+        err = _weighted_err(C, Cn, wa, wb)
+        s1 = rep.slices_used
+        pf = oz.prec(s1) if s1 <= 8 else oz.prec(0, tol=tol, smax=s1, sstart=s1)
+        fms = _time_ms(lambda: oz.oz_dgemm(h, "N", "N", m, n, k, 1.0, dA, m, dB, k, 0.0, dC, m, pf),
+                       stream, args.steps, args.warmup)
+        row = {"tol": tol, "ms": round(ms, 4), "tflops": round(flops / (ms * 1e-3) / 1e12, 2),
+               "speedup_vs_native": round(nms / ms, 3), "start_s": s1 - rep.fallbacks, "final_s": s1,
+               "estimate": rep.resid_est, "err_vs_native": err, "met": bool(err <= tol),
+               "fixed_s_ms": round(fms, 4), "fixed_s_tflops": round(flops / (fms * 1e-3) / 1e12, 2)}
+        print(json.dumps(row), flush=True)
+        rows.append(row)
+    oz.oz_destroy(h)
+    print(json.dumps({"workload": "wide-range dgemm 4096x4096x8192 (rows/cols x 10^U(-8,8)), tolerance-driven",
+                      "native_ms": round(nms, 4), "native_tflops": round(flops / (nms * 1e-3) / 1e12, 2),
+                      "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="zgemm4096", choices=["zgemm4096", "batch512", "select"])
+    ap.add_argument("--workload", default="zgemm4096", choices=["zgemm4096", "batch512", "select", "sweep", "wide_tol"])
     ap.add_argument("--select-data", default="normal,spread")
     ap.add_argument("--select-tols", default="1e-10,1e-12,1e-14")
+    ap.add_argument("--sweep-n", default="2048,4096")
+    ap.add_argument("--wide-tols", default="1e-6,1e-10,1e-14")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
@@ -300,6 +425,10 @@ def main():
         return bench_batch(args)
     if args.workload == "select":
         return bench_select(args)
+    if args.workload == "sweep":
+        return bench_sweep(args)
+    if args.workload == "wide_tol":
+        return bench_wide_tol(args)
 
     import torch
 

@@ -1,0 +1,95 @@
+"""The full-size workloads of the benchmark table, checked on sampled entries
+against the oracle (the CPU computes only the sampled rows and columns):
+
+* ZGEMM n = 2048 and 4096 with per-row exponents in [-20, 20], s = 3 .. 8, in
+  both complex forms: sampled entries bit-exact, and the scale-weighted error
+  against the double-double product falling by about 2^7 per slice, below
+  1e-12 from s = 7 on;
+* the wide-range DGEMM 4096 x 8192 x 4096 (rows of A and columns of B scaled
+  by 10^U(-8, 8)) driven by the tolerances 1e-6, 1e-10 and 1e-14: the
+  residual estimate meets each tolerance, the sampled error is within twice
+  it, and the result is bit-exact against the oracle's incremental emulation
+  from the reported start to the reported final s."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from gpu_util import from_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def oz():
+    import paper_2503_22875_amd as mod
+    return mod
+
+
+@pytest.fixture(scope="module")
+def handle(oz):
+    torch.cuda.set_device(0)
+    h = oz.oz_create(0)
+    oz.oz_set_stream(h, torch.cuda.current_stream().cuda_stream)
+    yield h
+    oz.oz_destroy(h)
+
+
+def _samples(n, count, seed):
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(n, count, replace=False)), np.sort(rng.choice(n, count, replace=False))
+
+
+@pytest.mark.parametrize("n", [2048, 4096])
+def test_zgemm_slice_sweep(oz, handle, n):
+    A, B = workloads.zgemm_rowexp(n, seed=0)
+    dA = torch.from_numpy(A.ravel(order="F")).cuda()
+    dB = torch.from_numpy(B.ravel(order="F")).cuda()
+    dC = torch.zeros(n * n, dtype=torch.complex128, device="cuda")
+    rows, cols = _samples(n, 12, n)
+    dd = oracle.gemm_dd("N", "N", A, B, rows=rows, cols=cols)
+    wa = np.maximum(np.abs(A.real), np.abs(A.imag)).max(1)[rows]
+    wb = np.maximum(np.abs(B.real), np.abs(B.imag)).max(0)[cols]
+    errs = {}
+    for zmode in (4, 3):
+        for s in range(3, 9):
+            print("sweep n=%d zmode=%d s=%d" % (n, zmode, s), flush=True)
+            oz.oz_zgemm(handle, "N", "N", n, n, n, 1.0, dA, n, dB, n, 0.0, dC, n, oz.prec(s, zmode=zmode))
+            torch.cuda.synchronize()
+            got = from_dev(dC, n, n, n)[np.ix_(rows, cols)]
+            want = (oracle.emu_zgemm3("N", "N", A, B, s, rows=rows, cols=cols) if zmode == 3
+                    else oracle.emu_gemm("N", "N", A, B, s, rows=rows, cols=cols))
+            assert np.array_equal(got, want), (zmode, s)
+            errs[zmode, s] = oracle.weighted_error(got, dd, wa, wb)
+        print("n=%d zmode=%d errors:" % (n, zmode), ["%.2g" % errs[zmode, s] for s in range(3, 9)])
+        for s in range(3, 7):
+            assert 2 ** 5 < errs[zmode, s] / errs[zmode, s + 1] < 2 ** 8.5, (zmode, s)
+        assert errs[zmode, 7] < 1e-12 and errs[zmode, 6] > 1e-12
+
+
+@pytest.mark.parametrize("tol", [1e-6, 1e-10, 1e-14])
+def test_wide_range_dgemm_tolerance(oz, handle, tol):
+    A, B = workloads.dgemm_wide(seed=0)
+    m, k = A.shape
+    n = B.shape[1]
+    dA = torch.from_numpy(A.ravel(order="F")).cuda()
+    dB = torch.from_numpy(B.ravel(order="F")).cuda()
+    dC = torch.zeros(m * n, dtype=torch.float64, device="cuda")
+    print("wide tol %g" % tol, flush=True)
+    st, rep = oz.oz_dgemm(handle, "N", "N", m, n, k, 1.0, dA, m, dB, k, 0.0, dC, m, oz.prec(0, tol=tol),
+                          report=True)
+    assert st == 0 and rep.status == 0
+    s0, s1 = rep.slices_used - rep.fallbacks, rep.slices_used
+    print("wide tol %g: start %d, final %d, estimate %.3g" % (tol, s0, s1, rep.resid_est))
+    rows, cols = _samples(4096, 16, 7)
+    got = from_dev(dC, m, n, m)[np.ix_(rows, cols)]
+    want = oracle.emu_gemm("N", "N", A, B, s0, s_to=s1, kc=oracle.kchunk(12), rows=rows, cols=cols)
+    assert np.array_equal(got, want)
+    dd = oracle.gemm_dd("N", "N", A, B, rows=rows, cols=cols)
+    err = oracle.weighted_error(got, dd, np.abs(A).max(1)[rows], np.abs(B).max(0)[cols])
+    print("wide tol %g: sampled weighted error %.3g" % (tol, err))
+    # the check's estimate meets the tolerance; the true error is within the
+    # estimate's factor-of-2 spread of it
+    assert rep.resid_est <= tol
+    assert err <= 2 * tol, (err, tol)
