@@ -68,7 +68,8 @@ struct Plan {
     oz::SliceLayout la, lb;
     int64_t nva, nvb;
     size_t off_maxa, off_maxb, off_ea, off_fb, off_sa, off_sb;
-    size_t off_acc, off_msa, off_msb, off_t, off_u, off_diff, off_ref, off_norms, off_sel, total;
+    size_t off_acc, off_msa, off_msb, off_t, off_u, off_diff, off_ref, off_norms, off_sel, off_part1, off_part2,
+        total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
@@ -92,6 +93,7 @@ Plan make_plan(int cplx, int64_t m, int64_t n, int64_t k, int s_lay, bool tol_bu
     p.off_sa = take(static_cast<size_t>(s_lay) * p.la.rows_pad * p.la.kpad);
     p.off_sb = take(static_cast<size_t>(s_lay) * p.lb.rows_pad * p.lb.kpad);
     p.off_acc = p.off_msa = p.off_msb = p.off_t = p.off_u = p.off_diff = p.off_ref = p.off_norms = p.off_sel = 0;
+    p.off_part1 = p.off_part2 = 0;
     if (tol_bufs) {
         p.off_acc = take(sizeof(double) * static_cast<size_t>(p.la.rows_pad) * p.lb.rows_pad);
         p.off_msa = take(sizeof(double) * static_cast<size_t>(m));
@@ -102,6 +104,8 @@ Plan make_plan(int cplx, int64_t m, int64_t n, int64_t k, int s_lay, bool tol_bu
         p.off_ref = take(sizeof(double) * 2 * static_cast<size_t>(m));
         p.off_norms = take(sizeof(double) * 2);
         p.off_sel = take(oz_learned_scratch_bytes());
+        p.off_part1 = take(oz::check_part_bytes(m, n, k));
+        p.off_part2 = take(oz::check_part_bytes(m, n, k));
     }
     p.total = o;
     return p;
@@ -209,8 +213,8 @@ bool grid_fits(const Plan& p) {
 }
 
 // Mean over vectors of the per-vector mean square of x * 2^-E (stats kernel).
-int vector_msq(oz_handle_t h, const oz::OperandView& v, const uint64_t* mx, double* ms, double* mean) {
-    if (oz::launch_vec_stats(v, mx, ms, h->stream) != hipSuccess) return OZ_ERR_HIP;
+int vector_msq(oz_handle_t h, const oz::OperandView& v, const uint64_t* mx, double* ms, double* part, double* mean) {
+    if (oz::launch_vec_stats(v, mx, ms, part, h->stream) != hipSuccess) return OZ_ERR_HIP;
     std::vector<double> host(static_cast<size_t>(v.nv));
     if (v.nv > 0 && (hipMemcpyAsync(host.data(), ms, sizeof(double) * v.nv, hipMemcpyDeviceToHost, h->stream) !=
                          hipSuccess ||
@@ -224,10 +228,10 @@ int vector_msq(oz_handle_t h, const oz::OperandView& v, const uint64_t* mx, doub
 
 // Smallest s in [1, smax] whose rule estimate meets tol (smax if none does).
 int rule_slices(oz_handle_t h, const oz::OperandView& va, const oz::OperandView& vb, const uint64_t* maxa,
-                const uint64_t* maxb, double* msa, double* msb, double tol, int smax, int* s_out) {
+                const uint64_t* maxb, double* msa, double* msb, double* part, double tol, int smax, int* s_out) {
     double ma = 0.0, mb = 0.0;
-    int st = vector_msq(h, va, maxa, msa, &ma);
-    if (!st) st = vector_msq(h, vb, maxb, msb, &mb);
+    int st = vector_msq(h, va, maxa, msa, part, &ma);
+    if (!st) st = vector_msq(h, vb, maxb, msb, part, &mb);
     if (st) return st;
     if (!(ma > 0.0) || !(mb > 0.0)) {  // a zero operand: every s is exact
         *s_out = 1;
@@ -473,7 +477,8 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
                                   ws + p.off_sel, &s);
             if (st) return st;
         } else {
-            st = rule_slices(h, va, vb, maxa, maxb, msa, msb, tol, smax, &s);
+            st = rule_slices(h, va, vb, maxa, maxb, msa, msb, reinterpret_cast<double*>(ws + p.off_part1), tol, smax,
+                             &s);
             if (st) return st;
         }
         // (2) digit planes 1..s, then emulate at s into the raw FP64 sums
@@ -501,6 +506,8 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
         c.diff = reinterpret_cast<double*>(ws + p.off_diff);
         c.ref = reinterpret_cast<double*>(ws + p.off_ref);
         c.norms = reinterpret_cast<double*>(ws + p.off_norms);
+        c.part1 = reinterpret_cast<double*>(ws + p.off_part1);
+        c.part2 = reinterpret_cast<double*>(ws + p.off_part2);
         int fallbacks = 0;
         double eps = 0.0;
         for (;;) {
@@ -790,6 +797,8 @@ int oz_select_slices(oz_handle_t h, char transa, char transb, int64_t m, int64_t
     o = align256(o + sizeof(double) * m);
     const size_t off_sb = o;
     o = align256(o + sizeof(double) * n);
+    const size_t off_part = o;
+    o = align256(o + oz::check_part_bytes(m, n, k));
     int st = ensure_ws(h, o);
     if (st) return st;
     char* ws = static_cast<char*>(h->ws);
@@ -803,7 +812,7 @@ int oz_select_slices(oz_handle_t h, char transa, char transb, int64_t m, int64_t
     if (e != hipSuccess) return OZ_ERR_HIP;
     int s = 0;
     st = rule_slices(h, va, vb, maxa, maxb, reinterpret_cast<double*>(ws + off_sa),
-                     reinterpret_cast<double*>(ws + off_sb), tol, smax, &s);
+                     reinterpret_cast<double*>(ws + off_sb), reinterpret_cast<double*>(ws + off_part), tol, smax, &s);
     if (st) return st;
     *s_out = s;
     return OZ_OK;

@@ -8,11 +8,17 @@
 //   y2 = D1 * op(A) * (op(B) * (D2 * sigma))
 // are formed in double-double arithmetic, and
 //   eps_est = || y1 - y2 || / || y2 ||
+// A single product splits each of its three reductions (op(B) t, the rows of
+// op(A) against u, the rows of C_emu against t) over many blocks with
+// fixed-order partial sums; a batch of small products runs one block per 64
+// vectors of each product.
 // estimates the scale-weighted Frobenius error || D1 (C_emu - AB) D2 ||_F /
 // || D1 AB D2 ||_F (for +-1 entries E||X sigma||^2 = ||X||_F^2).  Both sides use
 // the same rounded weights t_j = D2_jj * sigma_j and w_i = D1_ii, so y1 - y2
 // carries the emulation error only.  The work is O(mk + kn + mn), against
 // O(mnk) for the product itself.
+#include <algorithm>
+
 #include "oz_internal.h"
 
 namespace oz {
@@ -60,32 +66,6 @@ __device__ __forceinline__ void load_elem(const OperandView& op, int64_t v, int6
     im = op.cplx ? (op.conj ? -e[1] : e[1]) : 0.0;
 }
 
-// ---- per-vector mean square of x * 2^-E ------------------------------------
-// One block per 64 vectors; 4 waves split the terms; fixed-order reduction.
-__global__ __launch_bounds__(256) void vec_stats_kernel(OperandView op, const uint64_t* maxbits, double* ms) {
-    __shared__ double red[4][64];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t v = static_cast<int64_t>(blockIdx.x) * 64 + lane;
-    double acc = 0.0;
-    if (v < op.nv) {
-        const uint64_t mb = maxbits[v];
-        int E = 0;
-        if (mb != 0 && mb < 0x7ff0000000000000ull) frexp(max_of_bits(mb), &E);
-        for (int64_t l = wave; l < op.k; l += 4) {
-            double re, im;
-            load_elem(op, v, l, re, im);
-            const double a = ldexp(re, -E), b = ldexp(im, -E);
-            acc += a * a + b * b;
-        }
-    }
-    red[wave][lane] = acc;
-    __syncthreads();
-    if (wave == 0 && v < op.nv) {
-        const double t = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
-        ms[v] = op.k > 0 ? t / (static_cast<double>(op.k) * (op.cplx ? 2.0 : 1.0)) : 0.0;
-    }
-}
-
 // ---- t_j = sigma_j / max|op(B)_:j| ------------------------------------------
 __device__ __forceinline__ void weights_body(const CheckArgs& c, int64_t j) {
     if (j >= c.opb.nv) return;
@@ -93,8 +73,8 @@ __device__ __forceinline__ void weights_body(const CheckArgs& c, int64_t j) {
     c.t[j] = mx > 0.0 ? rademacher(c.seed, j) / mx : 0.0;
 }
 
-// ---- u = op(B) t in double-double; u[l] = (re.hi, re.lo, im.hi, im.lo) ------
-// Block: 64 terms (lanes) x 4 parts (waves); part w sums the columns
+// ---- many products: u = op(B) t in double-double; u[l] = (re.hi, re.lo,
+// im.hi, im.lo).  Block: 64 terms (lanes) x 4 parts (waves); part w sums the columns
 // j = w, w + 4, ...; the four partial sums are added in part order.
 __device__ __forceinline__ dd dd_add(dd a, dd b) {
     const dd s = two_sum(a.hi, b.hi);
@@ -134,7 +114,7 @@ __device__ __forceinline__ void gemv_b_body(const CheckArgs& c, int64_t lb) {
     c.u[4 * l + 3] = si.lo;
 }
 
-// ---- per row i of op(A): y2 = w_i op(A)_i: u, y1 = w_i sum_j C_emu_ij t_j ----
+// ---- many products, per row i of op(A): y2 = w_i op(A)_i: u, y1 = w_i sum_j C_emu_ij t_j
 // Writes diff[i] = y1 - y2 and ref[i] = y2 (real, or real and imaginary parts
 // at 2i, 2i+1 for complex).  Block: 64 rows (lanes) x 4 parts (waves); part w
 // takes the terms l = w, w + 4, ... and the columns j = w, w + 4, ...; the
@@ -197,6 +177,216 @@ __device__ __forceinline__ void rows_body(const CheckArgs& c, int64_t rb) {
     } else {
         y1i = dd_mul_d(dd_norm(y1i), w);
         y2i = dd_mul_d(dd_norm(y2i), w);
+        c.diff[2 * i] = dd_sub_to_d(y1r, y2r);
+        c.diff[2 * i + 1] = dd_sub_to_d(y1i, y2i);
+        c.ref[2 * i] = y2r.hi + y2r.lo;
+        c.ref[2 * i + 1] = y2i.hi + y2i.lo;
+    }
+}
+
+// ---- split reductions (single product) --------------------------------------
+// A reduction of R outputs over L terms, o[r] = sum_c f(r, c), runs in one of
+// two shapes chosen by which index is contiguous in memory:
+//   out: one thread per output, consecutive outputs on consecutive lanes, the
+//        terms cut into nch chunks along grid.y;
+//   in:  one wave per output, consecutive terms on consecutive lanes, the
+//        lanes' sums merged by a fixed butterfly; nch chunks along grid.y.
+// Each (chunk, output) partial goes to part[chunk * R + r]; a second pass adds
+// the chunks in chunk order.  The result is deterministic for a given shape.
+struct DC {
+    dd re, im;
+};
+__device__ __forceinline__ void acc_zero(DC& a) { a = {{0.0, 0.0}, {0.0, 0.0}}; }
+__device__ __forceinline__ void acc_zero(double& a) { a = 0.0; }
+__device__ __forceinline__ DC acc_merge(DC a, DC b) { return {dd_add(a.re, b.re), dd_add(a.im, b.im)}; }
+__device__ __forceinline__ double acc_merge(double a, double b) { return a + b; }
+__device__ __forceinline__ DC acc_xor(DC a, int off) {
+    return {{__shfl_xor(a.re.hi, off), __shfl_xor(a.re.lo, off)}, {__shfl_xor(a.im.hi, off), __shfl_xor(a.im.lo, off)}};
+}
+__device__ __forceinline__ double acc_xor(double a, int off) { return __shfl_xor(a, off); }
+
+// u = op(B) t: output = term l of op(B), reduction over its columns j
+struct OpU {
+    OperandView opb;
+    const double* t;
+    __device__ int64_t row(int64_t l) const { return l; }
+    __device__ void add(DC& a, int64_t l, int64_t j) const {
+        double re, im;
+        load_elem(opb, j, l, re, im);
+        const double tj = t[j];
+        a.re = dd_add_prod(a.re, re, tj);
+        a.im = dd_add_prod(a.im, im, tj);
+    }
+};
+
+// y2 = op(A)_i: u: output = row i of op(A), reduction over its terms l
+struct OpY2 {
+    OperandView opa;
+    const double* u;
+    __device__ int64_t row(int64_t i) const { return i; }
+    __device__ void add(DC& a, int64_t i, int64_t l) const {
+        double ar, ai;
+        load_elem(opa, i, l, ar, ai);
+        const double urh = u[4 * l], url = u[4 * l + 1], uih = u[4 * l + 2], uil = u[4 * l + 3];
+        a.re = dd_add_prod(a.re, ar, urh);
+        a.re = dd_add_prod(a.re, ar, url);
+        if (opa.cplx) {
+            a.re = dd_add_prod(a.re, -ai, uih);
+            a.re = dd_add_prod(a.re, -ai, uil);
+            a.im = dd_add_prod(a.im, ar, uih);
+            a.im = dd_add_prod(a.im, ar, uil);
+            a.im = dd_add_prod(a.im, ai, urh);
+            a.im = dd_add_prod(a.im, ai, url);
+        }
+    }
+};
+
+// y1 = sum_j ldexp(acc_ij, E_i + F_j) t_j: output = row i, reduction over j
+struct RowY1 {
+    int64_t r_re;
+    int32_t e;
+};
+struct OpY1 {
+    const double* acc;
+    int64_t Mp;
+    const int32_t* EA;
+    const int32_t* FB;
+    const double* t;
+    int cplx;
+    __device__ RowY1 row(int64_t i) const {
+        return {cplx ? 32 * (i >> 4) + 16 * ((i >> 3) & 1) + (i & 7) : i, EA[i]};
+    }
+    __device__ void add(DC& a, const RowY1& r, int64_t j) const {
+        const int ef = r.e + FB[j];
+        const double tj = t[j];
+        a.re = dd_add_prod(a.re, ldexp(acc[j * Mp + r.r_re], ef), tj);
+        if (cplx) a.im = dd_add_prod(a.im, ldexp(acc[j * Mp + r.r_re + 8], ef), tj);
+    }
+};
+
+// sum over the terms of vector v of |x * 2^-E_v|^2 (the rule's statistic)
+struct RowMsq {
+    int64_t v;
+    int E;
+};
+struct OpMsq {
+    OperandView op;
+    const uint64_t* maxbits;
+    __device__ RowMsq row(int64_t v) const {
+        const uint64_t mb = maxbits[v];
+        int E = 0;
+        if (mb != 0 && mb < 0x7ff0000000000000ull) frexp(max_of_bits(mb), &E);
+        return {v, E};
+    }
+    __device__ void add(double& a, const RowMsq& r, int64_t l) const {
+        double re, im;
+        load_elem(op, r.v, l, re, im);
+        const double x = ldexp(re, -r.E), y = ldexp(im, -r.E);
+        a += x * x + y * y;
+    }
+};
+
+template <class Op, class Acc>
+__global__ __launch_bounds__(256) void red_out_kernel(Op op, int64_t R, int64_t L, int64_t chunk, Acc* part) {
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (r >= R) return;
+    const int64_t c0 = static_cast<int64_t>(blockIdx.y) * chunk;
+    const int64_t c1 = c0 + chunk < L ? c0 + chunk : L;
+    Acc a;
+    acc_zero(a);
+    const auto rs = op.row(r);
+    for (int64_t c = c0; c < c1; ++c) op.add(a, rs, c);
+    part[static_cast<int64_t>(blockIdx.y) * R + r] = a;
+}
+
+template <class Op, class Acc>
+__global__ __launch_bounds__(256) void red_in_kernel(Op op, int64_t R, int64_t L, int64_t chunk, Acc* part) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (r >= R) return;  // uniform over the wave; no barrier follows
+    const int64_t c0 = static_cast<int64_t>(blockIdx.y) * chunk;
+    const int64_t c1 = c0 + chunk < L ? c0 + chunk : L;
+    Acc a;
+    acc_zero(a);
+    const auto rs = op.row(r);
+    for (int64_t c = c0 + lane; c < c1; c += 64) op.add(a, rs, c);
+    for (int off = 32; off > 0; off >>= 1) a = acc_merge(a, acc_xor(a, off));
+    if (lane == 0) part[static_cast<int64_t>(blockIdx.y) * R + r] = a;
+}
+
+// Chunk sums: a block takes 32 outputs (consecutive lanes, coalesced reads)
+// x 8 chunk groups; group g adds the chunks g, g + 8, ... in order, and the 8
+// group sums are merged in group order.
+constexpr int kSumOut = 32;
+constexpr int kSumGroups = 8;
+
+template <class Acc>
+__device__ __forceinline__ Acc group_sum(const Acc* part, int64_t R, int64_t nch, int64_t r, int g) {
+    Acc a;
+    acc_zero(a);
+    if (r < R)
+        for (int64_t q = g; q < nch; q += kSumGroups) a = acc_merge(a, part[q * R + r]);
+    return a;
+}
+
+template <class Acc>
+__device__ __forceinline__ Acc merge_groups(Acc a, Acc (*red)[kSumOut], int o) {
+    for (int q = 1; q < kSumGroups; ++q) a = acc_merge(a, red[q][o]);
+    return a;
+}
+
+// u[l] = (re.hi, re.lo, im.hi, im.lo) of the chunk sum, normalised
+__global__ __launch_bounds__(256) void u_sum_kernel(const DC* part, int64_t R, int64_t nch, double* u) {
+    __shared__ DC red[kSumGroups][kSumOut];
+    const int o = threadIdx.x % kSumOut, g = threadIdx.x / kSumOut;
+    const int64_t l = static_cast<int64_t>(blockIdx.x) * kSumOut + o;
+    DC a = group_sum(part, R, nch, l, g);
+    red[g][o] = a;
+    __syncthreads();
+    if (g != 0 || l >= R) return;
+    a = merge_groups(a, red, o);
+    const dd re = dd_norm(a.re), im = dd_norm(a.im);
+    u[4 * l] = re.hi;
+    u[4 * l + 1] = re.lo;
+    u[4 * l + 2] = im.hi;
+    u[4 * l + 3] = im.lo;
+}
+
+__global__ __launch_bounds__(256) void msq_sum_kernel(const double* part, int64_t R, int64_t nch, double denom,
+                                                      double* ms) {
+    __shared__ double red[kSumGroups][kSumOut];
+    const int o = threadIdx.x % kSumOut, g = threadIdx.x / kSumOut;
+    const int64_t v = static_cast<int64_t>(blockIdx.x) * kSumOut + o;
+    double a = group_sum(part, R, nch, v, g);
+    red[g][o] = a;
+    __syncthreads();
+    if (g != 0 || v >= R) return;
+    a = merge_groups(a, red, o);
+    ms[v] = denom > 0.0 ? a / denom : 0.0;
+}
+
+// diff[i] = w_i (y1 - y2), ref[i] = w_i y2 from the chunk sums of y1 and y2
+__global__ __launch_bounds__(256) void rows_combine_kernel(CheckArgs c, int64_t nch1, int64_t nch2) {
+    __shared__ DC red1[kSumGroups][kSumOut], red2[kSumGroups][kSumOut];
+    const int o = threadIdx.x % kSumOut, g = threadIdx.x / kSumOut;
+    const int64_t m = c.opa.nv;
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kSumOut + o;
+    DC y1 = group_sum(reinterpret_cast<const DC*>(c.part1), m, nch1, i, g);
+    DC y2 = group_sum(reinterpret_cast<const DC*>(c.part2), m, nch2, i, g);
+    red1[g][o] = y1;
+    red2[g][o] = y2;
+    __syncthreads();
+    if (g != 0 || i >= m) return;
+    y1 = merge_groups(y1, red1, o);
+    y2 = merge_groups(y2, red2, o);
+    const double mx = max_of_bits(c.maxa[i]);
+    const double w = mx > 0.0 ? 1.0 / mx : 0.0;
+    const dd y1r = dd_mul_d(dd_norm(y1.re), w), y2r = dd_mul_d(dd_norm(y2.re), w);
+    if (!c.opa.cplx) {
+        c.diff[i] = dd_sub_to_d(y1r, y2r);
+        c.ref[i] = y2r.hi + y2r.lo;
+    } else {
+        const dd y1i = dd_mul_d(dd_norm(y1.im), w), y2i = dd_mul_d(dd_norm(y2.im), w);
         c.diff[2 * i] = dd_sub_to_d(y1r, y2r);
         c.diff[2 * i + 1] = dd_sub_to_d(y1i, y2i);
         c.ref[2 * i] = y2r.hi + y2r.lo;
@@ -272,8 +462,6 @@ __device__ __forceinline__ void finalize_body(const double* acc, int64_t Mp, con
 
 // ---- kernels: one product -------------------------------------------------------
 __global__ void weights_kernel(CheckArgs c) { weights_body(c, static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x); }
-__global__ __launch_bounds__(256) void gemv_b_kernel(CheckArgs c) { gemv_b_body(c, blockIdx.x); }
-__global__ __launch_bounds__(256) void rows_kernel(CheckArgs c) { rows_body(c, blockIdx.x); }
 __global__ __launch_bounds__(256) void norms_kernel(const double* diff, const double* ref, int64_t len,
                                                     double* out) {
     norms_body(diff, ref, len, out);
@@ -319,19 +507,92 @@ __global__ void finalize_batched_kernel(const FinalArgs* f, const int32_t* activ
 
 }  // namespace
 
-hipError_t launch_vec_stats(const OperandView& op, const uint64_t* maxbits, double* ms, hipStream_t st) {
+// ---- chunking of the split reductions ----------------------------------------
+namespace {
+constexpr int64_t kOutBlocks = 2048;  // target blocks of the output-contiguous shape
+constexpr int64_t kInWaves = 8192;    // target waves of the term-contiguous shape
+
+struct RedSplit {
+    bool out;
+    int64_t L, nch, chunk;  // terms, chunks, terms per chunk (nch * chunk >= L)
+};
+
+RedSplit red_split(int64_t R, int64_t L, bool out) {
+    int64_t nch = 1;
+    if (L > 0 && R > 0) {
+        if (out) {  // at least 16 terms per thread
+            nch = std::min((kOutBlocks + (R + 255) / 256 - 1) / ((R + 255) / 256), (L + 15) / 16);
+        } else {    // at least 8 terms per lane
+            nch = std::min((kInWaves + R - 1) / R, (L + 511) / 512);
+        }
+        nch = std::max<int64_t>(nch, 1);
+    }
+    const int64_t chunk = L > 0 ? (L + nch - 1) / nch : 0;
+    if (L > 0) nch = (L + chunk - 1) / chunk;  // no empty chunk
+    return {out, L, nch, chunk};
+}
+
+template <class Op, class Acc>
+hipError_t launch_red(const Op& op, int64_t R, const RedSplit& sp, Acc* part, hipStream_t st) {
+    if (R <= 0) return hipSuccess;
+    if ((R + 3) / 4 > INT32_MAX || sp.nch > 65535) return hipErrorInvalidValue;
+    if (sp.out) {
+        dim3 grid(static_cast<unsigned>((R + 255) / 256), static_cast<unsigned>(sp.nch));
+        hipLaunchKernelGGL((red_out_kernel<Op, Acc>), grid, dim3(256), 0, st, op, R, sp.L, sp.chunk, part);
+    } else {
+        dim3 grid(static_cast<unsigned>((R + 3) / 4), static_cast<unsigned>(sp.nch));
+        hipLaunchKernelGGL((red_in_kernel<Op, Acc>), grid, dim3(256), 0, st, op, R, sp.L, sp.chunk, part);
+    }
+    return hipGetLastError();
+}
+}  // namespace
+
+int64_t red_entries(int64_t R, int64_t L) {
+    const RedSplit a = red_split(R, L, true), b = red_split(R, L, false);
+    return std::max(a.nch, b.nch) * std::max<int64_t>(R, 1);
+}
+
+size_t check_part_bytes(int64_t m, int64_t n, int64_t k) {
+    const int64_t e = std::max(std::max(red_entries(k, n), red_entries(m, n)),
+                               std::max(red_entries(m, k), red_entries(n, k)));
+    return sizeof(double) * 4 * static_cast<size_t>(e);
+}
+
+hipError_t launch_vec_stats(const OperandView& op, const uint64_t* maxbits, double* ms, double* part, hipStream_t st) {
     if (op.nv <= 0) return hipSuccess;
-    hipLaunchKernelGGL(vec_stats_kernel, dim3(static_cast<unsigned>((op.nv + 63) / 64)), dim3(256), 0, st, op, maxbits,
-                       ms);
+    const RedSplit sp = red_split(op.nv, op.k, op.sv == 1);
+    hipError_t e = launch_red(OpMsq{op, maxbits}, op.nv, sp, part, st);
+    if (e != hipSuccess) return e;
+    const double denom = static_cast<double>(op.k) * (op.cplx ? 2.0 : 1.0);
+    hipLaunchKernelGGL(msq_sum_kernel, dim3(static_cast<unsigned>((op.nv + 31) / 32)), dim3(256), 0, st, part, op.nv,
+                       sp.nch, denom, ms);
     return hipGetLastError();
 }
 
 hipError_t launch_residual(const CheckArgs& c, hipStream_t st) {
     const int64_t n = c.opb.nv, k = c.opa.k, m = c.opa.nv;
     if (m <= 0 || n <= 0) return hipSuccess;
+    DC* p1 = reinterpret_cast<DC*>(c.part1);
+    DC* p2 = reinterpret_cast<DC*>(c.part2);
     hipLaunchKernelGGL(weights_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, c);
-    if (k > 0) hipLaunchKernelGGL(gemv_b_kernel, dim3(static_cast<unsigned>((k + 63) / 64)), dim3(256), 0, st, c);
-    hipLaunchKernelGGL(rows_kernel, dim3(static_cast<unsigned>((m + 63) / 64)), dim3(256), 0, st, c);
+    hipError_t e = hipGetLastError();
+    // u = op(B) t over the n columns (partials in part1), then summed into u
+    if (e == hipSuccess && k > 0) {
+        const RedSplit su = red_split(k, n, c.opb.sl == 1);
+        e = launch_red(OpU{c.opb, c.t}, k, su, p1, st);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(u_sum_kernel, dim3(static_cast<unsigned>((k + 31) / 32)), dim3(256), 0, st, p1, k,
+                               su.nch, c.u);
+            e = hipGetLastError();
+        }
+    }
+    // y1 over the n columns of the FP64 sums (part1), y2 over the k terms (part2)
+    const RedSplit s1 = red_split(m, n, true), s2 = red_split(m, k, c.opa.sv == 1);
+    if (e == hipSuccess) e = launch_red(OpY1{c.acc, c.Mp, c.EA, c.FB, c.t, c.opa.cplx}, m, s1, p1, st);
+    if (e == hipSuccess) e = launch_red(OpY2{c.opa, c.u}, m, s2, p2, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(rows_combine_kernel, dim3(static_cast<unsigned>((m + 31) / 32)), dim3(256), 0, st, c, s1.nch,
+                       s2.nch);
     const int64_t len = c.opa.cplx ? 2 * m : m;
     hipLaunchKernelGGL(norms_kernel, dim3(1), dim3(256), 0, st, c.diff, c.ref, len, c.norms);
     return hipGetLastError();

@@ -154,7 +154,14 @@ hipError_t launch_gemm_stream_persistent(const GemmArgs* probs, const TileItem* 
                                          bool top, int blocks, hipStream_t st);
 
 // Tolerance-driven calls: operand statistics, residual check, final scaling.
-hipError_t launch_vec_stats(const OperandView& op, const uint64_t* maxbits, double* ms, hipStream_t st);
+// Per-vector mean square of x * 2^-E (E from maxbits); part: scratch of
+// red_entries(nv, k) doubles for the per-chunk partial sums.
+hipError_t launch_vec_stats(const OperandView& op, const uint64_t* maxbits, double* ms, double* part, hipStream_t st);
+// (chunk, output) entries a split reduction of R outputs over L terms may use.
+int64_t red_entries(int64_t R, int64_t L);
+// Bytes of each of the two partial-sum buffers of a single-product check
+// (and of the statistics pass) of an m x n x k product.
+size_t check_part_bytes(int64_t m, int64_t n, int64_t k);
 struct CheckArgs {
     OperandView opa, opb;      // op(A) rows and op(B) columns as vectors
     const uint64_t* maxa;      // max |.| bits per row of op(A) / column of op(B)
@@ -169,6 +176,8 @@ struct CheckArgs {
     double* diff;              // 2m     : y1 - y2
     double* ref;               // 2m     : y2
     double* norms;             // 2      : sum diff^2, sum ref^2
+    double* part1;             // check_part_bytes: per-chunk partial sums (single product)
+    double* part2;
 };
 hipError_t launch_residual(const CheckArgs& c, hipStream_t st);
 hipError_t launch_finalize(const double* acc, int64_t Mp, const int32_t* EA, const int32_t* FB, double* C,
