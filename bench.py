@@ -412,6 +412,8 @@ def main():
     ap.add_argument("--slices", type=int, default=7)
     ap.add_argument("--zmode", type=int, default=3, choices=[3, 4],
                     help="complex form: 3 = three real products (default), 4 = one real product over the two-row form")
+    ap.add_argument("--kernel", type=int, default=0, choices=[0, 1, 2, 4],
+                    help="GEMM kernel shape (as oz_prec_t.kernel; 0 chooses by size)")
     ap.add_argument("--cpu-rows", type=int, default=512)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (reference for HBM byte counters)")
@@ -444,7 +446,7 @@ def main():
     dC = torch.zeros(n * n, dtype=torch.complex128, device="cuda")
     h = oz.oz_create(0)
     oz.oz_set_stream(h, stream.cuda_stream)
-    p = oz.prec(s, zmode=args.zmode)
+    p = oz.prec(s, zmode=args.zmode, kernel=args.kernel)
 
     def step():
         oz.oz_zgemm(h, "N", "N", n, n, n, 1.0, dA, n, dB, n, 0.0, dC, n, p)
