@@ -75,6 +75,26 @@ __device__ __forceinline__ int digit(const Sig& g, int p /* 1-based */) {
     return g.neg ? -static_cast<int>(t) : static_cast<int>(t);
 }
 
+// The first 64 fractional bits of |x| * 2^-E, floor(M * 2^(64 - sh0)): digit
+// p <= 9 is bits [64 - 7p, 71 - 7p) of it (one shift and mask per digit).
+// |x| < 2^E gives sh0 >= 53 for a normal x (a left shift of at most 11) and
+// sh0 >= bitlength(M) for a subnormal one, so the left shift never overflows.
+constexpr int kWindowDigits = 9;
+__device__ __forceinline__ uint64_t frac_window(const Sig& g) {
+    const int sh = g.sh0 - 64;
+    if (sh >= 64) return 0;
+    if (sh >= 0) return g.M >> sh;
+    return g.M << (-sh);
+}
+
+// Digit p (1-based) of x under scale exponent E; W = frac_window(sig_of(x, E)).
+// Digits past the window are taken from the significand again.
+__device__ __forceinline__ int digit_of(double x, int E, uint64_t W, int p) {
+    if (p > kWindowDigits) return digit(sig_of(x, E), p);
+    const int t = static_cast<int>(static_cast<uint32_t>(W >> (64 - 7 * p)) & 127u);
+    return __double_as_longlong(x) < 0 ? -t : t;
+}
+
 __global__ void zero_u64_kernel(uint64_t* p, int64_t n) {
     int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;
@@ -182,9 +202,9 @@ __device__ __forceinline__ void digits_body(const OperandView& op, const uint64_
             x[e] = re;
         }
     }
-    Sig g[8];
+    uint64_t w[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) g[e] = sig_of(x[e], ex);
+    for (int e = 0; e < 8; ++e) w[e] = frac_window(sig_of(x[e], ex));
 
     if (CPLX && SIDE_A) {
         // real-part row holds (ar, -ai), imaginary-part row holds (ai, ar)
@@ -195,7 +215,8 @@ __device__ __forceinline__ void digits_body(const OperandView& op, const uint64_
             int dre[8], dim[8];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int ar = digit(g[2 * e], p + 1), ai = digit(g[2 * e + 1], p + 1);
+                const int ar = digit_of(x[2 * e], ex, w[2 * e], p + 1);
+                const int ai = digit_of(x[2 * e + 1], ex, w[2 * e + 1], p + 1);
                 dre[2 * e] = ar;
                 dre[2 * e + 1] = -ai;
                 dim[2 * e] = ai;
@@ -209,7 +230,7 @@ __device__ __forceinline__ void digits_body(const OperandView& op, const uint64_
         for (int p = p_lo; p < p_hi; ++p) {
             int d[8];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) d[e] = digit(g[e], p + 1);
+            for (int e = 0; e < 8; ++e) d[e] = digit_of(x[e], ex, w[e], p + 1);
             *reinterpret_cast<uint64_t*>(slices + slice_off(t0, p, v, lay.s, lay.rows_pad)) = pack8(d);
         }
     }
@@ -339,24 +360,31 @@ __global__ __launch_bounds__(256) void digits3_kernel(OperandView op, SliceLayou
         if (live) ex[q] = exponent_of_max(o.maxbits[q][v]);
         if (live && step == 0 && sub == 0) o.E[q][v] = ex[q];
     }
-    double x[3][8];
+    // the 8 complex elements of this thread, read once
+    double re[8], im[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const int64_t l = t0 + e;
         double px[3] = {0.0, 0.0, 0.0};
         if (live && l < op.k) parts3(op, op.X + (v * op.sv + l * op.sl) * 2, px);
-#pragma unroll
-        for (int q = 0; q < 3; ++q) x[q][e] = (ex[q] == kNonFiniteExp) ? 0.0 : px[q];
+        re[e] = px[0];
+        im[e] = px[1];
     }
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-        Sig g[8];
+        const bool bad = ex[q] == kNonFiniteExp;
+        double x[8];
+        uint64_t w[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) g[e] = sig_of(x[q][e], ex[q]);
+        for (int e = 0; e < 8; ++e) {
+            // part 2 is the FP64 sum of the two parts (as in the scan)
+            x[e] = bad ? 0.0 : (q == 0 ? re[e] : q == 1 ? im[e] : re[e] + im[e]);
+            w[e] = frac_window(sig_of(x[e], ex[q]));
+        }
         for (int p = 0; p < lay.s; ++p) {
             int d[8];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) d[e] = digit(g[e], p + 1);
+            for (int e = 0; e < 8; ++e) d[e] = digit_of(x[e], ex[q], w[e], p + 1);
             *reinterpret_cast<uint64_t*>(o.slices[q] + slice_off(t0, p, v, lay.s, lay.rows_pad)) = pack8(d);
         }
     }
