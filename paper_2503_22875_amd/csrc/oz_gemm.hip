@@ -23,6 +23,8 @@
 // (32 lanes x 16 consecutive bytes) is free of bank conflicts.  The copy of
 // step ks + NST - 1 is in flight while the MFMAs of step ks run, so NST - 1
 // steps of MFMA work cover the memory latency.
+#include <type_traits>
+
 #include "oz_internal.h"
 
 namespace oz {
@@ -291,11 +293,13 @@ __device__ __forceinline__ void tile_body(const GemmArgs& g, int64_t tm, int64_t
     __syncthreads();
 
     int64_t chunk_pos = 0, chunk = 0;
-    int buf = 0;
-    for (int64_t ks = 0; ks < nsteps; ++ks) {
+    // one step on ring buffer BUF (a compile-time index, so that every LDS
+    // read is a fixed register plus an immediate offset)
+    auto step = [&](int64_t ks, auto bufc) {
+        constexpr int BUF = decltype(bufc)::value;
         const bool more = ks + NST - 1 < nsteps;
-        if (more) issue((buf + NST - 1) % NST);
-        const v4i* L = lds[buf];
+        if (more) issue((BUF + NST - 1) % NST);
+        const v4i* L = lds[BUF];
         v4i bq[S];
 #pragma unroll
         for (int q = 0; q < S; ++q) bq[q] = L[T::A_CHUNKS + (half * S + q) * T::BN + wn * 32 + row];
@@ -332,7 +336,13 @@ __device__ __forceinline__ void tile_body(const GemmArgs& g, int64_t tm, int64_t
         else
             wait_vm<0>();
         ring_barrier();
-        buf = (buf + 1 == NST) ? 0 : buf + 1;
+    };
+    static_assert(NST == 2 || NST == 3, "ring of 2 or 3 stages");
+    for (int64_t ks = 0; ks < nsteps; ks += NST) {
+        step(ks, std::integral_constant<int, 0>{});
+        if (ks + 1 < nsteps) step(ks + 1, std::integral_constant<int, 1>{});
+        if constexpr (NST == 3)
+            if (ks + 2 < nsteps) step(ks + 2, std::integral_constant<int, 2>{});
     }
     if constexpr (DIAG) return;
     if constexpr (!MULTI) {
