@@ -412,8 +412,8 @@ def main():
     ap.add_argument("--slices", type=int, default=7)
     ap.add_argument("--zmode", type=int, default=3, choices=[3, 4],
                     help="complex form: 3 = three real products (default), 4 = one real product over the two-row form")
-    ap.add_argument("--kernel", type=int, default=0, choices=[0, 1, 2, 4],
-                    help="GEMM kernel shape (as oz_prec_t.kernel; 0 chooses by size)")
+    ap.add_argument("--kernel", type=int, default=0, choices=[0, 1, 2],
+                    help="GEMM kernel shape (as oz_prec_t.kernel; 0 = the default shape)")
     ap.add_argument("--cpu-rows", type=int, default=512)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (reference for HBM byte counters)")

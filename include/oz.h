@@ -89,10 +89,11 @@ typedef struct oz_handle_s* oz_handle_t;
  *           zmode 4.  Three quarters of the INT8 work; the error is of the same
  *           order (the sums can double the scale of T3).  A row or column
  *           whose sum overflows counts as non-finite.
- *  kernel : GEMM kernel shape; 0 chooses by size, 1 = 128 x 64 block with a
- *           3-stage LDS ring, 2 = 64 x 64 block with 2 stages (both for
- *           s <= 8), 3 = per-diagonal streaming (any s; the only choice for
- *           s > 8).  Every shape gives the same bits.
+ *  kernel : GEMM kernel shape; 0 = the default (the 64 x 64 block for
+ *           s <= 8, streaming above), 1 = 128 x 64 block with a 3-stage LDS
+ *           ring, 2 = 64 x 64 block with 2 stages (both for s <= 8), 3 =
+ *           per-diagonal streaming (any s; the only choice for s > 8).  Every
+ *           shape gives the same bits.
  *  sstart : tolerance-driven calls only: the starting slice count; 0 lets
  *           `selector` choose it.
  *  selector: tolerance-driven calls with sstart == 0: 0 = the rule of

@@ -362,7 +362,7 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
         if (prec->slices < 0 || prec->slices > OZ_MAX_SLICES) return 14;
         if (prec->zmode != 0 && prec->zmode != 3 && prec->zmode != 4) return 14;
         if (cplx && prec->zmode == 3 && prec->slices == 0) return 14;  // 3M: fixed slice counts only
-        if (prec->kernel < 0 || prec->kernel > 4) return 14;
+        if (prec->kernel < 0 || prec->kernel > 3) return 14;
         if (prec->reserved != 0) return 14;
         if (prec->slices == 0) {
             tol_mode = true;
@@ -382,7 +382,7 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
     const int s_plan = tol_mode ? smax : s;  // largest slice count this call may use
     if (kc < 0 || kc % 64 != 0 || (kc > 0 && kc > kchunk_bound(s_plan))) return 14;
     if (kc == 0) kc = kchunk_bound(s_plan);
-    if (!tol_mode && s > oz::kMaxLiveSlices && (kernel == 1 || kernel == 2 || kernel == 4)) return 14;
+    if (!tol_mode && s > oz::kMaxLiveSlices && (kernel == 1 || kernel == 2)) return 14;
     if (!alpha || !beta) return OZ_ERR_ARG;
 
     if (rep) {
@@ -747,8 +747,7 @@ int oz_diag_sums(oz_handle_t h, int32_t slices, int64_t kchunk, int32_t kernel, 
                  int64_t rows_pad_b, int64_t kpad, const int8_t* slices_a, const int8_t* slices_b, int32_t* out) {
     if (!valid(h)) return OZ_ERR_HANDLE;
     if (slices < 1 || slices > OZ_MAX_SLICES) return OZ_ERR_ARG;
-    if (kernel < 0 || kernel > 4 || (slices > oz::kMaxLiveSlices && (kernel == 1 || kernel == 2 || kernel == 4)))
-        return OZ_ERR_ARG;
+    if (kernel < 0 || kernel > 3 || (slices > oz::kMaxLiveSlices && (kernel == 1 || kernel == 2))) return OZ_ERR_ARG;
     if (kchunk <= 0 || kchunk % 64 != 0 || kchunk > kchunk_bound(slices)) return OZ_ERR_ARG;
     if (rows_pad_a <= 0 || rows_pad_b <= 0 || rows_pad_a % oz::kRowPad || rows_pad_b % oz::kRowPad) return OZ_ERR_ARG;
     if (kpad <= 0 || kpad % oz::kStep) return OZ_ERR_ARG;

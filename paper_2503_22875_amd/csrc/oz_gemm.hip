@@ -362,156 +362,6 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64 * WMW * WNW, 64 * WMW *
     tile_body<S, WMW, WNW, NST, TOP, DIAG, MULTI>(g, tm, tn, lds);
 }
 
-// ---- register-pipelined form -------------------------------------------------
-// 128 x 64 block tile, 4 waves (one per SIMD), each owning a 64 x 32 sub-tile:
-// two 32 x 32 MFMA tiles that share the B operand.  The operands of step
-// ks + 1 are read from LDS into a second register set while the MFMAs of step
-// ks run, so the MFMA stream waits on neither LDS nor the barrier of its own
-// step.  The LDS ring (3 stages, the layout of the 128 x 64 form) refills a
-// buffer as soon as its stage has been read into registers: the copy of step
-// ks + 3 goes into the buffer of step ks.  Same pairs, same diagonal tiles and
-// the same FP64 fold order as tile_body, hence the same bits.
-template <int S, int U>
-struct PfCfg {
-    static constexpr int BM = 64 * U, BN = 64, NW = 4, NST = 3;
-    static constexpr int RA = 2 * S * (BM / 64);
-    static constexpr int RB = 2 * S * (BN / 64);
-    static constexpr int R = RA + RB;
-    static constexpr int A_CHUNKS = RA * 64;
-    static constexpr int STAGE = R * 64;
-    static constexpr int RHI = (R + NW - 1) / NW;
-    static constexpr int RLO = R / NW;
-};
-
-template <int S, int U, bool TOP>
-__device__ __forceinline__ void tile_body_pf(const GemmArgs& g, int64_t tm, int64_t tn,
-                                             v4i (*lds)[PfCfg<S, U>::STAGE]) {
-    using T = PfCfg<S, U>;
-    constexpr int DLO = TOP ? S - 1 : 0;
-    constexpr int ND = S - DLO;
-
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
-    const int half = lane >> 5, row = lane & 31;
-    const v4i* SA = reinterpret_cast<const v4i*>(g.SA);
-    const v4i* SB = reinterpret_cast<const v4i*>(g.SB);
-    const int64_t nsteps = g.kpad / kStep;
-
-    auto issue = [&](int64_t ks, int buf) {
-#pragma unroll
-        for (int i = 0; i < T::RHI; ++i) {
-            const int j = wave + T::NW * i;  // wave-uniform
-            if (j >= T::R) break;
-            const v4i* src;
-            if (j < T::RA) {
-                const int hp = j / (T::BM / 64), rb = j % (T::BM / 64);
-                const int64_t plane = (2 * ks + hp / S) * g.s_lay + hp % S;
-                src = SA + plane * g.Mp + tm * T::BM + rb * 64 + lane;
-            } else {
-                const int jb = j - T::RA;
-                const int hp = jb / (T::BN / 64), cb = jb % (T::BN / 64);
-                const int64_t plane = (2 * ks + hp / S) * g.s_lay + hp % S;
-                src = SB + plane * g.Np + tn * T::BN + cb * 64 + lane;
-            }
-            __builtin_amdgcn_global_load_lds((global_cvoid*)(src), (lds_void*)(&lds[buf][j * 64]), 16, 0, 0);
-        }
-    };
-    auto wait_older = [&]() {
-        if (T::R % T::NW == 0 || wave < T::R % T::NW)
-            wait_vm<T::RHI>();
-        else
-            wait_vm<T::RLO>();
-    };
-    auto load_ops = [&](int buf, v4i (&xa)[U][S], v4i (&xb)[S]) {
-        const v4i* L = lds[buf];
-#pragma unroll
-        for (int q = 0; q < S; ++q) xb[q] = L[T::A_CHUNKS + (half * S + q) * T::BN + wn * 32 + row];
-#pragma unroll
-        for (int p = 0; p < S; ++p)
-#pragma unroll
-            for (int u = 0; u < U; ++u) xa[u][p] = L[(half * S + p) * T::BM + wm * 32 * U + u * 32 + row];
-    };
-
-    v16i acc[U][ND];
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-        for (int d = 0; d < ND; ++d)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[u][d][r] = 0;
-    // consecutive MFMAs go to different accumulators (sub-tile u alternates)
-    auto mfmas = [&](const v4i (&xa)[U][S], const v4i (&xb)[S]) {
-#pragma unroll
-        for (int p = 0; p < S; ++p)
-#pragma unroll
-            for (int q = (DLO > p ? DLO - p : 0); q < S - p; ++q)
-#pragma unroll
-                for (int u = 0; u < U; ++u)
-                    acc[u][p + q - DLO] =
-                        __builtin_amdgcn_mfma_i32_32x32x32_i8(xa[u][p], xb[q], acc[u][p + q - DLO], 0, 0, 0);
-    };
-
-    // prologue: stages 0, 1, 2 in flight, all landed, stage 0 into registers;
-    // buffer 0 is refilled in step 0, after every wave has read it
-#pragma unroll
-    for (int st = 0; st < T::NST; ++st)
-        if (st < nsteps) issue(st, st);
-    wait_vm<0>();
-    ring_barrier();
-    v4i ca[U][S], cb[S], na[U][S], nb[S];
-    load_ops(0, ca, cb);
-    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-    ring_barrier();
-
-    // one step: refill the buffer of step ks with step ks + 3, read step ks + 1
-    // into (xa1, xb1), multiply step ks from (xa0, xb0); at its end the stage
-    // of step ks + 2 has landed and this wave's reads of step ks + 1 are done
-    auto step = [&](int64_t ks, int buf, const v4i (&xa0)[U][S], const v4i (&xb0)[S], v4i (&xa1)[U][S],
-                    v4i (&xb1)[S]) {
-        const bool refill = ks + T::NST < nsteps;
-        if (refill) issue(ks + T::NST, buf);
-        if (ks + 1 < nsteps) load_ops(buf + 1 == T::NST ? 0 : buf + 1, xa1, xb1);
-        mfmas(xa0, xb0);
-        if (refill)
-            wait_older();
-        else
-            wait_vm<0>();
-        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-        ring_barrier();
-    };
-    int buf = 0;
-    for (int64_t ks = 0; ks < nsteps; ks += 2) {
-        step(ks, buf, ca, cb, na, nb);
-        buf = (buf + 1 == T::NST) ? 0 : buf + 1;
-        if (ks + 1 < nsteps) {
-            step(ks + 1, buf, na, nb, ca, cb);
-            buf = (buf + 1 == T::NST) ? 0 : buf + 1;
-        }
-    }
-
-    const int64_t col = tn * T::BN + wn * 32 + row;
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int64_t row0 = tm * T::BM + wm * 32 * U + u * 32;
-        double acc64[16];
-#pragma unroll
-        for (int r = 0; r < 16; ++r)
-            acc64[r] = (g.mode == kRawAdd) ? g.acc[col * g.Mp + row0 + 8 * (r >> 2) + 4 * half + (r & 3)] : 0.0;
-        fold_diags<ND, DLO, S - 1>(acc64, acc[u]);
-        store_tile(g, acc64, row0, half, col);
-    }
-}
-
-template <int S, int U, bool TOP>
-__global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(1, 1))) void gemm_pf_kernel(
-    GemmArgs g) {
-    using T = PfCfg<S, U>;
-    __shared__ v4i lds[T::NST][T::STAGE];
-    int64_t tm, tn;
-    tile_of_block(blockIdx.x, g.Mp / T::BM, g.Np / T::BN, tm, tn);
-    tile_body_pf<S, U, TOP>(g, tm, tn, lds);
-}
-
 // Persistent form for a batch: block b takes tiles b, b + gridDim.x, ... of the
 // tile list; a tile names its problem (a GemmArgs in device memory) and its
 // tile row and column (problem -1: a padding item, skipped).  Every problem of
@@ -696,28 +546,14 @@ hipError_t launch_persistent_s(const GemmArgs* probs, const TileItem* items, int
     return launch_persistent_cfg<S, 2, 2, 2>(probs, items, nitems, blocks, top, multi, st);
 }
 
-template <int S, int U>
-hipError_t launch_pf(const GemmArgs& g, hipStream_t st) {
-    using T = PfCfg<S, U>;
-    const int64_t blocks = (g.Np / T::BN) * (g.Mp / T::BM);
-    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    dim3 grid(static_cast<unsigned>(blocks)), block(64 * T::NW);
-    if (g.top)
-        hipLaunchKernelGGL((gemm_pf_kernel<S, U, true>), grid, block, 0, st, g);
-    else
-        hipLaunchKernelGGL((gemm_pf_kernel<S, U, false>), grid, block, 0, st, g);
-    return hipGetLastError();
-}
-
-// Block shape: 128 x 64 (8 waves, 3-stage ring) when the grid still fills
-// the 256 compute units twice over, else 64 x 64 (4 waves, 2 stages); tile 4
-// asks for the register-pipelined 128 x 64 form (one INT32 chunk, no export).
+// Block shape: 64 x 64 (4 waves, 2-stage ring) by default: two blocks share
+// a CU, each with its own barrier, so the two waves on a SIMD drift apart and
+// one keeps the matrix pipe busy while the other waits on LDS or the barrier
+// (measured faster than one 128 x 64 block per CU from n = 1024 to 4096).
+// Tile 1 asks for the 128 x 64 block (8 waves, 3-stage ring).
 template <int S>
 hipError_t launch_s(const GemmArgs& g, hipStream_t st) {
-    if (g.tile == 4 && !g.diag_out && g.chunk_steps >= g.kpad / kStep) return launch_pf<S, 1>(g, st);
-    const int tile = g.tile == 4 ? 0 : g.tile;  // elsewhere tile 4 takes the size rule
-    const int64_t big_tiles = (g.Mp / 128) * (g.Np / 64);
-    if (tile == 1 || (tile == 0 && big_tiles >= 512)) return launch_cfg<S, 4, 2, 3>(g, st);
+    if (g.tile == 1) return launch_cfg<S, 4, 2, 3>(g, st);
     return launch_cfg<S, 2, 2, 2>(g, st);
 }
 

@@ -157,7 +157,7 @@ def run_gemm(oz, handle, cplx, ta, tb, A, B, s, alpha=1.0, beta=0.0, C0=None, kc
 GEMM_SHAPES = [(1, 1, 1), (63, 65, 33), (130, 70, 257), (64, 192, 64)]
 
 
-@pytest.mark.parametrize("kernel", [0, 1, 3, 4])
+@pytest.mark.parametrize("kernel", [0, 1, 2, 3])
 @pytest.mark.parametrize("ta,tb", [("N", "N"), ("T", "N"), ("N", "T"), ("T", "T")])
 @pytest.mark.parametrize("m,n,k", GEMM_SHAPES)
 @pytest.mark.parametrize("s", [1, 3, 7, 8])
@@ -170,7 +170,7 @@ def test_dgemm_bit_exact(oz, handle, ta, tb, m, n, k, s, kernel):
     assert np.array_equal(got, oracle.emu_gemm(ta, tb, A, B, s))
 
 
-@pytest.mark.parametrize("kernel", [0, 1, 3, 4])
+@pytest.mark.parametrize("kernel", [0, 1, 2, 3])
 @pytest.mark.parametrize("ta,tb", [("N", "N"), ("C", "N"), ("T", "C"), ("C", "T")])
 @pytest.mark.parametrize("m,n,k", GEMM_SHAPES)
 @pytest.mark.parametrize("s", [2, 6, 7, 8])
@@ -196,7 +196,7 @@ def test_alpha_beta_bit_exact(oz, handle, cplx, alpha, beta):
     assert np.array_equal(got, oracle.emu_gemm("N", "N", A, B, 7, alpha=alpha, beta=beta, C=C0))
 
 
-@pytest.mark.parametrize("kernel", [1, 2, 3, 4])
+@pytest.mark.parametrize("kernel", [1, 2, 3])
 @pytest.mark.parametrize("cplx", [0, 1])
 @pytest.mark.parametrize("kc", [64, 128, 1024])
 def test_forced_split_k_bit_exact(oz, handle, cplx, kc, kernel):
@@ -504,7 +504,7 @@ def run_z3(oz, handle, ta, tb, A, B, s, alpha=1.0, beta=0.0, C0=None, kernel=0, 
 
 Z3_CASES = [("N", "N", 70, 65, 33, 7, 0), ("T", "C", 130, 70, 257, 5, 1), ("C", "T", 64, 192, 64, 3, 2),
             ("N", "C", 5, 300, 17, 8, 0), ("T", "N", 200, 3, 90, 10, 3), ("C", "N", 33, 47, 2, 1, 0),
-            ("N", "T", 150, 130, 300, 7, 4), ("C", "C", 65, 64, 31, 4, 4)]
+            ("N", "T", 150, 130, 300, 7, 2), ("C", "C", 65, 64, 31, 4, 1)]
 
 
 @pytest.mark.parametrize("ta,tb,m,n,k,s,kernel", Z3_CASES)
