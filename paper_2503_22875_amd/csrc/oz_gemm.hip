@@ -258,11 +258,20 @@ __device__ __forceinline__ void tile_body(const GemmArgs& g, int64_t tm, int64_t
         }
     };
     // all but the newest stage's copies of this wave have landed
-    auto wait_older = [&]() {
-        if (T::R % T::NW == 0 || wave < T::R % T::NW)
-            wait_vm<T::RHI>();
-        else
-            wait_vm<T::RLO>();
+    // Wait until the oldest stage in flight has landed while the `younger`
+    // (0 .. NST-2) stages issued after it may still fly; copies retire in
+    // issue order, and each stage is RHI or RLO copies of this wave.
+    auto wait_stage = [&](int64_t younger) {
+        const bool hi = T::R % T::NW == 0 || wave < T::R % T::NW;
+        if (NST > 3 && younger >= 2) {
+            if (hi) wait_vm<(NST > 3 ? 2 : 0) * T::RHI>();
+            else wait_vm<(NST > 3 ? 2 : 0) * T::RLO>();
+        } else if (NST > 2 && younger >= 1) {
+            if (hi) wait_vm<T::RHI>();
+            else wait_vm<T::RLO>();
+        } else {
+            wait_vm<0>();
+        }
     };
 
     v16i acc[ND];
@@ -282,14 +291,11 @@ __device__ __forceinline__ void tile_body(const GemmArgs& g, int64_t tm, int64_t
     double acc64[16];
     if constexpr (MULTI) init64(acc64);
 
-    // prologue: stages 0 .. NST-2 in flight
+    // prologue: stages 0 .. NST-2 in flight; stage 0 landed, the others may fly
 #pragma unroll
     for (int st = 0; st < NST - 1; ++st)
         if (st < nsteps) issue(st);
-    if (NST > 2 && nsteps > 1)
-        wait_older();  // stage 0 landed, stage 1 may still fly
-    else
-        wait_vm<0>();
+    wait_stage((nsteps - 1 < NST - 2) ? nsteps - 1 : NST - 2);
     __syncthreads();
 
     int64_t chunk_pos = 0, chunk = 0;
@@ -330,19 +336,22 @@ __device__ __forceinline__ void tile_body(const GemmArgs& g, int64_t tm, int64_t
                 ++chunk;
             }
         }
-        // the stage of step ks + 1 must have landed before the barrier
-        if (NST > 2 && more)
-            wait_older();
-        else
-            wait_vm<0>();
+        // the stage of step ks + 1 must have landed before the barrier; the
+        // stages issued after it (up to ks + NST - 1) may still fly
+        {
+            const int64_t after = nsteps - ks - 2;  // stages that exist after ks + 1
+            wait_stage(after < NST - 2 ? (after > 0 ? after : 0) : NST - 2);
+        }
         ring_barrier();
     };
-    static_assert(NST == 2 || NST == 3, "ring of 2 or 3 stages");
+    static_assert(NST >= 2 && NST <= 4, "ring of 2 to 4 stages");
     for (int64_t ks = 0; ks < nsteps; ks += NST) {
         step(ks, std::integral_constant<int, 0>{});
         if (ks + 1 < nsteps) step(ks + 1, std::integral_constant<int, 1>{});
-        if constexpr (NST == 3)
+        if constexpr (NST >= 3)
             if (ks + 2 < nsteps) step(ks + 2, std::integral_constant<int, 2>{});
+        if constexpr (NST >= 4)
+            if (ks + 3 < nsteps) step(ks + 3, std::integral_constant<int, 3>{});
     }
     if constexpr (DIAG) return;
     if constexpr (!MULTI) {
@@ -539,6 +548,13 @@ hipError_t launch_persistent_cfg(const GemmArgs* probs, const TileItem* items, i
     return hipGetLastError();
 }
 
+// Ring depth of the 64 x 64 block of a single product: as deep as two blocks
+// per CU allow in the 160 KiB of LDS (4 s KiB per stage), so that the copies
+// of short steps (small s) get more than one step to land.  The persistent
+// batch kernel keeps 2 stages: its tiles have few steps, and a deeper
+// prologue costs more there than it hides (measured on the 512-problem batch).
+constexpr int ring64(int s) { return s <= 4 ? 4 : (s <= 6 ? 3 : 2); }
+
 template <int S>
 hipError_t launch_persistent_s(const GemmArgs* probs, const TileItem* items, int64_t nitems, int blocks, int tile,
                                bool top, bool multi, hipStream_t st) {
@@ -554,7 +570,7 @@ hipError_t launch_persistent_s(const GemmArgs* probs, const TileItem* items, int
 template <int S>
 hipError_t launch_s(const GemmArgs& g, hipStream_t st) {
     if (g.tile == 1) return launch_cfg<S, 4, 2, 3>(g, st);
-    return launch_cfg<S, 2, 2, 2>(g, st);
+    return launch_cfg<S, 2, 2, ring64(S)>(g, st);
 }
 
 hipError_t launch_stream(const GemmArgs& g, hipStream_t st) {
