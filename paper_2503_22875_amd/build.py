@@ -1,4 +1,6 @@
-"""Compile the HIP sources of the library into liboz.so (gfx950 only).
+"""Compile the HIP sources of the library into liboz.so (gfx950 only), and the
+BLAS offload layer (dgemm_ / zgemm_, host code) into liboz_blas.so, which
+links liboz.so from its own directory and rocBLAS for the native mode.
 
 Every HIP file is compiled with:
   -ffp-contract=off   FP64 epilogue products and sums rounded separately, as
@@ -15,6 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liboz.so")
+BLAS_LIB = os.path.join(HERE, "liboz_blas.so")
+BLAS_SOURCE = "oz_blas.cpp"
 SOURCES = ["oz_split.hip", "oz_gemm.hip", "oz_check.hip", "oz_api.hip", "oz_batch.hip", "oz_select.hip",
            "oz_mlp.hip", "oz_learn.hip"]
 HEADERS = ["oz_internal.h", os.path.join("..", "..", "include", "oz.h")]
@@ -49,7 +53,25 @@ def build(verbose=False, extra_flags=()):
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
+    build_blas(verbose)
     return LIB
+
+
+def build_blas(verbose=False):
+    """liboz_blas.so: the Fortran-ABI dgemm_ / zgemm_ layer over liboz.so."""
+    obj = os.path.join(BUILD, BLAS_SOURCE.replace(".cpp", ".o"))
+    inc = os.path.join(HERE, "..", "include")
+    cmd = [HIPCC, "-O2", "-std=c++17", "-fPIC", "-Wall", "-I" + inc, "-c", os.path.join(CSRC, BLAS_SOURCE), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    cmd = [HIPCC, "-shared", "-fPIC", "-o", BLAS_LIB + ".tmp", obj, "-L" + HERE, "-l:liboz.so", "-lrocblas",
+           "-Wl,-rpath,$ORIGIN", "-Wl,-rpath,/opt/rocm/lib"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(BLAS_LIB + ".tmp", BLAS_LIB)
+    return BLAS_LIB
 
 
 if __name__ == "__main__":

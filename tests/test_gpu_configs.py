@@ -9,7 +9,8 @@ against the oracle (the CPU computes only the sampled rows and columns):
   by 10^U(-8, 8)) driven by the tolerances 1e-6, 1e-10 and 1e-14: the
   residual estimate meets each tolerance, the sampled error is within twice
   it, and the result is bit-exact against the oracle's incremental emulation
-  from the reported start to the reported final s."""
+  from the reported start to the reported final s; and the same DGEMM at
+  s = 8 with a forced INT32 split of k into chunks of 2048 terms."""
 import numpy as np
 import pytest
 import torch
@@ -93,3 +94,26 @@ def test_wide_range_dgemm_tolerance(oz, handle, tol):
     # estimate's factor-of-2 spread of it
     assert rep.resid_est <= tol
     assert err <= 2 * tol, (err, tol)
+
+
+def test_wide_range_dgemm_forced_split_k(oz, handle):
+    # the wide-range DGEMM at s = 8 with the INT32 accumulation cut into four
+    # chunks of 2048 terms: sampled entries bit-exact against the oracle's
+    # chunked FP64 order, and the same error as the one-chunk result
+    A, B = workloads.dgemm_wide(seed=0)
+    m, k = A.shape
+    n = B.shape[1]
+    dA = torch.from_numpy(A.ravel(order="F")).cuda()
+    dB = torch.from_numpy(B.ravel(order="F")).cuda()
+    dC = torch.zeros(m * n, dtype=torch.float64, device="cuda")
+    print("wide split-K", flush=True)
+    oz.oz_dgemm(handle, "N", "N", m, n, k, 1.0, dA, m, dB, k, 0.0, dC, m, oz.prec(8, kchunk=2048))
+    torch.cuda.synchronize()
+    rows, cols = _samples(4096, 16, 11)
+    got = from_dev(dC, m, n, m)[np.ix_(rows, cols)]
+    want = oracle.emu_gemm("N", "N", A, B, 8, kc=2048, rows=rows, cols=cols)
+    assert np.array_equal(got, want)
+    dd = oracle.gemm_dd("N", "N", A, B, rows=rows, cols=cols)
+    err = oracle.weighted_error(got, dd, np.abs(A).max(1)[rows], np.abs(B).max(0)[cols])
+    print("wide split-K weighted error %.3g" % err)
+    assert err < 1e-14
