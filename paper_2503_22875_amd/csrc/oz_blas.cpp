@@ -6,12 +6,15 @@
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 
+#include <algorithm>
 #include <cctype>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <thread>
+#include <vector>
 
 #include "oz.h"
 #include "oz_blas.h"
@@ -62,6 +65,13 @@ struct DevBuf {
     size_t cap = 0;
 };
 
+// Host<->device copies of host operands go through two pinned staging
+// buffers: the columns of one chunk are packed (by several threads for large
+// chunks) while the DMA of the other chunk runs.  Pageable memory cannot be
+// registered here, and the runtime's own staging of pageable copies is slower.
+constexpr size_t kStageBytes = size_t(32) << 20;
+constexpr size_t kThreadedBytes = size_t(4) << 20;  // chunks above this are packed by several threads
+
 struct Ctx {
     std::mutex mu;
     bool configured = false;  // environment read
@@ -72,6 +82,9 @@ struct Ctx {
     hipStream_t stream = nullptr;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     DevBuf buf[3];
+    void* pin[2] = {nullptr, nullptr};
+    hipEvent_t pin_free[2] = {nullptr, nullptr};  // the DMA that last used a staging buffer
+    int copy_threads = 1;
     oz_blas_stats_t st{};
 };
 
@@ -115,6 +128,13 @@ void setup(Ctx& c) {
     if (s) die("oz_set_stream", oz_status_string(s));
     if (rocblas_create_handle(&c.rb) != rocblas_status_success) die("rocblas_create_handle", "failed");
     if (rocblas_set_stream(c.rb, c.stream) != rocblas_status_success) die("rocblas_set_stream", "failed");
+    for (int b = 0; b < 2; ++b) {
+        check_hip(hipHostMalloc(&c.pin[b], kStageBytes, hipHostMallocDefault), "hipHostMalloc");
+        check_hip(hipEventCreateWithFlags(&c.pin_free[b], hipEventDisableTiming), "hipEventCreate");
+        check_hip(hipEventRecord(c.pin_free[b], c.stream), "hipEventRecord");
+    }
+    const unsigned hw = std::thread::hardware_concurrency();
+    c.copy_threads = static_cast<int>(std::max(1u, std::min(8u, hw / 2)));
     c.ready = true;
 }
 
@@ -124,6 +144,11 @@ void teardown(Ctx& c) {
     for (auto& b : c.buf) {
         if (b.p) check_hip(hipFree(b.p), "hipFree");
         b = DevBuf{};
+    }
+    for (int b = 0; b < 2; ++b) {
+        check_hip(hipHostFree(c.pin[b]), "hipHostFree");
+        check_hip(hipEventDestroy(c.pin_free[b]), "hipEventDestroy");
+        c.pin[b] = nullptr;
     }
     rocblas_destroy_handle(c.rb);
     oz_destroy(c.oz);
@@ -143,6 +168,83 @@ void* reserve(DevBuf& b, size_t bytes) {
         b.cap = bytes;
     }
     return b.p;
+}
+
+// Copy `cols` columns of `colb` bytes between a strided and a packed layout
+// (dst column j at dst + j * dld, src column j at src + j * sld), split over
+// up to `threads` threads when large.
+void copy_cols(char* dst, size_t dld, const char* src, size_t sld, size_t colb, int64_t cols, int threads) {
+    auto run = [&](int64_t j0, int64_t j1) {
+        if (dld == colb && sld == colb) {
+            std::memcpy(dst + j0 * dld, src + j0 * sld, colb * (j1 - j0));
+            return;
+        }
+        for (int64_t j = j0; j < j1; ++j) std::memcpy(dst + j * dld, src + j * sld, colb);
+    };
+    const size_t total = colb * static_cast<size_t>(cols);
+    const int nt = total >= kThreadedBytes ? static_cast<int>(std::min<int64_t>(threads, cols)) : 1;
+    if (nt <= 1) {
+        run(0, cols);
+        return;
+    }
+    std::vector<std::thread> pool;
+    const int64_t per = (cols + nt - 1) / nt;
+    for (int t = 1; t < nt; ++t) {
+        const int64_t j0 = t * per, j1 = std::min(cols, j0 + per);
+        if (j0 < j1) pool.emplace_back(run, j0, j1);
+    }
+    run(0, std::min(cols, per));
+    for (auto& th : pool) th.join();
+}
+
+// Host (leading dimension ld) -> device (packed, leading dimension rows).
+void to_device(Ctx& c, void* dst, const void* src, int64_t ld, int64_t rows, int64_t cols, size_t es) {
+    const size_t colb = es * static_cast<size_t>(rows);
+    if (colb > kStageBytes) {  // one column larger than a stage: the runtime copies it
+        check_hip(hipMemcpy2DAsync(dst, colb, src, es * ld, colb, cols, hipMemcpyHostToDevice, c.stream), "copy in");
+        return;
+    }
+    const int64_t per = static_cast<int64_t>(kStageBytes / colb);
+    int b = 0;
+    for (int64_t j0 = 0; j0 < cols; j0 += per, b ^= 1) {
+        const int64_t nc = std::min(per, cols - j0);
+        check_hip(hipEventSynchronize(c.pin_free[b]), "hipEventSynchronize");
+        copy_cols(static_cast<char*>(c.pin[b]), colb, static_cast<const char*>(src) + j0 * es * ld, es * ld, colb, nc,
+                  c.copy_threads);
+        check_hip(hipMemcpyAsync(static_cast<char*>(dst) + j0 * colb, c.pin[b], colb * nc, hipMemcpyHostToDevice,
+                                 c.stream),
+                  "copy in");
+        check_hip(hipEventRecord(c.pin_free[b], c.stream), "hipEventRecord");
+    }
+}
+
+// Device (packed, leading dimension rows) -> host (leading dimension ld).
+void to_host(Ctx& c, void* dst, int64_t ld, const void* src, int64_t rows, int64_t cols, size_t es) {
+    const size_t colb = es * static_cast<size_t>(rows);
+    if (colb > kStageBytes) {
+        check_hip(hipMemcpy2DAsync(dst, es * ld, src, colb, colb, cols, hipMemcpyDeviceToHost, c.stream), "copy out");
+        check_hip(hipStreamSynchronize(c.stream), "hipStreamSynchronize");
+        return;
+    }
+    const int64_t per = static_cast<int64_t>(kStageBytes / colb);
+    const int64_t nchunks = (cols + per - 1) / per;
+    auto issue = [&](int64_t i) {
+        const int64_t j0 = i * per, nc = std::min(per, cols - j0);
+        const int b = static_cast<int>(i & 1);
+        check_hip(hipMemcpyAsync(c.pin[b], static_cast<const char*>(src) + j0 * colb, colb * nc,
+                                 hipMemcpyDeviceToHost, c.stream),
+                  "copy out");
+        check_hip(hipEventRecord(c.pin_free[b], c.stream), "hipEventRecord");
+    };
+    issue(0);
+    for (int64_t i = 0; i < nchunks; ++i) {
+        if (i + 1 < nchunks) issue(i + 1);  // the other buffer was unpacked in the previous round
+        const int b = static_cast<int>(i & 1);
+        check_hip(hipEventSynchronize(c.pin_free[b]), "hipEventSynchronize");
+        const int64_t j0 = i * per, nc = std::min(per, cols - j0);
+        copy_cols(static_cast<char*>(dst) + j0 * es * ld, es * ld, static_cast<const char*>(c.pin[b]), colb, colb, nc,
+                  c.copy_threads);
+    }
 }
 
 // True when the GPU can use ptr directly (device or managed memory).
@@ -203,25 +305,20 @@ void gemm(const char* name, int cplx, const char* transa, const char* transb, co
     if (host_a) {
         dA = static_cast<const double*>(reserve(c.buf[0], es * rows_a * cols_a));
         la = rows_a;
-        check_hip(hipMemcpy2DAsync(const_cast<double*>(dA), es * rows_a, A, es * lda, es * rows_a, cols_a,
-                                   hipMemcpyHostToDevice, c.stream),
-                  "copy A");
+        to_device(c, const_cast<double*>(dA), A, lda, rows_a, cols_a, es);
         c.st.bytes_to_device += static_cast<int64_t>(es * rows_a * cols_a);
     }
     if (host_b) {
         dB = static_cast<const double*>(reserve(c.buf[1], es * rows_b * cols_b));
         lb = rows_b;
-        check_hip(hipMemcpy2DAsync(const_cast<double*>(dB), es * rows_b, B, es * ldb, es * rows_b, cols_b,
-                                   hipMemcpyHostToDevice, c.stream),
-                  "copy B");
+        to_device(c, const_cast<double*>(dB), B, ldb, rows_b, cols_b, es);
         c.st.bytes_to_device += static_cast<int64_t>(es * rows_b * cols_b);
     }
     if (host_c) {
         dC = static_cast<double*>(reserve(c.buf[2], es * m * n));
         lc = m;
         if (!beta_zero) {  // with beta = 0 C is write-only
-            check_hip(hipMemcpy2DAsync(dC, es * m, C, es * ldc, es * m, n, hipMemcpyHostToDevice, c.stream),
-                      "copy C");
+            to_device(c, dC, C, ldc, m, n, es);
             c.st.bytes_to_device += static_cast<int64_t>(es * m * n);
         }
     }
@@ -266,7 +363,7 @@ void gemm(const char* name, int cplx, const char* transa, const char* transb, co
     }
     check_hip(hipEventRecord(c.ev[2], c.stream), "hipEventRecord");
     if (host_c) {
-        check_hip(hipMemcpy2DAsync(C, es * ldc, dC, es * m, es * m, n, hipMemcpyDeviceToHost, c.stream), "copy C back");
+        to_host(c, C, ldc, dC, m, n, es);
         c.st.bytes_to_host += static_cast<int64_t>(es * m * n);
     }
     check_hip(hipEventRecord(c.ev[3], c.stream), "hipEventRecord");
