@@ -18,6 +18,7 @@ float64 or complex128; ``trans`` is 'N', 'T' or 'C'):
 * ``emu_gemm``    the full emulated product: digits, pair products with
                   p + q <= s + 1, FP64 accumulation, alpha/beta.
 * ``emu_zgemm3``  the complex product as three real emulated products (3M).
+* ``emu_gemm_x2`` the emulated product with a double-double result.
 * ``kchunk``      the INT32 chunk length (products per chunk).
 
 Submodules ``select`` (features, error table and labels of the learned
@@ -57,6 +58,8 @@ def _load():
     lib.oro_diag_sums.argtypes = [I32, I32, I64, I64, P, I64, P, I64, P, I64, P, I64, P]
     lib.oro_emu_dgemm.argtypes = [C, C, I64, I64, I64, D, P, I64, P, I64, D, P, I64, I32, I32, I64,
                                   P, I64, P, I64, P, I64]
+    lib.oro_emu_dgemm_x2.argtypes = [C, C, I64, I64, I64, P, I64, P, I64, I32, I64, P, I64, P, I64, P, P, I64]
+    lib.oro_emu_zgemm_x2.argtypes = [C, C, I64, I64, I64, P, I64, P, I64, I32, I64, P, I64, P, I64, P, P, I64]
     lib.oro_emu_zgemm.argtypes = [C, C, I64, I64, I64, P, P, I64, P, I64, P, P, I64, I32, I32, I64,
                                   P, I64, P, I64, P, I64]
     lib.oro_num_threads.restype = ctypes.c_int
@@ -278,6 +281,32 @@ def emu_gemm(transa, transb, A, B, s, alpha=1.0, beta=0.0, C=None, kc=None, rows
                           _ptr(B), _ld(B), float(beta), _ptr(Cin), _ld(Cin), s, s1, kc, _ptr(rs), nr,
                           _ptr(cs), nc, _ptr(out), max(1, nr))
     return out
+
+
+def emu_gemm_x2(transa, transb, A, B, s, kc=None, rows=None, cols=None):
+    """O4 beyond FP64: the product op(A) op(B) at s slices with its
+    anti-diagonal sums folded into a double-double (d = s+1 down to 2, chunk
+    by chunk; (hi, lo) + x by TwoSum, the error added to lo, then a fast
+    TwoSum).  Returns (hi, lo), each scaled by 2^(E_i + F_j), on the selected
+    rows x cols; hi + lo is the emulated sum while its terms span fewer than
+    about 100 bits."""
+    cplx = np.iscomplexobj(A) or np.iscomplexobj(B)
+    dt = np.complex128 if cplx else np.float64
+    A, B = _f(A, dt), _f(B, dt)
+    m, k = _dims(transa, A, "A")
+    k2, n = _dims(transb, B, "B")
+    assert k == k2
+    kc = kchunk(s, cplx) if kc is None else kc
+    assert kc > 0 and (not cplx or kc % 2 == 0)
+    rs, nr = _sel(rows, m)
+    cs, nc = _sel(cols, n)
+    hi = np.zeros((nr, nc), dtype=dt, order="F")
+    lo = np.zeros((nr, nc), dtype=dt, order="F")
+    lib = _load()
+    fn = lib.oro_emu_zgemm_x2 if cplx else lib.oro_emu_dgemm_x2
+    fn(transa.encode(), transb.encode(), m, n, k, _ptr(A), _ld(A), _ptr(B), _ld(B), s, kc, _ptr(rs), nr, _ptr(cs),
+       nc, _ptr(hi), _ptr(lo), max(1, nr))
+    return hi, lo
 
 
 def weighted_error(Cx, Cref, A_rowmax, B_colmax):

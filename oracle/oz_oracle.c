@@ -490,6 +490,87 @@ void oro_emu_zgemm(char ta, char tb, int64_t m, int64_t n, int64_t k, const doub
     free(EA); free(FB); free(dA); free(dB);
 }
 
+/* ---- products beyond FP64: the same sums folded into a double-double ---- */
+
+/* (hi, lo) + x, x exactly representable: TwoSum of hi and x, the error added
+   to lo, then a fast TwoSum renormalisation. */
+static void dd_add_exact(double* hi, double* lo, double x) {
+    double s = *hi + x;
+    double bb = s - *hi;
+    double err = (*hi - (s - bb)) + (x - bb);
+    double t = *lo + err;
+    double h = s + t;
+    *lo = t - (h - s);
+    *hi = h;
+}
+
+/* C = op(A) op(B) at s slices, the anti-diagonal sums of each INT32 chunk
+   folded from d = s+1 down to 2 into (hi, lo); outputs ldexp(hi, E+F) and
+   ldexp(lo, E+F) for the selected block (ldo). */
+void oro_emu_dgemm_x2(char ta, char tb, int64_t m, int64_t n, int64_t k, const double* A, int64_t lda,
+                      const double* B, int64_t ldb, int s, int64_t kc, const int64_t* rows, int64_t nr,
+                      const int64_t* cols, int64_t nc, double* out_hi, double* out_lo, int64_t ldo) {
+    int32_t* EA = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m + 1));
+    int32_t* FB = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
+    int8_t* dA = (int8_t*)malloc((size_t)(s * m * k + 1));
+    int8_t* dB = (int8_t*)malloc((size_t)(s * n * k + 1));
+    oro_split('A', ta, 0, m, k, A, lda, s, EA, dA);
+    oro_split('B', tb, 0, n, k, B, ldb, s, FB, dB);
+    int64_t nch = k > 0 ? (k + kc - 1) / kc : 0;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t jj = 0; jj < nc; ++jj) {
+        int64_t S[64];
+        for (int64_t ii = 0; ii < nr; ++ii) {
+            int64_t i = pick(rows, ii), j = pick(cols, jj);
+            double hi = 0.0, lo = 0.0;
+            for (int64_t c = 0; c < nch; ++c) {
+                int64_t l0 = c * kc, l1 = l0 + kc < k ? l0 + kc : k;
+                diag_sums_real(dA + i * k, dB + j * k, m * k, n * k, s, l0, l1, S);
+                for (int d = s + 1; d >= 2; --d) dd_add_exact(&hi, &lo, (double)S[d] * pow2i(-7 * d));
+            }
+            out_hi[ii + jj * ldo] = ldexp(hi, EA[i] + FB[j]);
+            out_lo[ii + jj * ldo] = ldexp(lo, EA[i] + FB[j]);
+        }
+    }
+    free(EA); free(FB); free(dA); free(dB);
+}
+
+/* Complex form: real and imaginary parts each a double-double (interleaved). */
+void oro_emu_zgemm_x2(char ta, char tb, int64_t m, int64_t n, int64_t k, const double* A, int64_t lda,
+                      const double* B, int64_t ldb, int s, int64_t kc, const int64_t* rows, int64_t nr,
+                      const int64_t* cols, int64_t nc, double* out_hi, double* out_lo, int64_t ldo) {
+    int32_t* EA = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m + 1));
+    int32_t* FB = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
+    int8_t* dA = (int8_t*)malloc((size_t)(2 * s * m * k + 1));
+    int8_t* dB = (int8_t*)malloc((size_t)(2 * s * n * k + 1));
+    oro_split('A', ta, 1, m, k, A, lda, s, EA, dA);
+    oro_split('B', tb, 1, n, k, B, ldb, s, FB, dB);
+    int64_t lchunk = kc / 2;
+    int64_t nch = k > 0 ? (k + lchunk - 1) / lchunk : 0;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t jj = 0; jj < nc; ++jj) {
+        int64_t Sr[64], Si[64];
+        for (int64_t ii = 0; ii < nr; ++ii) {
+            int64_t i = pick(rows, ii), j = pick(cols, jj);
+            double hr = 0.0, lr = 0.0, hi_ = 0.0, li = 0.0;
+            for (int64_t c = 0; c < nch; ++c) {
+                int64_t l0 = c * lchunk, l1 = l0 + lchunk < k ? l0 + lchunk : k;
+                diag_sums_cplx(dA + i * k * 2, dB + j * k * 2, m * k * 2, n * k * 2, s, l0, l1, Sr, Si);
+                for (int d = s + 1; d >= 2; --d) {
+                    dd_add_exact(&hr, &lr, (double)Sr[d] * pow2i(-7 * d));
+                    dd_add_exact(&hi_, &li, (double)Si[d] * pow2i(-7 * d));
+                }
+            }
+            int e = EA[i] + FB[j];
+            out_hi[2 * (ii + jj * ldo)] = ldexp(hr, e);
+            out_hi[2 * (ii + jj * ldo) + 1] = ldexp(hi_, e);
+            out_lo[2 * (ii + jj * ldo)] = ldexp(lr, e);
+            out_lo[2 * (ii + jj * ldo) + 1] = ldexp(li, e);
+        }
+    }
+    free(EA); free(FB); free(dA); free(dB);
+}
+
 int oro_num_threads(void) {
     int t = 1;
 #pragma omp parallel
