@@ -438,9 +438,45 @@ def bench_blas(args):
                       "rows": rows}), flush=True)
 
 
+def bench_x2(args):
+    """Products beyond FP64: DGEMM n = 4096 (N(0,1) entries) with a
+    double-double result (oz_dgemm_x2) at s = 8, 10, 12, 14, beside the FP64
+    result of the same streaming kernel (oz_dgemm, kernel 3).  The accuracy of
+    the double-double result is checked by the GPU tests against the exact
+    product; this line reports time only."""
+    import torch
+
+    import paper_2503_22875_amd as oz
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    h = oz.oz_create(0)
+    oz.oz_set_stream(h, stream.cuda_stream)
+    n = 4096
+    rng = np.random.default_rng(0)
+    dA = torch.from_numpy(rng.standard_normal(n * n)).cuda()
+    dB = torch.from_numpy(rng.standard_normal(n * n)).cuda()
+    dH = torch.zeros(n * n, dtype=torch.float64, device="cuda")
+    dL = torch.zeros(n * n, dtype=torch.float64, device="cuda")
+    flops = 2.0 * n ** 3
+    rows = []
+    for s in (8, 10, 12, 14):
+        p = oz.prec(s, kernel=3)
+        ms_x2 = _time_ms(lambda: oz.oz_dgemm_x2(h, "N", "N", n, n, n, dA, n, dB, n, dH, dL, n, p), stream,
+                         args.steps, args.warmup)
+        ms_d = _time_ms(lambda: oz.oz_dgemm(h, "N", "N", n, n, n, 1.0, dA, n, dB, n, 0.0, dH, n, p), stream,
+                        args.steps, args.warmup)
+        row = {"s": s, "x2_ms": round(ms_x2, 3), "x2_tflops": round(flops / (ms_x2 * 1e-3) / 1e12, 2),
+               "fp64_ms": round(ms_d, 3), "fp64_tflops": round(flops / (ms_d * 1e-3) / 1e12, 2)}
+        print(json.dumps(row), flush=True)
+        rows.append(row)
+    oz.oz_destroy(h)
+    print(json.dumps({"workload": "dgemm n=4096 double-double result (streaming kernel)", "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="zgemm4096", choices=["zgemm4096", "batch512", "select", "sweep", "wide_tol", "blas"])
+    ap.add_argument("--workload", default="zgemm4096", choices=["zgemm4096", "batch512", "select", "sweep", "wide_tol", "blas", "x2"])
     ap.add_argument("--select-data", default="normal,spread")
     ap.add_argument("--select-tols", default="1e-10,1e-12,1e-14")
     ap.add_argument("--sweep-n", default="2048,4096")
@@ -473,6 +509,8 @@ def main():
         return bench_wide_tol(args)
     if args.workload == "blas":
         return bench_blas(args)
+    if args.workload == "x2":
+        return bench_x2(args)
 
     import torch
 

@@ -173,6 +173,28 @@ int oz_zgemm(oz_handle_t handle, char transa, char transb, int64_t m, int64_t n,
              const double* alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
              const double* beta, double* C, int64_t ldc, const oz_prec_t* prec, oz_report_t* rep);
 
+/* Products beyond FP64 (paper Sec. 1: some computations need more than FP64;
+ * with s >= 9 the emulated product carries more bits than one double holds).
+ * C = op(A) op(B) as a double-double (C_hi + C_lo, both m x n with leading
+ * dimension ldc, device memory, distinct buffers; complex: interleaved pairs,
+ * real parts and imaginary parts each a double-double).  The digits, pairs and
+ * INT32 anti-diagonal sums are those of oz_dgemm with the same prec; the sums
+ * are folded in the same order (d = s+1 down to 2, chunk by chunk) but into a
+ * double-double: hi + x by TwoSum, its error added to lo, then a fast TwoSum
+ * renormalisation.  C_hi = ldexp(hi, E_i + F_j), C_lo = ldexp(lo, E_i + F_j);
+ * NaN in both for a row or column with Inf/NaN input (rep->status
+ * OZ_ERR_NONFINITE).  alpha = 1 and beta = 0 (C is not read).  Fixed slice
+ * counts only (prec->slices 1..18, tolerance mode returns 14); complex uses the
+ * 4-product form (zmode 3 returns 14); runs the per-diagonal streaming kernel
+ * whatever prec->kernel says.  Returns 12 when C_lo is NULL or equals C_hi;
+ * argument errors otherwise as oz_dgemm. */
+int oz_dgemm_x2(oz_handle_t handle, char transa, char transb, int64_t m, int64_t n, int64_t k,
+                const double* A, int64_t lda, const double* B, int64_t ldb, double* C_hi, double* C_lo,
+                int64_t ldc, const oz_prec_t* prec, oz_report_t* rep);
+int oz_zgemm_x2(oz_handle_t handle, char transa, char transb, int64_t m, int64_t n, int64_t k,
+                const double* A, int64_t lda, const double* B, int64_t ldb, double* C_hi, double* C_lo,
+                int64_t ldc, const oz_prec_t* prec, oz_report_t* rep);
+
 /* The starting slice count of a tolerance-driven call: the smallest s in
  * [1, smax] (smax 0: 12) with 2.5 (s+1) 2^(-7s) sqrt((1/M_A + 1/M_B)/3) <= tol,
  * M_A / M_B the mean over rows of op(A) / columns of op(B) of the mean square

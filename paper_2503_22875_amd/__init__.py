@@ -38,7 +38,7 @@ EXPORTS = ["oz_create", "oz_destroy", "oz_set_stream", "oz_status_string", "oz_w
            "oz_load_tuning", "oz_gen_operands", "oz_features", "oz_selector_dataset", "oz_mlp_create",
            "oz_mlp_destroy", "oz_mlp_set_params", "oz_mlp_get_params", "oz_mlp_fit_norm", "oz_mlp_forward",
            "oz_mlp_grad", "oz_mlp_train_step", "oz_mlp_train", "oz_mlp_save", "oz_mlp_load", "oz_set_selector",
-           "oz_predict_slices", "oz_batch_report"]
+           "oz_predict_slices", "oz_batch_report", "oz_dgemm_x2", "oz_zgemm_x2"]
 
 OZ_NUM_FEATURES = 16
 OZ_MLP_NPARAM = 5313
@@ -90,6 +90,8 @@ def _load():
                      PP(oz_report_t)],
         "oz_zgemm": [P, C, C, I64, I64, I64, PP(D), P, I64, P, I64, PP(D), P, I64, PP(oz_prec_t),
                      PP(oz_report_t)],
+        "oz_dgemm_x2": [P, C, C, I64, I64, I64, P, I64, P, I64, P, P, I64, PP(oz_prec_t), PP(oz_report_t)],
+        "oz_zgemm_x2": [P, C, C, I64, I64, I64, P, I64, P, I64, P, P, I64, PP(oz_prec_t), PP(oz_report_t)],
         "oz_split_layout": [C, ctypes.c_int, I64, I64, I32, PP(I64), PP(I64), PP(ctypes.c_size_t)],
         "oz_split": [P, C, C, ctypes.c_int, I64, I64, P, I64, I32, P, P],
         "oz_diag_sums": [P, I32, I64, I32, I64, I64, I64, P, P, P],
@@ -212,6 +214,28 @@ def oz_zgemm(handle, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ld
     """Complex version; A, B, C hold interleaved (re, im) doubles."""
     return _gemm("oz_zgemm", True, handle, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, p,
                  report, check)
+
+
+def _gemm_x2(fn, handle, transa, transb, m, n, k, A, lda, B, ldb, C_hi, C_lo, ldc, p, report, check):
+    rep = oz_report_t() if report else None
+    st = getattr(_lib, fn)(handle, _ch(transa), _ch(transb), m, n, k, _ptr(A), lda, _ptr(B), ldb, _ptr(C_hi),
+                           _ptr(C_lo), ldc, ctypes.byref(p) if p is not None else None,
+                           ctypes.byref(rep) if rep is not None else None)
+    if check:
+        _check(fn, st)
+    return (st, rep) if report else st
+
+
+def oz_dgemm_x2(handle, transa, transb, m, n, k, A, lda, B, ldb, C_hi, C_lo, ldc, p, report=False, check=True):
+    """C_hi + C_lo = op(A)*op(B) as a double-double (fixed slice count p.slices)."""
+    return _gemm_x2("oz_dgemm_x2", handle, transa, transb, m, n, k, A, lda, B, ldb, C_hi, C_lo, ldc, p, report,
+                    check)
+
+
+def oz_zgemm_x2(handle, transa, transb, m, n, k, A, lda, B, ldb, C_hi, C_lo, ldc, p, report=False, check=True):
+    """Complex version of oz_dgemm_x2 (interleaved (re, im) doubles)."""
+    return _gemm_x2("oz_zgemm_x2", handle, transa, transb, m, n, k, A, lda, B, ldb, C_hi, C_lo, ldc, p, report,
+                    check)
 
 
 def oz_split_layout(side, is_complex, nv, k, slices):

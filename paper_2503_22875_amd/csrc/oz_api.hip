@@ -338,9 +338,12 @@ int zgemm_3m(oz_handle_t h, char transa, char transb, int64_t m, int64_t n, int6
     return OZ_OK;
 }
 
+// c_lo != nullptr: double-double result (C the high parts, c_lo the low
+// parts), alpha = 1, beta = 0, fixed s, the streaming kernel.
 int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, int64_t n, int64_t k,
                 const double* alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
-                const double* beta, double* C, int64_t ldc, const oz_prec_t* prec, oz_report_t* rep) {
+                const double* beta, double* C, int64_t ldc, const oz_prec_t* prec, oz_report_t* rep,
+                double* c_lo = nullptr) {
     if (!valid(h)) return OZ_ERR_HANDLE;
     if (!trans_ok(transa)) return 1;
     if (!trans_ok(transb)) return 2;
@@ -379,6 +382,7 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
         kc = prec->kchunk;
         kernel = prec->kernel;
     }
+    if (c_lo && (tol_mode || (cplx && prec && prec->zmode == 3))) return 14;  // fixed s, 4-product form
     const int s_plan = tol_mode ? smax : s;  // largest slice count this call may use
     if (kc < 0 || kc % 64 != 0 || (kc > 0 && kc > kchunk_bound(s_plan))) return 14;
     if (kc == 0) kc = kchunk_bound(s_plan);
@@ -402,6 +406,7 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
     if (alpha_zero || k == 0) {
         if (beta_one) return OZ_OK;
         st = hip_status(oz::launch_scale_c(C, ldc, m, n, cplx, br, bi, beta_zero, h->stream));
+        if (st == OZ_OK && c_lo) st = hip_status(oz::launch_scale_c(c_lo, ldc, m, n, cplx, 0.0, 0.0, 1, h->stream));
         if (st == OZ_OK && rep && hipStreamSynchronize(h->stream) != hipSuccess) st = OZ_ERR_HIP;
         return st;
     }
@@ -460,8 +465,13 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
     g.diag_out = nullptr;
     if (rep) rep->kchunks = static_cast<int32_t>((p.la.kpad + kc - 1) / kc);
 
+    if (c_lo) {
+        g.mode = oz::kFinalDD;
+        g.c_lo = c_lo;
+        g.tile = 3;
+    }
     if (!tol_mode) {
-        g.mode = oz::kFinal;
+        if (!c_lo) g.mode = oz::kFinal;
         e = mark(h);
         if (e == hipSuccess) e = oz::launch_gemm(g, h->stream);
         if (e == hipSuccess) e = mark(h);
@@ -706,6 +716,26 @@ int oz_zgemm(oz_handle_t h, char transa, char transb, int64_t m, int64_t n, int6
              const double* A, int64_t lda, const double* B, int64_t ldb, const double* beta, double* C, int64_t ldc,
              const oz_prec_t* prec, oz_report_t* rep) {
     return gemm_common(h, 1, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, prec, rep);
+}
+
+int oz_dgemm_x2(oz_handle_t h, char transa, char transb, int64_t m, int64_t n, int64_t k, const double* A,
+                int64_t lda, const double* B, int64_t ldb, double* C_hi, double* C_lo, int64_t ldc,
+                const oz_prec_t* prec, oz_report_t* rep) {
+    if (!valid(h)) return OZ_ERR_HANDLE;
+    if (!prec || prec->slices < 1) return 14;
+    if (!C_lo || C_lo == C_hi) return 12;
+    const double one[2] = {1.0, 0.0}, zero[2] = {0.0, 0.0};
+    return gemm_common(h, 0, transa, transb, m, n, k, one, A, lda, B, ldb, zero, C_hi, ldc, prec, rep, C_lo);
+}
+
+int oz_zgemm_x2(oz_handle_t h, char transa, char transb, int64_t m, int64_t n, int64_t k, const double* A,
+                int64_t lda, const double* B, int64_t ldb, double* C_hi, double* C_lo, int64_t ldc,
+                const oz_prec_t* prec, oz_report_t* rep) {
+    if (!valid(h)) return OZ_ERR_HANDLE;
+    if (!prec || prec->slices < 1) return 14;
+    if (!C_lo || C_lo == C_hi) return 12;
+    const double one[2] = {1.0, 0.0}, zero[2] = {0.0, 0.0};
+    return gemm_common(h, 1, transa, transb, m, n, k, one, A, lda, B, ldb, zero, C_hi, ldc, prec, rep, C_lo);
 }
 
 int oz_split_layout(char side, int is_complex, int64_t nv, int64_t k, int32_t slices, int64_t* rows_pad,

@@ -187,6 +187,53 @@ __device__ __forceinline__ void store_tile(const GemmArgs& g, const double (&acc
     }
 }
 
+// (hi, lo) + x for an exactly representable x (a diagonal sum times a power
+// of two): TwoSum of hi and x, its error added to lo, then renormalised by a
+// fast TwoSum.  Exact while the running sum spans fewer than about 100 bits.
+__device__ __forceinline__ void dd_add_exact(double& hi, double& lo, double x) {
+    const double s = hi + x;
+    const double bb = s - hi;
+    const double err = (hi - (s - bb)) + (x - bb);
+    const double t = lo + err;
+    hi = s + t;
+    lo = t - (hi - s);
+}
+
+// Epilogue of kFinalDD: C = ldexp(hi, E_i + F_j), c_lo = ldexp(lo, E_i + F_j)
+// (NaN in both where a scale marks Inf/NaN input); layout as store_tile.
+__device__ __forceinline__ void store_tile_dd(const GemmArgs& g, const double (&hi)[16], const double (&lo)[16],
+                                              int64_t row0, int half, int64_t col) {
+    const double nan = __longlong_as_double(0x7ff8000000000000ll);
+    if (col >= g.n) return;
+    const int32_t f = g.FB[col];
+    if (!g.cplx) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int64_t i = row0 + 8 * (r >> 2) + 4 * half + (r & 3);
+            if (i >= g.m) continue;
+            const int32_t e = g.EA[i];
+            const bool bad = e == kNonFiniteExp || f == kNonFiniteExp;
+            g.C[i + col * g.ldc] = bad ? nan : ldexp(hi[r], e + f);
+            g.c_lo[i + col * g.ldc] = bad ? nan : ldexp(lo[r], e + f);
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            if ((r & 4) != 0) continue;
+            const int64_t ci = row0 / 2 + 8 * (r >> 3) + 4 * half + (r & 3);
+            if (ci >= g.m) continue;
+            const int32_t e = g.EA[ci];
+            const bool bad = e == kNonFiniteExp || f == kNonFiniteExp;
+            double* ch = g.C + 2 * (ci + col * g.ldc);
+            double* cl = g.c_lo + 2 * (ci + col * g.ldc);
+            ch[0] = bad ? nan : ldexp(hi[r], e + f);
+            ch[1] = bad ? nan : ldexp(hi[r + 4], e + f);
+            cl[0] = bad ? nan : ldexp(lo[r], e + f);
+            cl[1] = bad ? nan : ldexp(lo[r + 4], e + f);
+        }
+    }
+}
+
 template <int S, int WMW, int WNW, int NST>
 struct TileCfg {
     static constexpr int BM = 32 * WMW, BN = 32 * WNW;
@@ -419,10 +466,13 @@ __device__ __forceinline__ void stream_body(const GemmArgs& g, int s, int top, i
         __builtin_amdgcn_global_load_lds((global_cvoid*)(src), (lds_void*)(&lds[buf][wave * 64]), 16, 0, 0);
     };
 
-    double acc64[16];
+    double acc64[16], lo64[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r)
+    for (int r = 0; r < 16; ++r) {
         acc64[r] = (g.mode == kRawAdd) ? g.acc[col * g.Mp + row0 + 8 * (r >> 2) + 4 * half + (r & 3)] : 0.0;
+        lo64[r] = 0.0;
+    }
+    const bool dd = g.mode == kFinalDD;
     const int64_t nchunks = (nsteps + g.chunk_steps - 1) / g.chunk_steps;
     const int dmin = top ? s + 1 : 2;
     for (int64_t c = 0; c < nchunks; ++c) {
@@ -456,6 +506,10 @@ __device__ __forceinline__ void stream_body(const GemmArgs& g, int s, int top, i
                 for (int r = 0; r < 16; ++r)
                     g.diag_out[((c * s + (d - 2)) * g.Np + col) * g.Mp + row0 + 8 * (r >> 2) + 4 * half + (r & 3)] =
                         acc[r];
+            } else if (dd) {
+                const double sc = ldexp(1.0, -7 * d);  // exact power of two
+#pragma unroll
+                for (int r = 0; r < 16; ++r) dd_add_exact(acc64[r], lo64[r], static_cast<double>(acc[r]) * sc);
             } else {
                 const double sc = ldexp(1.0, -7 * d);  // exact power of two
 #pragma unroll
@@ -464,7 +518,10 @@ __device__ __forceinline__ void stream_body(const GemmArgs& g, int s, int top, i
         }
     }
     if constexpr (DIAG) return;
-    store_tile(g, acc64, row0, half, col);
+    if (dd)
+        store_tile_dd(g, acc64, lo64, row0, half, col);
+    else
+        store_tile(g, acc64, row0, half, col);
 }
 
 template <bool DIAG>
@@ -591,6 +648,7 @@ hipError_t launch_gemm(const GemmArgs& g, hipStream_t st) {
     const bool raw = g.mode == kRawWrite || g.mode == kRawAdd || g.mode == kRawWriteFinal;
     if (raw && g.acc == nullptr) return hipErrorInvalidValue;
     if (g.mode == kCombine3M && (g.t1 == nullptr || g.t2 == nullptr || g.cplx)) return hipErrorInvalidValue;
+    if (g.mode == kFinalDD) return g.c_lo == nullptr || g.top ? hipErrorInvalidValue : launch_stream(g, st);
     if (g.tile == 3) return launch_stream(g, st);
     switch (g.s) {
         case 1: return launch_s<1>(g, st);

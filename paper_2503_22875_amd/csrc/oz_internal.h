@@ -128,6 +128,8 @@ struct GemmArgs {
     const double* t1;
     const double* t2;
     int64_t ldt;
+    // kFinalDD: the low parts of the double-double result (same layout as C)
+    double* c_lo;
 };
 // Epilogue modes: kFinal writes alpha*ldexp(acc, E+F) + beta*C into C; kRawWrite
 // stores the FP64 tile sum acc (before ldexp) into g.acc; kRawAdd adds the new
@@ -135,8 +137,11 @@ struct GemmArgs {
 // kRawWriteFinal does both kRawWrite and kFinal (for beta = 0, where C can be
 // rewritten from acc if the slice count grows); kCombine3M finishes a complex
 // product in the 3-real-product form: this product is T3, t1 / t2 hold T1 / T2,
-// and C (complex) receives alpha (T1 - T2 + i ((T3 - T1) - T2)) + beta C.
-constexpr int kFinal = 0, kRawWrite = 1, kRawAdd = 2, kRawWriteFinal = 3, kCombine3M = 4;
+// and C (complex) receives alpha (T1 - T2 + i ((T3 - T1) - T2)) + beta C;
+// kFinalDD (streaming kernel only) folds the anti-diagonal sums into a
+// double-double (hi, lo) in the FP64 fold order and writes ldexp(hi, E+F) to C
+// and ldexp(lo, E+F) to c_lo (alpha = 1, beta = 0).
+constexpr int kFinal = 0, kRawWrite = 1, kRawAdd = 2, kRawWriteFinal = 3, kCombine3M = 4, kFinalDD = 5;
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t st);
 
 // Batched products: one persistent launch over a list of tiles of many
