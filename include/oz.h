@@ -90,10 +90,12 @@ typedef struct oz_handle_s* oz_handle_t;
  *           order (the sums can double the scale of T3).  A row or column
  *           whose sum overflows counts as non-finite.
  *  kernel : GEMM kernel shape; 0 = the default (the 64 x 64 block for
- *           s <= 8, streaming above), 1 = 128 x 64 block with a 3-stage LDS
- *           ring, 2 = 64 x 64 block with 2 stages (both for s <= 8), 3 =
- *           per-diagonal streaming (any s; the only choice for s > 8).  Every
- *           shape gives the same bits.
+ *           s <= 8; for 9 <= s <= 14 the same all-diagonal block at one wave
+ *           per SIMD, except where its registers would not hold the chunked
+ *           sums (several INT32 chunks at s >= 13); streaming otherwise),
+ *           1 = 128 x 64 block with a 3-stage LDS ring, 2 = 64 x 64 block with
+ *           2 stages (both for s <= 8), 3 = per-diagonal streaming (any s).
+ *           Every shape gives the same bits.
  *  sstart : tolerance-driven calls only: the starting slice count; 0 lets
  *           `selector` choose it.
  *  selector: tolerance-driven calls with sstart == 0: 0 = the rule of
@@ -185,8 +187,10 @@ int oz_zgemm(oz_handle_t handle, char transa, char transb, int64_t m, int64_t n,
  * NaN in both for a row or column with Inf/NaN input (rep->status
  * OZ_ERR_NONFINITE).  alpha = 1 and beta = 0 (C is not read).  Fixed slice
  * counts only (prec->slices 1..18, tolerance mode returns 14); complex uses the
- * 4-product form (zmode 3 returns 14); runs the per-diagonal streaming kernel
- * whatever prec->kernel says.  Returns 12 when C_lo is NULL or equals C_hi;
+ * 4-product form (zmode 3 returns 14); runs the all-diagonal kernel at one
+ * wave per SIMD for s <= 14 (one INT32 chunk, or several up to s = 11) and
+ * the per-diagonal streaming kernel otherwise, or when prec->kernel is 3.
+ * Returns 12 when C_lo is NULL or equals C_hi;
  * argument errors otherwise as oz_dgemm. */
 int oz_dgemm_x2(oz_handle_t handle, char transa, char transb, int64_t m, int64_t n, int64_t k,
                 const double* A, int64_t lda, const double* B, int64_t ldb, double* C_hi, double* C_lo,

@@ -465,10 +465,10 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
     g.diag_out = nullptr;
     if (rep) rep->kchunks = static_cast<int32_t>((p.la.kpad + kc - 1) / kc);
 
-    if (c_lo) {
+    if (c_lo) {  // the GEMM launcher picks the kernel for this mode
         g.mode = oz::kFinalDD;
         g.c_lo = c_lo;
-        g.tile = 3;
+        g.tile = 0;
     }
     if (!tol_mode) {
         if (!c_lo) g.mode = oz::kFinal;

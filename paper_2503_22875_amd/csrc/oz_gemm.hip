@@ -56,6 +56,16 @@ __device__ __forceinline__ void fold_diags(double (&acc64)[16], v16i (&acc)[ND])
     if constexpr (DD > DLO) fold_diags<ND, DLO, DD - 1>(acc64, acc);
 }
 
+// The same fold into a double-double (hi, lo): each term, exact in FP64, is
+// added by dd_add_exact (defined below).
+__device__ __forceinline__ void dd_add_exact(double& hi, double& lo, double x);
+template <int ND, int DLO, int DD>
+__device__ __forceinline__ void fold_diags_dd(double (&hi)[16], double (&lo)[16], v16i (&acc)[ND]) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) dd_add_exact(hi[r], lo[r], static_cast<double>(acc[DD - DLO][r]) * DiagScale<DD>::value);
+    if constexpr (DD > DLO) fold_diags_dd<ND, DLO, DD - 1>(hi, lo, acc);
+}
+
 // Tile order: the hardware hands consecutive blocks to the 8 XCDs in turn,
 // and each XCD has its own L2.  Block b is given the tile t = start(x) + b/8 of
 // a contiguous range per XCD x = b % 8, and inside that range tiles run in
@@ -252,7 +262,8 @@ struct TileCfg {
 // step S-1 -> S of a tolerance-driven call; otherwise all d = 2 .. S+1.
 // One BM x BN tile (tile row tm, tile column tn) of the product described by g,
 // staged through the caller's LDS ring lds[NST][STAGE].
-template <int S, int WMW, int WNW, int NST, bool TOP, bool DIAG, bool MULTI>
+// XD: fold into a double-double and write C_hi / C_lo (kFinalDD).
+template <int S, int WMW, int WNW, int NST, bool TOP, bool DIAG, bool MULTI, bool XD = false>
 __device__ __forceinline__ void tile_body(const GemmArgs& g, int64_t tm, int64_t tn,
                                           v4i (*lds)[TileCfg<S, WMW, WNW, NST>::STAGE]) {
     using T = TileCfg<S, WMW, WNW, NST>;
@@ -336,7 +347,11 @@ __device__ __forceinline__ void tile_body(const GemmArgs& g, int64_t tm, int64_t
             a64[r] = (g.mode == kRawAdd) ? g.acc[col * g.Mp + row0 + 8 * (r >> 2) + 4 * half + (r & 3)] : 0.0;
     };
     double acc64[16];
+    double lo64[XD ? 16 : 1];
     if constexpr (MULTI) init64(acc64);
+    if constexpr (XD)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) lo64[r] = 0.0;
 
     // prologue: stages 0 .. NST-2 in flight; stage 0 landed, the others may fly
 #pragma unroll
@@ -372,6 +387,8 @@ __device__ __forceinline__ void tile_body(const GemmArgs& g, int64_t tm, int64_t
                         for (int r = 0; r < 16; ++r)
                             g.diag_out[((chunk * S + d + DLO) * g.Np + col) * g.Mp + row0 + 8 * (r >> 2) +
                                        4 * half + (r & 3)] = acc[d][r];
+                } else if constexpr (XD) {
+                    fold_diags_dd<ND, DLO, S - 1>(acc64, lo64, acc);
                 } else {
                     fold_diags<ND, DLO, S - 1>(acc64, acc);
                 }
@@ -403,9 +420,15 @@ __device__ __forceinline__ void tile_body(const GemmArgs& g, int64_t tm, int64_t
     if constexpr (DIAG) return;
     if constexpr (!MULTI) {
         init64(acc64);
-        fold_diags<ND, DLO, S - 1>(acc64, acc);
+        if constexpr (XD)
+            fold_diags_dd<ND, DLO, S - 1>(acc64, lo64, acc);
+        else
+            fold_diags<ND, DLO, S - 1>(acc64, acc);
     }
-    store_tile(g, acc64, row0, half, col);
+    if constexpr (XD)
+        store_tile_dd(g, acc64, lo64, row0, half, col);
+    else
+        store_tile(g, acc64, row0, half, col);
 }
 
 template <int S, int WMW, int WNW, int NST, bool TOP, bool DIAG, bool MULTI>
@@ -416,6 +439,19 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64 * WMW * WNW, 64 * WMW *
     int64_t tm, tn;
     tile_of_block(blockIdx.x, g.Mp / T::BM, g.Np / T::BN, tm, tn);
     tile_body<S, WMW, WNW, NST, TOP, DIAG, MULTI>(g, tm, tn, lds);
+}
+
+// Wide form for 9 <= s <= kMaxWideSlices: the same tile body on a 64 x 64
+// block with a 2-stage ring at one wave per SIMD, which gives each wave the
+// 512 registers that s INT32 diagonal tiles need (one block per CU).
+template <int S, bool TOP, bool DIAG, bool MULTI, bool XD>
+__global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(1, 1))) void gemm_wide_kernel(
+    GemmArgs g) {
+    using T = TileCfg<S, 2, 2, 2>;
+    __shared__ v4i lds[2][T::STAGE];
+    int64_t tm, tn;
+    tile_of_block(blockIdx.x, g.Mp / T::BM, g.Np / T::BN, tm, tn);
+    tile_body<S, 2, 2, 2, TOP, DIAG, MULTI, XD>(g, tm, tn, lds);
 }
 
 // Persistent form for a batch: block b takes tiles b, b + gridDim.x, ... of the
@@ -630,6 +666,61 @@ hipError_t launch_s(const GemmArgs& g, hipStream_t st) {
     return launch_cfg<S, 2, 2, ring64(S)>(g, st);
 }
 
+hipError_t launch_stream(const GemmArgs& g, hipStream_t st);
+
+// Combinations whose INT32 tiles plus the FP64 (or double-double) chunk sums
+// would spill registers go to the streaming kernel instead: several INT32
+// chunks with s >= 13 (s >= 12 for a double-double result), and the chunked
+// diagonal export with s = 14.
+template <int S>
+hipError_t launch_wide(const GemmArgs& g, hipStream_t st) {
+    using T = TileCfg<S, 2, 2, 2>;
+    const int64_t blocks = (g.Np / T::BN) * (g.Mp / T::BM);
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    dim3 grid(static_cast<unsigned>(blocks)), block(256);
+    const bool multi = g.chunk_steps < g.kpad / kStep;
+#define OZ_WIDE(TOPV, DIAGV, MULTIV, XDV) \
+    hipLaunchKernelGGL((gemm_wide_kernel<S, TOPV, DIAGV, MULTIV, XDV>), grid, block, 0, st, g)
+    if (g.mode == kFinalDD) {
+        if (!multi) {
+            OZ_WIDE(false, false, false, true);
+        } else {
+            if constexpr (S <= 11) OZ_WIDE(false, false, true, true);
+            else return launch_stream(g, st);
+        }
+    } else if (g.diag_out && !g.top) {
+        if constexpr (S <= 13) OZ_WIDE(false, true, true, false);
+        else return launch_stream(g, st);
+    } else if (g.diag_out) {
+        OZ_WIDE(true, true, true, false);
+    } else if (g.top && multi) {
+        OZ_WIDE(true, false, true, false);
+    } else if (g.top) {
+        OZ_WIDE(true, false, false, false);
+    } else if (multi) {
+        if constexpr (S <= 12) OZ_WIDE(false, false, true, false);
+        else return launch_stream(g, st);
+    } else {
+        OZ_WIDE(false, false, false, false);
+    }
+#undef OZ_WIDE
+    return hipGetLastError();
+}
+
+// Double-double results for s <= 8: the wide form as well (its XD variants only).
+template <int S>
+hipError_t launch_wide_xd(const GemmArgs& g, hipStream_t st) {
+    using T = TileCfg<S, 2, 2, 2>;
+    const int64_t blocks = (g.Np / T::BN) * (g.Mp / T::BM);
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    dim3 grid(static_cast<unsigned>(blocks)), block(256);
+    if (g.chunk_steps < g.kpad / kStep)
+        hipLaunchKernelGGL((gemm_wide_kernel<S, false, false, true, true>), grid, block, 0, st, g);
+    else
+        hipLaunchKernelGGL((gemm_wide_kernel<S, false, false, false, true>), grid, block, 0, st, g);
+    return hipGetLastError();
+}
+
 hipError_t launch_stream(const GemmArgs& g, hipStream_t st) {
     const int64_t blocks = (g.Np / 64) * (g.Mp / 64);
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
@@ -648,8 +739,20 @@ hipError_t launch_gemm(const GemmArgs& g, hipStream_t st) {
     const bool raw = g.mode == kRawWrite || g.mode == kRawAdd || g.mode == kRawWriteFinal;
     if (raw && g.acc == nullptr) return hipErrorInvalidValue;
     if (g.mode == kCombine3M && (g.t1 == nullptr || g.t2 == nullptr || g.cplx)) return hipErrorInvalidValue;
-    if (g.mode == kFinalDD) return g.c_lo == nullptr || g.top ? hipErrorInvalidValue : launch_stream(g, st);
+    if (g.mode == kFinalDD && (g.c_lo == nullptr || g.top)) return hipErrorInvalidValue;
     if (g.tile == 3) return launch_stream(g, st);
+    if (g.mode == kFinalDD && g.s <= kMaxLiveSlices) {
+        switch (g.s) {
+            case 1: return launch_wide_xd<1>(g, st);
+            case 2: return launch_wide_xd<2>(g, st);
+            case 3: return launch_wide_xd<3>(g, st);
+            case 4: return launch_wide_xd<4>(g, st);
+            case 5: return launch_wide_xd<5>(g, st);
+            case 6: return launch_wide_xd<6>(g, st);
+            case 7: return launch_wide_xd<7>(g, st);
+            default: return launch_wide_xd<8>(g, st);
+        }
+    }
     switch (g.s) {
         case 1: return launch_s<1>(g, st);
         case 2: return launch_s<2>(g, st);
@@ -659,6 +762,12 @@ hipError_t launch_gemm(const GemmArgs& g, hipStream_t st) {
         case 6: return launch_s<6>(g, st);
         case 7: return launch_s<7>(g, st);
         case 8: return launch_s<8>(g, st);
+        case 9: return launch_wide<9>(g, st);
+        case 10: return launch_wide<10>(g, st);
+        case 11: return launch_wide<11>(g, st);
+        case 12: return launch_wide<12>(g, st);
+        case 13: return launch_wide<13>(g, st);
+        case 14: return launch_wide<14>(g, st);
         default: return launch_stream(g, st);
     }
 }

@@ -16,6 +16,7 @@ constexpr int kStep = 32;
 constexpr int kHalf = 16;
 // Largest slice count the all-diagonal kernel keeps in registers.
 constexpr int kMaxLiveSlices = 8;
+constexpr int kMaxWideSlices = 14;  // the all-diagonal tile at one wave per SIMD serves s = 9 .. 14
 // Scale exponent marking a vector that holds Inf or NaN.
 constexpr int32_t kNonFiniteExp = INT32_MIN;
 

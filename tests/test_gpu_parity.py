@@ -342,7 +342,7 @@ def test_dgemm_wide_range_full_size_sampled(oz, handle):
 
 
 @pytest.mark.parametrize("cplx", [0, 1])
-@pytest.mark.parametrize("s,kc", [(9, 0), (12, 128), (18, 0)])
+@pytest.mark.parametrize("s,kc", [(9, 0), (11, 0), (12, 128), (13, 0), (13, 128), (14, 0), (14, 256), (18, 0)])
 def test_large_slice_counts_bit_exact(oz, handle, cplx, s, kc):
     rng = np.random.default_rng(100 + s)
     m, n, k = 70, 65, 300

@@ -55,7 +55,7 @@ def run_x2(oz, handle, ta, tb, A, B, s, kchunk=0, check=True):
     return st, rep, from_dev(dH, m, n, ldc), from_dev(dL, m, n, ldc)
 
 
-@pytest.mark.parametrize("s", [2, 7, 9, 12, 18])
+@pytest.mark.parametrize("s", [2, 7, 9, 12, 14, 18])
 @pytest.mark.parametrize("ta,tb", [("N", "N"), ("T", "N"), ("N", "T"), ("T", "T")])
 def test_dgemm_x2_bit_exact(oz, handle, s, ta, tb):
     rng = np.random.default_rng(100 * s + ord(ta) + 3 * ord(tb))
@@ -91,6 +91,10 @@ def test_x2_forced_chunks_and_exact_integers(oz, handle, cplx):
     print("x2 chunks", cplx, flush=True)
     st, rep, hi, lo = run_x2(oz, handle, "N", "N", A, B, 10, kchunk=128)
     whi, wlo = oracle.emu_gemm_x2("N", "N", A, B, 10, kc=128)
+    assert rep.kchunks > 1
+    assert np.array_equal(hi, whi) and np.array_equal(lo, wlo)
+    st, rep, hi, lo = run_x2(oz, handle, "N", "N", A, B, 12, kchunk=128)  # chunked at s = 12: streaming kernel
+    whi, wlo = oracle.emu_gemm_x2("N", "N", A, B, 12, kc=128)
     assert rep.kchunks > 1
     assert np.array_equal(hi, whi) and np.array_equal(lo, wlo)
     # integer inputs at s = 12: hi + lo is the exact product (about 80 bits)
