@@ -23,7 +23,8 @@ float64 or complex128; ``trans`` is 'N', 'T' or 'C'):
 
 Submodules ``select`` (features, error table and labels of the learned
 slice-count selector) and ``mlp`` (the selector network: forward, pinball
-loss, backward, Adam) are plain numpy.
+loss, backward, Adam) are plain numpy; ``lu`` is the blocked LU factorisation
+and inverse of a complex matrix with every level-3 update an ``emu_gemm``.
 
 Parity of each function is pinned in tests/test_oracle_*.py; none is unpinned.
 """
