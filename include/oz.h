@@ -199,6 +199,45 @@ int oz_zgemm_x2(oz_handle_t handle, char transa, char transb, int64_t m, int64_t
                 const double* A, int64_t lda, const double* B, int64_t ldb, double* C_hi, double* C_lo,
                 int64_t ldc, const oz_prec_t* prec, oz_report_t* rep);
 
+/* ---- LU-based complex inversion (the paper's application, Sec. 3.2) --------
+ *
+ * The application's solver inverts complex matrices through an LU
+ * factorisation whose level-3 work is ZGEMM; here every such product is the
+ * emulated oz_zgemm at the precision `prec` (NULL: s = 7), on the handle's
+ * stream.  The panel factorisation, the row interchanges and the triangular
+ * solves run in FP64 kernels of this library.  Complex arithmetic outside the
+ * products is written out on the parts: a b = (ar br - ai bi, ar bi + ai br),
+ * 1/p = (pr / (pr^2 + pi^2), -pi / (pr^2 + pi^2)), each operation rounded.
+ *
+ * oz_zgetrf: A = P L U in place (n x n, interleaved complex, column-major,
+ * leading dimension lda >= max(1, n), device memory), right-looking in panels
+ * of nb columns (nb 0: 64).  For column j the pivot is the first row r >= j
+ * with the largest |Re a_rj| + |Im a_rj|; ipiv[j] = r (device int32, n
+ * entries, 0-based row numbers; interchanges apply in order j = 0 .. n-1).
+ * A panel is factored column by column (swap across the panel, scale the
+ * column below the diagonal by the pivot's reciprocal, rank-1 update of the
+ * panel columns to its right); its interchanges are then applied to the other
+ * columns, U12 = L11^-1 A12 by forward substitution (sums in index order), and
+ * A22 = A22 - L21 U12 by oz_zgemm (alpha = -1, beta = 1).  *info (host) = 0,
+ * or j + 1 for the first exactly zero pivot (the column is then left unscaled
+ * and the factorisation continues).  Synchronises.  Argument errors: 2 (n < 0),
+ * 4 (lda), 6 (nb < 0), 7 (prec), 8 (info NULL), OZ_ERR_ARG (A or ipiv NULL
+ * with n > 0); errors of oz_zgemm are passed on.  Inputs with Inf or NaN are
+ * not supported (the pivot search skips NaN entries).
+ *
+ * oz_zgetri: X = A^-1 (n x n, leading dimension ldx, device memory distinct
+ * from LU) from the output of oz_zgetrf, by solving A X = I: X = P I, then for
+ * block rows of nb (nb 0: 64) from the first, X_i = X_i - L[i, :i] X[:i]
+ * (oz_zgemm) followed by X_i = L_ii^-1 X_i, then from the last block row,
+ * X_i = X_i - U[i, i+1:] X[i+1:] (oz_zgemm) followed by back substitution
+ * with U_ii (each row multiplied by the reciprocal of its diagonal entry).
+ * Synchronises.  Argument errors: 2 (n), 4 (lda), 7 (ldx), 8 (nb), 9 (prec),
+ * OZ_ERR_ARG (a NULL pointer with n > 0, or X == LU). */
+int oz_zgetrf(oz_handle_t handle, int64_t n, double* A, int64_t lda, int32_t* ipiv, int32_t nb,
+              const oz_prec_t* prec, int32_t* info);
+int oz_zgetri(oz_handle_t handle, int64_t n, const double* LU, int64_t lda, const int32_t* ipiv, double* X,
+              int64_t ldx, int32_t nb, const oz_prec_t* prec);
+
 /* The starting slice count of a tolerance-driven call: the smallest s in
  * [1, smax] (smax 0: 12) with 2.5 (s+1) 2^(-7s) sqrt((1/M_A + 1/M_B)/3) <= tol,
  * M_A / M_B the mean over rows of op(A) / columns of op(B) of the mean square

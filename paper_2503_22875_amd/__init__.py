@@ -38,7 +38,7 @@ EXPORTS = ["oz_create", "oz_destroy", "oz_set_stream", "oz_status_string", "oz_w
            "oz_load_tuning", "oz_gen_operands", "oz_features", "oz_selector_dataset", "oz_mlp_create",
            "oz_mlp_destroy", "oz_mlp_set_params", "oz_mlp_get_params", "oz_mlp_fit_norm", "oz_mlp_forward",
            "oz_mlp_grad", "oz_mlp_train_step", "oz_mlp_train", "oz_mlp_save", "oz_mlp_load", "oz_set_selector",
-           "oz_predict_slices", "oz_batch_report", "oz_dgemm_x2", "oz_zgemm_x2"]
+           "oz_predict_slices", "oz_batch_report", "oz_dgemm_x2", "oz_zgemm_x2", "oz_zgetrf", "oz_zgetri"]
 
 OZ_NUM_FEATURES = 16
 OZ_MLP_NPARAM = 5313
@@ -92,6 +92,8 @@ def _load():
                      PP(oz_report_t)],
         "oz_dgemm_x2": [P, C, C, I64, I64, I64, P, I64, P, I64, P, P, I64, PP(oz_prec_t), PP(oz_report_t)],
         "oz_zgemm_x2": [P, C, C, I64, I64, I64, P, I64, P, I64, P, P, I64, PP(oz_prec_t), PP(oz_report_t)],
+        "oz_zgetrf": [P, I64, P, I64, P, I32, PP(oz_prec_t), PP(I32)],
+        "oz_zgetri": [P, I64, P, I64, P, P, I64, I32, PP(oz_prec_t)],
         "oz_split_layout": [C, ctypes.c_int, I64, I64, I32, PP(I64), PP(I64), PP(ctypes.c_size_t)],
         "oz_split": [P, C, C, ctypes.c_int, I64, I64, P, I64, I32, P, P],
         "oz_diag_sums": [P, I32, I64, I32, I64, I64, I64, P, P, P],
@@ -236,6 +238,26 @@ def oz_zgemm_x2(handle, transa, transb, m, n, k, A, lda, B, ldb, C_hi, C_lo, ldc
     """Complex version of oz_dgemm_x2 (interleaved (re, im) doubles)."""
     return _gemm_x2("oz_zgemm_x2", handle, transa, transb, m, n, k, A, lda, B, ldb, C_hi, C_lo, ldc, p, report,
                     check)
+
+
+def oz_zgetrf(handle, n, A, lda, ipiv, nb=0, p=None, check=True):
+    """LU with partial pivoting in place (device A, device int32 ipiv); returns info."""
+    info = ctypes.c_int32()
+    st = _lib.oz_zgetrf(handle, n, _ptr(A), lda, _ptr(ipiv), nb, ctypes.byref(p) if p is not None else None,
+                        ctypes.byref(info))
+    if check:
+        _check("oz_zgetrf", st)
+        return info.value
+    return st, info.value
+
+
+def oz_zgetri(handle, n, LU, lda, ipiv, X, ldx, nb=0, p=None, check=True):
+    """X = A^-1 from the factorisation oz_zgetrf left in LU and ipiv."""
+    st = _lib.oz_zgetri(handle, n, _ptr(LU), lda, _ptr(ipiv), _ptr(X), ldx, nb,
+                        ctypes.byref(p) if p is not None else None)
+    if check:
+        _check("oz_zgetri", st)
+    return st
 
 
 def oz_split_layout(side, is_complex, nv, k, slices):
