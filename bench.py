@@ -479,9 +479,65 @@ def bench_x2(args):
     print(json.dumps({"workload": "dgemm n=4096 double-double result", "rows": rows}), flush=True)
 
 
+def bench_inv(args):
+    """LU-based complex inversion, n = 4096 (entries N(0,1) + i N(0,1)): time
+    of oz_zgetrf + oz_zgetri at s = 3..8 and 14, panel width nb, beside the
+    native FP64 inverse (torch.linalg.inv, same GPU).  Per s: the inverse's
+    largest entry error relative to the largest entry of the native inverse,
+    its residual max |A X - I|, and the effective rate on LAPACK's operation
+    count of getrf + getri (8 n^3 real flops for complex)."""
+    import torch
+
+    import paper_2503_22875_amd as oz
+    import workloads
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    h = oz.oz_create(0)
+    oz.oz_set_stream(h, stream.cuda_stream)
+    n, nb = args.n, args.nb
+    A = workloads.zinv_gauss(n, seed=0)
+    Ad = torch.from_numpy(A).cuda()
+    dA0 = torch.view_as_real(torch.from_numpy(np.ascontiguousarray(A.T))).reshape(-1).cuda()
+    dA = torch.empty_like(dA0)
+    dX = torch.empty_like(dA0)
+    ipiv = torch.empty(n, dtype=torch.int32, device="cuda")
+    eye = torch.eye(n, dtype=torch.complex128, device="cuda")
+    flops = 8.0 * n ** 3
+    steps = max(1, min(args.steps, 5))
+    ms_nat = _time_ms(lambda: torch.linalg.inv(Ad), stream, steps, 1)
+    Xr = torch.linalg.inv(Ad)
+    resid_nat = float((Ad @ Xr - eye).abs().max())
+    rows = []
+    for s in [int(v) for v in args.inv_slices.split(",")]:
+        p = oz.prec(s)
+
+        def run():
+            dA.copy_(dA0)
+            oz.oz_zgetrf(h, n, dA, n, ipiv, nb, p)
+            oz.oz_zgetri(h, n, dA, n, ipiv, dX, n, nb, p)
+
+        run()
+        X = torch.view_as_complex(dX.view(n, n, 2)).T
+        err = float((X - Xr).abs().max() / Xr.abs().max())
+        resid = float((Ad @ X - eye).abs().max())
+        ms = _time_ms(run, stream, steps, 1)
+        row = {"s": s, "ms": round(ms, 3), "tflops_eff": round(flops / (ms * 1e-3) / 1e12, 2),
+               "err_vs_native": float("%.3e" % err), "resid": float("%.3e" % resid)}
+        print(json.dumps(row), flush=True)
+        rows.append(row)
+    oz.oz_destroy(h)
+    print(json.dumps({"workload": "complex LU inversion n=%d nb=%d (N(0,1)+iN(0,1))" % (n, nb),
+                      "native": {"ms": round(ms_nat, 3), "tflops_eff": round(flops / (ms_nat * 1e-3) / 1e12, 2),
+                                 "resid": float("%.3e" % resid_nat)},
+                      "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="zgemm4096", choices=["zgemm4096", "batch512", "select", "sweep", "wide_tol", "blas", "x2"])
+    ap.add_argument("--workload", default="zgemm4096", choices=["zgemm4096", "batch512", "select", "sweep", "wide_tol", "blas", "x2", "inv"])
+    ap.add_argument("--nb", type=int, default=64, help="panel width of the inversion workload")
+    ap.add_argument("--inv-slices", default="3,4,5,6,7,8,14")
     ap.add_argument("--select-data", default="normal,spread")
     ap.add_argument("--select-tols", default="1e-10,1e-12,1e-14")
     ap.add_argument("--sweep-n", default="2048,4096")
@@ -516,6 +572,8 @@ def main():
         return bench_blas(args)
     if args.workload == "x2":
         return bench_x2(args)
+    if args.workload == "inv":
+        return bench_inv(args)
 
     import torch
 

@@ -26,8 +26,10 @@ getri(LU, piv, nb, s)   X = A^-1 by solving A X = I:
   * forward, block row i: X_i <- X_i - L[i, :i] X[:i] (emulated), then
     X_i <- L_ii^-1 X_i;
   * backward, block row i from the last: X_i <- X_i - U[i, i+1:] X[i+1:]
-    (emulated), then X_i <- U_ii^-1 X_i by back substitution (sums in index
-    order, each row multiplied by the reciprocal of its diagonal entry).
+    (emulated), then X_i <- U_ii^-1 X_i by back substitution: rows from the
+    last, each row's sum taking the solved unknowns in the order they were
+    solved (highest index first), then multiplied by the reciprocal of its
+    diagonal entry.
 
 A singular U (a zero pivot) is reported as info = j + 1 for the first such
 column, as LAPACK does; the factorization then skips the scaling of that
@@ -97,11 +99,12 @@ def _trsm_lower_unit(Lr, Li, Br, Bi):
 
 
 def _trsm_upper(Ur, Ui, Br, Bi):
-    """B <- U^-1 B, U upper (nb x nb); rows from the last, sums in index order."""
+    """B <- U^-1 B, U upper (nb x nb); rows from the last, each sum over the
+    solved unknowns in solve order (k = nb-1 down to i+1)."""
     nb = Ur.shape[0]
     for i in range(nb - 1, -1, -1):
         accr, acci = Br[i].copy(), Bi[i].copy()
-        for k in range(i + 1, nb):
+        for k in range(nb - 1, i, -1):
             tr, ti = _cmul(Ur[i, k], Ui[i, k], Br[k], Bi[k])
             accr, acci = accr - tr, acci - ti
         rr, ri = _recip(Ur[i, i], Ui[i, i])

@@ -69,6 +69,36 @@ def test_getrf_getri_bit_exact(oz, handle, n, nb, s):
     assert np.array_equal(X, X_ref)
 
 
+def test_getrf_bit_exact_tall_panels(oz, handle):
+    # rows beyond 2048 below the first panels: the panel runs 4 rows per thread
+    rng = np.random.default_rng(2100)
+    n, nb, s = 2100, 32, 3
+    A = cmat(rng, n)
+    print("n=%d nb=%d s=%d" % (n, nb, s), flush=True)
+    dA, lda, ipiv, info = gpu_getrf(oz, handle, A, nb, s, pad=1)
+    LU_ref, piv_ref, info_ref = lu.getrf(A, nb, s)
+    assert info == info_ref == 0
+    assert np.array_equal(ipiv.cpu().numpy(), piv_ref)
+    assert np.array_equal(from_dev(dA, n, n, lda), LU_ref)
+
+
+def test_getrf_matches_lapack_pivots_beyond_4096_rows(oz, handle):
+    # rows beyond 4096 (8 rows per thread in the panel): at s = 14 the updates
+    # are FP64-accurate, so the pivots are LAPACK's (same rule) and the factors
+    # reproduce P A to rounding
+    import scipy.linalg
+    rng = np.random.default_rng(5000)
+    n, nb = 5000, 64
+    A = cmat(rng, n)
+    print("n=%d nb=%d s=14" % (n, nb), flush=True)
+    dA, lda, ipiv, info = gpu_getrf(oz, handle, A, nb, 14, pad=0)
+    assert info == 0
+    lu_ref, piv_ref = scipy.linalg.lu_factor(A)
+    assert np.array_equal(ipiv.cpu().numpy(), piv_ref)
+    LU = from_dev(dA, n, n, lda)
+    assert np.abs(LU - lu_ref).max() / np.abs(lu_ref).max() < 1e-11
+
+
 def test_getri_from_oracle_factors(oz, handle):
     # the inverse step alone, fed the oracle's factors and pivots
     rng = np.random.default_rng(77)

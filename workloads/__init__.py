@@ -19,6 +19,9 @@ distributions of the workloads the emulated GEMM is benchmarked on:
                       10^U(-8, 8) and columns of B by 10^U(-8, 8).
 * ``dgemm_spread``    general real operands whose per-entry exponents are
                       spread over sigma binades, for slice-count selection data.
+* ``zinv_gauss``      one n x n complex matrix to invert, entries
+                      N(0,1) + i N(0,1) (condition number of order n), the
+                      stand-in for the application's complex LU-inverted matrix.
 """
 import numpy as np
 
@@ -67,6 +70,11 @@ def zgemm_batch(count=512, seed=0):
         B = np.asfortranarray(rng.standard_normal((nb, nb)) + 1j * rng.standard_normal((nb, nb)))
         out.append((A, B))
     return out
+
+
+def zinv_gauss(n=4096, seed=0):
+    rng = np.random.default_rng(seed)
+    return np.asfortranarray(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
 
 
 def dgemm_wide(m=4096, n=4096, k=8192, seed=0):
