@@ -481,7 +481,8 @@ def bench_x2(args):
 
 def bench_inv(args):
     """LU-based complex inversion, n = 4096 (entries N(0,1) + i N(0,1)): time
-    of oz_zgetrf + oz_zgetri at s = 3..8 and 14, panel width nb, beside the
+    of oz_zgetrf + oz_zgetri at s = 3..8 and 14 (panel width nb, solve blocks
+    nb_inv), beside the
     native FP64 inverse (torch.linalg.inv, same GPU).  Per s: the inverse's
     largest entry error relative to the largest entry of the native inverse,
     its residual max |A X - I|, and the effective rate on LAPACK's operation
@@ -495,7 +496,7 @@ def bench_inv(args):
     stream = torch.cuda.current_stream()
     h = oz.oz_create(0)
     oz.oz_set_stream(h, stream.cuda_stream)
-    n, nb = args.n, args.nb
+    n, nb, nbi = args.n, args.nb, args.nb_inv
     A = workloads.zinv_gauss(n, seed=0)
     Ad = torch.from_numpy(A).cuda()
     dA0 = torch.view_as_real(torch.from_numpy(np.ascontiguousarray(A.T))).reshape(-1).cuda()
@@ -515,7 +516,7 @@ def bench_inv(args):
         def run():
             dA.copy_(dA0)
             oz.oz_zgetrf(h, n, dA, n, ipiv, nb, p)
-            oz.oz_zgetri(h, n, dA, n, ipiv, dX, n, nb, p)
+            oz.oz_zgetri(h, n, dA, n, ipiv, dX, n, nbi, p)
 
         run()
         X = torch.view_as_complex(dX.view(n, n, 2)).T
@@ -527,7 +528,7 @@ def bench_inv(args):
         print(json.dumps(row), flush=True)
         rows.append(row)
     oz.oz_destroy(h)
-    print(json.dumps({"workload": "complex LU inversion n=%d nb=%d (N(0,1)+iN(0,1))" % (n, nb),
+    print(json.dumps({"workload": "complex LU inversion n=%d nb=%d/%d (N(0,1)+iN(0,1))" % (n, nb, nbi),
                       "native": {"ms": round(ms_nat, 3), "tflops_eff": round(flops / (ms_nat * 1e-3) / 1e12, 2),
                                  "resid": float("%.3e" % resid_nat)},
                       "rows": rows}), flush=True)
@@ -536,7 +537,8 @@ def bench_inv(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="zgemm4096", choices=["zgemm4096", "batch512", "select", "sweep", "wide_tol", "blas", "x2", "inv"])
-    ap.add_argument("--nb", type=int, default=64, help="panel width of the inversion workload")
+    ap.add_argument("--nb", type=int, default=128, help="panel width of the inversion workload (getrf)")
+    ap.add_argument("--nb-inv", type=int, default=256, help="block rows of the inversion workload's solves (getri)")
     ap.add_argument("--inv-slices", default="3,4,5,6,7,8,14")
     ap.add_argument("--select-data", default="normal,spread")
     ap.add_argument("--select-tols", default="1e-10,1e-12,1e-14")

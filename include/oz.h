@@ -211,7 +211,7 @@ int oz_zgemm_x2(oz_handle_t handle, char transa, char transb, int64_t m, int64_t
  *
  * oz_zgetrf: A = P L U in place (n x n, interleaved complex, column-major,
  * leading dimension lda >= max(1, n), device memory), right-looking in panels
- * of nb columns (nb 0: 64).  For column j the pivot is the first row r >= j
+ * of nb columns (nb 0: 128).  For column j the pivot is the first row r >= j
  * with the largest |Re a_rj| + |Im a_rj|; ipiv[j] = r (device int32, n
  * entries, 0-based row numbers; interchanges apply in order j = 0 .. n-1).
  * A panel is factored column by column (swap across the panel, scale the
@@ -220,14 +220,18 @@ int oz_zgemm_x2(oz_handle_t handle, char transa, char transb, int64_t m, int64_t
  * columns, U12 = L11^-1 A12 by forward substitution (sums in index order), and
  * A22 = A22 - L21 U12 by oz_zgemm (alpha = -1, beta = 1).  *info (host) = 0,
  * or j + 1 for the first exactly zero pivot (the column is then left unscaled
- * and the factorisation continues).  Synchronises.  Argument errors: 2 (n < 0),
+ * and the factorisation continues).  The next panel is factored on a second,
+ * library-created stream while the handle's stream runs the rest of the
+ * trailing product (issued as two products split by columns, which changes no
+ * entry of a fixed-s product); both streams are drained before the call
+ * returns.  Synchronises.  Argument errors: 2 (n < 0),
  * 4 (lda), 6 (nb < 0), 7 (prec), 8 (info NULL), OZ_ERR_ARG (A or ipiv NULL
  * with n > 0); errors of oz_zgemm are passed on.  Inputs with Inf or NaN are
  * not supported (the pivot search skips NaN entries).
  *
  * oz_zgetri: X = A^-1 (n x n, leading dimension ldx, device memory distinct
  * from LU) from the output of oz_zgetrf, by solving A X = I: X = P I, then for
- * block rows of nb (nb 0: 64) from the first, X_i = X_i - L[i, :i] X[:i]
+ * block rows of nb (nb 0: 256) from the first, X_i = X_i - L[i, :i] X[:i]
  * (oz_zgemm) followed by X_i = L_ii^-1 X_i, then from the last block row,
  * X_i = X_i - U[i, i+1:] X[i+1:] (oz_zgemm) followed by back substitution
  * with U_ii (each row multiplied by the reciprocal of its diagonal entry).

@@ -30,6 +30,8 @@ constexpr int kPanelThreads = 1024;
 constexpr int kMaxRegRows = 8;    // register panel: rows n - c0 <= 8192
 constexpr int kMaxWaveTrsm = 256; // wave-per-column triangular solves: b <= 256
 constexpr int kMaxGatherSwaps = 256;
+constexpr int kDefaultPanel = 128;       // oz_zgetrf nb = 0
+constexpr int kDefaultSolveBlock = 256;  // oz_zgetri nb = 0
 
 __device__ __forceinline__ double* at(double* X, int64_t ld, int64_t r, int64_t c) { return X + 2 * (r + c * ld); }
 __device__ __forceinline__ const double* at(const double* X, int64_t ld, int64_t r, int64_t c) {
@@ -234,36 +236,68 @@ __global__ __launch_bounds__(kPanelThreads) void panel_reg_kernel(double* A, int
             l11[tid][2 * k + 1] = xi[0][k];
         }
     }
+    // net effect of the w interchanges on the rows they touch (the block rows
+    // c0 + e and the pivot rows): row dst[e] ends up holding row src[e]
+    __shared__ int dst[2 * W], src[2 * W];
+    if (tid < 2 * w) {
+        const int x = tid < w ? tid : psub[tid - w];
+        int y = x;
+        for (int i = w - 1; i >= 0; --i) {
+            const int p = psub[i];
+            if (y == i)
+                y = p;
+            else if (y == p)
+                y = i;
+        }
+        dst[tid] = x;
+        src[tid] = y;
+    }
     __syncthreads();
-    // the other panel columns: interchanges in order, then (right of the
-    // sub-panel) u_i = a_i - sum_{k < i} l_ik u_k over the w top rows
+    // the other panel columns: the interchanges (all loads, then the stores of
+    // the pivot rows), then right of the sub-panel u_i = a_i - sum_{k < i}
+    // l_ik u_k over the w top rows, in registers
     const int left = static_cast<int>(c0 - j0), right = b - left - w;
     for (int t = tid; t < left + right; t += kPanelThreads) {
         const int64_t col = t < left ? j0 + t : c0 + w + (t - left);
-        for (int i = 0; i < w; ++i) {
-            const int p = psub[i];
-            if (p == i) continue;
-            double* x = at(A, lda, c0 + i, col);
-            double* y = at(A, lda, c0 + p, col);
-            const double t0 = x[0], t1 = x[1];
-            x[0] = y[0];
-            x[1] = y[1];
-            y[0] = t0;
-            y[1] = t1;
+        double vr[2 * W], vi[2 * W];
+#pragma unroll
+        for (int e = 0; e < 2 * W; ++e) {
+            vr[e] = 0.0;
+            vi[e] = 0.0;
+            if (e < 2 * w) {
+                const double* q = at(A, lda, c0 + src[e], col);
+                vr[e] = q[0];
+                vi[e] = q[1];
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < 2 * W; ++e) {
+            if (e >= w && e < 2 * w && src[e] != dst[e]) {
+                double* q = at(A, lda, c0 + dst[e], col);
+                q[0] = vr[e];
+                q[1] = vi[e];
+            }
         }
         if (t >= left) {
-            for (int i = 1; i < w; ++i) {
-                double* o = at(A, lda, c0 + i, col);
-                double accr = o[0], acci = o[1];
-                for (int k = 0; k < i; ++k) {
-                    const double* u = at(A, lda, c0 + k, col);
-                    double tr, ti;
-                    cmul(l11[i][2 * k], l11[i][2 * k + 1], u[0], u[1], tr, ti);
-                    accr = accr - tr;
-                    acci = acci - ti;
+#pragma unroll
+            for (int i = 1; i < W; ++i) {
+                if (i < w) {
+#pragma unroll
+                    for (int k = 0; k < i; ++k) {
+                        double tr, ti;
+                        cmul(l11[i][2 * k], l11[i][2 * k + 1], vr[k], vi[k], tr, ti);
+                        vr[i] = vr[i] - tr;
+                        vi[i] = vi[i] - ti;
+                    }
                 }
-                o[0] = accr;
-                o[1] = acci;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            if (i < w) {
+                double* q = at(A, lda, c0 + i, col);
+                q[0] = vr[i];
+                q[1] = vi[i];
             }
         }
     }
@@ -490,83 +524,80 @@ __global__ void perm_fill_kernel(double* X, int64_t ld, int64_t n, const int32_t
 }
 
 // ---------------------------------------------------------------------------
-// Triangular solves with b x ncols right-hand sides B, one wave per column,
-// lane l holding rows l + 64 t (t < R2).  Column-oriented: once x_k is final
-// it is broadcast and every row still open subtracts t_ik x_k, so each row's
-// sum runs over the unknowns in the order they are solved (ascending for the
-// unit lower solve; descending for the upper one, where x_k is the open sum
-// times the reciprocal of u_kk).
+// Triangular solves with b x ncols right-hand sides B, one wave per column
+// (16 per block), lane l holding rows l + 64 t (t < R2), the triangle staged
+// through LDS 16 columns at a time.  Column-oriented: once x_k is final it is
+// broadcast and every row still open subtracts t_ik x_k, so each row's sum runs
+// over the unknowns in the order they are solved (ascending for the unit lower
+// solve; descending for the upper one, where x_k is the open sum times the
+// reciprocal of u_kk).
+constexpr int kTrsmWaves = 16;
+constexpr int kTrsmChunk = 16;
+
 template <int R2, bool UPPER>
-__global__ __launch_bounds__(256) void trsm_wave_kernel(const double* T, int64_t ldt, int b, double* B, int64_t ldb,
-                                                        int64_t ncols) {
+__global__ __launch_bounds__(64 * kTrsmWaves) void trsm_wave_kernel(const double* T, int64_t ldt, int b, double* B,
+                                                                    int64_t ldb, int64_t ncols) {
+    __shared__ double tk[kTrsmChunk][2 * 64 * R2];
     __shared__ double rec[2 * 64 * R2];
+    constexpr int kThreads = 64 * kTrsmWaves;
     if (UPPER) {
-        for (int i = threadIdx.x; i < b; i += 256) {
+        for (int i = threadIdx.x; i < b; i += kThreads) {
             const double* d = at(T, ldt, i, i);
             double rr, ri;
             crecip(d[0], d[1], rr, ri);
             rec[2 * i] = rr;
             rec[2 * i + 1] = ri;
         }
-        __syncthreads();
     }
     const int lane = threadIdx.x & 63;
-    const int64_t c = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
-    if (c >= ncols) return;
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * kTrsmWaves + (threadIdx.x >> 6);
+    const bool active = c < ncols;
     double xr[R2], xi[R2];
 #pragma unroll
     for (int t = 0; t < R2; ++t) {
         const int i = lane + 64 * t;
         xr[t] = 0.0;
         xi[t] = 0.0;
-        if (i < b) {
+        if (active && i < b) {
             const double* e = at(B, ldb, i, c);
             xr[t] = e[0];
             xi[t] = e[1];
         }
     }
-    if (!UPPER) {
-        for (int k = 0; k < b; ++k) {
-            const int tk = k >> 6, src = k & 63;
-            double vr = xr[0], vi = xi[0];
-#pragma unroll
-            for (int t = 1; t < R2; ++t)
-                if (tk == t) {
-                    vr = xr[t];
-                    vi = xi[t];
-                }
-            vr = lane_bcast(vr, src);
-            vi = lane_bcast(vi, src);
-#pragma unroll
-            for (int t = 0; t < R2; ++t) {
-                const int i = lane + 64 * t;
-                if (i > k && i < b) {
-                    const double* l = at(T, ldt, i, k);
-                    double tr, ti;
-                    cmul(l[0], l[1], vr, vi, tr, ti);
-                    xr[t] = xr[t] - tr;
-                    xi[t] = xi[t] - ti;
-                }
-            }
+    const int nchunks = (b + kTrsmChunk - 1) / kTrsmChunk;
+    for (int q = 0; q < nchunks; ++q) {
+        // columns k_lo .. k_lo + kc - 1 of the triangle
+        const int k_lo = UPPER ? (b - (q + 1) * kTrsmChunk > 0 ? b - (q + 1) * kTrsmChunk : 0) : q * kTrsmChunk;
+        const int k_hi = UPPER ? b - q * kTrsmChunk : (b < (q + 1) * kTrsmChunk ? b : (q + 1) * kTrsmChunk);
+        const int kc = k_hi - k_lo;
+        __syncthreads();
+        for (int e = threadIdx.x; e < b * kc; e += kThreads) {
+            const int kk = e / b, i = e - kk * b;
+            const double* v = at(T, ldt, i, k_lo + kk);
+            tk[kk][2 * i] = v[0];
+            tk[kk][2 * i + 1] = v[1];
         }
-    } else {
-        for (int k = b - 1; k >= 0; --k) {
-            const int tk = k >> 6, src = k & 63;
+        __syncthreads();
+        if (!active) continue;
+        for (int s = 0; s < kc; ++s) {
+            const int k = UPPER ? k_hi - 1 - s : k_lo + s;
+            const int kk = k - k_lo;
+            const int tk_ = k >> 6, src = k & 63;
             double ar = xr[0], ai = xi[0];
 #pragma unroll
             for (int t = 1; t < R2; ++t)
-                if (tk == t) {
+                if (tk_ == t) {
                     ar = xr[t];
                     ai = xi[t];
                 }
-            double vr, vi;
-            cmul(ar, ai, rec[2 * k], rec[2 * k + 1], vr, vi);
+            double vr = ar, vi = ai;
+            if (UPPER) cmul(ar, ai, rec[2 * k], rec[2 * k + 1], vr, vi);
             vr = lane_bcast(vr, src);
             vi = lane_bcast(vi, src);
-            if (lane == src) {
+            if (UPPER && lane == src) {
 #pragma unroll
                 for (int t = 0; t < R2; ++t)
-                    if (tk == t) {
+                    if (tk_ == t) {
                         xr[t] = vr;
                         xi[t] = vi;
                     }
@@ -574,16 +605,16 @@ __global__ __launch_bounds__(256) void trsm_wave_kernel(const double* T, int64_t
 #pragma unroll
             for (int t = 0; t < R2; ++t) {
                 const int i = lane + 64 * t;
-                if (i < k) {
-                    const double* u = at(T, ldt, i, k);
+                if (UPPER ? i < k : (i > k && i < b)) {
                     double tr, ti;
-                    cmul(u[0], u[1], vr, vi, tr, ti);
+                    cmul(tk[kk][2 * i], tk[kk][2 * i + 1], vr, vi, tr, ti);
                     xr[t] = xr[t] - tr;
                     xi[t] = xi[t] - ti;
                 }
             }
         }
     }
+    if (!active) return;
 #pragma unroll
     for (int t = 0; t < R2; ++t) {
         const int i = lane + 64 * t;
@@ -656,11 +687,12 @@ hipError_t launch_laswp(double* X, int64_t ld, int64_t c0, int64_t c1, int64_t r
 template <bool UPPER>
 void launch_trsm_wave(int r2, dim3 grid, hipStream_t st, const double* T, int64_t ldt, int b, double* B, int64_t ldb,
                       int64_t ncols) {
+    const dim3 blk(64 * kTrsmWaves);
     switch (r2) {
-        case 1: hipLaunchKernelGGL((trsm_wave_kernel<1, UPPER>), grid, dim3(256), 0, st, T, ldt, b, B, ldb, ncols); break;
-        case 2: hipLaunchKernelGGL((trsm_wave_kernel<2, UPPER>), grid, dim3(256), 0, st, T, ldt, b, B, ldb, ncols); break;
-        case 3: hipLaunchKernelGGL((trsm_wave_kernel<3, UPPER>), grid, dim3(256), 0, st, T, ldt, b, B, ldb, ncols); break;
-        default: hipLaunchKernelGGL((trsm_wave_kernel<4, UPPER>), grid, dim3(256), 0, st, T, ldt, b, B, ldb, ncols); break;
+        case 1: hipLaunchKernelGGL((trsm_wave_kernel<1, UPPER>), grid, blk, 0, st, T, ldt, b, B, ldb, ncols); break;
+        case 2: hipLaunchKernelGGL((trsm_wave_kernel<2, UPPER>), grid, blk, 0, st, T, ldt, b, B, ldb, ncols); break;
+        case 3: hipLaunchKernelGGL((trsm_wave_kernel<3, UPPER>), grid, blk, 0, st, T, ldt, b, B, ldb, ncols); break;
+        default: hipLaunchKernelGGL((trsm_wave_kernel<4, UPPER>), grid, blk, 0, st, T, ldt, b, B, ldb, ncols); break;
     }
 }
 
@@ -668,7 +700,7 @@ hipError_t launch_trsm(bool upper, const double* T, int64_t ldt, int b, double* 
                        hipStream_t st) {
     if (ncols <= 0 || b <= 0) return hipSuccess;
     if (b <= kMaxWaveTrsm) {
-        const dim3 grid(static_cast<unsigned>((ncols + 3) / 4));
+        const dim3 grid(static_cast<unsigned>((ncols + kTrsmWaves - 1) / kTrsmWaves));
         const int r2 = (b + 63) / 64;
         if (upper)
             launch_trsm_wave<true>(r2, grid, st, T, ldt, b, B, ldb, ncols);
@@ -736,38 +768,68 @@ int oz_zgetrf(oz_handle_t h, int64_t n, double* A, int64_t lda, int32_t* ipiv, i
     if (n == 0) return OZ_OK;
     if (!A || !ipiv) return OZ_ERR_ARG;
     if (n > INT32_MAX) return OZ_ERR_UNSUPPORTED;
-    if (nb == 0) nb = 64;
+    if (nb == 0) nb = kDefaultPanel;
     int st = oz_handle_use_device(h);
     if (st) return st;
     hipStream_t s = oz_handle_stream(h);
+    // Look-ahead: panel k + 1 is factored on a second stream while the handle's
+    // stream runs the rest of panel k's trailing product.  The trailing product
+    // is issued as two products split by columns (first the next panel's
+    // columns, then the rest); an entry of an emulated product depends only on
+    // its row of op(A) and its column of op(B), so the split changes no result.
+    hipStream_t s2 = nullptr;
+    hipEvent_t ev_start = nullptr, ev_panel = nullptr, ev_next = nullptr;
     int32_t* dinfo = nullptr;
-    if (hipMalloc(&dinfo, sizeof(int32_t)) != hipSuccess) return OZ_ERR_HIP;
     int rc = OZ_OK;
-    if (hipMemsetAsync(dinfo, 0, sizeof(int32_t), s) != hipSuccess) rc = OZ_ERR_HIP;
+    if (hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ev_start, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ev_panel, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ev_next, hipEventDisableTiming) != hipSuccess ||
+        hipMalloc(&dinfo, sizeof(int32_t)) != hipSuccess)
+        rc = OZ_ERR_HIP;
+    if (rc == OZ_OK && (hipMemsetAsync(dinfo, 0, sizeof(int32_t), s) != hipSuccess ||
+                        hipEventRecord(ev_start, s) != hipSuccess || hipStreamWaitEvent(s2, ev_start, 0) != hipSuccess))
+        rc = OZ_ERR_HIP;
     const double minus_one[2] = {-1.0, 0.0}, one[2] = {1.0, 0.0};
     for (int64_t j0 = 0; rc == OZ_OK && j0 < n; j0 += nb) {
         const int b = static_cast<int>(n - j0 < nb ? n - j0 : nb);
-        if (launch_panel(A, lda, n, j0, b, ipiv, dinfo, s) != hipSuccess ||
+        if (launch_panel(A, lda, n, j0, b, ipiv, dinfo, s2) != hipSuccess || hipEventRecord(ev_panel, s2) != hipSuccess ||
+            hipStreamWaitEvent(s, ev_panel, 0) != hipSuccess ||
             launch_laswp(A, lda, 0, j0, j0, j0 + b, ipiv, s) != hipSuccess) {
             rc = OZ_ERR_HIP;
             break;
         }
         const int64_t rest = n - j0 - b;
         if (rest <= 0) break;
+        const double* L21 = A + 2 * ((j0 + b) + j0 * lda);
         double* A12 = A + 2 * (j0 + (j0 + b) * lda);
+        double* A22 = A + 2 * ((j0 + b) + (j0 + b) * lda);
         if (launch_laswp(A, lda, j0 + b, n, j0, j0 + b, ipiv, s) != hipSuccess ||
             launch_trsm(false, A + 2 * (j0 + j0 * lda), lda, b, A12, lda, rest, s) != hipSuccess) {
             rc = OZ_ERR_HIP;
             break;
         }
-        rc = oz_zgemm(h, 'N', 'N', rest, rest, b, minus_one, A + 2 * ((j0 + b) + j0 * lda), lda, A12, lda, one,
-                      A + 2 * ((j0 + b) + (j0 + b) * lda), lda, prec, nullptr);
+        const int64_t next = rest < nb ? rest : nb;
+        rc = oz_zgemm(h, 'N', 'N', rest, next, b, minus_one, L21, lda, A12, lda, one, A22, lda, prec, nullptr);
+        if (rc) break;
+        if (hipEventRecord(ev_next, s) != hipSuccess || hipStreamWaitEvent(s2, ev_next, 0) != hipSuccess) {
+            rc = OZ_ERR_HIP;
+            break;
+        }
+        if (rest > next)
+            rc = oz_zgemm(h, 'N', 'N', rest, rest - next, b, minus_one, L21, lda, A12 + 2 * next * lda, lda, one,
+                          A22 + 2 * next * lda, lda, prec, nullptr);
     }
     if (rc == OZ_OK && (hipMemcpyAsync(info, dinfo, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
                         hipStreamSynchronize(s) != hipSuccess))
         rc = OZ_ERR_HIP;
+    if (s2 && hipStreamSynchronize(s2) != hipSuccess) rc = OZ_ERR_HIP;
     if (hipStreamSynchronize(s) != hipSuccess) rc = OZ_ERR_HIP;
-    if (hipFree(dinfo) != hipSuccess) rc = OZ_ERR_HIP;
+    if (dinfo && hipFree(dinfo) != hipSuccess) rc = OZ_ERR_HIP;
+    if (ev_start) (void)hipEventDestroy(ev_start);
+    if (ev_panel) (void)hipEventDestroy(ev_panel);
+    if (ev_next) (void)hipEventDestroy(ev_next);
+    if (s2) (void)hipStreamDestroy(s2);
     return rc;
 }
 
@@ -782,7 +844,7 @@ int oz_zgetri(oz_handle_t h, int64_t n, const double* LU, int64_t lda, const int
     if (n == 0) return OZ_OK;
     if (!LU || !ipiv || !X || X == LU) return OZ_ERR_ARG;
     if (n > INT32_MAX) return OZ_ERR_UNSUPPORTED;
-    if (nb == 0) nb = 64;
+    if (nb == 0) nb = kDefaultSolveBlock;
     int st = oz_handle_use_device(h);
     if (st) return st;
     hipStream_t s = oz_handle_stream(h);

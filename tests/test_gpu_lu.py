@@ -50,7 +50,7 @@ def gpu_getri(oz, handle, dLU, lda, ipiv, n, nb, s, pad=5):
 
 
 CASES = [(1, 16, 7), (5, 2, 7), (37, 16, 3), (64, 64, 7), (100, 32, 7), (130, 32, 5), (130, 64, 14),
-         (200, 48, 9), (257, 64, 7), (300, 0, 7)]
+         (200, 48, 9), (257, 64, 7), (300, 0, 7), (600, 0, 6), (520, 256, 7), (700, 200, 4)]
 
 
 @pytest.mark.parametrize("n,nb,s", CASES)
@@ -58,14 +58,14 @@ def test_getrf_getri_bit_exact(oz, handle, n, nb, s):
     rng = np.random.default_rng(1000 + 7 * n + s)
     A = cmat(rng, n)
     dA, lda, ipiv, info = gpu_getrf(oz, handle, A, nb, s)
-    LU_ref, piv_ref, info_ref = lu.getrf(A, nb or 64, s)
+    LU_ref, piv_ref, info_ref = lu.getrf(A, nb or 128, s)
     print("n=%d nb=%d s=%d" % (n, nb, s), flush=True)
     assert info == info_ref == 0
     assert np.array_equal(ipiv.cpu().numpy(), piv_ref)
     LU = from_dev(dA, n, n, lda)
     assert np.array_equal(LU, LU_ref)
     X = gpu_getri(oz, handle, dA, lda, ipiv, n, nb, s)
-    X_ref = lu.getri(LU_ref, piv_ref, nb or 64, s)
+    X_ref = lu.getri(LU_ref, piv_ref, nb or 256, s)
     assert np.array_equal(X, X_ref)
 
 
