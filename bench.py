@@ -486,7 +486,8 @@ def bench_inv(args):
     native FP64 inverse (torch.linalg.inv, same GPU).  Per s: the inverse's
     largest entry error relative to the largest entry of the native inverse,
     its residual max |A X - I|, and the effective rate on LAPACK's operation
-    count of getrf + getri (8 n^3 real flops for complex)."""
+    count of getrf + getri (8 n^3 real flops for complex).  Then the same with
+    every product tolerance-driven (each picks its own s) at --inv-tols."""
     import torch
 
     import paper_2503_22875_amd as oz
@@ -527,6 +528,23 @@ def bench_inv(args):
                "err_vs_native": float("%.3e" % err), "resid": float("%.3e" % resid)}
         print(json.dumps(row), flush=True)
         rows.append(row)
+    for tol in [float(v) for v in args.inv_tols.split(",") if v]:
+        p = oz.prec(0, tol=tol)
+
+        def run_tol():
+            dA.copy_(dA0)
+            oz.oz_zgetrf(h, n, dA, n, ipiv, nb, p)
+            oz.oz_zgetri(h, n, dA, n, ipiv, dX, n, nbi, p)
+
+        run_tol()
+        X = torch.view_as_complex(dX.view(n, n, 2)).T
+        err = float((X - Xr).abs().max() / Xr.abs().max())
+        resid = float((Ad @ X - eye).abs().max())
+        ms = _time_ms(run_tol, stream, steps, 1)
+        row = {"tol": tol, "ms": round(ms, 3), "tflops_eff": round(flops / (ms * 1e-3) / 1e12, 2),
+               "err_vs_native": float("%.3e" % err), "resid": float("%.3e" % resid)}
+        print(json.dumps(row), flush=True)
+        rows.append(row)
     oz.oz_destroy(h)
     print(json.dumps({"workload": "complex LU inversion n=%d nb=%d/%d (N(0,1)+iN(0,1))" % (n, nb, nbi),
                       "native": {"ms": round(ms_nat, 3), "tflops_eff": round(flops / (ms_nat * 1e-3) / 1e12, 2),
@@ -540,6 +558,8 @@ def main():
     ap.add_argument("--nb", type=int, default=128, help="panel width of the inversion workload (getrf)")
     ap.add_argument("--nb-inv", type=int, default=256, help="block rows of the inversion workload's solves (getri)")
     ap.add_argument("--inv-slices", default="3,4,5,6,7,8,14")
+    ap.add_argument("--inv-tols", default="1e-8,1e-10,1e-12",
+                    help="tolerance-driven rows of the inversion workload (each product picks its own s)")
     ap.add_argument("--select-data", default="normal,spread")
     ap.add_argument("--select-tols", default="1e-10,1e-12,1e-14")
     ap.add_argument("--sweep-n", default="2048,4096")

@@ -211,3 +211,31 @@ def test_full_size_properties(oz, handle, s, bound_lu, bound_inv):
         assert resid < 10 * resid_native
     else:
         assert err_inv < bound_inv
+
+
+def test_tolerance_driven_products(oz, handle):
+    # every emulated product of the factorisation and the solves picks its own
+    # slice count for the tolerance (the starting rule, then growth until the
+    # a-posteriori estimate passes): a tighter tolerance gives a smaller
+    # residual, and at 1e-13 the inverse is as good as at fixed s = 14 to
+    # within the condition number's amplification of 1e-13
+    n = 1024
+    rng = np.random.default_rng(1024)
+    A = cmat(rng, n)
+    Ad = torch.from_numpy(A).cuda()
+    eye = torch.eye(n, dtype=torch.complex128, device="cuda")
+    out = {}
+    for tol in (1e-8, 1e-13):
+        p = oz.prec(0, tol=tol)
+        dA, lda = to_dev(A, n)
+        ipiv = torch.empty(n, dtype=torch.int32, device="cuda")
+        assert oz.oz_zgetrf(handle, n, dA, lda, ipiv, 0, p) == 0
+        dX, ldx = to_dev(np.zeros((n, n), complex, order="F"), n)
+        oz.oz_zgetri(handle, n, dA, lda, ipiv, dX, ldx, 0, p)
+        X = torch.from_numpy(from_dev(dX, n, n, ldx)).cuda()
+        out[tol] = float((Ad @ X - eye).abs().max())
+    print("resid by tol", out, flush=True)
+    assert out[1e-13] < out[1e-8] / 100
+    assert out[1e-8] < 1e-8 * n * 10
+    assert out[1e-13] < 1e-13 * n * 10
+
