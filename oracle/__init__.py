@@ -19,6 +19,8 @@ float64 or complex128; ``trans`` is 'N', 'T' or 'C'):
                   p + q <= s + 1, FP64 accumulation, alpha/beta.
 * ``emu_zgemm3``  the complex product as three real emulated products (3M).
 * ``emu_gemm_x2`` the emulated product with a double-double result.
+* ``split(..., balanced=True)`` / ``emu_gemm(..., balanced=True)``: the
+                  round-to-nearest (balanced) digits and their product.
 * ``kchunk``      the INT32 chunk length (products per chunk).
 
 Submodules ``select`` (features, error table and labels of the learned
@@ -56,6 +58,11 @@ def _load():
     lib.oro_dgemm_dd.argtypes = [C, C, I64, I64, I64, D, P, I64, P, I64, D, P, I64, P, I64, P, I64, P, I64]
     lib.oro_zgemm_dd.argtypes = [C, C, I64, I64, I64, P, P, I64, P, I64, P, P, I64, P, I64, P, I64, P, I64]
     lib.oro_split.argtypes = [C, C, I32, I64, I64, P, I64, I32, P, P]
+    lib.oro_split_bal.argtypes = [C, C, I32, I64, I64, P, I64, I32, P, P]
+    lib.oro_emu_dgemm_bal.argtypes = [C, C, I64, I64, I64, D, P, I64, P, I64, D, P, I64, I32, I64,
+                                      P, I64, P, I64, P, I64]
+    lib.oro_emu_zgemm_bal.argtypes = [C, C, I64, I64, I64, P, P, I64, P, I64, P, P, I64, I32, I64,
+                                      P, I64, P, I64, P, I64]
     lib.oro_diag_sums.argtypes = [I32, I32, I64, I64, P, I64, P, I64, P, I64, P, I64, P]
     lib.oro_emu_dgemm.argtypes = [C, C, I64, I64, I64, D, P, I64, P, I64, D, P, I64, I32, I32, I64,
                                   P, I64, P, I64, P, I64]
@@ -100,16 +107,18 @@ def _ld(X):
     return max(1, X.shape[0])
 
 
-def kchunk(s, cplx=False):
+def kchunk(s, cplx=False, balanced=False):
     """INT32 chunk length in products per output entry.
 
     An anti-diagonal sum of one chunk holds at most s pair products per term
     (diagonal d = s + 1 has s pairs) and every pair product is at most 127^2 in
-    magnitude, so kc terms are safe while s * kc * 127^2 <= 2^31 - 1.  kc is
-    rounded down to a multiple of 64; a complex entry consumes two products per
-    value of l, so complex chunks cover kc / 2 values of l.
+    magnitude (128^2 with balanced digits), so kc terms are safe while
+    s * kc * 127^2 <= 2^31 - 1.  kc is rounded down to a multiple of 64; a
+    complex entry consumes two products per value of l, so complex chunks cover
+    kc / 2 values of l.
     """
-    kc = INT32_MAX // (s * DIGIT_MAX * DIGIT_MAX)
+    dmax = 128 if balanced else DIGIT_MAX
+    kc = INT32_MAX // (s * dmax * dmax)
     kc -= kc % 64
     return int(kc)
 
@@ -161,13 +170,16 @@ def gemm_dd(transa, transb, A, B, alpha=1.0, beta=0.0, C=None, rows=None, cols=N
     return out
 
 
-def split(side, trans, X, s):
+def split(side, trans, X, s, balanced=False):
     """Scale exponents and digits of the vectors of one operand.
 
     side 'A': the vectors are the rows of op(X); side 'B': the columns of op(X).
     Returns (E, dig): E int32 [nv]; dig int8 [s, nv, k] for real data or
-    [s, nv, k, 2] (real part, imaginary part) for complex data.
+    [s, nv, k, 2] (real part, imaginary part) for complex data.  balanced:
+    round-to-nearest digits (s <= 8), x = 2^(E+2) sum_p d_p 2^(-8p) to half a
+    unit of the last digit; otherwise truncated base-128 digits.
     """
+    assert not balanced or 1 <= s <= 8
     cplx = np.iscomplexobj(X)
     X = _f(X, np.complex128 if cplx else np.float64)
     if side == "A":
@@ -177,8 +189,8 @@ def split(side, trans, X, s):
     E = np.zeros(nv, dtype=np.int32)
     shape = (s, nv, k, 2) if cplx else (s, nv, k)
     dig = np.zeros(shape, dtype=np.int8)
-    _load().oro_split(side.encode(), trans.encode(), int(cplx), nv, k, _ptr(X), _ld(X), s, _ptr(E),
-                      _ptr(dig))
+    fn = _load().oro_split_bal if balanced else _load().oro_split
+    fn(side.encode(), trans.encode(), int(cplx), nv, k, _ptr(X), _ld(X), s, _ptr(E), _ptr(dig))
     return E, dig
 
 
@@ -249,29 +261,42 @@ def emu_zgemm3(transa, transb, A, B, s, alpha=1.0, beta=0.0, C=None, kc=None, ro
     return np.asfortranarray(outr + 1j * outi)
 
 
-def emu_gemm(transa, transb, A, B, s, alpha=1.0, beta=0.0, C=None, kc=None, rows=None, cols=None, s_to=None):
+def emu_gemm(transa, transb, A, B, s, alpha=1.0, beta=0.0, C=None, kc=None, rows=None, cols=None, s_to=None,
+             balanced=False):
     """O4: the emulated GEMM on the selected rows x cols (all by default).
 
     s_to > s: start at s slices and grow one slice at a time to s_to, adding
     each new anti-diagonal last (the order of the incremental fallback); kc is
     then the chunk length of the s_to plan (``kchunk(s_to)`` by default).
+    balanced: round-to-nearest digits and fold weights 2^(4-8d) (fixed s <= 8).
     """
     s1 = s if s_to is None else s_to
     assert s1 >= s
+    assert not balanced or (s_to is None and 1 <= s <= 8)
     cplx = np.iscomplexobj(A) or np.iscomplexobj(B) or np.iscomplexobj(alpha) or np.iscomplexobj(beta)
     dt = np.complex128 if cplx else np.float64
     A, B = _f(A, dt), _f(B, dt)
     m, k = _dims(transa, A, "A")
     k2, n = _dims(transb, B, "B")
     assert k == k2
-    kc = kchunk(s1, cplx) if kc is None else kc
+    kc = kchunk(s1, cplx, balanced) if kc is None else kc
     assert kc > 0 and (not cplx or kc % 2 == 0)
     Cin = np.zeros((max(m, 1), max(n, 1)), dtype=dt, order="F") if C is None else _f(C, dt)
     rs, nr = _sel(rows, m)
     cs, nc = _sel(cols, n)
     out = np.zeros((nr, nc), dtype=dt, order="F")
     lib = _load()
-    if cplx:
+    if balanced and cplx:
+        al = np.array([complex(alpha).real, complex(alpha).imag])
+        be = np.array([complex(beta).real, complex(beta).imag])
+        lib.oro_emu_zgemm_bal(transa.encode(), transb.encode(), m, n, k, _ptr(al), _ptr(A), _ld(A), _ptr(B),
+                              _ld(B), _ptr(be), _ptr(Cin), _ld(Cin), s, kc, _ptr(rs), nr, _ptr(cs), nc,
+                              _ptr(out), max(1, nr))
+    elif balanced:
+        lib.oro_emu_dgemm_bal(transa.encode(), transb.encode(), m, n, k, float(alpha), _ptr(A), _ld(A),
+                              _ptr(B), _ld(B), float(beta), _ptr(Cin), _ld(Cin), s, kc, _ptr(rs), nr,
+                              _ptr(cs), nc, _ptr(out), max(1, nr))
+    elif cplx:
         al = np.array([complex(alpha).real, complex(alpha).imag])
         be = np.array([complex(beta).real, complex(beta).imag])
         lib.oro_emu_zgemm(transa.encode(), transb.encode(), m, n, k, _ptr(al), _ptr(A), _ld(A), _ptr(B),

@@ -53,6 +53,20 @@
  *     (yr, yi) = beta, every product and sum rounded, evaluated as
  *     bracketed; with beta == 0 only the alpha part is formed.
  *
+ *
+ * Balanced digits (round to nearest; the round-to-nearest splitting the paper
+ * points to as worth about one bit per slice, Sec. 4), fixed s <= 8 only:
+ *   - N = |x| * 2^(6 - E + 8(s-1)) rounded to the nearest integer (ties away
+ *     from zero), with the sign of x; |x| < 2^E keeps |N| <= 2^(6+8(s-1));
+ *   - the digits are the unique d_1..d_s with N = sum_p d_p 256^(s-p) and
+ *     d_2..d_s in [-128, 127] (d_p = N mod 256 taken in that range, then
+ *     N = (N - d_p) / 256); d_1 is what remains, |d_1| <= 65;
+ *   - so x = 2^(E+2) sum_p d_p 2^(-8p) up to half a unit of the last digit,
+ *     and the fold weight of anti-diagonal d is 2^(4 - 8d):
+ *       acc = sum over chunks, then d = s+1 down to 2, of S_{d,c} * 2^(4-8d);
+ *   - every digit product is at most 128^2 in magnitude, so the INT32 chunk
+ *     bound is s * kc * 128^2 <= 2^31 - 1.
+ *
  * Build: gcc -O2 -fopenmp -ffp-contract=off -shared -fPIC (see build.py).
  * -ffp-contract=off keeps every multiply and add separately rounded; the only
  * fused multiply-add is the explicit fma() inside TwoProduct.
@@ -263,14 +277,38 @@ static void digits_of(double a, int E, int s, int8_t* out, int64_t stride) {
     }
 }
 
+/* Balanced digits of x under scale exponent E and slice count s (s <= 8).
+   ldexp is exact here: the result is below 2^62, and where it would be
+   subnormal it is below 1/2, which rounds to 0 whatever ldexp returns. */
+static void digits_bal_of(double a, int E, int s, int8_t* out, int64_t stride) {
+    int64_t N = 0;
+    if (isfinite(a)) {
+        double y = ldexp(fabs(a), 6 - E + 8 * (s - 1));
+        double ip = floor(y);
+        N = (int64_t)ip + ((y - ip) >= 0.5 ? 1 : 0);
+        if (a < 0) N = -N;
+    }
+    for (int p = s - 1; p >= 1; --p) {
+        int64_t r = ((N % 256) + 256) % 256;
+        if (r >= 128) r -= 256;
+        out[p * stride] = (int8_t)r;
+        N = (N - r) / 256;
+    }
+    out[0] = (int8_t)N;
+}
+
+/* Fold weight of anti-diagonal d: 2^(-7d) (truncated digits) or 2^(4-8d)
+   (balanced digits). */
+static double diag_weight(int d, int bal) { return ldexp(1.0, bal ? 4 - 8 * d : -7 * d); }
+
 /* Split the vectors of an operand.  side 'A': vector v is row v of op(A)
    (nv = m); side 'B': vector v is column v of op(B) (nv = n); length k.
    Real:    dig[(p*nv + v)*k + l]            = digit p+1 of element (v, l)
    Complex: dig[((p*nv + v)*k + l)*2 + part] = digit p+1 of the real (part 0)
             or imaginary (part 1) part, after conjugation by 'C'.
    E[v] receives the scale exponent. */
-void oro_split(char side, char trans, int cplx, int64_t nv, int64_t k, const double* X,
-               int64_t ldx, int s, int32_t* E, int8_t* dig) {
+static void split_impl(char side, char trans, int cplx, int64_t nv, int64_t k, const double* X,
+                       int64_t ldx, int s, int32_t* E, int8_t* dig, int bal) {
     int w = cplx ? 2 : 1;
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t v = 0; v < nv; ++v) {
@@ -287,9 +325,24 @@ void oro_split(char side, char trans, int cplx, int64_t nv, int64_t k, const dou
         int e = vec_exponent(vals, k * w);
         E[v] = e;
         int64_t stride = nv * k * w; /* distance between digit planes */
-        for (int64_t t = 0; t < k * w; ++t) digits_of(vals[t], e, s, dig + v * k * w + t, stride);
+        for (int64_t t = 0; t < k * w; ++t) {
+            if (bal)
+                digits_bal_of(vals[t], e, s, dig + v * k * w + t, stride);
+            else
+                digits_of(vals[t], e, s, dig + v * k * w + t, stride);
+        }
         free(vals);
     }
+}
+
+void oro_split(char side, char trans, int cplx, int64_t nv, int64_t k, const double* X,
+               int64_t ldx, int s, int32_t* E, int8_t* dig) {
+    split_impl(side, trans, cplx, nv, k, X, ldx, s, E, dig, 0);
+}
+
+void oro_split_bal(char side, char trans, int cplx, int64_t nv, int64_t k, const double* X,
+                   int64_t ldx, int s, int32_t* E, int8_t* dig) {
+    split_impl(side, trans, cplx, nv, k, X, ldx, s, E, dig, 1);
 }
 
 /* Anti-diagonal sums for one output entry and one chunk [l0, l1) of l:
@@ -396,18 +449,18 @@ void oro_diag_sums(int cplx, int s, int64_t k, int64_t kc, const int8_t* digA, i
 
 /* Emulated DGEMM on the selected block.  C (full, ldc) provides beta*C for the
    selected entries; out (nr x nc, ldo) receives the result. */
-void oro_emu_dgemm(char ta, char tb, int64_t m, int64_t n, int64_t k, double alpha,
-                   const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
-                   const double* C, int64_t ldc, int s, int s1, int64_t kc, const int64_t* rows, int64_t nr,
-                   const int64_t* cols, int64_t nc, double* out, int64_t ldo) {
+static void emu_dgemm_impl(char ta, char tb, int64_t m, int64_t n, int64_t k, double alpha,
+                           const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                           const double* C, int64_t ldc, int s, int s1, int64_t kc, const int64_t* rows,
+                           int64_t nr, const int64_t* cols, int64_t nc, double* out, int64_t ldo, int bal) {
     /* s1 >= s: grow incrementally from s to s1 (s1 == s: plain emulation) */
     int sd = s1 > s ? s1 : s; /* digits needed */
     int32_t* EA = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m + 1));
     int32_t* FB = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
     int8_t* dA = (int8_t*)malloc((size_t)(sd * m * k + 1));
     int8_t* dB = (int8_t*)malloc((size_t)(sd * n * k + 1));
-    oro_split('A', ta, 0, m, k, A, lda, sd, EA, dA);
-    oro_split('B', tb, 0, n, k, B, ldb, sd, FB, dB);
+    split_impl('A', ta, 0, m, k, A, lda, sd, EA, dA, bal);
+    split_impl('B', tb, 0, n, k, B, ldb, sd, FB, dB, bal);
     int64_t nch = k > 0 ? (k + kc - 1) / kc : 0;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t jj = 0; jj < nc; ++jj) {
@@ -418,14 +471,14 @@ void oro_emu_dgemm(char ta, char tb, int64_t m, int64_t n, int64_t k, double alp
             for (int64_t c = 0; c < nch; ++c) {
                 int64_t l0 = c * kc, l1 = l0 + kc < k ? l0 + kc : k;
                 diag_sums_real(dA + i * k, dB + j * k, m * k, n * k, s, l0, l1, S);
-                for (int d = s + 1; d >= 2; --d) acc = acc + (double)S[d] * pow2i(-7 * d);
+                for (int d = s + 1; d >= 2; --d) acc = acc + (double)S[d] * diag_weight(d, bal);
             }
             for (int st = s; st < sd; ++st) {
                 int d = st + 2;
                 for (int64_t c = 0; c < nch; ++c) {
                     int64_t l0 = c * kc, l1 = l0 + kc < k ? l0 + kc : k, Sd;
                     one_diag_real(dA + i * k, dB + j * k, m * k, n * k, st + 1, d, l0, l1, &Sd);
-                    acc = acc + (double)Sd * pow2i(-7 * d);
+                    acc = acc + (double)Sd * diag_weight(d, bal);
                 }
             }
             double v = ldexp(acc, EA[i] + FB[j]);
@@ -437,17 +490,33 @@ void oro_emu_dgemm(char ta, char tb, int64_t m, int64_t n, int64_t k, double alp
     free(EA); free(FB); free(dA); free(dB);
 }
 
-void oro_emu_zgemm(char ta, char tb, int64_t m, int64_t n, int64_t k, const double* alpha,
-                   const double* A, int64_t lda, const double* B, int64_t ldb, const double* beta,
+void oro_emu_dgemm(char ta, char tb, int64_t m, int64_t n, int64_t k, double alpha,
+                   const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
                    const double* C, int64_t ldc, int s, int s1, int64_t kc, const int64_t* rows, int64_t nr,
                    const int64_t* cols, int64_t nc, double* out, int64_t ldo) {
+    emu_dgemm_impl(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, s, s1, kc, rows, nr, cols, nc, out, ldo,
+                   0);
+}
+
+/* Balanced digits (fixed s: s1 is ignored) */
+void oro_emu_dgemm_bal(char ta, char tb, int64_t m, int64_t n, int64_t k, double alpha,
+                       const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                       const double* C, int64_t ldc, int s, int64_t kc, const int64_t* rows, int64_t nr,
+                       const int64_t* cols, int64_t nc, double* out, int64_t ldo) {
+    emu_dgemm_impl(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, s, s, kc, rows, nr, cols, nc, out, ldo, 1);
+}
+
+static void emu_zgemm_impl(char ta, char tb, int64_t m, int64_t n, int64_t k, const double* alpha,
+                           const double* A, int64_t lda, const double* B, int64_t ldb, const double* beta,
+                           const double* C, int64_t ldc, int s, int s1, int64_t kc, const int64_t* rows,
+                           int64_t nr, const int64_t* cols, int64_t nc, double* out, int64_t ldo, int bal) {
     int sd = s1 > s ? s1 : s;
     int32_t* EA = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m + 1));
     int32_t* FB = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
     int8_t* dA = (int8_t*)malloc((size_t)(2 * sd * m * k + 1));
     int8_t* dB = (int8_t*)malloc((size_t)(2 * sd * n * k + 1));
-    oro_split('A', ta, 1, m, k, A, lda, sd, EA, dA);
-    oro_split('B', tb, 1, n, k, B, ldb, sd, FB, dB);
+    split_impl('A', ta, 1, m, k, A, lda, sd, EA, dA, bal);
+    split_impl('B', tb, 1, n, k, B, ldb, sd, FB, dB, bal);
     int64_t lchunk = kc / 2;
     int64_t nch = k > 0 ? (k + lchunk - 1) / lchunk : 0;
     int bnz = beta[0] != 0.0 || beta[1] != 0.0;
@@ -461,8 +530,8 @@ void oro_emu_zgemm(char ta, char tb, int64_t m, int64_t n, int64_t k, const doub
                 int64_t l0 = c * lchunk, l1 = l0 + lchunk < k ? l0 + lchunk : k;
                 diag_sums_cplx(dA + i * k * 2, dB + j * k * 2, m * k * 2, n * k * 2, s, l0, l1, Sr, Si);
                 for (int d = s + 1; d >= 2; --d) {
-                    accr = accr + (double)Sr[d] * pow2i(-7 * d);
-                    acci = acci + (double)Si[d] * pow2i(-7 * d);
+                    accr = accr + (double)Sr[d] * diag_weight(d, bal);
+                    acci = acci + (double)Si[d] * diag_weight(d, bal);
                 }
             }
             for (int st = s; st < sd; ++st) {
@@ -470,8 +539,8 @@ void oro_emu_zgemm(char ta, char tb, int64_t m, int64_t n, int64_t k, const doub
                 for (int64_t c = 0; c < nch; ++c) {
                     int64_t l0 = c * lchunk, l1 = l0 + lchunk < k ? l0 + lchunk : k, Sdr, Sdi;
                     one_diag_cplx(dA + i * k * 2, dB + j * k * 2, m * k * 2, n * k * 2, st + 1, d, l0, l1, &Sdr, &Sdi);
-                    accr = accr + (double)Sdr * pow2i(-7 * d);
-                    acci = acci + (double)Sdi * pow2i(-7 * d);
+                    accr = accr + (double)Sdr * diag_weight(d, bal);
+                    acci = acci + (double)Sdi * diag_weight(d, bal);
                 }
             }
             double vr = ldexp(accr, EA[i] + FB[j]);
@@ -488,6 +557,21 @@ void oro_emu_zgemm(char ta, char tb, int64_t m, int64_t n, int64_t k, const doub
         }
     }
     free(EA); free(FB); free(dA); free(dB);
+}
+
+void oro_emu_zgemm(char ta, char tb, int64_t m, int64_t n, int64_t k, const double* alpha,
+                   const double* A, int64_t lda, const double* B, int64_t ldb, const double* beta,
+                   const double* C, int64_t ldc, int s, int s1, int64_t kc, const int64_t* rows, int64_t nr,
+                   const int64_t* cols, int64_t nc, double* out, int64_t ldo) {
+    emu_zgemm_impl(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, s, s1, kc, rows, nr, cols, nc, out, ldo,
+                   0);
+}
+
+void oro_emu_zgemm_bal(char ta, char tb, int64_t m, int64_t n, int64_t k, const double* alpha,
+                       const double* A, int64_t lda, const double* B, int64_t ldb, const double* beta,
+                       const double* C, int64_t ldc, int s, int64_t kc, const int64_t* rows, int64_t nr,
+                       const int64_t* cols, int64_t nc, double* out, int64_t ldo) {
+    emu_zgemm_impl(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, s, s, kc, rows, nr, cols, nc, out, ldo, 1);
 }
 
 /* ---- products beyond FP64: the same sums folded into a double-double ---- */
