@@ -65,7 +65,11 @@
  *     and the fold weight of anti-diagonal d is 2^(4 - 8d):
  *       acc = sum over chunks, then d = s+1 down to 2, of S_{d,c} * 2^(4-8d);
  *   - every digit product is at most 128^2 in magnitude, so the INT32 chunk
- *     bound is s * kc * 128^2 <= 2^31 - 1.
+ *     bound is s * kc * 128^2 <= 2^31 - 1;
+ *   - complex: Re C is the real emulated product of the rows (ar, -ai)
+ *     against (br, bi) over 2k terms, so it takes the digits of the value
+ *     -ai, which need not be the negated digits of ai; Im C pairs (ar, ai)
+ *     with (bi, br).
  *
  * Build: gcc -O2 -fopenmp -ffp-contract=off -shared -fPIC (see build.py).
  * -ffp-contract=off keeps every multiply and add separately rounded; the only
@@ -379,6 +383,29 @@ static void diag_sums_cplx(const int8_t* da, const int8_t* db, int64_t ps_a, int
         }
 }
 
+/* Balanced complex sums: the real part is the real emulated product of the
+   row (ar, -ai) against (br, bi), so it takes the digits of the value -ai
+   (dn, the split of A with negated imaginary parts), which with balanced
+   digits need not be the negated digits of ai. */
+static void diag_sums_cplx_bal(const int8_t* da, const int8_t* dn, const int8_t* db, int64_t ps_a, int64_t ps_b,
+                               int s, int64_t l0, int64_t l1, int64_t* Sr, int64_t* Si) {
+    for (int d = 0; d < s + 2; ++d) Sr[d] = Si[d] = 0;
+    for (int p = 1; p <= s; ++p)
+        for (int q = 1; p + q <= s + 1; ++q) {
+            const int8_t* a = da + (p - 1) * ps_a;
+            const int8_t* an = dn + (p - 1) * ps_a;
+            const int8_t* b = db + (q - 1) * ps_b;
+            int64_t accr = 0, acci = 0;
+            for (int64_t l = l0; l < l1; ++l) {
+                int64_t ar = a[2 * l], ai = a[2 * l + 1], nai = an[2 * l + 1], br = b[2 * l], bi = b[2 * l + 1];
+                accr += ar * br + nai * bi;
+                acci += ar * bi + ai * br;
+            }
+            Sr[p + q] += accr;
+            Si[p + q] += acci;
+        }
+}
+
 static double pow2i(int e) { return ldexp(1.0, e); }
 
 /* S_d of one diagonal d only, slices 1..s available (real / complex) */
@@ -517,6 +544,21 @@ static void emu_zgemm_impl(char ta, char tb, int64_t m, int64_t n, int64_t k, co
     int8_t* dB = (int8_t*)malloc((size_t)(2 * sd * n * k + 1));
     split_impl('A', ta, 1, m, k, A, lda, sd, EA, dA, bal);
     split_impl('B', tb, 1, n, k, B, ldb, sd, FB, dB, bal);
+    int8_t* dN = NULL; /* balanced: digits of A with negated imaginary parts */
+    if (bal) {
+        int64_t ra = (ta == 'N' || ta == 'n') ? m : k, ca = (ta == 'N' || ta == 'n') ? k : m;
+        double* An = (double*)malloc(sizeof(double) * (size_t)(2 * lda * (ca > 0 ? ca : 1) + 2));
+        for (int64_t c = 0; c < ca; ++c)
+            for (int64_t r = 0; r < ra; ++r) {
+                An[2 * (r + c * lda)] = A[2 * (r + c * lda)];
+                An[2 * (r + c * lda) + 1] = -A[2 * (r + c * lda) + 1];
+            }
+        int32_t* En = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m + 1));
+        dN = (int8_t*)malloc((size_t)(2 * sd * m * k + 1));
+        split_impl('A', ta, 1, m, k, An, lda, sd, En, dN, 1);
+        free(An);
+        free(En);
+    }
     int64_t lchunk = kc / 2;
     int64_t nch = k > 0 ? (k + lchunk - 1) / lchunk : 0;
     int bnz = beta[0] != 0.0 || beta[1] != 0.0;
@@ -528,7 +570,11 @@ static void emu_zgemm_impl(char ta, char tb, int64_t m, int64_t n, int64_t k, co
             double accr = 0.0, acci = 0.0;
             for (int64_t c = 0; c < nch; ++c) {
                 int64_t l0 = c * lchunk, l1 = l0 + lchunk < k ? l0 + lchunk : k;
-                diag_sums_cplx(dA + i * k * 2, dB + j * k * 2, m * k * 2, n * k * 2, s, l0, l1, Sr, Si);
+                if (bal)
+                    diag_sums_cplx_bal(dA + i * k * 2, dN + i * k * 2, dB + j * k * 2, m * k * 2, n * k * 2, s, l0,
+                                       l1, Sr, Si);
+                else
+                    diag_sums_cplx(dA + i * k * 2, dB + j * k * 2, m * k * 2, n * k * 2, s, l0, l1, Sr, Si);
                 for (int d = s + 1; d >= 2; --d) {
                     accr = accr + (double)Sr[d] * diag_weight(d, bal);
                     acci = acci + (double)Si[d] * diag_weight(d, bal);
@@ -556,7 +602,7 @@ static void emu_zgemm_impl(char ta, char tb, int64_t m, int64_t n, int64_t k, co
             out[2 * (ii + jj * ldo) + 1] = ri;
         }
     }
-    free(EA); free(FB); free(dA); free(dB);
+    free(EA); free(FB); free(dA); free(dB); free(dN);
 }
 
 void oro_emu_zgemm(char ta, char tb, int64_t m, int64_t n, int64_t k, const double* alpha,

@@ -141,3 +141,23 @@ def test_chunk_bound_with_extreme_digits(s):
     d = np.full((s, 1, kc), -128, dtype=np.int8)
     S = oracle.diag_sums(d, d, s, kc=kc)
     assert S[0, s - 1, 0, 0] == s * kc * 128 * 128
+
+
+@pytest.mark.parametrize("balanced", [False, True])
+@pytest.mark.parametrize("ta", ["N", "C"])
+def test_complex_is_the_real_product_over_two_k_terms(balanced, ta):
+    # Re C is the real emulated product of the rows (ar, -ai) against (br, bi),
+    # Im C that of (ar, ai) against (bi, br) (same shared scales; one INT32
+    # chunk, so term order does not matter): the complex sums are pinned to the
+    # real path, including the digits of the value -ai under balanced digits
+    rng = np.random.default_rng(21)
+    m, n, k = 24, 18, 40
+    A = rand_wide(rng, (m, k), 3, True)
+    B = rand_wide(rng, (k, n), 3, True)
+    As = np.asfortranarray(A.conj().T) if ta == "C" else A
+    for s in (2, 4, 7):
+        got = oracle.emu_gemm(ta, "N", As, B, s, balanced=balanced)
+        Ar, Ai, Br, Bi = A.real, A.imag, B.real, B.imag
+        re = oracle.emu_gemm("N", "N", np.hstack([Ar, -Ai]), np.vstack([Br, Bi]), s, balanced=balanced)
+        im = oracle.emu_gemm("N", "N", np.hstack([Ar, Ai]), np.vstack([Bi, Br]), s, balanced=balanced)
+        assert np.array_equal(got.real, re) and np.array_equal(got.imag, im), s
