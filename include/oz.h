@@ -101,7 +101,18 @@ typedef struct oz_handle_s* oz_handle_t;
  *  selector: tolerance-driven calls with sstart == 0: 0 = the rule of
  *           oz_select_slices, 1 = the learned selector attached to the handle
  *           (oz_set_selector; OZ_ERR_ARG without one), see oz_predict_slices.
- *  reserved: must be 0.
+ *  digits : 0 = truncated digits (the default, as described above).
+ *           1 = balanced, round-to-nearest digits (the rounding the paper
+ *           expects to be worth about one bit per slice, Sec. 4), fixed slice
+ *           counts 1..8, real products and the 4-product complex form (a
+ *           tolerance-driven, double-double, batched or zmode 3 call, or
+ *           s > 8, returns 14): N = |x| 2^(6-E+8(s-1)) rounded to the nearest
+ *           integer (ties away from zero) with the sign of x, digits d_1..d_s
+ *           with N = sum_p d_p 256^(s-p) and d_2..d_s in [-128, 127], so x is
+ *           2^(E+2) sum_p d_p 2^(-8p) to half a unit of the last digit; the
+ *           anti-diagonal weights are 2^(4-8d) and kchunk is bounded by
+ *           s*kchunk*128^2 <= 2^31-1.  Complex: the real-part row (ar, -ai)
+ *           takes the digits of the value -ai.
  */
 typedef struct {
     int32_t slices;
@@ -111,7 +122,7 @@ typedef struct {
     int32_t kernel;
     int32_t sstart;
     int32_t selector;
-    int32_t reserved;
+    int32_t digits;
     double tol;
 } oz_prec_t;
 

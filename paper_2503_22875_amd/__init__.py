@@ -53,7 +53,7 @@ class OzError(RuntimeError):
 class oz_prec_t(ctypes.Structure):
     _fields_ = [("slices", ctypes.c_int32), ("smax", ctypes.c_int32), ("kchunk", ctypes.c_int32),
                 ("zmode", ctypes.c_int32), ("kernel", ctypes.c_int32), ("sstart", ctypes.c_int32),
-                ("selector", ctypes.c_int32), ("reserved", ctypes.c_int32), ("tol", ctypes.c_double)]
+                ("selector", ctypes.c_int32), ("digits", ctypes.c_int32), ("tol", ctypes.c_double)]
 
 
 class oz_report_t(ctypes.Structure):
@@ -177,9 +177,10 @@ def oz_set_stream(handle, stream):
     return _check("oz_set_stream", _lib.oz_set_stream(handle, stream))
 
 
-def prec(slices=7, tol=0.0, smax=0, kchunk=0, zmode=0, kernel=0, sstart=0, selector=0):
-    """Precision record; prec(0, tol=...) asks for a tolerance-driven call."""
-    return oz_prec_t(slices, smax, kchunk, zmode, kernel, sstart, selector, 0, tol)
+def prec(slices=7, tol=0.0, smax=0, kchunk=0, zmode=0, kernel=0, sstart=0, selector=0, digits=0):
+    """Precision record; prec(0, tol=...) asks for a tolerance-driven call;
+    digits=1 selects balanced (round-to-nearest) digits."""
+    return oz_prec_t(slices, smax, kchunk, zmode, kernel, sstart, selector, digits, tol)
 
 
 def oz_workspace_size(handle, transa, transb, m, n, k, is_complex, p=None):

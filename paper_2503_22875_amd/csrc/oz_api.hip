@@ -56,11 +56,14 @@ int use_device(oz_handle_t h) {
 
 // Largest multiple of 64 with s * kc * 127^2 <= 2^31 - 1: the INT32 sum of one
 // anti-diagonal (at most s pair products per term, each |.| <= 127^2) over kc
-// terms cannot overflow.
-int64_t kchunk_bound(int s) {
-    int64_t kc = static_cast<int64_t>(INT32_MAX) / (static_cast<int64_t>(s) * 127 * 127);
+// terms cannot overflow.  Balanced digits reach -128: 128^2 per product.
+int64_t kchunk_bound(int s, bool bal = false) {
+    const int64_t dmax = bal ? 128 : 127;
+    int64_t kc = static_cast<int64_t>(INT32_MAX) / (static_cast<int64_t>(s) * dmax * dmax);
     return kc - kc % 64;
 }
+
+constexpr int kMaxBalancedSlices = 8;  // balanced digits: N below 2^62 in one int64
 
 // Workspace carve-up for one GEMM call (s_lay digit planes; the tol buffers
 // only when a tolerance-driven call needs them).
@@ -359,6 +362,7 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
     int64_t kc = 0;
     int kernel = 0;
     bool tol_mode = false;
+    bool bal = false;
     double tol = 0.0;
     int smax = kDefaultSmax;
     if (prec) {
@@ -366,7 +370,8 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
         if (prec->zmode != 0 && prec->zmode != 3 && prec->zmode != 4) return 14;
         if (cplx && prec->zmode == 3 && prec->slices == 0) return 14;  // 3M: fixed slice counts only
         if (prec->kernel < 0 || prec->kernel > 3) return 14;
-        if (prec->reserved != 0) return 14;
+        if (prec->digits != 0 && prec->digits != 1) return 14;
+        bal = prec->digits == 1;
         if (prec->slices == 0) {
             tol_mode = true;
             tol = prec->tol;
@@ -383,9 +388,11 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
         kernel = prec->kernel;
     }
     if (c_lo && (tol_mode || (cplx && prec && prec->zmode == 3))) return 14;  // fixed s, 4-product form
+    // balanced digits: fixed s <= 8, 4-product complex form, FP64 results
+    if (bal && (tol_mode || s > kMaxBalancedSlices || c_lo || (cplx && prec->zmode == 3))) return 14;
     const int s_plan = tol_mode ? smax : s;  // largest slice count this call may use
-    if (kc < 0 || kc % 64 != 0 || (kc > 0 && kc > kchunk_bound(s_plan))) return 14;
-    if (kc == 0) kc = kchunk_bound(s_plan);
+    if (kc < 0 || kc % 64 != 0 || (kc > 0 && kc > kchunk_bound(s_plan, bal))) return 14;
+    if (kc == 0) kc = kchunk_bound(s_plan, bal);
     if (!tol_mode && s > oz::kMaxLiveSlices && (kernel == 1 || kernel == 2)) return 14;
     if (!alpha || !beta) return OZ_ERR_ARG;
 
@@ -418,6 +425,7 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
     }
     Plan p = make_plan(cplx, m, n, k, s_plan, tol_mode);
     if (!grid_fits(p)) return OZ_ERR_UNSUPPORTED;
+    p.la.bal = p.lb.bal = bal ? 1 : 0;
     st = ensure_ws(h, p.total);
     if (st) return st;
     char* ws = static_cast<char*>(h->ws);
@@ -463,6 +471,7 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
     g.beta_i = bi;
     g.beta_zero = beta_zero ? 1 : 0;
     g.diag_out = nullptr;
+    g.bal = bal ? 1 : 0;
     if (rep) rep->kchunks = static_cast<int32_t>((p.la.kpad + kc - 1) / kc);
 
     if (c_lo) {  // the GEMM launcher picks the kernel for this mode

@@ -220,7 +220,7 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
     double tol = 0.0;
     int smax = kDefaultSmax, sstart = 0, selector = 0;
     if (prec) {
-        if (prec->kernel < 0 || prec->kernel > 2 || prec->reserved != 0) return 14;
+        if (prec->kernel < 0 || prec->kernel > 2 || prec->digits != 0) return 14;  // truncated digits only
         if (prec->zmode != 0 && prec->zmode != 4) return 14;  // batched: the 4-product form only
         if (prec->slices == 0) {
             // tolerance-driven: s per problem chosen at execution

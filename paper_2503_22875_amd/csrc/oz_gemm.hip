@@ -13,7 +13,8 @@
 // intensity of streaming one pair at a time, and no INT32 partial ever
 // leaves the registers.  Per INT32 chunk (kchunk terms, sized so that
 // s * kchunk * 127^2 <= 2^31 - 1) the s diagonal tiles are folded into an
-// FP64 tile, from d = s+1 down to 2, each times 2^(-7d) (exact).  The final
+// FP64 tile, from d = s+1 down to 2, each times 2^(-7d) (exact; 2^(4-8d) for
+// balanced digits).  The final
 // epilogue applies 2^(E_i + F_j) with ldexp and alpha/beta.
 //
 // LDS stages (a ring of NST): for each operand, 16-term half h, slice p:
@@ -36,34 +37,30 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 typedef __attribute__((address_space(3))) void lds_void;
 typedef __attribute__((address_space(1))) const void global_cvoid;
 
-// 2^(-7d) for d = dd + 2, exact.
-template <int DD>
-struct DiagScale {
-    static constexpr double value = DiagScale<DD - 1>::value * (1.0 / 128.0);
-};
-template <>
-struct DiagScale<0> {
-    static constexpr double value = 1.0 / 16384.0;
-};
+// Exponent of the weight of anti-diagonal d: 2^(-7d) for truncated digits,
+// 2^(4-8d) for balanced ones.  Every term S_d * 2^e is exact (ldexp of an
+// INT32 value far from the FP64 range limits).
+__device__ __forceinline__ int diag_exp(int d, int bal) { return bal ? 4 - 8 * d : -7 * d; }
 
 // Fold the live INT32 diagonal tiles into the FP64 tile, from the top
 // (d = DD + 2 = S + 1) down to d = DLO + 2; acc[i] holds diagonal DLO + i.
 template <int ND, int DLO, int DD>
-__device__ __forceinline__ void fold_diags(double (&acc64)[16], v16i (&acc)[ND]) {
+__device__ __forceinline__ void fold_diags(double (&acc64)[16], v16i (&acc)[ND], int bal) {
+    const int e = diag_exp(DD + 2, bal);
 #pragma unroll
-    for (int r = 0; r < 16; ++r)
-        acc64[r] = acc64[r] + static_cast<double>(acc[DD - DLO][r]) * DiagScale<DD>::value;
-    if constexpr (DD > DLO) fold_diags<ND, DLO, DD - 1>(acc64, acc);
+    for (int r = 0; r < 16; ++r) acc64[r] = acc64[r] + ldexp(static_cast<double>(acc[DD - DLO][r]), e);
+    if constexpr (DD > DLO) fold_diags<ND, DLO, DD - 1>(acc64, acc, bal);
 }
 
 // The same fold into a double-double (hi, lo): each term, exact in FP64, is
 // added by dd_add_exact (defined below).
 __device__ __forceinline__ void dd_add_exact(double& hi, double& lo, double x);
 template <int ND, int DLO, int DD>
-__device__ __forceinline__ void fold_diags_dd(double (&hi)[16], double (&lo)[16], v16i (&acc)[ND]) {
+__device__ __forceinline__ void fold_diags_dd(double (&hi)[16], double (&lo)[16], v16i (&acc)[ND], int bal) {
+    const int e = diag_exp(DD + 2, bal);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) dd_add_exact(hi[r], lo[r], static_cast<double>(acc[DD - DLO][r]) * DiagScale<DD>::value);
-    if constexpr (DD > DLO) fold_diags_dd<ND, DLO, DD - 1>(hi, lo, acc);
+    for (int r = 0; r < 16; ++r) dd_add_exact(hi[r], lo[r], ldexp(static_cast<double>(acc[DD - DLO][r]), e));
+    if constexpr (DD > DLO) fold_diags_dd<ND, DLO, DD - 1>(hi, lo, acc, bal);
 }
 
 // Tile order: the hardware hands consecutive blocks to the 8 XCDs in turn,
@@ -388,9 +385,9 @@ __device__ __forceinline__ void tile_body(const GemmArgs& g, int64_t tm, int64_t
                             g.diag_out[((chunk * S + d + DLO) * g.Np + col) * g.Mp + row0 + 8 * (r >> 2) +
                                        4 * half + (r & 3)] = acc[d][r];
                 } else if constexpr (XD) {
-                    fold_diags_dd<ND, DLO, S - 1>(acc64, lo64, acc);
+                    fold_diags_dd<ND, DLO, S - 1>(acc64, lo64, acc, g.bal);
                 } else {
-                    fold_diags<ND, DLO, S - 1>(acc64, acc);
+                    fold_diags<ND, DLO, S - 1>(acc64, acc, g.bal);
                 }
 #pragma unroll
                 for (int d = 0; d < ND; ++d)
@@ -421,9 +418,9 @@ __device__ __forceinline__ void tile_body(const GemmArgs& g, int64_t tm, int64_t
     if constexpr (!MULTI) {
         init64(acc64);
         if constexpr (XD)
-            fold_diags_dd<ND, DLO, S - 1>(acc64, lo64, acc);
+            fold_diags_dd<ND, DLO, S - 1>(acc64, lo64, acc, g.bal);
         else
-            fold_diags<ND, DLO, S - 1>(acc64, acc);
+            fold_diags<ND, DLO, S - 1>(acc64, acc, g.bal);
     }
     if constexpr (XD)
         store_tile_dd(g, acc64, lo64, row0, half, col);
@@ -543,11 +540,11 @@ __device__ __forceinline__ void stream_body(const GemmArgs& g, int s, int top, i
                     g.diag_out[((c * s + (d - 2)) * g.Np + col) * g.Mp + row0 + 8 * (r >> 2) + 4 * half + (r & 3)] =
                         acc[r];
             } else if (dd) {
-                const double sc = ldexp(1.0, -7 * d);  // exact power of two
+                const double sc = ldexp(1.0, diag_exp(d, g.bal));  // exact power of two
 #pragma unroll
                 for (int r = 0; r < 16; ++r) dd_add_exact(acc64[r], lo64[r], static_cast<double>(acc[r]) * sc);
             } else {
-                const double sc = ldexp(1.0, -7 * d);  // exact power of two
+                const double sc = ldexp(1.0, diag_exp(d, g.bal));  // exact power of two
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc64[r] = acc64[r] + static_cast<double>(acc[r]) * sc;
             }

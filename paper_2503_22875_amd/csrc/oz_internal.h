@@ -55,6 +55,7 @@ struct SliceLayout {
     int64_t rows_pad;   // padded vector count (multiple of kRowPad)
     int64_t kpad;       // padded term count (multiple of kStep)
     int s;              // slices
+    int bal;            // 1: balanced (round-to-nearest) digits, all s planes at once
 };
 
 SliceLayout slice_layout(int side_a, int cplx, int64_t nv, int64_t k, int s);
@@ -116,6 +117,7 @@ struct GemmArgs {
     int cplx;
     int tile;              // 0 auto, 1: 128 x 64 block, 2: 64 x 64 block, 3: per-diagonal streaming
     int mode;              // kFinal, kRawWrite, kRawAdd (see below)
+    int bal;               // 0: fold weights 2^(-7d) (truncated digits); 1: 2^(4-8d) (balanced)
     double* acc;           // raw FP64 tile sums acc[col * Mp + row] for the raw modes
     // epilogue
     double* C;

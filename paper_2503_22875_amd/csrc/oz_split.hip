@@ -95,6 +95,32 @@ __device__ __forceinline__ int digit_of(double x, int E, uint64_t W, int p) {
     return __double_as_longlong(x) < 0 ? -t : t;
 }
 
+// Balanced (round-to-nearest) digits, s <= 8: N = |x| * 2^(6 - E + 8(s-1))
+// rounded to the nearest integer (ties away from zero) with the sign of x --
+// one shift of the significand, |x| < 2^E keeping N below 2^62 -- then the
+// s digits are N's bytes read as signed int8 from the lowest up, each removed
+// before the next (N = (N - d) / 256), the top digit being what remains.
+__device__ __forceinline__ int64_t balanced_int(double x, int E, int s) {
+    const Sig g = sig_of(x, E);
+    const int sh = g.sh0 - 6 - 8 * (s - 1);
+    uint64_t n;
+    if (sh <= 0)
+        n = g.M << (-sh);
+    else if (sh <= 54)
+        n = (g.M + (1ull << (sh - 1))) >> sh;  // M < 2^53: no overflow
+    else
+        n = 0;  // M < 2^53 < 2^(sh-1): below one half
+    return g.neg ? -static_cast<int64_t>(n) : static_cast<int64_t>(n);
+}
+
+// Peel the lowest balanced digit off N (plane p = s-1 first, then down to 1;
+// plane 0 is the remaining N itself).
+__device__ __forceinline__ int peel_digit(int64_t& N) {
+    const int d = static_cast<int>(static_cast<int8_t>(static_cast<uint8_t>(N & 255)));
+    N = (N - d) >> 8;  // exact: N - d is a multiple of 256
+    return d;
+}
+
 __global__ void zero_u64_kernel(uint64_t* p, int64_t n) {
     int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;
@@ -166,7 +192,7 @@ __device__ __forceinline__ uint64_t pack8(const int* d) {
 // One block: 64 vectors (64 complex rows for a complex side-'A' operand) x one
 // MFMA step of 32 terms.  Each thread owns 8 consecutive terms of one vector:
 // 8 real elements, or 4 complex elements (terms 2l, 2l+1).
-template <bool LCONTIG, bool CPLX, bool SIDE_A>
+template <bool LCONTIG, bool CPLX, bool SIDE_A, bool BAL = false>
 __device__ __forceinline__ void digits_body(const OperandView& op, const uint64_t* maxbits, const SliceLayout& lay,
                                             int32_t* E, int8_t* slices, int64_t bx, int64_t by, int p_lo, int p_hi) {
     const int tid = threadIdx.x;
@@ -202,6 +228,51 @@ __device__ __forceinline__ void digits_body(const OperandView& op, const uint64_
             x[e] = re;
         }
     }
+    if constexpr (BAL) {
+        // all s planes at once (p_lo = 0, p_hi = s), lowest digit first
+        const int s = lay.s;
+        if (CPLX && SIDE_A) {
+            const int64_t r_re = 32 * (v >> 4) + 16 * ((v >> 3) & 1) + (v & 7);
+            const int64_t r_im = r_re + 8;
+            if (r_re >= lay.rows_pad) return;
+            // real-part row (ar, -ai): the digits of the value -ai are those of -N(ai)
+            int64_t nr[4], ni[4], nn[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                nr[e] = balanced_int(x[2 * e], ex, s);
+                ni[e] = balanced_int(x[2 * e + 1], ex, s);
+                nn[e] = -ni[e];
+            }
+            for (int p = s - 1; p >= 0; --p) {
+                int dre[8], dim[8];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int ar = p > 0 ? peel_digit(nr[e]) : static_cast<int>(nr[e]);
+                    const int ai = p > 0 ? peel_digit(ni[e]) : static_cast<int>(ni[e]);
+                    const int an = p > 0 ? peel_digit(nn[e]) : static_cast<int>(nn[e]);
+                    dre[2 * e] = ar;
+                    dre[2 * e + 1] = an;
+                    dim[2 * e] = ai;
+                    dim[2 * e + 1] = ar;
+                }
+                *reinterpret_cast<uint64_t*>(slices + slice_off(t0, p, r_re, s, lay.rows_pad)) = pack8(dre);
+                *reinterpret_cast<uint64_t*>(slices + slice_off(t0, p, r_im, s, lay.rows_pad)) = pack8(dim);
+            }
+        } else {
+            if (v >= lay.rows_pad) return;
+            int64_t nv8[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) nv8[e] = balanced_int(x[e], ex, s);
+            for (int p = s - 1; p >= 0; --p) {
+                int d[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) d[e] = p > 0 ? peel_digit(nv8[e]) : static_cast<int>(nv8[e]);
+                *reinterpret_cast<uint64_t*>(slices + slice_off(t0, p, v, s, lay.rows_pad)) = pack8(d);
+            }
+        }
+        return;
+    }
+
     uint64_t w[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) w[e] = frac_window(sig_of(x[e], ex));
@@ -236,10 +307,10 @@ __device__ __forceinline__ void digits_body(const OperandView& op, const uint64_
     }
 }
 
-template <bool LCONTIG, bool CPLX, bool SIDE_A>
+template <bool LCONTIG, bool CPLX, bool SIDE_A, bool BAL>
 __global__ __launch_bounds__(256) void digits_kernel(OperandView op, const uint64_t* maxbits, SliceLayout lay,
                                                      int32_t* E, int8_t* slices, int p_lo, int p_hi) {
-    digits_body<LCONTIG, CPLX, SIDE_A>(op, maxbits, lay, E, slices, blockIdx.x, blockIdx.y, p_lo, p_hi);
+    digits_body<LCONTIG, CPLX, SIDE_A, BAL>(op, maxbits, lay, E, slices, blockIdx.x, blockIdx.y, p_lo, p_hi);
 }
 
 // Batched forms: block b runs item b of a list naming the operand and the
@@ -415,6 +486,7 @@ SliceLayout slice_layout(int side_a, int cplx, int64_t nv, int64_t k, int s) {
     int64_t terms = cplx ? 2 * k : k;
     L.kpad = round_up(terms > 0 ? terms : 1, kStep);
     L.s = s;
+    L.bal = 0;
     return L;
 }
 
@@ -477,17 +549,27 @@ hipError_t launch_digits(const OperandView& op, const uint64_t* maxbits, const S
     // blocks along vectors: 64 vectors each (64 complex rows = 128 slice rows for two_row)
     const int64_t vec_cover = two_row ? lay.rows_pad / 2 : lay.rows_pad;
     dim3 grid(static_cast<unsigned>(lay.kpad / kStep), static_cast<unsigned>((vec_cover + 63) / 64));
-#define OZ_DIG(LC, CP, SA) \
-    hipLaunchKernelGGL((digits_kernel<LC, CP, SA>), grid, dim3(256), 0, st, op, maxbits, lay, E, slices, p_lo, p_hi)
-    if (lcontig) {
-        if (two_row) OZ_DIG(true, true, true);
-        else if (op.cplx) OZ_DIG(true, true, false);
-        else OZ_DIG(true, false, false);
-    } else {
-        if (two_row) OZ_DIG(false, true, true);
-        else if (op.cplx) OZ_DIG(false, true, false);
-        else OZ_DIG(false, false, false);
+    // balanced digits depend on s: all planes in one pass
+    if (lay.bal && (p_lo != 0 || p_hi != lay.s)) return hipErrorInvalidValue;
+#define OZ_DIG(LC, CP, SA, BL) \
+    hipLaunchKernelGGL((digits_kernel<LC, CP, SA, BL>), grid, dim3(256), 0, st, op, maxbits, lay, E, slices, p_lo, \
+                       p_hi)
+#define OZ_DIG_ALL(BL)                                    \
+    if (lcontig) {                                        \
+        if (two_row) OZ_DIG(true, true, true, BL);        \
+        else if (op.cplx) OZ_DIG(true, true, false, BL);  \
+        else OZ_DIG(true, false, false, BL);              \
+    } else {                                              \
+        if (two_row) OZ_DIG(false, true, true, BL);       \
+        else if (op.cplx) OZ_DIG(false, true, false, BL); \
+        else OZ_DIG(false, false, false, BL);             \
     }
+    if (lay.bal) {
+        OZ_DIG_ALL(true)
+    } else {
+        OZ_DIG_ALL(false)
+    }
+#undef OZ_DIG_ALL
 #undef OZ_DIG
     return hipGetLastError();
 }
