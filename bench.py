@@ -552,9 +552,51 @@ def bench_inv(args):
                       "rows": rows}), flush=True)
 
 
+def bench_balanced(args):
+    """Truncated vs balanced (round-to-nearest) digits: ZGEMM n = 4096 (row
+    exponents +-20, normal entries) in the 4-product form at s = 3..8, each
+    with its time per call and relative error (Frobenius) against the native
+    complex128 product on the same GPU."""
+    import torch
+
+    import paper_2503_22875_amd as oz
+    import workloads
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    h = oz.oz_create(0)
+    oz.oz_set_stream(h, stream.cuda_stream)
+    n = args.n
+    A, B = workloads.zgemm_rowexp(n, seed=0)
+    Ad = torch.from_numpy(A).cuda()
+    Bd = torch.from_numpy(B).cuda()
+    dA = torch.view_as_real(Ad.T.contiguous()).reshape(-1)
+    dB = torch.view_as_real(Bd.T.contiguous()).reshape(-1)
+    dC = torch.empty_like(dA)
+    N = Ad @ Bd
+    nrm = float(torch.linalg.norm(N))
+    flops = 8.0 * n ** 3
+    rows = []
+    for s in range(3, 9):
+        row = {"s": s}
+        for name, dig in (("truncated", 0), ("balanced", 1)):
+            p = oz.prec(s, digits=dig)
+            ms = _time_ms(lambda: oz.oz_zgemm(h, "N", "N", n, n, n, 1.0, dA, n, dB, n, 0.0, dC, n, p), stream,
+                          args.steps, args.warmup)
+            C = torch.view_as_complex(dC.view(n, n, 2)).T
+            err = float(torch.linalg.norm(C - N)) / nrm
+            row[name] = {"ms": round(ms, 3), "tflops": round(flops / (ms * 1e-3) / 1e12, 2),
+                         "rel_err_vs_native": float("%.3e" % err)}
+        print(json.dumps(row), flush=True)
+        rows.append(row)
+    oz.oz_destroy(h)
+    print(json.dumps({"workload": "zgemm n=%d 4-product form, truncated vs balanced digits" % n, "rows": rows}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="zgemm4096", choices=["zgemm4096", "batch512", "select", "sweep", "wide_tol", "blas", "x2", "inv"])
+    ap.add_argument("--workload", default="zgemm4096", choices=["zgemm4096", "batch512", "select", "sweep", "wide_tol", "blas", "x2", "inv", "balanced"])
     ap.add_argument("--nb", type=int, default=128, help="panel width of the inversion workload (getrf)")
     ap.add_argument("--nb-inv", type=int, default=256, help="block rows of the inversion workload's solves (getri)")
     ap.add_argument("--inv-slices", default="3,4,5,6,7,8,14")
@@ -596,6 +638,8 @@ def main():
         return bench_x2(args)
     if args.workload == "inv":
         return bench_inv(args)
+    if args.workload == "balanced":
+        return bench_balanced(args)
 
     import torch
 
