@@ -604,6 +604,8 @@ __global__ __launch_bounds__(64 * kTrsmWaves) void trsm_wave_kernel(const double
             }
 #pragma unroll
             for (int t = 0; t < R2; ++t) {
+                // slots whose rows are all solved (wave-uniform test) are skipped
+                if (UPPER ? 64 * t >= k : 64 * t + 63 <= k) continue;
                 const int i = lane + 64 * t;
                 if (UPPER ? i < k : (i > k && i < b)) {
                     double tr, ti;
