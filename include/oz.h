@@ -246,6 +246,10 @@ int oz_zgemm_x2(oz_handle_t handle, char transa, char transb, int64_t m, int64_t
  * (oz_zgemm) followed by X_i = L_ii^-1 X_i, then from the last block row,
  * X_i = X_i - U[i, i+1:] X[i+1:] (oz_zgemm) followed by back substitution
  * with U_ii (each row multiplied by the reciprocal of its diagonal entry).
+ * The solves run against I in a library-allocated n x n work matrix and the
+ * columns are permuted into X at the end (the same bits, without the
+ * structural zeros of L^-1).  ipiv must hold the pivots oz_zgetrf wrote
+ * (other values give an unspecified X but no access outside it).
  * Synchronises.  Argument errors: 2 (n), 4 (lda), 7 (ldx), 8 (nb), 9 (prec),
  * OZ_ERR_ARG (a NULL pointer with n > 0, or X == LU). */
 int oz_zgetrf(oz_handle_t handle, int64_t n, double* A, int64_t lda, int32_t* ipiv, int32_t nb,

@@ -17,7 +17,9 @@
 // A22 -= L21 U12 as an emulated ZGEMM (oz_zgemm with alpha = -1, beta = 1).
 // The inverse solves A X = I: X = P I, then block by block
 // X_i -= L[i, :i] X[:i] (emulated) and X_i = L_ii^-1 X_i, then from the last
-// block X_i -= U[i, i+1:] X[i+1:] (emulated) and X_i = U_ii^-1 X_i.
+// block X_i -= U[i, i+1:] X[i+1:] (emulated) and X_i = U_ii^-1 X_i -- run
+// against I with the columns permuted at the end, which gives the same bits
+// and skips the structural zeros of L^-1.
 // Complex arithmetic is written out on the parts, (ar br - ai bi, ar bi + ai br),
 // with no fused multiply-add (the library is built with -ffp-contract=off).
 #include <hip/hip_runtime.h>
@@ -511,15 +513,30 @@ __global__ __launch_bounds__(256) void perm_src_kernel(const int32_t* ipiv, int6
     if (x < n) src[x] = static_cast<int32_t>(y);
 }
 
-// X = P I: X[r, c] = 1 where c = src[r], else 0.
-__global__ void perm_fill_kernel(double* X, int64_t ld, int64_t n, const int32_t* src) {
+// T = I (n x n).
+__global__ void identity_kernel(double* T, int64_t ldt, int64_t n) {
     const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (r >= n) return;
-    const int64_t s = src[r];
     for (int64_t c = blockIdx.y; c < n; c += gridDim.y) {
-        double* e = at(X, ld, r, c);
-        e[0] = s == c ? 1.0 : 0.0;
+        double* e = at(T, ldt, r, c);
+        e[0] = r == c ? 1.0 : 0.0;
         e[1] = 0.0;
+    }
+}
+
+// X[:, src[c]] = T[:, c]: the column permutation that turns L^-1-based
+// columns into those of the inverse (grid.x over rows, grid.y over columns).
+__global__ void col_scatter_kernel(const double* T, int64_t ldt, double* X, int64_t ldx, int64_t n,
+                                   const int32_t* src) {
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    for (int64_t c = blockIdx.y; c < n; c += gridDim.y) {
+        const int64_t d = src[c];
+        if (d < 0 || d >= n) continue;  // pivots not from oz_zgetrf: no access outside X
+        const double* t = at(T, ldt, r, c);
+        double* x = at(X, ldx, r, d);
+        x[0] = t[0];
+        x[1] = t[1];
     }
 }
 
@@ -851,43 +868,68 @@ int oz_zgetri(oz_handle_t h, int64_t n, const double* LU, int64_t lda, const int
     if (st) return st;
     hipStream_t s = oz_handle_stream(h);
     const double minus_one[2] = {-1.0, 0.0}, one[2] = {1.0, 0.0};
+    // The solves run against I into a work matrix T, and the columns are
+    // permuted at the end: column j of L^-1 (P I) is column r of L^-1 for the
+    // row r of P I that holds the one of column j (src[r] = j).  Each column
+    // takes exactly the same operations either way -- an entry of an emulated
+    // product depends only on its row of op(A) and its column of op(B), and
+    // the triangular solves work column by column -- so the inverse is the
+    // same bit for bit.  Against I, block row i of L^-1 is zero right of
+    // column (i+1) nb: those columns are neither multiplied nor solved (they
+    // stay +0, as subtracting +-0 from them would leave them).
     int32_t* src = nullptr;
-    if (hipMalloc(&src, sizeof(int32_t) * n) != hipSuccess) return OZ_ERR_HIP;
+    double* T = nullptr;
+    const int64_t ldt = n;
+    auto release = [&]() {
+        bool ok = true;
+        if (src && hipFree(src) != hipSuccess) ok = false;
+        if (T && hipFree(T) != hipSuccess) ok = false;
+        return ok;
+    };
+    if (hipMalloc(&src, sizeof(int32_t) * n) != hipSuccess ||
+        hipMalloc(&T, sizeof(double) * 2 * static_cast<size_t>(n) * static_cast<size_t>(n)) != hipSuccess) {
+        release();
+        return OZ_ERR_HIP;
+    }
+    const dim3 grid_nn(static_cast<unsigned>((n + 255) / 256), static_cast<unsigned>(n < 65535 ? n : 65535));
     hipLaunchKernelGGL(perm_src_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, ipiv, n, src);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) {
-        const dim3 grid(static_cast<unsigned>((n + 255) / 256), static_cast<unsigned>(n < 65535 ? n : 65535));
-        hipLaunchKernelGGL(perm_fill_kernel, grid, dim3(256), 0, s, X, ldx, n, src);
+        hipLaunchKernelGGL(identity_kernel, grid_nn, dim3(256), 0, s, T, ldt, n);
         e = hipGetLastError();
     }
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (hipFree(src) != hipSuccess) e = hipErrorUnknown;
-    if (e != hipSuccess) return OZ_ERR_HIP;
-    // forward: L Y = P I
-    for (int64_t j0 = 0; j0 < n; j0 += nb) {
+    int rc = e == hipSuccess ? OZ_OK : OZ_ERR_HIP;
+    // forward: L Y = I, block row i over columns [0, (i+1) nb)
+    for (int64_t j0 = 0; rc == OZ_OK && j0 < n; j0 += nb) {
         const int b = static_cast<int>(n - j0 < nb ? n - j0 : nb);
         if (j0 > 0) {
-            const int rc = oz_zgemm(h, 'N', 'N', b, n, j0, minus_one, LU + 2 * j0, lda, X, ldx, one, X + 2 * j0, ldx,
-                                    prec, nullptr);
-            if (rc) return rc;
+            rc = oz_zgemm(h, 'N', 'N', b, j0, j0, minus_one, LU + 2 * j0, lda, T, ldt, one, T + 2 * j0, ldt, prec,
+                          nullptr);
+            if (rc) break;
         }
-        if (launch_trsm(false, LU + 2 * (j0 + j0 * lda), lda, b, X + 2 * j0, ldx, n, s) != hipSuccess)
-            return OZ_ERR_HIP;
+        if (launch_trsm(false, LU + 2 * (j0 + j0 * lda), lda, b, T + 2 * j0, ldt, j0 + b, s) != hipSuccess)
+            rc = OZ_ERR_HIP;
     }
-    // backward: U X = Y
+    // backward: U T = Y, all columns
     const int64_t last = ((n - 1) / nb) * nb;
-    for (int64_t j0 = last; j0 >= 0; j0 -= nb) {
+    for (int64_t j0 = last; rc == OZ_OK && j0 >= 0; j0 -= nb) {
         const int b = static_cast<int>(n - j0 < nb ? n - j0 : nb);
         const int64_t rest = n - j0 - b;
         if (rest > 0) {
-            const int rc = oz_zgemm(h, 'N', 'N', b, n, rest, minus_one, LU + 2 * (j0 + (j0 + b) * lda), lda,
-                                    X + 2 * (j0 + b), ldx, one, X + 2 * j0, ldx, prec, nullptr);
-            if (rc) return rc;
+            rc = oz_zgemm(h, 'N', 'N', b, n, rest, minus_one, LU + 2 * (j0 + (j0 + b) * lda), lda, T + 2 * (j0 + b),
+                          ldt, one, T + 2 * j0, ldt, prec, nullptr);
+            if (rc) break;
         }
-        if (launch_trsm(true, LU + 2 * (j0 + j0 * lda), lda, b, X + 2 * j0, ldx, n, s) != hipSuccess)
-            return OZ_ERR_HIP;
+        if (launch_trsm(true, LU + 2 * (j0 + j0 * lda), lda, b, T + 2 * j0, ldt, n, s) != hipSuccess)
+            rc = OZ_ERR_HIP;
     }
-    return hipStreamSynchronize(s) == hipSuccess ? OZ_OK : OZ_ERR_HIP;
+    if (rc == OZ_OK) {
+        hipLaunchKernelGGL(col_scatter_kernel, grid_nn, dim3(256), 0, s, T, ldt, X, ldx, n, src);
+        if (hipGetLastError() != hipSuccess) rc = OZ_ERR_HIP;
+    }
+    if (hipStreamSynchronize(s) != hipSuccess && rc == OZ_OK) rc = OZ_ERR_HIP;
+    if (!release() && rc == OZ_OK) rc = OZ_ERR_HIP;
+    return rc;
 }
 
 }  // extern "C"
