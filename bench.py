@@ -554,9 +554,9 @@ def bench_inv(args):
 
 def bench_balanced(args):
     """Truncated vs balanced (round-to-nearest) digits: ZGEMM n = 4096 (row
-    exponents +-20, normal entries) in the 4-product form at s = 3..8, each
-    with its time per call and relative error (Frobenius) against the native
-    complex128 product on the same GPU."""
+    exponents +-20, normal entries) in the 4-product and the 3-product form at
+    s = 3..8, each with its time per call and relative error (Frobenius)
+    against the native complex128 product on the same GPU."""
     import torch
 
     import paper_2503_22875_amd as oz
@@ -577,10 +577,10 @@ def bench_balanced(args):
     nrm = float(torch.linalg.norm(N))
     flops = 8.0 * n ** 3
     rows = []
-    for s in range(3, 9):
-        row = {"s": s}
+    for zmode, s in [(z, s) for z in (4, 3) for s in range(3, 9)]:
+        row = {"s": s, "zmode": zmode}
         for name, dig in (("truncated", 0), ("balanced", 1)):
-            p = oz.prec(s, digits=dig)
+            p = oz.prec(s, digits=dig, zmode=zmode)
             ms = _time_ms(lambda: oz.oz_zgemm(h, "N", "N", n, n, n, 1.0, dA, n, dB, n, 0.0, dC, n, p), stream,
                           args.steps, args.warmup)
             C = torch.view_as_complex(dC.view(n, n, 2)).T
@@ -590,7 +590,7 @@ def bench_balanced(args):
         print(json.dumps(row), flush=True)
         rows.append(row)
     oz.oz_destroy(h)
-    print(json.dumps({"workload": "zgemm n=%d 4-product form, truncated vs balanced digits" % n, "rows": rows}),
+    print(json.dumps({"workload": "zgemm n=%d, truncated vs balanced digits" % n, "rows": rows}),
           flush=True)
 
 

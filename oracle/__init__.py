@@ -224,7 +224,8 @@ def _op(trans, X):
     return X if t == "N" else (X.T if t == "T" else X.conj().T)
 
 
-def emu_zgemm3(transa, transb, A, B, s, alpha=1.0, beta=0.0, C=None, kc=None, rows=None, cols=None):
+def emu_zgemm3(transa, transb, A, B, s, alpha=1.0, beta=0.0, C=None, kc=None, rows=None, cols=None,
+               balanced=False):
     """O4, complex product in the 3-real-product form (3M).
 
     With op(A) = Ar + i Ai and op(B) = Br + i Bi, the pre-added operands
@@ -232,17 +233,19 @@ def emu_zgemm3(transa, transb, A, B, s, alpha=1.0, beta=0.0, C=None, kc=None, ro
     emulated products T1 = Ar Br, T2 = Ai Bi, T3 = As Bs (each with its own
     row / column scales, kc = ``kchunk(s)`` real terms) are combined as
     Cr = T1 - T2, Ci = (T3 - T1) - T2, and then alpha, beta are applied with
-    the complex formula of the 4-product form (each product and sum rounded)."""
+    the complex formula of the 4-product form (each product and sum rounded).
+    balanced: the three real products take balanced digits (none of their
+    operands is negated, so no digit of a negated value arises)."""
     A = _op(transa, _f(A, np.complex128))
     B = _op(transb, _f(B, np.complex128))
     Ar, Ai = np.asfortranarray(A.real), np.asfortranarray(A.imag)
     Br, Bi = np.asfortranarray(B.real), np.asfortranarray(B.imag)
     As = np.asfortranarray(Ar + Ai)
     Bs = np.asfortranarray(Br + Bi)
-    kc = kchunk(s) if kc is None else kc
-    T1 = emu_gemm("N", "N", Ar, Br, s, kc=kc, rows=rows, cols=cols)
-    T2 = emu_gemm("N", "N", Ai, Bi, s, kc=kc, rows=rows, cols=cols)
-    T3 = emu_gemm("N", "N", As, Bs, s, kc=kc, rows=rows, cols=cols)
+    kc = kchunk(s, balanced=balanced) if kc is None else kc
+    T1 = emu_gemm("N", "N", Ar, Br, s, kc=kc, rows=rows, cols=cols, balanced=balanced)
+    T2 = emu_gemm("N", "N", Ai, Bi, s, kc=kc, rows=rows, cols=cols, balanced=balanced)
+    T3 = emu_gemm("N", "N", As, Bs, s, kc=kc, rows=rows, cols=cols, balanced=balanced)
     Cr = T1 - T2
     Ci = (T3 - T1) - T2
     xr, xi = complex(alpha).real, complex(alpha).imag

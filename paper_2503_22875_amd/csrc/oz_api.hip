@@ -252,9 +252,10 @@ int rule_slices(oz_handle_t h, const oz::OperandView& va, const oz::OperandView&
 // Three quarters of the INT8 work of the 4-product form.
 int zgemm_3m(oz_handle_t h, char transa, char transb, int64_t m, int64_t n, int64_t k, const double* alpha,
              const double* A, int64_t lda, const double* B, int64_t ldb, const double* beta, double* C, int64_t ldc,
-             int s, int64_t kc, int kernel, oz_report_t* rep) {
+             int s, int64_t kc, int kernel, bool bal, oz_report_t* rep) {
     Plan3 p = make_plan3(m, n, k, s);
     if (p.la.rows_pad / 64 > 65535 || p.lb.rows_pad / 64 > 65535) return OZ_ERR_UNSUPPORTED;
+    p.la.bal = p.lb.bal = bal ? 1 : 0;
     int st = ensure_ws(h, p.total);
     if (st) return st;
     char* ws = static_cast<char*>(h->ws);
@@ -297,6 +298,7 @@ int zgemm_3m(oz_handle_t h, char transa, char transb, int64_t m, int64_t n, int6
         g.tile = kernel;
         g.m = m;
         g.n = n;
+        g.bal = bal ? 1 : 0;
         if (q < 2) {
             // T1, T2: plain FP64 results (alpha = 1, beta = 0: 1 * v is exact)
             g.mode = oz::kFinal;
@@ -388,8 +390,8 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
         kernel = prec->kernel;
     }
     if (c_lo && (tol_mode || (cplx && prec && prec->zmode == 3))) return 14;  // fixed s, 4-product form
-    // balanced digits: fixed s <= 8, 4-product complex form, FP64 results
-    if (bal && (tol_mode || s > kMaxBalancedSlices || c_lo || (cplx && prec->zmode == 3))) return 14;
+    // balanced digits: fixed s <= 8, FP64 results
+    if (bal && (tol_mode || s > kMaxBalancedSlices || c_lo)) return 14;
     const int s_plan = tol_mode ? smax : s;  // largest slice count this call may use
     if (kc < 0 || kc % 64 != 0 || (kc > 0 && kc > kchunk_bound(s_plan, bal))) return 14;
     if (kc == 0) kc = kchunk_bound(s_plan, bal);
@@ -420,8 +422,8 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
 
     if (cplx && prec && prec->zmode == 3) {
         // 3-real-product form: real INT32 chunks of k terms
-        const int64_t kc3 = prec->kchunk ? prec->kchunk : kchunk_bound(s);
-        return zgemm_3m(h, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, s, kc3, kernel, rep);
+        const int64_t kc3 = prec->kchunk ? prec->kchunk : kchunk_bound(s, bal);
+        return zgemm_3m(h, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, s, kc3, kernel, bal, rep);
     }
     Plan p = make_plan(cplx, m, n, k, s_plan, tol_mode);
     if (!grid_fits(p)) return OZ_ERR_UNSUPPORTED;

@@ -415,7 +415,7 @@ __global__ __launch_bounds__(256) void scan3_kernel(OperandView op, Split3Out o,
 
 // One block: 64 vectors x one step of 32 terms; each thread owns 8 consecutive
 // terms (complex elements) of one vector and writes them into all three parts.
-template <bool LCONTIG>
+template <bool LCONTIG, bool BAL>
 __global__ __launch_bounds__(256) void digits3_kernel(OperandView op, SliceLayout lay, Split3Out o) {
     const int tid = threadIdx.x;
     const int vi = LCONTIG ? (tid >> 2) : (tid & 63);
@@ -445,13 +445,25 @@ __global__ __launch_bounds__(256) void digits3_kernel(OperandView op, SliceLayou
     for (int q = 0; q < 3; ++q) {
         const bool bad = ex[q] == kNonFiniteExp;
         double x[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e)  // part 2 is the FP64 sum of the two parts (as in the scan)
+            x[e] = bad ? 0.0 : (q == 0 ? re[e] : q == 1 ? im[e] : re[e] + im[e]);
+        if constexpr (BAL) {
+            // balanced digits, lowest first (no part is negated in this form)
+            int64_t nv8[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) nv8[e] = balanced_int(x[e], ex[q], lay.s);
+            for (int p = lay.s - 1; p >= 0; --p) {
+                int d[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) d[e] = p > 0 ? peel_digit(nv8[e]) : static_cast<int>(nv8[e]);
+                *reinterpret_cast<uint64_t*>(o.slices[q] + slice_off(t0, p, v, lay.s, lay.rows_pad)) = pack8(d);
+            }
+            continue;
+        }
         uint64_t w[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            // part 2 is the FP64 sum of the two parts (as in the scan)
-            x[e] = bad ? 0.0 : (q == 0 ? re[e] : q == 1 ? im[e] : re[e] + im[e]);
-            w[e] = frac_window(sig_of(x[e], ex[q]));
-        }
+        for (int e = 0; e < 8; ++e) w[e] = frac_window(sig_of(x[e], ex[q]));
         for (int p = 0; p < lay.s; ++p) {
             int d[8];
 #pragma unroll
@@ -474,8 +486,13 @@ hipError_t launch_scan3(const OperandView& op, const Split3Out& o, hipStream_t s
 
 hipError_t launch_digits3(const OperandView& op, const SliceLayout& lay, const Split3Out& o, hipStream_t st) {
     dim3 grid(static_cast<unsigned>(lay.kpad / kStep), static_cast<unsigned>((lay.rows_pad + 63) / 64));
-    if (op.sl == 1) hipLaunchKernelGGL(digits3_kernel<true>, grid, dim3(256), 0, st, op, lay, o);
-    else hipLaunchKernelGGL(digits3_kernel<false>, grid, dim3(256), 0, st, op, lay, o);
+    if (lay.bal) {
+        if (op.sl == 1) hipLaunchKernelGGL((digits3_kernel<true, true>), grid, dim3(256), 0, st, op, lay, o);
+        else hipLaunchKernelGGL((digits3_kernel<false, true>), grid, dim3(256), 0, st, op, lay, o);
+    } else {
+        if (op.sl == 1) hipLaunchKernelGGL((digits3_kernel<true, false>), grid, dim3(256), 0, st, op, lay, o);
+        else hipLaunchKernelGGL((digits3_kernel<false, false>), grid, dim3(256), 0, st, op, lay, o);
+    }
     return hipGetLastError();
 }
 

@@ -156,8 +156,6 @@ def test_balanced_rejections(oz, handle):
     assert dg(oz.prec(7, digits=2)) == 14
     assert dg(oz.prec(7, digits=1, kchunk=18752)) == 14  # beyond s * kc * 128^2 <= 2^31 - 1
     assert dg(oz.prec(7, digits=1, kchunk=18688)) == 0
-    assert oz.oz_zgemm(handle, "N", "N", 4, 4, 4, 1.0, z, 4, z, 4, 0.0, z, 4, oz.prec(7, zmode=3, digits=1),
-                       check=False) == 14
     lo = torch.zeros(64, dtype=torch.float64, device="cuda")
     assert oz.oz_dgemm_x2(handle, "N", "N", 4, 4, 4, d, 4, d, 4, d, lo, 4, oz.prec(7, digits=1), check=False) == 14
 
@@ -190,3 +188,47 @@ def test_balanced_full_size_zgemm(oz, handle):
     et = np.linalg.norm(T - N) / np.linalg.norm(N)
     print("err balanced %.3e truncated %.3e" % (eb, et), flush=True)
     assert eb < et / 4
+
+
+@pytest.mark.parametrize("s", [3, 6, 7, 8])
+@pytest.mark.parametrize("ta,tb", [("N", "N"), ("C", "N"), ("T", "C")])
+def test_zgemm_3m_balanced_bit_exact(oz, handle, s, ta, tb):
+    rng = np.random.default_rng(3000 + 10 * s + ord(ta) + 7 * ord(tb))
+    m, n, k = 66, 50, 90
+    A = stored(rng, ta, m, k, 10, True)
+    B = stored(rng, tb, k, n, 10, True)
+    C = wide(rng, (m, n), 3, True)
+    al, be = complex(1.5, 0.5), complex(0.0, -1.0)
+    dA, lda = to_dev(A, A.shape[0] + 1)
+    dB, ldb = to_dev(B, B.shape[0] + 2)
+    dC, ldc = to_dev(C, m + 3)
+    oz.oz_zgemm(handle, ta, tb, m, n, k, al, dA, lda, dB, ldb, be, dC, ldc, oz.prec(s, zmode=3, digits=1))
+    torch.cuda.synchronize()
+    got = from_dev(dC, m, n, ldc)
+    ref = oracle.emu_zgemm3(ta, tb, A, B, s, alpha=al, beta=be, C=C, balanced=True)
+    assert np.array_equal(got, ref)
+
+
+def test_zgemm_3m_balanced_full_size(oz, handle):
+    # the benchmark's form (3M) at n = 4096, s = 7 with balanced digits:
+    # sampled entries bit-exact, error far below the truncated form's
+    import workloads
+    n, s = 4096, 7
+    A, B = workloads.zgemm_rowexp(n, seed=0)
+    dA, _ = to_dev(A)
+    dB, _ = to_dev(B)
+    dC, _ = to_dev(np.zeros((n, n), complex, order="F"))
+    print("zgemm 3M n=%d s=%d balanced" % (n, s), flush=True)
+    oz.oz_zgemm(handle, "N", "N", n, n, n, 1.0, dA, n, dB, n, 0.0, dC, n, oz.prec(s, zmode=3, digits=1))
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(1)
+    rows = np.sort(rng.choice(n, 16, replace=False))
+    cols = np.sort(rng.choice(n, 16, replace=False))
+    C = from_dev(dC, n, n, n)
+    ref = oracle.emu_zgemm3("N", "N", A, B, s, rows=rows, cols=cols, balanced=True)
+    assert np.array_equal(C[np.ix_(rows, cols)], ref)
+    N = (torch.from_numpy(A).cuda() @ torch.from_numpy(B).cuda()).cpu().numpy()
+    err = np.linalg.norm(C - N) / np.linalg.norm(N)
+    print("err 3M balanced %.3e" % err, flush=True)
+    assert err < 3e-14
+

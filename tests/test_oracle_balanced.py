@@ -161,3 +161,15 @@ def test_complex_is_the_real_product_over_two_k_terms(balanced, ta):
         re = oracle.emu_gemm("N", "N", np.hstack([Ar, -Ai]), np.vstack([Br, Bi]), s, balanced=balanced)
         im = oracle.emu_gemm("N", "N", np.hstack([Ar, Ai]), np.vstack([Bi, Br]), s, balanced=balanced)
         assert np.array_equal(got.real, re) and np.array_equal(got.imag, im), s
+
+
+def test_three_product_form_small_integers_exact():
+    # 3M with balanced digits: parts |x| <= 63 (their sums <= 126): from s = 3
+    # every nonzero digit pair is kept, so the complex product is exact
+    rng = np.random.default_rng(17)
+    A = rng.integers(-63, 64, (12, 20)) + 1j * rng.integers(-63, 64, (12, 20))
+    B = rng.integers(-63, 64, (20, 9)) + 1j * rng.integers(-63, 64, (20, 9))
+    for s in (3, 5, 8):
+        got = oracle.emu_zgemm3("N", "N", np.asfortranarray(A), np.asfortranarray(B), s, balanced=True)
+        assert np.array_equal(got, A @ B), s
+
