@@ -56,14 +56,17 @@
  *
  * Balanced digits (round to nearest; the round-to-nearest splitting the paper
  * points to as worth about one bit per slice, Sec. 4), fixed s <= 8 only:
- *   - N = |x| * 2^(6 - E + 8(s-1)) rounded to the nearest integer (ties away
- *     from zero), with the sign of x; |x| < 2^E keeps |N| <= 2^(6+8(s-1));
+ *   - the vector's exponent is E' = E, or E + 1 when its largest magnitude M
+ *     has M * 2^(7-E) > 127 (then the top digit could round to 128);
+ *   - N = |x| * 2^(7 - E' + 8(s-1)) rounded to the nearest integer (ties
+ *     away from zero), with the sign of x; |N| <= 127 * 256^(s-1);
  *   - the digits are the unique d_1..d_s with N = sum_p d_p 256^(s-p) and
  *     d_2..d_s in [-128, 127] (d_p = N mod 256 taken in that range, then
- *     N = (N - d_p) / 256); d_1 is what remains, |d_1| <= 65;
- *   - so x = 2^(E+2) sum_p d_p 2^(-8p) up to half a unit of the last digit,
- *     and the fold weight of anti-diagonal d is 2^(4 - 8d):
- *       acc = sum over chunks, then d = s+1 down to 2, of S_{d,c} * 2^(4-8d);
+ *     N = (N - d_p) / 256); d_1 is what remains, |d_1| <= 127;
+ *   - so x = 2^(E'+1) sum_p d_p 2^(-8p) up to half a unit of the last digit,
+ *     and the fold weight of anti-diagonal d is 2^(2 - 8d), the final scale
+ *     2^(E'_i + F'_j):
+ *       acc = sum over chunks, then d = s+1 down to 2, of S_{d,c} * 2^(2-8d);
  *   - every digit product is at most 128^2 in magnitude, so the INT32 chunk
  *     bound is s * kc * 128^2 <= 2^31 - 1;
  *   - complex: Re C is the real emulated product of the rows (ar, -ai)
@@ -281,13 +284,14 @@ static void digits_of(double a, int E, int s, int8_t* out, int64_t stride) {
     }
 }
 
-/* Balanced digits of x under scale exponent E and slice count s (s <= 8).
-   ldexp is exact here: the result is below 2^62, and where it would be
-   subnormal it is below 1/2, which rounds to 0 whatever ldexp returns. */
+/* Balanced digits of x under scale exponent E (the vector's E') and slice
+   count s (s <= 8).  ldexp is exact here: the result is below 2^63, and where
+   it would be subnormal it is below 1/2, which rounds to 0 whatever ldexp
+   returns. */
 static void digits_bal_of(double a, int E, int s, int8_t* out, int64_t stride) {
     int64_t N = 0;
     if (isfinite(a)) {
-        double y = ldexp(fabs(a), 6 - E + 8 * (s - 1));
+        double y = ldexp(fabs(a), 7 - E + 8 * (s - 1));
         double ip = floor(y);
         N = (int64_t)ip + ((y - ip) >= 0.5 ? 1 : 0);
         if (a < 0) N = -N;
@@ -301,9 +305,9 @@ static void digits_bal_of(double a, int E, int s, int8_t* out, int64_t stride) {
     out[0] = (int8_t)N;
 }
 
-/* Fold weight of anti-diagonal d: 2^(-7d) (truncated digits) or 2^(4-8d)
+/* Fold weight of anti-diagonal d: 2^(-7d) (truncated digits) or 2^(2-8d)
    (balanced digits). */
-static double diag_weight(int d, int bal) { return ldexp(1.0, bal ? 4 - 8 * d : -7 * d); }
+static double diag_weight(int d, int bal) { return ldexp(1.0, bal ? 2 - 8 * d : -7 * d); }
 
 /* Split the vectors of an operand.  side 'A': vector v is row v of op(A)
    (nv = m); side 'B': vector v is column v of op(B) (nv = n); length k.
@@ -327,6 +331,12 @@ static void split_impl(char side, char trans, int cplx, int64_t nv, int64_t k, c
             }
         }
         int e = vec_exponent(vals, k * w);
+        if (bal) { /* the top digit must stay within [-127, 127] */
+            double mx = 0.0;
+            for (int64_t t = 0; t < k * w; ++t)
+                if (fabs(vals[t]) > mx) mx = fabs(vals[t]);
+            if (mx > 0.0 && isfinite(mx) && ldexp(mx, 7 - e) > 127.0) e = e + 1;
+        }
         E[v] = e;
         int64_t stride = nv * k * w; /* distance between digit planes */
         for (int64_t t = 0; t < k * w; ++t) {

@@ -30,39 +30,51 @@ def round_half_away(q):
 
 @pytest.mark.parametrize("s", [1, 2, 3, 5, 7, 8])
 def test_digits_are_the_rounded_value_in_base_256(s):
-    # x = 2^(E+2) sum_p d_p 2^(-8p) must be the multiple of u = 2^(E+2-8s)
-    # nearest to x (ties away from zero), with d_2..d_s in [-128, 127]
+    # x = 2^(E'+1) sum_p d_p 2^(-8p) must be the multiple of u = 2^(E'+1-8s)
+    # nearest to x (ties away from zero), with d_2..d_s in [-128, 127] and
+    # |d_1| <= 127; E' = E, or E + 1 when the row max M has M 2^(7-E) > 127
     rng = np.random.default_rng(s)
     X = rand_wide(rng, (6, 40), 30)
     X[0, :5] = [0.0, 2.0 ** -1070, -3 * 2.0 ** -1074, 1.5, -1.5]
     X[1, :4] = [1.0, -1.0, 2.0 ** -40, -(2.0 ** -40)]
     # exact ties: x / u = integer + 1/2
     X[2, 0] = 1.0
+    # a row max with M 2^(7-E) > 127 (E' = E + 1) and one exactly at 127 (no bump)
+    X[3:5, :] = np.ldexp(X[3:5, :], -40)
+    X[3, 0] = 127.5 / 128
+    X[4, 0] = -127.0 / 128
     E, dig = oracle.split("A", "N", X, s, balanced=True)
     for v in range(X.shape[0]):
+        M = Fraction(float(np.max(np.abs(X[v]))))
+        e = int(np.frexp(float(M))[1])
+        assert int(E[v]) == (e + 1 if M * Fraction(2) ** (7 - e) > 127 else e)
         for l in range(X.shape[1]):
             x = Fraction(float(X[v, l]))
             d = [int(dig[p, v, l]) for p in range(s)]
-            assert all(-128 <= t <= 127 for t in d[1:]) and abs(d[0]) <= 65
+            assert all(-128 <= t <= 127 for t in d[1:]) and abs(d[0]) <= 127
             N = sum(t * 256 ** (s - 1 - p) for p, t in enumerate(d))
-            u = Fraction(2) ** (int(E[v]) + 2 - 8 * s)
+            u = Fraction(2) ** (int(E[v]) + 1 - 8 * s)
             assert N == round_half_away(x / u), (v, l)
             assert abs(x - N * u) <= u / 2
 
 
 def test_tie_rounds_away_from_zero():
-    # row max 1.5 -> E = 1; s = 1: N = round(|x| 2^5); x = 2^-6 * 1.5 gives x*2^5 = 0.75,
-    # x = 2^-6 gives 0.5 -> 1, x = -2^-6 gives -1
-    X = np.array([[1.5, 2.0 ** -6, -(2.0 ** -6), 3 * 2.0 ** -7]])
+    # row max 1.5 -> E = 1 (1.5 * 2^6 = 96 <= 127, no bump); s = 1:
+    # N = round(|x| 2^6): 2^-7 gives 0.5 -> 1, -2^-7 gives -1, 3 * 2^-7 gives 1.5 -> 2
+    X = np.array([[1.5, 2.0 ** -7, -(2.0 ** -7), 3 * 2.0 ** -7]])
     E, dig = oracle.split("A", "N", X, 1, balanced=True)
     assert E[0] == 1
-    assert list(dig[0, 0]) == [48, 1, -1, 1]
+    assert list(dig[0, 0]) == [96, 1, -1, 2]
+    # row max 127.5 / 128 -> E = 0, 127.5 > 127: E' = 1 and N = round(|x| 2^6)
+    E, dig = oracle.split("A", "N", np.array([[127.5 / 128, 1.0 / 256]]), 1, balanced=True)
+    assert E[0] == 1
+    assert list(dig[0, 0]) == [64, 0]
 
 
 def test_small_integers_give_exact_products():
-    # integer entries |x| <= 63 with every row / column max in [32, 64): E = 6,
-    # N = x 256^(s-1), so d_1 = x and the rest are zero -- the emulated product
-    # is the exact integer product at any s, real and complex
+    # integer entries |x| <= 63 with every row / column max in [32, 64): E = 6
+    # (M 2^(7-6) <= 126, no bump), N = 2x 256^(s-1), so d_1 = 2x and the rest
+    # are zero -- the emulated product is the exact integer product at any s
     rng = np.random.default_rng(7)
     for s in (1, 3, 8):
         A = rng.integers(-63, 64, (20, 30)).astype(float)
@@ -70,7 +82,7 @@ def test_small_integers_give_exact_products():
         A[:, 0] = 40
         B[0, :] = -33
         E, dA = oracle.split("A", "N", A, s, balanced=True)
-        assert np.all(E == 6) and np.array_equal(dA[0], A) and not dA[1:].any()
+        assert np.all(E == 6) and np.array_equal(dA[0], 2 * A) and not dA[1:].any()
         assert np.array_equal(oracle.emu_gemm("N", "N", A, B, s, balanced=True), A @ B)
         Az = A + 1j * rng.integers(-63, 64, A.shape)
         Bz = B + 1j * rng.integers(-63, 64, B.shape)
@@ -79,7 +91,7 @@ def test_small_integers_give_exact_products():
 
 
 def test_one_slice_is_the_product_of_rounded_values():
-    # s = 1: each entry becomes round(x 2^(6-E)) 2^(E-6); the product is the
+    # s = 1: each entry becomes round(x 2^(7-E')) 2^(E'-7); the product is the
     # exact product of those values (small integers times powers of two)
     rng = np.random.default_rng(3)
     A = rand_wide(rng, (15, 20), 4)
@@ -88,8 +100,9 @@ def test_one_slice_is_the_product_of_rounded_values():
     def rounded(X, axis):
         mx = np.max(np.abs(X), axis=axis, keepdims=True)
         E = np.frexp(mx)[1]
-        y = X * np.exp2(6.0 - E)
-        return np.sign(y) * np.floor(np.abs(y) + 0.5) * np.exp2(E - 6.0)
+        E = E + (mx * np.exp2(7.0 - E) > 127)
+        y = X * np.exp2(7.0 - E)
+        return np.sign(y) * np.floor(np.abs(y) + 0.5) * np.exp2(E - 7.0)
 
     ref = rounded(A, 1) @ rounded(B, 0)
     assert np.array_equal(oracle.emu_gemm("N", "N", A, B, 1, balanced=True), ref)
@@ -164,12 +177,13 @@ def test_complex_is_the_real_product_over_two_k_terms(balanced, ta):
 
 
 def test_three_product_form_small_integers_exact():
-    # 3M with balanced digits: parts |x| <= 63 (their sums <= 126): from s = 3
-    # every nonzero digit pair is kept, so the complex product is exact
+    # 3M with balanced digits: parts |x| <= 63 (their sums <= 126, which need
+    # no bump): every digit below the first is zero, so the complex product is
+    # exact at any s
     rng = np.random.default_rng(17)
     A = rng.integers(-63, 64, (12, 20)) + 1j * rng.integers(-63, 64, (12, 20))
     B = rng.integers(-63, 64, (20, 9)) + 1j * rng.integers(-63, 64, (20, 9))
-    for s in (3, 5, 8):
+    for s in (1, 3, 8):
         got = oracle.emu_zgemm3("N", "N", np.asfortranarray(A), np.asfortranarray(B), s, balanced=True)
         assert np.array_equal(got, A @ B), s
 
