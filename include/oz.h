@@ -106,12 +106,14 @@ typedef struct oz_handle_s* oz_handle_t;
  *           expects to be worth about one bit per slice, Sec. 4), fixed slice
  *           counts 1..8, real products and both complex forms (a
  *           tolerance-driven, double-double or batched call, or s > 8,
- *           returns 14): N = |x| 2^(6-E+8(s-1)) rounded to the nearest
- *           integer (ties away from zero) with the sign of x, digits d_1..d_s
- *           with N = sum_p d_p 256^(s-p) and d_2..d_s in [-128, 127], so x is
- *           2^(E+2) sum_p d_p 2^(-8p) to half a unit of the last digit; the
- *           anti-diagonal weights are 2^(4-8d) and kchunk is bounded by
- *           s*kchunk*128^2 <= 2^31-1.  Complex, 4-product form: the
+ *           returns 14): the vector exponent is E' = E, or E + 1 when the
+ *           largest magnitude M has M 2^(7-E) > 127; N = |x| 2^(7-E'+8(s-1))
+ *           rounded to the nearest integer (ties away from zero) with the
+ *           sign of x; digits d_1..d_s with N = sum_p d_p 256^(s-p), all in
+ *           [-128, 127] (|d_1| <= 127), so x is 2^(E'+1) sum_p d_p 2^(-8p) to
+ *           half a unit of the last digit; the anti-diagonal weights are
+ *           2^(2-8d), the result is scaled by 2^(E'_i + F'_j), and kchunk is
+ *           bounded by s*kchunk*128^2 <= 2^31-1.  Complex, 4-product form: the
  *           real-part row (ar, -ai) takes the digits of the value -ai;
  *           3-product form: the three real products take balanced digits.
  */

@@ -13,7 +13,7 @@
 // intensity of streaming one pair at a time, and no INT32 partial ever
 // leaves the registers.  Per INT32 chunk (kchunk terms, sized so that
 // s * kchunk * 127^2 <= 2^31 - 1) the s diagonal tiles are folded into an
-// FP64 tile, from d = s+1 down to 2, each times 2^(-7d) (exact; 2^(4-8d) for
+// FP64 tile, from d = s+1 down to 2, each times 2^(-7d) (exact; 2^(2-8d) for
 // balanced digits).  The final
 // epilogue applies 2^(E_i + F_j) with ldexp and alpha/beta.
 //
@@ -38,9 +38,9 @@ typedef __attribute__((address_space(3))) void lds_void;
 typedef __attribute__((address_space(1))) const void global_cvoid;
 
 // Exponent of the weight of anti-diagonal d: 2^(-7d) for truncated digits,
-// 2^(4-8d) for balanced ones.  Every term S_d * 2^e is exact (ldexp of an
+// 2^(2-8d) for balanced ones.  Every term S_d * 2^e is exact (ldexp of an
 // INT32 value far from the FP64 range limits).
-__device__ __forceinline__ int diag_exp(int d, int bal) { return bal ? 4 - 8 * d : -7 * d; }
+__device__ __forceinline__ int diag_exp(int d, int bal) { return bal ? 2 - 8 * d : -7 * d; }
 
 // Fold the live INT32 diagonal tiles into the FP64 tile, from the top
 // (d = DD + 2 = S + 1) down to d = DLO + 2; acc[i] holds diagonal DLO + i.

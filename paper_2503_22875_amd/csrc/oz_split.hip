@@ -95,14 +95,26 @@ __device__ __forceinline__ int digit_of(double x, int E, uint64_t W, int p) {
     return __double_as_longlong(x) < 0 ? -t : t;
 }
 
-// Balanced (round-to-nearest) digits, s <= 8: N = |x| * 2^(6 - E + 8(s-1))
-// rounded to the nearest integer (ties away from zero) with the sign of x --
-// one shift of the significand, |x| < 2^E keeping N below 2^62 -- then the
-// s digits are N's bytes read as signed int8 from the lowest up, each removed
-// before the next (N = (N - d) / 256), the top digit being what remains.
+// Balanced (round-to-nearest) digits, s <= 8.  The vector exponent is E' =
+// E, or E + 1 when its largest magnitude M has M * 2^(7-E) > 127 (so that the
+// top digit stays within [-127, 127]); N = |x| * 2^(7 - E' + 8(s-1)) rounded to
+// the nearest integer (ties away from zero) with the sign of x -- one shift of
+// the significand, N below 2^63 -- then the s digits are N's bytes read as
+// signed int8 from the lowest up, each removed before the next
+// (N = (N - d) / 256), the top digit being what remains.
+__device__ __forceinline__ int balanced_bump(uint64_t maxb, int E) {
+    // M * 2^(7-E) > 127 with M = Mi * 2^(e_eff - 1075): Mi > 127 * 2^(sh0 - 7)
+    if (maxb == 0 || maxb >= kInfBits) return 0;
+    const Sig g = sig_of(__longlong_as_double(static_cast<long long>(maxb)), E);
+    // sh0 is 53 for a normal M and its bit length for a subnormal one; below 7,
+    // M * 2^(7-E) = Mi * 2^(7-sh0) is an integer below 128, so at most 127
+    if (g.sh0 < 7) return 0;
+    return g.M > (127ull << (g.sh0 - 7)) ? 1 : 0;
+}
+
 __device__ __forceinline__ int64_t balanced_int(double x, int E, int s) {
     const Sig g = sig_of(x, E);
-    const int sh = g.sh0 - 6 - 8 * (s - 1);
+    const int sh = g.sh0 - 7 - 8 * (s - 1);
     uint64_t n;
     if (sh <= 0)
         n = g.M << (-sh);
@@ -206,6 +218,8 @@ __device__ __forceinline__ void digits_body(const OperandView& op, const uint64_
     int32_t ex = 0;
     if (live) ex = exponent_of_max(maxbits[v]);
     const bool bad = ex == kNonFiniteExp;
+    if constexpr (BAL)
+        if (live && !bad) ex += balanced_bump(maxbits[v], ex);
     if (live && step == 0 && sub == 0) E[v] = ex;
 
     // 8 doubles: real -> elements l = t0 .. t0+7; complex -> l = t0/2 .. t0/2+3 (re, im)
@@ -429,6 +443,8 @@ __global__ __launch_bounds__(256) void digits3_kernel(OperandView op, SliceLayou
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
         if (live) ex[q] = exponent_of_max(o.maxbits[q][v]);
+        if constexpr (BAL)
+            if (live && ex[q] != kNonFiniteExp) ex[q] += balanced_bump(o.maxbits[q][v], ex[q]);
         if (live && step == 0 && sub == 0) o.E[q][v] = ex[q];
     }
     // the 8 complex elements of this thread, read once
