@@ -100,8 +100,7 @@ __device__ __forceinline__ int digit_of(double x, int E, uint64_t W, int p) {
 // top digit stays within [-127, 127]); N = |x| * 2^(7 - E' + 8(s-1)) rounded to
 // the nearest integer (ties away from zero) with the sign of x -- one shift of
 // the significand, N below 2^63 -- then the s digits are N's bytes read as
-// signed int8 from the lowest up, each removed before the next
-// (N = (N - d) / 256), the top digit being what remains.
+// signed digits (see balanced_digit), the top digit taking the rest.
 __device__ __forceinline__ int balanced_bump(uint64_t maxb, int E) {
     // M * 2^(7-E) > 127 with M = Mi * 2^(e_eff - 1075): Mi > 127 * 2^(sh0 - 7)
     if (maxb == 0 || maxb >= kInfBits) return 0;
@@ -125,12 +124,18 @@ __device__ __forceinline__ int64_t balanced_int(double x, int E, int s) {
     return g.neg ? -static_cast<int64_t>(n) : static_cast<int64_t>(n);
 }
 
-// Peel the lowest balanced digit off N (plane p = s-1 first, then down to 1;
-// plane 0 is the remaining N itself).
-__device__ __forceinline__ int peel_digit(int64_t& N) {
-    const int d = static_cast<int>(static_cast<int8_t>(static_cast<uint8_t>(N & 255)));
-    N = (N - d) >> 8;  // exact: N - d is a multiple of 256
-    return d;
+// The digits of N all at once: with C = 0x80...80 over the s - 1 low bytes,
+// N + C = sum_{p>=2} (d_p + 128) 256^(s-p) + d_1 256^(s-1) with every
+// d_p + 128 in [0, 255], so plane p >= 1 (0-based) is byte s-1-p of N + C
+// minus 128 and plane 0 is N + C shifted right by 8(s-1) (arithmetic).
+// |N| <= 127 * 256^(s-1) keeps N + C below 2^63.
+__device__ __forceinline__ int64_t balanced_bias(int s) {
+    return static_cast<int64_t>(0x0080808080808080ull >> (8 * (8 - s)));
+}
+
+__device__ __forceinline__ int balanced_digit(int64_t nb, int p, int s) {
+    if (p == 0) return static_cast<int>(nb >> (8 * (s - 1)));
+    return static_cast<int>((static_cast<uint64_t>(nb) >> (8 * (s - 1 - p))) & 255u) - 128;
 }
 
 __global__ void zero_u64_kernel(uint64_t* p, int64_t n) {
@@ -243,27 +248,29 @@ __device__ __forceinline__ void digits_body(const OperandView& op, const uint64_
         }
     }
     if constexpr (BAL) {
-        // all s planes at once (p_lo = 0, p_hi = s), lowest digit first
+        // all s planes at once (p_lo = 0, p_hi = s)
         const int s = lay.s;
         if (CPLX && SIDE_A) {
             const int64_t r_re = 32 * (v >> 4) + 16 * ((v >> 3) & 1) + (v & 7);
             const int64_t r_im = r_re + 8;
             if (r_re >= lay.rows_pad) return;
             // real-part row (ar, -ai): the digits of the value -ai are those of -N(ai)
+            const int64_t bias = balanced_bias(s);
             int64_t nr[4], ni[4], nn[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                nr[e] = balanced_int(x[2 * e], ex, s);
-                ni[e] = balanced_int(x[2 * e + 1], ex, s);
-                nn[e] = -ni[e];
+                const int64_t r = balanced_int(x[2 * e], ex, s), i = balanced_int(x[2 * e + 1], ex, s);
+                nr[e] = r + bias;
+                ni[e] = i + bias;
+                nn[e] = bias - i;
             }
-            for (int p = s - 1; p >= 0; --p) {
+            for (int p = 0; p < s; ++p) {
                 int dre[8], dim[8];
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const int ar = p > 0 ? peel_digit(nr[e]) : static_cast<int>(nr[e]);
-                    const int ai = p > 0 ? peel_digit(ni[e]) : static_cast<int>(ni[e]);
-                    const int an = p > 0 ? peel_digit(nn[e]) : static_cast<int>(nn[e]);
+                    const int ar = balanced_digit(nr[e], p, s);
+                    const int ai = balanced_digit(ni[e], p, s);
+                    const int an = balanced_digit(nn[e], p, s);
                     dre[2 * e] = ar;
                     dre[2 * e + 1] = an;
                     dim[2 * e] = ai;
@@ -274,13 +281,14 @@ __device__ __forceinline__ void digits_body(const OperandView& op, const uint64_
             }
         } else {
             if (v >= lay.rows_pad) return;
+            const int64_t bias = balanced_bias(s);
             int64_t nv8[8];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) nv8[e] = balanced_int(x[e], ex, s);
-            for (int p = s - 1; p >= 0; --p) {
+            for (int e = 0; e < 8; ++e) nv8[e] = balanced_int(x[e], ex, s) + bias;
+            for (int p = 0; p < s; ++p) {
                 int d[8];
 #pragma unroll
-                for (int e = 0; e < 8; ++e) d[e] = p > 0 ? peel_digit(nv8[e]) : static_cast<int>(nv8[e]);
+                for (int e = 0; e < 8; ++e) d[e] = balanced_digit(nv8[e], p, s);
                 *reinterpret_cast<uint64_t*>(slices + slice_off(t0, p, v, s, lay.rows_pad)) = pack8(d);
             }
         }
@@ -465,14 +473,15 @@ __global__ __launch_bounds__(256) void digits3_kernel(OperandView op, SliceLayou
         for (int e = 0; e < 8; ++e)  // part 2 is the FP64 sum of the two parts (as in the scan)
             x[e] = bad ? 0.0 : (q == 0 ? re[e] : q == 1 ? im[e] : re[e] + im[e]);
         if constexpr (BAL) {
-            // balanced digits, lowest first (no part is negated in this form)
+            // balanced digits (no part is negated in this form)
+            const int64_t bias = balanced_bias(lay.s);
             int64_t nv8[8];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) nv8[e] = balanced_int(x[e], ex[q], lay.s);
-            for (int p = lay.s - 1; p >= 0; --p) {
+            for (int e = 0; e < 8; ++e) nv8[e] = balanced_int(x[e], ex[q], lay.s) + bias;
+            for (int p = 0; p < lay.s; ++p) {
                 int d[8];
 #pragma unroll
-                for (int e = 0; e < 8; ++e) d[e] = p > 0 ? peel_digit(nv8[e]) : static_cast<int>(nv8[e]);
+                for (int e = 0; e < 8; ++e) d[e] = balanced_digit(nv8[e], p, lay.s);
                 *reinterpret_cast<uint64_t*>(o.slices[q] + slice_off(t0, p, v, lay.s, lay.rows_pad)) = pack8(d);
             }
             continue;
