@@ -111,14 +111,15 @@ def _trsm_upper(Ur, Ui, Br, Bi):
         Br[i], Bi[i] = _cmul(accr, acci, rr, ri)
 
 
-def _emu_update(C, A, B, s, kc):
+def _emu_update(C, A, B, s, kc, balanced=False):
     """C <- C - A B as the emulated product (alpha = -1, beta = 1)."""
     return emu_gemm("N", "N", np.asfortranarray(A), np.asfortranarray(B), s, alpha=-1.0, beta=1.0,
-                    C=np.asfortranarray(C), kc=kc)
+                    C=np.asfortranarray(C), kc=kc, balanced=balanced)
 
 
-def getrf(A, nb, s, kc=None):
-    """LU with partial pivoting of the square complex A; returns (LU, piv, info)."""
+def getrf(A, nb, s, kc=None, balanced=False):
+    """LU with partial pivoting of the square complex A; returns (LU, piv, info).
+    balanced: the emulated products take balanced digits."""
     A = np.asarray(A, dtype=np.complex128)
     n = A.shape[0]
     Re, Im = A.real.copy(), A.imag.copy()
@@ -138,12 +139,12 @@ def getrf(A, nb, s, kc=None):
             C = Re[below, sr] + 1j * Im[below, sr]
             L21 = Re[below, sl] + 1j * Im[below, sl]
             U12 = Re[sl, sr] + 1j * Im[sl, sr]
-            C = _emu_update(C, L21, U12, s, kc)
+            C = _emu_update(C, L21, U12, s, kc, balanced)
             Re[below, sr], Im[below, sr] = C.real, C.imag
     return np.asfortranarray(Re + 1j * Im), piv, info[0]
 
 
-def getri(LU, piv, nb, s, kc=None):
+def getri(LU, piv, nb, s, kc=None, balanced=False):
     """Inverse of the matrix whose factorization getrf returned."""
     LU = np.asarray(LU, dtype=np.complex128)
     n = LU.shape[0]
@@ -156,14 +157,14 @@ def getri(LU, piv, nb, s, kc=None):
         sl = slice(j0, j0 + b)
         if j0 > 0:
             C = Xr[sl] + 1j * Xi[sl]
-            C = _emu_update(C, LU[sl, :j0], Xr[:j0] + 1j * Xi[:j0], s, kc)
+            C = _emu_update(C, LU[sl, :j0], Xr[:j0] + 1j * Xi[:j0], s, kc, balanced)
             Xr[sl], Xi[sl] = C.real, C.imag
         _trsm_lower_unit(Lr[sl, sl], Li[sl, sl], Xr[sl], Xi[sl])
     for j0, b in reversed(blocks):  # backward: U X = Y
         sl = slice(j0, j0 + b)
         if j0 + b < n:
             C = Xr[sl] + 1j * Xi[sl]
-            C = _emu_update(C, LU[sl, j0 + b:], Xr[j0 + b:] + 1j * Xi[j0 + b:], s, kc)
+            C = _emu_update(C, LU[sl, j0 + b:], Xr[j0 + b:] + 1j * Xi[j0 + b:], s, kc, balanced)
             Xr[sl], Xi[sl] = C.real, C.imag
         _trsm_upper(Lr[sl, sl], Li[sl, sl], Xr[sl], Xi[sl])
     return np.asfortranarray(Xr + 1j * Xi)

@@ -142,3 +142,23 @@ def test_inverse_error_falls_with_slices():
     for a, b in zip(errs, errs[1:]):
         assert b < a / 20
     assert errs[-1] < 1e-10
+
+
+def test_balanced_products_gain_about_one_bit_per_slice():
+    # with balanced digits every one of the s slices carries one bit more, so
+    # the inverse's error shrinks against truncated digits at the same s by a
+    # factor near 2^(s-1), growing with s
+    rng = np.random.default_rng(23)
+    n = 64
+    A = cmat(rng, n)
+    Xr = np.linalg.inv(A)
+
+    def err(s, bal):
+        LU, piv, _ = lu.getrf(A, 16, s, balanced=bal)
+        return np.abs(lu.getri(LU, piv, 16, s, balanced=bal) - Xr).max() / np.abs(Xr).max()
+
+    gains = [err(s, False) / err(s, True) for s in (3, 4, 5, 6)]
+    for s, g in zip((3, 4, 5, 6), gains):
+        assert g >= 2 ** (s - 2), (s, g)
+    assert gains == sorted(gains)
+
