@@ -531,6 +531,23 @@ def bench_inv(args):
                "err_vs_native": float("%.3e" % err), "resid": float("%.3e" % resid)}
         print(json.dumps(row), flush=True)
         rows.append(row)
+    for s in [int(v) for v in args.inv_balanced.split(",") if v]:
+        p = oz.prec(s, digits=1)
+
+        def run_bal():
+            dA.copy_(dA0)
+            oz.oz_zgetrf(h, n, dA, n, ipiv, nb, p)
+            oz.oz_zgetri(h, n, dA, n, ipiv, dX, n, nbi, p)
+
+        run_bal()
+        X = torch.view_as_complex(dX.view(n, n, 2)).T
+        err = float((X - Xr).abs().max() / Xr.abs().max())
+        resid = float((Ad @ X - eye).abs().max())
+        ms = _time_ms(run_bal, stream, steps, 1)
+        row = {"s": s, "digits": "balanced", "ms": round(ms, 3), "tflops_eff": round(flops / (ms * 1e-3) / 1e12, 2),
+               "err_vs_native": float("%.3e" % err), "resid": float("%.3e" % resid)}
+        print(json.dumps(row), flush=True)
+        rows.append(row)
     for tol in [float(v) for v in args.inv_tols.split(",") if v]:
         p = oz.prec(0, tol=tol)
 
@@ -603,6 +620,8 @@ def main():
     ap.add_argument("--nb", type=int, default=128, help="panel width of the inversion workload (getrf)")
     ap.add_argument("--nb-inv", type=int, default=256, help="block rows of the inversion workload's solves (getri)")
     ap.add_argument("--inv-slices", default="3,4,5,6,7,8,14")
+    ap.add_argument("--inv-balanced", default="4,5,6,7",
+                    help="inversion rows with balanced digits in every product (slice counts)")
     ap.add_argument("--inv-tols", default="1e-8,1e-10,1e-12",
                     help="tolerance-driven rows of the inversion workload (each product picks its own s)")
     ap.add_argument("--select-data", default="normal,spread")

@@ -99,6 +99,26 @@ def test_getrf_matches_lapack_pivots_beyond_4096_rows(oz, handle):
     assert np.abs(LU - lu_ref).max() / np.abs(lu_ref).max() < 1e-11
 
 
+@pytest.mark.parametrize("n,nb,s", [(100, 32, 5), (257, 64, 6), (300, 0, 7)])
+def test_getrf_getri_balanced_bit_exact(oz, handle, n, nb, s):
+    # balanced digits in every emulated product of the factorisation and solves
+    rng = np.random.default_rng(5000 + n + s)
+    A = cmat(rng, n)
+    dA, lda = to_dev(A, n + 2)
+    ipiv = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+    p = oz.prec(s, digits=1)
+    info = oz.oz_zgetrf(handle, n, dA, lda, ipiv, nb, p)
+    torch.cuda.synchronize()
+    LU_ref, piv_ref, info_ref = lu.getrf(A, nb or 128, s, balanced=True)
+    assert info == info_ref == 0
+    assert np.array_equal(ipiv.cpu().numpy(), piv_ref)
+    assert np.array_equal(from_dev(dA, n, n, lda), LU_ref)
+    dX, ldx = to_dev(np.zeros((n, n), complex, order="F"), n + 1)
+    oz.oz_zgetri(handle, n, dA, lda, ipiv, dX, ldx, nb, p)
+    torch.cuda.synchronize()
+    assert np.array_equal(from_dev(dX, n, n, ldx), lu.getri(LU_ref, piv_ref, nb or 256, s, balanced=True))
+
+
 def test_getri_from_oracle_factors(oz, handle):
     # the inverse step alone, fed the oracle's factors and pivots
     rng = np.random.default_rng(77)
