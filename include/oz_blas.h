@@ -16,6 +16,9 @@
  *   "fp64_int8_<s>"        emulation with s slices, 1 <= s <= 18 (default s = 7);
  *   "fp64_int8_tol<tol>"   tolerance-driven emulation (oz_prec_t.tol = tol,
  *                          smax 12), e.g. "fp64_int8_tol1e-12";
+ *   "fp64_int8_bal<s>"     emulation with s balanced (round-to-nearest) digits,
+ *                          1 <= s <= 8 (oz_prec_t.digits = 1), e.g.
+ *                          "fp64_int8_bal6";
  *   "dgemm"                native FP64 on the GPU (rocBLAS), for comparison.
  * OZ_ZMODE = 3 or 4 selects the complex form of zgemm_ in the emulated modes
  * (default 4, the library default); OZ_DEVICE selects the GPU (default 0).
@@ -69,8 +72,9 @@ typedef struct {
     double compute_ms;       /* time in the emulated (or native) product */
     int32_t last_info;       /* 0, or the illegal parameter of the last call */
     int32_t last_slices;     /* slice count used by the last emulated call */
-    int32_t mode;            /* 0 = native FP64, 1 = fixed s, 2 = tolerance-driven */
-    int32_t slices;          /* fixed s of mode 1 */
+    int32_t mode;            /* 0 = native FP64, 1 = fixed s, 2 = tolerance-driven,
+                                3 = fixed s with balanced digits */
+    int32_t slices;          /* fixed s of modes 1 and 3 */
     double tol;              /* tolerance of mode 2 */
 } oz_blas_stats_t;
 

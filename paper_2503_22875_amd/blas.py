@@ -70,7 +70,7 @@ def zgemm_(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc):
 
 
 def oz_blas_set_mode(mode):
-    """'fp64_int8_<s>', 'fp64_int8_tol<tol>' or 'dgemm'; False when not a mode."""
+    """'fp64_int8_<s>', 'fp64_int8_bal<s>', 'fp64_int8_tol<tol>' or 'dgemm'; False when not a mode."""
     return _lib.oz_blas_set_mode(mode.encode()) == 0
 
 

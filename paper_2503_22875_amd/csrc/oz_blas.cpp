@@ -21,7 +21,7 @@
 
 namespace {
 
-enum Mode { kNative = 0, kFixed = 1, kTol = 2 };
+enum Mode { kNative = 0, kFixed = 1, kTol = 2, kBalanced = 3 };
 
 struct Config {
     int mode = kFixed;
@@ -39,7 +39,15 @@ bool parse_mode(const char* s, Config* c) {
         c->mode = kNative;
         return true;
     }
-    const std::string tol_prefix = "fp64_int8_tol", fix_prefix = "fp64_int8_";
+    const std::string tol_prefix = "fp64_int8_tol", bal_prefix = "fp64_int8_bal", fix_prefix = "fp64_int8_";
+    if (m.compare(0, bal_prefix.size(), bal_prefix) == 0) {
+        char* end = nullptr;
+        const long v = std::strtol(m.c_str() + bal_prefix.size(), &end, 10);
+        if (!end || *end != '\0' || end == m.c_str() + bal_prefix.size() || v < 1 || v > 8) return false;
+        c->mode = kBalanced;
+        c->slices = static_cast<int>(v);
+        return true;
+    }
     if (m.compare(0, tol_prefix.size(), tol_prefix) == 0) {
         char* end = nullptr;
         const double t = std::strtod(m.c_str() + tol_prefix.size(), &end);
@@ -346,8 +354,9 @@ void gemm(const char* name, int cplx, const char* transa, const char* transb, co
     } else {
         oz_prec_t p;
         std::memset(&p, 0, sizeof(p));
-        if (c.cfg.mode == kFixed) {
+        if (c.cfg.mode == kFixed || c.cfg.mode == kBalanced) {
             p.slices = c.cfg.slices;
+            p.digits = c.cfg.mode == kBalanced ? 1 : 0;
         } else {
             p.slices = 0;
             p.tol = c.cfg.tol;

@@ -37,8 +37,11 @@ def test_mode_strings(blas):
     st = blas.oz_blas_stats()
     assert st.mode == 2 and st.tol == 1e-10
     assert blas.oz_blas_set_mode("dgemm") and blas.oz_blas_stats().mode == 0
+    assert blas.oz_blas_set_mode("fp64_int8_bal6")
+    st = blas.oz_blas_stats()
+    assert st.mode == 3 and st.slices == 6
     for bad in ("fp64_int8_0", "fp64_int8_19", "fp64_int8_", "fp64_int8_tol", "fp64_int8_tol-1", "int8", "",
-                "fp64_int8_7x"):
+                "fp64_int8_7x", "fp64_int8_bal", "fp64_int8_bal0", "fp64_int8_bal9", "fp64_int8_bal6x"):
         assert not blas.oz_blas_set_mode(bad), bad
     assert blas.oz_blas_set_mode("fp64_int8_7") and blas.oz_blas_stats().mode == 1
 

@@ -67,6 +67,24 @@ def test_zgemm_host_bit_exact(blas, ta, tb):
     assert np.array_equal(Cp[:m], want)
 
 
+@pytest.mark.parametrize("s", [4, 6])
+def test_balanced_mode_bit_exact(blas, s):
+    # OZ_COMPUTE_MODE fp64_int8_bal<s>: balanced digits in dgemm_ and zgemm_
+    rng = np.random.default_rng(40 + s)
+    m, n, k = 100, 60, 130
+    A, B, C0 = wide(rng, (m, k), 12), wide(rng, (k, n), 12), wide(rng, (m, n), 4)
+    Cp = padded(C0, 2)
+    assert blas.oz_blas_set_mode("fp64_int8_bal%d" % s)
+    print("blas balanced", s, flush=True)
+    blas.dgemm_("N", "T", m, n, k, 1.5, A, m, np.asfortranarray(B.T), n, -0.5, Cp, Cp.shape[0])
+    assert np.array_equal(Cp[:m], oracle.emu_gemm("N", "N", A, B, s, alpha=1.5, beta=-0.5, C=C0, balanced=True))
+    assert blas.oz_blas_stats().mode == 3
+    Az, Bz = wide(rng, (m, k), 8, True), wide(rng, (k, n), 8, True)
+    Cz = np.zeros((m, n), complex, order="F")
+    blas.zgemm_("N", "N", m, n, k, 1.0, Az, m, Bz, k, 0.0, Cz, m)
+    assert np.array_equal(Cz, oracle.emu_gemm("N", "N", Az, Bz, s, balanced=True))
+
+
 def test_device_pointers_used_in_place(blas):
     rng = np.random.default_rng(5)
     m, n, k = 100, 80, 120
