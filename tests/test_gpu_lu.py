@@ -119,6 +119,22 @@ def test_getrf_getri_balanced_bit_exact(oz, handle, n, nb, s):
     assert np.array_equal(from_dev(dX, n, n, ldx), lu.getri(LU_ref, piv_ref, nb or 256, s, balanced=True))
 
 
+def test_getrf_matches_lapack_pivots_beyond_8192_rows(oz, handle):
+    # the first panel has more rows than the register panel holds (8192): it
+    # runs the global-memory panel kernel; s = 14 as above
+    import scipy.linalg
+    rng = np.random.default_rng(8300)
+    n, nb = 8300, 128
+    A = cmat(rng, n)
+    print("n=%d nb=%d s=14" % (n, nb), flush=True)
+    dA, lda, ipiv, info = gpu_getrf(oz, handle, A, nb, 14, pad=0)
+    assert info == 0
+    lu_ref, piv_ref = scipy.linalg.lu_factor(A)
+    assert np.array_equal(ipiv.cpu().numpy(), piv_ref)
+    LU = from_dev(dA, n, n, lda)
+    assert np.abs(LU - lu_ref).max() / np.abs(lu_ref).max() < 1e-11
+
+
 def test_getri_from_oracle_factors(oz, handle):
     # the inverse step alone, fed the oracle's factors and pivots
     rng = np.random.default_rng(77)
