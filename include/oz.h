@@ -104,9 +104,11 @@ typedef struct oz_handle_s* oz_handle_t;
  *  digits : 0 = truncated digits (the default, as described above).
  *           1 = balanced, round-to-nearest digits (the rounding the paper
  *           expects to be worth about one bit per slice, Sec. 4), fixed slice
- *           counts 1..8, real products and both complex forms (a
- *           tolerance-driven, double-double or batched call, or s > 8,
- *           returns 14): the vector exponent is E' = E, or E + 1 when the
+ *           counts 1..8, real products and both complex forms, and
+ *           tolerance-driven calls (smax capped at 8; the start is one slice
+ *           below the rule's or the selector's; growth splits again at s + 1
+ *           and recomputes the sums, since the digits depend on s); a
+ *           double-double or batched call, or s > 8, returns 14: the vector exponent is E' = E, or E + 1 when the
  *           largest magnitude M has M 2^(7-E) > 127; N = |x| 2^(7-E'+8(s-1))
  *           rounded to the nearest integer (ties away from zero) with the
  *           sign of x; digits d_1..d_s with N = sum_p d_p 256^(s-p), all in

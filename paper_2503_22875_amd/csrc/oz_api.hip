@@ -380,6 +380,7 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
             if (!(tol > 0.0)) return 14;
             if (prec->smax) smax = prec->smax;
             if (smax < 1 || smax > OZ_MAX_SLICES) return 14;
+            if (bal && smax > kMaxBalancedSlices) smax = kMaxBalancedSlices;
             if (prec->sstart < 0 || prec->sstart > smax) return 14;
             if (prec->selector != 0 && prec->selector != 1) return 14;
             if (prec->selector == 1 && prec->sstart == 0 && !oz_mlp_valid(h->selector)) return OZ_ERR_ARG;
@@ -390,8 +391,8 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
         kernel = prec->kernel;
     }
     if (c_lo && (tol_mode || (cplx && prec && prec->zmode == 3))) return 14;  // fixed s, 4-product form
-    // balanced digits: fixed s <= 8, FP64 results
-    if (bal && (tol_mode || s > kMaxBalancedSlices || c_lo)) return 14;
+    // balanced digits: s <= 8, FP64 results
+    if (bal && (s > kMaxBalancedSlices || c_lo)) return 14;
     const int s_plan = tol_mode ? smax : s;  // largest slice count this call may use
     if (kc < 0 || kc % 64 != 0 || (kc > 0 && kc > kchunk_bound(s_plan, bal))) return 14;
     if (kc == 0) kc = kchunk_bound(s_plan, bal);
@@ -502,6 +503,10 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
                              &s);
             if (st) return st;
         }
+        // the rule and the learned start are calibrated on truncated digits;
+        // balanced digits reach the same error with about one slice fewer
+        if (bal && prec->sstart == 0 && s > 1) --s;
+        if (s > smax) s = smax;
         // (2) digit planes 1..s, then emulate at s into the raw FP64 sums
         if (oz::launch_digits(va, maxa, p.la, EA, SA, h->stream, 0, s) != hipSuccess ||
             oz::launch_digits(vb, maxb, p.lb, FB, SB, h->stream, 0, s) != hipSuccess)
@@ -539,6 +544,19 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
                 return OZ_ERR_HIP;
             eps = nrm[1] > 0.0 ? std::sqrt(nrm[0] / nrm[1]) : std::sqrt(nrm[0]);
             if (!(eps > tol) || s >= smax) break;  // NaN (non-finite input) also stops
+            if (bal) {
+                // balanced digits depend on s: split again at s + 1 and
+                // recompute the raw sums (no incremental growth)
+                if (oz::launch_digits(va, maxa, p.la, EA, SA, h->stream, 0, s + 1) != hipSuccess ||
+                    oz::launch_digits(vb, maxb, p.lb, FB, SB, h->stream, 0, s + 1) != hipSuccess)
+                    return OZ_ERR_HIP;
+                g.s = s + 1;
+                g.mode = oz::kRawWrite;
+                if (oz::launch_gemm(g, h->stream) != hipSuccess) return OZ_ERR_HIP;
+                ++s;
+                ++fallbacks;
+                continue;
+            }
             // digit plane s + 1, then the anti-diagonal s + 2
             if (oz::launch_digits(va, maxa, p.la, EA, SA, h->stream, s, s + 1) != hipSuccess ||
                 oz::launch_digits(vb, maxb, p.lb, FB, SB, h->stream, s, s + 1) != hipSuccess)

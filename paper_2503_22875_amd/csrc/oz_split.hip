@@ -248,8 +248,9 @@ __device__ __forceinline__ void digits_body(const OperandView& op, const uint64_
         }
     }
     if constexpr (BAL) {
-        // all s planes at once (p_lo = 0, p_hi = s)
-        const int s = lay.s;
+        // all p_hi planes at once (p_lo = 0): the digits of an s = p_hi split
+        // (a tolerance-driven plan lays out more planes than it fills)
+        const int s = p_hi;
         if (CPLX && SIDE_A) {
             const int64_t r_re = 32 * (v >> 4) + 16 * ((v >> 3) & 1) + (v & 7);
             const int64_t r_im = r_re + 8;
@@ -276,8 +277,8 @@ __device__ __forceinline__ void digits_body(const OperandView& op, const uint64_
                     dim[2 * e] = ai;
                     dim[2 * e + 1] = ar;
                 }
-                *reinterpret_cast<uint64_t*>(slices + slice_off(t0, p, r_re, s, lay.rows_pad)) = pack8(dre);
-                *reinterpret_cast<uint64_t*>(slices + slice_off(t0, p, r_im, s, lay.rows_pad)) = pack8(dim);
+                *reinterpret_cast<uint64_t*>(slices + slice_off(t0, p, r_re, lay.s, lay.rows_pad)) = pack8(dre);
+                *reinterpret_cast<uint64_t*>(slices + slice_off(t0, p, r_im, lay.s, lay.rows_pad)) = pack8(dim);
             }
         } else {
             if (v >= lay.rows_pad) return;
@@ -289,7 +290,7 @@ __device__ __forceinline__ void digits_body(const OperandView& op, const uint64_
                 int d[8];
 #pragma unroll
                 for (int e = 0; e < 8; ++e) d[e] = balanced_digit(nv8[e], p, s);
-                *reinterpret_cast<uint64_t*>(slices + slice_off(t0, p, v, s, lay.rows_pad)) = pack8(d);
+                *reinterpret_cast<uint64_t*>(slices + slice_off(t0, p, v, lay.s, lay.rows_pad)) = pack8(d);
             }
         }
         return;
@@ -591,8 +592,8 @@ hipError_t launch_digits(const OperandView& op, const uint64_t* maxbits, const S
     // blocks along vectors: 64 vectors each (64 complex rows = 128 slice rows for two_row)
     const int64_t vec_cover = two_row ? lay.rows_pad / 2 : lay.rows_pad;
     dim3 grid(static_cast<unsigned>(lay.kpad / kStep), static_cast<unsigned>((vec_cover + 63) / 64));
-    // balanced digits depend on s: all planes in one pass
-    if (lay.bal && (p_lo != 0 || p_hi != lay.s)) return hipErrorInvalidValue;
+    // balanced digits depend on s: planes 0 .. p_hi - 1 of an s = p_hi split, in one pass
+    if (lay.bal && p_lo != 0) return hipErrorInvalidValue;
 #define OZ_DIG(LC, CP, SA, BL) \
     hipLaunchKernelGGL((digits_kernel<LC, CP, SA, BL>), grid, dim3(256), 0, st, op, maxbits, lay, E, slices, p_lo, \
                        p_hi)

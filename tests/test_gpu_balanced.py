@@ -152,7 +152,7 @@ def test_balanced_rejections(oz, handle):
         return oz.oz_dgemm(handle, "N", "N", 4, 4, 4, 1.0, d, 4, d, 4, 0.0, d, 4, p, check=False)
 
     assert dg(oz.prec(9, digits=1)) == 14
-    assert dg(oz.prec(0, tol=1e-10, digits=1)) == 14
+    assert dg(oz.prec(0, tol=1e-10, digits=1)) == 0  # tolerance-driven calls take balanced digits
     assert dg(oz.prec(7, digits=2)) == 14
     assert dg(oz.prec(7, digits=1, kchunk=18752)) == 14  # beyond s * kc * 128^2 <= 2^31 - 1
     assert dg(oz.prec(7, digits=1, kchunk=18688)) == 0
@@ -231,4 +231,49 @@ def test_zgemm_3m_balanced_full_size(oz, handle):
     err = np.linalg.norm(C - N) / np.linalg.norm(N)
     print("err 3M balanced %.3e" % err, flush=True)
     assert err < 3e-14
+
+
+def run_tol_bal(oz, handle, A, B, tol, sstart=0):
+    cplx = np.iscomplexobj(A)
+    m, k = A.shape
+    n = B.shape[1]
+    dA, lda = to_dev(A)
+    dB, ldb = to_dev(B)
+    dC, ldc = to_dev(np.zeros((m, n), A.dtype, order="F"))
+    fn = oz.oz_zgemm if cplx else oz.oz_dgemm
+    st, rep = fn(handle, "N", "N", m, n, k, 1.0, dA, lda, dB, ldb, 0.0, dC, ldc,
+                 oz.prec(0, tol=tol, sstart=sstart, digits=1), report=True)
+    torch.cuda.synchronize()
+    return from_dev(dC, m, n, ldc), rep
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("tol", [1e-6, 1e-10, 1e-13])
+def test_balanced_tolerance_mode(oz, handle, cplx, tol):
+    # the result is the fresh balanced product at the final s (chunks of the
+    # smax = 8 plan), and the tolerance is met
+    rng = np.random.default_rng(60 + cplx + int(-np.log10(tol)))
+    A, B = wide(rng, (150, 200), 6, cplx), wide(rng, (200, 120), 6, cplx)
+    got, rep = run_tol_bal(oz, handle, A, B, tol)
+    s = rep.slices_used
+    print("balanced tol %g: s %d, fallbacks %d, resid %.3g" % (tol, s, rep.fallbacks, rep.resid_est), flush=True)
+    assert 1 <= s <= 8
+    want = oracle.emu_gemm("N", "N", A, B, s, kc=oracle.kchunk(8, cplx, balanced=True), balanced=True)
+    assert np.array_equal(got, want)
+    ref = oracle.gemm_dd("N", "N", A, B)
+    wa = np.maximum(np.abs(A.real), np.abs(A.imag)).max(1)
+    wb = np.maximum(np.abs(B.real), np.abs(B.imag)).max(0)
+    assert oracle.weighted_error(got, ref, wa, wb) <= 2 * tol
+
+
+def test_balanced_tolerance_growth_from_a_low_start(oz, handle):
+    # each growth step splits again and recomputes: the result is the fresh
+    # balanced product at the final s, not an incremental sum
+    rng = np.random.default_rng(71)
+    A, B = wide(rng, (100, 160), 4, True), wide(rng, (160, 90), 4, True)
+    got, rep = run_tol_bal(oz, handle, A, B, 1e-12, sstart=2)
+    assert rep.fallbacks >= 3 and rep.slices_used == 2 + rep.fallbacks
+    want = oracle.emu_gemm("N", "N", A, B, rep.slices_used, kc=oracle.kchunk(8, True, balanced=True),
+                           balanced=True)
+    assert np.array_equal(got, want)
 
