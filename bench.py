@@ -351,7 +351,8 @@ def bench_sweep(args):
 
 def bench_wide_tol(args):
     """Tolerance-driven wide-range DGEMM: m = n = 4096, k = 8192, rows of A and
-    columns of B scaled by 10^U(-8, 8), tol 1e-6, 1e-10, 1e-14 (smax 12).
+    columns of B scaled by 10^U(-8, 8), tol 1e-6, 1e-10, 1e-14 (smax 12;
+    --wide-digits 1: balanced digits, smax 8).
     Per tolerance: time of the whole call (selection, split, products, checks,
     growth), the start and final slice counts, the check's estimate, the true
     scale-weighted error against the native float64 product, and the time of
@@ -378,15 +379,16 @@ def bench_wide_tol(args):
     wa, wb = tA.abs().amax(1), tB.abs().amax(0)
     flops = 2.0 * m * n * k
     rows = []
+    dig = args.wide_digits
     for tol in [float(v) for v in args.wide_tols.split(",")]:
-        p = oz.prec(0, tol=tol, smax=12)
+        p = oz.prec(0, tol=tol, smax=12, digits=dig)
         ms = _time_ms(lambda: oz.oz_dgemm(h, "N", "N", m, n, k, 1.0, dA, m, dB, k, 0.0, dC, m, p),
                       stream, args.steps, args.warmup)
         st, rep = oz.oz_dgemm(h, "N", "N", m, n, k, 1.0, dA, m, dB, k, 0.0, dC, m, p, report=True)
         C = dC.view(n, m).t()
         err = _weighted_err(C, Cn, wa, wb)
         s1 = rep.slices_used
-        pf = oz.prec(s1) if s1 <= 8 else oz.prec(0, tol=tol, smax=s1, sstart=s1)
+        pf = oz.prec(s1, digits=dig) if s1 <= 8 else oz.prec(0, tol=tol, smax=s1, sstart=s1)
         fms = _time_ms(lambda: oz.oz_dgemm(h, "N", "N", m, n, k, 1.0, dA, m, dB, k, 0.0, dC, m, pf),
                        stream, args.steps, args.warmup)
         row = {"tol": tol, "ms": round(ms, 4), "tflops": round(flops / (ms * 1e-3) / 1e12, 2),
@@ -396,7 +398,8 @@ def bench_wide_tol(args):
         print(json.dumps(row), flush=True)
         rows.append(row)
     oz.oz_destroy(h)
-    print(json.dumps({"workload": "wide-range dgemm 4096x4096x8192 (rows/cols x 10^U(-8,8)), tolerance-driven",
+    print(json.dumps({"workload": "wide-range dgemm 4096x4096x8192 (rows/cols x 10^U(-8,8)), tolerance-driven, %s digits"
+                      % ("balanced" if dig else "truncated"),
                       "native_ms": round(nms, 4), "native_tflops": round(flops / (nms * 1e-3) / 1e12, 2),
                       "rows": rows}), flush=True)
 
@@ -628,6 +631,8 @@ def main():
     ap.add_argument("--select-tols", default="1e-10,1e-12,1e-14")
     ap.add_argument("--sweep-n", default="2048,4096")
     ap.add_argument("--wide-tols", default="1e-6,1e-10,1e-14")
+    ap.add_argument("--wide-digits", type=int, default=0, choices=[0, 1],
+                    help="wide_tol workload: 1 = balanced digits (smax 8)")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)

@@ -105,9 +105,10 @@ typedef struct oz_handle_s* oz_handle_t;
  *           1 = balanced, round-to-nearest digits (the rounding the paper
  *           expects to be worth about one bit per slice, Sec. 4), fixed slice
  *           counts 1..8, real products and both complex forms, and
- *           tolerance-driven calls (smax capped at 8; the start is one slice
- *           below the rule's or the selector's; growth splits again at s + 1
- *           and recomputes the sums, since the digits depend on s); a
+ *           tolerance-driven calls (smax capped at 8; the rule's estimate is
+ *           divided by 2^(s-1), and the selector's start lowered by one from
+ *           7 on; growth splits again at s + 1 and recomputes the sums, since
+ *           the digits depend on s); a
  *           double-double or batched call, or s > 8, returns 14: the vector exponent is E' = E, or E + 1 when the
  *           largest magnitude M has M 2^(7-E) > 127; N = |x| 2^(7-E'+8(s-1))
  *           rounded to the nearest integer (ties away from zero) with the

@@ -231,7 +231,8 @@ int vector_msq(oz_handle_t h, const oz::OperandView& v, const uint64_t* mx, doub
 
 // Smallest s in [1, smax] whose rule estimate meets tol (smax if none does).
 int rule_slices(oz_handle_t h, const oz::OperandView& va, const oz::OperandView& vb, const uint64_t* maxa,
-                const uint64_t* maxb, double* msa, double* msb, double* part, double tol, int smax, int* s_out) {
+                const uint64_t* maxb, double* msa, double* msb, double* part, double tol, int smax, int* s_out,
+                bool bal = false) {
     double ma = 0.0, mb = 0.0;
     int st = vector_msq(h, va, maxa, msa, part, &ma);
     if (!st) st = vector_msq(h, vb, maxb, msb, part, &mb);
@@ -240,7 +241,7 @@ int rule_slices(oz_handle_t h, const oz::OperandView& va, const oz::OperandView&
         *s_out = 1;
         return OZ_OK;
     }
-    *s_out = oz::rule_slices_of(ma, mb, tol, smax);
+    *s_out = oz::rule_slices_of(ma, mb, tol, smax, bal);
     return OZ_OK;
 }
 
@@ -500,12 +501,13 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
             if (st) return st;
         } else {
             st = rule_slices(h, va, vb, maxa, maxb, msa, msb, reinterpret_cast<double*>(ws + p.off_part1), tol, smax,
-                             &s);
+                             &s, bal);
             if (st) return st;
         }
-        // the rule and the learned start are calibrated on truncated digits;
-        // balanced digits reach the same error with about one slice fewer
-        if (bal && prec->sstart == 0 && s > 1) --s;
+        // the learned start is trained on truncated digits; balanced digits
+        // save a whole slice (2^7) only from about s = 7 on (their gain is
+        // about 2^(s-1)); the residual check still guards the result
+        if (bal && prec->sstart == 0 && prec->selector == 1 && s >= 7) --s;
         if (s > smax) s = smax;
         // (2) digit planes 1..s, then emulate at s into the raw FP64 sums
         if (oz::launch_digits(va, maxa, p.la, EA, SA, h->stream, 0, s) != hipSuccess ||

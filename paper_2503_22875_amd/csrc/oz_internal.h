@@ -222,12 +222,14 @@ hipError_t launch_finalize_batched(const FinalArgs* f, const int32_t* active, co
 // about 2^-7s per scaled operand entry; the dropped pairs add a term growing
 // with s).  c = 2.5 covers the data families measured (0.7 .. 2.0).  The
 // smallest s in [1, smax] meeting tol (smax if none; 1 for a zero operand).
+// Balanced digits carry one bit more in every slice but the first:
+// eps(s) / 2^(s-1).
 constexpr double kRuleC = 2.5;
-__host__ __device__ inline int rule_slices_of(double ma, double mb, double tol, int smax) {
+__host__ __device__ inline int rule_slices_of(double ma, double mb, double tol, int smax, bool bal = false) {
     if (!(ma > 0.0) || !(mb > 0.0)) return 1;
     const double spread = sqrt((1.0 / ma + 1.0 / mb) / 3.0);
     int s = 1;
-    while (s < smax && kRuleC * (s + 1) * ldexp(1.0, -7 * s) * spread > tol) ++s;
+    while (s < smax && kRuleC * (s + 1) * ldexp(1.0, bal ? 1 - 8 * s : -7 * s) * spread > tol) ++s;
     return s;
 }
 
