@@ -108,8 +108,10 @@ typedef struct oz_handle_s* oz_handle_t;
  *           tolerance-driven calls (smax capped at 8; the rule's estimate is
  *           divided by 2^(s-1), and the selector's start lowered by one from
  *           7 on; growth splits again at s + 1 and recomputes the sums, since
- *           the digits depend on s); a
- *           double-double or batched call, or s > 8, returns 14: the vector exponent is E' = E, or E + 1 when the
+ *           the digits depend on s), and batched calls with fixed slice counts
+ *           (the 4-product form; each problem's s from 1 to 8).  A
+ *           double-double call, a tolerance-driven batch, or s > 8 returns
+ *           14.  The vector exponent is E' = E, or E + 1 when the
  *           largest magnitude M has M 2^(7-E) > 127; N = |x| 2^(7-E'+8(s-1))
  *           rounded to the nearest integer (ties away from zero) with the
  *           sign of x; digits d_1..d_s with N = sum_p d_p 256^(s-p), all in
@@ -418,7 +420,8 @@ int oz_predict_slices(oz_handle_t handle, char transa, char transb, int64_t m, i
  * one double per problem, or two -- real, imaginary -- for complex); A[b],
  * B[b], C[b] are device pointers.  Each problem follows the oz_dgemm /
  * oz_zgemm semantics with its own slice count: slices[b] if the array is given,
- * else prec->slices (1..8; prec NULL: 7).  Errors are reported for the first
+ * else prec->slices (1..8; prec NULL: 7), and prec->digits = 1 gives every
+ * problem balanced digits.  Errors are reported for the first
  * problem that has one, at the reference-BLAS argument position.
  *
  * A plan computes the layouts, carves one device allocation (owned by the

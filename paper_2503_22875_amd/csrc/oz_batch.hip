@@ -86,8 +86,11 @@ bool trans_ok(char c) {
     return c == 'N' || c == 'T' || c == 'C';
 }
 
-int64_t kchunk_bound(int s) {
-    int64_t kc = static_cast<int64_t>(INT32_MAX) / (static_cast<int64_t>(s) * 127 * 127);
+// terms per INT32 chunk: s products of digits up to 127 (truncated) or 128
+// (balanced) in magnitude on one anti-diagonal
+int64_t kchunk_bound(int s, bool bal) {
+    const int64_t dmax = bal ? 128 : 127;
+    int64_t kc = static_cast<int64_t>(INT32_MAX) / (static_cast<int64_t>(s) * dmax * dmax);
     return kc - kc % 64;
 }
 
@@ -216,11 +219,11 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
     const int w = cplx ? 2 : 1;
     int s_default = 7, kernel = 0;
     int64_t kc_forced = 0;
-    bool tol_mode = false;
+    bool tol_mode = false, bal = false;
     double tol = 0.0;
     int smax = kDefaultSmax, sstart = 0, selector = 0;
     if (prec) {
-        if (prec->kernel < 0 || prec->kernel > 2 || prec->digits != 0) return 14;  // truncated digits only
+        if (prec->kernel < 0 || prec->kernel > 2 || prec->digits < 0 || prec->digits > 1) return 14;
         if (prec->zmode != 0 && prec->zmode != 4) return 14;  // batched: the 4-product form only
         if (prec->slices == 0) {
             // tolerance-driven: s per problem chosen at execution
@@ -229,8 +232,9 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
             if (prec->smax) smax = prec->smax;
             sstart = prec->sstart;
             selector = prec->selector;
+            // balanced digits: fixed slice counts only (the batched growth adds planes one at a time)
             if (!(tol > 0.0) || smax < 1 || smax > OZ_MAX_SLICES || sstart < 0 || sstart > smax ||
-                (selector != 0 && selector != 1) || slices)
+                (selector != 0 && selector != 1) || slices || prec->digits)
                 return 14;
             if (selector == 1 && sstart == 0 && !oz_mlp_valid(oz_handle_selector(h))) return OZ_ERR_ARG;
             s_default = smax;  // digit planes held for growth
@@ -240,6 +244,7 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
         }
         kernel = prec->kernel;
         kc_forced = prec->kchunk;
+        bal = prec->digits == 1;
     }
     // argument checks per problem (reference-BLAS positions)
     for (int32_t b = 0; b < batch; ++b) {
@@ -255,7 +260,7 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
         if (ldc[b] < (m[b] > 1 ? m[b] : 1)) return 13;
         const int sb = slices ? slices[b] : s_default;
         if (sb < 1 || sb > (tol_mode ? OZ_MAX_SLICES : oz::kMaxLiveSlices)) return 14;
-        if (kc_forced < 0 || kc_forced % 64 != 0 || (kc_forced > 0 && kc_forced > kchunk_bound(sb))) return 14;
+        if (kc_forced < 0 || kc_forced % 64 != 0 || (kc_forced > 0 && kc_forced > kchunk_bound(sb, bal))) return 14;
     }
     if (oz_handle_use_device(h)) return OZ_ERR_HIP;
 
@@ -311,11 +316,12 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
         q.vb = view(transb[b], B[b], ldb[b], n[b], k[b], cplx, 0);
         q.la = oz::slice_layout(1, cplx, m[b], k[b], q.s);
         q.lb = oz::slice_layout(0, cplx, n[b], k[b], q.s);
+        q.la.bal = q.lb.bal = bal ? 1 : 0;
         if (q.la.rows_pad / 64 > 65535 || q.lb.rows_pad / 64 > 65535) {
             delete P;
             return OZ_ERR_UNSUPPORTED;
         }
-        q.kc = kc_forced ? kc_forced : kchunk_bound(q.s);
+        q.kc = kc_forced ? kc_forced : kchunk_bound(q.s, bal);
         q.off_maxa = static_cast<size_t>(n_max) * 8;
         n_max += m[b];
         q.off_maxb = static_cast<size_t>(n_max) * 8;
@@ -414,6 +420,7 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
         g.s = q.s;
         g.s_lay = q.s;
         g.cplx = cplx;
+        g.bal = q.la.bal;
         // tolerance-driven: raw sums for the check; with beta = 0 also C, which
         // is then rewritten only for problems whose slice count grows
         g.mode = tol_mode ? oz::kRawWrite : oz::kFinal;

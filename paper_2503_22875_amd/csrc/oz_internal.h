@@ -117,7 +117,7 @@ struct GemmArgs {
     int cplx;
     int tile;              // 0 auto, 1: 128 x 64 block, 2: 64 x 64 block, 3: per-diagonal streaming
     int mode;              // kFinal, kRawWrite, kRawAdd (see below)
-    int bal;               // 0: fold weights 2^(-7d) (truncated digits); 1: 2^(4-8d) (balanced)
+    int bal;               // 0: fold weights 2^(-7d) (truncated digits); 1: 2^(2-8d) (balanced)
     double* acc;           // raw FP64 tile sums acc[col * Mp + row] for the raw modes
     // epilogue
     double* C;

@@ -357,7 +357,14 @@ __global__ __launch_bounds__(256) void digits_batched_kernel(const SplitOp* __re
     const int p_lo = prange ? prange[2 * it.op] : 0, p_hi = prange ? prange[2 * it.op + 1] : o.lay.s;
     if (p_lo >= p_hi) return;  // nothing to split for this operand (uniform over the block)
     const bool lc = o.op.sl == 1, two_row = o.op.cplx && o.op.side_a;
-#define OZ_DB(LC, CP, SA) digits_body<LC, CP, SA>(o.op, o.maxbits, o.lay, o.E, o.slices, it.bx, it.by, p_lo, p_hi)
+    // balanced operands (fixed s only) fill all their planes: p_lo = 0, p_hi = s
+#define OZ_DB(LC, CP, SA)                                                                                   \
+    do {                                                                                                    \
+        if (o.lay.bal)                                                                                      \
+            digits_body<LC, CP, SA, true>(o.op, o.maxbits, o.lay, o.E, o.slices, it.bx, it.by, 0, o.lay.s); \
+        else                                                                                                \
+            digits_body<LC, CP, SA>(o.op, o.maxbits, o.lay, o.E, o.slices, it.bx, it.by, p_lo, p_hi);       \
+    } while (0)
     if (lc) {
         if (two_row) OZ_DB(true, true, true);
         else if (o.op.cplx) OZ_DB(true, true, false);

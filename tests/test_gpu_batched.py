@@ -43,7 +43,7 @@ def make_problem(rng, cplx, m, n, k, ta, tb):
     return A, B, C0
 
 
-def batch_call(oz, handle, stream, cplx, probs, slices, use_plan=False, replays=0):
+def batch_call(oz, handle, stream, cplx, probs, slices, use_plan=False, replays=0, digits=0):
     dev = []
     for (ta, tb, A, B, C0, al, be) in probs:
         dA, lda = to_dev(A, A.shape[0] + 1)
@@ -60,10 +60,11 @@ def batch_call(oz, handle, stream, cplx, probs, slices, use_plan=False, replays=
                 C=[d[4] for d in dev], ldc=[d[5] for d in dev])
     if not use_plan:
         fn = oz.oz_zgemm_batched if cplx else oz.oz_dgemm_batched
-        fn(handle, p=oz.prec(slices if isinstance(slices, int) else 7),
+        fn(handle, p=oz.prec(slices if isinstance(slices, int) else 7, digits=digits),
            slices=None if isinstance(slices, int) else slices, **args)
     else:
-        plan = oz.oz_gemm_batched_plan(handle, cplx, p=oz.prec(slices if isinstance(slices, int) else 7),
+        plan = oz.oz_gemm_batched_plan(handle, cplx, p=oz.prec(slices if isinstance(slices, int) else 7,
+                                                               digits=digits),
                                        slices=None if isinstance(slices, int) else slices, **args)
         oz.oz_batch_graph_launch(plan)
         return plan, dev, args
@@ -97,6 +98,60 @@ def test_batched_bit_exact_mixed(oz, handle, stream, cplx):
                 assert np.array_equal(got[i], want), i
             continue
         assert np.array_equal(got[i], want), (i, ta, tb, A.shape, B.shape)
+
+
+@pytest.mark.parametrize("cplx", [0, 1])
+def test_batched_balanced_bit_exact_mixed(oz, handle, stream, cplx):
+    # balanced digits in every problem: slice counts 1..8 mixed (one GEMM
+    # launch per count), ragged shapes, every transpose, beta on half of them
+    rng = np.random.default_rng(40 + cplx)
+    shapes = [(1, 1, 1), (70, 65, 33), (130, 70, 257), (64, 192, 64), (5, 300, 17), (200, 3, 90), (96, 96, 96),
+              (33, 47, 2), (7, 8, 0), (40, 30, 20)]
+    probs, slices = [], []
+    for i, (m, n, k) in enumerate(shapes):
+        ta = "NTC"[i % 3] if cplx else "NT"[i % 2]
+        tb = "NCT"[(i // 3) % 3] if cplx else "TN"[i % 2]
+        A, B, C0 = make_problem(rng, cplx, m, n, k, ta, tb)
+        al = complex(1.0 - 0.1 * i, 0.3) if cplx else 1.0 + 0.2 * i
+        be = (complex(-0.5, 0.25) if i % 2 else 0.0) if cplx else (0.75 if i % 2 else 0.0)
+        probs.append((ta, tb, A, B, C0, al, be))
+        slices.append(1 + i % 8)
+    print("balanced batch cplx=%d" % cplx, flush=True)
+    got = batch_call(oz, handle, stream, cplx, probs, slices, digits=1)
+    for i, (ta, tb, A, B, C0, al, be) in enumerate(probs):
+        if A.size == 0 or B.size == 0:
+            assert np.array_equal(got[i], be * C0 if be != 0.0 else np.zeros_like(C0)), i
+            continue
+        want = oracle.emu_gemm(ta, tb, A, B, slices[i], alpha=al, beta=be, C=C0, balanced=True)
+        assert np.array_equal(got[i], want), (i, ta, tb, A.shape, B.shape, slices[i])
+
+
+def test_batched_balanced_graph_replay(oz, handle, stream):
+    # a captured balanced plan replays with new operands written in place
+    rng = np.random.default_rng(41)
+    probs = []
+    for nb in (48, 130, 64):
+        A, B, C0 = make_problem(rng, 0, nb, nb + 3, nb - 5, "N", "T")
+        probs.append(("N", "T", A, B, C0, 1.0, 0.0))
+    plan, dev, args = batch_call(oz, handle, stream, 0, probs, 6, use_plan=True, digits=1)
+    try:
+        for rep in range(3):
+            stream.synchronize()
+            for i, (_, _, A, B, _, _, _) in enumerate(probs):
+                A2 = np.asfortranarray(A * (rep + 2) - rep)
+                probs[i] = ("N", "T", A2, B, None, 1.0, 0.0)
+                dA, lda = dev[i][0], dev[i][1]
+                buf = np.zeros((lda, A2.shape[1]), order="F")
+                buf[:A2.shape[0]] = A2
+                with torch.cuda.stream(stream):
+                    dA.copy_(torch.from_numpy(buf.ravel(order="F")))
+            oz.oz_batch_graph_launch(plan)
+            stream.synchronize()
+            for i, (_, _, A2, B, _, _, _) in enumerate(probs):
+                got = from_dev(dev[i][4], A2.shape[0], B.shape[0], dev[i][5])
+                assert np.array_equal(got, oracle.emu_gemm("N", "T", A2, B, 6, balanced=True)), (rep, i)
+    finally:
+        oz.oz_batch_destroy(plan)
 
 
 def test_batched_graph_replays_track_new_inputs(oz, handle, stream):
@@ -177,6 +232,10 @@ def test_batched_argument_errors(oz, handle):
     st = oz.oz_zgemm(handle, "N", "N", 4, 4, 4, 1.0, d, 4, d, 4, 0.0, d, 4, oz.prec(0, tol=1e-10, zmode=3),
                      check=False)
     assert st == 14
+    # balanced digits: fixed slice counts up to 8 only
+    assert oz.oz_zgemm_batched(handle, check=False, p=oz.prec(9, digits=1), **base) == 14
+    assert oz.oz_zgemm_batched(handle, check=False, p=oz.prec(0, tol=1e-10, digits=1), **base) == 14
+    assert oz.oz_zgemm_batched(handle, check=False, p=oz.prec(6, digits=2), **base) == 14
 
 
 def _tol_batch(oz, handle, stream, cplx, probs, p):
