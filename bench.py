@@ -78,13 +78,16 @@ def cpu_baseline(A, B, s, C_gpu, rows, zmode=4, balanced=False):
 
 def bench_batch(args):
     """Batched workload: 512 square complex products, n_b = 32 * randint(1, 16),
-    s = 6, one persistent GEMM launch per replay of a captured HIP graph."""
+    s = --slices (6) with --digits (balanced by default), one persistent GEMM
+    launch per replay of a captured HIP graph."""
     import torch
 
     import paper_2503_22875_amd as oz
     import workloads
 
-    s = 6
+    s = args.slices
+    if not 1 <= s <= 8:
+        raise SystemExit("batch512: fixed slice counts 1..8")
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
     problems = workloads.zgemm_batch(512, seed=0)
@@ -97,7 +100,8 @@ def bench_batch(args):
     oz.oz_load_tuning(h)
     cnt = len(problems)
     plan = oz.oz_gemm_batched_plan(h, 1, "N" * cnt, "N" * cnt, ns, ns, ns, [1.0] * cnt, [d[0] for d in dev], ns,
-                                   [d[1] for d in dev], ns, [0.0] * cnt, [d[2] for d in dev], ns, p=oz.prec(s))
+                                   [d[1] for d in dev], ns, [0.0] * cnt, [d[2] for d in dev], ns,
+                                   p=oz.prec(s, digits=args.digits))
     launches, tiles, nbytes, _ = oz.oz_batch_info(plan, cnt)
     # dominant kernel: the persistent GEMM launch, timed with events around it
     oz.oz_timing_enable(h, True)
@@ -127,7 +131,9 @@ def bench_batch(args):
         "metric": METRIC, "value": round(flops / (ms * 1e-3) / 1e12, 3), "unit": "TFLOP/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "int8", "data": "synthetic",
-        "config": {"workload": "batched zgemm: 512 square problems n_b = 32*randint(1,16), s=6, graph replay",
+        "config": {"workload": "batched zgemm: 512 square problems n_b = 32*randint(1,16), s=%d%s, graph replay"
+                               % (s, " balanced digits" if args.digits else ""),
+                   "slices": s, "digits": "balanced" if args.digits else "truncated",
                    "problems": cnt, "sum_n3": int(sum(n ** 3 for n in ns)), "gemm_launches": launches,
                    "tiles": tiles, "plan_device_bytes": nbytes},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": INT8_PEAK_TOPS, "unit": "TFLOP/s",
@@ -164,6 +170,7 @@ def bench_batch(args):
         out["native_fp64"] = {"tflops": round(flops / (nms * 1e-3) / 1e12, 3), "ms": round(nms, 4),
                               "kind": "512 torch complex128 matmuls (rocBLAS zgemm) in one captured graph"}
         out["rel_err_vs_native_max"] = worst
+        out["meets_tolerance"] = bool(worst <= 1e-12)
         out["speedup_vs_native"] = round(nms / ms, 3)
     oz.oz_batch_destroy(plan)
     oz.oz_destroy(h)
