@@ -445,8 +445,30 @@ __global__ __launch_bounds__(256) void scan3_kernel(OperandView op, Split3Out o,
 
 // One block: 64 vectors x one step of 32 terms; each thread owns 8 consecutive
 // terms (complex elements) of one vector and writes them into all three parts.
+// Contiguous terms: the block's 64 x 32 elements are first read with 32
+// neighbouring lanes per vector (512 contiguous bytes) into LDS; each thread
+// then takes its 8 elements from there (a direct read would have every lane
+// of a load touch its own 128-byte line).
 template <bool LCONTIG, bool BAL>
 __global__ __launch_bounds__(256) void digits3_kernel(OperandView op, SliceLayout lay, Split3Out o) {
+    constexpr int kStagePad = 33;  // 16-byte entries per staged vector: 32 elements + 1 to spread LDS banks
+    __shared__ double2 stage[LCONTIG ? 64 * kStagePad : 1];
+    if constexpr (LCONTIG) {
+#pragma unroll
+        for (int it = 0; it < 8; ++it) {
+            const int idx = it * 256 + static_cast<int>(threadIdx.x);
+            const int sv = idx >> 5, se = idx & 31;
+            const int64_t vv = static_cast<int64_t>(blockIdx.y) * 64 + sv;
+            const int64_t l = static_cast<int64_t>(blockIdx.x) * kStep + se;
+            double2 val = make_double2(0.0, 0.0);
+            if (vv < op.nv && l < op.k) {
+                const double* src = op.X + (vv * op.sv + l) * 2;
+                val = make_double2(src[0], src[1]);
+            }
+            stage[sv * kStagePad + se] = val;
+        }
+        __syncthreads();
+    }
     const int tid = threadIdx.x;
     const int vi = LCONTIG ? (tid >> 2) : (tid & 63);
     const int sub = LCONTIG ? (tid & 3) : (tid >> 6);
@@ -469,7 +491,15 @@ __global__ __launch_bounds__(256) void digits3_kernel(OperandView op, SliceLayou
     for (int e = 0; e < 8; ++e) {
         const int64_t l = t0 + e;
         double px[3] = {0.0, 0.0, 0.0};
-        if (live && l < op.k) parts3(op, op.X + (v * op.sv + l * op.sl) * 2, px);
+        if (live && l < op.k) {
+            if constexpr (LCONTIG) {
+                const double2 val = stage[vi * kStagePad + sub * 8 + e];
+                const double pair[2] = {val.x, val.y};
+                parts3(op, pair, px);
+            } else {
+                parts3(op, op.X + (v * op.sv + l * op.sl) * 2, px);
+            }
+        }
         re[e] = px[0];
         im[e] = px[1];
     }
