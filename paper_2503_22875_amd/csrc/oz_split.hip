@@ -538,9 +538,13 @@ __global__ __launch_bounds__(256) void digits3_kernel(OperandView op, SliceLayou
 
 }  // namespace
 
+// Terms per exponent-scan block: 128 gives n = 4096 operands 2048 blocks of 64
+// vectors (8 per CU), enough loads in flight to stream the operand.
+int64_t scan_lspan() { return 128; }
+
 hipError_t launch_scan3(const OperandView& op, const Split3Out& o, hipStream_t st) {
     if (op.nv <= 0 || op.k <= 0) return hipSuccess;
-    const int64_t lspan = 512;
+    const int64_t lspan = scan_lspan();
     dim3 grid(static_cast<unsigned>((op.k + lspan - 1) / lspan), static_cast<unsigned>((op.nv + 63) / 64));
     if (op.sl == 1) hipLaunchKernelGGL(scan3_kernel<true>, grid, dim3(256), 0, st, op, o, lspan);
     else hipLaunchKernelGGL(scan3_kernel<false>, grid, dim3(256), 0, st, op, o, lspan);
@@ -570,7 +574,6 @@ SliceLayout slice_layout(int side_a, int cplx, int64_t nv, int64_t k, int s) {
     return L;
 }
 
-int64_t scan_lspan() { return 512; }
 
 void scan_blocks(const OperandView& op, int64_t* bx, int64_t* by) {
     *bx = op.k > 0 ? (op.k + scan_lspan() - 1) / scan_lspan() : 0;
