@@ -145,7 +145,8 @@ __global__ void zero_u64_kernel(uint64_t* p, int64_t n) {
 
 // One block: 64 vectors x lspan terms.
 // LCONTIG: terms of a vector are contiguous (sl == 1): each wave walks 16
-//          vectors, its 64 lanes reading 64 consecutive terms.
+//          vectors, 4 at a time with 16 lanes each reading 16 consecutive
+//          terms (a 16-lane reduction per vector instead of a 64-lane one).
 // else   : vectors are contiguous (sv == 1): lane = vector, the 4 waves
 //          split the terms, partial maxima merged through LDS.
 template <bool LCONTIG, bool CPLX>
@@ -157,17 +158,20 @@ __device__ __forceinline__ void scan_body(const OperandView& op, uint64_t* maxbi
     const int64_t l1 = (l0 + lspan < op.k) ? l0 + lspan : op.k;
     const int w = CPLX ? 2 : 1;
     if (LCONTIG) {
-        for (int vi = 0; vi < 16; ++vi) {
-            const int64_t v = v0 + wave * 16 + vi;
-            if (v >= op.nv) break;  // wave-uniform
+        // 16 lanes per vector, 4 vectors of the wave's 16 at a time
+        const int grp = lane >> 4, gl = lane & 15;
+        for (int r = 0; r < 4; ++r) {
+            const int64_t v = v0 + wave * 16 + r * 4 + grp;
             uint64_t mx = 0;
-            const double* base = op.X + v * op.sv * w;
-            for (int64_t l = l0 + lane; l < l1; l += 64) {
-                mx = umax64(mx, mag_bits(base[l * op.sl * w]));
-                if (CPLX) mx = umax64(mx, mag_bits(base[l * op.sl * w + 1]));
+            if (v < op.nv) {
+                const double* base = op.X + v * op.sv * w;
+                for (int64_t l = l0 + gl; l < l1; l += 16) {
+                    mx = umax64(mx, mag_bits(base[l * w]));
+                    if (CPLX) mx = umax64(mx, mag_bits(base[l * w + 1]));
+                }
             }
-            for (int off = 32; off > 0; off >>= 1) mx = umax64(mx, __shfl_xor(mx, off));
-            if (lane == 0 && mx != 0) atomicMax(reinterpret_cast<unsigned long long*>(maxbits + v), mx);
+            for (int off = 8; off > 0; off >>= 1) mx = umax64(mx, __shfl_xor(mx, off));
+            if (gl == 0 && v < op.nv && mx != 0) atomicMax(reinterpret_cast<unsigned long long*>(maxbits + v), mx);
         }
     } else {
         __shared__ uint64_t red[4][64];
@@ -396,21 +400,25 @@ __device__ __forceinline__ void scan3_body(const OperandView& op, const Split3Ou
     const int64_t l0 = bx * lspan;
     const int64_t l1 = (l0 + lspan < op.k) ? l0 + lspan : op.k;
     if (LCONTIG) {
-        for (int vi = 0; vi < 16; ++vi) {
-            const int64_t v = v0 + wave * 16 + vi;
-            if (v >= op.nv) break;  // wave-uniform
+        // 16 lanes per vector, 4 vectors of the wave's 16 at a time
+        const int grp = lane >> 4, gl = lane & 15;
+        for (int r = 0; r < 4; ++r) {
+            const int64_t v = v0 + wave * 16 + r * 4 + grp;
             uint64_t mx[3] = {0, 0, 0};
-            const double* base = op.X + v * op.sv * 2;
-            for (int64_t l = l0 + lane; l < l1; l += 64) {
-                double x[3];
-                parts3(op, base + l * op.sl * 2, x);
+            if (v < op.nv) {
+                const double* base = op.X + v * op.sv * 2;
+                for (int64_t l = l0 + gl; l < l1; l += 16) {
+                    double x[3];
+                    parts3(op, base + l * 2, x);
 #pragma unroll
-                for (int q = 0; q < 3; ++q) mx[q] = umax64(mx[q], mag_bits(x[q]));
+                    for (int q = 0; q < 3; ++q) mx[q] = umax64(mx[q], mag_bits(x[q]));
+                }
             }
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
-                for (int off = 32; off > 0; off >>= 1) mx[q] = umax64(mx[q], __shfl_xor(mx[q], off));
-                if (lane == 0 && mx[q] != 0) atomicMax(reinterpret_cast<unsigned long long*>(o.maxbits[q] + v), mx[q]);
+                for (int off = 8; off > 0; off >>= 1) mx[q] = umax64(mx[q], __shfl_xor(mx[q], off));
+                if (gl == 0 && v < op.nv && mx[q] != 0)
+                    atomicMax(reinterpret_cast<unsigned long long*>(o.maxbits[q] + v), mx[q]);
             }
         }
     } else {
