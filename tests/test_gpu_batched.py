@@ -43,7 +43,7 @@ def make_problem(rng, cplx, m, n, k, ta, tb):
     return A, B, C0
 
 
-def batch_call(oz, handle, stream, cplx, probs, slices, use_plan=False, replays=0, digits=0):
+def batch_call(oz, handle, stream, cplx, probs, slices, use_plan=False, replays=0, digits=0, kchunk=0):
     dev = []
     for (ta, tb, A, B, C0, al, be) in probs:
         dA, lda = to_dev(A, A.shape[0] + 1)
@@ -60,7 +60,7 @@ def batch_call(oz, handle, stream, cplx, probs, slices, use_plan=False, replays=
                 C=[d[4] for d in dev], ldc=[d[5] for d in dev])
     if not use_plan:
         fn = oz.oz_zgemm_batched if cplx else oz.oz_dgemm_batched
-        fn(handle, p=oz.prec(slices if isinstance(slices, int) else 7, digits=digits),
+        fn(handle, p=oz.prec(slices if isinstance(slices, int) else 7, digits=digits, kchunk=kchunk),
            slices=None if isinstance(slices, int) else slices, **args)
     else:
         plan = oz.oz_gemm_batched_plan(handle, cplx, p=oz.prec(slices if isinstance(slices, int) else 7,
@@ -124,6 +124,39 @@ def test_batched_balanced_bit_exact_mixed(oz, handle, stream, cplx):
             continue
         want = oracle.emu_gemm(ta, tb, A, B, slices[i], alpha=al, beta=be, C=C0, balanced=True)
         assert np.array_equal(got[i], want), (i, ta, tb, A.shape, B.shape, slices[i])
+
+
+@pytest.mark.parametrize("cplx", [0, 1])
+def test_batched_balanced_forced_chunks(oz, handle, stream, cplx):
+    # INT32 chunks of 64 terms: every problem folds several chunks with the
+    # balanced weights 2^(2-8d) in the persistent kernel
+    rng = np.random.default_rng(42 + cplx)
+    shapes = [(70, 33, 150), (64, 64, 64), (9, 130, 257), (100, 20, 65)]
+    probs, slices = [], []
+    for i, (m, n, k) in enumerate(shapes):
+        ta = "NC"[i % 2] if cplx else "NT"[i % 2]
+        tb = "TN"[i % 2]
+        A, B, C0 = make_problem(rng, cplx, m, n, k, ta, tb)
+        be = (complex(0.5, -0.5) if cplx else 0.5) if i % 2 else 0.0
+        probs.append((ta, tb, A, B, C0, 1.25, be))
+        slices.append((4, 6, 8, 5)[i])
+    print("balanced batch, kchunk 64, cplx=%d" % cplx, flush=True)
+    got = batch_call(oz, handle, stream, cplx, probs, slices, digits=1, kchunk=64)
+    for i, (ta, tb, A, B, C0, al, be) in enumerate(probs):
+        want = oracle.emu_gemm(ta, tb, A, B, slices[i], alpha=al, beta=be, C=C0, kc=64, balanced=True)
+        assert np.array_equal(got[i], want), (i, ta, tb, A.shape, B.shape, slices[i])
+
+
+def test_batched_balanced_chunk_bound(oz, handle):
+    # s = 8: 16384-term chunks fit INT32 with digits up to 127 (bound 16640)
+    # but not with balanced digits up to 128 in magnitude (bound 16320)
+    d = torch.zeros(16, dtype=torch.complex128, device="cuda")
+    base = dict(transa=["N"], transb=["N"], m=[4], n=[4], k=[4], alpha=[1], A=[d], lda=[4], B=[d], ldb=[4],
+                beta=[0], C=[d], ldc=[4])
+    assert oz.oz_zgemm_batched(handle, check=False, p=oz.prec(8, kchunk=16384, digits=1), **base) == 14
+    assert oz.oz_zgemm_batched(handle, check=False, p=oz.prec(8, kchunk=16320, digits=1), **base) == 0
+    assert oz.oz_zgemm_batched(handle, check=False, p=oz.prec(8, kchunk=16384), **base) == 0
+    torch.cuda.synchronize()
 
 
 def test_batched_balanced_graph_replay(oz, handle, stream):
