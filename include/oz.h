@@ -102,8 +102,9 @@ typedef struct oz_handle_s* oz_handle_t;
  *           oz_select_slices, 1 = the learned selector attached to the handle
  *           (oz_set_selector; OZ_ERR_ARG without one), see oz_predict_slices.
  *  digits : 0 = truncated digits (the default, as described above).
- *           1 = balanced, round-to-nearest digits (the rounding the paper
- *           expects to be worth about one bit per slice, Sec. 4), fixed slice
+ *           1 = balanced, round-to-nearest digits (this library's own
+ *           variant: the paper does not say how digits are rounded; rounding
+ *           gains about one bit per slice over truncation), fixed slice
  *           counts 1..8, real products and both complex forms, and
  *           tolerance-driven calls (smax capped at 8; the rule's estimate is
  *           divided by 2^(s-1), and the selector's start lowered by one from

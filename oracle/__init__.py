@@ -48,9 +48,12 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_build.LIB) or os.path.getmtime(_build.LIB) < os.path.getmtime(_build.SRC):
-        _build.build()
-    lib = ctypes.CDLL(_build.LIB)
+    path = os.environ.get("OZ_ORACLE_LIB")  # e.g. the sanitized build (oracle/build.py)
+    if not path:
+        path = _build.LIB
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
+            _build.build()
+    lib = ctypes.CDLL(path)
     I64, D, P, C = ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_char
     I32 = ctypes.c_int
     lib.oro_dgemm_plain.argtypes = [C, C, I64, I64, I64, D, P, I64, P, I64, D, P, I64]
@@ -176,8 +179,10 @@ def split(side, trans, X, s, balanced=False):
     side 'A': the vectors are the rows of op(X); side 'B': the columns of op(X).
     Returns (E, dig): E int32 [nv]; dig int8 [s, nv, k] for real data or
     [s, nv, k, 2] (real part, imaginary part) for complex data.  balanced:
-    round-to-nearest digits (s <= 8), x = 2^(E+2) sum_p d_p 2^(-8p) to half a
-    unit of the last digit; otherwise truncated base-128 digits.
+    round-to-nearest digits (s <= 8), x = 2^(E'+1) sum_p d_p 2^(-8p) to half a
+    unit of the last digit, with E' = E or E + 1 (the returned exponent; see
+    oz_oracle.c); otherwise truncated base-128 digits, x = 2^E sum_p t_p 2^(-7p)
+    up to the truncation residual.
     """
     assert not balanced or 1 <= s <= 8
     cplx = np.iscomplexobj(X)
@@ -271,7 +276,7 @@ def emu_gemm(transa, transb, A, B, s, alpha=1.0, beta=0.0, C=None, kc=None, rows
     s_to > s: start at s slices and grow one slice at a time to s_to, adding
     each new anti-diagonal last (the order of the incremental fallback); kc is
     then the chunk length of the s_to plan (``kchunk(s_to)`` by default).
-    balanced: round-to-nearest digits and fold weights 2^(4-8d) (fixed s <= 8).
+    balanced: round-to-nearest digits and fold weights 2^(2-8d) (fixed s <= 8).
     """
     s1 = s if s_to is None else s_to
     assert s1 >= s

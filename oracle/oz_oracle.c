@@ -54,8 +54,9 @@
  *     bracketed; with beta == 0 only the alpha part is formed.
  *
  *
- * Balanced digits (round to nearest; the round-to-nearest splitting the paper
- * points to as worth about one bit per slice, Sec. 4), fixed s <= 8 only:
+ * Balanced digits (round to nearest; a variant of this library's own, since
+ * the paper does not say how the digits are rounded; it gains about one bit
+ * per slice over truncation), fixed s <= 8 only:
  *   - the vector's exponent is E' = E, or E + 1 when its largest magnitude M
  *     has M * 2^(7-E) > 127 (then the top digit could round to 128);
  *   - N = |x| * 2^(7 - E' + 8(s-1)) rounded to the nearest integer (ties
@@ -81,10 +82,21 @@
 #include <math.h>
 #include <omp.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
 typedef struct { double re, im; } zval;
+
+/* malloc that never returns NULL: the oracle stops loudly when out of memory */
+static void* xmalloc(size_t bytes) {
+    void* p = malloc(bytes);
+    if (p == NULL) {
+        fprintf(stderr, "oz_oracle: out of memory (%zu bytes)\n", bytes);
+        abort();
+    }
+    return p;
+}
 
 /* ---- operand access -------------------------------------------------- */
 
@@ -320,7 +332,7 @@ static void split_impl(char side, char trans, int cplx, int64_t nv, int64_t k, c
     int w = cplx ? 2 : 1;
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t v = 0; v < nv; ++v) {
-        double* vals = (double*)malloc(sizeof(double) * (size_t)(k * w + 1));
+        double* vals = (double*)xmalloc(sizeof(double) * (size_t)(k * w + 1));
         for (int64_t l = 0; l < k; ++l) {
             if (cplx) {
                 zval z = (side == 'A') ? opA_z(trans, X, ldx, v, l) : opB_z(trans, X, ldx, l, v);
@@ -492,10 +504,10 @@ static void emu_dgemm_impl(char ta, char tb, int64_t m, int64_t n, int64_t k, do
                            int64_t nr, const int64_t* cols, int64_t nc, double* out, int64_t ldo, int bal) {
     /* s1 >= s: grow incrementally from s to s1 (s1 == s: plain emulation) */
     int sd = s1 > s ? s1 : s; /* digits needed */
-    int32_t* EA = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m + 1));
-    int32_t* FB = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
-    int8_t* dA = (int8_t*)malloc((size_t)(sd * m * k + 1));
-    int8_t* dB = (int8_t*)malloc((size_t)(sd * n * k + 1));
+    int32_t* EA = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)(m + 1));
+    int32_t* FB = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)(n + 1));
+    int8_t* dA = (int8_t*)xmalloc((size_t)(sd * m * k + 1));
+    int8_t* dB = (int8_t*)xmalloc((size_t)(sd * n * k + 1));
     split_impl('A', ta, 0, m, k, A, lda, sd, EA, dA, bal);
     split_impl('B', tb, 0, n, k, B, ldb, sd, FB, dB, bal);
     int64_t nch = k > 0 ? (k + kc - 1) / kc : 0;
@@ -548,23 +560,23 @@ static void emu_zgemm_impl(char ta, char tb, int64_t m, int64_t n, int64_t k, co
                            const double* C, int64_t ldc, int s, int s1, int64_t kc, const int64_t* rows,
                            int64_t nr, const int64_t* cols, int64_t nc, double* out, int64_t ldo, int bal) {
     int sd = s1 > s ? s1 : s;
-    int32_t* EA = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m + 1));
-    int32_t* FB = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
-    int8_t* dA = (int8_t*)malloc((size_t)(2 * sd * m * k + 1));
-    int8_t* dB = (int8_t*)malloc((size_t)(2 * sd * n * k + 1));
+    int32_t* EA = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)(m + 1));
+    int32_t* FB = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)(n + 1));
+    int8_t* dA = (int8_t*)xmalloc((size_t)(2 * sd * m * k + 1));
+    int8_t* dB = (int8_t*)xmalloc((size_t)(2 * sd * n * k + 1));
     split_impl('A', ta, 1, m, k, A, lda, sd, EA, dA, bal);
     split_impl('B', tb, 1, n, k, B, ldb, sd, FB, dB, bal);
     int8_t* dN = NULL; /* balanced: digits of A with negated imaginary parts */
     if (bal) {
         int64_t ra = (ta == 'N' || ta == 'n') ? m : k, ca = (ta == 'N' || ta == 'n') ? k : m;
-        double* An = (double*)malloc(sizeof(double) * (size_t)(2 * lda * (ca > 0 ? ca : 1) + 2));
+        double* An = (double*)xmalloc(sizeof(double) * (size_t)(2 * lda * (ca > 0 ? ca : 1) + 2));
         for (int64_t c = 0; c < ca; ++c)
             for (int64_t r = 0; r < ra; ++r) {
                 An[2 * (r + c * lda)] = A[2 * (r + c * lda)];
                 An[2 * (r + c * lda) + 1] = -A[2 * (r + c * lda) + 1];
             }
-        int32_t* En = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m + 1));
-        dN = (int8_t*)malloc((size_t)(2 * sd * m * k + 1));
+        int32_t* En = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)(m + 1));
+        dN = (int8_t*)xmalloc((size_t)(2 * sd * m * k + 1));
         split_impl('A', ta, 1, m, k, An, lda, sd, En, dN, 1);
         free(An);
         free(En);
@@ -650,10 +662,10 @@ static void dd_add_exact(double* hi, double* lo, double x) {
 void oro_emu_dgemm_x2(char ta, char tb, int64_t m, int64_t n, int64_t k, const double* A, int64_t lda,
                       const double* B, int64_t ldb, int s, int64_t kc, const int64_t* rows, int64_t nr,
                       const int64_t* cols, int64_t nc, double* out_hi, double* out_lo, int64_t ldo) {
-    int32_t* EA = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m + 1));
-    int32_t* FB = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
-    int8_t* dA = (int8_t*)malloc((size_t)(s * m * k + 1));
-    int8_t* dB = (int8_t*)malloc((size_t)(s * n * k + 1));
+    int32_t* EA = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)(m + 1));
+    int32_t* FB = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)(n + 1));
+    int8_t* dA = (int8_t*)xmalloc((size_t)(s * m * k + 1));
+    int8_t* dB = (int8_t*)xmalloc((size_t)(s * n * k + 1));
     oro_split('A', ta, 0, m, k, A, lda, s, EA, dA);
     oro_split('B', tb, 0, n, k, B, ldb, s, FB, dB);
     int64_t nch = k > 0 ? (k + kc - 1) / kc : 0;
@@ -679,10 +691,10 @@ void oro_emu_dgemm_x2(char ta, char tb, int64_t m, int64_t n, int64_t k, const d
 void oro_emu_zgemm_x2(char ta, char tb, int64_t m, int64_t n, int64_t k, const double* A, int64_t lda,
                       const double* B, int64_t ldb, int s, int64_t kc, const int64_t* rows, int64_t nr,
                       const int64_t* cols, int64_t nc, double* out_hi, double* out_lo, int64_t ldo) {
-    int32_t* EA = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m + 1));
-    int32_t* FB = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
-    int8_t* dA = (int8_t*)malloc((size_t)(2 * s * m * k + 1));
-    int8_t* dB = (int8_t*)malloc((size_t)(2 * s * n * k + 1));
+    int32_t* EA = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)(m + 1));
+    int32_t* FB = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)(n + 1));
+    int8_t* dA = (int8_t*)xmalloc((size_t)(2 * s * m * k + 1));
+    int8_t* dB = (int8_t*)xmalloc((size_t)(2 * s * n * k + 1));
     oro_split('A', ta, 1, m, k, A, lda, s, EA, dA);
     oro_split('B', tb, 1, n, k, B, ldb, s, FB, dB);
     int64_t lchunk = kc / 2;
