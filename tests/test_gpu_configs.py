@@ -2,9 +2,13 @@
 against the oracle (the CPU computes only the sampled rows and columns):
 
 * ZGEMM n = 2048 and 4096 with per-row exponents in [-20, 20], s = 3 .. 8, in
-  both complex forms: sampled entries bit-exact, and the scale-weighted error
-  against the double-double product falling by about 2^7 per slice, below
-  1e-12 from s = 7 on;
+  both complex forms and with both digit kinds: sampled entries bit-exact,
+  and the scale-weighted error against the double-double product falling by
+  about 2^7 per slice, below 1e-12 from s = 7 on (truncated digits) or from
+  s = 6 on (balanced digits);
+* the benchmark's own configuration -- ZGEMM n = 4096, balanced digits,
+  s = 6, both complex forms, launched as the benchmark launches it: a dense
+  sample of entries bit-exact and within 1e-12 of the double-double product;
 * the wide-range DGEMM 4096 x 8192 x 4096 (rows of A and columns of B scaled
   by 10^U(-8, 8)) driven by the tolerances 1e-6, 1e-10 and 1e-14: the
   residual estimate meets each tolerance, the sampled error is within twice
@@ -42,8 +46,9 @@ def _samples(n, count, seed):
     return np.sort(rng.choice(n, count, replace=False)), np.sort(rng.choice(n, count, replace=False))
 
 
+@pytest.mark.parametrize("digits", [0, 1])
 @pytest.mark.parametrize("n", [2048, 4096])
-def test_zgemm_slice_sweep(oz, handle, n):
+def test_zgemm_slice_sweep(oz, handle, n, digits):
     A, B = workloads.zgemm_rowexp(n, seed=0)
     dA = torch.from_numpy(A.ravel(order="F")).cuda()
     dB = torch.from_numpy(B.ravel(order="F")).cuda()
@@ -53,20 +58,60 @@ def test_zgemm_slice_sweep(oz, handle, n):
     wa = np.maximum(np.abs(A.real), np.abs(A.imag)).max(1)[rows]
     wb = np.maximum(np.abs(B.real), np.abs(B.imag)).max(0)[cols]
     errs = {}
+    bal = digits == 1
     for zmode in (4, 3):
         for s in range(3, 9):
-            print("sweep n=%d zmode=%d s=%d" % (n, zmode, s), flush=True)
-            oz.oz_zgemm(handle, "N", "N", n, n, n, 1.0, dA, n, dB, n, 0.0, dC, n, oz.prec(s, zmode=zmode))
+            print("sweep n=%d zmode=%d digits=%d s=%d" % (n, zmode, digits, s), flush=True)
+            oz.oz_zgemm(handle, "N", "N", n, n, n, 1.0, dA, n, dB, n, 0.0, dC, n,
+                        oz.prec(s, zmode=zmode, digits=digits))
             torch.cuda.synchronize()
             got = from_dev(dC, n, n, n)[np.ix_(rows, cols)]
-            want = (oracle.emu_zgemm3("N", "N", A, B, s, rows=rows, cols=cols) if zmode == 3
-                    else oracle.emu_gemm("N", "N", A, B, s, rows=rows, cols=cols))
+            want = (oracle.emu_zgemm3("N", "N", A, B, s, rows=rows, cols=cols, balanced=bal) if zmode == 3
+                    else oracle.emu_gemm("N", "N", A, B, s, rows=rows, cols=cols, balanced=bal))
             assert np.array_equal(got, want), (zmode, s)
             errs[zmode, s] = oracle.weighted_error(got, dd, wa, wb)
-        print("n=%d zmode=%d errors:" % (n, zmode), ["%.2g" % errs[zmode, s] for s in range(3, 9)])
-        for s in range(3, 7):
-            assert 2 ** 5 < errs[zmode, s] / errs[zmode, s + 1] < 2 ** 8.5, (zmode, s)
-        assert errs[zmode, 7] < 1e-12 and errs[zmode, 6] > 1e-12
+        print("n=%d zmode=%d digits=%d errors:" % (n, zmode, digits), ["%.2g" % errs[zmode, s] for s in range(3, 9)])
+        if not bal:
+            for s in range(3, 7):
+                assert 2 ** 5 < errs[zmode, s] / errs[zmode, s + 1] < 2 ** 8.5, (zmode, s)
+            assert errs[zmode, 7] < 1e-12 and errs[zmode, 6] > 1e-12
+        else:
+            # balanced digits: about 2^8 per slice (8 bits per digit) down to
+            # the FP64 floor, reached near s = 7
+            for s in range(3, 6):
+                assert 2 ** 6 < errs[zmode, s] / errs[zmode, s + 1] < 2 ** 9.5, (zmode, s)
+            assert errs[zmode, 6] < 1e-12 and errs[zmode, 5] > 1e-12
+            assert errs[zmode, 8] < 1e-15
+
+
+@pytest.mark.parametrize("zmode", [3, 4])
+def test_zgemm_bench_configuration(oz, handle, zmode):
+    # exactly the benchmark's call: n = 4096, per-row exponents +-20, seed 0,
+    # s = 6 balanced digits, default kernel, alpha = 1, beta = 0
+    n, s = 4096, 6
+    A, B = workloads.zgemm_rowexp(n, seed=0)
+    dA = torch.from_numpy(A.ravel(order="F")).cuda()
+    dB = torch.from_numpy(B.ravel(order="F")).cuda()
+    dC = torch.zeros(n * n, dtype=torch.complex128, device="cuda")
+    print("bench configuration zmode=%d" % zmode, flush=True)
+    oz.oz_zgemm(handle, "N", "N", n, n, n, 1.0, dA, n, dB, n, 0.0, dC, n, oz.prec(s, zmode=zmode, digits=1))
+    torch.cuda.synchronize()
+    C = from_dev(dC, n, n, n)
+    # 48 rows spread over the row blocks (first and last rows included) x 48 columns
+    rows, cols = _samples(n, 46, 101)
+    rows = np.unique(np.concatenate([[0, n - 1], rows]))
+    cols = np.unique(np.concatenate([[0, n - 1], cols]))
+    got = C[np.ix_(rows, cols)]
+    want = (oracle.emu_zgemm3("N", "N", A, B, s, rows=rows, cols=cols, balanced=True) if zmode == 3
+            else oracle.emu_gemm("N", "N", A, B, s, rows=rows, cols=cols, balanced=True))
+    assert np.array_equal(got, want)
+    dd = oracle.gemm_dd("N", "N", A, B, rows=rows, cols=cols)
+    wa = np.maximum(np.abs(A.real), np.abs(A.imag)).max(1)[rows]
+    wb = np.maximum(np.abs(B.real), np.abs(B.imag)).max(0)[cols]
+    err = oracle.weighted_error(got, dd, wa, wb)
+    print("bench configuration zmode=%d: sampled weighted error %.3g" % (zmode, err))
+    assert err <= 1e-12
+    assert np.all(np.isfinite(C))
 
 
 @pytest.mark.parametrize("tol", [1e-6, 1e-10, 1e-14])
