@@ -195,6 +195,31 @@ int oz_zgemm(oz_handle_t handle, char transa, char transb, int64_t m, int64_t n,
              const double* alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
              const double* beta, double* C, int64_t ldc, const oz_prec_t* prec, oz_report_t* rep);
 
+/* Allocation-free variant of oz_dgemm (is_complex = 0) and oz_zgemm
+ * (is_complex = 1), for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, semantics, kernels and bits as oz_dgemm /
+ * oz_zgemm with the same prec (both complex forms, both digit kinds, any
+ * kernel choice), with these differences:
+ *  - the workspace is a fixed device array inside the library,
+ *    OZ_NOALLOC_SCRATCH_BYTES (64 MiB) per GPU, held from the first
+ *    oz_create on that GPU until the process ends; the call allocates
+ *    nothing (no hipMalloc, no timing events);
+ *  - a call whose workspace need (oz_workspace_size) exceeds that size
+ *    returns OZ_ERR_ALLOC and enqueues nothing;
+ *  - fixed slice counts only: prec->slices == 0 (tolerance mode) returns 14;
+ *    prec NULL means s = 7;
+ *  - no report;
+ *  - every call on one GPU shares the array (the library zeroes what must
+ *    start at zero): calls that overlap in time on one GPU -- from several
+ *    handles, streams or threads -- race and give undefined results.
+ * Argument errors are numbered as in oz_dgemm / oz_zgemm (without the
+ * is_complex argument); is_complex other than 0 or 1 returns OZ_ERR_ARG. */
+#define OZ_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int oz_gemm_noalloc(oz_handle_t handle, int is_complex, char transa, char transb, int64_t m, int64_t n,
+                    int64_t k, const double* alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
+                    const double* beta, double* C, int64_t ldc, const oz_prec_t* prec);
+
 /* Products beyond FP64 (paper Sec. 1: some computations need more than FP64;
  * with s >= 9 the emulated product carries more bits than one double holds).
  * C = op(A) op(B) as a double-double (C_hi + C_lo, both m x n with leading

@@ -29,6 +29,7 @@ OZ_ERR_HANDLE = -4
 OZ_ERR_UNSUPPORTED = -5
 OZ_ERR_ARG = -6
 OZ_MAX_SLICES = 18
+OZ_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 # Every symbol include/oz.h declares (checked by the CPU test-suite).
 EXPORTS = ["oz_create", "oz_destroy", "oz_set_stream", "oz_status_string", "oz_workspace_size",
@@ -38,7 +39,8 @@ EXPORTS = ["oz_create", "oz_destroy", "oz_set_stream", "oz_status_string", "oz_w
            "oz_load_tuning", "oz_gen_operands", "oz_features", "oz_selector_dataset", "oz_mlp_create",
            "oz_mlp_destroy", "oz_mlp_set_params", "oz_mlp_get_params", "oz_mlp_fit_norm", "oz_mlp_forward",
            "oz_mlp_grad", "oz_mlp_train_step", "oz_mlp_train", "oz_mlp_save", "oz_mlp_load", "oz_set_selector",
-           "oz_predict_slices", "oz_batch_report", "oz_dgemm_x2", "oz_zgemm_x2", "oz_zgetrf", "oz_zgetri"]
+           "oz_predict_slices", "oz_batch_report", "oz_dgemm_x2", "oz_zgemm_x2", "oz_zgetrf", "oz_zgetri",
+           "oz_gemm_noalloc"]
 
 OZ_NUM_FEATURES = 16
 OZ_MLP_NPARAM = 5313
@@ -90,6 +92,8 @@ def _load():
                      PP(oz_report_t)],
         "oz_zgemm": [P, C, C, I64, I64, I64, PP(D), P, I64, P, I64, PP(D), P, I64, PP(oz_prec_t),
                      PP(oz_report_t)],
+        "oz_gemm_noalloc": [P, ctypes.c_int, C, C, I64, I64, I64, PP(D), P, I64, P, I64, PP(D), P, I64,
+                            PP(oz_prec_t)],
         "oz_dgemm_x2": [P, C, C, I64, I64, I64, P, I64, P, I64, P, P, I64, PP(oz_prec_t), PP(oz_report_t)],
         "oz_zgemm_x2": [P, C, C, I64, I64, I64, P, I64, P, I64, P, P, I64, PP(oz_prec_t), PP(oz_report_t)],
         "oz_zgetrf": [P, I64, P, I64, P, I32, PP(oz_prec_t), PP(I32)],
@@ -217,6 +221,19 @@ def oz_zgemm(handle, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ld
     """Complex version; A, B, C hold interleaved (re, im) doubles."""
     return _gemm("oz_zgemm", True, handle, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, p,
                  report, check)
+
+
+def oz_gemm_noalloc(handle, is_complex, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, p=None,
+                    check=True):
+    """oz_dgemm (is_complex 0) / oz_zgemm (1) on the library's fixed device
+    scratch: allocates nothing, fixed slice counts only, no report."""
+    al = (ctypes.c_double * 2)(complex(alpha).real, complex(alpha).imag)
+    be = (ctypes.c_double * 2)(complex(beta).real, complex(beta).imag)
+    st = _lib.oz_gemm_noalloc(handle, int(is_complex), _ch(transa), _ch(transb), m, n, k, al, _ptr(A), lda, _ptr(B),
+                              ldb, be, _ptr(C), ldc, ctypes.byref(p) if p is not None else None)
+    if check:
+        _check("oz_gemm_noalloc", st)
+    return st
 
 
 def _gemm_x2(fn, handle, transa, transb, m, n, k, A, lda, B, ldb, C_hi, C_lo, ldc, p, report, check):

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <new>
 #include <vector>
@@ -32,7 +33,34 @@ struct oz_handle_s {
     oz_mlp_t selector;
 };
 
+// Device scratch of the allocation-free entry point oz_gemm_noalloc: every
+// workspace buffer of one fixed-s call (scale scratch, exponents, slices, the
+// 3-product form's T1 / T2) is carved from it.  Each GPU the library runs on
+// holds its own copy for the life of the process.  Host code never uses the
+// name `scratch` as an address: its device address is looked up once per
+// device (scratch_setup) and kept in g_scratch_ptr.
+constexpr size_t kNoAllocScratchBytes = OZ_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
 namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices];
+
+// Device address of `scratch` on `device`, which must be the current device;
+// looked up on the first call per device.
+int scratch_setup(int device, char** out) {
+    if (device < 0 || device >= kMaxScratchDevices) return OZ_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return OZ_ERR_HIP;
+        g_scratch_ptr[device] = p;
+    }
+    if (out) *out = static_cast<char*>(g_scratch_ptr[device]);
+    return OZ_OK;
+}
 
 constexpr uint32_t kMagic = 0x6f7a3335u;  // "oz35"
 constexpr int kDefaultSlices = 7;
@@ -147,6 +175,29 @@ Plan3 make_plan3(int64_t m, int64_t n, int64_t k, int s) {
     return p;
 }
 
+// A caller-fixed workspace (the allocation-free entry point's scratch), or
+// none: the handle's own.
+struct FixedWs {
+    char* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+int ensure_ws(oz_handle_t h, size_t bytes);
+
+// Workspace of `bytes` for one call: the fixed buffer when given (too small:
+// OZ_ERR_ALLOC, nothing allocated), else the handle's.
+int take_ws(oz_handle_t h, const FixedWs& fixed, size_t bytes, char** ws) {
+    if (fixed.ptr) {
+        if (bytes > fixed.bytes) return OZ_ERR_ALLOC;
+        *ws = fixed.ptr;
+        return OZ_OK;
+    }
+    const int st = ensure_ws(h, bytes);
+    if (st) return st;
+    *ws = static_cast<char*>(h->ws);
+    return OZ_OK;
+}
+
 int ensure_ws(oz_handle_t h, size_t bytes) {
     if (bytes <= h->ws_bytes) return OZ_OK;
     if (!h->ws_owned) return OZ_ERR_ALLOC;
@@ -253,15 +304,17 @@ int rule_slices(oz_handle_t h, const oz::OperandView& va, const oz::OperandView&
 // Three quarters of the INT8 work of the 4-product form.
 int zgemm_3m(oz_handle_t h, char transa, char transb, int64_t m, int64_t n, int64_t k, const double* alpha,
              const double* A, int64_t lda, const double* B, int64_t ldb, const double* beta, double* C, int64_t ldc,
-             int s, int64_t kc, int kernel, bool bal, oz_report_t* rep) {
+             int s, int64_t kc, int kernel, bool bal, oz_report_t* rep, const FixedWs& fixed) {
     Plan3 p = make_plan3(m, n, k, s);
     if (p.la.rows_pad / 64 > 65535 || p.lb.rows_pad / 64 > 65535) return OZ_ERR_UNSUPPORTED;
     p.la.bal = p.lb.bal = bal ? 1 : 0;
-    int st = ensure_ws(h, p.total);
+    char* ws = nullptr;
+    int st = take_ws(h, fixed, p.total, &ws);
     if (st) return st;
-    char* ws = static_cast<char*>(h->ws);
     uint64_t* mx = reinterpret_cast<uint64_t*>(ws + p.off_max);
     const double ar = alpha[0], ai = alpha[1], br = beta[0], bi = beta[1];
+    // no timing events on the allocation-free path (events are created on demand)
+    auto mark = [&](oz_handle_t hh) { return fixed.ptr ? hipSuccess : ::mark(hh); };
     hipError_t e = mark(h);
     if (e == hipSuccess) e = oz::launch_zero_u64(mx, p.nmax, h->stream);
     // the three real operands of each side (real parts, imaginary parts,
@@ -349,7 +402,7 @@ int zgemm_3m(oz_handle_t h, char transa, char transb, int64_t m, int64_t n, int6
 int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, int64_t n, int64_t k,
                 const double* alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
                 const double* beta, double* C, int64_t ldc, const oz_prec_t* prec, oz_report_t* rep,
-                double* c_lo = nullptr) {
+                double* c_lo = nullptr, const FixedWs& fixed = FixedWs()) {
     if (!valid(h)) return OZ_ERR_HANDLE;
     if (!trans_ok(transa)) return 1;
     if (!trans_ok(transb)) return 2;
@@ -425,14 +478,17 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
     if (cplx && prec && prec->zmode == 3) {
         // 3-real-product form: real INT32 chunks of k terms
         const int64_t kc3 = prec->kchunk ? prec->kchunk : kchunk_bound(s, bal);
-        return zgemm_3m(h, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, s, kc3, kernel, bal, rep);
+        return zgemm_3m(h, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, s, kc3, kernel, bal, rep,
+                        fixed);
     }
+    if (fixed.ptr && tol_mode) return 14;  // the allocation-free path takes fixed slice counts
     Plan p = make_plan(cplx, m, n, k, s_plan, tol_mode);
     if (!grid_fits(p)) return OZ_ERR_UNSUPPORTED;
     p.la.bal = p.lb.bal = bal ? 1 : 0;
-    st = ensure_ws(h, p.total);
+    char* ws = nullptr;
+    st = take_ws(h, fixed, p.total, &ws);
     if (st) return st;
-    char* ws = static_cast<char*>(h->ws);
+    auto mark = [&](oz_handle_t hh) { return fixed.ptr ? hipSuccess : ::mark(hh); };
     uint64_t* maxa = reinterpret_cast<uint64_t*>(ws + p.off_maxa);
     uint64_t* maxb = reinterpret_cast<uint64_t*>(ws + p.off_maxb);
     int32_t* EA = reinterpret_cast<int32_t*>(ws + p.off_ea);
@@ -624,6 +680,9 @@ int oz_create(oz_handle_t* handle, int device) {
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) return OZ_ERR_HIP;
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return OZ_ERR_UNSUPPORTED;
     if (hipSetDevice(device) != hipSuccess) return OZ_ERR_HIP;
+    // the allocation-free entry point's scratch: its address on this device
+    const int sst = scratch_setup(device, nullptr);
+    if (sst) return sst;
     oz_handle_s* h = new (std::nothrow) oz_handle_s;
     if (!h) return OZ_ERR_ALLOC;
     h->magic = kMagic;
@@ -747,6 +806,22 @@ int oz_zgemm(oz_handle_t h, char transa, char transb, int64_t m, int64_t n, int6
              const double* A, int64_t lda, const double* B, int64_t ldb, const double* beta, double* C, int64_t ldc,
              const oz_prec_t* prec, oz_report_t* rep) {
     return gemm_common(h, 1, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, prec, rep);
+}
+
+int oz_gemm_noalloc(oz_handle_t h, int is_complex, char transa, char transb, int64_t m, int64_t n, int64_t k,
+                    const double* alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
+                    const double* beta, double* C, int64_t ldc, const oz_prec_t* prec) {
+    if (!valid(h)) return OZ_ERR_HANDLE;
+    if (is_complex != 0 && is_complex != 1) return OZ_ERR_ARG;
+    if (prec && prec->slices == 0) return 14;  // fixed slice counts only
+    int st = use_device(h);
+    if (st) return st;
+    FixedWs fixed;
+    st = scratch_setup(h->device, &fixed.ptr);
+    if (st) return st;
+    fixed.bytes = kNoAllocScratchBytes;
+    return gemm_common(h, is_complex, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, prec, nullptr,
+                       nullptr, fixed);
 }
 
 int oz_dgemm_x2(oz_handle_t h, char transa, char transb, int64_t m, int64_t n, int64_t k, const double* A,
