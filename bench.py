@@ -52,28 +52,65 @@ def traffic_for(workload):
     return ent["bytes_per_launch"]
 
 
-def cpu_baseline(A, B, s, C_gpu, rows, zmode=4, balanced=False):
-    """Oracle (step-by-step CPU emulation) on the first `rows` rows of C."""
+def cpu_info():
+    """CPU model, logical CPU count and the size of this process's affinity set."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "cpu_count": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
+
+
+def cpu_baseline(A, B, s, C_gpu, rows, zmode=4, balanced=False, C_native=None):
+    """Oracle on the first `rows` rows of C: O4 (the step-by-step CPU
+    emulation, timed: the reported rate; the GPU rows checked bit for bit
+    against it); on the first min(rows, 128) rows also O2 (the double-double
+    product, the accuracy reference) and O1 (plain FP64), both timed, and the
+    GPU and native rows' scale-weighted errors against O2."""
     import oracle
+    cplx = np.iscomplexobj(A)
+    As = np.asfortranarray(A[:rows])
     t0 = time.perf_counter()
-    if zmode == 3:
-        ref = oracle.emu_zgemm3("N", "N", np.asfortranarray(A[:rows]), B, s, balanced=balanced)
+    if cplx and zmode == 3:
+        ref = oracle.emu_zgemm3("N", "N", As, B, s, balanced=balanced)
     else:
-        ref = oracle.emu_gemm("N", "N", np.asfortranarray(A[:rows]), B, s, balanced=balanced)
+        ref = oracle.emu_gemm("N", "N", As, B, s, balanced=balanced)
     t = time.perf_counter() - t0
+    r2 = min(rows, 128)
+    A2 = np.asfortranarray(A[:r2])
+    t1 = time.perf_counter()
+    dd = oracle.gemm_dd("N", "N", A2, B)
+    t_dd = time.perf_counter() - t1
+    t2 = time.perf_counter()
+    oracle.gemm_plain("N", "N", A2, B)
+    t_plain = time.perf_counter() - t2
     n, k = B.shape[1], A.shape[1]
-    dd = oracle.gemm_dd("N", "N", np.asfortranarray(A[:rows]), B)
-    wa = np.abs(np.concatenate([A[:rows].real, A[:rows].imag], axis=1)).max(1)
-    wb = np.abs(np.concatenate([B.real, B.imag], axis=0)).max(0)
-    return {
-        "value": 8.0 * rows * n * k / t / 1e12,
+    if cplx:
+        wa = np.abs(np.concatenate([A2.real, A2.imag], axis=1)).max(1)
+        wb = np.abs(np.concatenate([B.real, B.imag], axis=0)).max(0)
+    else:
+        wa, wb = np.abs(A2).max(1), np.abs(B).max(0)
+    fl = (8.0 if cplx else 2.0) * rows * n * k
+    out = {
+        "value": fl / t / 1e12,
         "unit": "TFLOP/s",
         "cores": oracle.num_threads(),
         "kind": "oracle",
         "sample": "rows 0..%d of C (all %d columns), same inputs and s; %.1f s wall" % (rows - 1, n, t),
         "sample_bit_exact": bool(np.array_equal(C_gpu[:rows], ref)),
-        "rel_err_vs_double_double": oracle.weighted_error(C_gpu[:rows], dd, wa, wb),
+        "rel_err_vs_double_double": oracle.weighted_error(C_gpu[:r2], dd, wa, wb),
+        "o2_o1_sample": "rows 0..%d of C (all %d columns)" % (r2 - 1, n),
+        "o2_double_double_s": round(t_dd, 2),
+        "o1_plain_s": round(t_plain, 2),
     }
+    if C_native is not None:
+        out["native_rel_err_vs_double_double"] = oracle.weighted_error(C_native[:r2], dd, wa, wb)
+    out.update(cpu_info())
+    return out
 
 
 def bench_batch(args):
@@ -177,19 +214,136 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def mixed_batch_on_device(oz, h, count=512, seed=0):
+    """The heterogeneous batch (workloads.zgemm_batch_mixed) drawn on the GPU by
+    the library's counter-based generator: per problem the real and imaginary
+    parts of A and B come from the two instances of workloads.mixed_parts,
+    interleaved into complex column-major buffers.  Returns (dev, ns, tols,
+    params) with dev a list of (A, B, C) tensors."""
+    import torch
+
+    import workloads
+    params, tols = workloads.zgemm_batch_mixed(count, seed)
+    dev, ns = [], []
+    for p in params:
+        n = p["n"]
+        parts = []
+        for q in workloads.mixed_parts(p):
+            A = torch.empty(n * n, dtype=torch.float64, device="cuda")
+            B = torch.empty(n * n, dtype=torch.float64, device="cuda")
+            oz.oz_gen_operands(h, q, A, n, B, n)
+            parts.append((A, B))
+        torch.cuda.synchronize()
+        Az = torch.view_as_complex(torch.stack([parts[0][0], parts[1][0]], dim=1).contiguous())
+        Bz = torch.view_as_complex(torch.stack([parts[0][1], parts[1][1]], dim=1).contiguous())
+        dev.append((Az, Bz, torch.zeros(n * n, dtype=torch.complex128, device="cuda")))
+        ns.append(n)
+    return dev, ns, tols, params
+
+
+def selection_gain(oz, h, stream, dev, ns, tols, steps=5, warmup=2, fixed_max=12):
+    """Time and accuracy of one tolerance-driven batch run four ways, with
+    per-problem tolerances tols[i]:
+      fixed:    one slice count for every problem, the smallest s at which
+                every problem meets its tolerance by its true error (found by
+                trying s = 1, 2, ...; known only after the fact), run as a
+                plain fixed plan (s <= 8) or a tolerance plan pinned at s;
+      rule:     starting s per problem from the operand-statistics rule,
+                residual check and growth;
+      escalate: every problem starts at s = 2, check and growth;
+      learned:  starting s per problem from the trained network, check and
+                growth.
+    True error = scale-weighted error against the emulation at s = 12 (the
+    fixed-s emulation as judge; its own error is about 2^-84).  Time = whole
+    execution on the stream, median (and min) of `steps` runs after `warmup`.
+    Returns a dict of rows."""
+    import torch
+
+    cnt = len(ns)
+    tols = np.asarray(tols, dtype=np.float64)
+    pairs_ops = lambda s, n: s * (s + 1) // 2 * 2.0 * (2 * n) * n * (2 * n)  # INT8 ops, 4-product form
+    # judge: the s = 12 emulation of every problem, and the scale weights
+    ref, wts = [], []
+    for (dA, dB, _), n in zip(dev, ns):
+        Cr = torch.zeros(n * n, dtype=torch.complex128, device="cuda")
+        oz.oz_zgemm(h, "N", "N", n, n, n, 1.0, dA, n, dB, n, 0.0, Cr, n, oz.prec(12))
+        ref.append(Cr.view(n, n))
+        Ad, Bd = dA.view(n, n).t(), dB.view(n, n).t()  # row-major views of column-major storage
+        wa = torch.maximum(Ad.real.abs(), Ad.imag.abs()).amax(1)
+        wb = torch.maximum(Bd.real.abs(), Bd.imag.abs()).amax(0)
+        wa = torch.where(wa > 0, 1.0 / wa, torch.zeros_like(wa))
+        wb = torch.where(wb > 0, 1.0 / wb, torch.zeros_like(wb))
+        wts.append((wb[:, None] * wa[None, :]))  # transposed like the storage views
+    torch.cuda.synchronize()
+
+    def true_errors():
+        errs = []
+        for (_, _, dC), n, Cr, W in zip(dev, ns, ref, wts):
+            C = dC.view(n, n)
+            den = torch.linalg.norm(W * Cr)
+            num = torch.linalg.norm(W * (C - Cr))
+            errs.append(float(num / den) if float(den) > 0 else float(num))
+        return np.array(errs)
+
+    def run(p, per_problem_tols):
+        plan = oz.oz_gemm_batched_plan(h, 1, "N" * cnt, "N" * cnt, ns, ns, ns, [1.0] * cnt, [d[0] for d in dev], ns,
+                                       [d[1] for d in dev], ns, [0.0] * cnt, [d[2] for d in dev], ns, p=p,
+                                       tols=per_problem_tols)
+        try:
+            for _ in range(warmup):
+                oz.oz_batch_execute(plan)
+            stream.synchronize()
+            times = []
+            for _ in range(steps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                oz.oz_batch_execute(plan)
+                e1.record(stream)
+                stream.synchronize()
+                times.append(e0.elapsed_time(e1))
+            reps = oz.oz_batch_report(plan, cnt)
+        finally:
+            oz.oz_batch_destroy(plan)
+        err = true_errors()
+        final = np.array([r.slices_used for r in reps])
+        start = final - np.array([r.fallbacks for r in reps])
+        return {"ms": round(float(np.median(times)), 3), "ms_min": round(float(np.min(times)), 3),
+                "mean_start": round(float(start.mean()), 3), "mean_final": round(float(final.mean()), 3),
+                "grown": int((final > start).sum()),
+                "int8_tops": round(sum(pairs_ops(int(s), n) for s, n in zip(final, ns)) / 1e12, 3),
+                "pass_true": float(np.mean(err <= tols)), "worst_err_over_tol": float(np.max(err / tols))}
+
+    out = {}
+    tl = [float(t) for t in tols]
+    # fixed: the smallest single s that passes every problem
+    for s in range(1, fixed_max + 1):
+        if s <= 8:
+            row = run(oz.prec(s), None)
+        else:
+            row = run(oz.prec(0, tol=1.0, smax=s, sstart=s), tl)
+        if row["pass_true"] == 1.0:
+            row["s"] = s
+            out["fixed"] = row
+            break
+    out["rule"] = run(oz.prec(0, tol=1.0, smax=12, selector=0), tl)
+    out["escalate"] = run(oz.prec(0, tol=1.0, smax=12, sstart=2), tl)
+    out["learned"] = run(oz.prec(0, tol=1.0, smax=12, selector=1), tl)
+    if "fixed" in out:
+        out["learned_speedup"] = {k: round(out[k]["ms"] / out["learned"]["ms"], 3)
+                                  for k in ("fixed", "rule", "escalate")}
+    return out
+
+
 def bench_select(args):
-    """Gain of the learned slice-count selector.  Tolerance-driven batches of
-    512 square complex problems (n_b = 32 * randint(1, 16)) -- the batched
-    workload (N(0,1) entries) and a variant with a per-problem exponent spread
-    sigma ~ randint(0, 40) -- at tol 1e-10, 1e-12, 1e-14, each run four ways:
-    fixed: one slice count for all, the smallest at which every problem
-           passes (from the escalation run); a fixed plan, no check;
-    rule:  starting s from the operand statistics rule, check and growth;
-    escalate: every problem starts at s = 2, check and growth;
-    learned: starting s from the trained network, check and growth.
-    Time = whole execution on the stream (split, selection, GEMM rounds, checks,
-    scaling), median of --steps runs; error = scale-weighted error of every
-    problem against the native complex128 product."""
+    """Gain of the learned slice-count selector on tolerance-driven batches of
+    512 square complex problems (n_b = 32 * randint(1, 16)), each run as
+    fixed / rule / escalate / learned (``selection_gain``):
+      normal: the batched workload (N(0,1) entries) at one tolerance for the
+              batch, tol in --select-tols;
+      mixed:  the heterogeneous batch (workloads.zgemm_batch_mixed, drawn on
+              the GPU): every problem with its own structure from the
+              selector's instance distribution and its own tolerance,
+              log-uniform in [1e-15, 1e-4]."""
     import torch
 
     import paper_2503_22875_amd as oz
@@ -207,77 +361,29 @@ def bench_select(args):
     oz.oz_set_selector(h, net)
     results = []
     for dname in args.select_data.split(","):
-        problems = (workloads.zgemm_batch(512, seed=0) if dname == "normal"
-                    else workloads.zgemm_batch_spread(512, seed=0, sig_max=40))
-        cnt = len(problems)
-        ns = [A.shape[0] for A, _ in problems]
-        dev = [(torch.from_numpy(A.ravel(order="F")).cuda(), torch.from_numpy(B.ravel(order="F")).cuda(),
-                torch.zeros(A.shape[0] * B.shape[1], dtype=torch.complex128, device="cuda")) for A, B in problems]
-        del problems
-        flops = sum(8.0 * n ** 3 for n in ns)
-        # native products and scale weights for the error check
-        nat, wts = [], []
-        for (dA, dB, _), n in zip(dev, ns):
-            Ad = dA.view(n, n).t()  # column-major storage seen as a row-major transpose
-            Bd = dB.view(n, n).t()
-            nat.append(Ad @ Bd)
-            wa = torch.maximum(Ad.real.abs(), Ad.imag.abs()).amax(1)
-            wb = torch.maximum(Bd.real.abs(), Bd.imag.abs()).amax(0)
-            wts.append((1.0 / wa)[:, None] * (1.0 / wb)[None, :])
+        if dname == "mixed":
+            dev, ns, tols, _ = mixed_batch_on_device(oz, h, 512, seed=0)
+            cases = [("own", tols)]
+        else:
+            problems = workloads.zgemm_batch(512, seed=0)
+            ns = [A.shape[0] for A, _ in problems]
+            dev = [(torch.from_numpy(A.ravel(order="F")).cuda(), torch.from_numpy(B.ravel(order="F")).cuda(),
+                    torch.zeros(A.shape[0] * B.shape[1], dtype=torch.complex128, device="cuda"))
+                   for A, B in problems]
+            del problems
+            cases = [(t, [float(t)] * len(ns)) for t in args.select_tols.split(",")]
         torch.cuda.synchronize()
-
-        def true_errors():
-            errs = []
-            for (_, _, dC), n, C0, W in zip(dev, ns, nat, wts):
-                C = dC.view(n, n).t()
-                errs.append(float(torch.linalg.norm(W * (C - C0)) / torch.linalg.norm(W * C0)))
-            return np.array(errs)
-
-        def run(p, fixed=False):
-            plan = oz.oz_gemm_batched_plan(h, 1, "N" * cnt, "N" * cnt, ns, ns, ns, [1.0] * cnt,
-                                           [d[0] for d in dev], ns, [d[1] for d in dev], ns, [0.0] * cnt,
-                                           [d[2] for d in dev], ns, p=p)
-            try:
-                for _ in range(args.warmup):
-                    oz.oz_batch_execute(plan)
-                stream.synchronize()
-                times = []
-                for _ in range(args.steps):
-                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                    e0.record(stream)
-                    oz.oz_batch_execute(plan)
-                    e1.record(stream)
-                    stream.synchronize()
-                    times.append(e0.elapsed_time(e1))
-                reps = oz.oz_batch_report(plan, cnt)
-            finally:
-                oz.oz_batch_destroy(plan)
-            err = true_errors()
-            start = np.array([r.slices_used - r.fallbacks for r in reps])
-            final = np.array([r.slices_used for r in reps])
-            return float(np.median(times)), start, final, err, np.array([r.resid_est for r in reps])
-
-        for tol in [float(t) for t in args.select_tols.split(",")]:
-            row = {"data": dname, "tol": tol}
-            ms, st0, fin, err, est = run(oz.prec(0, tol=tol, smax=12, sstart=2))
-            s_fix = int(fin.max())
-            for name, p in (("escalate", None), ("rule", oz.prec(0, tol=tol, smax=12, selector=0)),
-                            ("learned", oz.prec(0, tol=tol, smax=12, selector=1)),
-                            ("fixed", oz.prec(s_fix) if s_fix <= 8 else oz.prec(0, tol=tol, smax=s_fix,
-                                                                                 sstart=s_fix))):
-                if p is not None:
-                    ms, st0, fin, err, est = run(p)
-                row[name] = {"ms": round(ms, 3), "tflops": round(flops / (ms * 1e-3) / 1e12, 2),
-                             "mean_start": round(float(st0.mean()), 3), "mean_final": round(float(fin.mean()), 3),
-                             "check_rounds": int((fin - st0).sum() + (cnt if name != "fixed" or s_fix > 8 else 0)),
-                             "pass_true": float(np.mean(err <= tol)), "worst_err": float(err.max())}
-                if name == "fixed":
-                    row[name]["s"] = s_fix
-            row["learned_speedup"] = {k: round(row[k]["ms"] / row["learned"]["ms"], 3)
-                                      for k in ("fixed", "rule", "escalate")}
+        flops = sum(8.0 * n ** 3 for n in ns)
+        for tname, tl in cases:
+            print("select: data %s, tol %s" % (dname, tname), flush=True)
+            row = {"data": dname, "tol": tname}
+            row.update(selection_gain(oz, h, stream, dev, ns, tl, steps=args.steps, warmup=args.warmup))
+            for k in ("fixed", "rule", "escalate", "learned"):
+                if k in row:
+                    row[k]["tflops"] = round(flops / (row[k]["ms"] * 1e-3) / 1e12, 2)
             print(json.dumps(row), flush=True)
             results.append(row)
-        del dev, nat, wts
+        del dev
         torch.cuda.empty_cache()
     oz.oz_set_selector(h, None)
     oz.oz_mlp_destroy(net)
@@ -409,6 +515,93 @@ def bench_wide_tol(args):
                       % ("balanced" if dig else "truncated"),
                       "native_ms": round(nms, 4), "native_tflops": round(flops / (nms * 1e-3) / 1e12, 2),
                       "rows": rows}), flush=True)
+
+
+def bench_dgemm(args):
+    """Real DGEMM C = A*B, m = n = k = --n (4096), entries U(-1, 1) * 2^randint(-4, 4)
+    (the 256^3 case's recipe at full size), emulated with --slices (6) and
+    --digits (balanced): the smallest configuration whose scale-weighted error
+    against the double-double product is below 1e-12 on this data (balanced
+    s = 5: 4.8e-11, truncated s = 6: 6.5e-12, truncated s = 7: 6e-14).  Same
+    report as the ZGEMM line: effective rate 2 n^3 / time, the GEMM kernel's
+    roofline, native float64 matmul (rocBLAS dgemm) with its error, and the
+    oracle on a sample of rows."""
+    import torch
+
+    import paper_2503_22875_amd as oz
+    import workloads
+
+    n, s = args.n, args.slices
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    A, B = workloads.dgemm_uniform(n, n, n, seed=0)
+    dA = torch.from_numpy(A.ravel(order="F")).cuda()
+    dB = torch.from_numpy(B.ravel(order="F")).cuda()
+    dC = torch.zeros(n * n, dtype=torch.float64, device="cuda")
+    h = oz.oz_create(0)
+    oz.oz_set_stream(h, stream.cuda_stream)
+    p = oz.prec(s, kernel=args.kernel, digits=args.digits)
+
+    def step():
+        oz.oz_dgemm(h, "N", "N", n, n, n, 1.0, dA, n, dB, n, 0.0, dC, n, p)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    oz.oz_timing_enable(h, True)
+    oz.oz_timing_read(h)
+    ms = _time_ms(step, stream, args.steps, 0)
+    split_ms, gemm_ms, calls = oz.oz_timing_read(h)
+    oz.oz_timing_enable(h, False)
+    flops = 2.0 * n ** 3
+    int8_ops = pairs(s) * 2.0 * n ** 3
+    gemm_avg_ms = gemm_ms / calls
+    achieved = int8_ops / (gemm_avg_ms * 1e-3) / 1e12
+    C_gpu = dC.cpu().numpy().reshape(n, n, order="F")
+    digits = "balanced digits" if args.digits == 1 else "truncated digits"
+    out = {"metric": METRIC, "workload": "dgemm n=%d s=%d %s (entries U(-1,1) * 2^randint(-4,4))" % (n, s, digits),
+           "ms": round(ms, 4), "tflops": round(flops / (ms * 1e-3) / 1e12, 3),
+           "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": INT8_PEAK_TOPS, "unit": "TFLOP/s",
+                        "frac": round(achieved / INT8_PEAK_TOPS, 4), "avg_ms": round(gemm_avg_ms, 4),
+                        "split_avg_ms": round(split_ms / calls, 4)}}
+    tA, tB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    res = {}
+    nms = _time_ms(lambda: res.__setitem__("C", tA @ tB), stream, args.steps, 3)
+    Cn = res["C"].cpu().numpy()
+    out["native_fp64"] = {"tflops": round(flops / (nms * 1e-3) / 1e12, 3), "ms": round(nms, 4),
+                          "kind": "torch float64 matmul (rocBLAS dgemm)"}
+    out["speedup_vs_native"] = round(nms / ms, 3)
+    if not args.no_cpu:
+        cb = cpu_baseline(A, B, s, C_gpu, args.cpu_rows, balanced=args.digits == 1, C_native=Cn)
+        out["cpu_baseline"] = cb
+        out["meets_tolerance"] = bool(cb["rel_err_vs_double_double"] <= 1e-12)
+    oz.oz_destroy(h)
+    print(json.dumps(out), flush=True)
+
+
+def bench_peaks(args):
+    """The rates the roofline fractions divide by, measured by the library's
+    own microbenchmarks (oz_peak): INT8 MFMA (v_mfma_i32_32x32x32_i8), FP64
+    MFMA (v_mfma_f64_16x16x4_f64) and a 1 GiB device copy; best of --steps."""
+    import torch
+
+    import paper_2503_22875_amd as oz
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    h = oz.oz_create(0)
+    oz.oz_set_stream(h, stream.cuda_stream)
+    src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    i8 = max(oz.oz_peak(h, 0, 20000) for _ in range(args.steps))
+    f64 = max(oz.oz_peak(h, 1, 20000) for _ in range(args.steps))
+    cp = max(oz.oz_peak(h, 2, 10, src, dst, src.numel() * 8) for _ in range(args.steps))
+    oz.oz_destroy(h)
+    print(json.dumps({"workload": "peaks", "int8_mfma_tops": round(i8 / 1e12, 1),
+                      "int8_vendor_tops": INT8_PEAK_TOPS, "fp64_mfma_tflops": round(f64 / 1e12, 2),
+                      "fp64_vendor_tflops": 78.6, "copy_gbs": round(cp / 1e9, 1), "hbm_vendor_gbs": 8000.0,
+                      "copy_bytes": src.numel() * 8}), flush=True)
 
 
 def bench_blas(args):
@@ -626,7 +819,9 @@ def bench_balanced(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="zgemm4096", choices=["zgemm4096", "batch512", "select", "sweep", "wide_tol", "blas", "x2", "inv", "balanced"])
+    ap.add_argument("--workload", default="zgemm4096",
+                    choices=["zgemm4096", "dgemm", "peaks", "batch512", "select", "sweep", "wide_tol", "blas", "x2",
+                             "inv", "balanced"])
     ap.add_argument("--nb", type=int, default=128, help="panel width of the inversion workload (getrf)")
     ap.add_argument("--nb-inv", type=int, default=256, help="block rows of the inversion workload's solves (getri)")
     ap.add_argument("--inv-slices", default="3,4,5,6,7,8,14")
@@ -634,10 +829,10 @@ def main():
                     help="inversion rows with balanced digits in every product (slice counts)")
     ap.add_argument("--inv-tols", default="1e-8,1e-10,1e-12",
                     help="tolerance-driven rows of the inversion workload (each product picks its own s)")
-    ap.add_argument("--select-data", default="normal,spread")
+    ap.add_argument("--select-data", default="mixed,normal")
     ap.add_argument("--select-tols", default="1e-10,1e-12,1e-14")
     ap.add_argument("--sweep-n", default="2048,4096")
-    ap.add_argument("--wide-tols", default="1e-6,1e-10,1e-14")
+    ap.add_argument("--wide-tols", default="1e-6,1e-10,1e-12,1e-14")
     ap.add_argument("--wide-digits", type=int, default=0, choices=[0, 1],
                     help="wide_tol workload: 1 = balanced digits (smax 8)")
     ap.add_argument("--gpus", type=int, default=1)
@@ -660,6 +855,10 @@ def main():
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "dgemm":
+        return bench_dgemm(args)
+    if args.workload == "peaks":
+        return bench_peaks(args)
     if args.workload == "batch512":
         return bench_batch(args)
     if args.workload == "select":
@@ -786,7 +985,8 @@ def main():
         torch.cuda.synchronize()
         del x, y
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(A, B, s, C_gpu, args.cpu_rows, args.zmode, args.digits == 1)
+        out["cpu_baseline"] = cpu_baseline(A, B, s, C_gpu, args.cpu_rows, args.zmode, args.digits == 1,
+                                           C_native=None if args.no_native else Cn)
     oz.oz_destroy(h)
     print(json.dumps(out), flush=True)
 

@@ -65,11 +65,14 @@ typedef struct oz_handle_s* oz_handle_t;
  *  tol    : target when slices == 0 (must then be > 0): the scale-weighted
  *           relative error || D1 (C - AB) D2 ||_F / || D1 AB D2 ||_F with
  *           D1 = diag(1 / max|op(A)_i:|), D2 = diag(1 / max|op(B)_:j|), on
- *           the product before alpha/beta.  The call picks a starting s by a
- *           rule on operand statistics (oz_select_slices), emulates, checks
- *           the result a posteriori with a randomised double-double residual,
- *           and while the estimate exceeds tol adds one slice (the next digit
- *           and the next anti-diagonal, added last) up to smax.  Sec. 4 of
+ *           the product before alpha/beta.  The call picks a starting s for
+ *           tol/2 by a rule on operand statistics (oz_select_slices) or the
+ *           learned selector, emulates, checks the result a posteriori with a
+ *           randomised double-double residual, and while the estimate exceeds
+ *           tol/2 adds one slice (the next digit and the next anti-diagonal,
+ *           added last) up to smax.  The one-probe estimate lies within about
+ *           0.7x .. 1.4x of the true error, so the margin of 2 keeps the true
+ *           error within tol.  Sec. 4 of
  *           the paper motivates adjusting the split number to the operator.
  *           Tolerance-driven calls synchronise their stream.
  *  smax   : largest s the tol-driven selection may use (0: 12).
@@ -422,8 +425,8 @@ int oz_mlp_train_step(oz_mlp_t mlp, int64_t rows, const float* X, const float* t
  * receives the mean loss of each pass.  Synchronous. */
 int oz_mlp_train(oz_mlp_t mlp, int64_t rows, const float* X, const float* t, int32_t epochs, int32_t batch,
                  float tau, float lr, uint64_t seed, float* epoch_loss);
-/* Binary file: 8-byte magic "OZMLP001", int32 16, 64, 5313, then mu[16],
- * sd[16] and the parameters as little-endian floats. */
+/* Binary file: 8-byte magic "OZMLP001", int32 16, 64, 5313, then the 5313
+ * parameters, mu[16] and sd[16] as little-endian floats. */
 int oz_mlp_save(oz_mlp_t mlp, const char* path);
 int oz_mlp_load(oz_handle_t handle, const char* path, oz_mlp_t* mlp);
 
@@ -438,6 +441,20 @@ int oz_set_selector(oz_handle_t handle, oz_mlp_t mlp);
 int oz_predict_slices(oz_handle_t handle, char transa, char transb, int64_t m, int64_t n, int64_t k,
                       int is_complex, const double* A, int64_t lda, const double* B, int64_t ldb, double tol,
                       int32_t smax, int32_t* s_out);
+
+/* ---- Measured peaks -------------------------------------------------------
+ *
+ * Rates of this GPU that roofline reports divide by, measured by the
+ * library's own microbenchmarks on the handle's stream (synchronises):
+ *  kind 0: INT8 matrix cores, back-to-back v_mfma_i32_32x32x32_i8 on every
+ *          SIMD, iters instructions per accumulator chain -> ops per second;
+ *  kind 1: FP64 matrix cores, v_mfma_f64_16x16x4_f64 -> flops per second;
+ *  kind 2: device copy of `bytes` (a multiple of 16) from src to dst (device
+ *          buffers of the caller), iters repetitions -> bytes read plus bytes
+ *          written per second.
+ * src, dst and bytes are ignored for kinds 0 and 1.  OZ_ERR_ARG for a bad
+ * kind, iters < 1, a NULL rate, or a bad copy buffer. */
+int oz_peak(oz_handle_t handle, int kind, int64_t iters, const void* src, void* dst, size_t bytes, double* rate);
 
 /* ---- Batched products ----------------------------------------------------
  *
@@ -467,7 +484,8 @@ int oz_gemm_batched_plan(oz_handle_t handle, int is_complex, int32_t batch, cons
                          const char* transb, const int64_t* m, const int64_t* n, const int64_t* k,
                          const double* alpha, const double* const* A, const int64_t* lda,
                          const double* const* B, const int64_t* ldb, const double* beta, double* const* C,
-                         const int64_t* ldc, const oz_prec_t* prec, const int32_t* slices, oz_batch_t* plan);
+                         const int64_t* ldc, const oz_prec_t* prec, const int32_t* slices, const double* tols,
+                         oz_batch_t* plan);
 int oz_batch_execute(oz_batch_t plan);
 /* Replay the captured execution (fixed slice counts only; a tolerance-driven
  * plan returns OZ_ERR_ARG). */
@@ -475,14 +493,15 @@ int oz_batch_graph_launch(oz_batch_t plan);
 int oz_batch_destroy(oz_batch_t plan);
 /* Tolerance-driven batches: prec->slices == 0 with prec->tol > 0 (slices
  * array NULL) plans every problem as a tolerance-driven oz_dgemm / oz_zgemm
- * call with the same tol, smax (0: 12, up to OZ_MAX_SLICES), sstart and
- * selector.  An execution then runs: the batched split with smax digit planes;
+ * call with its own tolerance -- tols[b] (every entry > 0) when the array is
+ * given, else prec->tol -- and the same smax (0: 12, up to OZ_MAX_SLICES),
+ * sstart and selector; tols given with a fixed slice count returns 14.  An execution then runs: the batched split with smax digit planes;
  * the starting s of every problem (sstart, or one batched statistics pass and
  * the rule or the handle's learned selector); raw sums at those s (problems
  * grouped by s, one persistent launch per group: the all-diagonal kernel for
  * s <= 8, the streaming kernel above); then rounds of a batched residual check over the
  * problems still open and one more slice (digit already split, next
- * anti-diagonal added last) for those whose estimate exceeds tol, until all
+ * anti-diagonal added last) for those whose estimate exceeds tol/2, until all
  * pass or reach smax; finally one batched scaling pass into C.  Each problem's
  * result is bit-identical to the single tolerance-driven call that starts at
  * the same s.  The execution synchronises the stream at every round. */

@@ -40,7 +40,7 @@ EXPORTS = ["oz_create", "oz_destroy", "oz_set_stream", "oz_status_string", "oz_w
            "oz_mlp_destroy", "oz_mlp_set_params", "oz_mlp_get_params", "oz_mlp_fit_norm", "oz_mlp_forward",
            "oz_mlp_grad", "oz_mlp_train_step", "oz_mlp_train", "oz_mlp_save", "oz_mlp_load", "oz_set_selector",
            "oz_predict_slices", "oz_batch_report", "oz_dgemm_x2", "oz_zgemm_x2", "oz_zgetrf", "oz_zgetri",
-           "oz_gemm_noalloc"]
+           "oz_gemm_noalloc", "oz_peak"]
 
 OZ_NUM_FEATURES = 16
 OZ_MLP_NPARAM = 5313
@@ -105,7 +105,7 @@ def _load():
         "oz_timing_read": [P, PP(D), PP(D), PP(I64)],
         "oz_select_slices": [P, C, C, I64, I64, I64, ctypes.c_int, P, I64, P, I64, D, I32, PP(I32)],
         "oz_gemm_batched_plan": [P, ctypes.c_int, I32, P, P, P, P, P, P, P, P, P, P, P, P, P, PP(oz_prec_t), P,
-                                 PP(P)],
+                                 P, PP(P)],
         "oz_batch_execute": [P],
         "oz_batch_graph_launch": [P],
         "oz_batch_destroy": [P],
@@ -130,6 +130,7 @@ def _load():
         "oz_mlp_load": [P, ctypes.c_char_p, PP(P)],
         "oz_set_selector": [P, P],
         "oz_predict_slices": [P, C, C, I64, I64, I64, ctypes.c_int, P, I64, P, I64, D, I32, PP(I32)],
+        "oz_peak": [P, ctypes.c_int, I64, P, P, ctypes.c_size_t, PP(D)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -338,10 +339,12 @@ def _batch_args(is_complex, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta
 
 
 def oz_gemm_batched_plan(handle, is_complex, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, p=None,
-                         slices=None):
+                         slices=None, tols=None):
     """Plan a batch (host lists of per-problem arguments); returns the plan handle.
-    transa / transb: strings or lists of one character per problem."""
+    transa / transb: strings or lists of one character per problem; tols: one
+    tolerance per problem (tolerance-driven plans)."""
     nb, a = _batch_args(is_complex, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, slices)
+    tl = (ctypes.c_double * nb)(*[float(t) for t in tols]) if tols is not None else None
     plan = ctypes.c_void_p()
     _check("oz_gemm_batched_plan", _lib.oz_gemm_batched_plan(
         handle, int(is_complex), nb, ctypes.cast(a["ta"], ctypes.c_void_p), ctypes.cast(a["tb"], ctypes.c_void_p),
@@ -351,7 +354,8 @@ def oz_gemm_batched_plan(handle, is_complex, transa, transb, m, n, k, alpha, A, 
         ctypes.cast(a["B"], ctypes.c_void_p), ctypes.cast(a["ldb"], ctypes.c_void_p),
         ctypes.cast(a["beta"], ctypes.c_void_p), ctypes.cast(a["C"], ctypes.c_void_p),
         ctypes.cast(a["ldc"], ctypes.c_void_p), ctypes.byref(p) if p is not None else None,
-        ctypes.cast(a["slices"], ctypes.c_void_p) if a["slices"] is not None else None, ctypes.byref(plan)))
+        ctypes.cast(a["slices"], ctypes.c_void_p) if a["slices"] is not None else None,
+        ctypes.cast(tl, ctypes.c_void_p) if tl is not None else None, ctypes.byref(plan)))
     return plan
 
 
@@ -545,4 +549,13 @@ def oz_predict_slices(handle, transa, transb, m, n, k, is_complex, A, lda, B, ld
     _check("oz_predict_slices", _lib.oz_predict_slices(handle, _ch(transa), _ch(transb), m, n, k, int(is_complex),
                                                         _ptr(A), lda, _ptr(B), ldb, float(tol), smax,
                                                         ctypes.byref(out)))
+    return out.value
+
+
+def oz_peak(handle, kind, iters, src=None, dst=None, nbytes=0):
+    """Measured rate: kind 0 INT8 MFMA ops/s, 1 FP64 MFMA flop/s, 2 device copy
+    bytes/s (read + written) from src to dst."""
+    out = ctypes.c_double()
+    _check("oz_peak", _lib.oz_peak(handle, int(kind), int(iters), _ptr(src), _ptr(dst), int(nbytes),
+                                   ctypes.byref(out)))
     return out.value

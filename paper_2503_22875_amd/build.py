@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "liboz.so")
 BLAS_LIB = os.path.join(HERE, "liboz_blas.so")
 BLAS_SOURCE = "oz_blas.cpp"
 SOURCES = ["oz_split.hip", "oz_gemm.hip", "oz_check.hip", "oz_api.hip", "oz_batch.hip", "oz_select.hip",
-           "oz_mlp.hip", "oz_learn.hip", "oz_lu.hip"]
+           "oz_mlp.hip", "oz_learn.hip", "oz_lu.hip", "oz_peak.hip"]
 HEADERS = ["oz_internal.h", os.path.join("..", "..", "include", "oz.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

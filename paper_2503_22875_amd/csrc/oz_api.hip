@@ -546,18 +546,19 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
         if (e == hipSuccess) e = mark(h);
         if (e != hipSuccess) return OZ_ERR_HIP;
     } else {
-        // (1) starting s from the operand statistics
+        // (1) starting s from the operand statistics, for the checked target
+        const double tol_eff = tol / oz::kCheckMargin;
         double* msa = reinterpret_cast<double*>(ws + p.off_msa);
         double* msb = reinterpret_cast<double*>(ws + p.off_msb);
         if (prec->sstart > 0) {
             s = prec->sstart;
         } else if (prec->selector == 1) {
-            st = oz_learned_start(h, h->selector, va, vb, maxa, maxb, msa, msb, m, n, k, cplx, tol, smax,
+            st = oz_learned_start(h, h->selector, va, vb, maxa, maxb, msa, msb, m, n, k, cplx, tol_eff, smax,
                                   ws + p.off_sel, &s);
             if (st) return st;
         } else {
-            st = rule_slices(h, va, vb, maxa, maxb, msa, msb, reinterpret_cast<double*>(ws + p.off_part1), tol, smax,
-                             &s, bal);
+            st = rule_slices(h, va, vb, maxa, maxb, msa, msb, reinterpret_cast<double*>(ws + p.off_part1), tol_eff,
+                             smax, &s, bal);
             if (st) return st;
         }
         // the learned start is trained on truncated digits; balanced digits
@@ -601,7 +602,7 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
                 hipStreamSynchronize(h->stream) != hipSuccess)
                 return OZ_ERR_HIP;
             eps = nrm[1] > 0.0 ? std::sqrt(nrm[0] / nrm[1]) : std::sqrt(nrm[0]);
-            if (!(eps > tol) || s >= smax) break;  // NaN (non-finite input) also stops
+            if (!(eps > tol_eff) || s >= smax) break;  // NaN (non-finite input) also stops
             if (bal) {
                 // balanced digits depend on s: split again at s + 1 and
                 // recompute the raw sums (no incremental growth)

@@ -27,9 +27,14 @@ constexpr int kDefaultSmax = 12;
 
 constexpr uint32_t kBatchMagic = 0x6f7a6274u;  // "ozbt"
 
+// Launch kinds of a group: the all-diagonal tile of one s on 128 x 64 or
+// 64 x 64 blocks, the streaming body, the 64 x 64 tile of mixed slice counts
+// (s <= 8, each problem its own), the wide tile (9 <= s <= 14).
+constexpr int kTile128 = 1, kTile64 = 2, kStream = 3, kMixed = 4, kWide = 5;
+
 struct Group {
-    int s;
-    int tile;       // 1: 128 x 64, 2: 64 x 64
+    int s;          // 0 for a mixed group
+    int tile;       // launch kind (kTile128 ... kWide)
     int blocks;     // persistent grid
     bool multi;     // some problem spans several INT32 chunks
     int64_t nitems;
@@ -65,6 +70,7 @@ struct oz_batch_s {
     double tol;
     int smax, sstart, selector, kernel, cplx, cus;
     std::vector<int32_t> prob_b;          // plan problem -> batch index
+    std::vector<double> tols;             // tolerance per plan problem
     std::vector<oz::GemmArgs> host_args;  // raw-write descriptors (host copies)
     size_t off_args_add;                  // raw-add descriptors
     size_t off_stat_sides, off_stat_items, off_hist, off_fp, off_feat, off_y, off_s, off_tols;
@@ -114,10 +120,11 @@ oz::OperandView view(char t, const double* X, int64_t ld, int64_t nv, int64_t k,
 }
 
 // One persistent launch over the tiles of `members` (indices into args), all
-// with slice count sv: block shape as requested (kernel 1 / 2), else the tuned
-// vote, else 128 x 64 when the group has at least two such tiles per compute
-// unit; tile order 0 (problems with the most work per tile first) or 1
-// (whole problems dealt to per-XCD queues) as tuned.
+// with slice count sv (sv = 0: a mixed group, each problem at its own
+// args[i].s): launch kind as requested (kernel 1 / 2, or kStream, kMixed,
+// kWide), else the tuned vote, else 128 x 64 when the group has at least two
+// such tiles per compute unit; tile order 0 (problems with the most work per
+// tile first) or 1 (whole problems dealt to per-XCD queues) as tuned.
 void build_group(const std::vector<oz::GemmArgs>& args, std::vector<size_t> members, int sv, int kernel, int cplx,
                  int cus, const std::vector<oz::TuneEntry>& tune, Group* out, std::vector<oz::TileItem>* out_items) {
     // tuned choice for one problem: the entry with the same complexity and s
@@ -158,16 +165,22 @@ void build_group(const std::vector<oz::GemmArgs>& args, std::vector<size_t> memb
     int tile = kernel;
     if (!tile) tile = have_tune ? (vote_tile[1] > vote_tile[2] ? 1 : 2) : (big >= 2 * cus ? 1 : 2);
     const int order = have_tune && vote_order[1] > vote_order[0] ? 1 : 0;
-    const int64_t bm = tile == 1 ? 128 : 64, bn = 64;
-    std::stable_sort(members.begin(), members.end(), [&](size_t a, size_t b) { return args[a].kpad > args[b].kpad; });
+    const int64_t bm = tile == kTile128 ? 128 : 64, bn = 64;
+    // work of one tile: slice pairs times steps
+    auto tile_work = [&](size_t i) {
+        const int64_t si = args[i].s;
+        return static_cast<double>(si * (si + 1) / 2) * static_cast<double>(args[i].kpad);
+    };
+    std::stable_sort(members.begin(), members.end(), [&](size_t a, size_t b) { return tile_work(a) > tile_work(b); });
     auto tiles_of = [&](size_t i, std::vector<oz::TileItem>& dst) {
         for (int64_t tm = 0; tm < args[i].Mp / bm; ++tm)
             for (int64_t tn = 0; tn < args[i].Np / bn; ++tn)
-                dst.push_back({static_cast<int32_t>(i), static_cast<int32_t>(tm), static_cast<int32_t>(tn), 0});
+                dst.push_back({static_cast<int32_t>(i), static_cast<int32_t>(tm), static_cast<int32_t>(tn),
+                               static_cast<int32_t>(args[i].s)});
     };
     std::vector<oz::TileItem>& items = *out_items;
     items.clear();
-    const int64_t per_cu = tile == 1 ? 1 : 2;  // blocks resident per compute unit
+    const int64_t per_cu = (tile == kTile128 || tile == kWide) ? 1 : 2;  // blocks resident per compute unit
     if (order == 0) {
         for (size_t i : members) tiles_of(i, items);
     } else {
@@ -183,7 +196,7 @@ void build_group(const std::vector<oz::GemmArgs>& args, std::vector<size_t> memb
             for (int y = 1; y < kX; ++y)
                 if (load[y] < load[x]) x = y;
             tiles_of(i, q[x]);
-            load[x] += static_cast<double>(args[i].Mp / bm) * (args[i].Np / bn) * args[i].kpad;
+            load[x] += static_cast<double>(args[i].Mp / bm) * (args[i].Np / bn) * tile_work(i);
         }
         size_t longest = 0;
         for (int x = 0; x < kX; ++x) longest = std::max(longest, q[x].size());
@@ -201,6 +214,59 @@ void build_group(const std::vector<oz::GemmArgs>& args, std::vector<size_t> memb
     gr.off_items = 0;
 }
 
+// Launch of one group (any kind) over its tile list.
+hipError_t launch_group(const Group& gr, const oz::GemmArgs* dargs, const oz::TileItem* items, bool top,
+                        hipStream_t st) {
+    switch (gr.tile) {
+        case kStream: return oz::launch_gemm_stream_persistent(dargs, items, gr.nitems, gr.s, top, gr.blocks, st);
+        case kMixed: return oz::launch_gemm_persistent_mixed(dargs, items, gr.nitems, gr.blocks, top, gr.multi, st);
+        case kWide: return oz::launch_gemm_wide_persistent(dargs, items, gr.nitems, gr.s, gr.blocks, top, gr.multi, st);
+        default:
+            return oz::launch_gemm_persistent(dargs, items, gr.nitems, gr.s, gr.tile, gr.blocks, top, gr.multi, st);
+    }
+}
+
+// Groups of one GEMM round over `members` (slice counts s_of(i)): every
+// problem with s <= 8 in one mixed 64 x 64 launch (or, with a single such s,
+// the tuned block shape for it), one wide launch per s in 9..14, one
+// streaming launch per larger s.
+template <class SOf>
+void round_groups(const std::vector<oz::GemmArgs>& args, const std::vector<size_t>& members, SOf s_of, int kernel,
+                  int cplx, int cus, const std::vector<oz::TuneEntry>& tune, std::vector<Group>* groups,
+                  std::vector<std::vector<oz::TileItem>>* items) {
+    std::vector<int> svals;
+    std::vector<size_t> low;
+    for (size_t i : members) {
+        const int s = s_of(i);
+        if (s <= oz::kMaxLiveSlices) low.push_back(i);
+        if (std::find(svals.begin(), svals.end(), s) == svals.end()) svals.push_back(s);
+    }
+    std::sort(svals.begin(), svals.end());
+    int nlow = 0;
+    for (int sv : svals) nlow += sv <= oz::kMaxLiveSlices ? 1 : 0;
+    for (int sv : svals) {
+        if (sv <= oz::kMaxLiveSlices && nlow > 1) continue;  // in the mixed group below
+        std::vector<size_t> mem;
+        for (size_t i : members)
+            if (s_of(i) == sv) mem.push_back(i);
+        const int kind = sv <= oz::kMaxLiveSlices ? kernel : (sv <= oz::kMaxWideSlices ? kWide : kStream);
+        Group gr;
+        std::vector<oz::TileItem> it;
+        build_group(args, mem, sv, kind, cplx, cus, tune, &gr, &it);
+        gr.tile = kind ? kind : gr.tile;
+        groups->push_back(gr);
+        items->push_back(std::move(it));
+    }
+    if (nlow > 1) {
+        Group gr;
+        std::vector<oz::TileItem> it;
+        build_group(args, low, 0, kMixed, cplx, cus, tune, &gr, &it);
+        groups->push_back(gr);
+        items->push_back(std::move(it));
+    }
+}
+
+
 }  // namespace
 
 extern "C" {
@@ -209,7 +275,7 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
                          const int64_t* m, const int64_t* n, const int64_t* k, const double* alpha,
                          const double* const* A, const int64_t* lda, const double* const* B, const int64_t* ldb,
                          const double* beta, double* const* C, const int64_t* ldc, const oz_prec_t* prec,
-                         const int32_t* slices, oz_batch_t* plan_out) {
+                         const int32_t* slices, const double* tols, oz_batch_t* plan_out) {
     if (!oz_handle_valid(h)) return OZ_ERR_HANDLE;
     if (!plan_out || batch < 0 || !transa || !transb || !m || !n || !k || !alpha || !A || !lda || !B || !ldb ||
         !beta || !C || !ldc)
@@ -238,14 +304,18 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
                 return 14;
             if (selector == 1 && sstart == 0 && !oz_mlp_valid(oz_handle_selector(h))) return OZ_ERR_ARG;
             s_default = smax;  // digit planes held for growth
+            if (tols)
+                for (int32_t b = 0; b < batch; ++b)
+                    if (!(tols[b] > 0.0)) return 14;
         } else {
-            if (prec->slices < 1 || prec->slices > oz::kMaxLiveSlices) return 14;  // fixed s per problem, s <= 8
+            if (prec->slices < 1 || prec->slices > oz::kMaxWideSlices) return 14;  // fixed s per problem, s <= 14
             s_default = prec->slices;
         }
         kernel = prec->kernel;
         kc_forced = prec->kchunk;
         bal = prec->digits == 1;
     }
+    if (tols && !tol_mode) return 14;  // per-problem tolerances: tolerance-driven plans only
     // argument checks per problem (reference-BLAS positions)
     for (int32_t b = 0; b < batch; ++b) {
         if (!trans_ok(transa[b])) return 1;
@@ -259,7 +329,8 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
         if (ldb[b] < (rb > 1 ? rb : 1)) return 10;
         if (ldc[b] < (m[b] > 1 ? m[b] : 1)) return 13;
         const int sb = slices ? slices[b] : s_default;
-        if (sb < 1 || sb > (tol_mode ? OZ_MAX_SLICES : oz::kMaxLiveSlices)) return 14;
+        if (sb < 1 || sb > (tol_mode ? OZ_MAX_SLICES : oz::kMaxWideSlices)) return 14;
+        if (bal && sb > oz::kMaxLiveSlices) return 14;  // balanced digits: s <= 8
         if (kc_forced < 0 || kc_forced % 64 != 0 || (kc_forced > 0 && kc_forced > kchunk_bound(sb, bal))) return 14;
     }
     if (oz_handle_use_device(h)) return OZ_ERR_HIP;
@@ -328,6 +399,7 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
         n_max += n[b];
         probs.push_back(q);
         P->prob_b.push_back(b);
+        P->tols.push_back(tols ? tols[b] : tol);
         P->slices[b] = tol_mode ? 0 : q.s;
     }
     P->off_maxbits = take(static_cast<size_t>(n_max) * 8);
@@ -438,20 +510,10 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
     }
     std::vector<std::vector<oz::TileItem>> group_items;
     if (!tol_mode) {
-        std::vector<int> svals;
-        for (const Prob& q : probs)
-            if (std::find(svals.begin(), svals.end(), q.s) == svals.end()) svals.push_back(q.s);
-        std::sort(svals.begin(), svals.end());
-        for (int sv : svals) {
-            std::vector<size_t> members;
-            for (size_t i = 0; i < probs.size(); ++i)
-                if (probs[i].s == sv) members.push_back(i);
-            Group gr;
-            std::vector<oz::TileItem> items;
-            build_group(args, members, sv, kernel, cplx, cus, oz_handle_tuning(h), &gr, &items);
-            P->groups.push_back(gr);
-            group_items.push_back(std::move(items));
-        }
+        std::vector<size_t> members(probs.size());
+        for (size_t i = 0; i < probs.size(); ++i) members[i] = i;
+        round_groups(args, members, [&](size_t i) { return probs[i].s; }, kernel, cplx, cus, oz_handle_tuning(h),
+                     &P->groups, &group_items);
     }
     // descriptors after the workspace
     P->off_ops = take(sizeof(oz::SplitOp) * ops.size());
@@ -629,7 +691,6 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
     for (size_t gi = 0; gi < P->groups.size(); ++gi)
         up_load(P->groups[gi].off_items, group_items[gi].data(), sizeof(oz::TileItem) * group_items[gi].size());
     if (tol_mode) {
-        const std::vector<double> tolv(nprob, tol);
         up_load(P->off_args_add, args_add.data(), sizeof(oz::GemmArgs) * nprob);
         up_load(P->off_stat_sides, stat_sides.data(), sizeof(oz::StatSide) * stat_sides.size());
         up_load(P->off_stat_items, stat_items.data(), sizeof(oz::BlockItem) * stat_items.size());
@@ -640,7 +701,10 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
         up_load(P->off_row, row_items.data(), sizeof(oz::BlockItem) * row_items.size());
         up_load(P->off_final, finals.data(), sizeof(oz::FinalArgs) * nprob);
         up_load(P->off_final_items, fin_items.data(), sizeof(oz::BlockItem) * fin_items.size());
-        up_load(P->off_tols, tolv.data(), sizeof(double) * nprob);
+        // the selection (features, rule) targets the checked tolerance
+        std::vector<double> tol_eff(P->tols);
+        for (double& t : tol_eff) t /= oz::kCheckMargin;
+        up_load(P->off_tols, tol_eff.data(), sizeof(double) * nprob);
     }
     if (e != hipSuccess) {
         hipFree(P->dev);
@@ -657,33 +721,23 @@ namespace {
 
 // One round of GEMM work of a tolerance-driven plan: every listed problem at
 // its current slice count, raw-write (first round) or only the new
-// anti-diagonal added to the raw sums (growth).  Problems are grouped by s,
-// one persistent launch per group: the all-diagonal kernel for s <= 8, the
-// streaming kernel above.
+// anti-diagonal added to the raw sums (growth), in the launches of
+// round_groups.
 int tol_round(oz_batch_t P, const std::vector<size_t>& members, bool growth, hipStream_t st) {
     char* dev = static_cast<char*>(P->dev);
     const oz::GemmArgs* dargs =
         reinterpret_cast<const oz::GemmArgs*>(dev + (growth ? P->off_args_add : P->off_args));
-    std::vector<int> svals;
-    for (size_t i : members)
-        if (std::find(svals.begin(), svals.end(), P->s_cur[i]) == svals.end()) svals.push_back(P->s_cur[i]);
-    std::sort(svals.begin(), svals.end());
-    std::vector<oz::TileItem> all;
+    // the descriptors on the device carry the planned s: the round's s is set per problem below
+    std::vector<oz::GemmArgs> cur(P->host_args);
+    for (size_t i : members) cur[i].s = P->s_cur[i];
     std::vector<Group> groups;
-    for (int sv : svals) {
-        std::vector<size_t> mem;
-        for (size_t i : members)
-            if (P->s_cur[i] == sv) mem.push_back(i);
-        // above the all-diagonal kernel's register budget: the streaming body on 64 x 64 tiles
-        const bool stream = sv > oz::kMaxLiveSlices;
-        Group gr;
-        std::vector<oz::TileItem> items;
-        build_group(P->host_args, mem, sv, stream ? 2 : P->kernel, P->cplx, P->cus, oz_handle_tuning(P->h), &gr,
-                    &items);
-        gr.tile = stream ? 3 : gr.tile;
-        gr.off_items = all.size();
-        all.insert(all.end(), items.begin(), items.end());
-        groups.push_back(gr);
+    std::vector<std::vector<oz::TileItem>> gitems;
+    round_groups(cur, members, [&](size_t i) { return P->s_cur[i]; }, P->kernel == 1 ? 1 : 0, P->cplx, P->cus,
+                 oz_handle_tuning(P->h), &groups, &gitems);
+    std::vector<oz::TileItem> all;
+    for (size_t g = 0; g < groups.size(); ++g) {
+        groups[g].off_items = all.size();
+        all.insert(all.end(), gitems[g].begin(), gitems[g].end());
     }
     if (groups.empty()) return OZ_OK;
     if (static_cast<int64_t>(all.size()) > P->dyn_cap) return OZ_ERR_ALLOC;
@@ -693,14 +747,8 @@ int tol_round(oz_batch_t P, const std::vector<size_t>& members, bool growth, hip
             hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
         return OZ_ERR_HIP;
-    for (const Group& gr : groups) {
-        const hipError_t e =
-            gr.tile == 3 ? oz::launch_gemm_stream_persistent(dargs, ditems + gr.off_items, gr.nitems, gr.s, growth,
-                                                             gr.blocks, st)
-                         : oz::launch_gemm_persistent(dargs, ditems + gr.off_items, gr.nitems, gr.s, gr.tile,
-                                                      gr.blocks, growth, gr.multi, st);
-        if (e != hipSuccess) return OZ_ERR_HIP;
-    }
+    for (const Group& gr : groups)
+        if (launch_group(gr, dargs, ditems + gr.off_items, growth, st) != hipSuccess) return OZ_ERR_HIP;
     return OZ_OK;
 }
 
@@ -792,7 +840,7 @@ int execute_tol(oz_batch_t P) {
             const double n0 = norms[2 * i], n1 = norms[2 * i + 1];
             const double eps = n1 > 0.0 ? std::sqrt(n0 / n1) : std::sqrt(n0);
             P->resid[i] = eps;
-            if (!(eps > P->tol) || P->s_cur[i] >= P->smax) {  // NaN (non-finite input) also stops
+            if (!(eps > P->tols[i] / oz::kCheckMargin) || P->s_cur[i] >= P->smax) {  // NaN also stops
                 active[i] = 0;
                 continue;
             }
@@ -860,8 +908,7 @@ int oz_batch_execute(oz_batch_t P) {
     if (e == hipSuccess) e = oz_handle_mark(h);  // between split and GEMM
     for (const Group& gr : P->groups)
         if (e == hipSuccess)
-            e = oz::launch_gemm_persistent(args, reinterpret_cast<const oz::TileItem*>(dev + gr.off_items), gr.nitems,
-                                           gr.s, gr.tile, gr.blocks, false, gr.multi, st);
+            e = launch_group(gr, args, reinterpret_cast<const oz::TileItem*>(dev + gr.off_items), false, st);
     if (e == hipSuccess) e = oz_handle_mark(h);  // after the GEMM launches
     return e == hipSuccess ? OZ_OK : OZ_ERR_HIP;
 }
@@ -956,7 +1003,7 @@ int oz_zgemm_batched(oz_handle_t h, int32_t batch, const char* transa, const cha
                      double* const* C, const int64_t* ldc, const oz_prec_t* prec, const int32_t* slices) {
     oz_batch_t P = nullptr;
     int st = oz_gemm_batched_plan(h, 1, batch, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, prec,
-                                  slices, &P);
+                                  slices, nullptr, &P);
     if (st) return st;
     st = oz_batch_execute(P);
     const int st2 = oz_batch_destroy(P);
@@ -969,7 +1016,7 @@ int oz_dgemm_batched(oz_handle_t h, int32_t batch, const char* transa, const cha
                      double* const* C, const int64_t* ldc, const oz_prec_t* prec, const int32_t* slices) {
     oz_batch_t P = nullptr;
     int st = oz_gemm_batched_plan(h, 0, batch, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, prec,
-                                  slices, &P);
+                                  slices, nullptr, &P);
     if (st) return st;
     st = oz_batch_execute(P);
     const int st2 = oz_batch_destroy(P);

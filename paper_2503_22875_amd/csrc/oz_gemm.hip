@@ -471,6 +471,54 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64 * WMW * WNW, 64 * WMW *
     }
 }
 
+// Persistent form over tiles of problems with different slice counts (all
+// s <= kMaxLiveSlices): each tile runs the 64 x 64 all-diagonal body of its own
+// problem's s, so one launch covers a whole round of a heterogeneous batch
+// instead of one launch (and one tail) per slice count.  The 2-stage LDS ring
+// is sized for the largest s; a tile of smaller s uses a prefix of it.
+template <int S, bool TOP, bool MULTI>
+__device__ __forceinline__ void mixed_tile(const GemmArgs& g, const TileItem& ti, v4i* lds) {
+    using T = TileCfg<S, 2, 2, 2>;
+    tile_body<S, 2, 2, 2, TOP, false, MULTI>(g, ti.tm, ti.tn, reinterpret_cast<v4i(*)[T::STAGE]>(lds));
+}
+
+template <bool TOP, bool MULTI>
+__global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(2, 2))) void
+gemm_persistent_mixed_kernel(const GemmArgs* __restrict__ probs, const TileItem* __restrict__ items, int64_t nitems) {
+    __shared__ v4i lds[2 * TileCfg<kMaxLiveSlices, 2, 2, 2>::STAGE];
+    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const TileItem ti = items[it];
+        if (ti.prob < 0) continue;  // padding item (uniform over the block)
+        const GemmArgs& g = probs[ti.prob];
+        switch (ti.s) {  // the tile's slice count, uniform over the block
+            case 1: mixed_tile<1, TOP, MULTI>(g, ti, lds); break;
+            case 2: mixed_tile<2, TOP, MULTI>(g, ti, lds); break;
+            case 3: mixed_tile<3, TOP, MULTI>(g, ti, lds); break;
+            case 4: mixed_tile<4, TOP, MULTI>(g, ti, lds); break;
+            case 5: mixed_tile<5, TOP, MULTI>(g, ti, lds); break;
+            case 6: mixed_tile<6, TOP, MULTI>(g, ti, lds); break;
+            case 7: mixed_tile<7, TOP, MULTI>(g, ti, lds); break;
+            default: mixed_tile<8, TOP, MULTI>(g, ti, lds); break;
+        }
+        __syncthreads();  // the next tile refills the LDS ring
+    }
+}
+
+// Persistent form of the wide all-diagonal tile (9 <= s <= kMaxWideSlices, one
+// wave per SIMD), for batched problems above the 2-waves-per-SIMD budget.
+template <int S, bool TOP, bool MULTI>
+__global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(1, 1))) void
+gemm_wide_persistent_kernel(const GemmArgs* __restrict__ probs, const TileItem* __restrict__ items, int64_t nitems) {
+    using T = TileCfg<S, 2, 2, 2>;
+    __shared__ v4i lds[2][T::STAGE];
+    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const TileItem ti = items[it];
+        if (ti.prob < 0) continue;
+        tile_body<S, 2, 2, 2, TOP, false, MULTI>(probs[ti.prob], ti.tm, ti.tn, lds);
+        __syncthreads();
+    }
+}
+
 // Streaming form for any s (used above the all-diagonal kernel's register
 // budget, s > kMaxLiveSlices): one INT32 tile, one anti-diagonal at a time.
 // For each INT32 chunk and each d = s+1 down to 2, the pairs (p, d-p) of that
@@ -782,6 +830,54 @@ hipError_t launch_gemm_persistent(const GemmArgs* probs, const TileItem* items, 
         case 6: return launch_persistent_s<6>(probs, items, nitems, blocks, tile, top, multi, st);
         case 7: return launch_persistent_s<7>(probs, items, nitems, blocks, tile, top, multi, st);
         case 8: return launch_persistent_s<8>(probs, items, nitems, blocks, tile, top, multi, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_gemm_persistent_mixed(const GemmArgs* probs, const TileItem* items, int64_t nitems, int blocks,
+                                        bool top, bool multi, hipStream_t st) {
+    if (nitems <= 0) return hipSuccess;
+    if (blocks <= 0) return hipErrorInvalidValue;
+    dim3 grid(static_cast<unsigned>(blocks)), block(256);
+#define OZ_MIXED(TOPV, MULTIV) \
+    hipLaunchKernelGGL((gemm_persistent_mixed_kernel<TOPV, MULTIV>), grid, block, 0, st, probs, items, nitems)
+    if (top && multi) OZ_MIXED(true, true);
+    else if (top) OZ_MIXED(true, false);
+    else if (multi) OZ_MIXED(false, true);
+    else OZ_MIXED(false, false);
+#undef OZ_MIXED
+    return hipGetLastError();
+}
+
+namespace {
+template <int S>
+hipError_t launch_wide_persistent_s(const GemmArgs* probs, const TileItem* items, int64_t nitems, int blocks,
+                                    bool top, bool multi, hipStream_t st) {
+    dim3 grid(static_cast<unsigned>(blocks)), block(256);
+#define OZ_WIDEP(TOPV, MULTIV) \
+    hipLaunchKernelGGL((gemm_wide_persistent_kernel<S, TOPV, MULTIV>), grid, block, 0, st, probs, items, nitems)
+    if (top && multi) OZ_WIDEP(true, true);
+    else if (top) OZ_WIDEP(true, false);
+    else if (multi) OZ_WIDEP(false, true);
+    else OZ_WIDEP(false, false);
+#undef OZ_WIDEP
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_gemm_wide_persistent(const GemmArgs* probs, const TileItem* items, int64_t nitems, int s,
+                                       int blocks, bool top, bool multi, hipStream_t st) {
+    if (nitems <= 0) return hipSuccess;
+    if (blocks <= 0) return hipErrorInvalidValue;
+    // several INT32 chunks from s = 13 on would spill: the streaming body
+    if (multi && s >= 13) return launch_gemm_stream_persistent(probs, items, nitems, s, top, blocks, st);
+    switch (s) {
+        case 9: return launch_wide_persistent_s<9>(probs, items, nitems, blocks, top, multi, st);
+        case 10: return launch_wide_persistent_s<10>(probs, items, nitems, blocks, top, multi, st);
+        case 11: return launch_wide_persistent_s<11>(probs, items, nitems, blocks, top, multi, st);
+        case 12: return launch_wide_persistent_s<12>(probs, items, nitems, blocks, top, multi, st);
+        case 13: return launch_wide_persistent_s<13>(probs, items, nitems, blocks, top, multi, st);
+        case 14: return launch_wide_persistent_s<14>(probs, items, nitems, blocks, top, multi, st);
         default: return hipErrorInvalidValue;
     }
 }

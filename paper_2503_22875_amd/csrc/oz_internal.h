@@ -153,13 +153,21 @@ struct TileItem {
     int32_t prob;
     int32_t tm;
     int32_t tn;
-    int32_t pad;
+    int32_t s;  // slice count of this tile's problem (read by the mixed-s launch)
 };
 hipError_t launch_gemm_persistent(const GemmArgs* probs, const TileItem* items, int64_t nitems, int s, int tile,
                                   int blocks, bool top, bool multi, hipStream_t st);
 // Same for any s with the per-diagonal streaming body (64 x 64 tiles).
 hipError_t launch_gemm_stream_persistent(const GemmArgs* probs, const TileItem* items, int64_t nitems, int s,
                                          bool top, int blocks, hipStream_t st);
+// Tiles of problems with different slice counts (each s <= kMaxLiveSlices, read
+// from its GemmArgs) in one persistent launch of 64 x 64 blocks.
+hipError_t launch_gemm_persistent_mixed(const GemmArgs* probs, const TileItem* items, int64_t nitems, int blocks,
+                                        bool top, bool multi, hipStream_t st);
+// 9 <= s <= kMaxWideSlices: the wide all-diagonal tile (64 x 64, one block per
+// compute unit); several INT32 chunks at s >= 13 take the streaming body.
+hipError_t launch_gemm_wide_persistent(const GemmArgs* probs, const TileItem* items, int64_t nitems, int s,
+                                       int blocks, bool top, bool multi, hipStream_t st);
 
 // Tolerance-driven calls: operand statistics, residual check, final scaling.
 // Per-vector mean square of x * 2^-E (E from maxbits); part: scratch of
@@ -215,6 +223,13 @@ hipError_t launch_finalize_batched(const FinalArgs* f, const int32_t* active, co
                                    hipStream_t st);
 
 // ---- slice-count selection ------------------------------------------------
+// Margin of the a-posteriori check: a tolerance-driven call selects its
+// starting s for tol / kCheckMargin and grows until the one-probe estimate is
+// at most tol / kCheckMargin.  The estimate scatters around the true
+// scale-weighted error (measured within 0.70x .. 1.40x of it on the selector's
+// instance distribution), so the margin keeps the true error within tol.
+constexpr double kCheckMargin = 2.0;
+
 // Rule for the starting slice count of a tolerance-driven call: the
 // scale-weighted error of the emulation behaves like
 //   eps(s) ~ c (s + 1) 2^(-7s) sqrt((1/M_A + 1/M_B) / 3),

@@ -101,6 +101,42 @@ def test_batched_bit_exact_mixed(oz, handle, stream, cplx):
 
 
 @pytest.mark.parametrize("cplx", [0, 1])
+@pytest.mark.parametrize("use_plan", [False, True])
+def test_batched_bit_exact_wide_and_mixed(oz, handle, stream, cplx, use_plan):
+    # fixed slice counts 1..14 in one batch: s <= 8 share one mixed-s launch,
+    # each s in 9..14 takes the wide persistent tile; ragged shapes, every
+    # transpose, beta on half of them; as a one-shot call and as a captured plan
+    rng = np.random.default_rng(60 + cplx)
+    shapes = [(70, 65, 33), (130, 70, 257), (64, 192, 64), (5, 300, 17), (200, 3, 90), (96, 96, 96), (33, 47, 2),
+              (40, 30, 20), (129, 64, 65), (64, 129, 31), (1, 1, 1), (17, 250, 100), (88, 88, 200), (31, 33, 35)]
+    probs, slices = [], []
+    for i, (m, n, k) in enumerate(shapes):
+        ta = "NTC"[i % 3] if cplx else "NT"[i % 2]
+        tb = "NCT"[(i // 3) % 3] if cplx else "TN"[i % 2]
+        A, B, C0 = make_problem(rng, cplx, m, n, k, ta, tb)
+        al = complex(1.0 - 0.05 * i, 0.1) if cplx else 1.0 + 0.1 * i
+        be = (complex(0.5, -0.25) if i % 2 else 0.0) if cplx else (0.5 if i % 2 else 0.0)
+        probs.append((ta, tb, A, B, C0, al, be))
+        slices.append(1 + i)
+    print("wide and mixed batch cplx=%d plan=%d" % (cplx, use_plan), flush=True)
+    if use_plan:
+        plan, dev, args = batch_call(oz, handle, stream, cplx, probs, slices, use_plan=True)
+        try:
+            launches, _, _, sl = oz.oz_batch_info(plan, len(probs))
+            assert sl == slices
+            assert launches == 1 + 6  # one mixed launch for s <= 8, one wide launch per s in 9..14
+            stream.synchronize()
+            got = [from_dev(d[4], args["m"][i], args["n"][i], d[5]) for i, d in enumerate(dev)]
+        finally:
+            oz.oz_batch_destroy(plan)
+    else:
+        got = batch_call(oz, handle, stream, cplx, probs, slices)
+    for i, (ta, tb, A, B, C0, al, be) in enumerate(probs):
+        want = oracle.emu_gemm(ta, tb, A, B, slices[i], alpha=al, beta=be, C=C0)
+        assert np.array_equal(got[i], want), (i, ta, tb, A.shape, B.shape, slices[i])
+
+
+@pytest.mark.parametrize("cplx", [0, 1])
 def test_batched_balanced_bit_exact_mixed(oz, handle, stream, cplx):
     # balanced digits in every problem: slice counts 1..8 mixed (one GEMM
     # launch per count), ragged shapes, every transpose, beta on half of them
@@ -259,7 +295,9 @@ def test_batched_argument_errors(oz, handle):
         args = dict(base)
         args[key] = val
         assert oz.oz_zgemm_batched(handle, check=False, p=oz.prec(6), **args) == pos
-    assert oz.oz_zgemm_batched(handle, check=False, p=oz.prec(9), **base) == 14
+    # fixed slice counts up to 14 (the wide tile from 9 on); 15 and above only tolerance-driven
+    assert oz.oz_zgemm_batched(handle, check=False, p=oz.prec(15), **base) == 14
+    assert oz.oz_zgemm_batched(handle, check=False, p=oz.prec(14), **base) == 0
     # the 3-real-product form is for single calls with a fixed slice count
     assert oz.oz_zgemm_batched(handle, check=False, p=oz.prec(6, zmode=3), **base) == 14
     st = oz.oz_zgemm(handle, "N", "N", 4, 4, 4, 1.0, d, 4, d, 4, 0.0, d, 4, oz.prec(0, tol=1e-10, zmode=3),

@@ -284,3 +284,4 @@ def test_predicted_slices_match_oracle_network(oz, handle):
     finally:
         oz.oz_set_selector(handle, None)
         oz.oz_mlp_destroy(net)
+

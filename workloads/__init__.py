@@ -19,6 +19,10 @@ distributions of the workloads the emulated GEMM is benchmarked on:
                       10^U(-8, 8) and columns of B by 10^U(-8, 8).
 * ``dgemm_spread``    general real operands whose per-entry exponents are
                       spread over sigma binades, for slice-count selection data.
+* ``zgemm_batch_mixed`` the batched workload's sizes with operands drawn per
+                      problem from the selector's instance distribution
+                      (exponent spread, kept significand bits, zeros, value
+                      family), complex, and one tolerance per problem.
 * ``zinv_gauss``      one n x n complex matrix to invert, entries
                       N(0,1) + i N(0,1) (condition number of order n), the
                       stand-in for the application's complex LU-inverted matrix.
@@ -235,3 +239,45 @@ def zgemm_batch_spread(count=512, seed=0, sig_max=40):
 
         out.append((one(), one()))
     return out
+
+
+def zgemm_batch_mixed(count=512, seed=0, tol_lo=1e-15, tol_hi=1e-4):
+    """Heterogeneous batch: the square sizes of ``zgemm_batch`` (n_b =
+    32 * randint(1, 16)), each problem's structure drawn as one selector
+    instance (spread sigma ~ randint(0, 40) per entry / per vector / half and
+    half, 70% full significands else randint(4, 52) kept bits, 30% with a zero
+    fraction U(0, 0.8), family 0 or 1), and one tolerance per problem,
+    log-uniform in [tol_lo, tol_hi].  Returns (list of parameter dicts, tols);
+    ``mixed_operands(p)`` draws a problem's complex operands."""
+    sizes = zgemm_batch_sizes(count, seed)
+    rng = np.random.default_rng(seed + 3)
+    params = []
+    for nb in sizes:
+        sigma = int(rng.integers(0, 41))
+        mode = int(rng.integers(0, 3))
+        sig_el = sigma if mode == 0 else (0 if mode == 1 else sigma // 2)
+        bits = 53 if rng.random() < 0.7 else int(rng.integers(4, 53))
+        zero_q = 0 if rng.random() < 0.7 else int(rng.uniform(0.0, 0.8) * (1 << 24))
+        params.append(dict(m=nb, n=nb, k=nb, sig_el=sig_el, sig_vec=sigma - sig_el, bits=bits,
+                           family=int(rng.integers(0, 2)), zero_q=zero_q,
+                           key=int(rng.integers(0, 1 << 63, dtype=np.int64))))
+    tols = np.exp(rng.uniform(np.log(tol_lo), np.log(tol_hi), size=count))
+    return params, tols
+
+
+def mixed_parts(p):
+    """The two real instances whose operands are the real and imaginary parts
+    of a ``zgemm_batch_mixed`` problem: p itself, and p with the key replaced
+    by draw 4 of p's key stream (so each part has its own entry draws and its
+    own per-vector exponents)."""
+    q = dict(p)
+    q["key"] = int(_draw_scalar(int(p["key"]), 4) & 0x7FFFFFFFFFFFFFFF)
+    return p, q
+
+
+def mixed_operands(p):
+    """Complex operands (A, B) of one ``zgemm_batch_mixed`` problem, column-major."""
+    pr, pi = mixed_parts(p)
+    Ar, Br = gen_operands(pr)
+    Ai, Bi = gen_operands(pi)
+    return np.asfortranarray(Ar + 1j * Ai), np.asfortranarray(Br + 1j * Bi)
