@@ -214,16 +214,18 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
-def mixed_batch_on_device(oz, h, count=512, seed=0):
-    """The heterogeneous batch (workloads.zgemm_batch_mixed) drawn on the GPU by
-    the library's counter-based generator: per problem the real and imaginary
-    parts of A and B come from the two instances of workloads.mixed_parts,
-    interleaved into complex column-major buffers.  Returns (dev, ns, tols,
-    params) with dev a list of (A, B, C) tensors."""
+def mixed_batch_on_device(oz, h, count=512, seed=0, kind="mixed"):
+    """A heterogeneous batch (workloads.zgemm_batch_mixed, or with kind
+    "lowprec" workloads.zgemm_batch_lowprec) drawn on the GPU by the library's
+    counter-based generator: per problem the real and imaginary parts of A and
+    B come from the two instances of workloads.mixed_parts, interleaved into
+    complex column-major buffers.  Returns (dev, ns, tols, params) with dev a
+    list of (A, B, C) tensors."""
     import torch
 
     import workloads
-    params, tols = workloads.zgemm_batch_mixed(count, seed)
+    gen = workloads.zgemm_batch_lowprec if kind == "lowprec" else workloads.zgemm_batch_mixed
+    params, tols = gen(count, seed)
     dev, ns = [], []
     for p in params:
         n = p["n"]
@@ -234,6 +236,13 @@ def mixed_batch_on_device(oz, h, count=512, seed=0):
             oz.oz_gen_operands(h, q, A, n, B, n)
             parts.append((A, B))
         torch.cuda.synchronize()
+        # imaginary parts: scaled by the real parts' per-vector powers of two (exact)
+        ea, eb = workloads.vector_exponents(p)
+        sa = torch.pow(2.0, torch.from_numpy(ea).double()).cuda()
+        sb = torch.pow(2.0, torch.from_numpy(eb).double()).cuda()
+        Ai = (parts[1][0].view(n, n) * sa[None, :]).reshape(-1)  # storage view [column][row]
+        Bi = (parts[1][1].view(n, n) * sb[:, None]).reshape(-1)
+        parts[1] = (Ai, Bi)
         Az = torch.view_as_complex(torch.stack([parts[0][0], parts[1][0]], dim=1).contiguous())
         Bz = torch.view_as_complex(torch.stack([parts[0][1], parts[1][1]], dim=1).contiguous())
         dev.append((Az, Bz, torch.zeros(n * n, dtype=torch.complex128, device="cuda")))
@@ -343,7 +352,9 @@ def bench_select(args):
       mixed:  the heterogeneous batch (workloads.zgemm_batch_mixed, drawn on
               the GPU): every problem with its own structure from the
               selector's instance distribution and its own tolerance,
-              log-uniform in [1e-15, 1e-4]."""
+              log-uniform in [1e-15, 1e-4];
+      lowprec: the same with significands of bfloat16 / float16 / float32 /
+              float64 width (workloads.zgemm_batch_lowprec)."""
     import torch
 
     import paper_2503_22875_amd as oz
@@ -361,8 +372,8 @@ def bench_select(args):
     oz.oz_set_selector(h, net)
     results = []
     for dname in args.select_data.split(","):
-        if dname == "mixed":
-            dev, ns, tols, _ = mixed_batch_on_device(oz, h, 512, seed=0)
+        if dname in ("mixed", "lowprec"):
+            dev, ns, tols, _ = mixed_batch_on_device(oz, h, 512, seed=0, kind=dname)
             cases = [("own", tols)]
         else:
             problems = workloads.zgemm_batch(512, seed=0)
@@ -829,7 +840,7 @@ def main():
                     help="inversion rows with balanced digits in every product (slice counts)")
     ap.add_argument("--inv-tols", default="1e-8,1e-10,1e-12",
                     help="tolerance-driven rows of the inversion workload (each product picks its own s)")
-    ap.add_argument("--select-data", default="mixed,normal")
+    ap.add_argument("--select-data", default="mixed,lowprec,normal")
     ap.add_argument("--select-tols", default="1e-10,1e-12,1e-14")
     ap.add_argument("--sweep-n", default="2048,4096")
     ap.add_argument("--wide-tols", default="1e-6,1e-10,1e-12,1e-14")

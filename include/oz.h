@@ -69,11 +69,13 @@ typedef struct oz_handle_s* oz_handle_t;
  *           tol/2 by a rule on operand statistics (oz_select_slices) or the
  *           learned selector, emulates, checks the result a posteriori with a
  *           randomised double-double residual, and while the estimate exceeds
- *           tol/2 adds one slice (the next digit and the next anti-diagonal,
- *           added last) up to smax.  The one-probe estimate lies within about
- *           0.7x .. 1.4x of the true error, so the margin of 2 keeps the true
- *           error within tol.  Sec. 4 of
- *           the paper motivates adjusting the split number to the operator.
+ *           tol/2 adds ceil(log2(estimate / (tol/2)) / 6) slices, at least one
+ *           (each the next digit and the next anti-diagonal, added last, in
+ *           turn) up to smax, then checks again.  The one-probe estimate lies
+ *           within about 0.7x .. 1.4x of the true error, so the margin of 2
+ *           keeps the true error within tol; the error falls by at least about
+ *           2^6 per slice.  Sec. 4 of the paper motivates adjusting the split
+ *           number to the operator.
  *           Tolerance-driven calls synchronise their stream.
  *  smax   : largest s the tol-driven selection may use (0: 12).
  *  kchunk : products per INT32 chunk along k; 0 picks the largest multiple of
@@ -495,16 +497,20 @@ int oz_batch_destroy(oz_batch_t plan);
  * array NULL) plans every problem as a tolerance-driven oz_dgemm / oz_zgemm
  * call with its own tolerance -- tols[b] (every entry > 0) when the array is
  * given, else prec->tol -- and the same smax (0: 12, up to OZ_MAX_SLICES),
- * sstart and selector; tols given with a fixed slice count returns 14.  An execution then runs: the batched split with smax digit planes;
- * the starting s of every problem (sstart, or one batched statistics pass and
- * the rule or the handle's learned selector); raw sums at those s (problems
- * grouped by s, one persistent launch per group: the all-diagonal kernel for
- * s <= 8, the streaming kernel above); then rounds of a batched residual check over the
- * problems still open and one more slice (digit already split, next
- * anti-diagonal added last) for those whose estimate exceeds tol/2, until all
- * pass or reach smax; finally one batched scaling pass into C.  Each problem's
- * result is bit-identical to the single tolerance-driven call that starts at
- * the same s.  The execution synchronises the stream at every round. */
+ * sstart and selector; tols given with a fixed slice count returns 14.  An
+ * execution then runs: the batched scan; the starting s of every problem
+ * (sstart, or one batched statistics pass and the rule or the handle's
+ * learned selector); the split of digit planes 1..s; raw sums at those s
+ * (every problem with s <= 8 in one mixed-s persistent launch, those with
+ * 9 <= s <= 14 in one wide launch on a second stream beside it, streaming
+ * launches above); then rounds of a batched residual check over the problems
+ * still open, and for those whose estimate exceeds tol/2 the slices the
+ * single call would add (new digit planes, then one anti-diagonal at a time,
+ * each added last), until all pass or reach smax; finally one batched
+ * scaling pass into C for the problems with beta != 0 (with beta = 0 every
+ * GEMM pass writes C).  Each problem's result is bit-identical to the single
+ * tolerance-driven call that starts and ends at the same s.  The execution
+ * synchronises the stream at every round. */
 /* Per-problem reports of the last execution (batch entries): slices used,
  * slices added by the check, INT32 chunks, the final error estimate (tol
  * plans), status OZ_ERR_NONFINITE for non-finite input.  Synchronises. */

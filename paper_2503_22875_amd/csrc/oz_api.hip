@@ -31,6 +31,12 @@ struct oz_handle_s {
     std::vector<oz::TuneEntry> tune;
     // learned slice-count selector (oz_set_selector), not owned
     oz_mlp_t selector;
+    // LU factorisation / inverse: the look-ahead stream and its events, and a
+    // grow-only device buffer apart from the GEMM workspace (created on first use)
+    hipStream_t lu_stream;
+    hipEvent_t lu_ev[3];
+    void* lu_ws;
+    size_t lu_ws_bytes;
 };
 
 // Device scratch of the allocation-free entry point oz_gemm_noalloc: every
@@ -603,33 +609,41 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
                 return OZ_ERR_HIP;
             eps = nrm[1] > 0.0 ? std::sqrt(nrm[0] / nrm[1]) : std::sqrt(nrm[0]);
             if (!(eps > tol_eff) || s >= smax) break;  // NaN (non-finite input) also stops
+            // slices to add before the next check: the estimate falls by at
+            // least about 2^6 per slice (one for an estimate just above the target)
+            int add = static_cast<int>(std::ceil(std::log2(eps / tol_eff) / 6.0));
+            add = add < 1 ? 1 : (add > smax - s ? smax - s : add);
             if (bal) {
-                // balanced digits depend on s: split again at s + 1 and
+                // balanced digits depend on s: split again at s + add and
                 // recompute the raw sums (no incremental growth)
-                if (oz::launch_digits(va, maxa, p.la, EA, SA, h->stream, 0, s + 1) != hipSuccess ||
-                    oz::launch_digits(vb, maxb, p.lb, FB, SB, h->stream, 0, s + 1) != hipSuccess)
+                if (oz::launch_digits(va, maxa, p.la, EA, SA, h->stream, 0, s + add) != hipSuccess ||
+                    oz::launch_digits(vb, maxb, p.lb, FB, SB, h->stream, 0, s + add) != hipSuccess)
                     return OZ_ERR_HIP;
-                g.s = s + 1;
-                g.mode = oz::kRawWrite;
+                g.s = s + add;
+                g.mode = beta_zero ? oz::kRawWriteFinal : oz::kRawWrite;
                 if (oz::launch_gemm(g, h->stream) != hipSuccess) return OZ_ERR_HIP;
-                ++s;
-                ++fallbacks;
+                s += add;
+                fallbacks += add;
                 continue;
             }
-            // digit plane s + 1, then the anti-diagonal s + 2
-            if (oz::launch_digits(va, maxa, p.la, EA, SA, h->stream, s, s + 1) != hipSuccess ||
-                oz::launch_digits(vb, maxb, p.lb, FB, SB, h->stream, s, s + 1) != hipSuccess)
+            // digit planes s + 1 .. s + add, then the anti-diagonals s + 2 ..
+            // s + add + 1, one at a time (the incremental order)
+            if (oz::launch_digits(va, maxa, p.la, EA, SA, h->stream, s, s + add) != hipSuccess ||
+                oz::launch_digits(vb, maxb, p.lb, FB, SB, h->stream, s, s + add) != hipSuccess)
                 return OZ_ERR_HIP;
-            g.s = s + 1;
-            g.top = 1;
-            g.mode = oz::kRawAdd;
-            if (oz::launch_gemm(g, h->stream) != hipSuccess) return OZ_ERR_HIP;
-            g.top = 0;
-            ++s;
-            ++fallbacks;
+            for (int j = 0; j < add; ++j) {
+                g.s = s + 1;
+                g.top = 1;
+                g.mode = beta_zero ? oz::kRawAddFinal : oz::kRawAdd;  // with beta = 0 the growth step writes C
+                if (oz::launch_gemm(g, h->stream) != hipSuccess) return OZ_ERR_HIP;
+                g.top = 0;
+                ++s;
+                ++fallbacks;
+            }
         }
-        // (4) C = alpha * ldexp(acc, E + F) + beta * C (unless the first pass wrote it)
-        if ((fallbacks > 0 || !beta_zero) &&
+        // (4) C = alpha * ldexp(acc, E + F) + beta * C (with beta = 0 the last
+        // GEMM pass wrote it)
+        if (!beta_zero &&
             oz::launch_finalize(g.acc, p.la.rows_pad, EA, FB, C, ldc, m, n, cplx, ar, ai, br, bi, beta_zero ? 1 : 0,
                                 h->stream) != hipSuccess)
             return OZ_ERR_HIP;
@@ -668,6 +682,47 @@ char* oz_handle_ws(oz_handle_t h, size_t bytes, int* status) {
     return st ? nullptr : static_cast<char*>(h->ws);
 }
 oz_mlp_t oz_handle_selector(oz_handle_t h) { return h->selector; }
+int oz_handle_lu_stream(oz_handle_t h, hipStream_t* s2, hipEvent_t* ev) {
+    if (!h->lu_stream) {
+        hipStream_t s = nullptr;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return OZ_ERR_HIP;
+        for (int i = 0; i < 3; ++i)
+            if (hipEventCreateWithFlags(&h->lu_ev[i], hipEventDisableTiming) != hipSuccess) {
+                for (int j = 0; j < i; ++j) {
+                    (void)hipEventDestroy(h->lu_ev[j]);
+                    h->lu_ev[j] = nullptr;
+                }
+                (void)hipStreamDestroy(s);
+                return OZ_ERR_HIP;
+            }
+        h->lu_stream = s;
+    }
+    *s2 = h->lu_stream;
+    for (int i = 0; i < 3; ++i) ev[i] = h->lu_ev[i];
+    return OZ_OK;
+}
+char* oz_handle_lu_ws(oz_handle_t h, size_t bytes, int* status) {
+    *status = OZ_OK;
+    if (bytes > h->lu_ws_bytes) {
+        if (h->lu_ws) {
+            if (hipStreamSynchronize(h->stream) != hipSuccess ||
+                (h->lu_stream && hipStreamSynchronize(h->lu_stream) != hipSuccess)) {
+                *status = OZ_ERR_HIP;
+                return nullptr;
+            }
+            (void)hipFree(h->lu_ws);
+            h->lu_ws = nullptr;
+            h->lu_ws_bytes = 0;
+        }
+        if (hipMalloc(&h->lu_ws, bytes) != hipSuccess) {
+            h->lu_ws = nullptr;
+            *status = OZ_ERR_ALLOC;
+            return nullptr;
+        }
+        h->lu_ws_bytes = bytes;
+    }
+    return static_cast<char*>(h->lu_ws);
+}
 void oz_handle_set_selector(oz_handle_t h, oz_mlp_t mlp) { h->selector = mlp; }
 
 extern "C" {
@@ -694,6 +749,10 @@ int oz_create(oz_handle_t* handle, int device) {
     h->ws_owned = true;
     h->timing = false;
     h->selector = nullptr;
+    h->lu_stream = nullptr;
+    h->lu_ev[0] = h->lu_ev[1] = h->lu_ev[2] = nullptr;
+    h->lu_ws = nullptr;
+    h->lu_ws_bytes = 0;
     *handle = h;
     return OZ_OK;
 }
@@ -703,6 +762,10 @@ int oz_destroy(oz_handle_t h) {
     use_device(h);
     hipStreamSynchronize(h->stream);
     if (h->ws_owned && h->ws) hipFree(h->ws);
+    if (h->lu_ws) (void)hipFree(h->lu_ws);
+    for (hipEvent_t ev : h->lu_ev)
+        if (ev) (void)hipEventDestroy(ev);
+    if (h->lu_stream) (void)hipStreamDestroy(h->lu_stream);
     for (hipEvent_t ev : h->ev_pool) hipEventDestroy(ev);
     for (hipEvent_t ev : h->ev_pending) hipEventDestroy(ev);
     h->magic = 0;

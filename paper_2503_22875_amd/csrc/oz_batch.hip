@@ -64,6 +64,11 @@ struct oz_batch_s {
     std::vector<ScaleOnly> scale_only;
     std::vector<int32_t> slices;  // per problem (0 for quick returns)
     hipGraph_t graph;
+    // second stream for the one-wave-per-SIMD launches (s > 8), forked from
+    // and joined back into the handle's stream, so they fill the tail of the
+    // mixed-s launch instead of running after it
+    hipStream_t aux;
+    hipEvent_t ev_fork, ev_join;
     hipGraphExec_t graph_exec;
     // ---- tolerance-driven plans ----
     bool tol_mode;
@@ -78,6 +83,10 @@ struct oz_batch_s {
     size_t off_check, off_active, off_norms, off_wt, off_gv, off_row, off_final, off_final_items, off_dyn;
     size_t off_prange;  // digit-plane range per operand of a split round
     int64_t n_wt, n_gv, n_row, n_final, dyn_cap;
+    // host copies of the check work lists, and room for the lists of one
+    // round compacted to its open problems
+    std::vector<oz::BlockItem> wt_items, gv_items, row_items;
+    size_t off_check_dyn;
     std::vector<int32_t> s_cur, fallbacks;
     std::vector<double> resid;
 };
@@ -220,50 +229,91 @@ hipError_t launch_group(const Group& gr, const oz::GemmArgs* dargs, const oz::Ti
     switch (gr.tile) {
         case kStream: return oz::launch_gemm_stream_persistent(dargs, items, gr.nitems, gr.s, top, gr.blocks, st);
         case kMixed: return oz::launch_gemm_persistent_mixed(dargs, items, gr.nitems, gr.blocks, top, gr.multi, st);
-        case kWide: return oz::launch_gemm_wide_persistent(dargs, items, gr.nitems, gr.s, gr.blocks, top, gr.multi, st);
+        case kWide: return oz::launch_gemm_wide_persistent(dargs, items, gr.nitems, gr.blocks, top, gr.multi, st);
         default:
             return oz::launch_gemm_persistent(dargs, items, gr.nitems, gr.s, gr.tile, gr.blocks, top, gr.multi, st);
     }
 }
 
+// Every group of a round: the wide and streaming groups (s > 8) on the
+// plan's second stream, the others on st, when there are both kinds.
+// items_of(gr) gives the device address of a group's tile list.
+template <class ItemsOf>
+hipError_t launch_groups(oz_batch_t P, const std::vector<Group>& groups, const oz::GemmArgs* dargs, ItemsOf items_of,
+                         bool top, hipStream_t st) {
+    bool narrow = false, wide = false;
+    for (const Group& gr : groups) {
+        if (gr.tile == kWide || gr.tile == kStream) wide = true;
+        else narrow = true;
+    }
+    const bool fork = narrow && wide;
+    hipError_t e = hipSuccess;
+    if (fork) {
+        e = hipEventRecord(P->ev_fork, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(P->aux, P->ev_fork, 0);
+    }
+    for (const Group& gr : groups)
+        if (e == hipSuccess && (gr.tile == kWide || gr.tile == kStream))
+            e = launch_group(gr, dargs, items_of(gr), top, fork ? P->aux : st);
+    for (const Group& gr : groups)
+        if (e == hipSuccess && gr.tile != kWide && gr.tile != kStream)
+            e = launch_group(gr, dargs, items_of(gr), top, st);
+    if (fork) {
+        if (e == hipSuccess) e = hipEventRecord(P->ev_join, P->aux);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, P->ev_join, 0);
+    }
+    return e;
+}
+
 // Groups of one GEMM round over `members` (slice counts s_of(i)): every
 // problem with s <= 8 in one mixed 64 x 64 launch (or, with a single such s,
-// the tuned block shape for it), one wide launch per s in 9..14, one
-// streaming launch per larger s.
+// the tuned block shape for it), every problem with s in 9..14 in one wide
+// launch (several INT32 chunks at s >= 13 excepted), one streaming launch per
+// remaining s.
 template <class SOf>
 void round_groups(const std::vector<oz::GemmArgs>& args, const std::vector<size_t>& members, SOf s_of, int kernel,
                   int cplx, int cus, const std::vector<oz::TuneEntry>& tune, std::vector<Group>* groups,
                   std::vector<std::vector<oz::TileItem>>* items) {
-    std::vector<int> svals;
-    std::vector<size_t> low;
+    auto multi_of = [&](size_t i) { return args[i].chunk_steps < args[i].kpad / oz::kStep; };
+    // a wide launch with several INT32 chunks holds s <= 12 only (register budget)
+    bool wide_multi = false;
     for (size_t i : members) {
         const int s = s_of(i);
-        if (s <= oz::kMaxLiveSlices) low.push_back(i);
-        if (std::find(svals.begin(), svals.end(), s) == svals.end()) svals.push_back(s);
+        if (s > oz::kMaxLiveSlices && s <= 12 && multi_of(i)) wide_multi = true;
     }
-    std::sort(svals.begin(), svals.end());
-    int nlow = 0;
-    for (int sv : svals) nlow += sv <= oz::kMaxLiveSlices ? 1 : 0;
-    for (int sv : svals) {
-        if (sv <= oz::kMaxLiveSlices && nlow > 1) continue;  // in the mixed group below
-        std::vector<size_t> mem;
-        for (size_t i : members)
-            if (s_of(i) == sv) mem.push_back(i);
-        const int kind = sv <= oz::kMaxLiveSlices ? kernel : (sv <= oz::kMaxWideSlices ? kWide : kStream);
+    std::vector<size_t> low, wide, streamed;
+    std::vector<int> lowvals, streamvals;
+    for (size_t i : members) {
+        const int s = s_of(i);
+        if (s <= oz::kMaxLiveSlices) {
+            low.push_back(i);
+            if (std::find(lowvals.begin(), lowvals.end(), s) == lowvals.end()) lowvals.push_back(s);
+        } else if (s <= (wide_multi ? 12 : oz::kMaxWideSlices) && !(s >= 13 && multi_of(i))) {
+            wide.push_back(i);
+        } else {
+            streamed.push_back(i);
+            if (std::find(streamvals.begin(), streamvals.end(), s) == streamvals.end()) streamvals.push_back(s);
+        }
+    }
+    auto add = [&](const std::vector<size_t>& mem, int sv, int kind) {
         Group gr;
         std::vector<oz::TileItem> it;
         build_group(args, mem, sv, kind, cplx, cus, tune, &gr, &it);
-        gr.tile = kind ? kind : gr.tile;
+        if (kind) gr.tile = kind;
         groups->push_back(gr);
         items->push_back(std::move(it));
+    };
+    // the longest tiles first: their launch runs beside the others (second stream)
+    if (!wide.empty()) add(wide, 0, kWide);
+    std::sort(streamvals.begin(), streamvals.end());
+    for (int sv : streamvals) {
+        std::vector<size_t> mem;
+        for (size_t i : streamed)
+            if (s_of(i) == sv) mem.push_back(i);
+        add(mem, sv, kStream);
     }
-    if (nlow > 1) {
-        Group gr;
-        std::vector<oz::TileItem> it;
-        build_group(args, low, 0, kMixed, cplx, cus, tune, &gr, &it);
-        groups->push_back(gr);
-        items->push_back(std::move(it));
-    }
+    if (lowvals.size() == 1) add(low, lowvals[0], kernel);
+    else if (lowvals.size() > 1) add(low, 0, kMixed);
 }
 
 
@@ -342,6 +392,16 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
     P->dev = nullptr;
     P->graph = nullptr;
     P->graph_exec = nullptr;
+    P->aux = nullptr;
+    P->ev_fork = P->ev_join = nullptr;
+    if (hipStreamCreateWithFlags(&P->aux, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming) != hipSuccess) {
+        if (P->aux) (void)hipStreamDestroy(P->aux);
+        if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
+        delete P;
+        return OZ_ERR_HIP;
+    }
     P->slices.assign(static_cast<size_t>(batch), 0);
     P->tol_mode = tol_mode;
     P->tol = tol;
@@ -594,7 +654,7 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
             finals.push_back({g.acc, g.Mp, g.EA, g.FB, g.C, g.ldc, g.m, g.n, cplx, g.alpha_r, g.alpha_i, g.beta_r,
                               g.beta_i, g.beta_zero});
             oz::GemmArgs ga = g;
-            ga.mode = oz::kRawAdd;
+            ga.mode = g.beta_zero ? oz::kRawAddFinal : oz::kRawAdd;  // beta = 0: growth writes C
             args_add.push_back(ga);
             tiles += (g.Mp / 64) * (g.Np / 64);
         }
@@ -607,6 +667,7 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
         P->off_fp = take(sizeof(oz::FeatProb) * nprob);
         P->off_check = take(sizeof(oz::CheckArgs) * nprob);
         P->off_wt = take(sizeof(oz::BlockItem) * wt_items.size());
+        P->off_check_dyn = take(sizeof(oz::BlockItem) * (wt_items.size() + gv_items.size() + row_items.size()));
         P->off_gv = take(sizeof(oz::BlockItem) * gv_items.size());
         P->off_row = take(sizeof(oz::BlockItem) * row_items.size());
         P->off_final = take(sizeof(oz::FinalArgs) * nprob);
@@ -616,6 +677,9 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
         P->n_wt = static_cast<int64_t>(wt_items.size());
         P->n_gv = static_cast<int64_t>(gv_items.size());
         P->n_row = static_cast<int64_t>(row_items.size());
+        P->wt_items = wt_items;
+        P->gv_items = gv_items;
+        P->row_items = row_items;
         P->n_final = static_cast<int64_t>(fin_items.size());
     }
     P->s_cur.assign(nprob, 0);
@@ -747,9 +811,11 @@ int tol_round(oz_batch_t P, const std::vector<size_t>& members, bool growth, hip
             hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
         return OZ_ERR_HIP;
-    for (const Group& gr : groups)
-        if (launch_group(gr, dargs, ditems + gr.off_items, growth, st) != hipSuccess) return OZ_ERR_HIP;
-    return OZ_OK;
+    // off_items: index into the round's tile list
+    return launch_groups(P, groups, dargs, [&](const Group& gr) { return ditems + gr.off_items; }, growth, st) ==
+                   hipSuccess
+               ? OZ_OK
+               : OZ_ERR_HIP;
 }
 
 int execute_tol(oz_batch_t P) {
@@ -819,16 +885,39 @@ int execute_tol(oz_batch_t P) {
     if (rc) return rc;
     // (3) check the active problems; grow the failing ones by one slice
     std::vector<int32_t> active(nprob, 1);
+    std::vector<int> target_s(nprob, 0);
     std::vector<double> norms(2 * nprob);
     const oz::CheckArgs* checks = reinterpret_cast<const oz::CheckArgs*>(dev + P->off_check);
     int32_t* dactive = reinterpret_cast<int32_t*>(dev + P->off_active);
-    for (;;) {
+    std::vector<oz::BlockItem> citems;
+    oz::BlockItem* dcitems = reinterpret_cast<oz::BlockItem*>(dev + P->off_check_dyn);
+    for (bool first = true;; first = false) {
         e = hipMemcpyAsync(dactive, active.data(), sizeof(int32_t) * nprob, hipMemcpyHostToDevice, st);
+        // the first round checks every problem (the planned lists); later
+        // rounds only the open ones (lists compacted on the host)
+        const oz::BlockItem *wt = reinterpret_cast<const oz::BlockItem*>(dev + P->off_wt),
+                            *gv = reinterpret_cast<const oz::BlockItem*>(dev + P->off_gv),
+                            *rw = reinterpret_cast<const oz::BlockItem*>(dev + P->off_row);
+        int64_t nwt = P->n_wt, ngv = P->n_gv, nrw = P->n_row;
+        if (!first) {
+            citems.clear();
+            for (const auto* lst : {&P->wt_items, &P->gv_items, &P->row_items}) {
+                for (const oz::BlockItem& it : *lst)
+                    if (active[it.op]) citems.push_back(it);
+                if (lst == &P->wt_items) nwt = static_cast<int64_t>(citems.size());
+                else if (lst == &P->gv_items) ngv = static_cast<int64_t>(citems.size()) - nwt;
+                else nrw = static_cast<int64_t>(citems.size()) - nwt - ngv;
+            }
+            if (e == hipSuccess && !citems.empty())
+                e = hipMemcpyAsync(dcitems, citems.data(), sizeof(oz::BlockItem) * citems.size(),
+                                   hipMemcpyHostToDevice, st);
+            wt = dcitems;
+            gv = dcitems + nwt;
+            rw = dcitems + nwt + ngv;
+        }
         if (e == hipSuccess)
-            e = oz::launch_residual_batched(checks, static_cast<int64_t>(nprob), dactive,
-                                            reinterpret_cast<const oz::BlockItem*>(dev + P->off_wt), P->n_wt,
-                                            reinterpret_cast<const oz::BlockItem*>(dev + P->off_gv), P->n_gv,
-                                            reinterpret_cast<const oz::BlockItem*>(dev + P->off_row), P->n_row, st);
+            e = oz::launch_residual_batched(checks, static_cast<int64_t>(nprob), dactive, wt, nwt, gv, ngv, rw, nrw,
+                                            st);
         if (e == hipSuccess)
             e = hipMemcpyAsync(norms.data(), dev + P->off_norms, sizeof(double) * 2 * nprob, hipMemcpyDeviceToHost,
                                st);
@@ -840,31 +929,51 @@ int execute_tol(oz_batch_t P) {
             const double n0 = norms[2 * i], n1 = norms[2 * i + 1];
             const double eps = n1 > 0.0 ? std::sqrt(n0 / n1) : std::sqrt(n0);
             P->resid[i] = eps;
-            if (!(eps > P->tols[i] / oz::kCheckMargin) || P->s_cur[i] >= P->smax) {  // NaN also stops
+            const double target = P->tols[i] / oz::kCheckMargin;
+            if (!(eps > target) || P->s_cur[i] >= P->smax) {  // NaN also stops
                 active[i] = 0;
                 continue;
             }
-            ++P->s_cur[i];
-            ++P->fallbacks[i];
+            // slices to add before the next check: the estimate falls by at
+            // least about 2^6 per slice, so ceil(log2(eps / target) / 6)
+            // (one for an estimate just above the target)
+            int add = static_cast<int>(std::ceil(std::log2(eps / target) / 6.0));
+            add = add < 1 ? 1 : add;
+            const int room = P->smax - P->s_cur[i];
             grow.push_back(i);
+            target_s[i] = P->s_cur[i] + (add < room ? add : room);
         }
         if (grow.empty()) break;
-        // the new digit plane of the growing problems only
+        // the new digit planes of the growing problems only
         std::fill(prange.begin(), prange.end(), 0);
-        for (size_t i : grow)
+        int steps = 0;
+        for (size_t i : grow) {
             for (int side = 0; side < 2; ++side) {
-                prange[4 * i + 2 * side] = P->s_cur[i] - 1;
-                prange[4 * i + 2 * side + 1] = P->s_cur[i];
+                prange[4 * i + 2 * side] = P->s_cur[i];
+                prange[4 * i + 2 * side + 1] = target_s[i];
             }
+            steps = std::max(steps, target_s[i] - P->s_cur[i]);
+        }
         if (split_round() != hipSuccess) return OZ_ERR_HIP;
-        rc = tol_round(P, grow, true, st);
-        if (rc) return rc;
+        // one anti-diagonal at a time, each problem up to its target (the
+        // order of the single call's growth, without the checks in between)
+        for (int j = 0; j < steps; ++j) {
+            std::vector<size_t> step_members;
+            for (size_t i : grow)
+                if (P->s_cur[i] < target_s[i]) {
+                    ++P->s_cur[i];
+                    ++P->fallbacks[i];
+                    step_members.push_back(i);
+                }
+            rc = tol_round(P, step_members, true, st);
+            if (rc) return rc;
+        }
     }
-    // (4) C = alpha * ldexp(acc, E + F) + beta * C where the first pass did not
-    // write the final C (beta != 0) or the slice count grew since
+    // (4) C = alpha * ldexp(acc, E + F) + beta * C for the problems with
+    // beta != 0 (with beta = 0 every GEMM pass, first or growth, writes C)
     bool any = false;
     for (size_t i = 0; i < nprob; ++i) {
-        active[i] = (P->fallbacks[i] > 0 || P->host_args[i].mode != oz::kRawWriteFinal) ? 1 : 0;
+        active[i] = P->host_args[i].mode != oz::kRawWriteFinal ? 1 : 0;  // beta != 0
         any = any || active[i];
     }
     e = hipSuccess;
@@ -906,9 +1015,10 @@ int oz_batch_execute(oz_batch_t P) {
                                       st);
     const oz::GemmArgs* args = reinterpret_cast<const oz::GemmArgs*>(dev + P->off_args);
     if (e == hipSuccess) e = oz_handle_mark(h);  // between split and GEMM
-    for (const Group& gr : P->groups)
-        if (e == hipSuccess)
-            e = launch_group(gr, args, reinterpret_cast<const oz::TileItem*>(dev + gr.off_items), false, st);
+    if (e == hipSuccess)
+        e = launch_groups(  // off_items: byte offset into the plan's allocation
+            P, P->groups, args,
+            [&](const Group& gr) { return reinterpret_cast<const oz::TileItem*>(dev + gr.off_items); }, false, st);
     if (e == hipSuccess) e = oz_handle_mark(h);  // after the GEMM launches
     return e == hipSuccess ? OZ_OK : OZ_ERR_HIP;
 }
@@ -945,6 +1055,9 @@ int oz_batch_destroy(oz_batch_t P) {
     if (P->graph_exec) hipGraphExecDestroy(P->graph_exec);
     if (P->graph) hipGraphDestroy(P->graph);
     if (P->dev) hipFree(P->dev);
+    if (P->aux) (void)hipStreamDestroy(P->aux);
+    if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
+    if (P->ev_join) (void)hipEventDestroy(P->ev_join);
     P->magic = 0;
     delete P;
     return OZ_OK;

@@ -143,7 +143,7 @@ __device__ __forceinline__ void store_tile(const GemmArgs& g, const double (&acc
         // raw tile sums in C' space (every padded row and column is stored)
 #pragma unroll
         for (int r = 0; r < 16; ++r) g.acc[col * g.Mp + row0 + 8 * (r >> 2) + 4 * half + (r & 3)] = acc64[r];
-        if (g.mode != kRawWriteFinal) return;
+        if (g.mode != kRawWriteFinal && g.mode != kRawAddFinal) return;
     }
     if (col >= g.n) return;
     const int32_t f = g.FB[col];
@@ -341,7 +341,9 @@ __device__ __forceinline__ void tile_body(const GemmArgs& g, int64_t tm, int64_t
     auto init64 = [&](double (&a64)[16]) {
 #pragma unroll
         for (int r = 0; r < 16; ++r)
-            a64[r] = (g.mode == kRawAdd) ? g.acc[col * g.Mp + row0 + 8 * (r >> 2) + 4 * half + (r & 3)] : 0.0;
+            a64[r] = (g.mode == kRawAdd || g.mode == kRawAddFinal)
+                         ? g.acc[col * g.Mp + row0 + 8 * (r >> 2) + 4 * half + (r & 3)]
+                         : 0.0;
     };
     double acc64[16];
     double lo64[XD ? 16 : 1];
@@ -505,16 +507,30 @@ gemm_persistent_mixed_kernel(const GemmArgs* __restrict__ probs, const TileItem*
 }
 
 // Persistent form of the wide all-diagonal tile (9 <= s <= kMaxWideSlices, one
-// wave per SIMD), for batched problems above the 2-waves-per-SIMD budget.
-template <int S, bool TOP, bool MULTI>
+// wave per SIMD), for batched problems above the 2-waves-per-SIMD budget; like
+// the mixed form, each tile runs at its own problem's s (one launch for every
+// s in 9..14).  Several INT32 chunks at s >= 13 would spill: those problems
+// take the streaming body instead (MULTI launches see s <= 12 only).
+template <bool TOP, bool MULTI>
 __global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(1, 1))) void
 gemm_wide_persistent_kernel(const GemmArgs* __restrict__ probs, const TileItem* __restrict__ items, int64_t nitems) {
-    using T = TileCfg<S, 2, 2, 2>;
-    __shared__ v4i lds[2][T::STAGE];
+    __shared__ v4i lds[2 * TileCfg<kMaxWideSlices, 2, 2, 2>::STAGE];
     for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
         const TileItem ti = items[it];
         if (ti.prob < 0) continue;
-        tile_body<S, 2, 2, 2, TOP, false, MULTI>(probs[ti.prob], ti.tm, ti.tn, lds);
+        const GemmArgs& g = probs[ti.prob];
+        switch (ti.s) {  // uniform over the block
+            case 9: mixed_tile<9, TOP, MULTI>(g, ti, lds); break;
+            case 10: mixed_tile<10, TOP, MULTI>(g, ti, lds); break;
+            case 11: mixed_tile<11, TOP, MULTI>(g, ti, lds); break;
+            case 12: mixed_tile<12, TOP, MULTI>(g, ti, lds); break;
+            case 13:
+                if constexpr (!MULTI) mixed_tile<13, TOP, false>(g, ti, lds);
+                break;
+            default:
+                if constexpr (!MULTI) mixed_tile<14, TOP, false>(g, ti, lds);
+                break;
+        }
         __syncthreads();
     }
 }
@@ -550,7 +566,9 @@ __device__ __forceinline__ void stream_body(const GemmArgs& g, int s, int top, i
     double acc64[16], lo64[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-        acc64[r] = (g.mode == kRawAdd) ? g.acc[col * g.Mp + row0 + 8 * (r >> 2) + 4 * half + (r & 3)] : 0.0;
+        acc64[r] = (g.mode == kRawAdd || g.mode == kRawAddFinal)
+                       ? g.acc[col * g.Mp + row0 + 8 * (r >> 2) + 4 * half + (r & 3)]
+                       : 0.0;
         lo64[r] = 0.0;
     }
     const bool dd = g.mode == kFinalDD;
@@ -781,7 +799,7 @@ hipError_t launch_stream(const GemmArgs& g, hipStream_t st) {
 
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t st) {
     if (g.s < 1 || g.s > 18 || g.s_lay < g.s) return hipErrorInvalidValue;
-    const bool raw = g.mode == kRawWrite || g.mode == kRawAdd || g.mode == kRawWriteFinal;
+    const bool raw = g.mode == kRawWrite || g.mode == kRawAdd || g.mode == kRawWriteFinal || g.mode == kRawAddFinal;
     if (raw && g.acc == nullptr) return hipErrorInvalidValue;
     if (g.mode == kCombine3M && (g.t1 == nullptr || g.t2 == nullptr || g.cplx)) return hipErrorInvalidValue;
     if (g.mode == kFinalDD && (g.c_lo == nullptr || g.top)) return hipErrorInvalidValue;
@@ -849,37 +867,19 @@ hipError_t launch_gemm_persistent_mixed(const GemmArgs* probs, const TileItem* i
     return hipGetLastError();
 }
 
-namespace {
-template <int S>
-hipError_t launch_wide_persistent_s(const GemmArgs* probs, const TileItem* items, int64_t nitems, int blocks,
-                                    bool top, bool multi, hipStream_t st) {
+hipError_t launch_gemm_wide_persistent(const GemmArgs* probs, const TileItem* items, int64_t nitems, int blocks,
+                                       bool top, bool multi, hipStream_t st) {
+    if (nitems <= 0) return hipSuccess;
+    if (blocks <= 0) return hipErrorInvalidValue;
     dim3 grid(static_cast<unsigned>(blocks)), block(256);
 #define OZ_WIDEP(TOPV, MULTIV) \
-    hipLaunchKernelGGL((gemm_wide_persistent_kernel<S, TOPV, MULTIV>), grid, block, 0, st, probs, items, nitems)
+    hipLaunchKernelGGL((gemm_wide_persistent_kernel<TOPV, MULTIV>), grid, block, 0, st, probs, items, nitems)
     if (top && multi) OZ_WIDEP(true, true);
     else if (top) OZ_WIDEP(true, false);
     else if (multi) OZ_WIDEP(false, true);
     else OZ_WIDEP(false, false);
 #undef OZ_WIDEP
     return hipGetLastError();
-}
-}  // namespace
-
-hipError_t launch_gemm_wide_persistent(const GemmArgs* probs, const TileItem* items, int64_t nitems, int s,
-                                       int blocks, bool top, bool multi, hipStream_t st) {
-    if (nitems <= 0) return hipSuccess;
-    if (blocks <= 0) return hipErrorInvalidValue;
-    // several INT32 chunks from s = 13 on would spill: the streaming body
-    if (multi && s >= 13) return launch_gemm_stream_persistent(probs, items, nitems, s, top, blocks, st);
-    switch (s) {
-        case 9: return launch_wide_persistent_s<9>(probs, items, nitems, blocks, top, multi, st);
-        case 10: return launch_wide_persistent_s<10>(probs, items, nitems, blocks, top, multi, st);
-        case 11: return launch_wide_persistent_s<11>(probs, items, nitems, blocks, top, multi, st);
-        case 12: return launch_wide_persistent_s<12>(probs, items, nitems, blocks, top, multi, st);
-        case 13: return launch_wide_persistent_s<13>(probs, items, nitems, blocks, top, multi, st);
-        case 14: return launch_wide_persistent_s<14>(probs, items, nitems, blocks, top, multi, st);
-        default: return hipErrorInvalidValue;
-    }
 }
 
 hipError_t launch_gemm_stream_persistent(const GemmArgs* probs, const TileItem* items, int64_t nitems, int s,

@@ -29,6 +29,11 @@ hipError_t oz_handle_mark(oz_handle_t h);  // timing event (no-op unless oz_timi
 // library-owned workspace of at least `bytes` (grown on demand); null and
 // *status set on failure
 char* oz_handle_ws(oz_handle_t h, size_t bytes, int* status);
+// LU: the handle's look-ahead stream and three events (created on the first
+// call, kept until oz_destroy), and a grow-only device buffer of at least
+// `bytes` apart from the GEMM workspace (null and *status set on failure)
+int oz_handle_lu_stream(oz_handle_t h, hipStream_t* s2, hipEvent_t* ev);
+char* oz_handle_lu_ws(oz_handle_t h, size_t bytes, int* status);
 // learned slice-count selector attached to the handle (may be null)
 oz_mlp_t oz_handle_selector(oz_handle_t h);
 void oz_handle_set_selector(oz_handle_t h, oz_mlp_t mlp);

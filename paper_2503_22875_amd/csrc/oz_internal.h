@@ -138,13 +138,15 @@ struct GemmArgs {
 // stores the FP64 tile sum acc (before ldexp) into g.acc; kRawAdd adds the new
 // anti-diagonal terms onto the acc already in g.acc (chunk by chunk);
 // kRawWriteFinal does both kRawWrite and kFinal (for beta = 0, where C can be
-// rewritten from acc if the slice count grows); kCombine3M finishes a complex
+// rewritten from acc if the slice count grows); kRawAddFinal does both kRawAdd
+// and kFinal (a growth step with beta = 0 writes C itself); kCombine3M finishes a complex
 // product in the 3-real-product form: this product is T3, t1 / t2 hold T1 / T2,
 // and C (complex) receives alpha (T1 - T2 + i ((T3 - T1) - T2)) + beta C;
 // kFinalDD (streaming kernel only) folds the anti-diagonal sums into a
 // double-double (hi, lo) in the FP64 fold order and writes ldexp(hi, E+F) to C
 // and ldexp(lo, E+F) to c_lo (alpha = 1, beta = 0).
-constexpr int kFinal = 0, kRawWrite = 1, kRawAdd = 2, kRawWriteFinal = 3, kCombine3M = 4, kFinalDD = 5;
+constexpr int kFinal = 0, kRawWrite = 1, kRawAdd = 2, kRawWriteFinal = 3, kCombine3M = 4, kFinalDD = 5,
+              kRawAddFinal = 6;
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t st);
 
 // Batched products: one persistent launch over a list of tiles of many
@@ -164,10 +166,11 @@ hipError_t launch_gemm_stream_persistent(const GemmArgs* probs, const TileItem* 
 // from its GemmArgs) in one persistent launch of 64 x 64 blocks.
 hipError_t launch_gemm_persistent_mixed(const GemmArgs* probs, const TileItem* items, int64_t nitems, int blocks,
                                         bool top, bool multi, hipStream_t st);
-// 9 <= s <= kMaxWideSlices: the wide all-diagonal tile (64 x 64, one block per
-// compute unit); several INT32 chunks at s >= 13 take the streaming body.
-hipError_t launch_gemm_wide_persistent(const GemmArgs* probs, const TileItem* items, int64_t nitems, int s,
-                                       int blocks, bool top, bool multi, hipStream_t st);
+// Tiles of problems with 9 <= s <= kMaxWideSlices (each its own s, from the
+// tile item) on the wide all-diagonal tile (64 x 64, one block per compute
+// unit); with multi (several INT32 chunks) every s must be at most 12.
+hipError_t launch_gemm_wide_persistent(const GemmArgs* probs, const TileItem* items, int64_t nitems, int blocks,
+                                       bool top, bool multi, hipStream_t st);
 
 // Tolerance-driven calls: operand statistics, residual check, final scaling.
 // Per-vector mean square of x * 2^-E (E from maxbits); part: scratch of

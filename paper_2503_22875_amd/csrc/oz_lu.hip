@@ -796,16 +796,15 @@ int oz_zgetrf(oz_handle_t h, int64_t n, double* A, int64_t lda, int32_t* ipiv, i
     // is issued as two products split by columns (first the next panel's
     // columns, then the rest); an entry of an emulated product depends only on
     // its row of op(A) and its column of op(B), so the split changes no result.
+    // the second stream, its events and the info word come from the handle
+    // (created on the first call, reused after): nothing is allocated per call
     hipStream_t s2 = nullptr;
-    hipEvent_t ev_start = nullptr, ev_panel = nullptr, ev_next = nullptr;
-    int32_t* dinfo = nullptr;
-    int rc = OZ_OK;
-    if (hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&ev_start, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&ev_panel, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&ev_next, hipEventDisableTiming) != hipSuccess ||
-        hipMalloc(&dinfo, sizeof(int32_t)) != hipSuccess)
-        rc = OZ_ERR_HIP;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    int rc = oz_handle_lu_stream(h, &s2, ev);
+    if (rc) return rc;
+    hipEvent_t ev_start = ev[0], ev_panel = ev[1], ev_next = ev[2];
+    int32_t* dinfo = reinterpret_cast<int32_t*>(oz_handle_lu_ws(h, 256, &rc));
+    if (rc) return rc;
     if (rc == OZ_OK && (hipMemsetAsync(dinfo, 0, sizeof(int32_t), s) != hipSuccess ||
                         hipEventRecord(ev_start, s) != hipSuccess || hipStreamWaitEvent(s2, ev_start, 0) != hipSuccess))
         rc = OZ_ERR_HIP;
@@ -844,11 +843,6 @@ int oz_zgetrf(oz_handle_t h, int64_t n, double* A, int64_t lda, int32_t* ipiv, i
         rc = OZ_ERR_HIP;
     if (s2 && hipStreamSynchronize(s2) != hipSuccess) rc = OZ_ERR_HIP;
     if (hipStreamSynchronize(s) != hipSuccess) rc = OZ_ERR_HIP;
-    if (dinfo && hipFree(dinfo) != hipSuccess) rc = OZ_ERR_HIP;
-    if (ev_start) (void)hipEventDestroy(ev_start);
-    if (ev_panel) (void)hipEventDestroy(ev_panel);
-    if (ev_next) (void)hipEventDestroy(ev_next);
-    if (s2) (void)hipStreamDestroy(s2);
     return rc;
 }
 
@@ -877,20 +871,15 @@ int oz_zgetri(oz_handle_t h, int64_t n, const double* LU, int64_t lda, const int
     // same bit for bit.  Against I, block row i of L^-1 is zero right of
     // column (i+1) nb: those columns are neither multiplied nor solved (they
     // stay +0, as subtracting +-0 from them would leave them).
-    int32_t* src = nullptr;
-    double* T = nullptr;
+    // T (n x n complex) and the column sources from the handle's LU buffer
+    // (grow-only): nothing is allocated per call once it is large enough
     const int64_t ldt = n;
-    auto release = [&]() {
-        bool ok = true;
-        if (src && hipFree(src) != hipSuccess) ok = false;
-        if (T && hipFree(T) != hipSuccess) ok = false;
-        return ok;
-    };
-    if (hipMalloc(&src, sizeof(int32_t) * n) != hipSuccess ||
-        hipMalloc(&T, sizeof(double) * 2 * static_cast<size_t>(n) * static_cast<size_t>(n)) != hipSuccess) {
-        release();
-        return OZ_ERR_HIP;
-    }
+    const size_t t_bytes = sizeof(double) * 2 * static_cast<size_t>(n) * static_cast<size_t>(n);
+    int wst = OZ_OK;
+    char* ws = oz_handle_lu_ws(h, t_bytes + ((sizeof(int32_t) * static_cast<size_t>(n) + 255) & ~size_t(255)), &wst);
+    if (wst) return wst;
+    double* T = reinterpret_cast<double*>(ws);
+    int32_t* src = reinterpret_cast<int32_t*>(ws + t_bytes);
     const dim3 grid_nn(static_cast<unsigned>((n + 255) / 256), static_cast<unsigned>(n < 65535 ? n : 65535));
     hipLaunchKernelGGL(perm_src_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, ipiv, n, src);
     hipError_t e = hipGetLastError();
@@ -928,7 +917,6 @@ int oz_zgetri(oz_handle_t h, int64_t n, const double* LU, int64_t lda, const int
         if (hipGetLastError() != hipSuccess) rc = OZ_ERR_HIP;
     }
     if (hipStreamSynchronize(s) != hipSuccess && rc == OZ_OK) rc = OZ_ERR_HIP;
-    if (!release() && rc == OZ_OK) rc = OZ_ERR_HIP;
     return rc;
 }
 

@@ -101,11 +101,12 @@ def test_batched_bit_exact_mixed(oz, handle, stream, cplx):
 
 
 @pytest.mark.parametrize("cplx", [0, 1])
-@pytest.mark.parametrize("use_plan", [False, True])
-def test_batched_bit_exact_wide_and_mixed(oz, handle, stream, cplx, use_plan):
+@pytest.mark.parametrize("use_plan,kchunk", [(False, 0), (True, 0), (False, 64)])
+def test_batched_bit_exact_wide_and_mixed(oz, handle, stream, cplx, use_plan, kchunk):
     # fixed slice counts 1..14 in one batch: s <= 8 share one mixed-s launch,
-    # each s in 9..14 takes the wide persistent tile; ragged shapes, every
-    # transpose, beta on half of them; as a one-shot call and as a captured plan
+    # s in 9..14 one wide launch (with several INT32 chunks, s = 13, 14 take
+    # the streaming body); ragged shapes, every transpose, beta on half of
+    # them; as a one-shot call, as a captured plan, and with 64-term chunks
     rng = np.random.default_rng(60 + cplx)
     shapes = [(70, 65, 33), (130, 70, 257), (64, 192, 64), (5, 300, 17), (200, 3, 90), (96, 96, 96), (33, 47, 2),
               (40, 30, 20), (129, 64, 65), (64, 129, 31), (1, 1, 1), (17, 250, 100), (88, 88, 200), (31, 33, 35)]
@@ -118,21 +119,21 @@ def test_batched_bit_exact_wide_and_mixed(oz, handle, stream, cplx, use_plan):
         be = (complex(0.5, -0.25) if i % 2 else 0.0) if cplx else (0.5 if i % 2 else 0.0)
         probs.append((ta, tb, A, B, C0, al, be))
         slices.append(1 + i)
-    print("wide and mixed batch cplx=%d plan=%d" % (cplx, use_plan), flush=True)
+    print("wide and mixed batch cplx=%d plan=%d kchunk=%d" % (cplx, use_plan, kchunk), flush=True)
     if use_plan:
         plan, dev, args = batch_call(oz, handle, stream, cplx, probs, slices, use_plan=True)
         try:
             launches, _, _, sl = oz.oz_batch_info(plan, len(probs))
             assert sl == slices
-            assert launches == 1 + 6  # one mixed launch for s <= 8, one wide launch per s in 9..14
+            assert launches == 2  # one mixed launch for s <= 8, one wide launch for s in 9..14
             stream.synchronize()
             got = [from_dev(d[4], args["m"][i], args["n"][i], d[5]) for i, d in enumerate(dev)]
         finally:
             oz.oz_batch_destroy(plan)
     else:
-        got = batch_call(oz, handle, stream, cplx, probs, slices)
+        got = batch_call(oz, handle, stream, cplx, probs, slices, kchunk=kchunk)
     for i, (ta, tb, A, B, C0, al, be) in enumerate(probs):
-        want = oracle.emu_gemm(ta, tb, A, B, slices[i], alpha=al, beta=be, C=C0)
+        want = oracle.emu_gemm(ta, tb, A, B, slices[i], alpha=al, beta=be, C=C0, kc=kchunk or None)
         assert np.array_equal(got[i], want), (i, ta, tb, A.shape, B.shape, slices[i])
 
 
@@ -353,7 +354,8 @@ def _check_tol_results(probs, got, reps, smax, tol, kc_s):
         r = reps[i]
         s1, s0 = r.slices_used, r.slices_used - r.fallbacks
         assert 1 <= s0 <= s1 <= smax, (i, s0, s1)
-        assert r.resid_est <= tol or s1 == smax, (i, r.resid_est)
+        # the check stops at half the tolerance unless it ran out of slices
+        assert r.resid_est <= tol / 2 or s1 == smax, (i, r.resid_est)
         want = oracle.emu_gemm(ta, tb, A, B, s0, alpha=al, beta=be, C=C0, s_to=s1,
                                kc=oracle.kchunk(kc_s, np.iscomplexobj(A)))
         assert np.array_equal(got[i], want), (i, ta, tb, A.shape, B.shape, s0, s1)

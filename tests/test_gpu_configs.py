@@ -11,8 +11,8 @@ against the oracle (the CPU computes only the sampled rows and columns):
   sample of entries bit-exact and within 1e-12 of the double-double product;
 * the wide-range DGEMM 4096 x 8192 x 4096 (rows of A and columns of B scaled
   by 10^U(-8, 8)) driven by the tolerances 1e-6, 1e-10 and 1e-14: the
-  residual estimate meets each tolerance, the sampled error is within twice
-  it, and the result is bit-exact against the oracle's incremental emulation
+  residual estimate is within half of each tolerance, the sampled error
+  within it, and the result is bit-exact against the oracle's incremental emulation
   from the reported start to the reported final s; and the same DGEMM at
   s = 8 with a forced INT32 split of k into chunks of 2048 terms."""
 import numpy as np
@@ -135,10 +135,9 @@ def test_wide_range_dgemm_tolerance(oz, handle, tol):
     dd = oracle.gemm_dd("N", "N", A, B, rows=rows, cols=cols)
     err = oracle.weighted_error(got, dd, np.abs(A).max(1)[rows], np.abs(B).max(0)[cols])
     print("wide tol %g: sampled weighted error %.3g" % (tol, err))
-    # the check's estimate meets the tolerance; the true error is within the
-    # estimate's factor-of-2 spread of it
-    assert rep.resid_est <= tol
-    assert err <= 2 * tol, (err, tol)
+    # the check stops at half the tolerance; the true error is within it
+    assert rep.resid_est <= tol / 2
+    assert err <= tol, (err, tol)
 
 
 def test_wide_range_dgemm_forced_split_k(oz, handle):

@@ -285,3 +285,59 @@ def test_predicted_slices_match_oracle_network(oz, handle):
         oz.oz_set_selector(handle, None)
         oz.oz_mlp_destroy(net)
 
+
+
+
+def _selection_gain(oz, kind):
+    import bench
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    h = oz.oz_create(0)
+    oz.oz_set_stream(h, stream.cuda_stream)
+    net = None
+    try:
+        oz.oz_load_tuning(h)
+        net = oz.oz_mlp_load(h)
+        oz.oz_set_selector(h, net)
+        print("gain: drawing the %s batch" % kind, flush=True)
+        dev, ns, tols, _ = bench.mixed_batch_on_device(oz, h, 512, seed=0, kind=kind)
+        print("gain: running fixed / rule / escalate / learned", flush=True)
+        out = bench.selection_gain(oz, h, stream, dev, ns, tols, steps=5, warmup=1)
+        print(out, flush=True)
+        for way in ("fixed", "rule", "escalate", "learned"):
+            assert out[way]["pass_true"] == 1.0, way
+        return out
+    finally:
+        oz.oz_set_selector(h, None)
+        if net is not None:
+            oz.oz_mlp_destroy(net)
+        oz.oz_destroy(h)
+
+
+def test_learned_selection_gain_instance_distribution(oz):
+    # 512 problems of the batched workload's sizes, each with its own
+    # structure drawn from the selector's instance distribution and its own
+    # tolerance in [1e-15, 1e-4]: every way of choosing s meets every
+    # problem's tolerance by its true error (judged by the s = 12 emulation);
+    # the learned start spends less INT8 work than the rule and than the
+    # smallest single fixed s that passes every problem, and less time than
+    # that fixed s and than escalation from s = 2 (best of 5 executions).
+    out = _selection_gain(oz, "mixed")
+    assert out["learned"]["int8_tops"] < out["rule"]["int8_tops"] < out["fixed"]["int8_tops"]
+    assert out["learned"]["ms_min"] < out["fixed"]["ms_min"]
+    assert out["learned"]["ms_min"] < out["escalate"]["ms_min"]
+
+
+def test_learned_selection_gain_low_precision_operands(oz):
+    # the same batch with significands of bfloat16 / float16 / float32 /
+    # float64 width: the network sees the narrow significands (its width
+    # features) that the rule's mean-square statistic cannot, so the learned
+    # start beats the rule in INT8 work and in time, and needs well under the
+    # INT8 work of the smallest fixed s that passes every problem.  (That
+    # fixed s, known here only after the fact, runs without the statistics
+    # pass and the residual check.)
+    out = _selection_gain(oz, "lowprec")
+    assert out["learned"]["int8_tops"] < out["rule"]["int8_tops"] < out["fixed"]["int8_tops"]
+    assert out["learned"]["int8_tops"] < 0.7 * out["fixed"]["int8_tops"]
+    assert out["learned"]["ms_min"] < out["rule"]["ms_min"]
+    assert out["learned"]["ms_min"] < out["escalate"]["ms_min"]

@@ -23,6 +23,8 @@ distributions of the workloads the emulated GEMM is benchmarked on:
                       problem from the selector's instance distribution
                       (exponent spread, kept significand bits, zeros, value
                       family), complex, and one tolerance per problem.
+* ``zgemm_batch_lowprec`` the same with significands of bfloat16 / float16 /
+                      float32 / float64 width (operands of lower-precision origin).
 * ``zinv_gauss``      one n x n complex matrix to invert, entries
                       N(0,1) + i N(0,1) (condition number of order n), the
                       stand-in for the application's complex LU-inverted matrix.
@@ -265,14 +267,49 @@ def zgemm_batch_mixed(count=512, seed=0, tol_lo=1e-15, tol_hi=1e-4):
     return params, tols
 
 
+def zgemm_batch_lowprec(count=512, seed=0, tol_lo=1e-15, tol_hi=1e-4):
+    """The heterogeneous batch with operands of lower-precision origin: as
+    ``zgemm_batch_mixed`` (sizes, exponent spread, zeros, family, one
+    tolerance per problem), but every problem's significands keep 8, 11, 24 or
+    53 bits (those of bfloat16, float16, float32 and float64 values), one of
+    the four with equal odds.  Returns (list of parameter dicts, tols)."""
+    sizes = zgemm_batch_sizes(count, seed)
+    rng = np.random.default_rng(seed + 4)
+    params = []
+    for nb in sizes:
+        sigma = int(rng.integers(0, 41))
+        mode = int(rng.integers(0, 3))
+        sig_el = sigma if mode == 0 else (0 if mode == 1 else sigma // 2)
+        bits = (8, 11, 24, 53)[int(rng.integers(0, 4))]
+        zero_q = 0 if rng.random() < 0.7 else int(rng.uniform(0.0, 0.8) * (1 << 24))
+        params.append(dict(m=nb, n=nb, k=nb, sig_el=sig_el, sig_vec=sigma - sig_el, bits=bits,
+                           family=int(rng.integers(0, 2)), zero_q=zero_q,
+                           key=int(rng.integers(0, 1 << 63, dtype=np.int64))))
+    tols = np.exp(rng.uniform(np.log(tol_lo), np.log(tol_hi), size=count))
+    return params, tols
+
+
 def mixed_parts(p):
-    """The two real instances whose operands are the real and imaginary parts
+    """The two real instances whose operands give the real and imaginary parts
     of a ``zgemm_batch_mixed`` problem: p itself, and p with the key replaced
-    by draw 4 of p's key stream (so each part has its own entry draws and its
-    own per-vector exponents)."""
+    by draw 4 of p's key stream and no per-vector spread.  The imaginary part
+    is the second instance's operand scaled by the first one's per-vector
+    powers of two (``vector_exponents``), so both parts of a row of A (column
+    of B) share its scale, as the parts of one complex entry do."""
     q = dict(p)
     q["key"] = int(_draw_scalar(int(p["key"]), 4) & 0x7FFFFFFFFFFFFFFF)
+    q["sig_vec"] = 0
     return p, q
+
+
+def vector_exponents(p):
+    """Per-vector exponents e_vec of an instance: rows of A, columns of B
+    (the generator's draw(vkey, i) mod (sig_vec + 1) - sig_vec // 2)."""
+    _, _, kva, kvb = gen_keys(p["key"])
+    sv = int(p["sig_vec"])
+    ea = (draw(kva, np.arange(int(p["m"]), dtype=np.uint64)) % np.uint64(sv + 1)).astype(np.int64) - sv // 2
+    eb = (draw(kvb, np.arange(int(p["n"]), dtype=np.uint64)) % np.uint64(sv + 1)).astype(np.int64) - sv // 2
+    return ea, eb
 
 
 def mixed_operands(p):
@@ -280,4 +317,7 @@ def mixed_operands(p):
     pr, pi = mixed_parts(p)
     Ar, Br = gen_operands(pr)
     Ai, Bi = gen_operands(pi)
+    ea, eb = vector_exponents(pr)
+    Ai = np.ldexp(Ai, ea[:, None])
+    Bi = np.ldexp(Bi, eb[None, :])
     return np.asfortranarray(Ar + 1j * Ai), np.asfortranarray(Br + 1j * Bi)
