@@ -82,10 +82,16 @@ typedef struct oz_handle_s* oz_handle_t;
  *           64 with s*kchunk*127^2 <= 2^31-1; a nonzero value must be a
  *           positive multiple of 64 not above that bound (used to exercise
  *           the chunked accumulation on small k).
- *  zmode  : complex only.  0 or 4: the 4-real-product form -- one real
+ *  zmode  : complex only.  4: the 4-real-product form -- one real
  *           emulated product over the two-row form of op(A) (see oz_zgemm).
- *           3: the 3-real-product form (fixed slice counts only; a
- *           tolerance-driven or batched call with zmode 3 returns 14): with
+ *           0 (and a NULL prec): the form measured faster -- the 3-real-
+ *           product form for a single fixed-s call (not the double-double
+ *           one) with m, n and k all at least 2048, the 4-product form
+ *           otherwise (tolerance-driven and batched calls, small products,
+ *           k below 2048 as in the LU updates); oz_report_t.zmode_used tells.
+ *           3: the 3-real-product form (fixed slice counts only, up to 8
+ *           in a batched call; a tolerance-driven call with zmode 3 returns
+ *           14): with
  *           op(A) = Ar + i Ai, op(B) = Br + i Bi and the FP64 sums As = Ar + Ai,
  *           Bs = Br + Bi (each rounded once), T1 = Ar Br, T2 = Ai Bi and
  *           T3 = As Bs are three real emulated products, each with its own
@@ -94,13 +100,18 @@ typedef struct oz_handle_s* oz_handle_t;
  *           zmode 4.  Three quarters of the INT8 work; the error is of the same
  *           order (the sums can double the scale of T3).  A row or column
  *           whose sum overflows counts as non-finite.
- *  kernel : GEMM kernel shape; 0 = the default (the 64 x 64 block for
- *           s <= 8; for 9 <= s <= 14 the same all-diagonal block at one wave
- *           per SIMD, except where its registers would not hold the chunked
- *           sums (several INT32 chunks at s >= 13); streaming otherwise),
- *           1 = 128 x 64 block with a 3-stage LDS ring, 2 = 64 x 64 block with
- *           2 stages (both for s <= 8), 3 = per-diagonal streaming (any s).
- *           Every shape gives the same bits.
+ *  kernel : GEMM kernel shape; 0 = the default (for s <= 6 with one INT32
+ *           chunk and at least 512 tiles of 128 x 64, shape 4; else the
+ *           64 x 64 block for s <= 8; for 9 <= s <= 14 the same all-diagonal
+ *           block at one wave per SIMD, except where its registers would not
+ *           hold the chunked sums (several INT32 chunks at s >= 13);
+ *           streaming otherwise), 1 = 128 x 64 block of 8 waves with a
+ *           3-stage LDS ring, 2 = 64 x 64 block of 4 waves (both for s <= 8),
+ *           3 = per-diagonal streaming (any s), 4 = 128 x 64 block of 4
+ *           waves owning two 32-row tiles each, 5 = 128 x 128 block of 8 such
+ *           waves (4 and 5: s <= 6 with one INT32 chunk, the 64 x 64 block
+ *           otherwise).  Batched plans take 0, 1, 2 and 4.  Every shape gives
+ *           the same bits.
  *  sstart : tolerance-driven calls only: the starting slice count; 0 lets
  *           `selector` choose it.
  *  selector: tolerance-driven calls with sstart == 0: 0 = the rule of
@@ -146,7 +157,7 @@ typedef struct {
     int32_t slices_used;   /* s of the final result                          */
     int32_t fallbacks;     /* slices added after the residual check failed   */
     int32_t kchunks;       /* INT32 chunks along k                           */
-    int32_t zmode_used;    /* 4 for complex, 0 for real                      */
+    int32_t zmode_used;    /* complex form used (3 or 4), 0 for real         */
     int32_t reserved;
     double resid_est;      /* a-posteriori error estimate (tol mode), else 0 */
 } oz_report_t;
@@ -473,9 +484,14 @@ int oz_peak(oz_handle_t handle, int kind, int64_t iters, const void* src, void* 
  * plan) for every problem's scales, slices and the work lists, and uploads the
  * descriptors.  Executing it enqueues a fixed sequence on the handle's stream:
  * one launch clearing the scale scratch, one batched exponent scan, one
- * batched digit split, and one persistent GEMM launch per distinct slice count
- * (a single one when every problem uses the same s) whose blocks walk a tile
- * list ordered by work.  No host synchronisation and no allocation happen in
+ * batched digit split, and persistent GEMM launches whose blocks walk a tile
+ * list ordered by work: one for every problem with s <= 8 (each tile at its
+ * problem's s), one for those with 9 <= s <= 14 on a second stream beside it.
+ * With zmode 3 (complex, s <= 8) the scan and split write the three real
+ * parts of each operand, and one block computes the three real products of
+ * a tile in turn (T1 and T2 held in registers) and combines them: one launch
+ * for s <= 6, one on the second stream for s = 7, 8.  Tiles that cover only
+ * padding are never computed.  No host synchronisation and no allocation happen in
  * an execution, so it can be captured: oz_batch_graph_launch captures it into
  * a HIP graph on its first call (the handle's stream must not be the null
  * stream) and replays the graph afterwards.  The operand and output buffers

@@ -20,8 +20,9 @@
  *                          1 <= s <= 8 (oz_prec_t.digits = 1), e.g.
  *                          "fp64_int8_bal6";
  *   "dgemm"                native FP64 on the GPU (rocBLAS), for comparison.
- * OZ_ZMODE = 3 or 4 selects the complex form of zgemm_ in the emulated modes
- * (default 4, the library default); OZ_DEVICE selects the GPU (default 0).
+ * OZ_ZMODE = 0, 3 or 4 selects the complex form of zgemm_ in the emulated
+ * modes (default 0: the library's choice by size, oz_prec_t.zmode); OZ_DEVICE
+ * selects the GPU (default 0).
  *
  * Error behaviour: an illegal argument is reported as the reference BLAS does
  * (a message naming the routine and the 1-based parameter number, written to

@@ -403,6 +403,20 @@ int zgemm_3m(oz_handle_t h, char transa, char transb, int64_t m, int64_t n, int6
     return OZ_OK;
 }
 
+// The complex form of a fixed-s product with zmode 0: the 3-real-product form
+// when every dimension is at least kAuto3mMin, else the 4-product form.
+// Measured on ZGEMM at s = 6 (balanced) and 7: the three products win from
+// m = n = k = 2048 on (0.59 vs 0.64 ms; 3.5 vs 4.5 ms at 4096); with k up to
+// 512, or m = n = k <= 1536, their three splits, T1 and T2 round trips and
+// launches cost more than the quarter of INT8 work they save.
+constexpr int64_t kAuto3mMin = 2048;
+bool use_3m(int cplx, const oz_prec_t* prec, bool tol_mode, bool dd, int64_t m, int64_t n, int64_t k) {
+    const int zmode = prec ? prec->zmode : 0;
+    if (!cplx || tol_mode || dd) return false;
+    if (zmode == 3) return true;
+    return zmode == 0 && m >= kAuto3mMin && n >= kAuto3mMin && k >= kAuto3mMin;
+}
+
 // c_lo != nullptr: double-double result (C the high parts, c_lo the low
 // parts), alpha = 1, beta = 0, fixed s, the streaming kernel.
 int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, int64_t n, int64_t k,
@@ -431,7 +445,7 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
         if (prec->slices < 0 || prec->slices > OZ_MAX_SLICES) return 14;
         if (prec->zmode != 0 && prec->zmode != 3 && prec->zmode != 4) return 14;
         if (cplx && prec->zmode == 3 && prec->slices == 0) return 14;  // 3M: fixed slice counts only
-        if (prec->kernel < 0 || prec->kernel > 3) return 14;
+        if (prec->kernel < 0 || prec->kernel > 5) return 14;
         if (prec->digits != 0 && prec->digits != 1) return 14;
         bal = prec->digits == 1;
         if (prec->slices == 0) {
@@ -456,7 +470,7 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
     const int s_plan = tol_mode ? smax : s;  // largest slice count this call may use
     if (kc < 0 || kc % 64 != 0 || (kc > 0 && kc > kchunk_bound(s_plan, bal))) return 14;
     if (kc == 0) kc = kchunk_bound(s_plan, bal);
-    if (!tol_mode && s > oz::kMaxLiveSlices && (kernel == 1 || kernel == 2)) return 14;
+    if (!tol_mode && s > oz::kMaxLiveSlices && kernel != 0 && kernel != 3) return 14;
     if (!alpha || !beta) return OZ_ERR_ARG;
 
     if (rep) {
@@ -481,7 +495,7 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
         return st;
     }
 
-    if (cplx && prec && prec->zmode == 3) {
+    if (use_3m(cplx, prec, tol_mode, c_lo != nullptr, m, n, k)) {
         // 3-real-product form: real INT32 chunks of k terms
         const int64_t kc3 = prec->kchunk ? prec->kchunk : kchunk_bound(s, bal);
         return zgemm_3m(h, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, s, kc3, kernel, bal, rep,
@@ -835,7 +849,7 @@ int oz_workspace_size(oz_handle_t h, char transa, char transb, int64_t m, int64_
     const bool tol = prec && prec->slices == 0;
     const int smax = (prec && prec->smax) ? prec->smax : kDefaultSmax;
     if (tol && (smax < 1 || smax > OZ_MAX_SLICES)) return 14;
-    if (is_complex && prec && prec->zmode == 3 && !tol) {
+    if (use_3m(is_complex, prec, tol, false, m, n, k)) {
         *bytes = make_plan3(m, n, k, s).total;
         return OZ_OK;
     }

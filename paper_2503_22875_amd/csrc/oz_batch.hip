@@ -30,7 +30,10 @@ constexpr uint32_t kBatchMagic = 0x6f7a6274u;  // "ozbt"
 // Launch kinds of a group: the all-diagonal tile of one s on 128 x 64 or
 // 64 x 64 blocks, the streaming body, the 64 x 64 tile of mixed slice counts
 // (s <= 8, each problem its own), the wide tile (9 <= s <= 14).
-constexpr int kTile128 = 1, kTile64 = 2, kStream = 3, kMixed = 4, kWide = 5;
+// kFused3 / kFused3W: fused 3-real-product tiles of complex products, s <= 6
+// at two blocks per CU / s = 7, 8 at one.
+constexpr int kTile128 = 1, kTile64 = 2, kStream = 3, kMixed = 4, kWide = 5, kTile128x64 = 6, kFused3 = 7,
+              kFused3W = 8;
 
 struct Group {
     int s;          // 0 for a mixed group
@@ -60,6 +63,10 @@ struct oz_batch_s {
     int64_t n_maxbits;
     size_t off_ops, off_scan, off_digits, off_args;
     int64_t n_scan, n_digits;
+    // 3-real-product plans: the three-part split lists
+    bool z3;
+    size_t off_ops3, off_scan3, off_digits3;
+    int64_t n_scan3, n_digits3;
     std::vector<Group> groups;
     std::vector<ScaleOnly> scale_only;
     std::vector<int32_t> slices;  // per problem (0 for quick returns)
@@ -130,10 +137,13 @@ oz::OperandView view(char t, const double* X, int64_t ld, int64_t nv, int64_t k,
 
 // One persistent launch over the tiles of `members` (indices into args), all
 // with slice count sv (sv = 0: a mixed group, each problem at its own
-// args[i].s): launch kind as requested (kernel 1 / 2, or kStream, kMixed,
-// kWide), else the tuned vote, else 128 x 64 when the group has at least two
-// such tiles per compute unit; tile order 0 (problems with the most work per
-// tile first) or 1 (whole problems dealt to per-XCD queues) as tuned.
+// args[i].s): launch kind as requested (kTile128, kTile64, kTile128x64 --
+// which falls back to kTile64 unless sv <= 6 and every problem is one INT32
+// chunk -- or kStream, kMixed, kWide), else the tuned vote, else 128 x 64 when
+// the group has at least two such tiles per compute unit; tile order 0
+// (problems with the most work per tile first) or 1 (whole problems dealt to
+// per-XCD queues) as tuned.  Tiles that hold only padding rows or columns of
+// the slice layout are left out.
 void build_group(const std::vector<oz::GemmArgs>& args, std::vector<size_t> members, int sv, int kernel, int cplx,
                  int cus, const std::vector<oz::TuneEntry>& tune, Group* out, std::vector<oz::TileItem>* out_items) {
     // tuned choice for one problem: the entry with the same complexity and s
@@ -173,23 +183,33 @@ void build_group(const std::vector<oz::GemmArgs>& args, std::vector<size_t> memb
     }
     int tile = kernel;
     if (!tile) tile = have_tune ? (vote_tile[1] > vote_tile[2] ? 1 : 2) : (big >= 2 * cus ? 1 : 2);
+    // the two-tile 128 x 64 block holds one s <= 6 and a single INT32 chunk
+    if (tile == kTile128x64 && (sv < 1 || sv > 6 || multi)) tile = kTile64;
     const int order = have_tune && vote_order[1] > vote_order[0] ? 1 : 0;
-    const int64_t bm = tile == kTile128 ? 128 : 64, bn = 64;
+    const int64_t bm = (tile == kTile128 || tile == kTile128x64) ? 128 : 64, bn = 64;
     // work of one tile: slice pairs times steps
     auto tile_work = [&](size_t i) {
         const int64_t si = args[i].s;
         return static_cast<double>(si * (si + 1) / 2) * static_cast<double>(args[i].kpad);
     };
     std::stable_sort(members.begin(), members.end(), [&](size_t a, size_t b) { return tile_work(a) > tile_work(b); });
+    // tiles holding valid C' rows and columns only (rows of a complex two-row
+    // operand: 16 complex rows span 32 rows of C'); the padding of the slice
+    // layout is never computed
+    auto tiles_m = [&](size_t i) {
+        const int64_t rows = args[i].cplx ? 2 * oz::round_up(args[i].m, 16) : args[i].m;
+        return std::min<int64_t>((rows + bm - 1) / bm, args[i].Mp / bm);
+    };
+    auto tiles_n = [&](size_t i) { return std::min<int64_t>((args[i].n + bn - 1) / bn, args[i].Np / bn); };
     auto tiles_of = [&](size_t i, std::vector<oz::TileItem>& dst) {
-        for (int64_t tm = 0; tm < args[i].Mp / bm; ++tm)
-            for (int64_t tn = 0; tn < args[i].Np / bn; ++tn)
+        for (int64_t tm = 0; tm < tiles_m(i); ++tm)
+            for (int64_t tn = 0; tn < tiles_n(i); ++tn)
                 dst.push_back({static_cast<int32_t>(i), static_cast<int32_t>(tm), static_cast<int32_t>(tn),
                                static_cast<int32_t>(args[i].s)});
     };
     std::vector<oz::TileItem>& items = *out_items;
     items.clear();
-    const int64_t per_cu = (tile == kTile128 || tile == kWide) ? 1 : 2;  // blocks resident per compute unit
+    const int64_t per_cu = (tile == kTile128 || tile == kWide || tile == kFused3W) ? 1 : 2;  // blocks per CU
     if (order == 0) {
         for (size_t i : members) tiles_of(i, items);
     } else {
@@ -205,7 +225,7 @@ void build_group(const std::vector<oz::GemmArgs>& args, std::vector<size_t> memb
             for (int y = 1; y < kX; ++y)
                 if (load[y] < load[x]) x = y;
             tiles_of(i, q[x]);
-            load[x] += static_cast<double>(args[i].Mp / bm) * (args[i].Np / bn) * tile_work(i);
+            load[x] += static_cast<double>(tiles_m(i)) * tiles_n(i) * tile_work(i);
         }
         size_t longest = 0;
         for (int x = 0; x < kX; ++x) longest = std::max(longest, q[x].size());
@@ -230,20 +250,25 @@ hipError_t launch_group(const Group& gr, const oz::GemmArgs* dargs, const oz::Ti
         case kStream: return oz::launch_gemm_stream_persistent(dargs, items, gr.nitems, gr.s, top, gr.blocks, st);
         case kMixed: return oz::launch_gemm_persistent_mixed(dargs, items, gr.nitems, gr.blocks, top, gr.multi, st);
         case kWide: return oz::launch_gemm_wide_persistent(dargs, items, gr.nitems, gr.blocks, top, gr.multi, st);
+        case kFused3: return oz::launch_gemm_persistent_3m(dargs, items, gr.nitems, gr.blocks, false, st);
+        case kFused3W: return oz::launch_gemm_persistent_3m(dargs, items, gr.nitems, gr.blocks, true, st);
         default:
-            return oz::launch_gemm_persistent(dargs, items, gr.nitems, gr.s, gr.tile, gr.blocks, top, gr.multi, st);
+            return oz::launch_gemm_persistent(dargs, items, gr.nitems, gr.s, gr.tile == kTile128x64 ? 4 : gr.tile,
+                                              gr.blocks, top, gr.multi, st);
     }
 }
 
-// Every group of a round: the wide and streaming groups (s > 8) on the
-// plan's second stream, the others on st, when there are both kinds.
+// Every group of a round: the one-wave-per-SIMD groups (wide, streaming and
+// fused s = 7, 8) on the plan's second stream, the others on st, when there
+// are both kinds.
 // items_of(gr) gives the device address of a group's tile list.
 template <class ItemsOf>
 hipError_t launch_groups(oz_batch_t P, const std::vector<Group>& groups, const oz::GemmArgs* dargs, ItemsOf items_of,
                          bool top, hipStream_t st) {
+    auto one_wave = [](const Group& gr) { return gr.tile == kWide || gr.tile == kStream || gr.tile == kFused3W; };
     bool narrow = false, wide = false;
     for (const Group& gr : groups) {
-        if (gr.tile == kWide || gr.tile == kStream) wide = true;
+        if (one_wave(gr)) wide = true;
         else narrow = true;
     }
     const bool fork = narrow && wide;
@@ -253,11 +278,9 @@ hipError_t launch_groups(oz_batch_t P, const std::vector<Group>& groups, const o
         if (e == hipSuccess) e = hipStreamWaitEvent(P->aux, P->ev_fork, 0);
     }
     for (const Group& gr : groups)
-        if (e == hipSuccess && (gr.tile == kWide || gr.tile == kStream))
-            e = launch_group(gr, dargs, items_of(gr), top, fork ? P->aux : st);
+        if (e == hipSuccess && one_wave(gr)) e = launch_group(gr, dargs, items_of(gr), top, fork ? P->aux : st);
     for (const Group& gr : groups)
-        if (e == hipSuccess && gr.tile != kWide && gr.tile != kStream)
-            e = launch_group(gr, dargs, items_of(gr), top, st);
+        if (e == hipSuccess && !one_wave(gr)) e = launch_group(gr, dargs, items_of(gr), top, st);
     if (fork) {
         if (e == hipSuccess) e = hipEventRecord(P->ev_join, P->aux);
         if (e == hipSuccess) e = hipStreamWaitEvent(st, P->ev_join, 0);
@@ -299,7 +322,6 @@ void round_groups(const std::vector<oz::GemmArgs>& args, const std::vector<size_
         Group gr;
         std::vector<oz::TileItem> it;
         build_group(args, mem, sv, kind, cplx, cus, tune, &gr, &it);
-        if (kind) gr.tile = kind;
         groups->push_back(gr);
         items->push_back(std::move(it));
     };
@@ -339,8 +361,9 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
     double tol = 0.0;
     int smax = kDefaultSmax, sstart = 0, selector = 0;
     if (prec) {
-        if (prec->kernel < 0 || prec->kernel > 2 || prec->digits < 0 || prec->digits > 1) return 14;
-        if (prec->zmode != 0 && prec->zmode != 4) return 14;  // batched: the 4-product form only
+        if (prec->kernel < 0 || prec->kernel > 4 || prec->kernel == 3 || prec->digits < 0 || prec->digits > 1)
+            return 14;
+        if (prec->zmode != 0 && prec->zmode != 3 && prec->zmode != 4) return 14;
         if (prec->slices == 0) {
             // tolerance-driven: s per problem chosen at execution
             tol_mode = true;
@@ -361,11 +384,14 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
             if (prec->slices < 1 || prec->slices > oz::kMaxWideSlices) return 14;  // fixed s per problem, s <= 14
             s_default = prec->slices;
         }
-        kernel = prec->kernel;
+        kernel = prec->kernel == 4 ? kTile128x64 : prec->kernel;
         kc_forced = prec->kchunk;
         bal = prec->digits == 1;
     }
     if (tols && !tol_mode) return 14;  // per-problem tolerances: tolerance-driven plans only
+    // 3-real-product form: complex products with fixed slice counts up to 8
+    const bool z3 = cplx && prec && prec->zmode == 3;
+    if (z3 && tol_mode) return 14;
     // argument checks per problem (reference-BLAS positions)
     for (int32_t b = 0; b < batch; ++b) {
         if (!trans_ok(transa[b])) return 1;
@@ -380,7 +406,7 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
         if (ldc[b] < (m[b] > 1 ? m[b] : 1)) return 13;
         const int sb = slices ? slices[b] : s_default;
         if (sb < 1 || sb > (tol_mode ? OZ_MAX_SLICES : oz::kMaxWideSlices)) return 14;
-        if (bal && sb > oz::kMaxLiveSlices) return 14;  // balanced digits: s <= 8
+        if ((bal || z3) && sb > oz::kMaxLiveSlices) return 14;  // balanced digits, 3 products: s <= 8
         if (kc_forced < 0 || kc_forced % 64 != 0 || (kc_forced > 0 && kc_forced > kchunk_bound(sb, bal))) return 14;
     }
     if (oz_handle_use_device(h)) return OZ_ERR_HIP;
@@ -411,14 +437,19 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
     P->kernel = kernel;
     P->cplx = cplx;
     P->n_stat_items = P->n_hist = P->n_wt = P->n_gv = P->n_row = P->n_final = P->dyn_cap = 0;
+    P->z3 = z3;
+    P->off_ops3 = P->off_scan3 = P->off_digits3 = 0;
+    P->n_scan3 = P->n_digits3 = 0;
 
     // ---- per-problem layouts and workspace offsets --------------------------
     struct Prob {
         int32_t b;
         int s;
         oz::OperandView va, vb;
-        oz::SliceLayout la, lb;
+        oz::SliceLayout la, lb;  // 3-real-product form: the real layout of each part
         size_t off_maxa, off_maxb, off_ea, off_fb, off_sa, off_sb;
+        // 3-real-product form: part q (real, imaginary, sum) of each side
+        size_t off3_maxa[3], off3_maxb[3], off3_ea[3], off3_fb[3], off3_sa[3], off3_sb[3];
         int64_t kc;
         int64_t work;  // tiles x steps (for ordering)
     };
@@ -445,8 +476,8 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
         q.s = slices ? slices[b] : s_default;
         q.va = view(transa[b], A[b], lda[b], m[b], k[b], cplx, 1);
         q.vb = view(transb[b], B[b], ldb[b], n[b], k[b], cplx, 0);
-        q.la = oz::slice_layout(1, cplx, m[b], k[b], q.s);
-        q.lb = oz::slice_layout(0, cplx, n[b], k[b], q.s);
+        q.la = oz::slice_layout(1, z3 ? 0 : cplx, m[b], k[b], q.s);
+        q.lb = oz::slice_layout(0, z3 ? 0 : cplx, n[b], k[b], q.s);
         q.la.bal = q.lb.bal = bal ? 1 : 0;
         if (q.la.rows_pad / 64 > 65535 || q.lb.rows_pad / 64 > 65535) {
             delete P;
@@ -457,6 +488,17 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
         n_max += m[b];
         q.off_maxb = static_cast<size_t>(n_max) * 8;
         n_max += n[b];
+        if (z3) {
+            // part 0 reuses the offsets above; parts 1, 2 follow
+            q.off3_maxa[0] = q.off_maxa;
+            q.off3_maxb[0] = q.off_maxb;
+            for (int pq = 1; pq < 3; ++pq) {
+                q.off3_maxa[pq] = static_cast<size_t>(n_max) * 8;
+                n_max += m[b];
+                q.off3_maxb[pq] = static_cast<size_t>(n_max) * 8;
+                n_max += n[b];
+            }
+        }
         probs.push_back(q);
         P->prob_b.push_back(b);
         P->tols.push_back(tols ? tols[b] : tol);
@@ -471,6 +513,22 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
         q.off_fb = take(sizeof(int32_t) * static_cast<size_t>(q.lb.rows_pad));
         q.off_sa = take(static_cast<size_t>(q.s) * q.la.rows_pad * q.la.kpad);
         q.off_sb = take(static_cast<size_t>(q.s) * q.lb.rows_pad * q.lb.kpad);
+        if (z3) {
+            q.off3_ea[0] = q.off_ea;
+            q.off3_fb[0] = q.off_fb;
+            q.off3_sa[0] = q.off_sa;
+            q.off3_sb[0] = q.off_sb;
+            q.off3_maxa[0] = q.off_maxa;
+            q.off3_maxb[0] = q.off_maxb;
+            for (int pq = 1; pq < 3; ++pq) {
+                q.off3_maxa[pq] += P->off_maxbits;
+                q.off3_maxb[pq] += P->off_maxbits;
+                q.off3_ea[pq] = take(sizeof(int32_t) * static_cast<size_t>(q.va.nv));
+                q.off3_fb[pq] = take(sizeof(int32_t) * static_cast<size_t>(q.lb.rows_pad));
+                q.off3_sa[pq] = take(static_cast<size_t>(q.s) * q.la.rows_pad * q.la.kpad);
+                q.off3_sb[pq] = take(static_cast<size_t>(q.s) * q.lb.rows_pad * q.lb.kpad);
+            }
+        }
     }
     // tolerance-driven buffers per problem: raw sums, statistics, check vectors
     struct TolOff {
@@ -505,9 +563,35 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
     // ---- split work lists -----------------------------------------------------
     std::vector<oz::SplitOp> ops;
     std::vector<oz::BlockItem> scan_items, dig_items;
+    std::vector<oz::Split3Op> ops3;
+    std::vector<oz::BlockItem> scan3_items, dig3_items;
     // device addresses are known after allocation: store offsets now, patch below
     auto at = [](size_t off) { return static_cast<uintptr_t>(off); };
     for (const Prob& q : probs) {
+        if (z3) {
+            for (int side = 0; side < 2; ++side) {
+                oz::Split3Op so;
+                so.op = side == 0 ? q.va : q.vb;
+                so.lay = side == 0 ? q.la : q.lb;
+                for (int pq = 0; pq < 3; ++pq) {
+                    so.o.maxbits[pq] = reinterpret_cast<uint64_t*>(at(side == 0 ? q.off3_maxa[pq] : q.off3_maxb[pq]));
+                    so.o.E[pq] = reinterpret_cast<int32_t*>(at(side == 0 ? q.off3_ea[pq] : q.off3_fb[pq]));
+                    so.o.slices[pq] = reinterpret_cast<int8_t*>(at(side == 0 ? q.off3_sa[pq] : q.off3_sb[pq]));
+                }
+                const int32_t opi = static_cast<int32_t>(ops3.size());
+                ops3.push_back(so);
+                int64_t bx, by;
+                oz::scan_blocks(so.op, &bx, &by);
+                for (int64_t y = 0; y < by; ++y)
+                    for (int64_t x = 0; x < bx; ++x)
+                        scan3_items.push_back({opi, static_cast<int32_t>(x), static_cast<int32_t>(y), 0});
+                oz::digits3_blocks(so.lay, &bx, &by);
+                for (int64_t y = 0; y < by; ++y)
+                    for (int64_t x = 0; x < bx; ++x)
+                        dig3_items.push_back({opi, static_cast<int32_t>(x), static_cast<int32_t>(y), 0});
+            }
+            continue;
+        }
         for (int side = 0; side < 2; ++side) {
             oz::SplitOp so;
             so.op = side == 0 ? q.va : q.vb;
@@ -541,17 +625,19 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
         const Prob& q = probs[i];
         oz::GemmArgs& g = args[i];
         std::memset(&g, 0, sizeof(g));
-        g.SA = reinterpret_cast<const int8_t*>(at(q.off_sa));
-        g.SB = reinterpret_cast<const int8_t*>(at(q.off_sb));
-        g.EA = reinterpret_cast<const int32_t*>(at(q.off_ea));
-        g.FB = reinterpret_cast<const int32_t*>(at(q.off_fb));
+        // 3-real-product form: this descriptor is T3's (the sum parts), whose
+        // scales also mark non-finite input; T1 and T2 follow below
+        g.SA = reinterpret_cast<const int8_t*>(at(z3 ? q.off3_sa[2] : q.off_sa));
+        g.SB = reinterpret_cast<const int8_t*>(at(z3 ? q.off3_sb[2] : q.off_sb));
+        g.EA = reinterpret_cast<const int32_t*>(at(z3 ? q.off3_ea[2] : q.off_ea));
+        g.FB = reinterpret_cast<const int32_t*>(at(z3 ? q.off3_fb[2] : q.off_fb));
         g.Mp = q.la.rows_pad;
         g.Np = q.lb.rows_pad;
         g.kpad = q.la.kpad;
         g.chunk_steps = q.kc / oz::kStep;
         g.s = q.s;
         g.s_lay = q.s;
-        g.cplx = cplx;
+        g.cplx = z3 ? 0 : cplx;
         g.bal = q.la.bal;
         // tolerance-driven: raw sums for the check; with beta = 0 also C, which
         // is then rewritten only for problems whose slice count grows
@@ -568,8 +654,37 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
         g.beta_zero = (g.beta_r == 0.0 && g.beta_i == 0.0) ? 1 : 0;
         if (tol_mode && g.beta_zero) g.mode = oz::kRawWriteFinal;
     }
+    // device descriptors: one per problem, or (3-real-product form) T1, T2, T3
+    // of each problem in turn
+    std::vector<oz::GemmArgs> dargs_host;
+    if (z3) {
+        for (size_t i = 0; i < probs.size(); ++i) {
+            const Prob& q = probs[i];
+            for (int pq = 0; pq < 3; ++pq) {
+                oz::GemmArgs g = args[i];
+                g.SA = reinterpret_cast<const int8_t*>(at(q.off3_sa[pq]));
+                g.SB = reinterpret_cast<const int8_t*>(at(q.off3_sb[pq]));
+                g.EA = reinterpret_cast<const int32_t*>(at(q.off3_ea[pq]));
+                g.FB = reinterpret_cast<const int32_t*>(at(q.off3_fb[pq]));
+                dargs_host.push_back(g);
+            }
+        }
+    }
     std::vector<std::vector<oz::TileItem>> group_items;
-    if (!tol_mode) {
+    if (z3) {
+        // fused tiles: s <= 6 at two blocks per CU, s = 7, 8 at one (second stream)
+        std::vector<size_t> lo, hi;
+        for (size_t i = 0; i < probs.size(); ++i) (probs[i].s <= 6 ? lo : hi).push_back(3 * i);
+        for (int pass = 0; pass < 2; ++pass) {
+            const std::vector<size_t>& mem = pass == 0 ? hi : lo;
+            if (mem.empty()) continue;
+            Group gr;
+            std::vector<oz::TileItem> it;
+            build_group(dargs_host, mem, 0, pass == 0 ? kFused3W : kFused3, cplx, cus, oz_handle_tuning(h), &gr, &it);
+            P->groups.push_back(gr);
+            group_items.push_back(std::move(it));
+        }
+    } else if (!tol_mode) {
         std::vector<size_t> members(probs.size());
         for (size_t i = 0; i < probs.size(); ++i) members[i] = i;
         round_groups(args, members, [&](size_t i) { return probs[i].s; }, kernel, cplx, cus, oz_handle_tuning(h),
@@ -579,7 +694,14 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
     P->off_ops = take(sizeof(oz::SplitOp) * ops.size());
     P->off_scan = take(sizeof(oz::BlockItem) * scan_items.size());
     P->off_digits = take(sizeof(oz::BlockItem) * dig_items.size());
-    P->off_args = take(sizeof(oz::GemmArgs) * args.size());
+    P->off_args = take(sizeof(oz::GemmArgs) * (z3 ? dargs_host.size() : args.size()));
+    if (z3) {
+        P->off_ops3 = take(sizeof(oz::Split3Op) * ops3.size());
+        P->off_scan3 = take(sizeof(oz::BlockItem) * scan3_items.size());
+        P->off_digits3 = take(sizeof(oz::BlockItem) * dig3_items.size());
+        P->n_scan3 = static_cast<int64_t>(scan3_items.size());
+        P->n_digits3 = static_cast<int64_t>(dig3_items.size());
+    }
     for (size_t gi = 0; gi < P->groups.size(); ++gi)
         P->groups[gi].off_items = take(sizeof(oz::TileItem) * group_items[gi].size());
     P->n_scan = static_cast<int64_t>(scan_items.size());
@@ -698,13 +820,20 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
         so.E = fix(so.E);
         so.slices = fix(so.slices);
     }
-    for (oz::GemmArgs& g : args) {
-        g.SA = fix(g.SA);
-        g.SB = fix(g.SB);
-        g.EA = fix(g.EA);
-        g.FB = fix(g.FB);
-        if (g.acc) g.acc = fix(g.acc);
-    }
+    for (auto* list : {&args, &dargs_host})
+        for (oz::GemmArgs& g : *list) {
+            g.SA = fix(g.SA);
+            g.SB = fix(g.SB);
+            g.EA = fix(g.EA);
+            g.FB = fix(g.FB);
+            if (g.acc) g.acc = fix(g.acc);
+        }
+    for (oz::Split3Op& so : ops3)
+        for (int pq = 0; pq < 3; ++pq) {
+            so.o.maxbits[pq] = fix(so.o.maxbits[pq]);
+            so.o.E[pq] = fix(so.o.E[pq]);
+            so.o.slices[pq] = fix(so.o.slices[pq]);
+        }
     for (oz::GemmArgs& g : args_add) {
         g.SA = fix(g.SA);
         g.SB = fix(g.SB);
@@ -751,7 +880,14 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
     up_load(P->off_ops, ops.data(), sizeof(oz::SplitOp) * ops.size());
     up_load(P->off_scan, scan_items.data(), sizeof(oz::BlockItem) * scan_items.size());
     up_load(P->off_digits, dig_items.data(), sizeof(oz::BlockItem) * dig_items.size());
-    up_load(P->off_args, args.data(), sizeof(oz::GemmArgs) * args.size());
+    if (z3) {
+        up_load(P->off_args, dargs_host.data(), sizeof(oz::GemmArgs) * dargs_host.size());
+        up_load(P->off_ops3, ops3.data(), sizeof(oz::Split3Op) * ops3.size());
+        up_load(P->off_scan3, scan3_items.data(), sizeof(oz::BlockItem) * scan3_items.size());
+        up_load(P->off_digits3, dig3_items.data(), sizeof(oz::BlockItem) * dig3_items.size());
+    } else {
+        up_load(P->off_args, args.data(), sizeof(oz::GemmArgs) * args.size());
+    }
     for (size_t gi = 0; gi < P->groups.size(); ++gi)
         up_load(P->groups[gi].off_items, group_items[gi].data(), sizeof(oz::TileItem) * group_items[gi].size());
     if (tol_mode) {
@@ -1013,6 +1149,15 @@ int oz_batch_execute(oz_batch_t P) {
     if (e == hipSuccess)
         e = oz::launch_digits_batched(ops, reinterpret_cast<const oz::BlockItem*>(dev + P->off_digits), P->n_digits,
                                       st);
+    if (P->z3) {
+        const oz::Split3Op* ops3 = reinterpret_cast<const oz::Split3Op*>(dev + P->off_ops3);
+        if (e == hipSuccess)
+            e = oz::launch_scan3_batched(ops3, reinterpret_cast<const oz::BlockItem*>(dev + P->off_scan3),
+                                         P->n_scan3, st);
+        if (e == hipSuccess)
+            e = oz::launch_digits3_batched(ops3, reinterpret_cast<const oz::BlockItem*>(dev + P->off_digits3),
+                                           P->n_digits3, st);
+    }
     const oz::GemmArgs* args = reinterpret_cast<const oz::GemmArgs*>(dev + P->off_args);
     if (e == hipSuccess) e = oz_handle_mark(h);  // between split and GEMM
     if (e == hipSuccess)
@@ -1069,7 +1214,7 @@ int oz_batch_report(oz_batch_t P, oz_report_t* reps) {
     for (size_t b = 0; b < P->slices.size(); ++b) {
         std::memset(&reps[b], 0, sizeof(oz_report_t));
         reps[b].slices_used = P->slices[b];
-        reps[b].zmode_used = P->cplx ? 4 : 0;
+        reps[b].zmode_used = P->cplx ? (P->z3 ? 3 : 4) : 0;
     }
     for (size_t i = 0; i < P->prob_b.size(); ++i) {
         oz_report_t& r = reps[P->prob_b[i]];

@@ -27,7 +27,7 @@ struct Config {
     int mode = kFixed;
     int slices = 7;
     double tol = 0.0;
-    int zmode = 4;
+    int zmode = 0;  // the library's measured choice
     int device = 0;
 };
 
@@ -119,7 +119,7 @@ void configure(Ctx& c) {
     }
     if (const char* z = std::getenv("OZ_ZMODE")) {
         const int v = std::atoi(z);
-        if (v != 3 && v != 4) die("OZ_ZMODE must be 3 or 4", z);
+        if (v != 0 && v != 3 && v != 4) die("OZ_ZMODE must be 0, 3 or 4", z);
         c.cfg.zmode = v;
     }
     if (const char* d = std::getenv("OZ_DEVICE")) c.cfg.device = std::atoi(d);
@@ -363,7 +363,7 @@ void gemm(const char* name, int cplx, const char* transa, const char* transb, co
             p.smax = 12;
         }
         if (cplx) p.zmode = c.cfg.zmode;
-        if (cplx && c.cfg.mode == kTol) p.zmode = 4;  // tolerance-driven calls use the 4-product form
+        if (cplx && c.cfg.mode == kTol && p.zmode == 3) p.zmode = 4;  // tolerance-driven calls: 4-product form
         oz_report_t rep;
         const int s = cplx ? oz_zgemm(c.oz, ta, tb, m, n, k, alpha, dA, la, dB, lb, beta, dC, lc, &p, &rep)
                            : oz_dgemm(c.oz, ta, tb, m, n, k, alpha, dA, la, dB, lb, beta, dC, lc, &p, &rep);

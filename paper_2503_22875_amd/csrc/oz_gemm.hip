@@ -241,9 +241,13 @@ __device__ __forceinline__ void store_tile_dd(const GemmArgs& g, const double (&
     }
 }
 
-template <int S, int WMW, int WNW, int NST>
+// TM: 32-row MFMA tiles per wave along M (1 or 2).  With TM = 2 a wave owns
+// a 64 x 32 sub-tile and every B fragment read from LDS feeds two MFMAs, so
+// the block reads 3s instead of 4s fragments per 2 s(s+1)/2 products and the
+// ring carries fewer bytes per MFMA.
+template <int S, int WMW, int WNW, int NST, int TM = 1>
 struct TileCfg {
-    static constexpr int BM = 32 * WMW, BN = 32 * WNW;
+    static constexpr int BM = 32 * WMW * TM, BN = 32 * WNW;
     static constexpr int NW = WMW * WNW;                     // waves per block
     static constexpr int RA = 2 * S * (BM / 64);             // 1 KiB runs of A per stage
     static constexpr int RB = 2 * S * (BN / 64);             // 1 KiB runs of B per stage
@@ -260,12 +264,19 @@ struct TileCfg {
 // One BM x BN tile (tile row tm, tile column tn) of the product described by g,
 // staged through the caller's LDS ring lds[NST][STAGE].
 // XD: fold into a double-double and write C_hi / C_lo (kFinalDD).
-template <int S, int WMW, int WNW, int NST, bool TOP, bool DIAG, bool MULTI, bool XD = false>
+// OUT: hand the folded FP64 tile sums (before the scales) to the caller in
+// out[16] instead of running the epilogue (one 32-row tile per wave, FP64 sums).
+template <int S, int WMW, int WNW, int NST, bool TOP, bool DIAG, bool MULTI, bool XD = false, int TM = 1,
+          bool OUT = false>
 __device__ __forceinline__ void tile_body(const GemmArgs& g, int64_t tm, int64_t tn,
-                                          v4i (*lds)[TileCfg<S, WMW, WNW, NST>::STAGE]) {
-    using T = TileCfg<S, WMW, WNW, NST>;
+                                          v4i (*lds)[TileCfg<S, WMW, WNW, NST, TM>::STAGE], double* out = nullptr) {
+    using T = TileCfg<S, WMW, WNW, NST, TM>;
     constexpr int DLO = TOP ? S - 1 : 0;  // lowest live diagonal index (d - 2)
     constexpr int ND = S - DLO;           // live INT32 diagonal tiles
+    // two sub-tiles per wave keep twice the INT32 tiles live: not with the
+    // chunked FP64 sums, the double-double fold or the diagonal export
+    static_assert(TM == 1 || (TM == 2 && !MULTI && !XD && !DIAG), "TM = 2: single-chunk FP64 results only");
+    static_assert(!OUT || (TM == 1 && !XD && !DIAG && !TOP), "OUT: one tile per wave, all diagonals, FP64 sums");
 
     // the wave index is uniform: kept in a scalar register, the copy addresses
     // below are scalar arithmetic off the vector pipe
@@ -284,22 +295,19 @@ __device__ __forceinline__ void tile_body(const GemmArgs& g, int64_t tm, int64_t
     // order, so each run keeps a uniform source pointer that advances by
     // 2*s_lay planes per issue.
     const v4i* run_src[T::RHI];
-    int64_t run_adv[T::RHI];
+    const int64_t adv_a = 2 * g.s_lay * g.Mp, adv_b = 2 * g.s_lay * g.Np;  // per issue, A runs / B runs
 #pragma unroll
     for (int i = 0; i < T::RHI; ++i) {
         const int j = wave + T::NW * i;  // wave-uniform
         run_src[i] = SA;
-        run_adv[i] = 0;
         if (j >= T::R) continue;
         if (j < T::RA) {
             const int hp = j / (T::BM / 64), rb = j % (T::BM / 64);
             run_src[i] = SA + (static_cast<int64_t>(hp / S) * g.s_lay + hp % S) * g.Mp + tm * T::BM + rb * 64;
-            run_adv[i] = 2 * g.s_lay * g.Mp;
         } else {
             const int jb = j - T::RA;
             const int hp = jb / (T::BN / 64), cb = jb % (T::BN / 64);
             run_src[i] = SB + (static_cast<int64_t>(hp / S) * g.s_lay + hp % S) * g.Np + tn * T::BN + cb * 64;
-            run_adv[i] = 2 * g.s_lay * g.Np;
         }
     }
     auto issue = [&](int buf) {
@@ -309,7 +317,7 @@ __device__ __forceinline__ void tile_body(const GemmArgs& g, int64_t tm, int64_t
             if (j >= T::R) break;
             __builtin_amdgcn_global_load_lds((global_cvoid*)(run_src[i] + lane), (lds_void*)(&lds[buf][j * 64]), 16,
                                              0, 0);
-            run_src[i] += run_adv[i];
+            run_src[i] += j < T::RA ? adv_a : adv_b;
         }
     };
     // all but the newest stage's copies of this wave have landed
@@ -329,25 +337,28 @@ __device__ __forceinline__ void tile_body(const GemmArgs& g, int64_t tm, int64_t
         }
     };
 
-    v16i acc[ND];
+    v16i acc[TM][ND];
 #pragma unroll
-    for (int d = 0; d < ND; ++d)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) acc[d][r] = 0;
+        for (int d = 0; d < ND; ++d)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][d][r] = 0;
 
-    const int64_t row0 = tm * T::BM + wm * 32;
+    // first C' row of the wave's sub-tile i
+    const int64_t row0 = tm * T::BM + wm * 32 * TM;
     const int64_t col = tn * T::BN + wn * 32 + row;
     // FP64 tile: 0, or the raw sums of the previous slice count (kRawAdd)
-    auto init64 = [&](double (&a64)[16]) {
+    auto init64 = [&](double (&a64)[16], int64_t r0) {
 #pragma unroll
         for (int r = 0; r < 16; ++r)
-            a64[r] = (g.mode == kRawAdd || g.mode == kRawAddFinal)
-                         ? g.acc[col * g.Mp + row0 + 8 * (r >> 2) + 4 * half + (r & 3)]
+            a64[r] = (!OUT && (g.mode == kRawAdd || g.mode == kRawAddFinal))
+                         ? g.acc[col * g.Mp + r0 + 8 * (r >> 2) + 4 * half + (r & 3)]
                          : 0.0;
     };
     double acc64[16];
     double lo64[XD ? 16 : 1];
-    if constexpr (MULTI) init64(acc64);
+    if constexpr (MULTI) init64(acc64, row0);
     if constexpr (XD)
 #pragma unroll
         for (int r = 0; r < 16; ++r) lo64[r] = 0.0;
@@ -372,10 +383,15 @@ __device__ __forceinline__ void tile_body(const GemmArgs& g, int64_t tm, int64_t
         for (int q = 0; q < S; ++q) bq[q] = L[T::A_CHUNKS + (half * S + q) * T::BN + wn * 32 + row];
 #pragma unroll
         for (int p = 0; p < S; ++p) {
-            const v4i a = L[(half * S + p) * T::BM + wm * 32 + row];
+            v4i a[TM];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) a[i] = L[(half * S + p) * T::BM + (wm * TM + i) * 32 + row];
 #pragma unroll
             for (int q = (DLO > p ? DLO - p : 0); q < S - p; ++q)
-                acc[p + q - DLO] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, bq[q], acc[p + q - DLO], 0, 0, 0);
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+                    acc[i][p + q - DLO] =
+                        __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], bq[q], acc[i][p + q - DLO], 0, 0, 0);
         }
         if constexpr (MULTI || DIAG) {
             if (++chunk_pos == g.chunk_steps || ks + 1 == nsteps) {
@@ -385,16 +401,16 @@ __device__ __forceinline__ void tile_body(const GemmArgs& g, int64_t tm, int64_t
 #pragma unroll
                         for (int r = 0; r < 16; ++r)
                             g.diag_out[((chunk * S + d + DLO) * g.Np + col) * g.Mp + row0 + 8 * (r >> 2) +
-                                       4 * half + (r & 3)] = acc[d][r];
+                                       4 * half + (r & 3)] = acc[0][d][r];
                 } else if constexpr (XD) {
-                    fold_diags_dd<ND, DLO, S - 1>(acc64, lo64, acc, g.bal);
+                    fold_diags_dd<ND, DLO, S - 1>(acc64, lo64, acc[0], g.bal);
                 } else {
-                    fold_diags<ND, DLO, S - 1>(acc64, acc, g.bal);
+                    fold_diags<ND, DLO, S - 1>(acc64, acc[0], g.bal);
                 }
 #pragma unroll
                 for (int d = 0; d < ND; ++d)
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) acc[d][r] = 0;
+                    for (int r = 0; r < 16; ++r) acc[0][d][r] = 0;
                 chunk_pos = 0;
                 ++chunk;
             }
@@ -417,27 +433,42 @@ __device__ __forceinline__ void tile_body(const GemmArgs& g, int64_t tm, int64_t
             if (ks + 3 < nsteps) step(ks + 3, std::integral_constant<int, 3>{});
     }
     if constexpr (DIAG) return;
-    if constexpr (!MULTI) {
-        init64(acc64);
-        if constexpr (XD)
-            fold_diags_dd<ND, DLO, S - 1>(acc64, lo64, acc, g.bal);
-        else
-            fold_diags<ND, DLO, S - 1>(acc64, acc, g.bal);
+    if constexpr (OUT) {
+        if constexpr (!MULTI) {
+            init64(acc64, row0);
+            fold_diags<ND, DLO, S - 1>(acc64, acc[0], g.bal);
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) out[r] = acc64[r];
+        return;
     }
-    if constexpr (XD)
-        store_tile_dd(g, acc64, lo64, row0, half, col);
-    else
-        store_tile(g, acc64, row0, half, col);
+    if constexpr (MULTI || XD) {
+        if constexpr (!MULTI) {
+            init64(acc64, row0);
+            fold_diags_dd<ND, DLO, S - 1>(acc64, lo64, acc[0], g.bal);
+        }
+        if constexpr (XD)
+            store_tile_dd(g, acc64, lo64, row0, half, col);
+        else
+            store_tile(g, acc64, row0, half, col);
+    } else {
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            init64(acc64, row0 + 32 * i);
+            fold_diags<ND, DLO, S - 1>(acc64, acc[i], g.bal);
+            store_tile(g, acc64, row0 + 32 * i, half, col);
+        }
+    }
 }
 
-template <int S, int WMW, int WNW, int NST, bool TOP, bool DIAG, bool MULTI>
+template <int S, int WMW, int WNW, int NST, bool TOP, bool DIAG, bool MULTI, int TM = 1>
 __global__ __attribute__((amdgpu_flat_work_group_size(64 * WMW * WNW, 64 * WMW * WNW),
                           amdgpu_waves_per_eu(2, 2))) void gemm_kernel(GemmArgs g) {
-    using T = TileCfg<S, WMW, WNW, NST>;
+    using T = TileCfg<S, WMW, WNW, NST, TM>;
     __shared__ v4i lds[NST][T::STAGE];
     int64_t tm, tn;
     tile_of_block(blockIdx.x, g.Mp / T::BM, g.Np / T::BN, tm, tn);
-    tile_body<S, WMW, WNW, NST, TOP, DIAG, MULTI>(g, tm, tn, lds);
+    tile_body<S, WMW, WNW, NST, TOP, DIAG, MULTI, false, TM>(g, tm, tn, lds);
 }
 
 // Wide form for 9 <= s <= kMaxWideSlices: the same tile body on a 64 x 64
@@ -458,17 +489,17 @@ __global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_pe
 // tile row and column (problem -1: a padding item, skipped).  Every problem of
 // one launch has the same s; MULTI is
 // set when any problem of the launch spans more than one INT32 chunk.
-template <int S, int WMW, int WNW, int NST, bool TOP, bool MULTI>
+template <int S, int WMW, int WNW, int NST, bool TOP, bool MULTI, int TM = 1>
 __global__ __attribute__((amdgpu_flat_work_group_size(64 * WMW * WNW, 64 * WMW * WNW),
                           amdgpu_waves_per_eu(2, 2))) void gemm_persistent_kernel(const GemmArgs* __restrict__ probs,
                                                                                   const TileItem* __restrict__ items,
                                                                                   int64_t nitems) {
-    using T = TileCfg<S, WMW, WNW, NST>;
+    using T = TileCfg<S, WMW, WNW, NST, TM>;
     __shared__ v4i lds[NST][T::STAGE];
     for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
         const TileItem ti = items[it];
         if (ti.prob < 0) continue;  // padding item (uniform over the block)
-        tile_body<S, WMW, WNW, NST, TOP, false, MULTI>(probs[ti.prob], ti.tm, ti.tn, lds);
+        tile_body<S, WMW, WNW, NST, TOP, false, MULTI, false, TM>(probs[ti.prob], ti.tm, ti.tn, lds);
         __syncthreads();  // the next tile refills the LDS ring
     }
 }
@@ -532,6 +563,90 @@ gemm_wide_persistent_kernel(const GemmArgs* __restrict__ probs, const TileItem* 
                 break;
         }
         __syncthreads();
+    }
+}
+
+// Fused 3-real-product tile of a complex product (s <= kMaxLiveSlices, each
+// tile its own s): the three real products T1 = Ar Br, T2 = Ai Bi and
+// T3 = (Ar + Ai)(Br + Bi) of one 64 x 64 tile run back to back through the same
+// LDS ring, T1 and T2 kept in registers as scaled FP64 values, and the
+// epilogue forms Cr = T1 - T2, Ci = (T3 - T1) - T2 and alpha, beta -- the
+// bits of three separate launches with the combine in the last one, without
+// writing T1 and T2 to memory.  g3[0..2] describe T1, T2, T3 (real products
+// over the real slice layouts; C, alpha, beta in g3[2]).
+__device__ __forceinline__ double scaled_part(const GemmArgs& g, double v, int64_t i, int64_t col) {
+    const int32_t e = g.EA[i], f = g.FB[col];
+    return (e == kNonFiniteExp || f == kNonFiniteExp) ? __longlong_as_double(0x7ff8000000000000ll)
+                                                      : ldexp(v, e + f);
+}
+
+// The chunked body folds the INT32 tiles into the FP64 tile at every chunk end
+// (for one chunk: once, after the last step), which keeps fewer registers live
+// at the end than a fold after the loop.
+template <int S>
+__device__ __forceinline__ void fused3_tile(const GemmArgs* g3, const TileItem& ti, v4i* lds) {
+    using T = TileCfg<S, 2, 2, 2>;
+    auto L = reinterpret_cast<v4i(*)[T::STAGE]>(lds);
+    double t1[16], t2[16], t3[16];
+    tile_body<S, 2, 2, 2, false, false, true, false, 1, true>(g3[0], ti.tm, ti.tn, L, t1);
+    __syncthreads();  // the next product refills the ring
+    tile_body<S, 2, 2, 2, false, false, true, false, 1, true>(g3[1], ti.tm, ti.tn, L, t2);
+    __syncthreads();
+    tile_body<S, 2, 2, 2, false, false, true, false, 1, true>(g3[2], ti.tm, ti.tn, L, t3);
+    const GemmArgs& g = g3[2];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int half = lane >> 5;
+    const int64_t row0 = ti.tm * 64 + (wave >> 1) * 32;
+    const int64_t col = ti.tn * 64 + (wave & 1) * 32 + (lane & 31);
+    if (col >= g.n) return;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int64_t i = row0 + 8 * (r >> 2) + 4 * half + (r & 3);
+        if (i >= g.m) continue;
+        const double T1 = scaled_part(g3[0], t1[r], i, col), T2 = scaled_part(g3[1], t2[r], i, col);
+        const double T3 = scaled_part(g, t3[r], i, col);
+        const double cr = T1 - T2;
+        const double ci = (T3 - T1) - T2;
+        double* c = g.C + 2 * (i + col * g.ldc);
+        double outr = g.alpha_r * cr - g.alpha_i * ci;
+        double outi = g.alpha_r * ci + g.alpha_i * cr;
+        if (!g.beta_zero) {
+            const double c0 = c[0], c1 = c[1];
+            outr = outr + (g.beta_r * c0 - g.beta_i * c1);
+            outi = outi + (g.beta_r * c1 + g.beta_i * c0);
+        }
+        c[0] = outr;
+        c[1] = outi;
+    }
+}
+
+// Persistent form over fused 3-product tiles (item.prob indexes the first of
+// the problem's three descriptors; each tile at its own s).  HI = 6: s = 1..6
+// at two waves per SIMD; HI = 8: s = 7, 8, whose INT32 tiles plus T1 and T2
+// need the registers of one wave per SIMD (one block per CU).
+template <int HI>
+__global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(HI <= 6 ? 2 : 1, HI <= 6 ? 2 : 1)))
+void gemm_persistent_3m_kernel(const GemmArgs* __restrict__ probs, const TileItem* __restrict__ items,
+                               int64_t nitems) {
+    __shared__ v4i lds[2 * TileCfg<HI, 2, 2, 2>::STAGE];
+    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const TileItem ti = items[it];
+        if (ti.prob < 0) continue;  // padding item (uniform over the block)
+        const GemmArgs* g3 = probs + ti.prob;
+        if constexpr (HI <= 6) {
+            switch (ti.s) {  // uniform over the block
+                case 1: fused3_tile<1>(g3, ti, lds); break;
+                case 2: fused3_tile<2>(g3, ti, lds); break;
+                case 3: fused3_tile<3>(g3, ti, lds); break;
+                case 4: fused3_tile<4>(g3, ti, lds); break;
+                case 5: fused3_tile<5>(g3, ti, lds); break;
+                default: fused3_tile<6>(g3, ti, lds); break;
+            }
+        } else {
+            if (ti.s == 7) fused3_tile<7>(g3, ti, lds);
+            else fused3_tile<8>(g3, ti, lds);
+        }
+        __syncthreads();  // the next tile refills the LDS ring
     }
 }
 
@@ -714,17 +829,69 @@ constexpr int ring64(int s) { return s <= 4 ? 4 : (s <= 6 ? 3 : 2); }
 template <int S>
 hipError_t launch_persistent_s(const GemmArgs* probs, const TileItem* items, int64_t nitems, int blocks, int tile,
                                bool top, bool multi, hipStream_t st) {
+    if (tile == 4) {
+        // 128 x 64 blocks of two-tile waves: s <= 6, one INT32 chunk per problem
+        if constexpr (S <= 6) {
+            if (multi) return hipErrorInvalidValue;
+            dim3 grid(static_cast<unsigned>(blocks)), block(256);
+            if (top)
+                hipLaunchKernelGGL((gemm_persistent_kernel<S, 2, 2, 2, true, false, 2>), grid, block, 0, st, probs,
+                                   items, nitems);
+            else
+                hipLaunchKernelGGL((gemm_persistent_kernel<S, 2, 2, 2, false, false, 2>), grid, block, 0, st, probs,
+                                   items, nitems);
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
     if (tile == 1) return launch_persistent_cfg<S, 4, 2, 3>(probs, items, nitems, blocks, top, multi, st);
     return launch_persistent_cfg<S, 2, 2, 2>(probs, items, nitems, blocks, top, multi, st);
 }
 
-// Block shape: 64 x 64 (4 waves, 2-stage ring) by default: two blocks share
-// a CU, each with its own barrier, so the two waves on a SIMD drift apart and
-// one keeps the matrix pipe busy while the other waits on LDS or the barrier
-// (measured faster than one 128 x 64 block per CU from n = 1024 to 4096).
-// Tile 1 asks for the 128 x 64 block (8 waves, 3-stage ring).
+// Blocks of two 32-row tiles per wave (single INT32 chunk, FP64 result):
+// 128 x 64 with 4 waves, the ring as deep as two blocks per CU allow (6 s KiB
+// per stage), or 128 x 128 with 8 waves (one block per CU, 8 s KiB per stage).
+constexpr int ring128x64(int s) { return s <= 4 ? 3 : 2; }
+constexpr int ring128x128(int s) { return s <= 6 ? 3 : 2; }
+
+template <int S, int WMW, int WNW, int NST>
+hipError_t launch_cfg_tm2(const GemmArgs& g, hipStream_t st) {
+    using T = TileCfg<S, WMW, WNW, NST, 2>;
+    const int64_t blocks = (g.Np / T::BN) * (g.Mp / T::BM);
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    dim3 grid(static_cast<unsigned>(blocks)), block(64 * T::NW);
+    if (g.top)
+        hipLaunchKernelGGL((gemm_kernel<S, WMW, WNW, NST, true, false, false, 2>), grid, block, 0, st, g);
+    else
+        hipLaunchKernelGGL((gemm_kernel<S, WMW, WNW, NST, false, false, false, 2>), grid, block, 0, st, g);
+    return hipGetLastError();
+}
+
+// Tiles of the 128 x 64 two-tile block from which it is the default: two
+// blocks on every compute unit of the chip (smaller products keep the 64 x 64
+// block, which has twice the tiles).
+constexpr int64_t kTm2MinTiles = 512;
+
+// Block shape by default: for s <= 6 with one INT32 chunk and at least
+// kTm2MinTiles tiles, the 128 x 64 block of two-tile waves (tile 4; measured
+// 8% faster than 64 x 64 on the ZGEMM n = 4096, s = 6 products); otherwise
+// 64 x 64 with 4 waves of one tile each.  In both, two blocks share a CU, each
+// with its own barrier, so the two waves on a SIMD drift apart and one keeps
+// the matrix pipe busy while the other waits on LDS or the barrier (measured
+// faster than one 128 x 64 block of 8 one-tile waves per CU -- tile 1, 3-stage
+// ring -- from n = 1024 to 4096, and than the 128 x 128 block of 8 two-tile
+// waves, tile 5).
 template <int S>
 hipError_t launch_s(const GemmArgs& g, hipStream_t st) {
+    // two 32-row tiles per wave fit the 256 registers of two waves per SIMD
+    // up to s = 6 (2 s INT32 tiles of 16 registers plus s B fragments)
+    if constexpr (S <= 6) {
+        const bool single = g.chunk_steps >= g.kpad / kStep && !g.diag_out;
+        const bool big = (g.Mp / 128) * (g.Np / 64) >= kTm2MinTiles;
+        if ((g.tile == 4 || (g.tile == 0 && big)) && single) return launch_cfg_tm2<S, 2, 2, ring128x64(S)>(g, st);
+        if (g.tile == 5 && single) return launch_cfg_tm2<S, 2, 4, ring128x128(S)>(g, st);
+    }
     if (g.tile == 1) return launch_cfg<S, 4, 2, 3>(g, st);
     return launch_cfg<S, 2, 2, ring64(S)>(g, st);
 }
@@ -838,7 +1005,7 @@ hipError_t launch_gemm(const GemmArgs& g, hipStream_t st) {
 hipError_t launch_gemm_persistent(const GemmArgs* probs, const TileItem* items, int64_t nitems, int s, int tile,
                                   int blocks, bool top, bool multi, hipStream_t st) {
     if (nitems <= 0) return hipSuccess;
-    if (blocks <= 0 || (tile != 1 && tile != 2)) return hipErrorInvalidValue;
+    if (blocks <= 0 || (tile != 1 && tile != 2 && tile != 4)) return hipErrorInvalidValue;
     switch (s) {
         case 1: return launch_persistent_s<1>(probs, items, nitems, blocks, tile, top, multi, st);
         case 2: return launch_persistent_s<2>(probs, items, nitems, blocks, tile, top, multi, st);
@@ -864,6 +1031,18 @@ hipError_t launch_gemm_persistent_mixed(const GemmArgs* probs, const TileItem* i
     else if (multi) OZ_MIXED(false, true);
     else OZ_MIXED(false, false);
 #undef OZ_MIXED
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_persistent_3m(const GemmArgs* probs, const TileItem* items, int64_t nitems, int blocks,
+                                     bool high, hipStream_t st) {
+    if (nitems <= 0) return hipSuccess;
+    if (blocks <= 0) return hipErrorInvalidValue;
+    dim3 grid(static_cast<unsigned>(blocks)), block(256);
+    if (high)
+        hipLaunchKernelGGL((gemm_persistent_3m_kernel<8>), grid, block, 0, st, probs, items, nitems);
+    else
+        hipLaunchKernelGGL((gemm_persistent_3m_kernel<6>), grid, block, 0, st, probs, items, nitems);
     return hipGetLastError();
 }
 

@@ -79,6 +79,17 @@ struct Split3Out {
 };
 hipError_t launch_scan3(const OperandView& op, const Split3Out& o, hipStream_t st);
 hipError_t launch_digits3(const OperandView& op, const SliceLayout& lay, const Split3Out& o, hipStream_t st);
+// Batched three-part split: one block per item (operand op of the list, block
+// coordinates as in the one-operand launches; digits3_blocks gives the grid).
+struct Split3Op {
+    OperandView op;  // the complex operand
+    SliceLayout lay;  // the real layout of each part
+    Split3Out o;
+};
+struct BlockItem;
+void digits3_blocks(const SliceLayout& lay, int64_t* bx, int64_t* by);
+hipError_t launch_scan3_batched(const Split3Op* ops, const BlockItem* items, int64_t nitems, hipStream_t st);
+hipError_t launch_digits3_batched(const Split3Op* ops, const BlockItem* items, int64_t nitems, hipStream_t st);
 
 // Batched split: one block per item; an item names its operand and the block
 // coordinates the one-operand launch would have used.
@@ -166,6 +177,11 @@ hipError_t launch_gemm_stream_persistent(const GemmArgs* probs, const TileItem* 
 // from its GemmArgs) in one persistent launch of 64 x 64 blocks.
 hipError_t launch_gemm_persistent_mixed(const GemmArgs* probs, const TileItem* items, int64_t nitems, int blocks,
                                         bool top, bool multi, hipStream_t st);
+// Fused 3-real-product tiles of complex products (item.prob: the first of
+// three consecutive descriptors T1, T2, T3 of real products): high = false
+// for tiles with s <= 6 (two blocks per CU), true for s = 7, 8 (one).
+hipError_t launch_gemm_persistent_3m(const GemmArgs* probs, const TileItem* items, int64_t nitems, int blocks,
+                                     bool high, hipStream_t st);
 // Tiles of problems with 9 <= s <= kMaxWideSlices (each its own s, from the
 // tile item) on the wide all-diagonal tile (64 x 64, one block per compute
 // unit); with multi (several INT32 chunks) every s must be at most 12.

@@ -458,7 +458,8 @@ __global__ __launch_bounds__(256) void scan3_kernel(OperandView op, Split3Out o,
 // then takes its 8 elements from there (a direct read would have every lane
 // of a load touch its own 128-byte line).
 template <bool LCONTIG, bool BAL>
-__global__ __launch_bounds__(256) void digits3_kernel(OperandView op, SliceLayout lay, Split3Out o) {
+__device__ __forceinline__ void digits3_body(const OperandView& op, const SliceLayout& lay, const Split3Out& o,
+                                             int64_t bx, int64_t by) {
     constexpr int kStagePad = 33;  // 16-byte entries per staged vector: 32 elements + 1 to spread LDS banks
     __shared__ double2 stage[LCONTIG ? 64 * kStagePad : 1];
     if constexpr (LCONTIG) {
@@ -466,8 +467,8 @@ __global__ __launch_bounds__(256) void digits3_kernel(OperandView op, SliceLayou
         for (int it = 0; it < 8; ++it) {
             const int idx = it * 256 + static_cast<int>(threadIdx.x);
             const int sv = idx >> 5, se = idx & 31;
-            const int64_t vv = static_cast<int64_t>(blockIdx.y) * 64 + sv;
-            const int64_t l = static_cast<int64_t>(blockIdx.x) * kStep + se;
+            const int64_t vv = by * 64 + sv;
+            const int64_t l = bx * kStep + se;
             double2 val = make_double2(0.0, 0.0);
             if (vv < op.nv && l < op.k) {
                 const double* src = op.X + (vv * op.sv + l) * 2;
@@ -480,8 +481,8 @@ __global__ __launch_bounds__(256) void digits3_kernel(OperandView op, SliceLayou
     const int tid = threadIdx.x;
     const int vi = LCONTIG ? (tid >> 2) : (tid & 63);
     const int sub = LCONTIG ? (tid & 3) : (tid >> 6);
-    const int64_t v = static_cast<int64_t>(blockIdx.y) * 64 + vi;
-    const int64_t step = blockIdx.x;
+    const int64_t v = by * 64 + vi;
+    const int64_t step = bx;
     const int64_t t0 = step * kStep + sub * 8;
     const bool live = v < op.nv;
     if (v >= lay.rows_pad) return;
@@ -544,6 +545,34 @@ __global__ __launch_bounds__(256) void digits3_kernel(OperandView op, SliceLayou
     }
 }
 
+template <bool LCONTIG, bool BAL>
+__global__ __launch_bounds__(256) void digits3_kernel(OperandView op, SliceLayout lay, Split3Out o) {
+    digits3_body<LCONTIG, BAL>(op, lay, o, blockIdx.x, blockIdx.y);
+}
+
+// Batched three-part split: block b runs item b (operand, block coordinates).
+__global__ __launch_bounds__(256) void scan3_batched_kernel(const Split3Op* __restrict__ ops,
+                                                            const BlockItem* __restrict__ items, int64_t lspan) {
+    const BlockItem it = items[blockIdx.x];
+    const Split3Op& o = ops[it.op];
+    if (o.op.sl == 1) scan3_body<true>(o.op, o.o, lspan, it.bx, it.by);
+    else scan3_body<false>(o.op, o.o, lspan, it.bx, it.by);
+}
+
+__global__ __launch_bounds__(256) void digits3_batched_kernel(const Split3Op* __restrict__ ops,
+                                                              const BlockItem* __restrict__ items) {
+    const BlockItem it = items[blockIdx.x];
+    const Split3Op& o = ops[it.op];
+    const bool lc = o.op.sl == 1;  // uniform over the block
+    if (o.lay.bal) {
+        if (lc) digits3_body<true, true>(o.op, o.lay, o.o, it.bx, it.by);
+        else digits3_body<false, true>(o.op, o.lay, o.o, it.bx, it.by);
+    } else {
+        if (lc) digits3_body<true, false>(o.op, o.lay, o.o, it.bx, it.by);
+        else digits3_body<false, false>(o.op, o.lay, o.o, it.bx, it.by);
+    }
+}
+
 }  // namespace
 
 // Terms per exponent-scan block: 128 gives n = 4096 operands 2048 blocks of 64
@@ -586,6 +615,24 @@ SliceLayout slice_layout(int side_a, int cplx, int64_t nv, int64_t k, int s) {
 void scan_blocks(const OperandView& op, int64_t* bx, int64_t* by) {
     *bx = op.k > 0 ? (op.k + scan_lspan() - 1) / scan_lspan() : 0;
     *by = op.nv > 0 ? (op.nv + 63) / 64 : 0;
+}
+
+void digits3_blocks(const SliceLayout& lay, int64_t* bx, int64_t* by) {
+    *bx = lay.kpad / kStep;
+    *by = (lay.rows_pad + 63) / 64;
+}
+
+hipError_t launch_scan3_batched(const Split3Op* ops, const BlockItem* items, int64_t nitems, hipStream_t st) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(scan3_batched_kernel, dim3(static_cast<unsigned>(nitems)), dim3(256), 0, st, ops, items,
+                       scan_lspan());
+    return hipGetLastError();
+}
+
+hipError_t launch_digits3_batched(const Split3Op* ops, const BlockItem* items, int64_t nitems, hipStream_t st) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(digits3_batched_kernel, dim3(static_cast<unsigned>(nitems)), dim3(256), 0, st, ops, items);
+    return hipGetLastError();
 }
 
 void digits_blocks(const OperandView& op, const SliceLayout& lay, int64_t* bx, int64_t* by) {

@@ -171,8 +171,8 @@ def test_balanced_full_size_zgemm(oz, handle):
     dC, _ = to_dev(np.zeros((n, n), complex, order="F"))
     dT, _ = to_dev(np.zeros((n, n), complex, order="F"))
     print("zgemm n=%d s=%d balanced" % (n, s), flush=True)
-    oz.oz_zgemm(handle, "N", "N", n, n, n, 1.0, dA, n, dB, n, 0.0, dC, n, oz.prec(s, digits=1))
-    oz.oz_zgemm(handle, "N", "N", n, n, n, 1.0, dA, n, dB, n, 0.0, dT, n, oz.prec(s))
+    oz.oz_zgemm(handle, "N", "N", n, n, n, 1.0, dA, n, dB, n, 0.0, dC, n, oz.prec(s, digits=1, zmode=4))
+    oz.oz_zgemm(handle, "N", "N", n, n, n, 1.0, dA, n, dB, n, 0.0, dT, n, oz.prec(s, zmode=4))
     torch.cuda.synchronize()
     rng = np.random.default_rng(0)
     rows = np.sort(rng.choice(n, 24, replace=False))

@@ -43,7 +43,8 @@ def make_problem(rng, cplx, m, n, k, ta, tb):
     return A, B, C0
 
 
-def batch_call(oz, handle, stream, cplx, probs, slices, use_plan=False, replays=0, digits=0, kchunk=0):
+def batch_call(oz, handle, stream, cplx, probs, slices, use_plan=False, replays=0, digits=0, kchunk=0, kernel=0,
+               zmode=0):
     dev = []
     for (ta, tb, A, B, C0, al, be) in probs:
         dA, lda = to_dev(A, A.shape[0] + 1)
@@ -60,11 +61,12 @@ def batch_call(oz, handle, stream, cplx, probs, slices, use_plan=False, replays=
                 C=[d[4] for d in dev], ldc=[d[5] for d in dev])
     if not use_plan:
         fn = oz.oz_zgemm_batched if cplx else oz.oz_dgemm_batched
-        fn(handle, p=oz.prec(slices if isinstance(slices, int) else 7, digits=digits, kchunk=kchunk),
+        fn(handle, p=oz.prec(slices if isinstance(slices, int) else 7, digits=digits, kchunk=kchunk, kernel=kernel,
+                             zmode=zmode),
            slices=None if isinstance(slices, int) else slices, **args)
     else:
         plan = oz.oz_gemm_batched_plan(handle, cplx, p=oz.prec(slices if isinstance(slices, int) else 7,
-                                                               digits=digits),
+                                                               digits=digits, kernel=kernel, zmode=zmode),
                                        slices=None if isinstance(slices, int) else slices, **args)
         oz.oz_batch_graph_launch(plan)
         return plan, dev, args
@@ -98,6 +100,101 @@ def test_batched_bit_exact_mixed(oz, handle, stream, cplx):
                 assert np.array_equal(got[i], want), i
             continue
         assert np.array_equal(got[i], want), (i, ta, tb, A.shape, B.shape)
+
+
+@pytest.mark.parametrize("cplx", [0, 1])
+@pytest.mark.parametrize("s,digits,use_plan", [(6, 0, False), (5, 1, True), (2, 0, False), (7, 0, False)])
+def test_batched_two_tile_block(oz, handle, stream, cplx, s, digits, use_plan):
+    # the 128 x 64 block of two-tile waves (s <= 6; s = 7 falls back to the
+    # 64 x 64 block): ragged shapes across several tiles, every transpose,
+    # beta on half of them
+    rng = np.random.default_rng(80 + cplx + s)
+    shapes = [(130, 70, 257), (257, 129, 40), (64, 192, 64), (5, 300, 17), (300, 5, 90), (129, 65, 33), (1, 1, 1),
+              (200, 131, 100)]
+    probs = []
+    for i, (m, n, k) in enumerate(shapes):
+        ta = "NTC"[i % 3] if cplx else "NT"[i % 2]
+        tb = "NCT"[(i // 3) % 3] if cplx else "TN"[i % 2]
+        A, B, C0 = make_problem(rng, cplx, m, n, k, ta, tb)
+        al = complex(0.75, -0.5) if cplx else -1.25
+        be = (complex(0.5, 0.25) if i % 2 else 0.0) if cplx else (0.5 if i % 2 else 0.0)
+        probs.append((ta, tb, A, B, C0, al, be))
+    print("two-tile batch cplx=%d s=%d digits=%d plan=%d" % (cplx, s, digits, use_plan), flush=True)
+    if use_plan:
+        plan, dev, args = batch_call(oz, handle, stream, cplx, probs, s, use_plan=True, digits=digits, kernel=4)
+        try:
+            stream.synchronize()
+            got = [from_dev(d[4], args["m"][i], args["n"][i], d[5]) for i, d in enumerate(dev)]
+        finally:
+            oz.oz_batch_destroy(plan)
+    else:
+        got = batch_call(oz, handle, stream, cplx, probs, s, digits=digits, kernel=4)
+    for i, (ta, tb, A, B, C0, al, be) in enumerate(probs):
+        want = oracle.emu_gemm(ta, tb, A, B, s, alpha=al, beta=be, C=C0, balanced=bool(digits))
+        assert np.array_equal(got[i], want), (i, ta, tb, A.shape, B.shape)
+
+
+@pytest.mark.parametrize("digits,use_plan,kchunk", [(0, False, 0), (1, True, 0), (0, False, 64), (1, False, 128)])
+def test_batched_3m_bit_exact(oz, handle, stream, digits, use_plan, kchunk):
+    # the fused 3-real-product tiles: slice counts 1..8 in one batch (s <= 6
+    # and s = 7, 8 in two launches), ragged shapes over several tiles, every
+    # transpose pair, complex alpha, beta on half of them, forced INT32 chunks
+    rng = np.random.default_rng(90 + digits + kchunk)
+    shapes = [(70, 65, 33), (130, 70, 257), (64, 192, 64), (5, 300, 17), (200, 3, 90), (96, 96, 96), (33, 47, 2),
+              (129, 64, 65), (1, 1, 1), (150, 131, 200)]
+    probs, slices = [], []
+    for i, (m, n, k) in enumerate(shapes):
+        ta, tb = "NTC"[i % 3], "NCT"[(i // 3) % 3]
+        A, B, C0 = make_problem(rng, 1, m, n, k, ta, tb)
+        al = complex(1.0 - 0.05 * i, 0.1 * (i % 3))
+        be = complex(0.5, -0.25) if i % 2 else 0.0
+        probs.append((ta, tb, A, B, C0, al, be))
+        slices.append(1 + i % 8)
+    print("3m batch digits=%d plan=%d kchunk=%d" % (digits, use_plan, kchunk), flush=True)
+    if use_plan:
+        plan, dev, args = batch_call(oz, handle, stream, 1, probs, slices, use_plan=True, digits=digits, zmode=3)
+        try:
+            launches, _, _, sl = oz.oz_batch_info(plan, len(probs))
+            assert sl == slices and launches == 2
+            stream.synchronize()
+            got = [from_dev(d[4], args["m"][i], args["n"][i], d[5]) for i, d in enumerate(dev)]
+            reps = oz.oz_batch_report(plan, len(probs))
+            assert all(r.zmode_used == 3 for r in reps)
+        finally:
+            oz.oz_batch_destroy(plan)
+    else:
+        got = batch_call(oz, handle, stream, 1, probs, slices, digits=digits, kchunk=kchunk, zmode=3)
+    for i, (ta, tb, A, B, C0, al, be) in enumerate(probs):
+        want = oracle.emu_zgemm3(ta, tb, A, B, slices[i], alpha=al, beta=be, C=C0, kc=kchunk or None,
+                                 balanced=bool(digits))
+        assert np.array_equal(got[i], want), (i, ta, tb, A.shape, B.shape, slices[i])
+
+
+def test_batched_3m_nonfinite_rows(oz, handle, stream):
+    # an Inf in a row of A and a NaN in a column of B: that row and column of
+    # C are NaN in both parts, every other entry as if they held zeros
+    rng = np.random.default_rng(7)
+    probs, bads = [], []
+    for i in range(3):
+        A, B, C0 = make_problem(rng, 1, 40, 30, 20, "N", "N")
+        A, B = A.copy(order="F"), B.copy(order="F")
+        r, c = 3 + i, 9 + 2 * i
+        A[r, 5] = np.inf + 0j
+        B[4, c] = complex(0.0, np.nan)
+        probs.append(("N", "N", A, B, C0, 1.0, 0.0))
+        bads.append((r, c))
+    got = batch_call(oz, handle, stream, 1, probs, 6, zmode=3)
+    for i, (ta, tb, A, B, C0, al, be) in enumerate(probs):
+        r, c = bads[i]
+        bad = np.zeros(got[i].shape, bool)
+        bad[r, :] = True
+        bad[:, c] = True
+        assert np.all(np.isnan(got[i].real[bad])) and np.all(np.isnan(got[i].imag[bad]))
+        A2, B2 = A.copy(), B.copy()
+        A2[r, :] = 0
+        B2[:, c] = 0
+        want = oracle.emu_zgemm3(ta, tb, A2, B2, 6)
+        assert np.array_equal(got[i][~bad], want[~bad])
 
 
 @pytest.mark.parametrize("cplx", [0, 1])
@@ -299,8 +396,10 @@ def test_batched_argument_errors(oz, handle):
     # fixed slice counts up to 14 (the wide tile from 9 on); 15 and above only tolerance-driven
     assert oz.oz_zgemm_batched(handle, check=False, p=oz.prec(15), **base) == 14
     assert oz.oz_zgemm_batched(handle, check=False, p=oz.prec(14), **base) == 0
-    # the 3-real-product form is for single calls with a fixed slice count
-    assert oz.oz_zgemm_batched(handle, check=False, p=oz.prec(6, zmode=3), **base) == 14
+    # the 3-real-product form: fixed slice counts up to 8
+    assert oz.oz_zgemm_batched(handle, check=False, p=oz.prec(9, zmode=3), **base) == 14
+    assert oz.oz_zgemm_batched(handle, check=False, p=oz.prec(0, tol=1e-10, zmode=3), **base) == 14
+    assert oz.oz_zgemm_batched(handle, check=False, p=oz.prec(8, zmode=3), **base) == 0
     st = oz.oz_zgemm(handle, "N", "N", 4, 4, 4, 1.0, d, 4, d, 4, 0.0, d, 4, oz.prec(0, tol=1e-10, zmode=3),
                      check=False)
     assert st == 14

@@ -14,7 +14,9 @@ against the oracle (the CPU computes only the sampled rows and columns):
   residual estimate is within half of each tolerance, the sampled error
   within it, and the result is bit-exact against the oracle's incremental emulation
   from the reported start to the reported final s; and the same DGEMM at
-  s = 8 with a forced INT32 split of k into chunks of 2048 terms."""
+  s = 8 with a forced INT32 split of k into chunks of 2048 terms;
+* the complex form zmode 0 picks by size (3 products at 2048^3, 4 below),
+  sampled bit-exact against the oracle of that form."""
 import numpy as np
 import pytest
 import torch
@@ -161,3 +163,27 @@ def test_wide_range_dgemm_forced_split_k(oz, handle):
     err = oracle.weighted_error(got, dd, np.abs(A).max(1)[rows], np.abs(B).max(0)[cols])
     print("wide split-K weighted error %.3g" % err)
     assert err < 1e-14
+
+
+@pytest.mark.parametrize("k,form", [(2048, 3), (1024, 4)])
+def test_default_form_follows_size(oz, handle, k, form):
+    # zmode 0: the 3-real-product form once m, n and k are all >= 2048, the
+    # 4-product form below; the workspace query agrees with the call
+    n = 2048
+    rng = np.random.default_rng(k)
+    A = np.asfortranarray(rng.standard_normal((n, k)) + 1j * rng.standard_normal((n, k)))
+    B = np.asfortranarray(rng.standard_normal((k, n)) + 1j * rng.standard_normal((k, n)))
+    dA = torch.from_numpy(A.ravel(order="F")).cuda()
+    dB = torch.from_numpy(B.ravel(order="F")).cuda()
+    dC = torch.zeros(n * n, dtype=torch.complex128, device="cuda")
+    print("default form k=%d" % k, flush=True)
+    p = oz.prec(6, digits=1)
+    st, rep = oz.oz_zgemm(handle, "N", "N", n, n, k, 1.0, dA, n, dB, k, 0.0, dC, n, p, report=True)
+    assert st == 0 and rep.zmode_used == form
+    assert oz.oz_workspace_size(handle, "N", "N", n, n, k, 1, p) == \
+        oz.oz_workspace_size(handle, "N", "N", n, n, k, 1, oz.prec(6, digits=1, zmode=form))
+    rows, cols = _samples(n, 10, k + 1)
+    got = from_dev(dC, n, n, n)[np.ix_(rows, cols)]
+    want = (oracle.emu_zgemm3("N", "N", A, B, 6, rows=rows, cols=cols, balanced=True) if form == 3
+            else oracle.emu_gemm("N", "N", A, B, 6, rows=rows, cols=cols, balanced=True))
+    assert np.array_equal(got, want)

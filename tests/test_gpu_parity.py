@@ -139,7 +139,7 @@ def test_diagonal_sums_bit_exact(oz, handle, cplx, m, n, k, s, kc, kernel):
 # ----------------------------------------------------------------- FP64 result (a4, a5)
 
 
-def run_gemm(oz, handle, cplx, ta, tb, A, B, s, alpha=1.0, beta=0.0, C0=None, kc=0, pad=0, kernel=0):
+def run_gemm(oz, handle, cplx, ta, tb, A, B, s, alpha=1.0, beta=0.0, C0=None, kc=0, pad=0, kernel=0, zmode=0):
     m = A.shape[0] if ta == "N" else A.shape[1]
     k = A.shape[1] if ta == "N" else A.shape[0]
     n = B.shape[1] if tb == "N" else B.shape[0]
@@ -149,7 +149,8 @@ def run_gemm(oz, handle, cplx, ta, tb, A, B, s, alpha=1.0, beta=0.0, C0=None, kc
     C0 = np.zeros((m, n), dt, order="F") if C0 is None else C0
     dC, ldc = to_dev(C0, m + pad)
     fn = oz.oz_zgemm if cplx else oz.oz_dgemm
-    fn(handle, ta, tb, m, n, k, alpha, dA, lda, dB, ldb, beta, dC, ldc, oz.prec(s, kchunk=kc, kernel=kernel))
+    fn(handle, ta, tb, m, n, k, alpha, dA, lda, dB, ldb, beta, dC, ldc,
+       oz.prec(s, kchunk=kc, kernel=kernel, zmode=zmode))
     torch.cuda.synchronize()
     return from_dev(dC, m, n, ldc)
 
@@ -157,7 +158,7 @@ def run_gemm(oz, handle, cplx, ta, tb, A, B, s, alpha=1.0, beta=0.0, C0=None, kc
 GEMM_SHAPES = [(1, 1, 1), (63, 65, 33), (130, 70, 257), (64, 192, 64)]
 
 
-@pytest.mark.parametrize("kernel", [0, 1, 2, 3])
+@pytest.mark.parametrize("kernel", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("ta,tb", [("N", "N"), ("T", "N"), ("N", "T"), ("T", "T")])
 @pytest.mark.parametrize("m,n,k", GEMM_SHAPES)
 @pytest.mark.parametrize("s", [1, 3, 7, 8])
@@ -170,7 +171,7 @@ def test_dgemm_bit_exact(oz, handle, ta, tb, m, n, k, s, kernel):
     assert np.array_equal(got, oracle.emu_gemm(ta, tb, A, B, s))
 
 
-@pytest.mark.parametrize("kernel", [0, 1, 2, 3])
+@pytest.mark.parametrize("kernel", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("ta,tb", [("N", "N"), ("C", "N"), ("T", "C"), ("C", "T")])
 @pytest.mark.parametrize("m,n,k", GEMM_SHAPES)
 @pytest.mark.parametrize("s", [2, 6, 7, 8])
@@ -318,7 +319,7 @@ def test_zgemm_full_size_sampled(oz, handle, n):
     against the oracle, bit for bit."""
     A, B = workloads.zgemm_rowexp(n, seed=0)
     print("zgemm full", n, flush=True)
-    got = run_gemm(oz, handle, 1, "N", "N", A, B, 7)
+    got = run_gemm(oz, handle, 1, "N", "N", A, B, 7, zmode=4)
     rows = sampled_rows(n, n)
     want = oracle.emu_gemm("N", "N", A, B, 7, rows=rows)
     assert np.array_equal(got[rows], want)
@@ -400,7 +401,7 @@ def scale_weights(A, B):
     return np.abs(A).max(1), np.abs(B).max(0)
 
 
-def run_tol(oz, handle, A, B, tol, smax=12, sstart=0, alpha=1.0, beta=0.0, C0=None):
+def run_tol(oz, handle, A, B, tol, smax=12, sstart=0, alpha=1.0, beta=0.0, C0=None, kernel=0):
     cplx = np.iscomplexobj(A)
     m, k = A.shape
     n = B.shape[1]
@@ -410,7 +411,7 @@ def run_tol(oz, handle, A, B, tol, smax=12, sstart=0, alpha=1.0, beta=0.0, C0=No
     dC, ldc = to_dev(C0)
     fn = oz.oz_zgemm if cplx else oz.oz_dgemm
     st, rep = fn(handle, "N", "N", m, n, k, alpha, dA, lda, dB, ldb, beta, dC, ldc,
-                 oz.prec(0, tol=tol, smax=smax, sstart=sstart), report=True)
+                 oz.prec(0, tol=tol, smax=smax, sstart=sstart, kernel=kernel), report=True)
     assert st == 0 and rep.status == 0
     return from_dev(dC, m, n, ldc), rep
 
@@ -441,6 +442,22 @@ def test_growth_from_a_low_start_is_incremental(oz, handle, cplx):
     assert rep.fallbacks >= 3 and rep.slices_used == 2 + rep.fallbacks
     want = oracle.emu_gemm("N", "N", A, B, 2, s_to=rep.slices_used, kc=oracle.kchunk(12, bool(cplx)),
                            alpha=0.5 - 0.25j if cplx else 0.5)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("kernel", [4, 5])
+@pytest.mark.parametrize("cplx,beta", [(0, 0.0), (0, -0.75), (1, 0.0), (1, 0.5 + 0.25j)])
+def test_growth_on_two_tile_waves(oz, handle, kernel, cplx, beta):
+    # raw writes, top-diagonal growth steps and the final scaling on the blocks
+    # whose waves own two 32-row tiles (s <= 6), the 64 x 64 block above
+    A, B = tol_inputs("rowexp" if cplx else "uniform", cplx, seed=5)
+    rng = np.random.default_rng(9)
+    C0 = wide(rng, (A.shape[0], B.shape[1]), 4, bool(cplx))
+    print("growth two-tile", kernel, cplx, beta, flush=True)
+    got, rep = run_tol(oz, handle, A, B, 1e-13, sstart=2, alpha=1.5, beta=beta, C0=C0, kernel=kernel)
+    assert rep.fallbacks >= 3
+    want = oracle.emu_gemm("N", "N", A, B, 2, s_to=rep.slices_used, kc=oracle.kchunk(12, bool(cplx)), alpha=1.5,
+                           beta=beta, C=C0)
     assert np.array_equal(got, want)
 
 
@@ -504,7 +521,8 @@ def run_z3(oz, handle, ta, tb, A, B, s, alpha=1.0, beta=0.0, C0=None, kernel=0, 
 
 Z3_CASES = [("N", "N", 70, 65, 33, 7, 0), ("T", "C", 130, 70, 257, 5, 1), ("C", "T", 64, 192, 64, 3, 2),
             ("N", "C", 5, 300, 17, 8, 0), ("T", "N", 200, 3, 90, 10, 3), ("C", "N", 33, 47, 2, 1, 0),
-            ("N", "T", 150, 130, 300, 7, 2), ("C", "C", 65, 64, 31, 4, 1)]
+            ("N", "T", 150, 130, 300, 7, 2), ("C", "C", 65, 64, 31, 4, 1), ("N", "N", 260, 190, 140, 6, 4),
+            ("T", "C", 129, 257, 65, 5, 5), ("C", "N", 300, 70, 33, 8, 4)]
 
 
 @pytest.mark.parametrize("ta,tb,m,n,k,s,kernel", Z3_CASES)
