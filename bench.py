@@ -857,8 +857,9 @@ def main():
     ap.add_argument("--slices", type=int, default=6)
     ap.add_argument("--digits", type=int, default=1, choices=[0, 1],
                     help="1 = balanced (round-to-nearest) digits (default), 0 = truncated digits")
-    ap.add_argument("--zmode", type=int, default=3, choices=[3, 4],
-                    help="complex form: 3 = three real products (default), 4 = one real product over the two-row form")
+    ap.add_argument("--zmode", type=int, default=None, choices=[0, 3, 4],
+                    help="complex form: 3 = three real products, 4 = one real product over the two-row form, "
+                         "0 = the library's choice (default: 3 for single ZGEMM workloads, 0 for batches)")
     ap.add_argument("--kernel", type=int, default=0, choices=[0, 1, 2, 4, 5],
                     help="GEMM kernel shape (as oz_prec_t.kernel; 0 = the default shape)")
     ap.add_argument("--cpu-rows", type=int, default=512)
@@ -867,6 +868,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-native", action="store_true")
     args = ap.parse_args()
+    if args.zmode is None:
+        # batches: the library's choice (the 4-product form, measured faster
+        # there); single ZGEMM workloads: the 3-product form
+        args.zmode = 0 if args.workload in ("batch512", "select") else 3
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)

@@ -2,9 +2,10 @@
 
 For every size bucket n and slice count s it builds a batch of square
 complex problems of that size, and times its graph replay under each
-candidate GEMM configuration: block shape (1 = 128 x 64 with a 3-stage LDS
-ring, 2 = 64 x 64 with 2 stages) and tile order (0 = by work, problem by
-problem; 1 = whole problems dealt to per-XCD queues).  A candidate is forced
+candidate GEMM configuration: block shape (1 = 128 x 64 of 8 one-tile waves
+with a 3-stage LDS ring, 2 = 64 x 64 with 2 stages, 4 = 128 x 64 of 4 waves
+owning two 32-row tiles each -- s <= 6 only) and tile order (0 = by work,
+problem by problem; 1 = whole problems dealt to per-XCD queues).  A candidate is forced
 by loading a one-entry table before planning.  The fastest candidate of each
 bucket goes into the table (JSON), together with every measured time.
 
@@ -92,7 +93,7 @@ def main():
         torch.cuda.synchronize()
         for s in [int(x) for x in args.slices.split(",")]:
             timings = {}
-            for tile in (1, 2):
+            for tile in ((1, 2, 4) if s <= 6 else (1, 2)):
                 for order in (0, 1):
                     timings["tile%d_order%d" % (tile, order)] = time_config(oz, torch, handle, stream, dev, n, s,
                                                                             tile, order, args.reps)

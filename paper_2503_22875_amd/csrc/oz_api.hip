@@ -1073,7 +1073,8 @@ int oz_load_tuning(oz_handle_t h, const char* path) {
         if (!field(obj, "complex", &c) || !field(obj, "n", &n) || !field(obj, "s", &s) || !field(obj, "tile", &t) ||
             !field(obj, "order", &o))
             return OZ_ERR_ARG;
-        if ((t != 1 && t != 2) || (o != 0 && o != 1) || s < 1 || s > oz::kMaxLiveSlices || n < 1) return OZ_ERR_ARG;
+        if ((t != 1 && t != 2 && t != 4) || (o != 0 && o != 1) || s < 1 || s > oz::kMaxLiveSlices || n < 1)
+            return OZ_ERR_ARG;
         out.push_back({static_cast<int>(c), static_cast<int64_t>(n), static_cast<int>(s), static_cast<int>(t),
                        static_cast<int>(o)});
         pos = close + 1;

@@ -63,6 +63,9 @@ struct oz_batch_s {
     int64_t n_maxbits;
     size_t off_ops, off_scan, off_digits, off_args;
     int64_t n_scan, n_digits;
+    // one-pass split of the operands with short vectors (fixed-s plans)
+    size_t off_fused;
+    int64_t n_fused;
     // 3-real-product plans: the three-part split lists
     bool z3;
     size_t off_ops3, off_scan3, off_digits3;
@@ -168,7 +171,7 @@ void build_group(const std::vector<oz::GemmArgs>& args, std::vector<size_t> memb
     };
     int64_t big = 0;
     bool multi = false;
-    double vote_tile[3] = {0, 0, 0}, vote_order[2] = {0, 0};
+    double vote_tile[5] = {0, 0, 0, 0, 0}, vote_order[2] = {0, 0};  // tiles 1, 2, 4
     bool have_tune = false;
     for (size_t i : members) {
         big += (args[i].Mp / 128) * (args[i].Np / 64);
@@ -182,7 +185,11 @@ void build_group(const std::vector<oz::GemmArgs>& args, std::vector<size_t> memb
         }
     }
     int tile = kernel;
-    if (!tile) tile = have_tune ? (vote_tile[1] > vote_tile[2] ? 1 : 2) : (big >= 2 * cus ? 1 : 2);
+    if (!tile && have_tune) {
+        tile = vote_tile[1] > vote_tile[2] ? 1 : 2;
+        if (vote_tile[4] > vote_tile[tile]) tile = kTile128x64;
+    }
+    if (!tile) tile = big >= 2 * cus ? 1 : 2;
     // the two-tile 128 x 64 block holds one s <= 6 and a single INT32 chunk
     if (tile == kTile128x64 && (sv < 1 || sv > 6 || multi)) tile = kTile64;
     const int order = have_tune && vote_order[1] > vote_order[0] ? 1 : 0;
@@ -438,6 +445,8 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
     P->cplx = cplx;
     P->n_stat_items = P->n_hist = P->n_wt = P->n_gv = P->n_row = P->n_final = P->dyn_cap = 0;
     P->z3 = z3;
+    P->off_fused = 0;
+    P->n_fused = 0;
     P->off_ops3 = P->off_scan3 = P->off_digits3 = 0;
     P->n_scan3 = P->n_digits3 = 0;
 
@@ -562,7 +571,7 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
 
     // ---- split work lists -----------------------------------------------------
     std::vector<oz::SplitOp> ops;
-    std::vector<oz::BlockItem> scan_items, dig_items;
+    std::vector<oz::BlockItem> scan_items, dig_items, fused_items;
     std::vector<oz::Split3Op> ops3;
     std::vector<oz::BlockItem> scan3_items, dig3_items;
     // device addresses are known after allocation: store offsets now, patch below
@@ -602,6 +611,12 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
             const int32_t opi = static_cast<int32_t>(ops.size());
             ops.push_back(so);
             int64_t bx, by;
+            if (!tol_mode && oz::split_fusable(so.op)) {
+                // short vectors: one pass reads the operand once
+                oz::fused_split_blocks(so.op, &by);
+                for (int64_t y = 0; y < by; ++y) fused_items.push_back({opi, 0, static_cast<int32_t>(y), 0});
+                continue;
+            }
             oz::scan_blocks(so.op, &bx, &by);
             for (int64_t y = 0; y < by; ++y)
                 for (int64_t x = 0; x < bx; ++x)
@@ -694,6 +709,8 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
     P->off_ops = take(sizeof(oz::SplitOp) * ops.size());
     P->off_scan = take(sizeof(oz::BlockItem) * scan_items.size());
     P->off_digits = take(sizeof(oz::BlockItem) * dig_items.size());
+    P->off_fused = take(sizeof(oz::BlockItem) * fused_items.size());
+    P->n_fused = static_cast<int64_t>(fused_items.size());
     P->off_args = take(sizeof(oz::GemmArgs) * (z3 ? dargs_host.size() : args.size()));
     if (z3) {
         P->off_ops3 = take(sizeof(oz::Split3Op) * ops3.size());
@@ -880,6 +897,7 @@ int oz_gemm_batched_plan(oz_handle_t h, int is_complex, int32_t batch, const cha
     up_load(P->off_ops, ops.data(), sizeof(oz::SplitOp) * ops.size());
     up_load(P->off_scan, scan_items.data(), sizeof(oz::BlockItem) * scan_items.size());
     up_load(P->off_digits, dig_items.data(), sizeof(oz::BlockItem) * dig_items.size());
+    up_load(P->off_fused, fused_items.data(), sizeof(oz::BlockItem) * fused_items.size());
     if (z3) {
         up_load(P->off_args, dargs_host.data(), sizeof(oz::GemmArgs) * dargs_host.size());
         up_load(P->off_ops3, ops3.data(), sizeof(oz::Split3Op) * ops3.size());
@@ -1149,6 +1167,9 @@ int oz_batch_execute(oz_batch_t P) {
     if (e == hipSuccess)
         e = oz::launch_digits_batched(ops, reinterpret_cast<const oz::BlockItem*>(dev + P->off_digits), P->n_digits,
                                       st);
+    if (e == hipSuccess)
+        e = oz::launch_split_fused_batched(ops, reinterpret_cast<const oz::BlockItem*>(dev + P->off_fused),
+                                           P->n_fused, st);
     if (P->z3) {
         const oz::Split3Op* ops3 = reinterpret_cast<const oz::Split3Op*>(dev + P->off_ops3);
         if (e == hipSuccess)

@@ -15,7 +15,7 @@ struct TuneEntry {
     int cplx;
     int64_t n;
     int s;
-    int tile;   // 1: 128 x 64 blocks, 2: 64 x 64 blocks
+    int tile;   // 1: 128 x 64 blocks, 2: 64 x 64 blocks, 4: 128 x 64 blocks of two-tile waves
     int order;  // 0: tiles by work, problem by problem; 1: problems dealt to per-XCD queues
 };
 }  // namespace oz

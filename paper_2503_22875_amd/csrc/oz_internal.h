@@ -113,6 +113,14 @@ hipError_t launch_scan_batched(const SplitOp* ops, const BlockItem* items, int64
 // [prange[2 op], prange[2 op + 1]) of operand op; an empty range skips it.
 hipError_t launch_digits_batched(const SplitOp* ops, const BlockItem* items, int64_t nitems, hipStream_t st,
                                  const int32_t* prange = nullptr);
+// One-pass split (scan and all digit planes of a fixed-s layout) of operands
+// whose vectors hold at most 1024 doubles (complex k <= 512, real k <= 1024)
+// and whose vectors or terms are contiguous: one block per item (op, by = block
+// of 8 of the operand's vectors; fused_split_blocks gives the count).  The
+// padding rows of the layout past the last block are not written.
+bool split_fusable(const OperandView& op);
+void fused_split_blocks(const OperandView& op, int64_t* by);
+hipError_t launch_split_fused_batched(const SplitOp* ops, const BlockItem* items, int64_t nitems, hipStream_t st);
 
 // GEMM over slice buffers with fused FP64 epilogue.
 struct GemmArgs {

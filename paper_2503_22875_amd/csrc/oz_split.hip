@@ -210,47 +210,14 @@ __device__ __forceinline__ uint64_t pack8(const int* d) {
     return r;
 }
 
-// One block: 64 vectors (64 complex rows for a complex side-'A' operand) x one
-// MFMA step of 32 terms.  Each thread owns 8 consecutive terms of one vector:
-// 8 real elements, or 4 complex elements (terms 2l, 2l+1).
-template <bool LCONTIG, bool CPLX, bool SIDE_A, bool BAL = false>
-__device__ __forceinline__ void digits_body(const OperandView& op, const uint64_t* maxbits, const SliceLayout& lay,
-                                            int32_t* E, int8_t* slices, int64_t bx, int64_t by, int p_lo, int p_hi) {
-    const int tid = threadIdx.x;
-    const int vi = LCONTIG ? (tid >> 2) : (tid & 63);
-    const int sub = LCONTIG ? (tid & 3) : (tid >> 6);
-    const int64_t v = by * 64 + vi;
-    const int64_t step = bx;
-    const int64_t t0 = step * kStep + sub * 8;  // first term of this thread
-    const bool live = v < op.nv;
-
-    int32_t ex = 0;
-    if (live) ex = exponent_of_max(maxbits[v]);
-    const bool bad = ex == kNonFiniteExp;
-    if constexpr (BAL)
-        if (live && !bad) ex += balanced_bump(maxbits[v], ex);
-    if (live && step == 0 && sub == 0) E[v] = ex;
-
-    // 8 doubles: real -> elements l = t0 .. t0+7; complex -> l = t0/2 .. t0/2+3 (re, im)
-    double x[8];
-    constexpr int NEL = CPLX ? 4 : 8;
-    const int64_t lbase = CPLX ? t0 / 2 : t0;
-#pragma unroll
-    for (int e = 0; e < NEL; ++e) {
-        const int64_t l = lbase + e;
-        double re = 0.0, im = 0.0;
-        if (live && !bad && l < op.k) {
-            const double* src = op.X + (v * op.sv + l * op.sl) * (CPLX ? 2 : 1);
-            re = src[0];
-            if (CPLX) im = op.conj ? -src[1] : src[1];
-        }
-        if (CPLX) {
-            x[2 * e] = re;
-            x[2 * e + 1] = im;
-        } else {
-            x[e] = re;
-        }
-    }
+// Digits of the 8 terms t0 .. t0+7 of vector v (x: 8 real elements, or 4
+// complex elements as (re, im) pairs; zeros for a non-finite vector or past k)
+// under scale exponent ex, written as one 8-byte chunk per digit plane (and
+// per row of the two-row form); planes p_lo .. p_hi - 1 (balanced digits: all
+// p_hi planes of an s = p_hi split).
+template <bool CPLX, bool SIDE_A, bool BAL>
+__device__ __forceinline__ void emit_digits(const double (&x)[8], int32_t ex, int64_t v, int64_t t0,
+                                            const SliceLayout& lay, int8_t* slices, int p_lo, int p_hi) {
     if constexpr (BAL) {
         // all p_hi planes at once (p_lo = 0): the digits of an s = p_hi split
         // (a tolerance-driven plan lays out more planes than it fills)
@@ -334,6 +301,50 @@ __device__ __forceinline__ void digits_body(const OperandView& op, const uint64_
     }
 }
 
+// One block: 64 vectors (64 complex rows for a complex side-'A' operand) x one
+// MFMA step of 32 terms.  Each thread owns 8 consecutive terms of one vector:
+// 8 real elements, or 4 complex elements (terms 2l, 2l+1).
+template <bool LCONTIG, bool CPLX, bool SIDE_A, bool BAL = false>
+__device__ __forceinline__ void digits_body(const OperandView& op, const uint64_t* maxbits, const SliceLayout& lay,
+                                            int32_t* E, int8_t* slices, int64_t bx, int64_t by, int p_lo, int p_hi) {
+    const int tid = threadIdx.x;
+    const int vi = LCONTIG ? (tid >> 2) : (tid & 63);
+    const int sub = LCONTIG ? (tid & 3) : (tid >> 6);
+    const int64_t v = by * 64 + vi;
+    const int64_t step = bx;
+    const int64_t t0 = step * kStep + sub * 8;  // first term of this thread
+    const bool live = v < op.nv;
+
+    int32_t ex = 0;
+    if (live) ex = exponent_of_max(maxbits[v]);
+    const bool bad = ex == kNonFiniteExp;
+    if constexpr (BAL)
+        if (live && !bad) ex += balanced_bump(maxbits[v], ex);
+    if (live && step == 0 && sub == 0) E[v] = ex;
+
+    // 8 doubles: real -> elements l = t0 .. t0+7; complex -> l = t0/2 .. t0/2+3 (re, im)
+    double x[8];
+    constexpr int NEL = CPLX ? 4 : 8;
+    const int64_t lbase = CPLX ? t0 / 2 : t0;
+#pragma unroll
+    for (int e = 0; e < NEL; ++e) {
+        const int64_t l = lbase + e;
+        double re = 0.0, im = 0.0;
+        if (live && !bad && l < op.k) {
+            const double* src = op.X + (v * op.sv + l * op.sl) * (CPLX ? 2 : 1);
+            re = src[0];
+            if (CPLX) im = op.conj ? -src[1] : src[1];
+        }
+        if (CPLX) {
+            x[2 * e] = re;
+            x[2 * e + 1] = im;
+        } else {
+            x[e] = re;
+        }
+    }
+    emit_digits<CPLX, SIDE_A, BAL>(x, ex, v, t0, lay, slices, p_lo, p_hi);
+}
+
 template <bool LCONTIG, bool CPLX, bool SIDE_A, bool BAL>
 __global__ __launch_bounds__(256) void digits_kernel(OperandView op, const uint64_t* maxbits, SliceLayout lay,
                                                      int32_t* E, int8_t* slices, int p_lo, int p_hi) {
@@ -379,6 +390,137 @@ __global__ __launch_bounds__(256) void digits_batched_kernel(const SplitOp* __re
         else OZ_DB(false, false, false);
     }
 #undef OZ_DB
+}
+
+// ---- one-pass split of short vectors ----------------------------------------
+// Block = kFuseV vectors, each at most kFuseMaxDoubles doubles long (complex
+// k <= 512, real k <= 1024): the vectors are read once from HBM into LDS
+// (consecutive lanes on consecutive doubles of a vector when its terms are
+// contiguous, on consecutive vectors otherwise), the per-vector maxima are
+// taken from LDS, and the digits are emitted from LDS with the arithmetic of
+// digits_body (emit_digits): the FP64 operand is read once instead of twice.
+// Threads of the digit phase: (vector v, 8-term half h, 16-term chunk c) with v
+// fastest, so the chunks of the block's rows for one (c, plane) are one
+// contiguous run of 16-byte rows.
+constexpr int kFuseV = 4;
+constexpr int kFuseMaxDoubles = 1024;
+constexpr int kFuseRow = kFuseMaxDoubles + 2;  // LDS doubles per staged vector (+2 spreads the banks)
+
+template <bool LCONTIG, bool CPLX, bool SIDE_A, bool BAL>
+__device__ __forceinline__ void fused_split_body(const SplitOp& o, int64_t by, double* stage, uint64_t* vmax) {
+    const OperandView& op = o.op;
+    const int tid = threadIdx.x;
+    constexpr int W = CPLX ? 2 : 1;  // doubles per element
+    const int64_t K = op.k;
+    const int64_t v0 = by * kFuseV;
+    const int nvb = op.nv - v0 < kFuseV ? static_cast<int>(op.nv - v0 > 0 ? op.nv - v0 : 0) : kFuseV;
+    // phase 1: stage the block's vectors, stage[v * kFuseRow + l * W + part];
+    // each thread owns kLoads doubles, all loaded before any is stored so that
+    // the loads are in flight together
+    constexpr int kLoads = kFuseV * kFuseMaxDoubles / 256;
+    double buf[kLoads];
+    static_assert(kFuseMaxDoubles == 4 * 256 && kFuseV * 4 == kLoads, "4 doubles of a vector per thread");
+    if constexpr (LCONTIG) {
+        // double i of the thread: vector i / 4, double tid + 256 (i % 4) of it
+#pragma unroll
+        for (int i = 0; i < kLoads; ++i) {
+            const int v = i >> 2;
+            const int64_t d = tid + 256 * (i & 3);
+            buf[i] = (v < nvb && d < K * W) ? op.X[(v0 + v) * op.sv * W + d] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < kLoads; ++i) {
+            const int64_t d = tid + 256 * (i & 3);
+            if (d < K * W) stage[(i >> 2) * kFuseRow + d] = buf[i];
+        }
+    } else {
+        // kFuseV consecutive vectors of one term are contiguous (sv == 1):
+        // double i of the thread is term lo + LPER i of vector v, part `part`
+        constexpr int LPER = 256 / (kFuseV * W);  // terms per pass
+        const int part = tid % W, v = (tid / W) % kFuseV, lo = tid / (kFuseV * W);
+#pragma unroll
+        for (int i = 0; i < kLoads; ++i) {
+            const int64_t l = lo + static_cast<int64_t>(LPER) * i;
+            buf[i] = (v < nvb && l < K) ? op.X[(v0 + v + l * op.sl) * W + part] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < kLoads; ++i) {
+            const int64_t l = lo + static_cast<int64_t>(LPER) * i;
+            if (l < K) stage[v * kFuseRow + l * W + part] = buf[i];
+        }
+    }
+    __syncthreads();
+    // per-vector max of |x| bits: TPV threads per vector
+    {
+        constexpr int TPV = 256 / kFuseV;
+        const int v = tid / TPV, j = tid % TPV;
+        uint64_t mx = 0;
+        for (int64_t d = j; d < K * W; d += TPV) mx = umax64(mx, mag_bits(stage[v * kFuseRow + d]));
+        for (int off = TPV / 2; off > 0; off >>= 1) mx = umax64(mx, __shfl_xor(mx, off, TPV));
+        if (j == 0) {
+            vmax[v] = mx;
+            if (v < nvb) o.maxbits[v0 + v] = mx;
+        }
+    }
+    __syncthreads();
+    // phase 2: digits from LDS
+    const int v = tid % kFuseV, h = (tid / kFuseV) & 1;
+    const int64_t vg = v0 + v;
+    const bool live = v < nvb;
+    int32_t ex = 0;
+    if (live) ex = exponent_of_max(vmax[v]);
+    const bool bad = ex == kNonFiniteExp;
+    if constexpr (BAL)
+        if (live && !bad) ex += balanced_bump(vmax[v], ex);
+    if (live && tid < kFuseV) o.E[vg] = ex;
+    const bool take = live && !bad;
+    const int64_t nchunks = o.lay.kpad / 16;
+    for (int64_t c = tid / (2 * kFuseV); c < nchunks; c += 256 / (2 * kFuseV)) {
+        const int64_t t0 = c * 16 + h * 8;
+        double x[8];
+        constexpr int NEL = CPLX ? 4 : 8;
+        const int64_t lbase = CPLX ? t0 / 2 : t0;
+#pragma unroll
+        for (int e = 0; e < NEL; ++e) {
+            const int64_t l = lbase + e;
+            double re = 0.0, im = 0.0;
+            if (take && l < K) {
+                re = stage[v * kFuseRow + l * W];
+                if (CPLX) im = op.conj ? -stage[v * kFuseRow + l * W + 1] : stage[v * kFuseRow + l * W + 1];
+            }
+            if (CPLX) {
+                x[2 * e] = re;
+                x[2 * e + 1] = im;
+            } else {
+                x[e] = re;
+            }
+        }
+        emit_digits<CPLX, SIDE_A, BAL>(x, ex, vg, t0, o.lay, o.slices, 0, o.lay.s);
+    }
+}
+
+__global__ __launch_bounds__(256) void split_fused_batched_kernel(const SplitOp* __restrict__ ops,
+                                                                  const BlockItem* __restrict__ items) {
+    __shared__ double stage[kFuseV * kFuseRow];
+    __shared__ uint64_t vmax[kFuseV];
+    const BlockItem it = items[blockIdx.x];
+    const SplitOp& o = ops[it.op];
+    const bool lc = o.op.sl == 1, two_row = o.op.cplx && o.op.side_a;  // uniform over the block
+#define OZ_FS(LC, CP, SA)                                                                  \
+    do {                                                                                   \
+        if (o.lay.bal) fused_split_body<LC, CP, SA, true>(o, it.by, stage, vmax);          \
+        else fused_split_body<LC, CP, SA, false>(o, it.by, stage, vmax);                   \
+    } while (0)
+    if (lc) {
+        if (two_row) OZ_FS(true, true, true);
+        else if (o.op.cplx) OZ_FS(true, true, false);
+        else OZ_FS(true, false, false);
+    } else {
+        if (two_row) OZ_FS(false, true, true);
+        else if (o.op.cplx) OZ_FS(false, true, false);
+        else OZ_FS(false, false, false);
+    }
+#undef OZ_FS
 }
 
 // ---- three real operands of one complex operand in one pass ---------------
@@ -626,6 +768,22 @@ hipError_t launch_scan3_batched(const Split3Op* ops, const BlockItem* items, int
     if (nitems <= 0) return hipSuccess;
     hipLaunchKernelGGL(scan3_batched_kernel, dim3(static_cast<unsigned>(nitems)), dim3(256), 0, st, ops, items,
                        scan_lspan());
+    return hipGetLastError();
+}
+
+bool split_fusable(const OperandView& op) {
+    return op.k * (op.cplx ? 2 : 1) <= kFuseMaxDoubles && (op.sl == 1 || op.sv == 1);
+}
+
+// Blocks over the operand's own vectors only: a GEMM tile that reaches into
+// the padding rows of the layout reads whatever they hold, but those rows only
+// feed rows (columns) of C' that are never stored, so they need no digits.
+void fused_split_blocks(const OperandView& op, int64_t* by) { *by = (op.nv + kFuseV - 1) / kFuseV; }
+
+hipError_t launch_split_fused_batched(const SplitOp* ops, const BlockItem* items, int64_t nitems, hipStream_t st) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(split_fused_batched_kernel, dim3(static_cast<unsigned>(nitems)), dim3(256), 0, st, ops,
+                       items);
     return hipGetLastError();
 }
 

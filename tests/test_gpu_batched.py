@@ -103,6 +103,29 @@ def test_batched_bit_exact_mixed(oz, handle, stream, cplx):
 
 
 @pytest.mark.parametrize("cplx", [0, 1])
+@pytest.mark.parametrize("digits", [0, 1])
+def test_batched_split_paths(oz, handle, stream, cplx, digits):
+    # vectors of at most 1024 doubles (complex k <= 512, real k <= 1024) take
+    # the one-pass split, longer ones the scan + digits passes; both at the
+    # boundary and past it, every transpose pair, in one batch
+    rng = np.random.default_rng(40 + 2 * cplx + digits)
+    kmax = 512 if cplx else 1024
+    shapes = [(37, 29, kmax), (45, 61, kmax + 1), (9, 130, kmax - 3), (130, 9, kmax + 200), (64, 64, 1)]
+    probs = []
+    for i, (m, n, k) in enumerate(shapes):
+        ta = "NTC"[i % 3] if cplx else "NT"[i % 2]
+        tb = "NCT"[(i // 2) % 3] if cplx else "TN"[(i // 2) % 2]
+        A, B, C0 = make_problem(rng, cplx, m, n, k, ta, tb)
+        be = (complex(0.5, 0.25) if i % 2 else 0.0) if cplx else (0.5 if i % 2 else 0.0)
+        probs.append((ta, tb, A, B, C0, 1.25, be))
+    print("split paths cplx=%d digits=%d" % (cplx, digits), flush=True)
+    got = batch_call(oz, handle, stream, cplx, probs, 6, digits=digits)
+    for i, (ta, tb, A, B, C0, al, be) in enumerate(probs):
+        want = oracle.emu_gemm(ta, tb, A, B, 6, alpha=al, beta=be, C=C0, balanced=bool(digits))
+        assert np.array_equal(got[i], want), (i, ta, tb, A.shape, B.shape)
+
+
+@pytest.mark.parametrize("cplx", [0, 1])
 @pytest.mark.parametrize("s,digits,use_plan", [(6, 0, False), (5, 1, True), (2, 0, False), (7, 0, False)])
 def test_batched_two_tile_block(oz, handle, stream, cplx, s, digits, use_plan):
     # the 128 x 64 block of two-tile waves (s <= 6; s = 7 falls back to the
