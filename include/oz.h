@@ -89,9 +89,9 @@ typedef struct oz_handle_s* oz_handle_t;
  *           one) with m, n and k all at least 2048, the 4-product form
  *           otherwise (tolerance-driven and batched calls, small products,
  *           k below 2048 as in the LU updates); oz_report_t.zmode_used tells.
- *           3: the 3-real-product form (fixed slice counts only, up to 8
- *           in a batched call; a tolerance-driven call with zmode 3 returns
- *           14): with
+ *           3: the 3-real-product form (batched calls: fixed slice counts up
+ *           to 8; tolerance-driven single calls: truncated digits, and 14
+ *           with digits = 1): with
  *           op(A) = Ar + i Ai, op(B) = Br + i Bi and the FP64 sums As = Ar + Ai,
  *           Bs = Br + Bi (each rounded once), T1 = Ar Br, T2 = Ai Bi and
  *           T3 = As Bs are three real emulated products, each with its own
@@ -99,7 +99,12 @@ typedef struct oz_handle_s* oz_handle_t;
  *           then Cr = T1 - T2, Ci = (T3 - T1) - T2 and alpha, beta as for
  *           zmode 4.  Three quarters of the INT8 work; the error is of the same
  *           order (the sums can double the scale of T3).  A row or column
- *           whose sum overflows counts as non-finite.
+ *           whose sum overflows counts as non-finite.  A tolerance-driven
+ *           call picks its start from the complex operands as for zmode 4,
+ *           keeps the raw sums of T1, T2 and T3, checks the combined result,
+ *           grows each product by its top anti-diagonals (T1, T2, T3 in turn)
+ *           and combines the sums into C at the end: bit-identical to three
+ *           real tolerance products grown the same way and combined once.
  *  kernel : GEMM kernel shape; 0 = the default (for s <= 6 with one INT32
  *           chunk and at least 512 tiles of 128 x 64, shape 4; else the
  *           64 x 64 block for s <= 8; for 9 <= s <= 14 the same all-diagonal

@@ -230,7 +230,7 @@ def _op(trans, X):
 
 
 def emu_zgemm3(transa, transb, A, B, s, alpha=1.0, beta=0.0, C=None, kc=None, rows=None, cols=None,
-               balanced=False):
+               balanced=False, s_to=None):
     """O4, complex product in the 3-real-product form (3M).
 
     With op(A) = Ar + i Ai and op(B) = Br + i Bi, the pre-added operands
@@ -240,17 +240,20 @@ def emu_zgemm3(transa, transb, A, B, s, alpha=1.0, beta=0.0, C=None, kc=None, ro
     Cr = T1 - T2, Ci = (T3 - T1) - T2, and then alpha, beta are applied with
     the complex formula of the 4-product form (each product and sum rounded).
     balanced: the three real products take balanced digits (none of their
-    operands is negated, so no digit of a negated value arises)."""
+    operands is negated, so no digit of a negated value arises).
+    s_to: each real product is formed at s and then grown to s_to by its
+    top anti-diagonals (the incremental order of ``emu_gemm``); the three are
+    combined once, at s_to."""
     A = _op(transa, _f(A, np.complex128))
     B = _op(transb, _f(B, np.complex128))
     Ar, Ai = np.asfortranarray(A.real), np.asfortranarray(A.imag)
     Br, Bi = np.asfortranarray(B.real), np.asfortranarray(B.imag)
     As = np.asfortranarray(Ar + Ai)
     Bs = np.asfortranarray(Br + Bi)
-    kc = kchunk(s, balanced=balanced) if kc is None else kc
-    T1 = emu_gemm("N", "N", Ar, Br, s, kc=kc, rows=rows, cols=cols, balanced=balanced)
-    T2 = emu_gemm("N", "N", Ai, Bi, s, kc=kc, rows=rows, cols=cols, balanced=balanced)
-    T3 = emu_gemm("N", "N", As, Bs, s, kc=kc, rows=rows, cols=cols, balanced=balanced)
+    kc = kchunk(s if s_to is None else s_to, balanced=balanced) if kc is None else kc
+    T1 = emu_gemm("N", "N", Ar, Br, s, kc=kc, rows=rows, cols=cols, balanced=balanced, s_to=s_to)
+    T2 = emu_gemm("N", "N", Ai, Bi, s, kc=kc, rows=rows, cols=cols, balanced=balanced, s_to=s_to)
+    T3 = emu_gemm("N", "N", As, Bs, s, kc=kc, rows=rows, cols=cols, balanced=balanced, s_to=s_to)
     Cr = T1 - T2
     Ci = (T3 - T1) - T2
     xr, xi = complex(alpha).real, complex(alpha).imag

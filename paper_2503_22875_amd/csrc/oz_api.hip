@@ -150,14 +150,19 @@ Plan make_plan(int cplx, int64_t m, int64_t n, int64_t k, int s_lay, bool tol_bu
 
 // Workspace of a complex product in the 3-real-product form: per real operand
 // (parts 1: real, 2: imaginary, 3: their sum) the scale scratch, exponents and
-// slices of A and B, then the real products T1, T2 (m x n).
+// slices of A and B (s_lay digit planes), then the real products T1, T2
+// (m x n) of a fixed-s call, or for a tolerance-driven call the raw sums of
+// T1, T2, T3, the complex operands' own maxima and the check and statistics
+// buffers.
 struct Plan3 {
     oz::SliceLayout la, lb;
     size_t off_max, off_ea[3], off_fb[3], off_sa[3], off_sb[3], off_t1, off_t2, total;
+    size_t off_acc[3], off_maxc, off_msa, off_msb, off_t, off_u, off_diff, off_ref, off_norms, off_sel, off_part1,
+        off_part2;
     int64_t nmax;
 };
 
-Plan3 make_plan3(int64_t m, int64_t n, int64_t k, int s) {
+Plan3 make_plan3(int64_t m, int64_t n, int64_t k, int s, bool tol_bufs = false) {
     Plan3 p;
     p.la = oz::slice_layout(1, 0, m, k, s);
     p.lb = oz::slice_layout(0, 0, n, k, s);
@@ -175,8 +180,28 @@ Plan3 make_plan3(int64_t m, int64_t n, int64_t k, int s) {
         p.off_sa[q] = take(static_cast<size_t>(s) * p.la.rows_pad * p.la.kpad);
         p.off_sb[q] = take(static_cast<size_t>(s) * p.lb.rows_pad * p.lb.kpad);
     }
-    p.off_t1 = take(sizeof(double) * static_cast<size_t>(m) * n);
-    p.off_t2 = take(sizeof(double) * static_cast<size_t>(m) * n);
+    p.off_t1 = p.off_t2 = 0;
+    for (int q = 0; q < 3; ++q) p.off_acc[q] = 0;
+    p.off_maxc = p.off_msa = p.off_msb = p.off_t = p.off_u = p.off_diff = p.off_ref = p.off_norms = p.off_sel = 0;
+    p.off_part1 = p.off_part2 = 0;
+    if (!tol_bufs) {
+        p.off_t1 = take(sizeof(double) * static_cast<size_t>(m) * n);
+        p.off_t2 = take(sizeof(double) * static_cast<size_t>(m) * n);
+    } else {
+        for (int q = 0; q < 3; ++q)
+            p.off_acc[q] = take(sizeof(double) * static_cast<size_t>(p.la.rows_pad) * p.lb.rows_pad);
+        p.off_maxc = take(sizeof(uint64_t) * static_cast<size_t>(m + n));
+        p.off_msa = take(sizeof(double) * static_cast<size_t>(m));
+        p.off_msb = take(sizeof(double) * static_cast<size_t>(n));
+        p.off_t = take(sizeof(double) * static_cast<size_t>(n));
+        p.off_u = take(sizeof(double) * 4 * static_cast<size_t>(k));
+        p.off_diff = take(sizeof(double) * 2 * static_cast<size_t>(m));
+        p.off_ref = take(sizeof(double) * 2 * static_cast<size_t>(m));
+        p.off_norms = take(sizeof(double) * 2);
+        p.off_sel = take(oz_learned_scratch_bytes());
+        p.off_part1 = take(oz::check_part_bytes(m, n, k));
+        p.off_part2 = take(oz::check_part_bytes(m, n, k));
+    }
     p.total = o;
     return p;
 }
@@ -308,10 +333,25 @@ int rule_slices(oz_handle_t h, const oz::OperandView& va, const oz::OperandView&
 // operands rounded once in FP64 as the split reads them); the last one's
 // epilogue forms Cr = T1 - T2, Ci = (T3 - T1) - T2 and applies alpha, beta.
 // Three quarters of the INT8 work of the 4-product form.
+//
+// Tolerance-driven (tp != nullptr, truncated digits): the starting s comes from
+// the complex operands' statistics as for the 4-product form; the three
+// products write raw FP64 sums; the residual check forms C from them with the
+// combine's roundings; each growth step adds a digit plane to every part and
+// the new top anti-diagonal to each product (T1, T2, T3 in turn); a last pass
+// combines the sums into C.
+struct Tol3 {
+    double tol;
+    int smax, sstart, selector;
+};
+
 int zgemm_3m(oz_handle_t h, char transa, char transb, int64_t m, int64_t n, int64_t k, const double* alpha,
              const double* A, int64_t lda, const double* B, int64_t ldb, const double* beta, double* C, int64_t ldc,
-             int s, int64_t kc, int kernel, bool bal, oz_report_t* rep, const FixedWs& fixed) {
-    Plan3 p = make_plan3(m, n, k, s);
+             int s, int64_t kc, int kernel, bool bal, oz_report_t* rep, const FixedWs& fixed,
+             const Tol3* tp = nullptr) {
+    const bool tol_mode = tp != nullptr;
+    const int s_lay = tol_mode ? tp->smax : s;
+    Plan3 p = make_plan3(m, n, k, s_lay, tol_mode);
     if (p.la.rows_pad / 64 > 65535 || p.lb.rows_pad / 64 > 65535) return OZ_ERR_UNSUPPORTED;
     p.la.bal = p.lb.bal = bal ? 1 : 0;
     char* ws = nullptr;
@@ -319,9 +359,10 @@ int zgemm_3m(oz_handle_t h, char transa, char transb, int64_t m, int64_t n, int6
     if (st) return st;
     uint64_t* mx = reinterpret_cast<uint64_t*>(ws + p.off_max);
     const double ar = alpha[0], ai = alpha[1], br = beta[0], bi = beta[1];
+    const int beta_zero = (br == 0.0 && bi == 0.0) ? 1 : 0;
     // no timing events on the allocation-free path (events are created on demand)
     auto mark = [&](oz_handle_t hh) { return fixed.ptr ? hipSuccess : ::mark(hh); };
-    hipError_t e = mark(h);
+    hipError_t e = tol_mode ? hipSuccess : mark(h);
     if (e == hipSuccess) e = oz::launch_zero_u64(mx, p.nmax, h->stream);
     // the three real operands of each side (real parts, imaginary parts,
     // their sums) in one scan and one digit pass over the complex operand
@@ -338,12 +379,9 @@ int zgemm_3m(oz_handle_t h, char transa, char transb, int64_t m, int64_t n, int6
     }
     if (e == hipSuccess) e = oz::launch_scan3(va, oa, h->stream);
     if (e == hipSuccess) e = oz::launch_scan3(vb, ob, h->stream);
-    if (e == hipSuccess) e = oz::launch_digits3(va, p.la, oa, h->stream);
-    if (e == hipSuccess) e = oz::launch_digits3(vb, p.lb, ob, h->stream);
-    if (e == hipSuccess) e = mark(h);
-    double* T[2] = {reinterpret_cast<double*>(ws + p.off_t1), reinterpret_cast<double*>(ws + p.off_t2)};
-    for (int q = 0; q < 3 && e == hipSuccess; ++q) {
-        oz::GemmArgs g;
+    oz::GemmArgs g3[3];
+    for (int q = 0; q < 3; ++q) {
+        oz::GemmArgs& g = g3[q];
         std::memset(&g, 0, sizeof(g));
         g.SA = reinterpret_cast<const int8_t*>(ws + p.off_sa[q]);
         g.SB = reinterpret_cast<const int8_t*>(ws + p.off_sb[q]);
@@ -354,37 +392,141 @@ int zgemm_3m(oz_handle_t h, char transa, char transb, int64_t m, int64_t n, int6
         g.kpad = p.la.kpad;
         g.chunk_steps = kc / oz::kStep;
         g.s = s;
-        g.s_lay = s;
+        g.s_lay = s_lay;
         g.tile = kernel;
         g.m = m;
         g.n = n;
         g.bal = bal ? 1 : 0;
-        if (q < 2) {
-            // T1, T2: plain FP64 results (alpha = 1, beta = 0: 1 * v is exact)
-            g.mode = oz::kFinal;
-            g.C = T[q];
-            g.ldc = m;
-            g.alpha_r = 1.0;
-            g.beta_zero = 1;
-        } else {
-            g.mode = oz::kCombine3M;
-            g.C = C;
-            g.ldc = ldc;
-            g.alpha_r = ar;
-            g.alpha_i = ai;
-            g.beta_r = br;
-            g.beta_i = bi;
-            g.beta_zero = (br == 0.0 && bi == 0.0) ? 1 : 0;
-            g.t1 = T[0];
-            g.t2 = T[1];
-            g.ldt = m;
-        }
-        e = oz::launch_gemm(g, h->stream);
     }
-    if (e == hipSuccess) e = mark(h);
-    if (e != hipSuccess) return OZ_ERR_HIP;
+    int fallbacks = 0;
+    double eps = 0.0;
+    if (!tol_mode) {
+        if (e == hipSuccess) e = oz::launch_digits3(va, p.la, oa, h->stream);
+        if (e == hipSuccess) e = oz::launch_digits3(vb, p.lb, ob, h->stream);
+        if (e == hipSuccess) e = mark(h);
+        double* T[2] = {reinterpret_cast<double*>(ws + p.off_t1), reinterpret_cast<double*>(ws + p.off_t2)};
+        for (int q = 0; q < 3 && e == hipSuccess; ++q) {
+            oz::GemmArgs& g = g3[q];
+            if (q < 2) {
+                // T1, T2: plain FP64 results (alpha = 1, beta = 0: 1 * v is exact)
+                g.mode = oz::kFinal;
+                g.C = T[q];
+                g.ldc = m;
+                g.alpha_r = 1.0;
+                g.beta_zero = 1;
+            } else {
+                g.mode = oz::kCombine3M;
+                g.C = C;
+                g.ldc = ldc;
+                g.alpha_r = ar;
+                g.alpha_i = ai;
+                g.beta_r = br;
+                g.beta_i = bi;
+                g.beta_zero = beta_zero;
+                g.t1 = T[0];
+                g.t2 = T[1];
+                g.ldt = m;
+            }
+            e = oz::launch_gemm(g, h->stream);
+        }
+        if (e == hipSuccess) e = mark(h);
+        if (e != hipSuccess) return OZ_ERR_HIP;
+    } else {
+        if (e != hipSuccess) return OZ_ERR_HIP;
+        // (1) starting s from the complex operands' statistics (their own
+        // maxima), for the checked target
+        uint64_t* maxa = reinterpret_cast<uint64_t*>(ws + p.off_maxc);
+        uint64_t* maxb = maxa + m;
+        double* msa = reinterpret_cast<double*>(ws + p.off_msa);
+        double* msb = reinterpret_cast<double*>(ws + p.off_msb);
+        const double tol_eff = tp->tol / oz::kCheckMargin;
+        const int smax = tp->smax;
+        if (oz::launch_zero_u64(maxa, m + n, h->stream) != hipSuccess ||
+            oz::launch_scan(va, maxa, h->stream) != hipSuccess || oz::launch_scan(vb, maxb, h->stream) != hipSuccess)
+            return OZ_ERR_HIP;
+        if (tp->sstart > 0) {
+            s = tp->sstart;
+        } else if (tp->selector == 1) {
+            st = oz_learned_start(h, h->selector, va, vb, maxa, maxb, msa, msb, m, n, k, 1, tol_eff, smax,
+                                  ws + p.off_sel, &s);
+            if (st) return st;
+        } else {
+            st = rule_slices(h, va, vb, maxa, maxb, msa, msb, reinterpret_cast<double*>(ws + p.off_part1), tol_eff,
+                             smax, &s);
+            if (st) return st;
+        }
+        if (s > smax) s = smax;
+        // (2) digit planes 1..s of every part, raw sums of T1, T2, T3 at s
+        if (oz::launch_digits3(va, p.la, oa, h->stream, 0, s) != hipSuccess ||
+            oz::launch_digits3(vb, p.lb, ob, h->stream, 0, s) != hipSuccess)
+            return OZ_ERR_HIP;
+        for (int q = 0; q < 3; ++q) {
+            g3[q].acc = reinterpret_cast<double*>(ws + p.off_acc[q]);
+            g3[q].s = s;
+            g3[q].mode = oz::kRawWrite;
+            if (oz::launch_gemm(g3[q], h->stream) != hipSuccess) return OZ_ERR_HIP;
+        }
+        // (3) check; grow until it passes
+        oz::CheckArgs c;
+        std::memset(&c, 0, sizeof(c));
+        c.opa = va;
+        c.opb = vb;
+        c.maxa = maxa;
+        c.maxb = maxb;
+        c.Mp = p.la.rows_pad;
+        c.seed = kProbeSeed;
+        c.t = reinterpret_cast<double*>(ws + p.off_t);
+        c.u = reinterpret_cast<double*>(ws + p.off_u);
+        c.diff = reinterpret_cast<double*>(ws + p.off_diff);
+        c.ref = reinterpret_cast<double*>(ws + p.off_ref);
+        c.norms = reinterpret_cast<double*>(ws + p.off_norms);
+        c.part1 = reinterpret_cast<double*>(ws + p.off_part1);
+        c.part2 = reinterpret_cast<double*>(ws + p.off_part2);
+        c.z3 = 1;
+        for (int q = 0; q < 3; ++q) {
+            c.acc3[q] = g3[q].acc;
+            c.EA3[q] = g3[q].EA;
+            c.FB3[q] = g3[q].FB;
+        }
+        for (;;) {
+            if (oz::launch_residual(c, h->stream) != hipSuccess) return OZ_ERR_HIP;
+            double nrm[2];
+            if (hipMemcpyAsync(nrm, c.norms, sizeof(nrm), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+                hipStreamSynchronize(h->stream) != hipSuccess)
+                return OZ_ERR_HIP;
+            eps = nrm[1] > 0.0 ? std::sqrt(nrm[0] / nrm[1]) : std::sqrt(nrm[0]);
+            if (!(eps > tol_eff) || s >= smax) break;  // NaN (non-finite input) also stops
+            int add = static_cast<int>(std::ceil(std::log2(eps / tol_eff) / 6.0));
+            add = add < 1 ? 1 : (add > smax - s ? smax - s : add);
+            // digit planes s + 1 .. s + add of every part, then the
+            // anti-diagonals s + 2 .. s + add + 1 of each product, one at a time
+            if (oz::launch_digits3(va, p.la, oa, h->stream, s, s + add) != hipSuccess ||
+                oz::launch_digits3(vb, p.lb, ob, h->stream, s, s + add) != hipSuccess)
+                return OZ_ERR_HIP;
+            for (int j = 0; j < add; ++j) {
+                for (int q = 0; q < 3; ++q) {
+                    g3[q].s = s + 1;
+                    g3[q].top = 1;
+                    g3[q].mode = oz::kRawAdd;
+                    if (oz::launch_gemm(g3[q], h->stream) != hipSuccess) return OZ_ERR_HIP;
+                    g3[q].top = 0;
+                }
+                ++s;
+                ++fallbacks;
+            }
+        }
+        // (4) C = alpha ((T1 - T2) + i ((T3 - T1) - T2)) + beta C
+        const double* acc3[3] = {g3[0].acc, g3[1].acc, g3[2].acc};
+        const int32_t* ea3[3] = {g3[0].EA, g3[1].EA, g3[2].EA};
+        const int32_t* fb3[3] = {g3[0].FB, g3[1].FB, g3[2].FB};
+        if (oz::launch_finalize3(acc3, p.la.rows_pad, ea3, fb3, C, ldc, m, n, ar, ai, br, bi, beta_zero,
+                                 h->stream) != hipSuccess)
+            return OZ_ERR_HIP;
+    }
     if (rep) {
         rep->slices_used = s;
+        rep->fallbacks = fallbacks;
+        rep->resid_est = eps;
         rep->zmode_used = 3;
         rep->kchunks = static_cast<int32_t>((p.la.kpad + kc - 1) / kc);
         if (hipStreamSynchronize(h->stream) != hipSuccess) return OZ_ERR_HIP;
@@ -403,8 +545,9 @@ int zgemm_3m(oz_handle_t h, char transa, char transb, int64_t m, int64_t n, int6
     return OZ_OK;
 }
 
-// The complex form of a fixed-s product with zmode 0: the 3-real-product form
-// when every dimension is at least kAuto3mMin, else the 4-product form.
+// The complex form: zmode 3 asks for the 3-real-product form; with zmode 0 a
+// fixed-s product takes it when every dimension is at least kAuto3mMin, and
+// the 4-product form otherwise (and always for a tolerance-driven call).
 // Measured on ZGEMM at s = 6 (balanced) and 7: the three products win from
 // m = n = k = 2048 on (0.59 vs 0.64 ms; 3.5 vs 4.5 ms at 4096); with k up to
 // 512, or m = n = k <= 1536, their three splits, T1 and T2 round trips and
@@ -412,9 +555,9 @@ int zgemm_3m(oz_handle_t h, char transa, char transb, int64_t m, int64_t n, int6
 constexpr int64_t kAuto3mMin = 2048;
 bool use_3m(int cplx, const oz_prec_t* prec, bool tol_mode, bool dd, int64_t m, int64_t n, int64_t k) {
     const int zmode = prec ? prec->zmode : 0;
-    if (!cplx || tol_mode || dd) return false;
+    if (!cplx || dd) return false;
     if (zmode == 3) return true;
-    return zmode == 0 && m >= kAuto3mMin && n >= kAuto3mMin && k >= kAuto3mMin;
+    return zmode == 0 && !tol_mode && m >= kAuto3mMin && n >= kAuto3mMin && k >= kAuto3mMin;
 }
 
 // c_lo != nullptr: double-double result (C the high parts, c_lo the low
@@ -444,7 +587,8 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
     if (prec) {
         if (prec->slices < 0 || prec->slices > OZ_MAX_SLICES) return 14;
         if (prec->zmode != 0 && prec->zmode != 3 && prec->zmode != 4) return 14;
-        if (cplx && prec->zmode == 3 && prec->slices == 0) return 14;  // 3M: fixed slice counts only
+        // 3M tolerance-driven: truncated digits (balanced growth is not incremental)
+        if (cplx && prec->zmode == 3 && prec->slices == 0 && prec->digits == 1) return 14;
         if (prec->kernel < 0 || prec->kernel > 5) return 14;
         if (prec->digits != 0 && prec->digits != 1) return 14;
         bal = prec->digits == 1;
@@ -497,9 +641,14 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
 
     if (use_3m(cplx, prec, tol_mode, c_lo != nullptr, m, n, k)) {
         // 3-real-product form: real INT32 chunks of k terms
-        const int64_t kc3 = prec->kchunk ? prec->kchunk : kchunk_bound(s, bal);
+        const int64_t kc3 = kc;  // the bound of the largest slice count the call may use
+        if (!tol_mode)
+            return zgemm_3m(h, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, s, kc3, kernel, bal, rep,
+                            fixed);
+        if (fixed.ptr) return 14;  // the allocation-free path takes fixed slice counts
+        const Tol3 t3{tol, smax, prec->sstart, prec->selector};
         return zgemm_3m(h, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, s, kc3, kernel, bal, rep,
-                        fixed);
+                        fixed, &t3);
     }
     if (fixed.ptr && tol_mode) return 14;  // the allocation-free path takes fixed slice counts
     Plan p = make_plan(cplx, m, n, k, s_plan, tol_mode);
@@ -597,6 +746,7 @@ int gemm_common(oz_handle_t h, int cplx, char transa, char transb, int64_t m, in
         if (oz::launch_gemm(g, h->stream) != hipSuccess) return OZ_ERR_HIP;
         // (3) check; grow by one slice (new digit, new anti-diagonal) until it passes
         oz::CheckArgs c;
+        std::memset(&c, 0, sizeof(c));  // z3 = 0: the raw sums of one product
         c.opa = va;
         c.opb = vb;
         c.maxa = maxa;
@@ -850,7 +1000,7 @@ int oz_workspace_size(oz_handle_t h, char transa, char transb, int64_t m, int64_
     const int smax = (prec && prec->smax) ? prec->smax : kDefaultSmax;
     if (tol && (smax < 1 || smax > OZ_MAX_SLICES)) return 14;
     if (use_3m(is_complex, prec, tol, false, m, n, k)) {
-        *bytes = make_plan3(m, n, k, s).total;
+        *bytes = make_plan3(m, n, k, tol ? smax : s, tol).total;
         return OZ_OK;
     }
     *bytes = make_plan(is_complex ? 1 : 0, m, n, k, tol ? smax : s, tol).total;

@@ -264,6 +264,36 @@ struct OpY1 {
     }
 };
 
+// 3-real-product form: y1 = sum_j C_ij t_j with C_ij = (T1 - T2) + i ((T3 - T1)
+// - T2), T_q = ldexp(acc_q, E_q,i + F_q,j) (real layout), each difference
+// rounded as in the combining epilogue; NaN where a scale marks Inf/NaN input
+struct RowY13 {
+    int64_t i;
+    int32_t e[3];
+};
+struct OpY1z3 {
+    const double* acc[3];
+    int64_t Mp;
+    const int32_t* EA[3];
+    const int32_t* FB[3];
+    const double* t;
+    __device__ RowY13 row(int64_t i) const { return {i, {EA[0][i], EA[1][i], EA[2][i]}}; }
+    __device__ void add(DC& a, const RowY13& r, int64_t j) const {
+        double T[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int32_t f = FB[q][j];
+            T[q] = (r.e[q] == kNonFiniteExp || f == kNonFiniteExp) ? __longlong_as_double(0x7ff8000000000000ll)
+                                                                    : ldexp(acc[q][j * Mp + r.i], r.e[q] + f);
+        }
+        const double cr = T[0] - T[1];
+        const double ci = (T[2] - T[0]) - T[1];
+        const double tj = t[j];
+        a.re = dd_add_prod(a.re, cr, tj);
+        a.im = dd_add_prod(a.im, ci, tj);
+    }
+};
+
 // sum over the terms of vector v of |x * 2^-E_v|^2 (the rule's statistic)
 struct RowMsq {
     int64_t v;
@@ -460,6 +490,43 @@ __device__ __forceinline__ void finalize_body(const double* acc, int64_t Mp, con
     }
 }
 
+// ---- the 3-real-product form: combine the raw sums of T1, T2, T3 into C ----
+struct Final3 {
+    const double* acc[3];
+    int64_t Mp;
+    const int32_t* EA[3];
+    const int32_t* FB[3];
+    double* C;
+    int64_t ldc, m, n;
+    double ar, ai, br, bi;
+    int beta_zero;
+};
+
+__global__ void finalize3_kernel(Final3 f) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= f.m) return;
+    const double nan = __longlong_as_double(0x7ff8000000000000ll);
+    const int32_t e0 = f.EA[0][i], e1 = f.EA[1][i], e2 = f.EA[2][i];
+    for (int64_t j = blockIdx.y; j < f.n; j += gridDim.y) {
+        const int32_t g0 = f.FB[0][j], g1 = f.FB[1][j], g2 = f.FB[2][j];
+        const double T1 = (e0 == kNonFiniteExp || g0 == kNonFiniteExp) ? nan : ldexp(f.acc[0][j * f.Mp + i], e0 + g0);
+        const double T2 = (e1 == kNonFiniteExp || g1 == kNonFiniteExp) ? nan : ldexp(f.acc[1][j * f.Mp + i], e1 + g1);
+        const double T3 = (e2 == kNonFiniteExp || g2 == kNonFiniteExp) ? nan : ldexp(f.acc[2][j * f.Mp + i], e2 + g2);
+        const double cr = T1 - T2;
+        const double ci = (T3 - T1) - T2;
+        double* c = f.C + 2 * (i + j * f.ldc);
+        double outr = f.ar * cr - f.ai * ci;
+        double outi = f.ar * ci + f.ai * cr;
+        if (!f.beta_zero) {
+            const double c0 = c[0], c1 = c[1];
+            outr = outr + (f.br * c0 - f.bi * c1);
+            outi = outi + (f.br * c1 + f.bi * c0);
+        }
+        c[0] = outr;
+        c[1] = outi;
+    }
+}
+
 // ---- kernels: one product -------------------------------------------------------
 __global__ void weights_kernel(CheckArgs c) { weights_body(c, static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x); }
 __global__ __launch_bounds__(256) void norms_kernel(const double* diff, const double* ref, int64_t len,
@@ -588,7 +655,14 @@ hipError_t launch_residual(const CheckArgs& c, hipStream_t st) {
     }
     // y1 over the n columns of the FP64 sums (part1), y2 over the k terms (part2)
     const RedSplit s1 = red_split(m, n, true), s2 = red_split(m, k, c.opa.sv == 1);
-    if (e == hipSuccess) e = launch_red(OpY1{c.acc, c.Mp, c.EA, c.FB, c.t, c.opa.cplx}, m, s1, p1, st);
+    if (e == hipSuccess) {
+        if (c.z3)
+            e = launch_red(OpY1z3{{c.acc3[0], c.acc3[1], c.acc3[2]}, c.Mp, {c.EA3[0], c.EA3[1], c.EA3[2]},
+                                  {c.FB3[0], c.FB3[1], c.FB3[2]}, c.t},
+                           m, s1, p1, st);
+        else
+            e = launch_red(OpY1{c.acc, c.Mp, c.EA, c.FB, c.t, c.opa.cplx}, m, s1, p1, st);
+    }
     if (e == hipSuccess) e = launch_red(OpY2{c.opa, c.u}, m, s2, p2, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(rows_combine_kernel, dim3(static_cast<unsigned>((m + 31) / 32)), dim3(256), 0, st, c, s1.nch,
@@ -605,6 +679,31 @@ hipError_t launch_finalize(const double* acc, int64_t Mp, const int32_t* EA, con
     dim3 grid(static_cast<unsigned>((m + 255) / 256), static_cast<unsigned>(n < 65535 ? n : 65535));
     hipLaunchKernelGGL(finalize_kernel, grid, dim3(256), 0, st, acc, Mp, EA, FB, C, ldc, m, n, cplx, ar, ai, br, bi,
                        beta_zero);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize3(const double* const* acc3, int64_t Mp, const int32_t* const* EA3,
+                            const int32_t* const* FB3, double* C, int64_t ldc, int64_t m, int64_t n, double ar,
+                            double ai, double br, double bi, int beta_zero, hipStream_t st) {
+    if (m <= 0 || n <= 0) return hipSuccess;
+    Final3 f;
+    for (int q = 0; q < 3; ++q) {
+        f.acc[q] = acc3[q];
+        f.EA[q] = EA3[q];
+        f.FB[q] = FB3[q];
+    }
+    f.Mp = Mp;
+    f.C = C;
+    f.ldc = ldc;
+    f.m = m;
+    f.n = n;
+    f.ar = ar;
+    f.ai = ai;
+    f.br = br;
+    f.bi = bi;
+    f.beta_zero = beta_zero;
+    dim3 grid(static_cast<unsigned>((m + 255) / 256), static_cast<unsigned>(n < 65535 ? n : 65535));
+    hipLaunchKernelGGL(finalize3_kernel, grid, dim3(256), 0, st, f);
     return hipGetLastError();
 }
 

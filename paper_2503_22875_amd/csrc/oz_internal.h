@@ -78,7 +78,10 @@ struct Split3Out {
     int8_t* slices[3];
 };
 hipError_t launch_scan3(const OperandView& op, const Split3Out& o, hipStream_t st);
-hipError_t launch_digits3(const OperandView& op, const SliceLayout& lay, const Split3Out& o, hipStream_t st);
+// Digit planes p_lo .. p_hi - 1 of every part (p_hi < 0: all planes of the
+// layout; balanced digits: all planes only).
+hipError_t launch_digits3(const OperandView& op, const SliceLayout& lay, const Split3Out& o, hipStream_t st,
+                          int p_lo = 0, int p_hi = -1);
 // Batched three-part split: one block per item (operand op of the list, block
 // coordinates as in the one-operand launches; digits3_blocks gives the grid).
 struct Split3Op {
@@ -221,11 +224,24 @@ struct CheckArgs {
     double* norms;             // 2      : sum diff^2, sum ref^2
     double* part1;             // check_part_bytes: per-chunk partial sums (single product)
     double* part2;
+    // 3-real-product form (z3 = 1, single product): C_emu is formed from the
+    // raw sums and scales of T1, T2, T3 (real layout, rows_pad Mp) as
+    // (T1 - T2) + i ((T3 - T1) - T2); acc, EA and FB are then unused
+    int z3 = 0;
+    const double* acc3[3] = {nullptr, nullptr, nullptr};
+    const int32_t* EA3[3] = {nullptr, nullptr, nullptr};
+    const int32_t* FB3[3] = {nullptr, nullptr, nullptr};
 };
 hipError_t launch_residual(const CheckArgs& c, hipStream_t st);
 hipError_t launch_finalize(const double* acc, int64_t Mp, const int32_t* EA, const int32_t* FB, double* C,
                            int64_t ldc, int64_t m, int64_t n, int cplx, double ar, double ai, double br, double bi,
                            int beta_zero, hipStream_t st);
+// The 3-real-product form: C = alpha ((T1 - T2) + i ((T3 - T1) - T2)) + beta C
+// with T_q = ldexp(acc_q, E_q + F_q) (NaN where a scale marks Inf/NaN input),
+// the arithmetic of the combining GEMM epilogue.
+hipError_t launch_finalize3(const double* const* acc3, int64_t Mp, const int32_t* const* EA3,
+                            const int32_t* const* FB3, double* C, int64_t ldc, int64_t m, int64_t n, double ar,
+                            double ai, double br, double bi, int beta_zero, hipStream_t st);
 // Many products: items of the weights (256 columns of op(B) per block), gemv
 // (64 terms) and rows (64 rows of op(A)) phases name the product (op) and the
 // block (bx); the norms phase runs one block per product.  Products whose

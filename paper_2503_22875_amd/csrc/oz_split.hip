@@ -601,7 +601,10 @@ __global__ __launch_bounds__(256) void scan3_kernel(OperandView op, Split3Out o,
 // of a load touch its own 128-byte line).
 template <bool LCONTIG, bool BAL>
 __device__ __forceinline__ void digits3_body(const OperandView& op, const SliceLayout& lay, const Split3Out& o,
-                                             int64_t bx, int64_t by) {
+                                             int64_t bx, int64_t by, int p_lo = 0, int p_hi = -1) {
+    // truncated digits: planes p_lo .. p_hi - 1 (all with p_hi < 0); balanced
+    // digits depend on s and are written all at once
+    if (p_hi < 0) p_hi = lay.s;
     constexpr int kStagePad = 33;  // 16-byte entries per staged vector: 32 elements + 1 to spread LDS banks
     __shared__ double2 stage[LCONTIG ? 64 * kStagePad : 1];
     if constexpr (LCONTIG) {
@@ -678,7 +681,7 @@ __device__ __forceinline__ void digits3_body(const OperandView& op, const SliceL
         uint64_t w[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) w[e] = frac_window(sig_of(x[e], ex[q]));
-        for (int p = 0; p < lay.s; ++p) {
+        for (int p = p_lo; p < p_hi; ++p) {
             int d[8];
 #pragma unroll
             for (int e = 0; e < 8; ++e) d[e] = digit_of(x[e], ex[q], w[e], p + 1);
@@ -688,8 +691,9 @@ __device__ __forceinline__ void digits3_body(const OperandView& op, const SliceL
 }
 
 template <bool LCONTIG, bool BAL>
-__global__ __launch_bounds__(256) void digits3_kernel(OperandView op, SliceLayout lay, Split3Out o) {
-    digits3_body<LCONTIG, BAL>(op, lay, o, blockIdx.x, blockIdx.y);
+__global__ __launch_bounds__(256) void digits3_kernel(OperandView op, SliceLayout lay, Split3Out o, int p_lo,
+                                                      int p_hi) {
+    digits3_body<LCONTIG, BAL>(op, lay, o, blockIdx.x, blockIdx.y, p_lo, p_hi);
 }
 
 // Batched three-part split: block b runs item b (operand, block coordinates).
@@ -730,14 +734,21 @@ hipError_t launch_scan3(const OperandView& op, const Split3Out& o, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t launch_digits3(const OperandView& op, const SliceLayout& lay, const Split3Out& o, hipStream_t st) {
+hipError_t launch_digits3(const OperandView& op, const SliceLayout& lay, const Split3Out& o, hipStream_t st, int p_lo,
+                          int p_hi) {
+    if (p_hi < 0) p_hi = lay.s;
+    if (p_lo < 0 || p_hi > lay.s || p_lo > p_hi) return hipErrorInvalidValue;
+    if (lay.bal && (p_lo != 0 || p_hi != lay.s)) return hipErrorInvalidValue;  // balanced: all planes at once
+    if (p_lo == p_hi) return hipSuccess;
     dim3 grid(static_cast<unsigned>(lay.kpad / kStep), static_cast<unsigned>((lay.rows_pad + 63) / 64));
     if (lay.bal) {
-        if (op.sl == 1) hipLaunchKernelGGL((digits3_kernel<true, true>), grid, dim3(256), 0, st, op, lay, o);
-        else hipLaunchKernelGGL((digits3_kernel<false, true>), grid, dim3(256), 0, st, op, lay, o);
+        if (op.sl == 1) hipLaunchKernelGGL((digits3_kernel<true, true>), grid, dim3(256), 0, st, op, lay, o, p_lo, p_hi);
+        else hipLaunchKernelGGL((digits3_kernel<false, true>), grid, dim3(256), 0, st, op, lay, o, p_lo, p_hi);
     } else {
-        if (op.sl == 1) hipLaunchKernelGGL((digits3_kernel<true, false>), grid, dim3(256), 0, st, op, lay, o);
-        else hipLaunchKernelGGL((digits3_kernel<false, false>), grid, dim3(256), 0, st, op, lay, o);
+        if (op.sl == 1)
+            hipLaunchKernelGGL((digits3_kernel<true, false>), grid, dim3(256), 0, st, op, lay, o, p_lo, p_hi);
+        else
+            hipLaunchKernelGGL((digits3_kernel<false, false>), grid, dim3(256), 0, st, op, lay, o, p_lo, p_hi);
     }
     return hipGetLastError();
 }

@@ -423,7 +423,8 @@ def test_batched_argument_errors(oz, handle):
     assert oz.oz_zgemm_batched(handle, check=False, p=oz.prec(9, zmode=3), **base) == 14
     assert oz.oz_zgemm_batched(handle, check=False, p=oz.prec(0, tol=1e-10, zmode=3), **base) == 14
     assert oz.oz_zgemm_batched(handle, check=False, p=oz.prec(8, zmode=3), **base) == 0
-    st = oz.oz_zgemm(handle, "N", "N", 4, 4, 4, 1.0, d, 4, d, 4, 0.0, d, 4, oz.prec(0, tol=1e-10, zmode=3),
+    # a single tolerance-driven 3M call: truncated digits only
+    st = oz.oz_zgemm(handle, "N", "N", 4, 4, 4, 1.0, d, 4, d, 4, 0.0, d, 4, oz.prec(0, tol=1e-10, zmode=3, digits=1),
                      check=False)
     assert st == 14
     # balanced digits: fixed slice counts up to 8 only

@@ -461,6 +461,79 @@ def test_growth_on_two_tile_waves(oz, handle, kernel, cplx, beta):
     assert np.array_equal(got, want)
 
 
+TOL3_CASES = [("rowexp", 1e-10), ("rowexp", 1e-14), ("uniform", 1e-6), ("spread30", 1e-12)]
+
+
+def tol3_inputs(kind, seed=0):
+    """Complex operands: the row-exponent case, or real and imaginary parts
+    drawn as two independent real cases."""
+    if kind == "rowexp":
+        return tol_inputs("rowexp", 1, seed)
+    Ar, Br = tol_inputs(kind, 0, seed)
+    Ai, Bi = tol_inputs(kind, 0, seed + 100)
+    return np.asfortranarray(Ar + 1j * Ai), np.asfortranarray(Br + 1j * Bi)
+
+
+@pytest.mark.parametrize("kind,tol", TOL3_CASES)
+def test_tolerance_mode_3m_meets_tol_and_matches_oracle(oz, handle, kind, tol):
+    # the 3-real-product form driven by a tolerance: start from the rule, the
+    # check on the combined result, growth of all three products; bit-exact
+    # against the oracle's incremental 3M order, the true error within tol
+    A, B = tol3_inputs(kind)
+    m, k = A.shape
+    n = B.shape[1]
+    dA, lda = to_dev(A)
+    dB, ldb = to_dev(B)
+    dC, ldc = to_dev(np.zeros((m, n), np.complex128, order="F"))
+    print("tol3 %s %g" % (kind, tol), flush=True)
+    st, rep = oz.oz_zgemm(handle, "N", "N", m, n, k, 1.0, dA, lda, dB, ldb, 0.0, dC, ldc,
+                          oz.prec(0, tol=tol, zmode=3), report=True)
+    assert st == 0 and rep.status == 0 and rep.zmode_used == 3
+    s1, s0 = rep.slices_used, rep.slices_used - rep.fallbacks
+    print("tol3 %s %g: start %d, used %d, resid %.3g" % (kind, tol, s0, s1, rep.resid_est))
+    got = from_dev(dC, m, n, ldc)
+    want = oracle.emu_zgemm3("N", "N", A, B, s0, s_to=s1, kc=oracle.kchunk(12))
+    assert np.array_equal(got, want)
+    ref = oracle.gemm_dd("N", "N", A, B)
+    wa, wb = scale_weights(A, B)
+    err = oracle.weighted_error(got, ref, wa, wb)
+    assert err <= tol, (err, tol)
+    assert err / 3 <= rep.resid_est <= 3 * err + 1e-17
+    if s1 < 12:
+        assert rep.resid_est <= tol / 2
+
+
+@pytest.mark.parametrize("beta", [0.0, 0.5 - 0.75j])
+def test_tolerance_mode_3m_growth_from_low_start(oz, handle, beta):
+    A, B = tol_inputs("rowexp", 1, seed=4)
+    m, k = A.shape
+    n = B.shape[1]
+    rng = np.random.default_rng(12)
+    C0 = wide(rng, (m, n), 4, True)
+    dA, lda = to_dev(A)
+    dB, ldb = to_dev(B)
+    dC, ldc = to_dev(C0)
+    print("tol3 growth beta=%s" % beta, flush=True)
+    st, rep = oz.oz_zgemm(handle, "N", "N", m, n, k, 0.75 + 0.5j, dA, lda, dB, ldb, beta, dC, ldc,
+                          oz.prec(0, tol=1e-13, sstart=2, zmode=3), report=True)
+    assert st == 0 and rep.fallbacks >= 3 and rep.slices_used == 2 + rep.fallbacks
+    want = oracle.emu_zgemm3("N", "N", A, B, 2, s_to=rep.slices_used, kc=oracle.kchunk(12), alpha=0.75 + 0.5j,
+                             beta=beta, C=C0)
+    assert np.array_equal(from_dev(dC, m, n, ldc), want)
+
+
+def test_tolerance_mode_3m_arguments(oz, handle):
+    d = torch.zeros(16, dtype=torch.complex128, device="cuda")
+    # balanced digits do not grow incrementally: not in the 3-product form
+    st = oz.oz_zgemm(handle, "N", "N", 4, 4, 4, 1.0, d, 4, d, 4, 0.0, d, 4,
+                     oz.prec(0, tol=1e-10, zmode=3, digits=1), check=False)
+    assert st == 14
+    # the workspace query matches the call's plan
+    p = oz.prec(0, tol=1e-10, zmode=3)
+    assert oz.oz_workspace_size(handle, "N", "N", 300, 200, 100, 1, p) > \
+        oz.oz_workspace_size(handle, "N", "N", 300, 200, 100, 1, oz.prec(6, zmode=3))
+
+
 def test_growth_past_eight_slices_uses_streaming_kernel(oz, handle):
     # tolerance below what 8 slices reach on wide data: the growth goes on with the streaming kernel
     A, B = tol_inputs("wide", 0, seed=4)

@@ -254,6 +254,12 @@ def test_learned_start_in_tolerance_mode(oz, handle):
         assert rep.slices_used - rep.fallbacks == 4
         want = oracle.emu_gemm("N", "N", Az, Bz, 4, s_to=rep.slices_used, kc=oracle.kchunk(12, True))
         assert np.array_equal(from_dev(dC, 36, 40, ldc), want)
+        # and in the 3-real-product form
+        st, rep = oz.oz_zgemm(handle, "N", "N", 36, 40, 52, 1.0, dA, lda, dB, ldb, 0.0, dC, ldc,
+                              oz.prec(0, tol=1e-9, selector=1, zmode=3), report=True)
+        assert rep.slices_used - rep.fallbacks == 4 and rep.zmode_used == 3
+        want = oracle.emu_zgemm3("N", "N", Az, Bz, 4, s_to=rep.slices_used, kc=oracle.kchunk(12))
+        assert np.array_equal(from_dev(dC, 36, 40, ldc), want)
     finally:
         oz.oz_set_selector(handle, None)
         oz.oz_mlp_destroy(net)

@@ -522,3 +522,34 @@ def test_3m_error_decays_and_stays_near_4m():
             assert 2 ** 5 < prev / e3 < 2 ** 8.5, s        # about 2^6.6 per slice (Table 1)
         prev = e3
     assert prev < 1e-12
+
+
+@pytest.mark.parametrize("s0,s1", [(2, 5), (4, 7)])
+def test_3m_growth_matches_fresh_run_up_to_rounding(s0, s1):
+    """The 3-product form grown from s0 to s1 (each real product by its top
+    anti-diagonals, combined once): no growth is the plain form; each real
+    product differs from a fresh s1 run only by the order of the same exact
+    terms, (s1 + 1) u K 2^(E+F) at most, and the combine's two differences
+    add those bounds plus their own roundings; the error falls with s."""
+    rng = np.random.default_rng(70 + s0)
+    A = rand_cwide(rng, (9, 40), 8)
+    B = rand_cwide(rng, (40, 8), 8)
+    assert np.array_equal(oracle.emu_zgemm3("N", "N", A, B, s0, s_to=s0), oracle.emu_zgemm3("N", "N", A, B, s0))
+    grown = oracle.emu_zgemm3("N", "N", A, B, s0, s_to=s1)
+    fresh = oracle.emu_zgemm3("N", "N", A, B, s1)
+    parts_a = [A.real, A.imag, A.real + A.imag]
+    parts_b = [B.real, B.imag, B.real + B.imag]
+    bnd = []
+    for pa, pb in zip(parts_a, parts_b):
+        E, _ = oracle.split("A", "N", np.asfortranarray(pa), 1)
+        F, _ = oracle.split("B", "N", np.asfortranarray(pb), 1)
+        bnd.append((s1 + 1) * U * 40 * np.exp2(E[:, None] + F[None, :].astype(float)))
+    mag = np.abs(fresh.real) + np.abs(fresh.imag)
+    assert np.all(np.abs(grown.real - fresh.real) <= bnd[0] + bnd[1] + 4 * U * mag + 1e-300)
+    assert np.all(np.abs(grown.imag - fresh.imag) <= bnd[0] + bnd[1] + bnd[2] + 8 * U * mag + 1e-300)
+    ref = oracle.gemm_dd("N", "N", A, B)
+    wa = np.maximum(np.abs(A.real), np.abs(A.imag)).max(1)
+    wb = np.maximum(np.abs(B.real), np.abs(B.imag)).max(0)
+    e0 = oracle.weighted_error(oracle.emu_zgemm3("N", "N", A, B, s0), ref, wa, wb)
+    e1 = oracle.weighted_error(grown, ref, wa, wb)
+    assert e1 < e0 * 2.0 ** (-5 * (s1 - s0)) or e1 < 1e-15
