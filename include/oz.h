@@ -469,8 +469,10 @@ int oz_predict_slices(oz_handle_t handle, char transa, char transb, int64_t m, i
  *  kind 1: FP64 matrix cores, v_mfma_f64_16x16x4_f64 -> flops per second;
  *  kind 2: device copy of `bytes` (a multiple of 16) from src to dst (device
  *          buffers of the caller), iters repetitions -> bytes read plus bytes
- *          written per second.
- * src, dst and bytes are ignored for kinds 0 and 1.  OZ_ERR_ARG for a bad
+ *          written per second;
+ *  kind 3: INT8 matrix cores in the 16 x 16 x 64 shape,
+ *          v_mfma_i32_16x16x64_i8 -> ops per second.
+ * src, dst and bytes are ignored for kinds 0, 1 and 3.  OZ_ERR_ARG for a bad
  * kind, iters < 1, a NULL rate, or a bad copy buffer. */
 int oz_peak(oz_handle_t handle, int kind, int64_t iters, const void* src, void* dst, size_t bytes, double* rate);
 

@@ -3,9 +3,12 @@
 // matrix-core throughput (what a native DGEMM / ZGEMM runs on), and HBM copy
 // bandwidth (what the split and epilogue passes stream through).
 //
-// The MFMA kernels keep kChains independent accumulators per wave and issue
+// The MFMA kernels (INT8 in the 32 x 32 x 32 shape the slice GEMM uses and in
+// the 16 x 16 x 64 shape) keep kChains independent accumulators per wave and issue
 // the instruction round-robin over them, so consecutive instructions never
-// depend on each other and the matrix pipe stays fed; two waves per SIMD.
+// depend on each other and one wave keeps its SIMD's matrix pipe fed (the
+// 32 x 32 x 32 kernel's 8 chains take 128 accumulator registers, so one wave
+// per SIMD is resident and the second block per CU runs after the first).
 // The operands come from the lane index (not foldable), and every
 // accumulator feeds one value stored per lane, so nothing is dead code.
 #include <hip/hip_runtime.h>
@@ -22,7 +25,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int kChains = 8;
 constexpr int kPeakThreads = 256;  // 4 waves per block
-constexpr int kBlocksPerCu = 2;    // 8 waves per compute unit, 2 per SIMD
+constexpr int kBlocksPerCu = 2;    // 8 waves per compute unit
 
 __global__ __launch_bounds__(kPeakThreads) void peak_i8_kernel(int64_t iters, int* out) {
     const int lane = threadIdx.x & 63;
@@ -45,6 +48,32 @@ __global__ __launch_bounds__(kPeakThreads) void peak_i8_kernel(int64_t iters, in
     for (int c = 0; c < kChains; ++c)
 #pragma unroll
         for (int r = 0; r < 16; ++r) sum += acc[c][r];
+    out[blockIdx.x * kPeakThreads + threadIdx.x] = sum;
+}
+
+// the 16 x 16 x 64 INT8 shape: 4 lanes' 16 bytes form a 64-term row, 4 INT32
+// results per lane
+__global__ __launch_bounds__(kPeakThreads) void peak_i8_16_kernel(int64_t iters, int* out) {
+    const int lane = threadIdx.x & 63;
+    v4i a, b;
+    for (int r = 0; r < 4; ++r) {
+        a[r] = (lane * 0x01030507 + r) & 0x3f3f3f3f;
+        b[r] = (lane * 0x07050301 + 3 * r) & 0x3f3f3f3f;
+    }
+    v4i acc[kChains];
+#pragma unroll
+    for (int c = 0; c < kChains; ++c)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[c][r] = 0;
+    for (int64_t it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int c = 0; c < kChains; ++c) acc[c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, acc[c], 0, 0, 0);
+    }
+    int sum = 0;
+#pragma unroll
+    for (int c = 0; c < kChains; ++c)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sum += acc[c][r];
     out[blockIdx.x * kPeakThreads + threadIdx.x] = sum;
 }
 
@@ -81,7 +110,7 @@ extern "C" {
 
 int oz_peak(oz_handle_t h, int kind, int64_t iters, const void* src, void* dst, size_t bytes, double* rate) {
     if (!oz_handle_valid(h)) return OZ_ERR_HANDLE;
-    if (kind < 0 || kind > 2 || iters < 1 || !rate) return OZ_ERR_ARG;
+    if (kind < 0 || kind > 3 || iters < 1 || !rate) return OZ_ERR_ARG;
     if (kind == 2 && (!src || !dst || bytes == 0 || bytes % 16 != 0)) return OZ_ERR_ARG;
     if (oz_handle_use_device(h)) return OZ_ERR_HIP;
     hipStream_t st = oz_handle_stream(h);
@@ -96,6 +125,9 @@ int oz_peak(oz_handle_t h, int kind, int64_t iters, const void* src, void* dst, 
     auto launch = [&](int64_t n) {
         if (kind == 0)
             hipLaunchKernelGGL(peak_i8_kernel, dim3(blocks), dim3(kPeakThreads), 0, st, n, static_cast<int*>(out));
+        else if (kind == 3)
+            hipLaunchKernelGGL(peak_i8_16_kernel, dim3(blocks), dim3(kPeakThreads), 0, st, n,
+                               static_cast<int*>(out));
         else if (kind == 1)
             hipLaunchKernelGGL(peak_f64_kernel, dim3(blocks), dim3(kPeakThreads), 0, st, n, static_cast<double*>(out));
         else
@@ -116,6 +148,7 @@ int oz_peak(oz_handle_t h, int kind, int64_t iters, const void* src, void* dst, 
         const double waves = static_cast<double>(blocks) * (kPeakThreads / 64);
         double work;
         if (kind == 0) work = waves * iters * kChains * (32.0 * 32.0 * 32.0 * 2.0);
+        else if (kind == 3) work = waves * iters * kChains * (16.0 * 16.0 * 64.0 * 2.0);
         else if (kind == 1) work = waves * iters * kChains * (16.0 * 16.0 * 4.0 * 2.0);
         else work = 2.0 * static_cast<double>(bytes) * iters;
         *rate = ms > 0.f ? work / (ms * 1e-3) : 0.0;
