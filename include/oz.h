@@ -525,7 +525,7 @@ int oz_batch_destroy(oz_batch_t plan);
  * (sstart, or one batched statistics pass and the rule or the handle's
  * learned selector); the split of digit planes 1..s; raw sums at those s
  * (every problem with s <= 8 in one mixed-s persistent launch, those with
- * 9 <= s <= 14 in one wide launch on a second stream beside it, streaming
+ * 9 <= s <= 14 in wide launches on a second stream beside it, streaming
  * launches above); then rounds of a batched residual check over the problems
  * still open, and for those whose estimate exceeds tol/2 the slices the
  * single call would add (new digit planes, then one anti-diagonal at a time,

@@ -256,7 +256,8 @@ hipError_t launch_group(const Group& gr, const oz::GemmArgs* dargs, const oz::Ti
     switch (gr.tile) {
         case kStream: return oz::launch_gemm_stream_persistent(dargs, items, gr.nitems, gr.s, top, gr.blocks, st);
         case kMixed: return oz::launch_gemm_persistent_mixed(dargs, items, gr.nitems, gr.blocks, top, gr.multi, st);
-        case kWide: return oz::launch_gemm_wide_persistent(dargs, items, gr.nitems, gr.blocks, top, gr.multi, st);
+        case kWide:
+            return oz::launch_gemm_wide_persistent(dargs, items, gr.nitems, gr.blocks, top, gr.multi, gr.s, st);
         case kFused3: return oz::launch_gemm_persistent_3m(dargs, items, gr.nitems, gr.blocks, false, st);
         case kFused3W: return oz::launch_gemm_persistent_3m(dargs, items, gr.nitems, gr.blocks, true, st);
         default:
@@ -297,9 +298,9 @@ hipError_t launch_groups(oz_batch_t P, const std::vector<Group>& groups, const o
 
 // Groups of one GEMM round over `members` (slice counts s_of(i)): every
 // problem with s <= 8 in one mixed 64 x 64 launch (or, with a single such s,
-// the tuned block shape for it), every problem with s in 9..14 in one wide
-// launch (several INT32 chunks at s >= 13 excepted), one streaming launch per
-// remaining s.
+// the tuned block shape for it), every problem with s in 9..14 in one or two
+// wide launches (several INT32 chunks at s >= 13 excepted), one streaming
+// launch per remaining s.
 template <class SOf>
 void round_groups(const std::vector<oz::GemmArgs>& args, const std::vector<size_t>& members, SOf s_of, int kernel,
                   int cplx, int cus, const std::vector<oz::TuneEntry>& tune, std::vector<Group>* groups,
@@ -332,8 +333,15 @@ void round_groups(const std::vector<oz::GemmArgs>& args, const std::vector<size_
         groups->push_back(gr);
         items->push_back(std::move(it));
     };
-    // the longest tiles first: their launch runs beside the others (second stream)
-    if (!wide.empty()) add(wide, 0, kWide);
+    // the longest tiles first: their launches run beside the others (second
+    // stream), one per slice range that the wide kernel holds without spills
+    // (group s = the range's top: 9..12 and 13..14 with one INT32 chunk, 9..11
+    // and 12 with several)
+    const int wide_lo_top = wide_multi ? 11 : 12;
+    std::vector<size_t> wide_lo, wide_hi;
+    for (size_t i : wide) (s_of(i) <= wide_lo_top ? wide_lo : wide_hi).push_back(i);
+    if (!wide_lo.empty()) add(wide_lo, wide_lo_top, kWide);
+    if (!wide_hi.empty()) add(wide_hi, wide_multi ? 12 : oz::kMaxWideSlices, kWide);
     std::sort(streamvals.begin(), streamvals.end());
     for (int sv : streamvals) {
         std::vector<size_t> mem;

@@ -544,29 +544,29 @@ gemm_persistent_mixed_kernel(const GemmArgs* __restrict__ probs, const TileItem*
 
 // Persistent form of the wide all-diagonal tile (9 <= s <= kMaxWideSlices, one
 // wave per SIMD), for batched problems above the 2-waves-per-SIMD budget; like
-// the mixed form, each tile runs at its own problem's s (one launch for every
-// s in 9..14).  Several INT32 chunks at s >= 13 would spill: those problems
-// take the streaming body instead (MULTI launches see s <= 12 only).
-template <bool TOP, bool MULTI>
+// the mixed form, each tile runs at its own problem's s, within the launch's
+// range LO..HI.  The ranges are what one function holds without spilling
+// (measured): 9..12 and 13..14 with one INT32 chunk, 9..11 and 12 with several
+// (several chunks at s >= 13 take the streaming body).  A single instance over
+// 9..14 spilled 63 registers to scratch.
+template <int K, int HI, bool TOP, bool MULTI>
+__device__ __forceinline__ void wide_tile(int s, const GemmArgs& g, const TileItem& ti, v4i* lds) {
+    if constexpr (K < HI) {
+        if (s == K) mixed_tile<K, TOP, MULTI>(g, ti, lds);
+        else wide_tile<K + 1, HI, TOP, MULTI>(s, g, ti, lds);
+    } else {
+        mixed_tile<HI, TOP, MULTI>(g, ti, lds);
+    }
+}
+
+template <bool TOP, bool MULTI, int LO, int HI>
 __global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(1, 1))) void
 gemm_wide_persistent_kernel(const GemmArgs* __restrict__ probs, const TileItem* __restrict__ items, int64_t nitems) {
-    __shared__ v4i lds[2 * TileCfg<kMaxWideSlices, 2, 2, 2>::STAGE];
+    __shared__ v4i lds[2 * TileCfg<HI, 2, 2, 2>::STAGE];
     for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
         const TileItem ti = items[it];
         if (ti.prob < 0) continue;
-        const GemmArgs& g = probs[ti.prob];
-        switch (ti.s) {  // uniform over the block
-            case 9: mixed_tile<9, TOP, MULTI>(g, ti, lds); break;
-            case 10: mixed_tile<10, TOP, MULTI>(g, ti, lds); break;
-            case 11: mixed_tile<11, TOP, MULTI>(g, ti, lds); break;
-            case 12: mixed_tile<12, TOP, MULTI>(g, ti, lds); break;
-            case 13:
-                if constexpr (!MULTI) mixed_tile<13, TOP, false>(g, ti, lds);
-                break;
-            default:
-                if constexpr (!MULTI) mixed_tile<14, TOP, false>(g, ti, lds);
-                break;
-        }
+        wide_tile<LO, HI, TOP, MULTI>(ti.s, probs[ti.prob], ti, lds);  // ti.s uniform over the block
         __syncthreads();
     }
 }
@@ -1051,16 +1051,24 @@ hipError_t launch_gemm_persistent_3m(const GemmArgs* probs, const TileItem* item
 }
 
 hipError_t launch_gemm_wide_persistent(const GemmArgs* probs, const TileItem* items, int64_t nitems, int blocks,
-                                       bool top, bool multi, hipStream_t st) {
+                                       bool top, bool multi, int s_hi, hipStream_t st) {
     if (nitems <= 0) return hipSuccess;
     if (blocks <= 0) return hipErrorInvalidValue;
     dim3 grid(static_cast<unsigned>(blocks)), block(256);
-#define OZ_WIDEP(TOPV, MULTIV) \
-    hipLaunchKernelGGL((gemm_wide_persistent_kernel<TOPV, MULTIV>), grid, block, 0, st, probs, items, nitems)
-    if (top && multi) OZ_WIDEP(true, true);
-    else if (top) OZ_WIDEP(true, false);
-    else if (multi) OZ_WIDEP(false, true);
-    else OZ_WIDEP(false, false);
+#define OZ_WIDEP(TOPV, MULTIV, LO, HI) \
+    hipLaunchKernelGGL((gemm_wide_persistent_kernel<TOPV, MULTIV, LO, HI>), grid, block, 0, st, probs, items, nitems)
+#define OZ_WIDEP_RANGES(TOPV)                         \
+    if (multi && s_hi == 11) OZ_WIDEP(TOPV, true, 9, 11); \
+    else if (multi && s_hi == 12) OZ_WIDEP(TOPV, true, 12, 12); \
+    else if (!multi && (s_hi == 11 || s_hi == 12)) OZ_WIDEP(TOPV, false, 9, 12); \
+    else if (!multi && s_hi == 14) OZ_WIDEP(TOPV, false, 13, 14); \
+    else return hipErrorInvalidValue;
+    if (top) {
+        OZ_WIDEP_RANGES(true)
+    } else {
+        OZ_WIDEP_RANGES(false)
+    }
+#undef OZ_WIDEP_RANGES
 #undef OZ_WIDEP
     return hipGetLastError();
 }

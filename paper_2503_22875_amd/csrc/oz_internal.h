@@ -195,9 +195,12 @@ hipError_t launch_gemm_persistent_3m(const GemmArgs* probs, const TileItem* item
                                      bool high, hipStream_t st);
 // Tiles of problems with 9 <= s <= kMaxWideSlices (each its own s, from the
 // tile item) on the wide all-diagonal tile (64 x 64, one block per compute
-// unit); with multi (several INT32 chunks) every s must be at most 12.
+// unit), over one slice range named by its top s_hi: without multi 9..12
+// (s_hi 11 or 12) or 13..14 (s_hi 14); with multi (several INT32 chunks)
+// 9..11 (s_hi 11) or 12 (s_hi 12).  Every tile's s must lie in the range.
+// Other s_hi: hipErrorInvalidValue.
 hipError_t launch_gemm_wide_persistent(const GemmArgs* probs, const TileItem* items, int64_t nitems, int blocks,
-                                       bool top, bool multi, hipStream_t st);
+                                       bool top, bool multi, int s_hi, hipStream_t st);
 
 // Tolerance-driven calls: operand statistics, residual check, final scaling.
 // Per-vector mean square of x * 2^-E (E from maxbits); part: scratch of

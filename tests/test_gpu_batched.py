@@ -224,9 +224,10 @@ def test_batched_3m_nonfinite_rows(oz, handle, stream):
 @pytest.mark.parametrize("use_plan,kchunk", [(False, 0), (True, 0), (False, 64)])
 def test_batched_bit_exact_wide_and_mixed(oz, handle, stream, cplx, use_plan, kchunk):
     # fixed slice counts 1..14 in one batch: s <= 8 share one mixed-s launch,
-    # s in 9..14 one wide launch (with several INT32 chunks, s = 13, 14 take
-    # the streaming body); ragged shapes, every transpose, beta on half of
-    # them; as a one-shot call, as a captured plan, and with 64-term chunks
+    # s in 9..12 and 13..14 one wide launch each (with several INT32 chunks:
+    # 9..11 and 12, and s = 13, 14 take the streaming body); ragged shapes,
+    # every transpose, beta on half of them; as a one-shot call, as a captured
+    # plan, and with 64-term chunks
     rng = np.random.default_rng(60 + cplx)
     shapes = [(70, 65, 33), (130, 70, 257), (64, 192, 64), (5, 300, 17), (200, 3, 90), (96, 96, 96), (33, 47, 2),
               (40, 30, 20), (129, 64, 65), (64, 129, 31), (1, 1, 1), (17, 250, 100), (88, 88, 200), (31, 33, 35)]
@@ -245,7 +246,7 @@ def test_batched_bit_exact_wide_and_mixed(oz, handle, stream, cplx, use_plan, kc
         try:
             launches, _, _, sl = oz.oz_batch_info(plan, len(probs))
             assert sl == slices
-            assert launches == 2  # one mixed launch for s <= 8, one wide launch for s in 9..14
+            assert launches == 3  # one mixed launch for s <= 8, wide launches for 9..12 and 13..14
             stream.synchronize()
             got = [from_dev(d[4], args["m"][i], args["n"][i], d[5]) for i, d in enumerate(dev)]
         finally:
