@@ -82,6 +82,12 @@ __device__ __forceinline__ dd dd_add(dd a, dd b) {
 }
 constexpr int kParts = 4;
 constexpr int kLanes = 64;
+// Terms per wave whose loads are issued before any of them is added: the
+// reductions below are chains of double-double additions, and one load
+// round trip per term left them latency-bound.
+constexpr int kBatch = 8;
+// an index past the end reads the last element (in bounds; its term is not added)
+__device__ __forceinline__ int64_t clamp_index(int64_t x, int64_t n) { return x < n ? x : n - 1; }
 
 __device__ __forceinline__ void gemv_b_body(const CheckArgs& c, int64_t lb) {
     __shared__ dd red[kParts][2][kLanes];
@@ -90,12 +96,21 @@ __device__ __forceinline__ void gemv_b_body(const CheckArgs& c, int64_t lb) {
     const int64_t l = lb * kLanes + lane;
     dd sr = {0.0, 0.0}, si = {0.0, 0.0};
     if (l < opb.k) {
-        for (int64_t j = part; j < opb.nv; j += kParts) {
-            double re, im;
-            load_elem(opb, j, l, re, im);
-            const double tj = c.t[j];
-            sr = dd_add_prod(sr, re, tj);
-            si = dd_add_prod(si, im, tj);
+        // kBatch columns' loads issued together, then added in column order
+        for (int64_t j0 = part; j0 < opb.nv; j0 += kParts * kBatch) {
+            double re[kBatch], im[kBatch], tj[kBatch];
+#pragma unroll
+            for (int q = 0; q < kBatch; ++q) {
+                const int64_t j = clamp_index(j0 + q * kParts, opb.nv);
+                load_elem(opb, j, l, re[q], im[q]);
+                tj[q] = c.t[j];
+            }
+#pragma unroll
+            for (int q = 0; q < kBatch; ++q) {
+                if (j0 + q * kParts >= opb.nv) break;
+                sr = dd_add_prod(sr, re[q], tj[q]);
+                si = dd_add_prod(si, im[q], tj[q]);
+            }
         }
     }
     red[part][0][lane] = sr;
@@ -119,7 +134,8 @@ __device__ __forceinline__ void gemv_b_body(const CheckArgs& c, int64_t lb) {
 // at 2i, 2i+1 for complex).  Block: 64 rows (lanes) x 4 parts (waves); part w
 // takes the terms l = w, w + 4, ... and the columns j = w, w + 4, ...; the
 // partial sums are added in part order.
-__device__ __forceinline__ void rows_body(const CheckArgs& c, int64_t rb) {
+template <bool CPLX>
+__device__ __forceinline__ void rows_body_t(const CheckArgs& c, int64_t rb) {
     __shared__ dd red[kParts][4][kLanes];
     const OperandView& opa = c.opa;
     const int lane = threadIdx.x & 63, part = threadIdx.x >> 6;
@@ -129,30 +145,53 @@ __device__ __forceinline__ void rows_body(const CheckArgs& c, int64_t rb) {
     dd y2r = {0.0, 0.0}, y2i = {0.0, 0.0}, y1r = {0.0, 0.0}, y1i = {0.0, 0.0};
     if (i < opa.nv) {
         // y2 = a_i . u  (complex: (ar + i ai)(ur + i ui))
-        for (int64_t l = part; l < opa.k; l += kParts) {
-            double ar, ai;
-            load_elem(opa, i, l, ar, ai);
-            const double urh = u[4 * l], url = u[4 * l + 1], uih = u[4 * l + 2], uil = u[4 * l + 3];
-            y2r = dd_add_prod(y2r, ar, urh);
-            y2r = dd_add_prod(y2r, ar, url);
-            if (opa.cplx) {
-                y2r = dd_add_prod(y2r, -ai, uih);
-                y2r = dd_add_prod(y2r, -ai, uil);
-                y2i = dd_add_prod(y2i, ar, uih);
-                y2i = dd_add_prod(y2i, ar, uil);
-                y2i = dd_add_prod(y2i, ai, urh);
-                y2i = dd_add_prod(y2i, ai, url);
+        for (int64_t l0 = part; l0 < opa.k; l0 += kParts * kBatch) {
+            double ar[kBatch], ai[kBatch], uu[kBatch][4];
+#pragma unroll
+            for (int q = 0; q < kBatch; ++q) {
+                const int64_t l = clamp_index(l0 + q * kParts, opa.k);
+                load_elem(opa, i, l, ar[q], ai[q]);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) uu[q][r] = u[4 * l + r];
+            }
+#pragma unroll
+            for (int q = 0; q < kBatch; ++q) {
+                if (l0 + q * kParts >= opa.k) break;
+                const double urh = uu[q][0], url = uu[q][1], uih = uu[q][2], uil = uu[q][3];
+                y2r = dd_add_prod(y2r, ar[q], urh);
+                y2r = dd_add_prod(y2r, ar[q], url);
+                if (CPLX) {
+                    y2r = dd_add_prod(y2r, -ai[q], uih);
+                    y2r = dd_add_prod(y2r, -ai[q], uil);
+                    y2i = dd_add_prod(y2i, ar[q], uih);
+                    y2i = dd_add_prod(y2i, ar[q], uil);
+                    y2i = dd_add_prod(y2i, ai[q], urh);
+                    y2i = dd_add_prod(y2i, ai[q], url);
+                }
             }
         }
         // y1 = sum_j ldexp(acc_ij, E_i + F_j) t_j over the slice-row(s) of row i
-        const int64_t r_re = opa.cplx ? 32 * (i >> 4) + 16 * ((i >> 3) & 1) + (i & 7) : i;
+        const int64_t r_re = CPLX ? 32 * (i >> 4) + 16 * ((i >> 3) & 1) + (i & 7) : i;
         const int64_t r_im = r_re + 8;
         const int32_t e = c.EA[i];
-        for (int64_t j = part; j < n; j += kParts) {
-            const int ef = e + c.FB[j];
-            const double tj = c.t[j];
-            y1r = dd_add_prod(y1r, ldexp(c.acc[j * Mp + r_re], ef), tj);
-            if (opa.cplx) y1i = dd_add_prod(y1i, ldexp(c.acc[j * Mp + r_im], ef), tj);
+        for (int64_t j0 = part; j0 < n; j0 += kParts * kBatch) {
+            int fb[kBatch];
+            double tj[kBatch], cr[kBatch], ci[kBatch];
+#pragma unroll
+            for (int q = 0; q < kBatch; ++q) {
+                const int64_t j = clamp_index(j0 + q * kParts, n);
+                fb[q] = c.FB[j];
+                tj[q] = c.t[j];
+                cr[q] = c.acc[j * Mp + r_re];
+                if (CPLX) ci[q] = c.acc[j * Mp + r_im];
+            }
+#pragma unroll
+            for (int q = 0; q < kBatch; ++q) {
+                if (j0 + q * kParts >= n) break;
+                const int ef = e + fb[q];
+                y1r = dd_add_prod(y1r, ldexp(cr[q], ef), tj[q]);
+                if (CPLX) y1i = dd_add_prod(y1i, ldexp(ci[q], ef), tj[q]);
+            }
         }
     }
     red[part][0][lane] = y1r;
@@ -171,7 +210,7 @@ __device__ __forceinline__ void rows_body(const CheckArgs& c, int64_t rb) {
     const double w = mx > 0.0 ? 1.0 / mx : 0.0;
     y1r = dd_mul_d(dd_norm(y1r), w);
     y2r = dd_mul_d(dd_norm(y2r), w);
-    if (!opa.cplx) {
+    if (!CPLX) {
         c.diff[i] = dd_sub_to_d(y1r, y2r);
         c.ref[i] = y2r.hi + y2r.lo;
     } else {
@@ -182,6 +221,10 @@ __device__ __forceinline__ void rows_body(const CheckArgs& c, int64_t rb) {
         c.ref[2 * i] = y2r.hi + y2r.lo;
         c.ref[2 * i + 1] = y2i.hi + y2i.lo;
     }
+}
+__device__ __forceinline__ void rows_body(const CheckArgs& c, int64_t rb) {
+    if (c.opa.cplx) rows_body_t<true>(c, rb);
+    else rows_body_t<false>(c, rb);
 }
 
 // ---- split reductions (single product) --------------------------------------

@@ -68,10 +68,25 @@ __global__ void gen_kernel(GenSide g) {
 }
 
 // ---- exponent statistics ---------------------------------------------------------
-__device__ __forceinline__ void stat_entry(double x, int E, uint32_t* lh, double& sq) {
+// The block's histogram is kept in kHistCopies copies, lane l adding to copy
+// l % kHistCopies: most entries of a vector share a few gap and width values,
+// and 64 lanes adding to one LDS word serialise (one lane per clock), which
+// held the pass to a third of the HBM rate.  Copy c starts kHistLen words
+// after copy c - 1 (kHistLen = 1 mod 32), so one bin lies in a different bank
+// in every copy.
+constexpr int kHistCopies = 16;
+static_assert(kHistLen % 32 == 1 && (kHistCopies & (kHistCopies - 1)) == 0, "histogram copy layout");
+__device__ __forceinline__ void lane_hist_add(uint32_t* h, int bin) {
+    if (bin >= 0) atomicAdd(&h[(threadIdx.x & (kHistCopies - 1)) * kHistLen + bin], 1u);
+}
+
+// One entry: its gap bin and width bin (the zero bin and -1 for a zero), and
+// its term of the mean square.
+__device__ __forceinline__ void stat_entry(double x, int E, int& gbin, int& wbin, double& sq) {
     const uint64_t b = static_cast<uint64_t>(__double_as_longlong(x)) & kMagMask;
     if (b == 0) {
-        atomicAdd(&lh[2 * kHistBins], 1u);
+        gbin = 2 * kHistBins;
+        wbin = -1;
         return;
     }
     const int eb = static_cast<int>(b >> 52);
@@ -79,27 +94,45 @@ __device__ __forceinline__ void stat_entry(double x, int E, uint32_t* lh, double
     const int bl = 64 - __clzll(static_cast<long long>(M));
     const int ex = eb ? eb - 1022 : bl - 1074;          // frexp exponent of x
     const int tz = __builtin_ctzll(M);
-    int gap = E - ex;
-    int wid = gap + bl - tz;
-    gap = gap < kHistCap ? gap : kHistCap;
-    wid = wid < kHistCap ? wid : kHistCap;
-    atomicAdd(&lh[gap], 1u);
-    atomicAdd(&lh[kHistBins + wid], 1u);
+    const int gap = E - ex;
+    const int wid = gap + bl - tz;
+    gbin = gap < kHistCap ? gap : kHistCap;
+    wbin = kHistBins + (wid < kHistCap ? wid : kHistCap);
     const double y = ldexp(x, -E);
     sq += y * y;
 }
+
+// Histogram counts and mean-square terms of one entry per active lane (CPLX:
+// the two parts), from values already loaded.
+template <bool CPLX>
+__device__ __forceinline__ void stat_terms(double re, double im, int E, uint32_t* lh, double& sq) {
+    int g0, w0;
+    stat_entry(re, E, g0, w0, sq);
+    lane_hist_add(lh, g0);
+    lane_hist_add(lh, w0);
+    if (CPLX) {
+        int g1, w1;
+        stat_entry(im, E, g1, w1, sq);
+        lane_hist_add(lh, g1);
+        lane_hist_add(lh, w1);
+    }
+}
+
+// Terms per lane whose loads are issued before any of them is processed (one
+// load round trip per term left the pass latency-bound).
+constexpr int kStatBatch = 8;
 
 // One block: 64 vectors, all their terms.
 // LCONTIG (terms contiguous): each wave walks 16 vectors, lanes along terms,
 //   per-vector sums by a fixed butterfly.
 // else (vectors contiguous): lane = vector, the 4 waves split the terms,
 //   partial sums combined through LDS in wave order.
+// Each lane adds its terms in ascending order; lh and red are the block's
+// shared arrays (one allocation for every instantiation).
 template <bool LCONTIG, bool CPLX>
-__device__ __forceinline__ void stats_body(const StatSide& s, int64_t by) {
-    __shared__ uint32_t lh[kHistLen];
-    __shared__ double red[4][64];
+__device__ __forceinline__ void stats_body(const StatSide& s, int64_t by, uint32_t* lh, double (*red)[64]) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int b = tid; b < kHistLen; b += 256) lh[b] = 0;
+    for (int b = tid; b < kHistCopies * kHistLen; b += 256) lh[b] = 0;
     __syncthreads();
     const OperandView& op = s.op;
     const int w = CPLX ? 2 : 1;
@@ -112,9 +145,18 @@ __device__ __forceinline__ void stats_body(const StatSide& s, int64_t by) {
             double sq = 0.0;
             if (E != kNonFiniteExp) {
                 const double* base = op.X + v * op.sv * w;
-                for (int64_t l = lane; l < op.k; l += 64) {
-                    stat_entry(base[l * op.sl * w], E, lh, sq);
-                    if (CPLX) stat_entry(base[l * op.sl * w + 1], E, lh, sq);
+                for (int64_t l0 = lane; l0 < op.k; l0 += 64 * kStatBatch) {
+                    double re[kStatBatch], im[kStatBatch];
+#pragma unroll
+                    for (int q = 0; q < kStatBatch; ++q) {
+                        const int64_t l = l0 + 64 * q;
+                        const double* e = base + (l < op.k ? l : l0) * op.sl * w;
+                        re[q] = e[0];
+                        im[q] = CPLX ? e[1] : 0.0;
+                    }
+#pragma unroll
+                    for (int q = 0; q < kStatBatch; ++q)
+                        if (l0 + 64 * q < op.k) stat_terms<CPLX>(re[q], im[q], E, lh, sq);
                 }
             }
             for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off);
@@ -126,10 +168,18 @@ __device__ __forceinline__ void stats_body(const StatSide& s, int64_t by) {
         if (v < op.nv) {
             const int E = scale_exp(s.maxbits[v]);
             if (E != kNonFiniteExp)
-                for (int64_t l = wave; l < op.k; l += 4) {
-                    const double* e = op.X + (v * op.sv + l * op.sl) * w;
-                    stat_entry(e[0], E, lh, sq);
-                    if (CPLX) stat_entry(e[1], E, lh, sq);
+                for (int64_t l0 = wave; l0 < op.k; l0 += 4 * kStatBatch) {
+                    double re[kStatBatch], im[kStatBatch];
+#pragma unroll
+                    for (int q = 0; q < kStatBatch; ++q) {
+                        const int64_t l = l0 + 4 * q;
+                        const double* e = op.X + (v * op.sv + (l < op.k ? l : l0) * op.sl) * w;
+                        re[q] = e[0];
+                        im[q] = CPLX ? e[1] : 0.0;
+                    }
+#pragma unroll
+                    for (int q = 0; q < kStatBatch; ++q)
+                        if (l0 + 4 * q < op.k) stat_terms<CPLX>(re[q], im[q], E, lh, sq);
                 }
         }
         red[wave][lane] = sq;
@@ -140,18 +190,23 @@ __device__ __forceinline__ void stats_body(const StatSide& s, int64_t by) {
         }
     }
     __syncthreads();
-    for (int b = tid; b < kHistLen; b += 256)
-        if (lh[b]) atomicAdd(&s.hist[b], static_cast<unsigned long long>(lh[b]));
+    for (int b = tid; b < kHistLen; b += 256) {
+        unsigned long long t = 0;
+        for (int c = 0; c < kHistCopies; ++c) t += lh[c * kHistLen + b];
+        if (t) atomicAdd(&s.hist[b], t);
+    }
 }
 
 __device__ __forceinline__ void stats_dispatch(const StatSide& s, int64_t by) {
+    __shared__ uint32_t lh[kHistCopies * kHistLen];
+    __shared__ double red[4][64];
     const bool lc = s.op.sl == 1 && s.op.sv != 1;
     if (lc) {
-        if (s.op.cplx) stats_body<true, true>(s, by);
-        else stats_body<true, false>(s, by);
+        if (s.op.cplx) stats_body<true, true>(s, by, lh, red);
+        else stats_body<true, false>(s, by, lh, red);
     } else {
-        if (s.op.cplx) stats_body<false, true>(s, by);
-        else stats_body<false, false>(s, by);
+        if (s.op.cplx) stats_body<false, true>(s, by, lh, red);
+        else stats_body<false, false>(s, by, lh, red);
     }
 }
 
