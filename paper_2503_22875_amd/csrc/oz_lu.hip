@@ -29,7 +29,12 @@
 namespace {
 
 constexpr int kPanelThreads = 1024;
-constexpr int kMaxRegRows = 8;    // register panel: rows n - c0 <= 8192
+// Register panel of width 8 (up to 2048 rows): 512 threads of 4 rows; 1024
+// threads of 2 rows spilled 88 registers.  Widths 4 and 2 keep 1024
+// threads: 512 threads of 8 rows measured the same at width 4 (28.0 us per
+// launch either way), and 16 rows per thread would spill at width 2.
+constexpr int kRegPanelThreads = 512;
+constexpr int kMaxRegRows = 8192;
 constexpr int kMaxWaveTrsm = 256; // wave-per-column triangular solves: b <= 256
 constexpr int kMaxGatherSwaps = 256;
 constexpr int kDefaultPanel = 128;       // oz_zgetrf nb = 0
@@ -68,17 +73,16 @@ __device__ __forceinline__ bool pivot_better(double v, int i, double bv, int bi)
 }
 
 // ---------------------------------------------------------------------------
-// Panel, sub-panel step 1 (one block of 1024 threads): factor the sub-panel
+// Panel, sub-panel step 1 (one block of NT threads): factor the sub-panel
 // columns c0 .. c0 + w - 1 over rows c0 .. n - 1, thread t holding rows
-// c0 + t + 1024 s (s < R) of those columns in registers; then, for every other
+// c0 + t + NT s (s < R) of those columns in registers; then, for every other
 // panel column (j0 .. j0 + b - 1), apply the sub-panel's interchanges and, to
 // the right of it, solve the w top rows with the unit lower w x w block.
-template <int R, int W>
-__global__ __launch_bounds__(kPanelThreads) void panel_reg_kernel(double* A, int64_t lda, int64_t n, int64_t j0,
-                                                                  int b, int64_t c0, int w, int32_t* ipiv,
-                                                                  int32_t* info) {
-    __shared__ double red_v[kPanelThreads / 64];
-    __shared__ int red_i[kPanelThreads / 64];
+template <int NT, int R, int W>
+__global__ __launch_bounds__(NT) void panel_reg_kernel(double* A, int64_t lda, int64_t n, int64_t j0, int b,
+                                                       int64_t c0, int w, int32_t* ipiv, int32_t* info) {
+    __shared__ double red_v[NT / 64];
+    __shared__ int red_i[NT / 64];
     __shared__ double rowj[2 * W], rowp[2 * W];
     __shared__ double l11[W][2 * W];
     __shared__ int psub[W];
@@ -87,7 +91,7 @@ __global__ __launch_bounds__(kPanelThreads) void panel_reg_kernel(double* A, int
     double xr[R][W], xi[R][W];
 #pragma unroll
     for (int s = 0; s < R; ++s) {
-        const int r = tid + kPanelThreads * s;
+        const int r = tid + NT * s;
 #pragma unroll
         for (int c = 0; c < W; ++c) {
             xr[s][c] = 0.0;
@@ -107,7 +111,7 @@ __global__ __launch_bounds__(kPanelThreads) void panel_reg_kernel(double* A, int
             int bi = c;
     #pragma unroll
             for (int s = 0; s < R; ++s) {
-                const int r = tid + kPanelThreads * s;
+                const int r = tid + NT * s;
                 if (r >= c && r < m) {
                     const double v = fabs(xr[s][c]) + fabs(xi[s][c]);
                     if (v > best) {
@@ -132,13 +136,13 @@ __global__ __launch_bounds__(kPanelThreads) void panel_reg_kernel(double* A, int
             __syncthreads();
             best = red_v[0];
             bi = red_i[0];
-            for (int q = 1; q < kPanelThreads / 64; ++q)
+            for (int q = 1; q < NT / 64; ++q)
                 if (pivot_better(red_v[q], red_i[q], best, bi)) {
                     best = red_v[q];
                     bi = red_i[q];
                 }
             const int p = bi;
-            const int owner = p % kPanelThreads, slot = p / kPanelThreads;
+            const int owner = p % NT, slot = p / NT;
             // exchange rows c and p of the sub-panel through LDS (row c: thread c, slot 0)
             if (tid == c) {
     #pragma unroll
@@ -192,7 +196,7 @@ __global__ __launch_bounds__(kPanelThreads) void panel_reg_kernel(double* A, int
                 crecip(ppr, ppi, rr, ri);
     #pragma unroll
                 for (int s = 0; s < R; ++s) {
-                    const int r = tid + kPanelThreads * s;
+                    const int r = tid + NT * s;
                     if (r > c && r < m) {
                         double lr, li;
                         cmul(xr[s][c], xi[s][c], rr, ri, lr, li);
@@ -204,7 +208,7 @@ __global__ __launch_bounds__(kPanelThreads) void panel_reg_kernel(double* A, int
             // rank-1 update of the sub-panel columns right of c
     #pragma unroll
             for (int s = 0; s < R; ++s) {
-                const int r = tid + kPanelThreads * s;
+                const int r = tid + NT * s;
                 if (r > c && r < m) {
     #pragma unroll
                     for (int k = c + 1; k < W; ++k) {
@@ -222,7 +226,7 @@ __global__ __launch_bounds__(kPanelThreads) void panel_reg_kernel(double* A, int
     // write the factored sub-panel back; keep its top w x w block in LDS
 #pragma unroll
     for (int s = 0; s < R; ++s) {
-        const int r = tid + kPanelThreads * s;
+        const int r = tid + NT * s;
 #pragma unroll
         for (int c = 0; c < W; ++c)
             if (r < m && c < w) {
@@ -259,7 +263,7 @@ __global__ __launch_bounds__(kPanelThreads) void panel_reg_kernel(double* A, int
     // the pivot rows), then right of the sub-panel u_i = a_i - sum_{k < i}
     // l_ik u_k over the w top rows, in registers
     const int left = static_cast<int>(c0 - j0), right = b - left - w;
-    for (int t = tid; t < left + right; t += kPanelThreads) {
+    for (int t = tid; t < left + right; t += NT) {
         const int64_t col = t < left ? j0 + t : c0 + w + (t - left);
         double vr[2 * W], vi[2 * W];
 #pragma unroll
@@ -736,23 +740,24 @@ hipError_t launch_trsm(bool upper, const double* T, int64_t ldt, int b, double* 
 }
 
 // One panel (columns j0 .. j0 + b - 1): sub-panels in registers when the rows
-// fit (width 8, 4, 2 for R = 2, 4, 8 rows per thread), else the global-memory
-// panel kernel.
+// fit (width 8: 4 rows per thread of 512; widths 4 and 2: 4 and 8 rows per
+// thread of 1024), else the global-memory panel kernel.
 hipError_t launch_panel(double* A, int64_t lda, int64_t n, int64_t j0, int b, int32_t* ipiv, int32_t* info,
                         hipStream_t st) {
-    if (n - j0 > static_cast<int64_t>(kMaxRegRows) * kPanelThreads) {
+    if (n - j0 > kMaxRegRows) {
         hipLaunchKernelGGL(panel_kernel, dim3(1), dim3(kPanelThreads), 0, st, A, lda, n, j0, b, ipiv, info);
         return hipGetLastError();
     }
     for (int64_t c0 = j0; c0 < j0 + b;) {
         const int64_t m = n - c0;
-        const int r = m <= 2048 ? 2 : m <= 4096 ? 4 : 8;
-        const int W = 16 / r;
+        // sub-panel width 8, 4, 2 for up to 2048, 4096, 8192 rows
+        const int W = m <= 2048 ? 8 : m <= 4096 ? 4 : 2;
         const int w = static_cast<int>(j0 + b - c0 < W ? j0 + b - c0 : W);
-        switch (r) {
-            case 2: hipLaunchKernelGGL((panel_reg_kernel<2, 8>), dim3(1), dim3(kPanelThreads), 0, st, A, lda, n, j0, b, c0, w, ipiv, info); break;
-            case 4: hipLaunchKernelGGL((panel_reg_kernel<4, 4>), dim3(1), dim3(kPanelThreads), 0, st, A, lda, n, j0, b, c0, w, ipiv, info); break;
-            default: hipLaunchKernelGGL((panel_reg_kernel<8, 2>), dim3(1), dim3(kPanelThreads), 0, st, A, lda, n, j0, b, c0, w, ipiv, info); break;
+        const dim3 grid(1), small(kRegPanelThreads), large(kPanelThreads);
+        switch (W) {
+            case 8: hipLaunchKernelGGL((panel_reg_kernel<kRegPanelThreads, 4, 8>), grid, small, 0, st, A, lda, n, j0, b, c0, w, ipiv, info); break;
+            case 4: hipLaunchKernelGGL((panel_reg_kernel<kPanelThreads, 4, 4>), grid, large, 0, st, A, lda, n, j0, b, c0, w, ipiv, info); break;
+            default: hipLaunchKernelGGL((panel_reg_kernel<kPanelThreads, 8, 2>), grid, large, 0, st, A, lda, n, j0, b, c0, w, ipiv, info); break;
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
