@@ -489,6 +489,22 @@ __global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_pe
     tile_body<S, 2, 2, 2, TOP, DIAG, MULTI, XD>(g, tm, tn, lds);
 }
 
+// Tile list walk of a persistent block: tiles b, b + gridDim.x, ...; the next
+// item is loaded while the current tile runs, so its load is off the path
+// between tiles.  Padding items (problem -1) are skipped.
+template <class F>
+__device__ __forceinline__ void for_each_item(const TileItem* __restrict__ items, int64_t nitems, F&& f) {
+    int64_t it = blockIdx.x;
+    if (it >= nitems) return;
+    TileItem ti = items[it];
+    for (; it < nitems; it += gridDim.x) {
+        const int64_t nx = it + gridDim.x;
+        const TileItem next = nx < nitems ? items[nx] : TileItem{-1, 0, 0, 0};
+        if (ti.prob >= 0) f(ti);  // uniform over the block
+        ti = next;
+    }
+}
+
 // Persistent form for a batch: block b takes tiles b, b + gridDim.x, ... of the
 // tile list; a tile names its problem (a GemmArgs in device memory) and its
 // tile row and column (problem -1: a padding item, skipped).  Every problem of
@@ -501,12 +517,10 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64 * WMW * WNW, 64 * WMW *
                                                                                   int64_t nitems) {
     using T = TileCfg<S, WMW, WNW, NST, TM>;
     __shared__ v4i lds[NST][T::STAGE];
-    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-        const TileItem ti = items[it];
-        if (ti.prob < 0) continue;  // padding item (uniform over the block)
+    for_each_item(items, nitems, [&](const TileItem& ti) {
         tile_body<S, WMW, WNW, NST, TOP, false, MULTI, false, TM>(probs[ti.prob], ti.tm, ti.tn, lds);
         __syncthreads();  // the next tile refills the LDS ring
-    }
+    });
 }
 
 // Persistent form over tiles of problems with different slice counts (all
@@ -529,9 +543,7 @@ template <bool TOP, bool MULTI>
 __global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(2, 2))) void
 gemm_persistent_mixed_kernel(const GemmArgs* __restrict__ probs, const TileItem* __restrict__ items, int64_t nitems) {
     __shared__ v4i lds[2 * TileCfg<kMaxLiveSlices, 2, 2, 2>::STAGE];
-    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-        const TileItem ti = items[it];
-        if (ti.prob < 0) continue;  // padding item (uniform over the block)
+    for_each_item(items, nitems, [&](const TileItem& ti) {
         const GemmArgs& g = probs[ti.prob];
         switch (ti.s) {  // the tile's slice count, uniform over the block
             case 1: mixed_tile<1, TOP, true>(g, ti, lds); break;
@@ -544,7 +556,7 @@ gemm_persistent_mixed_kernel(const GemmArgs* __restrict__ probs, const TileItem*
             default: mixed_tile<8, TOP, true>(g, ti, lds); break;
         }
         __syncthreads();  // the next tile refills the LDS ring
-    }
+    });
 }
 
 // Persistent form of the wide all-diagonal tile (9 <= s <= kMaxWideSlices, one
@@ -568,12 +580,10 @@ template <bool TOP, bool MULTI, int LO, int HI>
 __global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(1, 1))) void
 gemm_wide_persistent_kernel(const GemmArgs* __restrict__ probs, const TileItem* __restrict__ items, int64_t nitems) {
     __shared__ v4i lds[2 * TileCfg<HI, 2, 2, 2>::STAGE];
-    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-        const TileItem ti = items[it];
-        if (ti.prob < 0) continue;
+    for_each_item(items, nitems, [&](const TileItem& ti) {
         wide_tile<LO, HI, TOP, MULTI>(ti.s, probs[ti.prob], ti, lds);  // ti.s uniform over the block
         __syncthreads();
-    }
+    });
 }
 
 // Fused 3-real-product tile of a complex product (s <= kMaxLiveSlices, each
@@ -639,9 +649,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_pe
 void gemm_persistent_3m_kernel(const GemmArgs* __restrict__ probs, const TileItem* __restrict__ items,
                                int64_t nitems) {
     __shared__ v4i lds[2 * TileCfg<HI, 2, 2, 2>::STAGE];
-    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-        const TileItem ti = items[it];
-        if (ti.prob < 0) continue;  // padding item (uniform over the block)
+    for_each_item(items, nitems, [&](const TileItem& ti) {
         const GemmArgs* g3 = probs + ti.prob;
         if constexpr (HI <= 6) {
             switch (ti.s) {  // uniform over the block
@@ -657,7 +665,7 @@ void gemm_persistent_3m_kernel(const GemmArgs* __restrict__ probs, const TileIte
             else fused3_tile<8>(g3, ti, lds);
         }
         __syncthreads();  // the next tile refills the LDS ring
-    }
+    });
 }
 
 // Streaming form for any s (used above the all-diagonal kernel's register
@@ -761,12 +769,10 @@ __global__ __attribute__((amdgpu_flat_work_group_size(256, 256))) void gemm_stre
 __global__ __attribute__((amdgpu_flat_work_group_size(256, 256))) void gemm_stream_persistent_kernel(
     const GemmArgs* __restrict__ probs, const TileItem* __restrict__ items, int64_t nitems, int s, int top) {
     __shared__ v4i lds[2][256];
-    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-        const TileItem ti = items[it];
-        if (ti.prob < 0) continue;  // padding item (uniform over the block)
+    for_each_item(items, nitems, [&](const TileItem& ti) {
         stream_body<false>(probs[ti.prob], s, top, ti.tm, ti.tn, lds);
         __syncthreads();
-    }
+    });
 }
 
 __global__ void scale_c_kernel(double* C, int64_t ldc, int64_t m, int64_t n, int cplx, double br, double bi,
