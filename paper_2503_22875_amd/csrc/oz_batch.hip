@@ -193,26 +193,35 @@ void build_group(const std::vector<oz::GemmArgs>& args, std::vector<size_t> memb
     // the two-tile 128 x 64 block holds one s <= 6 and a single INT32 chunk
     if (tile == kTile128x64 && (sv < 1 || sv > 6 || multi)) tile = kTile64;
     const int order = have_tune && vote_order[1] > vote_order[0] ? 1 : 0;
-    const int64_t bm = (tile == kTile128 || tile == kTile128x64) ? 128 : 64, bn = 64;
-    // work of one tile: slice pairs times steps
+    // a mixed-s launch runs the problems with s <= 6 and one INT32 chunk on
+    // 128 x 64 two-tile blocks, the others on 64 x 64 blocks
+    auto two_tile = [&](size_t i) {
+        return tile == kMixed && args[i].s <= 6 && args[i].chunk_steps >= args[i].kpad / oz::kStep;
+    };
+    auto bm_of = [&](size_t i) -> int64_t {
+        return (tile == kTile128 || tile == kTile128x64 || two_tile(i)) ? 128 : 64;
+    };
+    const int64_t bn = 64;
+    // work of one tile: slice pairs times steps, times its 64-row blocks
     auto tile_work = [&](size_t i) {
         const int64_t si = args[i].s;
-        return static_cast<double>(si * (si + 1) / 2) * static_cast<double>(args[i].kpad);
+        return static_cast<double>(si * (si + 1) / 2) * static_cast<double>(args[i].kpad) *
+               static_cast<double>(bm_of(i) / 64);
     };
     std::stable_sort(members.begin(), members.end(), [&](size_t a, size_t b) { return tile_work(a) > tile_work(b); });
     // tiles holding valid C' rows and columns only (rows of a complex two-row
     // operand: 16 complex rows span 32 rows of C'); the padding of the slice
     // layout is never computed
     auto tiles_m = [&](size_t i) {
-        const int64_t rows = args[i].cplx ? 2 * oz::round_up(args[i].m, 16) : args[i].m;
+        const int64_t rows = args[i].cplx ? 2 * oz::round_up(args[i].m, 16) : args[i].m, bm = bm_of(i);
         return std::min<int64_t>((rows + bm - 1) / bm, args[i].Mp / bm);
     };
     auto tiles_n = [&](size_t i) { return std::min<int64_t>((args[i].n + bn - 1) / bn, args[i].Np / bn); };
     auto tiles_of = [&](size_t i, std::vector<oz::TileItem>& dst) {
+        const int32_t sflag = static_cast<int32_t>(args[i].s) | (two_tile(i) ? oz::kTwoTileItem : 0);
         for (int64_t tm = 0; tm < tiles_m(i); ++tm)
             for (int64_t tn = 0; tn < tiles_n(i); ++tn)
-                dst.push_back({static_cast<int32_t>(i), static_cast<int32_t>(tm), static_cast<int32_t>(tn),
-                               static_cast<int32_t>(args[i].s)});
+                dst.push_back({static_cast<int32_t>(i), static_cast<int32_t>(tm), static_cast<int32_t>(tn), sflag});
     };
     std::vector<oz::TileItem>& items = *out_items;
     items.clear();

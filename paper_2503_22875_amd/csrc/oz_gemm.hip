@@ -539,12 +539,34 @@ __device__ __forceinline__ void mixed_tile(const GemmArgs& g, const TileItem& ti
 // the fold after the loop): with the fold after the loop the s = 7, 8 bodies of
 // this one function spilled about 110 registers to scratch (measured: the
 // tolerance-driven batches ran 3% faster without the spills).
+// A tile item whose s carries kTwoTileItem is a 128 x 64 tile of two-tile
+// waves (s <= 6, one INT32 chunk): half the tiles of the 64 x 64 form, and
+// each B fragment read from LDS feeds two MFMAs.
+template <int S, bool TOP>
+__device__ __forceinline__ void mixed_tile2(const GemmArgs& g, const TileItem& ti, v4i* lds) {
+    using T = TileCfg<S, 2, 2, 2, 2>;
+    tile_body<S, 2, 2, 2, TOP, false, false, false, 2>(g, ti.tm, ti.tn, reinterpret_cast<v4i(*)[T::STAGE]>(lds));
+}
+
 template <bool TOP, bool MULTI>
 __global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(2, 2))) void
 gemm_persistent_mixed_kernel(const GemmArgs* __restrict__ probs, const TileItem* __restrict__ items, int64_t nitems) {
-    __shared__ v4i lds[2 * TileCfg<kMaxLiveSlices, 2, 2, 2>::STAGE];
+    constexpr int kLds1 = 2 * TileCfg<kMaxLiveSlices, 2, 2, 2>::STAGE, kLds2 = 2 * TileCfg<6, 2, 2, 2, 2>::STAGE;
+    __shared__ v4i lds[kLds1 > kLds2 ? kLds1 : kLds2];
     for_each_item(items, nitems, [&](const TileItem& ti) {
         const GemmArgs& g = probs[ti.prob];
+        if (ti.s & kTwoTileItem) {
+            switch (ti.s & ~kTwoTileItem) {  // uniform over the block
+                case 1: mixed_tile2<1, TOP>(g, ti, lds); break;
+                case 2: mixed_tile2<2, TOP>(g, ti, lds); break;
+                case 3: mixed_tile2<3, TOP>(g, ti, lds); break;
+                case 4: mixed_tile2<4, TOP>(g, ti, lds); break;
+                case 5: mixed_tile2<5, TOP>(g, ti, lds); break;
+                default: mixed_tile2<6, TOP>(g, ti, lds); break;
+            }
+            __syncthreads();  // the next tile refills the LDS ring
+            return;
+        }
         switch (ti.s) {  // the tile's slice count, uniform over the block
             case 1: mixed_tile<1, TOP, true>(g, ti, lds); break;
             case 2: mixed_tile<2, TOP, true>(g, ti, lds); break;

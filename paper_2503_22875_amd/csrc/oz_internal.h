@@ -179,6 +179,9 @@ struct TileItem {
     int32_t tn;
     int32_t s;  // slice count of this tile's problem (read by the mixed-s launch)
 };
+// Flag in TileItem::s of a mixed-s launch: a 128 x 64 two-tile block (tm in
+// units of 128 rows; s <= 6 and one INT32 chunk).
+constexpr int32_t kTwoTileItem = 0x100;
 hipError_t launch_gemm_persistent(const GemmArgs* probs, const TileItem* items, int64_t nitems, int s, int tile,
                                   int blocks, bool top, bool multi, hipStream_t st);
 // Same for any s with the per-diagonal streaming body (64 x 64 tiles).

@@ -513,6 +513,22 @@ def test_batched_tolerance_growth_past_eight(oz, handle, stream):
     _check_tol_results(probs, got, reps, 11, 1e-300, 11)
 
 
+@pytest.mark.parametrize("kchunk", [0, 64])
+def test_batched_tolerance_growth_to_fourteen(oz, handle, stream, kchunk):
+    # growth 11 -> 14 one anti-diagonal per round: the wide launches' ranges
+    # 9..12 and 13..14 with one INT32 chunk; with 64-term chunks 12 (several
+    # chunks) and the streaming body at 13, 14
+    rng = np.random.default_rng(52 + kchunk)
+    probs = _tol_probs(rng, 0, [(40, 50, 130), (70, 20, 30), (65, 33, 100)])
+    print("growth to 14 kchunk=%d" % kchunk, flush=True)
+    got, reps = _tol_batch(oz, handle, stream, 0, probs,
+                           oz.prec(0, tol=1e-300, smax=14, sstart=11, kchunk=kchunk))
+    assert all(r.slices_used == 14 and r.fallbacks == 3 for r in reps)
+    for i, (ta, tb, A, B, C0, al, be) in enumerate(probs):
+        want = oracle.emu_gemm(ta, tb, A, B, 11, alpha=al, beta=be, C=C0, s_to=14, kc=kchunk or oracle.kchunk(14))
+        assert np.array_equal(got[i], want), (i, A.shape, B.shape)
+
+
 def test_batched_tolerance_learned_start(oz, handle, stream):
     from oracle import mlp as omlp
     P = {name: np.zeros(shape) for name, shape in omlp.SIZES}
