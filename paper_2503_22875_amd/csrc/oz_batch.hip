@@ -87,6 +87,10 @@ struct oz_batch_s {
     std::vector<int32_t> prob_b;          // plan problem -> batch index
     std::vector<double> tols;             // tolerance per plan problem
     std::vector<oz::GemmArgs> host_args;  // raw-write descriptors (host copies)
+    // host copies of the tile lists uploaded by the GEMM rounds of the current
+    // execution (each read by its asynchronous upload; cleared once the
+    // execution has synchronised after its last upload)
+    std::vector<std::vector<oz::TileItem>> round_lists;
     size_t off_args_add;                  // raw-add descriptors
     size_t off_stat_sides, off_stat_items, off_hist, off_fp, off_feat, off_y, off_s, off_tols;
     int64_t n_stat_items, n_hist;
@@ -969,7 +973,11 @@ int tol_round(oz_batch_t P, const std::vector<size_t>& members, bool growth, hip
     std::vector<std::vector<oz::TileItem>> gitems;
     round_groups(cur, members, [&](size_t i) { return P->s_cur[i]; }, P->kernel == 1 ? 1 : 0, P->cplx, P->cus,
                  oz_handle_tuning(P->h), &groups, &gitems);
-    std::vector<oz::TileItem> all;
+    // the host list lives in the plan until the execution ends (moving the
+    // outer vector keeps every list's storage): the copy needs no wait of its
+    // own, and the GEMM launches queue behind the split
+    P->round_lists.emplace_back();
+    std::vector<oz::TileItem>& all = P->round_lists.back();
     for (size_t g = 0; g < groups.size(); ++g) {
         groups[g].off_items = all.size();
         all.insert(all.end(), gitems[g].begin(), gitems[g].end());
@@ -977,10 +985,8 @@ int tol_round(oz_batch_t P, const std::vector<size_t>& members, bool growth, hip
     if (groups.empty()) return OZ_OK;
     if (static_cast<int64_t>(all.size()) > P->dyn_cap) return OZ_ERR_ALLOC;
     oz::TileItem* ditems = reinterpret_cast<oz::TileItem*>(dev + P->off_dyn);
-    // the host list must outlive the copy: wait for it
     if (hipMemcpyAsync(ditems, all.data(), sizeof(oz::TileItem) * all.size(), hipMemcpyHostToDevice, st) !=
-            hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
+        hipSuccess)
         return OZ_ERR_HIP;
     // off_items: index into the round's tile list
     return launch_groups(P, groups, dargs, [&](const Group& gr) { return ditems + gr.off_items; }, growth, st) ==
@@ -992,6 +998,12 @@ int tol_round(oz_batch_t P, const std::vector<size_t>& members, bool growth, hip
 int execute_tol(oz_batch_t P) {
     oz_handle_t h = P->h;
     hipStream_t st = oz_handle_stream(h);
+    // lists left by an execution that stopped on an error: their uploads may
+    // still read them
+    if (!P->round_lists.empty()) {
+        if (hipStreamSynchronize(st) != hipSuccess) return OZ_ERR_HIP;
+        P->round_lists.clear();
+    }
     char* dev = static_cast<char*>(P->dev);
     const size_t nprob = P->prob_b.size();
     hipError_t e = hipSuccess;
@@ -1159,6 +1171,8 @@ int execute_tol(oz_batch_t P) {
         if (e == hipSuccess) e = hipStreamSynchronize(st);
     }
     for (size_t i = 0; i < nprob; ++i) P->slices[P->prob_b[i]] = P->s_cur[i];
+    // every upload was followed by a synchronising read of the residual check
+    if (e == hipSuccess) P->round_lists.clear();
     return e == hipSuccess ? OZ_OK : OZ_ERR_HIP;
 }
 
