@@ -597,7 +597,8 @@ def bench_dgemm(args):
 def bench_peaks(args):
     """The rates the roofline fractions divide by, measured by the library's
     own microbenchmarks (oz_peak): INT8 MFMA (v_mfma_i32_32x32x32_i8, the
-    slice GEMM's shape, and v_mfma_i32_16x16x64_i8), FP64 MFMA
+    slice GEMM's shape, with fixed small operands and with full-range operands
+    that change between instructions, and v_mfma_i32_16x16x64_i8), FP64 MFMA
     (v_mfma_f64_16x16x4_f64) and a 1 GiB device copy; best of --steps."""
     import torch
 
@@ -612,11 +613,13 @@ def bench_peaks(args):
     torch.cuda.synchronize()
     i8 = max(oz.oz_peak(h, 0, 20000) for _ in range(args.steps))
     i8_16 = max(oz.oz_peak(h, 3, 20000) for _ in range(args.steps))
+    i8_rand = max(oz.oz_peak(h, 4, 20000) for _ in range(args.steps))
     f64 = max(oz.oz_peak(h, 1, 20000) for _ in range(args.steps))
     cp = max(oz.oz_peak(h, 2, 10, src, dst, src.numel() * 8) for _ in range(args.steps))
     oz.oz_destroy(h)
     print(json.dumps({"workload": "peaks", "int8_mfma_tops": round(i8 / 1e12, 1),
                       "int8_mfma_16x16x64_tops": round(i8_16 / 1e12, 1),
+                      "int8_mfma_random_operands_tops": round(i8_rand / 1e12, 1),
                       "int8_vendor_tops": INT8_PEAK_TOPS, "fp64_mfma_tflops": round(f64 / 1e12, 2),
                       "fp64_vendor_tflops": 78.6, "copy_gbs": round(cp / 1e9, 1), "hbm_vendor_gbs": 8000.0,
                       "copy_bytes": src.numel() * 8}), flush=True)

@@ -471,8 +471,12 @@ int oz_predict_slices(oz_handle_t handle, char transa, char transb, int64_t m, i
  *          buffers of the caller), iters repetitions -> bytes read plus bytes
  *          written per second;
  *  kind 3: INT8 matrix cores in the 16 x 16 x 64 shape,
- *          v_mfma_i32_16x16x64_i8 -> ops per second.
- * src, dst and bytes are ignored for kinds 0, 1 and 3.  OZ_ERR_ARG for a bad
+ *          v_mfma_i32_16x16x64_i8 -> ops per second;
+ *  kind 4: as kind 0 with two pairs of full-range pseudo-random operand
+ *          bytes used by alternate instructions (consecutive MFMAs see
+ *          different data, as in a GEMM over random digits; kind 0 feeds
+ *          the same small bytes to every instruction) -> ops per second.
+ * src, dst and bytes are ignored for kinds 0, 1, 3 and 4.  OZ_ERR_ARG for a bad
  * kind, iters < 1, a NULL rate, or a bad copy buffer. */
 int oz_peak(oz_handle_t handle, int kind, int64_t iters, const void* src, void* dst, size_t bytes, double* rate);
 

@@ -555,7 +555,8 @@ def oz_predict_slices(handle, transa, transb, m, n, k, is_complex, A, lda, B, ld
 def oz_peak(handle, kind, iters, src=None, dst=None, nbytes=0):
     """Measured rate: kind 0 INT8 MFMA ops/s (32 x 32 x 32 shape), 1 FP64 MFMA
     flop/s, 2 device copy bytes/s (read + written) from src to dst, 3 INT8
-    MFMA ops/s (16 x 16 x 64 shape)."""
+    MFMA ops/s (16 x 16 x 64 shape), 4 INT8 MFMA ops/s (32 x 32 x 32 shape,
+    full-range operands that change between instructions)."""
     out = ctypes.c_double()
     _check("oz_peak", _lib.oz_peak(handle, int(kind), int(iters), _ptr(src), _ptr(dst), int(nbytes),
                                    ctypes.byref(out)))

@@ -3,9 +3,10 @@
 // matrix-core throughput (what a native DGEMM / ZGEMM runs on), and HBM copy
 // bandwidth (what the split and epilogue passes stream through).
 //
-// The MFMA kernels (INT8 in the 32 x 32 x 32 shape the slice GEMM uses and in
-// the 16 x 16 x 64 shape) keep kChains independent accumulators per wave and issue
-// the instruction round-robin over them, so consecutive instructions never
+// The MFMA kernels (INT8 in the 32 x 32 x 32 shape the slice GEMM uses, also
+// with changing full-range operands, and in the 16 x 16 x 64 shape) keep
+// kChains independent accumulators per wave and issue the instruction
+// round-robin over them, so consecutive instructions never
 // depend on each other and one wave keeps its SIMD's matrix pipe fed (the
 // 32 x 32 x 32 kernel's 8 chains take 128 accumulator registers, so one wave
 // per SIMD is resident and the second block per CU runs after the first).
@@ -27,13 +28,32 @@ constexpr int kChains = 8;
 constexpr int kPeakThreads = 256;  // 4 waves per block
 constexpr int kBlocksPerCu = 2;    // 8 waves per compute unit
 
+// TOGGLE = false: one operand pair of bytes at most 63, the same for every
+// instruction.  TOGGLE = true: two pairs of full-range pseudo-random bytes
+// (a splitmix64 hash of lane and register), used by alternate instructions, so
+// that consecutive MFMAs see different data as in a GEMM over random digits
+// (the matrix cores' power, and with it the clock, depends on the data).
+__device__ __forceinline__ int peak_bytes(uint64_t key) {
+    key += 0x9E3779B97F4A7C15ull;
+    key = (key ^ (key >> 30)) * 0xBF58476D1CE4E5B9ull;
+    key = (key ^ (key >> 27)) * 0x94D049BB133111EBull;
+    return static_cast<int>((key ^ (key >> 31)) & 0xffffffffull);
+}
+
+template <bool TOGGLE>
 __global__ __launch_bounds__(kPeakThreads) void peak_i8_kernel(int64_t iters, int* out) {
     const int lane = threadIdx.x & 63;
-    v4i a, b;
-    for (int r = 0; r < 4; ++r) {
-        a[r] = (lane * 0x01030507 + r) & 0x3f3f3f3f;
-        b[r] = (lane * 0x07050301 + 3 * r) & 0x3f3f3f3f;
-    }
+    v4i a[2], b[2];
+    for (int q = 0; q < 2; ++q)
+        for (int r = 0; r < 4; ++r) {
+            if (TOGGLE) {
+                a[q][r] = peak_bytes(static_cast<uint64_t>(((q * 4 + r) * 2) * 64 + lane));
+                b[q][r] = peak_bytes(static_cast<uint64_t>(((q * 4 + r) * 2 + 1) * 64 + lane));
+            } else {
+                a[q][r] = (lane * 0x01030507 + r) & 0x3f3f3f3f;
+                b[q][r] = (lane * 0x07050301 + 3 * r) & 0x3f3f3f3f;
+            }
+        }
     v16i acc[kChains];
 #pragma unroll
     for (int c = 0; c < kChains; ++c)
@@ -41,7 +61,10 @@ __global__ __launch_bounds__(kPeakThreads) void peak_i8_kernel(int64_t iters, in
         for (int r = 0; r < 16; ++r) acc[c][r] = 0;
     for (int64_t it = 0; it < iters; ++it) {
 #pragma unroll
-        for (int c = 0; c < kChains; ++c) acc[c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, acc[c], 0, 0, 0);
+        for (int c = 0; c < kChains; ++c) {
+            const int q = TOGGLE ? (c & 1) : 0;
+            acc[c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[q], b[q], acc[c], 0, 0, 0);
+        }
     }
     int sum = 0;
 #pragma unroll
@@ -110,7 +133,7 @@ extern "C" {
 
 int oz_peak(oz_handle_t h, int kind, int64_t iters, const void* src, void* dst, size_t bytes, double* rate) {
     if (!oz_handle_valid(h)) return OZ_ERR_HANDLE;
-    if (kind < 0 || kind > 3 || iters < 1 || !rate) return OZ_ERR_ARG;
+    if (kind < 0 || kind > 4 || iters < 1 || !rate) return OZ_ERR_ARG;
     if (kind == 2 && (!src || !dst || bytes == 0 || bytes % 16 != 0)) return OZ_ERR_ARG;
     if (oz_handle_use_device(h)) return OZ_ERR_HIP;
     hipStream_t st = oz_handle_stream(h);
@@ -124,7 +147,11 @@ int oz_peak(oz_handle_t h, int kind, int64_t iters, const void* src, void* dst, 
     if (e == hipSuccess) e = hipEventCreate(&e1);
     auto launch = [&](int64_t n) {
         if (kind == 0)
-            hipLaunchKernelGGL(peak_i8_kernel, dim3(blocks), dim3(kPeakThreads), 0, st, n, static_cast<int*>(out));
+            hipLaunchKernelGGL(peak_i8_kernel<false>, dim3(blocks), dim3(kPeakThreads), 0, st, n,
+                               static_cast<int*>(out));
+        else if (kind == 4)
+            hipLaunchKernelGGL(peak_i8_kernel<true>, dim3(blocks), dim3(kPeakThreads), 0, st, n,
+                               static_cast<int*>(out));
         else if (kind == 3)
             hipLaunchKernelGGL(peak_i8_16_kernel, dim3(blocks), dim3(kPeakThreads), 0, st, n,
                                static_cast<int*>(out));
@@ -147,7 +174,7 @@ int oz_peak(oz_handle_t h, int kind, int64_t iters, const void* src, void* dst, 
     if (e == hipSuccess) {
         const double waves = static_cast<double>(blocks) * (kPeakThreads / 64);
         double work;
-        if (kind == 0) work = waves * iters * kChains * (32.0 * 32.0 * 32.0 * 2.0);
+        if (kind == 0 || kind == 4) work = waves * iters * kChains * (32.0 * 32.0 * 32.0 * 2.0);
         else if (kind == 3) work = waves * iters * kChains * (16.0 * 16.0 * 64.0 * 2.0);
         else if (kind == 1) work = waves * iters * kChains * (16.0 * 16.0 * 4.0 * 2.0);
         else work = 2.0 * static_cast<double>(bytes) * iters;
